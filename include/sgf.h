@@ -1,0 +1,194 @@
+/*
+ * sgf.h - C ABI of the Sparse Geometric Factorization (SGF) library for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The library computes the hierarchical approximate factorization
+ *     A ~= A_l = G_1 B_1 G_2 B_2 ... G_l G_l^T ... B_1^T G_1^T
+ * of a sparse symmetric positive definite matrix A that comes from a PDE on
+ * a Cartesian grid (Klockiewicz & Darve, "Sparse hierarchical
+ * preconditioners using piecewise smooth approximations of eigenvectors",
+ * Sec. 2.1 and Algorithm 4.1), applies A_l^{-1} (Sec. 4.7) and runs
+ * conjugate gradients preconditioned by it (Sec. 7).
+ *
+ * Conventions shared by every entry point:
+ *  - Unknown numbering: grid node (ix, iy[, iz]) has id ix + gx*(iy + gy*iz)
+ *    (x fastest); its dofs_per_node unknowns are node*dofs_per_node + comp.
+ *  - Return value: SGF_OK or an error code; a thread-local message is kept
+ *    for sgf_last_error().  No C++ exception crosses this boundary.  On error
+ *    no output handle is created and an existing handle is left usable
+ *    unless the code is SGF_EDEVICE.
+ *  - Streams: every `stream` argument is a hipStream_t passed as void*
+ *    (NULL = the null stream).  Calls enqueue work on that stream; entry
+ *    points that return host-visible results (ranks, iteration counts)
+ *    synchronize it before returning.
+ *  - A handle is not thread safe: use it from one host thread / stream at a
+ *    time.  Distinct handles are independent.
+ *  - Vectors passed to sgf_apply / sgf_multiply / sgf_pcg_solve are DEVICE
+ *    pointers to FP64 column-major n x nrhs arrays owned by the caller.
+ */
+#ifndef SGF_H
+#define SGF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sgf_handle_s* sgf_handle;
+
+typedef enum {
+  SGF_OK = 0,
+  SGF_EINVAL = 1,     /* bad argument, shape or option                      */
+  SGF_ENOTSPD = 2,    /* non-positive pivot in a Cholesky (cluster in info) */
+  SGF_ENOMEM = 3,     /* device or host allocation failed                    */
+  SGF_EDEVICE = 4,    /* HIP runtime error                                   */
+  SGF_ENOCONV = 5,    /* CG reached maxit before the tolerance               */
+  SGF_ESTATE = 6      /* call out of order (e.g. apply before factorize)     */
+} sgf_status;
+
+/* Which separator interactions are compressed (Sec. 5.1). */
+enum { SGF_NEST_ALL_ALL = 0, SGF_NEST_2_ALL = 1 };
+/* When the hierarchy ends (Sec. 4.5 and Sec. 7). */
+enum { SGF_STOP_ROOT = 0, SGF_STOP_PAPER = 1 };
+/* Arithmetic of the factor and the apply; CG itself is always FP64. */
+enum { SGF_FP64 = 0, SGF_FP32 = 1 };
+
+typedef struct {
+  int32_t dim;                 /* 2 or 3                                           */
+  int32_t grid[3];             /* grid nodes per axis (grid[2] ignored in 2D)      */
+  int32_t dofs_per_node;       /* 1 (scalar PDE) or 3 (elasticity, Eq. 7.4)        */
+  int32_t q;                   /* polynomial degree 0, 1 or 2 (Sec. 3.1)           */
+  int32_t leaf;                /* b > 1: level-t period d_t = b * 2^(t-1) (Sec 5.1)*/
+  int32_t scheme;              /* SGF_NEST_ALL_ALL (default) or SGF_NEST_2_ALL     */
+  int32_t compress;            /* 0 = exact nested-dissection block Cholesky       */
+  int32_t compress_from_level; /* first level whose separators are compressed (1) */
+  int32_t stop_rule;           /* SGF_STOP_ROOT (default) or SGF_STOP_PAPER        */
+  int32_t precision;           /* SGF_FP64 (default) or SGF_FP32                   */
+  double rank_tol;             /* pivoted-QR rank threshold relative to |R_00|;
+                                  <= 0 selects 1e-12 (FP64) / 1e-6 (FP32)         */
+} sgf_options;
+
+typedef struct {
+  int32_t levels;              /* partitions processed, including the top         */
+  int64_t n;                   /* unknowns                                         */
+  int64_t top_size;            /* unknowns left for the final exact Cholesky      */
+  int64_t factor_entries;      /* stored factor values (L_I, W, L_B, V_B, top)    */
+  int64_t factor_bytes;        /* device bytes held by the factor                 */
+  int64_t compressed;          /* separators whose rank was below their size      */
+  double factor_flops;         /* algorithmic flops of the last numeric factorize */
+  double apply_bytes;          /* algorithmic bytes of one apply (factor read 2x) */
+  int32_t failed_cluster;      /* cluster id of a non-positive pivot, else -1     */
+  int32_t failed_level;        /* its level (1-based), else -1                    */
+} sgf_info;
+
+/* Fills *opt with the defaults: scheme NEST_ALL_ALL, compress 1, compress
+ * from level 1, stop ROOT, FP64, rank_tol 0 (automatic), q 1, leaf 8. */
+void sgf_default_options(sgf_options* opt);
+
+/*
+ * Symbolic analysis (Sec. 5.1 partition hierarchy, Algorithm 4.1 REQUIRE):
+ * builds the level-1 nodes (nested-dissection cells, interiors then
+ * separators), their active sets, the cluster adjacency and all index maps
+ * that do not depend on numerical values.
+ *   n            number of unknowns = prod(grid) * dofs_per_node
+ *   row_ptr      HOST int64[n+1], col_idx HOST int32[nnz]: the FULL
+ *                symmetric pattern of A (both triangles), any column order
+ *   coords       HOST double[n_nodes * dim], node positions (row per node)
+ *   opt          options (copied)
+ *   out          receives the new handle (caller destroys it)
+ * The pattern must only couple nodes within one grid step of each other
+ * (the 3^dim vertex stencil assumed in Sec. 5); otherwise SGF_EINVAL.
+ * Host-only: no device memory is touched.
+ */
+sgf_status sgf_analyze(int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
+                       const double* coords, const sgf_options* opt, sgf_handle* out);
+
+/*
+ * Numeric factorization (Algorithm 4.1): per level, block-Cholesky of the
+ * interiors (Eq. 4.2), polynomial compression of the separators
+ * (Eqs. 3.1-3.5, 4.5-4.6), coarsening (Eq. 4.7); exact Cholesky of the
+ * last node (Sec. 4.5).
+ *   vals         DEVICE double[nnz], values of A in the pattern given to
+ *                sgf_analyze (A must be symmetric)
+ * May be called again with new values (same pattern): the previous factor
+ * is replaced.  Synchronizes `stream` once per level (ranks decide the next
+ * level's sizes).  SGF_ENOTSPD when a pivot is not positive.
+ */
+sgf_status sgf_factorize_numeric(sgf_handle h, const double* vals, void* stream);
+
+/* sgf_analyze followed by sgf_factorize_numeric; `vals` may be a host or a
+ * device pointer. */
+sgf_status sgf_factorize(int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
+                         const double* vals, const double* coords,
+                         const sgf_options* opt, void* stream, sgf_handle* out);
+
+/*
+ * z = A_l^{-1} r (Sec. 4.7): forward sweep G_1^{-1}, B_1^{-1}, ..., exact top
+ * solve, backward sweep with the transposes.  r and z are DEVICE FP64
+ * column-major n x nrhs with leading dimensions ldr, ldz >= n; r == z is
+ * allowed.  Does not synchronize.
+ */
+sgf_status sgf_apply(sgf_handle h, int32_t nrhs, const double* r, int64_t ldr,
+                     double* z, int64_t ldz, void* stream);
+
+/* y = A_l v (Sec. 2.1 product form; a test hook for the preservation
+ * property of Prop. 6.1).  Same layout rules as sgf_apply. */
+sgf_status sgf_multiply(sgf_handle h, int32_t nrhs, const double* v, int64_t ldv,
+                        double* y, int64_t ldy, void* stream);
+
+/*
+ * Conjugate gradients on A x = b preconditioned by A_l^{-1} (Sec. 7): x0 = 0,
+ * stop when the recursive residual satisfies ||r_k||_2 / ||b||_2 < rtol.
+ * b, x: DEVICE FP64 column-major n x nrhs; each column is an independent CG
+ * (per-column scalars, converged columns stop updating).  iters, relres:
+ * HOST arrays of nrhs (iterations taken, final recursive relative residual).
+ * Returns SGF_ENOCONV if some column did not converge within maxit.
+ */
+sgf_status sgf_pcg_solve(sgf_handle h, int32_t nrhs, const double* b, int64_t ldb,
+                         double* x, int64_t ldx, double rtol, int32_t maxit,
+                         int32_t* iters, double* relres, void* stream);
+
+/* y = A v with the CSR matrix held by the handle (FP64).  DEVICE pointers. */
+sgf_status sgf_spmv(sgf_handle h, const double* v, double* y, void* stream);
+
+sgf_status sgf_get_info(sgf_handle h, sgf_info* info);
+
+/*
+ * Partition export for bit-exact parity checks.
+ * sgf_get_perm: HOST int64[n]; perm[slot] = unknown stored in level-1 slot
+ *   `slot` (clusters contiguous, ascending cell id; ascending unknown inside).
+ * sgf_get_level: for level t (1-based, t <= info.levels) the number of
+ *   active clusters (return via *count); when the arrays are non-NULL they
+ *   receive, per cluster in ascending cell id: cell id (lexicographic, x
+ *   fastest), cell type (number of odd per-axis classes), size of its active
+ *   set at the start of the level, and its size after the level's
+ *   compressions (= rank when compressed; 0 for eliminated interiors).
+ *   Levels above 1 exist only after sgf_factorize_numeric.
+ */
+sgf_status sgf_get_perm(sgf_handle h, int64_t* perm);
+sgf_status sgf_get_level(sgf_handle h, int32_t level, int32_t* count, int32_t* cell_ids,
+                         int32_t* types, int32_t* sizes, int32_t* ranks);
+
+/*
+ * Host-only dry run of the level planner, for checking the partition
+ * hierarchy without a GPU: replays the coarsening of Sec. 4.3-4.4 with the
+ * compression ranks supplied by `rank_fn(level, cell_id, size, ctx)` (called
+ * once per compressible separator, level 1-based) instead of computed ones.
+ * Afterwards sgf_get_level reports every level.  The handle must not have
+ * been factorized; it stays unfactorized (sgf_factorize_numeric re-plans).
+ */
+typedef int32_t (*sgf_rank_fn)(int32_t level, int64_t cell_id, int32_t size, void* ctx);
+sgf_status sgf_plan_dry_run(sgf_handle h, sgf_rank_fn rank_fn, void* ctx);
+
+/* Releases every host and device resource of the handle (NULL is a no-op). */
+sgf_status sgf_destroy(sgf_handle h);
+
+const char* sgf_status_str(sgf_status s);
+const char* sgf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SGF_H */

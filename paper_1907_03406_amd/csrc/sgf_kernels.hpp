@@ -1,0 +1,841 @@
+// Device kernels of the SGF factorization, apply and CG for gfx950.
+//
+// All kernels are batched over the clusters of one tree level: one
+// workgroup of 256 threads (four 64-wide wavefronts) per cluster, clusters
+// of uneven sizes described by the planner's descriptor tables.  Every sum
+// whose terms come from different clusters is formed by a gather in a fixed
+// order (no floating-point atomics), so results are deterministic.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "sgf_plan.hpp"
+
+namespace sgf {
+
+constexpr int WG = 256;
+constexpr int WAVE = 64;
+constexpr double TIE_RTOL = 1e-10;
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+  for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+  return v;
+}
+
+// Sum over the workgroup; every thread gets the result.  `red` holds WG/WAVE.
+template <typename T>
+__device__ __forceinline__ T block_sum(T v, T* red) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  T s = 0;
+  for (int i = 0; i < WG / WAVE; ++i) s += red[i];
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// Fills and copies
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ void k_fill_csr(const double* __restrict__ vals, const int64_t* __restrict__ dst,
+                           int64_t nnz, T* __restrict__ arena) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < nnz) {
+    int64_t d = dst[e];
+    if (d >= 0) arena[d] = (T)vals[e];
+  }
+}
+
+template <typename T>
+__global__ void k_copy_blocks(const CopyDesc* __restrict__ D, const T* __restrict__ src,
+                              T* __restrict__ dst) {
+  const CopyDesc d = D[blockIdx.x];
+  const int64_t tot = (int64_t)d.rows * d.cols;
+  for (int64_t idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+    int i = (int)(idx % d.rows), j = (int)(idx / d.rows);
+    T v = src[d.src_off + i + (int64_t)j * d.src_ld];
+    if (d.mode == 0) dst[d.dst_off + i + (int64_t)j * d.dst_ld] = v;
+    else dst[d.dst_off + j + (int64_t)i * d.dst_ld] = v;
+  }
+}
+
+template <typename T>
+__global__ void k_zero(T* __restrict__ p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = T(0);
+}
+
+// Phi_B = Pi(B, :) for every level-1 cluster (Sec. 3.1; block diagonal per
+// component for dofs_per_node > 1, Eq. 7.4).  Coordinates normalised
+// globally to [-1, 1]: xh = (x - lo) * sc - 1 with sc = 2 / (hi - lo).
+struct PhiInit {
+  double lo[3], sc[3];
+  int dim, q, dpn, pi, p0;
+};
+
+template <typename T>
+__global__ void k_phi_init(const int64_t* __restrict__ slot_ptr, const int64_t* __restrict__ phi_off,
+                           const int64_t* __restrict__ perm, const double* __restrict__ coords,
+                           PhiInit pin, T* __restrict__ phi) {
+  const int c = blockIdx.x;
+  const int64_t s0 = slot_ptr[c];
+  const int s = (int)(slot_ptr[c + 1] - s0);
+  T* out = phi + phi_off[c];
+  for (int i = threadIdx.x; i < s; i += blockDim.x) {
+    int64_t dof = perm[s0 + i];
+    int64_t node = dof / pin.dpn;
+    int comp = (int)(dof % pin.dpn);
+    double x[3] = {0, 0, 0};
+    for (int a = 0; a < pin.dim; ++a) {
+      double v = coords[node * pin.dim + a];
+      x[a] = pin.sc[a] > 0 ? (v - pin.lo[a]) * pin.sc[a] - 1.0 : 0.0;
+    }
+    double mono[10];
+    int n = 0;
+    mono[n++] = 1.0;
+    if (pin.q >= 1)
+      for (int a = 0; a < pin.dim; ++a) mono[n++] = x[a];
+    if (pin.q >= 2) {
+      for (int a = 0; a < pin.dim; ++a) mono[n++] = x[a] * x[a];
+      if (pin.dim == 2) mono[n++] = x[0] * x[1];
+      else {
+        mono[n++] = x[0] * x[1];
+        mono[n++] = x[1] * x[2];
+        mono[n++] = x[2] * x[0];
+      }
+    }
+    for (int p = 0; p < pin.pi; ++p) {
+      int cc = p / pin.p0, j = p % pin.p0;
+      out[i + (int64_t)p * s] = (cc == comp) ? (T)mono[j] : T(0);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Workgroup dense kernels (column-major matrices in global memory)
+// ---------------------------------------------------------------------------
+
+// Partial Cholesky of the R x R front C (ld): factor the first m columns into
+// [L ; L21] and subtract L21 L21^T from the trailing columns [m, nupd).
+// Right-looking, panels of nbmax columns staged in LDS.  A non-positive pivot
+// sets *fail = code (and continues with pivot 1).
+template <typename T>
+__device__ void wg_potrf(T* __restrict__ C, int64_t ld, int R, int m, int nupd, T* lds,
+                         int nbmax, int* fail, int code) {
+  const int tid = threadIdx.x;
+  for (int jb = 0; jb < m; jb += nbmax) {
+    const int nb = min(nbmax, m - jb);
+    const int pr = R - jb;
+    for (int idx = tid; idx < pr * nb; idx += WG) {
+      int i = idx % pr, p = idx / pr;
+      lds[idx] = C[(jb + i) + (int64_t)(jb + p) * ld];
+    }
+    __syncthreads();
+    for (int j = 0; j < nb; ++j) {
+      T piv = lds[j * pr + j];
+      bool bad = !(piv > T(0));
+      __syncthreads();
+      if (bad) {
+        if (tid == 0) atomicCAS(fail, -1, code);
+        piv = T(1);
+      }
+      const T d = sqrt(piv);
+      const T inv = T(1) / d;
+      for (int i = j + tid; i < pr; i += WG) lds[j * pr + i] = (i == j) ? d : lds[j * pr + i] * inv;
+      __syncthreads();
+      const int ncol = nb - j - 1;
+      for (int idx = tid; idx < ncol * pr; idx += WG) {
+        int l = j + 1 + idx / pr, i = idx % pr;
+        if (i >= l) lds[l * pr + i] -= lds[j * pr + i] * lds[j * pr + l];
+      }
+      __syncthreads();
+    }
+    for (int idx = tid; idx < pr * nb; idx += WG) {
+      int i = idx % pr, p = idx / pr;
+      if (i >= p) C[(jb + i) + (int64_t)(jb + p) * ld] = lds[idx];
+    }
+    // trailing update with 4 x 4 register tiles
+    const int r0 = jb + nb;
+    if (r0 < nupd) {
+      const int RT = (R - r0 + 3) / 4, CT = (nupd - r0 + 3) / 4;
+      for (int idx = tid; idx < RT * CT; idx += WG) {
+        const int rt = idx % RT, ct = idx / RT;
+        if (rt < ct) continue;
+        const int i0 = r0 + 4 * rt, l0 = r0 + 4 * ct;
+        T acc[4][4];
+        for (int a = 0; a < 4; ++a)
+          for (int b = 0; b < 4; ++b) acc[a][b] = 0;
+        for (int p = 0; p < nb; ++p) {
+          const T* col = lds + p * pr - jb;
+          T av[4], bv[4];
+          for (int a = 0; a < 4; ++a) av[a] = (i0 + a < R) ? col[i0 + a] : T(0);
+          for (int b = 0; b < 4; ++b) bv[b] = (l0 + b < nupd) ? col[l0 + b] : T(0);
+          for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b) acc[a][b] += av[a] * bv[b];
+        }
+        for (int b = 0; b < 4; ++b) {
+          const int l = l0 + b;
+          if (l >= nupd) break;
+          for (int a = 0; a < 4; ++a) {
+            const int i = i0 + a;
+            if (i < R && i >= l) C[i + (int64_t)l * ld] -= acc[a][b];
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// X (n x ncols, ldx) <- L^{-1} X with L lower (n x n, ldl).
+template <typename T>
+__device__ void wg_trsm_lower(const T* __restrict__ L, int64_t ldl, int n, T* __restrict__ X,
+                              int64_t ldx, int ncols) {
+  for (int j = 0; j < n; ++j) {
+    const T inv = T(1) / L[j + (int64_t)j * ldl];
+    for (int c = threadIdx.x; c < ncols; c += WG) X[j + (int64_t)c * ldx] *= inv;
+    __syncthreads();
+    const int rows = n - j - 1;
+    for (int idx = threadIdx.x; idx < rows * ncols; idx += WG) {
+      int i = j + 1 + idx % rows, c = idx / rows;
+      X[i + (int64_t)c * ldx] -= L[i + (int64_t)j * ldl] * X[j + (int64_t)c * ldx];
+    }
+    __syncthreads();
+  }
+}
+
+// X (n x ncols, ldx) <- Q^T X, Q = H_0 ... H_{r-1}, reflector k in column k
+// of V (unit diagonal implied, entries below it), coefficients tau.
+template <typename T>
+__device__ void wg_apply_qt(const T* __restrict__ V, int64_t ldv, const T* __restrict__ tau, int n,
+                            int r, T* __restrict__ X, int64_t ldx, int ncols) {
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  for (int k = 0; k < r; ++k) {
+    const T tk = tau[k];
+    if (tk != T(0)) {
+      for (int c = w; c < ncols; c += WG / WAVE) {
+        T* x = X + (int64_t)c * ldx;
+        T s = 0;
+        for (int i = k + lane; i < n; i += WAVE) s += (i == k ? T(1) : V[i + (int64_t)k * ldv]) * x[i];
+        s = wave_sum(s) * tk;
+        for (int i = k + lane; i < n; i += WAVE) x[i] -= s * (i == k ? T(1) : V[i + (int64_t)k * ldv]);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Factorization kernels
+// ---------------------------------------------------------------------------
+
+// Eliminate the interiors of a level (Eq. 4.2): one front per workgroup.
+template <typename T>
+__global__ __launch_bounds__(WG) void k_elim(const ElimDesc* __restrict__ D, T* __restrict__ arena,
+                                             int nbmax, int* fail) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* lds = reinterpret_cast<T*>(smem_raw);
+  const ElimDesc d = D[blockIdx.x];
+  const int R = d.m + d.k;
+  wg_potrf(arena + d.front_off, R, R, d.m, R, lds, nbmax, fail, d.cluster);
+}
+
+// Subtract the interiors' Schur complements from the separator pair blocks,
+// contributions summed in ascending interior order.
+template <typename T>
+__global__ __launch_bounds__(WG) void k_schur(const PairDesc* __restrict__ P, const SchurDesc* __restrict__ S,
+                                              const T* __restrict__ fronts, T* __restrict__ blocks) {
+  const PairDesc pd = P[blockIdx.x];
+  if (pd.c_cnt == 0) return;
+  T* blk = blocks + pd.blk_off;
+  const int tot = pd.s_a * pd.s_b;
+  for (int idx = threadIdx.x; idx < tot; idx += WG) {
+    const int i = idx % pd.s_a, j = idx / pd.s_a;
+    T acc = blk[idx];
+    for (int c = 0; c < pd.c_cnt; ++c) {
+      const SchurDesc s = S[pd.c_ptr + c];
+      const T* src = fronts + s.src_off;
+      if (s.diag) acc += src[max(i, j) + (int64_t)min(i, j) * s.src_ld];
+      else acc += src[j + (int64_t)i * s.src_ld];
+    }
+    blk[idx] = acc;
+  }
+}
+
+// Compression fronts [M_BB ; M_X1B ; ... ] ((s + K) x s) from the pair blocks.
+template <typename T>
+__global__ __launch_bounds__(WG) void k_comp_gather(const CompDesc* __restrict__ D, const CompNbr* __restrict__ NB,
+                                                    const T* __restrict__ blocks, T* __restrict__ cf) {
+  const CompDesc d = D[blockIdx.x];
+  const int64_t ld = d.s + d.K;
+  T* F = cf + d.cf_off;
+  const T* dg = blocks + d.blk_diag;
+  for (int idx = threadIdx.x; idx < d.s * d.s; idx += WG) {
+    int i = idx % d.s, j = idx / d.s;
+    F[i + (int64_t)j * ld] = dg[idx];
+  }
+  for (int q = 0; q < d.nnb; ++q) {
+    const CompNbr x = NB[d.nb_ptr + q];
+    const T* b = blocks + x.blk_off;
+    for (int idx = threadIdx.x; idx < x.s_x * d.s; idx += WG) {
+      int j = idx % x.s_x, i = idx / x.s_x;   // row j of X, column i of B
+      T v = x.trans ? b[i + (int64_t)j * d.s] : b[j + (int64_t)i * x.s_x];
+      F[(x.row + j) + (int64_t)i * ld] = v;
+    }
+  }
+}
+
+// One compression (Eqs. 3.1-3.4): L_B = chol(M_BB), Mhat^T = M_XB L_B^{-T},
+// N = [L^T Phi_B | Mhat_X Phi_X ...], pivoted Householder QR of N stopped at
+// the numerical rank, Phi_B <- (Q^T L^T Phi_B)[:r].
+template <typename T>
+__global__ __launch_bounds__(WG) void k_compress(const CompDesc* __restrict__ D, const CompNbr* __restrict__ NB,
+                                                 T* __restrict__ cf, T* __restrict__ nbuf, T* __restrict__ phi,
+                                                 T* __restrict__ ltphi, T* __restrict__ tau_all,
+                                                 int* __restrict__ rank, int pi, int nbmax, double rank_tol,
+                                                 int* fail) {
+  // Phi of the neighbours is read here and must not change during the launch.
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* lds = reinterpret_cast<T*>(smem_raw);
+  __shared__ T red[WG / WAVE];
+  __shared__ int s_piv, s_stop;
+  __shared__ T s_r00;
+  const CompDesc d = D[blockIdx.x];
+  const int s = d.s, c = d.c;
+  const int64_t ld = s + d.K;
+  T* F = cf + d.cf_off;
+  wg_potrf(F, ld, s + d.K, s, s, lds, nbmax, fail, d.cluster);
+  // ---- N (Eq. 4.5) -----------------------------------------------------------
+  T* N = nbuf + d.n_off;
+  T* PhB = phi + d.phi_off;
+  T* LtP = ltphi + d.ltphi_off;
+  for (int idx = threadIdx.x; idx < s * pi; idx += WG) {
+    int i = idx % s, p = idx / s;
+    T acc = 0;
+    for (int j = i; j < s; ++j) acc += F[j + (int64_t)i * ld] * PhB[j + (int64_t)p * s];
+    N[i + (int64_t)p * s] = acc;
+    LtP[i + (int64_t)p * s] = acc;
+  }
+  for (int q = 0; q < d.nnb; ++q) {
+    const CompNbr x = NB[d.nb_ptr + q];
+    const T* PhX = phi + x.phi_off;
+    for (int idx = threadIdx.x; idx < s * pi; idx += WG) {
+      int i = idx % s, p = idx / s;
+      T acc = 0;
+      for (int j = 0; j < x.s_x; ++j) acc += F[(x.row + j) + (int64_t)i * ld] * PhX[j + (int64_t)p * x.s_x];
+      N[i + (int64_t)(pi * (1 + q) + p) * s] = acc;
+    }
+  }
+  __syncthreads();
+  // ---- pivoted Householder QR of N (Eq. 3.3) ---------------------------------
+  T* norms = lds;  // c entries (the potrf panel is no longer needed)
+  T* tau = tau_all + d.tau_off;
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  int r = 0;
+  const int kmax = min(s, c);
+  for (int k = 0; k < kmax; ++k) {
+    for (int j = k + w; j < c; j += WG / WAVE) {
+      const T* col = N + (int64_t)j * s;
+      T acc = 0;
+      for (int i = k + lane; i < s; i += WAVE) acc += col[i] * col[i];
+      acc = wave_sum(acc);
+      if (lane == 0) norms[j] = sqrt(acc);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      T nmax = 0;
+      for (int j = k; j < c; ++j) nmax = norms[j] > nmax ? norms[j] : nmax;
+      if (k == 0) s_r00 = nmax;
+      int stop = (nmax == T(0)) || (nmax <= (T)rank_tol * s_r00);
+      int piv = k;
+      if (!stop) {
+        const T thr = nmax * (T)(1.0 - TIE_RTOL);
+        for (int j = k; j < c; ++j)
+          if (norms[j] >= thr) { piv = j; break; }
+      }
+      s_piv = piv;
+      s_stop = stop;
+    }
+    __syncthreads();
+    if (s_stop) break;
+    const int piv = s_piv;
+    if (piv != k)
+      for (int i = threadIdx.x; i < s; i += WG) {
+        T a = N[i + (int64_t)k * s], b = N[i + (int64_t)piv * s];
+        N[i + (int64_t)k * s] = b;
+        N[i + (int64_t)piv * s] = a;
+      }
+    __syncthreads();
+    // reflector of column k, rows k..s-1
+    T* x = N + (int64_t)k * s;
+    T part = 0;
+    for (int i = k + 1 + threadIdx.x; i < s; i += WG) part += x[i] * x[i];
+    const T tail = block_sum(part, red);
+    const T alpha = x[k];
+    T beta, tk, scale;
+    if (tail == T(0)) {
+      beta = alpha;
+      tk = 0;
+      scale = 0;
+    } else {
+      const T nrm = sqrt(alpha * alpha + tail);
+      beta = alpha >= T(0) ? -nrm : nrm;
+      tk = (beta - alpha) / beta;
+      scale = T(1) / (alpha - beta);
+    }
+    __syncthreads();
+    if (tk != T(0))
+      for (int i = k + 1 + threadIdx.x; i < s; i += WG) x[i] *= scale;
+    __syncthreads();
+    if (tk != T(0))
+      for (int j = k + 1 + w; j < c; j += WG / WAVE) {
+        T* y = N + (int64_t)j * s;
+        T acc = 0;
+        for (int i = k + lane; i < s; i += WAVE) acc += (i == k ? T(1) : x[i]) * y[i];
+        acc = wave_sum(acc) * tk;
+        for (int i = k + lane; i < s; i += WAVE) y[i] -= acc * (i == k ? T(1) : x[i]);
+      }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      x[k] = beta;
+      tau[k] = tk;
+    }
+    __syncthreads();
+    ++r;
+  }
+  // ---- (Q^T L^T Phi_B)[:r] (Eq. 3.4) into the scratch; neighbours may still be
+  // reading Phi_B, so k_phi_commit installs it after every compression ended.
+  if (r < s) wg_apply_qt(N, s, tau, s, r, LtP, s, pi);
+  if (threadIdx.x == 0) rank[blockIdx.x] = r;
+}
+
+// Phi_B <- (Q^T L^T Phi_B)[:r] for the separators that were compressed.
+template <typename T>
+__global__ __launch_bounds__(WG) void k_phi_commit(const CompDesc* __restrict__ D, const int* __restrict__ rank,
+                                                   const T* __restrict__ ltphi, T* __restrict__ phi, int pi) {
+  const CompDesc d = D[blockIdx.x];
+  const int r = rank[blockIdx.x];
+  if (r >= d.s) return;
+  for (int idx = threadIdx.x; idx < r * pi; idx += WG) {
+    int i = idx % r, p = idx / r;
+    phi[d.phi_off + i + (int64_t)p * d.s] = ltphi[d.ltphi_off + i + (int64_t)p * d.s];
+  }
+}
+
+// Coarse couplings C_ab = T_a M_ab T_b^T with T = Q_1^T L^{-1} for compressed
+// separators and T = I otherwise; the diagonal of a compressed separator
+// becomes I_r (Sec. 3.2: the scaled, rotated block; fine rows dropped).
+template <typename T>
+__global__ __launch_bounds__(WG) void k_pair(const PairDesc* __restrict__ P, const CompDesc* __restrict__ D,
+                                             const int* __restrict__ rank, const T* __restrict__ cf,
+                                             const T* __restrict__ nbuf, const T* __restrict__ tau_all,
+                                             T* __restrict__ blocks, T* __restrict__ scratch) {
+  const PairDesc pd = P[blockIdx.x];
+  const int sa = pd.s_a, sb = pd.s_b;
+  const int ra = (pd.ca >= 0 && rank[pd.ca] < sa) ? rank[pd.ca] : sa;
+  const int rb = (pd.cb >= 0 && rank[pd.cb] < sb) ? rank[pd.cb] : sb;
+  const bool ca = ra < sa, cb = rb < sb;
+  T* blk = blocks + pd.blk_off;
+  if (pd.a == pd.b) {
+    if (ca)
+      for (int idx = threadIdx.x; idx < ra * ra; idx += WG) {
+        int i = idx % ra, j = idx / ra;
+        blk[i + (int64_t)j * sa] = (i == j) ? T(1) : T(0);
+      }
+    return;
+  }
+  if (!ca && !cb) return;
+  T* G = scratch + pd.scratch_off;             // sa x sb, ld sa
+  T* H = G + (int64_t)sa * sb;                 // sb x ra, ld sb
+  if (ca) {
+    const CompDesc da = D[pd.ca];
+    const int64_t lda = da.s + da.K;
+    const T* Fa = cf + da.cf_off;
+    for (int idx = threadIdx.x; idx < sa * sb; idx += WG) {
+      int i = idx % sa, j = idx / sa;
+      G[idx] = Fa[(pd.row_in_a + j) + (int64_t)i * lda];
+    }
+    __syncthreads();
+    wg_apply_qt(nbuf + da.n_off, sa, tau_all + da.tau_off, sa, ra, G, sa, sb);
+  } else {
+    for (int idx = threadIdx.x; idx < sa * sb; idx += WG) G[idx] = blk[idx];
+  }
+  __syncthreads();
+  if (cb) {
+    const CompDesc db = D[pd.cb];
+    const int64_t ldb = db.s + db.K;
+    for (int idx = threadIdx.x; idx < sb * ra; idx += WG) {
+      int j = idx % sb, i = idx / sb;
+      H[j + (int64_t)i * sb] = G[i + (int64_t)j * sa];
+    }
+    __syncthreads();
+    wg_trsm_lower(cf + db.cf_off, ldb, sb, H, sb, ra);
+    wg_apply_qt(nbuf + db.n_off, sb, tau_all + db.tau_off, sb, rb, H, sb, ra);
+    for (int idx = threadIdx.x; idx < ra * rb; idx += WG) {
+      int i = idx % ra, j = idx / ra;
+      blk[i + (int64_t)j * sa] = H[j + (int64_t)i * sb];
+    }
+  } else {
+    for (int idx = threadIdx.x; idx < ra * sb; idx += WG) {
+      int i = idx % ra, j = idx / ra;
+      blk[i + (int64_t)j * sa] = G[i + (int64_t)j * sa];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Apply kernels (Sec. 4.7) and the product form (Sec. 2.1)
+// ---------------------------------------------------------------------------
+
+// y (m) <- L^{-1} y in LDS, L lower with ld, blocks of 64 solved by wave 0.
+template <typename T>
+__device__ void wg_trsv_lower(const T* __restrict__ L, int64_t ld, int m, T* ys) {
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  for (int jb = 0; jb < m; jb += WAVE) {
+    const int nb = min(WAVE, m - jb);
+    if (w == 0) {
+      T v = lane < nb ? ys[jb + lane] : T(0);
+      for (int j = 0; j < nb; ++j) {
+        T xj = __shfl(v, j, WAVE) / L[(jb + j) + (int64_t)(jb + j) * ld];
+        if (lane == j) v = xj;
+        if (lane > j && lane < nb) v -= L[(jb + lane) + (int64_t)(jb + j) * ld] * xj;
+      }
+      if (lane < nb) ys[jb + lane] = v;
+    }
+    __syncthreads();
+    for (int i = jb + nb + threadIdx.x; i < m; i += WG) {
+      T acc = 0;
+      for (int j = 0; j < nb; ++j) acc += L[i + (int64_t)(jb + j) * ld] * ys[jb + j];
+      ys[i] -= acc;
+    }
+    __syncthreads();
+  }
+}
+
+// y (m) <- L^{-T} y in LDS.
+template <typename T>
+__device__ void wg_trsv_lower_t(const T* __restrict__ L, int64_t ld, int m, T* ys) {
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  const int nblk = (m + WAVE - 1) / WAVE;
+  for (int bj = nblk - 1; bj >= 0; --bj) {
+    const int jb = bj * WAVE, nb = min(WAVE, m - jb), below = jb + nb;
+    // y_J -= L[below:, J]^T y[below:]
+    for (int j = jb + w; j < below; j += WG / WAVE) {
+      T acc = 0;
+      for (int i = below + lane; i < m; i += WAVE) acc += L[i + (int64_t)j * ld] * ys[i];
+      acc = wave_sum(acc);
+      if (lane == 0) ys[j] -= acc;
+    }
+    __syncthreads();
+    if (w == 0) {
+      T v = lane < nb ? ys[jb + lane] : T(0);
+      for (int j = nb - 1; j >= 0; --j) {
+        T xj = __shfl(v, j, WAVE) / L[(jb + j) + (int64_t)(jb + j) * ld];
+        if (lane == j) v = xj;
+        if (lane < j) v -= L[(jb + j) + (int64_t)(jb + lane) * ld] * xj;
+      }
+      if (lane < nb) ys[jb + lane] = v;
+    }
+    __syncthreads();
+  }
+}
+
+// Forward step of one interior: y_I <- L^{-1} y_I, t <- W^T y_I (to scratch).
+// mode 1 (product form): y_I <- L y_I, t <- W^T y_I (before the multiply).
+template <typename T>
+__global__ __launch_bounds__(WG) void k_elim_fwd(const ElimDesc* __restrict__ D, const T* __restrict__ arena,
+                                                 const int32_t* __restrict__ slots, T* __restrict__ y, int64_t ldy,
+                                                 T* __restrict__ tscr, int64_t ldt, int mode) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* ys = reinterpret_cast<T*>(smem_raw);
+  const ElimDesc d = D[blockIdx.x];
+  const int m = d.m, k = d.k;
+  const int64_t R = (int64_t)m + k;
+  const T* C = arena + d.front_off;
+  T* yv = y + blockIdx.y * ldy;
+  const int32_t* sl = slots + d.slot_off;
+  for (int i = threadIdx.x; i < m; i += WG) ys[i] = yv[sl[i]];
+  __syncthreads();
+  if (mode == 0) wg_trsv_lower(C, R, m, ys);
+  T* tv = tscr + blockIdx.y * ldt + d.t_off;
+  for (int a = threadIdx.x; a < k; a += WG) {
+    T acc = 0;
+    for (int j = 0; j < m; ++j) acc += C[(m + a) + (int64_t)j * R] * ys[j];
+    tv[a] = acc;
+  }
+  if (mode == 1) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < m; i += WG) {
+      T acc = 0;
+      for (int j = 0; j <= i; ++j) acc += C[i + (int64_t)j * R] * ys[j];
+      yv[sl[i]] = acc;
+    }
+  } else {
+    for (int i = threadIdx.x; i < m; i += WG) yv[sl[i]] = ys[i];
+  }
+}
+
+// y_S <- y_S + sign * sum_I t_I[S part], interiors in ascending order.
+template <typename T>
+__global__ __launch_bounds__(WG) void k_sepacc(const SepAcc* __restrict__ A, const int64_t* __restrict__ src,
+                                               const int32_t* __restrict__ slots, const T* __restrict__ tscr,
+                                               int64_t ldt, T* __restrict__ y, int64_t ldy, T sign) {
+  const SepAcc a = A[blockIdx.x];
+  T* yv = y + blockIdx.y * ldy;
+  const T* tv = tscr + blockIdx.y * ldt;
+  for (int i = threadIdx.x; i < a.s; i += WG) {
+    int32_t sl = slots[a.slot_off + i];
+    T acc = 0;
+    for (int c = 0; c < a.c_cnt; ++c) acc += tv[src[a.c_ptr + c] + i];
+    yv[sl] += sign * acc;
+  }
+}
+
+// Backward step of one interior: y_I <- L^{-T} (y_I - W y_S).
+// mode 1 (product form, first half): y_I <- L^T y_I + W y_S.
+template <typename T>
+__global__ __launch_bounds__(WG) void k_elim_bwd(const ElimDesc* __restrict__ D, const T* __restrict__ arena,
+                                                 const int32_t* __restrict__ slots, const int32_t* __restrict__ nslots,
+                                                 T* __restrict__ y, int64_t ldy, int mode) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const ElimDesc d = D[blockIdx.x];
+  const int m = d.m, k = d.k;
+  T* ys = reinterpret_cast<T*>(smem_raw);
+  T* g = ys + m;
+  const int64_t R = (int64_t)m + k;
+  const T* C = arena + d.front_off;
+  T* yv = y + blockIdx.y * ldy;
+  const int32_t* sl = slots + d.slot_off;
+  const int32_t* ns = nslots + d.nslot_off;
+  for (int i = threadIdx.x; i < m; i += WG) ys[i] = yv[sl[i]];
+  for (int a = threadIdx.x; a < k; a += WG) g[a] = yv[ns[a]];
+  __syncthreads();
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  if (mode == 0) {
+    for (int j = w; j < m; j += WG / WAVE) {
+      T acc = 0;
+      for (int a = lane; a < k; a += WAVE) acc += C[(m + a) + (int64_t)j * R] * g[a];
+      acc = wave_sum(acc);
+      if (lane == 0) ys[j] -= acc;
+    }
+    __syncthreads();
+    wg_trsv_lower_t(C, R, m, ys);
+    for (int i = threadIdx.x; i < m; i += WG) yv[sl[i]] = ys[i];
+  } else {
+    // out_j = sum_{i >= j} L_ij ys_i + sum_a W^T_aj g_a
+    T* out = g + k;
+    for (int j = w; j < m; j += WG / WAVE) {
+      T acc = 0;
+      for (int i = j + lane; i < m; i += WAVE) acc += C[i + (int64_t)j * R] * ys[i];
+      for (int a = lane; a < k; a += WAVE) acc += C[(m + a) + (int64_t)j * R] * g[a];
+      acc = wave_sum(acc);
+      if (lane == 0) out[j] = acc;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < m; i += WG) yv[sl[i]] = out[i];
+  }
+}
+
+// Compressed separators: mode 0: y_B <- Q^T L^{-1} y_B; mode 1: y_B <- L^{-T} Q y_B;
+// mode 2 (product): y_B <- Q^T L^T y_B; mode 3 (product): y_B <- L Q y_B.
+template <typename T>
+__global__ __launch_bounds__(WG) void k_comp_apply(const CompApply* __restrict__ A, const T* __restrict__ cf,
+                                                   const T* __restrict__ nbuf, const T* __restrict__ tau_all,
+                                                   const int32_t* __restrict__ slots, T* __restrict__ y, int64_t ldy,
+                                                   int mode) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ T red[WG / WAVE];
+  const CompApply a = A[blockIdx.x];
+  const int s = a.s;
+  T* ys = reinterpret_cast<T*>(smem_raw);
+  T* tmp = ys + s;
+  const T* L = cf + a.cf_off;
+  const T* V = nbuf + a.v_off;
+  const T* tau = tau_all + a.tau_off;
+  T* yv = y + blockIdx.y * ldy;
+  const int32_t* sl = slots + a.slot_off;
+  for (int i = threadIdx.x; i < s; i += WG) ys[i] = yv[sl[i]];
+  __syncthreads();
+  auto qt = [&](bool transpose_order) {
+    for (int kk = 0; kk < a.r; ++kk) {
+      const int k = transpose_order ? kk : a.r - 1 - kk;
+      T part = 0;
+      for (int i = k + threadIdx.x; i < s; i += WG) part += (i == k ? T(1) : V[i + (int64_t)k * s]) * ys[i];
+      const T wk = block_sum(part, red) * tau[k];
+      for (int i = k + threadIdx.x; i < s; i += WG) ys[i] -= wk * (i == k ? T(1) : V[i + (int64_t)k * s]);
+      __syncthreads();
+    }
+  };
+  if (mode == 0) {
+    wg_trsv_lower(L, a.ld, s, ys);
+    qt(true);
+  } else if (mode == 1) {
+    qt(false);
+    wg_trsv_lower_t(L, a.ld, s, ys);
+  } else if (mode == 2) {
+    for (int j = threadIdx.x; j < s; j += WG) {
+      T acc = 0;
+      for (int i = j; i < s; ++i) acc += L[i + (int64_t)j * a.ld] * ys[i];
+      tmp[j] = acc;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < s; i += WG) ys[i] = tmp[i];
+    __syncthreads();
+    qt(true);
+  } else {
+    qt(false);
+    for (int i = threadIdx.x; i < s; i += WG) {
+      T acc = 0;
+      for (int j = 0; j <= i; ++j) acc += L[i + (int64_t)j * a.ld] * ys[j];
+      tmp[i] = acc;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < s; i += WG) ys[i] = tmp[i];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < s; i += WG) yv[sl[i]] = ys[i];
+}
+
+// Top node: mode 0: y <- L^{-T} L^{-1} y; mode 1: y <- L L^T y.
+template <typename T>
+__global__ __launch_bounds__(WG) void k_top(const ElimDesc* __restrict__ D, const T* __restrict__ arena,
+                                            const int32_t* __restrict__ slots, T* __restrict__ y, int64_t ldy,
+                                            int mode) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* ys = reinterpret_cast<T*>(smem_raw);
+  const ElimDesc d = D[0];
+  const int m = d.m;
+  T* tmp = ys + m;
+  const T* L = arena + d.front_off;
+  T* yv = y + blockIdx.y * ldy;
+  const int32_t* sl = slots + d.slot_off;
+  for (int i = threadIdx.x; i < m; i += WG) ys[i] = yv[sl[i]];
+  __syncthreads();
+  if (mode == 0) {
+    wg_trsv_lower(L, m, m, ys);
+    wg_trsv_lower_t(L, m, m, ys);
+  } else {
+    const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+    for (int j = w; j < m; j += WG / WAVE) {
+      T acc = 0;
+      for (int i = j + lane; i < m; i += WAVE) acc += L[i + (int64_t)j * m] * ys[i];
+      acc = wave_sum(acc);
+      if (lane == 0) tmp[j] = acc;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < m; i += WG) {
+      T acc = 0;
+      for (int j = 0; j <= i; ++j) acc += L[i + (int64_t)j * m] * tmp[j];
+      ys[i] = acc;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < m; i += WG) yv[sl[i]] = ys[i];
+}
+
+// Permutation between the caller's unknown order and the slot order.
+template <typename TI, typename TO>
+__global__ void k_gather_perm(const int64_t* __restrict__ perm, int64_t n, const TI* __restrict__ in, int64_t ldi,
+                              TO* __restrict__ out, int64_t ldo) {
+  int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < n) out[s + blockIdx.y * ldo] = (TO)in[perm[s] + blockIdx.y * ldi];
+}
+template <typename TI, typename TO>
+__global__ void k_scatter_perm(const int64_t* __restrict__ perm, int64_t n, const TI* __restrict__ in, int64_t ldi,
+                               TO* __restrict__ out, int64_t ldo) {
+  int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < n) out[perm[s] + blockIdx.y * ldo] = (TO)in[s + blockIdx.y * ldi];
+}
+
+// ---------------------------------------------------------------------------
+// CG kernels (FP64)
+// ---------------------------------------------------------------------------
+
+// y = A x (CSR, one row per thread); partial[b] = sum over the block's rows of x_i y_i.
+__global__ __launch_bounds__(WG) void k_spmv_dot(const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                                 const double* __restrict__ va, int64_t n,
+                                                 const double* __restrict__ x, int64_t ldx, double* __restrict__ y,
+                                                 int64_t ldy, double* __restrict__ partial) {
+  __shared__ double red[WG / WAVE];
+  const double* xv = x + blockIdx.y * ldx;
+  double* yv = y + blockIdx.y * ldy;
+  int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+  double dot = 0;
+  if (i < n) {
+    double acc = 0;
+    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) acc += va[e] * xv[ci[e]];
+    yv[i] = acc;
+    dot = acc * xv[i];
+  }
+  double s = block_sum(dot, red);
+  if (threadIdx.x == 0 && partial) partial[blockIdx.y * gridDim.x + blockIdx.x] = s;
+}
+
+// partial[b] = sum over the block of a_i * b_i.
+__global__ __launch_bounds__(WG) void k_dot_partial(const double* __restrict__ a, int64_t lda,
+                                                    const double* __restrict__ b, int64_t ldb, int64_t n,
+                                                    double* __restrict__ partial) {
+  __shared__ double red[WG / WAVE];
+  const double* av = a + blockIdx.y * lda;
+  const double* bv = b + blockIdx.y * ldb;
+  double acc = 0;
+  for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) acc += av[i] * bv[i];
+  double s = block_sum(acc, red);
+  if (threadIdx.x == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = s;
+}
+
+// out[col] = sum of npart partials (fixed order), one workgroup per column.
+__global__ __launch_bounds__(WG) void k_reduce(const double* __restrict__ partial, int npart,
+                                               double* __restrict__ out) {
+  __shared__ double red[WG / WAVE];
+  const double* p = partial + (int64_t)blockIdx.x * npart;
+  double acc = 0;
+  for (int i = threadIdx.x; i < npart; i += WG) acc += p[i];
+  double s = block_sum(acc, red);
+  if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
+// CG scalars per column.  st layout per column: [rz, pAp, rr, alpha, beta, active].
+__global__ void k_cg_alpha(double* st, int nrhs) {
+  int c = threadIdx.x;
+  if (c < nrhs) {
+    double* s = st + 8 * c;
+    s[3] = (s[5] != 0.0 && s[1] != 0.0) ? s[0] / s[1] : 0.0;
+  }
+}
+__global__ void k_cg_beta(double* st, const double* rz_new, int nrhs) {
+  int c = threadIdx.x;
+  if (c < nrhs) {
+    double* s = st + 8 * c;
+    s[4] = (s[5] != 0.0 && s[0] != 0.0) ? rz_new[c] / s[0] : 0.0;
+    if (s[5] != 0.0) s[0] = rz_new[c];
+  }
+}
+
+// x += alpha p, r -= alpha Ap
+__global__ void k_cg_update_xr(double* __restrict__ x, int64_t ldx, double* __restrict__ r, int64_t ldr,
+                               const double* __restrict__ p, const double* __restrict__ Ap, int64_t ldp, int64_t n,
+                               const double* __restrict__ st) {
+  const double alpha = st[8 * blockIdx.y + 3];
+  if (alpha == 0.0) return;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    x[i + blockIdx.y * ldx] += alpha * p[i + blockIdx.y * ldp];
+    r[i + blockIdx.y * ldr] -= alpha * Ap[i + blockIdx.y * ldp];
+  }
+}
+// p = z + beta p
+__global__ void k_cg_update_p(double* __restrict__ p, const double* __restrict__ z, int64_t ld, int64_t n,
+                              const double* __restrict__ st) {
+  if (st[8 * blockIdx.y + 5] == 0.0) return;
+  const double beta = st[8 * blockIdx.y + 4];
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i + blockIdx.y * ld] = z[i + blockIdx.y * ld] + beta * p[i + blockIdx.y * ld];
+}
+
+}  // namespace sgf

@@ -1,0 +1,832 @@
+// C ABI of the SGF library: handles, device memory, the level loop of the
+// factorization (Algorithm 4.1), the preconditioner apply (Sec. 4.7), the
+// product form (Sec. 2.1) and preconditioned CG (Sec. 7).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "sgf.h"
+#include "sgf_kernels.hpp"
+#include "sgf_plan.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct SgfError : std::runtime_error {
+  sgf_status code;
+  SgfError(sgf_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIP_CHECK(expr)                                                                      \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      throw SgfError(SGF_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));       \
+  } while (0)
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) {
+    o.p = nullptr;
+    o.bytes = 0;
+  }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) {
+      release();
+      p = o.p;
+      bytes = o.bytes;
+      o.p = nullptr;
+      o.bytes = 0;
+    }
+    return *this;
+  }
+  void ensure(size_t b) {
+    if (b <= bytes && p) return;
+    release();
+    size_t want = b ? b : 16;
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+      p = nullptr;
+      bytes = 0;
+      (void)hipGetLastError();
+      throw SgfError(SGF_ENOMEM, "hipMalloc of " + std::to_string(want) + " bytes failed");
+    }
+    bytes = want;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <typename T>
+  T* as() const {
+    return reinterpret_cast<T*>(p);
+  }
+  ~DevBuf() { release(); }
+};
+
+template <typename V>
+void upload(DevBuf& b, const std::vector<V>& v, hipStream_t st) {
+  b.ensure(v.size() * sizeof(V));
+  if (!v.empty()) HIP_CHECK(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(V), hipMemcpyHostToDevice, st));
+}
+
+struct LevelDev {
+  DevBuf arena, scratch, cf, nbuf, ltphi, tau, phi, rank;
+  DevBuf elim, pairs, schur, comp, compnbr, sepacc, sepsrc, capply, slots, nslots;
+  DevBuf blkmap, phimap, slotptr, phioff;
+  std::vector<sgf::CopyDesc> h_blkmap, h_phimap;
+};
+
+constexpr size_t LDS_BYTES = 64 * 1024;
+
+inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+}  // namespace
+
+struct sgf_handle_s {
+  sgf::Plan plan;
+  std::vector<int64_t> h_rowptr;
+  std::vector<int32_t> h_colidx;
+  std::vector<double> h_coords;
+  int64_t nnz = 0;
+  size_t esz = 8;
+  bool dev_static = false;   // CSR structure, perm, coords, fill map on the device
+  bool factored = false;
+  DevBuf d_perm, d_rowptr, d_colidx, d_vals, d_csrdst, d_coords, d_fail;
+  std::vector<LevelDev> lev;
+  DevBuf y, tscr;
+  DevBuf cg_r, cg_z, cg_p, cg_ap, cg_part, cg_st, cg_scal;
+  int64_t max_t = 0;
+  int32_t max_m_all = 0, max_k_all = 0, max_s_all = 0;
+  int32_t failed_cluster = -1, failed_level = -1;
+  double factor_flops = 0, apply_bytes = 0;
+  int64_t factor_entries = 0, factor_bytes = 0, compressed = 0;
+};
+
+namespace {
+
+sgf_status fail(sgf_status c, const std::string& m) {
+  g_last_error = m;
+  return c;
+}
+
+template <typename F>
+sgf_status guard(F&& f) {
+  try {
+    f();
+    return SGF_OK;
+  } catch (const SgfError& e) {
+    return fail(e.code, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(SGF_ENOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(SGF_EINVAL, e.what());
+  }
+}
+
+void check_options(const sgf_options* o, int64_t n) {
+  if (!o) throw SgfError(SGF_EINVAL, "options pointer is NULL");
+  if (o->dim != 2 && o->dim != 3) throw SgfError(SGF_EINVAL, "dim must be 2 or 3");
+  int64_t nodes = 1;
+  for (int a = 0; a < o->dim; ++a) {
+    if (o->grid[a] < 1) throw SgfError(SGF_EINVAL, "grid sizes must be positive");
+    nodes *= o->grid[a];
+  }
+  if (o->dofs_per_node < 1) throw SgfError(SGF_EINVAL, "dofs_per_node must be >= 1");
+  if (nodes * o->dofs_per_node != n) throw SgfError(SGF_EINVAL, "n != prod(grid) * dofs_per_node");
+  if (o->q < 0 || o->q > 2) throw SgfError(SGF_EINVAL, "q must be 0, 1 or 2");
+  if (o->leaf < 2) throw SgfError(SGF_EINVAL, "leaf must be > 1");
+  if (o->scheme != SGF_NEST_ALL_ALL && o->scheme != SGF_NEST_2_ALL) throw SgfError(SGF_EINVAL, "unknown scheme");
+  if (o->precision != SGF_FP64 && o->precision != SGF_FP32) throw SgfError(SGF_EINVAL, "unknown precision");
+  if (o->stop_rule != SGF_STOP_ROOT && o->stop_rule != SGF_STOP_PAPER) throw SgfError(SGF_EINVAL, "unknown stop rule");
+  if (n >= (int64_t)1 << 31) throw SgfError(SGF_EINVAL, "n must be below 2^31");
+}
+
+int nb_for(int rows, size_t esz, int cap = 32) {
+  int nb = (int)(LDS_BYTES / ((size_t)std::max(rows, 1) * esz));
+  nb = std::min(nb, cap);
+  if (nb < 1) throw SgfError(SGF_EINVAL, "front of " + std::to_string(rows) + " rows does not fit the LDS panel");
+  return nb;
+}
+
+void ensure_static(sgf_handle h, hipStream_t st) {
+  if (h->dev_static) return;
+  upload(h->d_perm, h->plan.perm, st);
+  upload(h->d_rowptr, h->h_rowptr, st);
+  upload(h->d_colidx, h->h_colidx, st);
+  upload(h->d_csrdst, h->plan.csr_dst, st);
+  upload(h->d_coords, h->h_coords, st);
+  h->d_vals.ensure(h->nnz * sizeof(double));
+  h->d_fail.ensure(sizeof(int));
+  h->dev_static = true;
+}
+
+// Upload the descriptor tables of level index li and size its buffers.
+void upload_level(sgf_handle h, int li, hipStream_t st) {
+  sgf::Level& L = h->plan.levels[li];
+  if ((int)h->lev.size() <= li) h->lev.resize(li + 1);
+  LevelDev& D = h->lev[li];
+  const size_t e = h->esz;
+  D.arena.ensure((L.front_elems + L.blk_elems) * e);
+  D.scratch.ensure(L.scratch_elems * e);
+  D.cf.ensure(L.cf_elems * e);
+  D.nbuf.ensure(L.n_elems * e);
+  D.ltphi.ensure(L.ltphi_elems * e);
+  D.tau.ensure(L.tau_elems * e);
+  D.phi.ensure(L.phi_elems * e);
+  D.rank.ensure(std::max<size_t>(L.comp.size(), 1) * sizeof(int));
+  upload(D.elim, L.elim, st);
+  upload(D.pairs, L.pairs, st);
+  upload(D.schur, L.schur, st);
+  upload(D.comp, L.comp, st);
+  upload(D.compnbr, L.comp_nbr, st);
+  upload(D.sepacc, L.sepacc, st);
+  upload(D.sepsrc, L.sepacc_src, st);
+  upload(D.slots, L.slots, st);
+  upload(D.nslots, L.nslots, st);
+  upload(D.slotptr, L.slot_ptr, st);
+  upload(D.phioff, L.phi_off, st);
+}
+
+template <typename T>
+void zero(DevBuf& b, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  unsigned g = std::min<int64_t>(cdiv(n, sgf::WG), 65536);
+  hipLaunchKernelGGL(sgf::k_zero<T>, dim3(g), dim3(sgf::WG), 0, st, b.as<T>(), n);
+}
+
+int check_fail(sgf_handle h, hipStream_t st) {
+  int f = -1;
+  HIP_CHECK(hipMemcpyAsync(&f, h->d_fail.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  return f;
+}
+
+void account_level(sgf_handle h, const sgf::Level& L) {
+  for (const auto& d : L.elim) {
+    double m = d.m, k = d.k;
+    h->factor_flops += m * m * m / 3.0 + m * m * k + m * k * k;
+    h->factor_entries += (int64_t)d.m * (d.m + 1) / 2 + (int64_t)d.m * d.k;
+    h->apply_bytes += 2.0 * ((double)d.m * (d.m + 1) / 2 + (double)d.m * d.k) * h->esz;
+  }
+  const int pi = h->plan.pi;
+  for (size_t c = 0; c < L.comp.size(); ++c) {
+    const auto& d = L.comp[c];
+    double s = d.s, K = d.K, cc = d.c, r = L.rank.empty() ? 0 : L.rank[c];
+    h->factor_flops += s * s * s / 3.0 + s * s * K + s * s * pi + 2.0 * s * K * pi;
+    h->factor_flops += 4.0 * s * cc * r - 2.0 * r * r * (s + cc) + 4.0 * r * r * r / 3.0;
+  }
+  for (const auto& a : L.capply) {
+    h->factor_entries += (int64_t)a.s * (a.s + 1) / 2 + (int64_t)a.s * a.r;
+    h->apply_bytes += 2.0 * ((double)a.s * (a.s + 1) / 2 + (double)a.s * a.r) * h->esz;
+  }
+  for (const auto& p : L.pairs) {
+    if (p.a == p.b) continue;
+    int ra = p.ca >= 0 && L.rank[p.ca] < p.s_a ? L.rank[p.ca] : p.s_a;
+    int rb = p.cb >= 0 && L.rank[p.cb] < p.s_b ? L.rank[p.cb] : p.s_b;
+    if (ra < p.s_a) h->factor_flops += 4.0 * (double)p.s_a * ra * p.s_b;
+    if (rb < p.s_b) h->factor_flops += (double)p.s_b * p.s_b * ra + 4.0 * (double)p.s_b * rb * ra;
+  }
+}
+
+template <typename T>
+void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
+  sgf::Plan& P = h->plan;
+  ensure_static(h, st);
+  // the numeric phase re-plans every level above the first (ranks decide them)
+  if (P.levels.size() > 1) P.levels.resize(1);
+  P.parts.resize(1);
+  P.max_node = 0;
+  for (int s : P.levels[0].size) P.max_node = std::max<int64_t>(P.max_node, s);
+  h->factored = false;
+  h->factor_flops = 0;
+  h->apply_bytes = 0;
+  h->factor_entries = 0;
+  h->compressed = 0;
+  h->failed_cluster = h->failed_level = -1;
+  h->max_t = 0;
+  h->max_m_all = h->max_k_all = h->max_s_all = 0;
+  if (vals != h->d_vals.as<double>())
+    HIP_CHECK(hipMemcpyAsync(h->d_vals.p, vals, h->nnz * sizeof(double), hipMemcpyDefault, st));
+  int init = -1;
+  HIP_CHECK(hipMemcpyAsync(h->d_fail.p, &init, sizeof(int), hipMemcpyHostToDevice, st));
+  // ---- level 1 inputs ---------------------------------------------------------
+  upload_level(h, 0, st);
+  {
+    sgf::Level& L = P.levels[0];
+    LevelDev& D = h->lev[0];
+    zero<T>(D.arena, L.front_elems + L.blk_elems, st);
+    hipLaunchKernelGGL(sgf::k_fill_csr<T>, dim3(cdiv(h->nnz, sgf::WG)), dim3(sgf::WG), 0, st,
+                       h->d_vals.as<double>(), h->d_csrdst.as<int64_t>(), h->nnz, D.arena.as<T>());
+    sgf::PhiInit pin{};
+    for (int a = 0; a < 3; ++a) {
+      pin.lo[a] = P.cmin[a];
+      pin.sc[a] = P.cmax[a] > P.cmin[a] ? 2.0 / (P.cmax[a] - P.cmin[a]) : 0.0;
+    }
+    pin.dim = P.opt.dim;
+    pin.q = P.opt.q;
+    pin.dpn = P.opt.dpn;
+    pin.pi = P.pi;
+    pin.p0 = P.pi / P.opt.dpn;
+    if (!L.cell.empty())
+      hipLaunchKernelGGL(sgf::k_phi_init<T>, dim3((unsigned)L.cell.size()), dim3(sgf::WG), 0, st,
+                         D.slotptr.as<int64_t>(), D.phioff.as<int64_t>(), h->d_perm.as<int64_t>(),
+                         h->d_coords.as<double>(), pin, D.phi.as<T>());
+  }
+  // ---- level loop (Algorithm 4.1) --------------------------------------------
+  for (int li = 0;; ++li) {
+    sgf::Level& L = P.levels[li];
+    LevelDev& D = h->lev[li];
+    T* arena = D.arena.as<T>();
+    T* blocks = arena + L.front_elems;
+    for (const auto& e : L.elim) {
+      h->max_m_all = std::max(h->max_m_all, e.m);
+      h->max_k_all = std::max(h->max_k_all, e.k);
+    }
+    h->max_t = std::max(h->max_t, L.t_elems);
+    if (!L.elim.empty()) {
+      int nb = nb_for(L.max_front_rows, sizeof(T));
+      size_t lds = (size_t)nb * L.max_front_rows * sizeof(T);
+      hipLaunchKernelGGL(sgf::k_elim<T>, dim3((unsigned)L.elim.size()), dim3(sgf::WG), lds, st,
+                         D.elim.as<sgf::ElimDesc>(), arena, nb, h->d_fail.as<int>());
+    }
+    if (L.top) {
+      int f = check_fail(h, st);
+      HIP_CHECK(hipGetLastError());
+      if (f >= 0) {
+        h->failed_cluster = f;
+        h->failed_level = L.t;
+        throw SgfError(SGF_ENOTSPD, "non-positive pivot at the top node");
+      }
+      account_level(h, L);
+      break;
+    }
+    if (!L.pairs.empty())
+      hipLaunchKernelGGL(sgf::k_schur<T>, dim3((unsigned)L.pairs.size()), dim3(sgf::WG), 0, st,
+                         D.pairs.as<sgf::PairDesc>(), D.schur.as<sgf::SchurDesc>(), arena, blocks);
+    if (!L.comp.empty()) {
+      hipLaunchKernelGGL(sgf::k_comp_gather<T>, dim3((unsigned)L.comp.size()), dim3(sgf::WG), 0, st,
+                         D.comp.as<sgf::CompDesc>(), D.compnbr.as<sgf::CompNbr>(), blocks, D.cf.as<T>());
+      int nb = nb_for(L.max_cf_rows, sizeof(T));
+      size_t lds = std::max<size_t>((size_t)nb * L.max_cf_rows, (size_t)L.max_c) * sizeof(T);
+      if (lds > LDS_BYTES) throw SgfError(SGF_EINVAL, "compression too wide for LDS");
+      double tol = P.opt.rank_tol;
+      hipLaunchKernelGGL(sgf::k_compress<T>, dim3((unsigned)L.comp.size()), dim3(sgf::WG), lds, st,
+                         D.comp.as<sgf::CompDesc>(), D.compnbr.as<sgf::CompNbr>(), D.cf.as<T>(), D.nbuf.as<T>(),
+                         D.phi.as<T>(), D.ltphi.as<T>(), D.tau.as<T>(), D.rank.as<int>(), P.pi, nb, tol,
+                         h->d_fail.as<int>());
+      hipLaunchKernelGGL(sgf::k_phi_commit<T>, dim3((unsigned)L.comp.size()), dim3(sgf::WG), 0, st,
+                         D.comp.as<sgf::CompDesc>(), D.rank.as<int>(), D.ltphi.as<T>(), D.phi.as<T>(), P.pi);
+      hipLaunchKernelGGL(sgf::k_pair<T>, dim3((unsigned)L.pairs.size()), dim3(sgf::WG), 0, st,
+                         D.pairs.as<sgf::PairDesc>(), D.comp.as<sgf::CompDesc>(), D.rank.as<int>(), D.cf.as<T>(),
+                         D.nbuf.as<T>(), D.tau.as<T>(), blocks, D.scratch.as<T>());
+    }
+    HIP_CHECK(hipGetLastError());
+    L.rank.assign(L.comp.size(), 0);
+    if (!L.comp.empty())
+      HIP_CHECK(hipMemcpyAsync(L.rank.data(), D.rank.p, L.comp.size() * sizeof(int), hipMemcpyDeviceToHost, st));
+    int f = check_fail(h, st);
+    if (f >= 0) {
+      h->failed_cluster = f;
+      h->failed_level = L.t;
+      throw SgfError(SGF_ENOTSPD, "non-positive pivot at level " + std::to_string(L.t));
+    }
+    // compressed separators of this level, for the apply
+    L.capply.clear();
+    for (size_t c = 0; c < L.comp.size(); ++c) {
+      const auto& d = L.comp[c];
+      if (L.rank[c] < d.s) {
+        sgf::CompApply a{};
+        a.cf_off = d.cf_off;
+        a.v_off = d.n_off;
+        a.tau_off = d.tau_off;
+        a.slot_off = d.slot_off;
+        a.s = d.s;
+        a.ld = d.s + d.K;
+        a.r = L.rank[c];
+        L.capply.push_back(a);
+        h->max_s_all = std::max(h->max_s_all, d.s);
+        ++h->compressed;
+      }
+    }
+    upload(D.capply, L.capply, st);
+    account_level(h, L);
+    // ---- coarsen (Secs. 4.3-4.4) ----------------------------------------------
+    sgf::plan_next_level(P, D.h_blkmap, D.h_phimap);
+    upload(D.blkmap, D.h_blkmap, st);
+    upload(D.phimap, D.h_phimap, st);
+    upload_level(h, li + 1, st);
+    sgf::Level& N = P.levels[li + 1];
+    LevelDev& E = h->lev[li + 1];
+    LevelDev& Dc = h->lev[li];   // re-fetch: lev may have grown
+    zero<T>(E.arena, N.front_elems + N.blk_elems, st);
+    if (!Dc.h_blkmap.empty())
+      hipLaunchKernelGGL(sgf::k_copy_blocks<T>, dim3((unsigned)Dc.h_blkmap.size()), dim3(sgf::WG), 0, st,
+                         Dc.blkmap.as<sgf::CopyDesc>(), Dc.arena.as<T>(), E.arena.as<T>());
+    if (!Dc.h_phimap.empty())
+      hipLaunchKernelGGL(sgf::k_copy_blocks<T>, dim3((unsigned)Dc.h_phimap.size()), dim3(sgf::WG), 0, st,
+                         Dc.phimap.as<sgf::CopyDesc>(), Dc.phi.as<T>(), E.phi.as<T>());
+    HIP_CHECK(hipGetLastError());
+  }
+  // device bytes held by the factor
+  h->factor_bytes = 0;
+  for (size_t li = 0; li < P.levels.size(); ++li) {
+    const auto& D = h->lev[li];
+    h->factor_bytes += D.arena.bytes + D.cf.bytes + D.nbuf.bytes + D.tau.bytes;
+  }
+  const auto& top = P.levels.back().elim[0];
+  h->max_m_all = std::max(h->max_m_all, top.m);
+  int64_t n = P.n;
+  h->apply_bytes += 2.0 * n * h->esz * 2;  // work vector read + write per sweep
+  h->factored = true;
+}
+
+template <typename T>
+void ensure_work(sgf_handle h, int nrhs) {
+  h->y.ensure((size_t)h->plan.n * nrhs * sizeof(T));
+  h->tscr.ensure((size_t)std::max<int64_t>(h->max_t, 1) * nrhs * sizeof(T));
+}
+
+template <typename T>
+void run_sweeps(sgf_handle h, int nrhs, bool product, hipStream_t st) {
+  sgf::Plan& P = h->plan;
+  const int64_t n = P.n;
+  T* y = h->y.as<T>();
+  T* ts = h->tscr.as<T>();
+  const int64_t ldt = std::max<int64_t>(h->max_t, 1);
+  const int nl = (int)P.levels.size();
+  auto fwd_level = [&](int li) {
+    sgf::Level& L = P.levels[li];
+    LevelDev& D = h->lev[li];
+    int maxm = 0;
+    for (auto& e : L.elim) maxm = std::max(maxm, e.m);
+    if (!product) {
+      if (!L.elim.empty())
+        hipLaunchKernelGGL(sgf::k_elim_fwd<T>, dim3((unsigned)L.elim.size(), nrhs), dim3(sgf::WG),
+                           maxm * sizeof(T), st, D.elim.as<sgf::ElimDesc>(), D.arena.as<T>(), D.slots.as<int32_t>(),
+                           y, n, ts, ldt, 0);
+      if (!L.sepacc.empty())
+        hipLaunchKernelGGL(sgf::k_sepacc<T>, dim3((unsigned)L.sepacc.size(), nrhs), dim3(sgf::WG), 0, st,
+                           D.sepacc.as<sgf::SepAcc>(), D.sepsrc.as<int64_t>(), D.slots.as<int32_t>(), ts, ldt, y, n,
+                           T(-1));
+      if (!L.capply.empty()) {
+        int ms = 0;
+        for (auto& a : L.capply) ms = std::max(ms, a.s);
+        hipLaunchKernelGGL(sgf::k_comp_apply<T>, dim3((unsigned)L.capply.size(), nrhs), dim3(sgf::WG),
+                           2 * ms * sizeof(T), st, D.capply.as<sgf::CompApply>(), D.cf.as<T>(), D.nbuf.as<T>(),
+                           D.tau.as<T>(), D.slots.as<int32_t>(), y, n, 0);
+      }
+    } else {
+      int maxk = 0;
+      for (auto& e : L.elim) maxk = std::max(maxk, e.k);
+      if (!L.elim.empty())
+        hipLaunchKernelGGL(sgf::k_elim_bwd<T>, dim3((unsigned)L.elim.size(), nrhs), dim3(sgf::WG),
+                           (2 * maxm + maxk) * sizeof(T), st, D.elim.as<sgf::ElimDesc>(), D.arena.as<T>(),
+                           D.slots.as<int32_t>(), D.nslots.as<int32_t>(), y, n, 1);
+      if (!L.capply.empty()) {
+        int ms = 0;
+        for (auto& a : L.capply) ms = std::max(ms, a.s);
+        hipLaunchKernelGGL(sgf::k_comp_apply<T>, dim3((unsigned)L.capply.size(), nrhs), dim3(sgf::WG),
+                           2 * ms * sizeof(T), st, D.capply.as<sgf::CompApply>(), D.cf.as<T>(), D.nbuf.as<T>(),
+                           D.tau.as<T>(), D.slots.as<int32_t>(), y, n, 2);
+      }
+    }
+  };
+  auto bwd_level = [&](int li) {
+    sgf::Level& L = P.levels[li];
+    LevelDev& D = h->lev[li];
+    int maxm = 0, maxk = 0;
+    for (auto& e : L.elim) {
+      maxm = std::max(maxm, e.m);
+      maxk = std::max(maxk, e.k);
+    }
+    if (!L.capply.empty()) {
+      int ms = 0;
+      for (auto& a : L.capply) ms = std::max(ms, a.s);
+      hipLaunchKernelGGL(sgf::k_comp_apply<T>, dim3((unsigned)L.capply.size(), nrhs), dim3(sgf::WG),
+                         2 * ms * sizeof(T), st, D.capply.as<sgf::CompApply>(), D.cf.as<T>(), D.nbuf.as<T>(),
+                         D.tau.as<T>(), D.slots.as<int32_t>(), y, n, product ? 3 : 1);
+    }
+    if (!product) {
+      if (!L.elim.empty())
+        hipLaunchKernelGGL(sgf::k_elim_bwd<T>, dim3((unsigned)L.elim.size(), nrhs), dim3(sgf::WG),
+                           (2 * maxm + maxk) * sizeof(T), st, D.elim.as<sgf::ElimDesc>(), D.arena.as<T>(),
+                           D.slots.as<int32_t>(), D.nslots.as<int32_t>(), y, n, 0);
+    } else {
+      if (!L.elim.empty())
+        hipLaunchKernelGGL(sgf::k_elim_fwd<T>, dim3((unsigned)L.elim.size(), nrhs), dim3(sgf::WG),
+                           maxm * sizeof(T), st, D.elim.as<sgf::ElimDesc>(), D.arena.as<T>(), D.slots.as<int32_t>(),
+                           y, n, ts, ldt, 1);
+      if (!L.sepacc.empty())
+        hipLaunchKernelGGL(sgf::k_sepacc<T>, dim3((unsigned)L.sepacc.size(), nrhs), dim3(sgf::WG), 0, st,
+                           D.sepacc.as<sgf::SepAcc>(), D.sepsrc.as<int64_t>(), D.slots.as<int32_t>(), ts, ldt, y, n,
+                           T(1));
+    }
+  };
+  for (int li = 0; li < nl - 1; ++li) fwd_level(li);
+  {
+    sgf::Level& L = P.levels[nl - 1];
+    LevelDev& D = h->lev[nl - 1];
+    int m = L.elim[0].m;
+    if (m > 0)
+      hipLaunchKernelGGL(sgf::k_top<T>, dim3(1, nrhs), dim3(sgf::WG), 2 * m * sizeof(T), st,
+                         D.elim.as<sgf::ElimDesc>(), D.arena.as<T>(), D.slots.as<int32_t>(), y, n, product ? 1 : 0);
+  }
+  for (int li = nl - 2; li >= 0; --li) bwd_level(li);
+}
+
+template <typename T>
+void apply_impl(sgf_handle h, int nrhs, const double* r, int64_t ldr, double* z, int64_t ldz, bool product,
+                hipStream_t st) {
+  const int64_t n = h->plan.n;
+  ensure_work<T>(h, nrhs);
+  dim3 g(cdiv(n, sgf::WG), nrhs);
+  hipLaunchKernelGGL((sgf::k_gather_perm<double, T>), g, dim3(sgf::WG), 0, st, h->d_perm.as<int64_t>(), n, r, ldr,
+                     h->y.as<T>(), n);
+  run_sweeps<T>(h, nrhs, product, st);
+  hipLaunchKernelGGL((sgf::k_scatter_perm<T, double>), g, dim3(sgf::WG), 0, st, h->d_perm.as<int64_t>(), n,
+                     h->y.as<T>(), n, z, ldz);
+  HIP_CHECK(hipGetLastError());
+}
+
+void apply_any(sgf_handle h, int nrhs, const double* r, int64_t ldr, double* z, int64_t ldz, bool product,
+               hipStream_t st) {
+  if (h->esz == 8) apply_impl<double>(h, nrhs, r, ldr, z, ldz, product, st);
+  else apply_impl<float>(h, nrhs, r, ldr, z, ldz, product, st);
+}
+
+void dot_cols(sgf_handle h, const double* a, const double* b, int nrhs, double* out, hipStream_t st) {
+  const int64_t n = h->plan.n;
+  const int nb = (int)std::min<int64_t>(1024, cdiv(n, sgf::WG));
+  hipLaunchKernelGGL(sgf::k_dot_partial, dim3(nb, nrhs), dim3(sgf::WG), 0, st, a, n, b, n, n,
+                     h->cg_part.as<double>());
+  hipLaunchKernelGGL(sgf::k_reduce, dim3(nrhs), dim3(sgf::WG), 0, st, h->cg_part.as<double>(), nb, out);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+void sgf_default_options(sgf_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->dim = 2;
+  o->grid[0] = o->grid[1] = o->grid[2] = 1;
+  o->dofs_per_node = 1;
+  o->q = 1;
+  o->leaf = 8;
+  o->scheme = SGF_NEST_ALL_ALL;
+  o->compress = 1;
+  o->compress_from_level = 1;
+  o->stop_rule = SGF_STOP_ROOT;
+  o->precision = SGF_FP64;
+  o->rank_tol = 0.0;
+}
+
+const char* sgf_status_str(sgf_status s) {
+  switch (s) {
+    case SGF_OK: return "ok";
+    case SGF_EINVAL: return "invalid argument";
+    case SGF_ENOTSPD: return "matrix not positive definite";
+    case SGF_ENOMEM: return "out of memory";
+    case SGF_EDEVICE: return "device error";
+    case SGF_ENOCONV: return "no convergence";
+    case SGF_ESTATE: return "call out of order";
+  }
+  return "unknown status";
+}
+
+const char* sgf_last_error(void) { return g_last_error.c_str(); }
+
+sgf_status sgf_analyze(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const double* coords,
+                       const sgf_options* opt, sgf_handle* out) {
+  if (!out) return fail(SGF_EINVAL, "out is NULL");
+  *out = nullptr;
+  std::unique_ptr<sgf_handle_s> h(new (std::nothrow) sgf_handle_s());
+  if (!h) return fail(SGF_ENOMEM, "handle allocation failed");
+  sgf_status st = guard([&] {
+    check_options(opt, n);
+    if (!row_ptr || !col_idx || !coords) throw SgfError(SGF_EINVAL, "NULL input array");
+    sgf::Options& o = h->plan.opt;
+    o.dim = opt->dim;
+    for (int a = 0; a < 3; ++a) o.grid[a] = a < opt->dim ? opt->grid[a] : 1;
+    o.dpn = opt->dofs_per_node;
+    o.q = opt->q;
+    o.leaf = opt->leaf;
+    o.scheme = opt->scheme;
+    o.compress = opt->compress;
+    o.compress_from_level = std::max(1, opt->compress_from_level);
+    o.stop_rule = opt->stop_rule;
+    o.precision = opt->precision;
+    o.rank_tol = opt->rank_tol > 0 ? opt->rank_tol : (opt->precision == SGF_FP64 ? 1e-12 : 1e-6);
+    h->esz = opt->precision == SGF_FP64 ? 8 : 4;
+    h->plan.n = n;
+    h->plan.n_nodes = n / o.dpn;
+    h->plan.pi = sgf::poly_cols(o.dim, o.q, o.dpn);
+    if (row_ptr[0] != 0) throw SgfError(SGF_EINVAL, "row_ptr[0] must be 0");
+    for (int64_t i = 0; i < n; ++i)
+      if (row_ptr[i + 1] < row_ptr[i]) throw SgfError(SGF_EINVAL, "row_ptr not monotone");
+    h->nnz = row_ptr[n];
+    h->h_rowptr.assign(row_ptr, row_ptr + n + 1);
+    h->h_colidx.assign(col_idx, col_idx + h->nnz);
+    h->h_coords.assign(coords, coords + h->plan.n_nodes * o.dim);
+    for (int a = 0; a < 3; ++a) {
+      h->plan.cmin[a] = 0;
+      h->plan.cmax[a] = 0;
+    }
+    for (int a = 0; a < o.dim; ++a) {
+      double lo = coords[a], hi = coords[a];
+      for (int64_t v = 0; v < h->plan.n_nodes; ++v) {
+        lo = std::min(lo, coords[v * o.dim + a]);
+        hi = std::max(hi, coords[v * o.dim + a]);
+      }
+      h->plan.cmin[a] = lo;
+      h->plan.cmax[a] = hi;
+    }
+    sgf::plan_level1(h->plan, row_ptr, col_idx);
+  });
+  if (st != SGF_OK) return st;
+  *out = h.release();
+  return SGF_OK;
+}
+
+sgf_status sgf_factorize_numeric(sgf_handle h, const double* vals, void* stream) {
+  if (!h || !vals) return fail(SGF_EINVAL, "NULL handle or values");
+  hipStream_t st = (hipStream_t)stream;
+  return guard([&] {
+    if (h->esz == 8) factor_numeric<double>(h, vals, st);
+    else factor_numeric<float>(h, vals, st);
+  });
+}
+
+sgf_status sgf_factorize(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const double* vals,
+                         const double* coords, const sgf_options* opt, void* stream, sgf_handle* out) {
+  sgf_handle h = nullptr;
+  sgf_status s = sgf_analyze(n, row_ptr, col_idx, coords, opt, &h);
+  if (s != SGF_OK) return s;
+  s = sgf_factorize_numeric(h, vals, stream);
+  if (s != SGF_OK) {
+    sgf_destroy(h);
+    if (out) *out = nullptr;
+    return s;
+  }
+  *out = h;
+  return SGF_OK;
+}
+
+sgf_status sgf_apply(sgf_handle h, int32_t nrhs, const double* r, int64_t ldr, double* z, int64_t ldz, void* stream) {
+  if (!h || !r || !z || nrhs < 1) return fail(SGF_EINVAL, "bad apply arguments");
+  if (!h->factored) return fail(SGF_ESTATE, "apply before a successful factorization");
+  if (ldr < h->plan.n || ldz < h->plan.n) return fail(SGF_EINVAL, "leading dimension below n");
+  return guard([&] { apply_any(h, nrhs, r, ldr, z, ldz, false, (hipStream_t)stream); });
+}
+
+sgf_status sgf_multiply(sgf_handle h, int32_t nrhs, const double* v, int64_t ldv, double* y, int64_t ldy,
+                        void* stream) {
+  if (!h || !v || !y || nrhs < 1) return fail(SGF_EINVAL, "bad multiply arguments");
+  if (!h->factored) return fail(SGF_ESTATE, "multiply before a successful factorization");
+  if (ldv < h->plan.n || ldy < h->plan.n) return fail(SGF_EINVAL, "leading dimension below n");
+  return guard([&] { apply_any(h, nrhs, v, ldv, y, ldy, true, (hipStream_t)stream); });
+}
+
+sgf_status sgf_spmv(sgf_handle h, const double* v, double* y, void* stream) {
+  if (!h || !v || !y) return fail(SGF_EINVAL, "bad spmv arguments");
+  if (!h->dev_static) return fail(SGF_ESTATE, "spmv before factorization");
+  return guard([&] {
+    const int64_t n = h->plan.n;
+    hipLaunchKernelGGL(sgf::k_spmv_dot, dim3(cdiv(n, sgf::WG), 1), dim3(sgf::WG), 0, (hipStream_t)stream,
+                       h->d_rowptr.as<int64_t>(), h->d_colidx.as<int32_t>(), h->d_vals.as<double>(), n, v, n, y, n,
+                       (double*)nullptr);
+    HIP_CHECK(hipGetLastError());
+  });
+}
+
+sgf_status sgf_pcg_solve(sgf_handle h, int32_t nrhs, const double* b, int64_t ldb, double* x, int64_t ldx,
+                         double rtol, int32_t maxit, int32_t* iters, double* relres, void* stream) {
+  if (!h || !b || !x || nrhs < 1 || nrhs > 256 || maxit < 0 || !iters || !relres)
+    return fail(SGF_EINVAL, "bad pcg arguments");
+  if (!h->factored) return fail(SGF_ESTATE, "pcg before a successful factorization");
+  if (ldb < h->plan.n || ldx < h->plan.n) return fail(SGF_EINVAL, "leading dimension below n");
+  hipStream_t st = (hipStream_t)stream;
+  bool all_conv = true;
+  sgf_status s = guard([&] {
+    const int64_t n = h->plan.n;
+    const size_t vb = (size_t)n * nrhs * sizeof(double);
+    h->cg_r.ensure(vb);
+    h->cg_z.ensure(vb);
+    h->cg_p.ensure(vb);
+    h->cg_ap.ensure(vb);
+    const int nbs = (int)std::min<int64_t>(1024, cdiv(n, sgf::WG));
+    const int nbspmv = (int)cdiv(n, sgf::WG);
+    h->cg_part.ensure((size_t)std::max(nbs, nbspmv) * nrhs * sizeof(double));
+    h->cg_st.ensure(8 * nrhs * sizeof(double));
+    h->cg_scal.ensure(2 * nrhs * sizeof(double));
+    double* r = h->cg_r.as<double>();
+    double* z = h->cg_z.as<double>();
+    double* p = h->cg_p.as<double>();
+    double* Ap = h->cg_ap.as<double>();
+    double* stv = h->cg_st.as<double>();
+    double* sc = h->cg_scal.as<double>();
+    for (int c = 0; c < nrhs; ++c) {
+      HIP_CHECK(hipMemsetAsync(x + c * ldx, 0, n * sizeof(double), st));
+      HIP_CHECK(hipMemcpyAsync(r + c * n, b + c * ldb, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    }
+    std::vector<double> hst(8 * nrhs, 0.0), bn(nrhs), rr(nrhs);
+    dot_cols(h, r, r, nrhs, sc, st);
+    HIP_CHECK(hipMemcpyAsync(bn.data(), sc, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    std::vector<int> active(nrhs);
+    int nactive = 0;
+    for (int c = 0; c < nrhs; ++c) {
+      bn[c] = std::sqrt(bn[c]);
+      active[c] = bn[c] > 0;
+      nactive += active[c];
+      iters[c] = 0;
+      relres[c] = 0.0;
+      hst[8 * c + 5] = active[c];
+    }
+    HIP_CHECK(hipMemcpyAsync(stv, hst.data(), 8 * nrhs * sizeof(double), hipMemcpyHostToDevice, st));
+    if (nactive == 0) {
+      HIP_CHECK(hipStreamSynchronize(st));
+      return;
+    }
+    apply_any(h, nrhs, r, n, z, n, false, st);
+    dot_cols(h, r, z, nrhs, sc, st);
+    for (int c = 0; c < nrhs; ++c)
+      HIP_CHECK(hipMemcpyAsync(stv + 8 * c, sc + c, sizeof(double), hipMemcpyDeviceToDevice, st));
+    HIP_CHECK(hipMemcpyAsync(p, z, vb, hipMemcpyDeviceToDevice, st));
+    dim3 gv(cdiv(n, sgf::WG), nrhs);
+    for (int it = 1; it <= maxit; ++it) {
+      hipLaunchKernelGGL(sgf::k_spmv_dot, dim3(nbspmv, nrhs), dim3(sgf::WG), 0, st, h->d_rowptr.as<int64_t>(),
+                         h->d_colidx.as<int32_t>(), h->d_vals.as<double>(), n, p, n, Ap, n, h->cg_part.as<double>());
+      hipLaunchKernelGGL(sgf::k_reduce, dim3(nrhs), dim3(sgf::WG), 0, st, h->cg_part.as<double>(), nbspmv, sc);
+      for (int c = 0; c < nrhs; ++c)
+        HIP_CHECK(hipMemcpyAsync(stv + 8 * c + 1, sc + c, sizeof(double), hipMemcpyDeviceToDevice, st));
+      hipLaunchKernelGGL(sgf::k_cg_alpha, dim3(1), dim3(256), 0, st, stv, nrhs);
+      hipLaunchKernelGGL(sgf::k_cg_update_xr, gv, dim3(sgf::WG), 0, st, x, ldx, r, n, p, Ap, n, n, stv);
+      dot_cols(h, r, r, nrhs, sc, st);
+      HIP_CHECK(hipMemcpyAsync(rr.data(), sc, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIP_CHECK(hipStreamSynchronize(st));
+      bool changed = false;
+      nactive = 0;
+      for (int c = 0; c < nrhs; ++c) {
+        if (!active[c]) continue;
+        double rel = std::sqrt(std::max(rr[c], 0.0)) / bn[c];
+        iters[c] = it;
+        relres[c] = rel;
+        if (rel < rtol) {
+          active[c] = 0;
+          changed = true;
+        } else {
+          ++nactive;
+        }
+      }
+      if (changed) {
+        for (int c = 0; c < nrhs; ++c) {
+          double a = active[c];
+          HIP_CHECK(hipMemcpyAsync(stv + 8 * c + 5, &a, sizeof(double), hipMemcpyHostToDevice, st));
+          HIP_CHECK(hipStreamSynchronize(st));
+        }
+      }
+      if (nactive == 0) break;
+      apply_any(h, nrhs, r, n, z, n, false, st);
+      dot_cols(h, r, z, nrhs, sc, st);
+      hipLaunchKernelGGL(sgf::k_cg_beta, dim3(1), dim3(256), 0, st, stv, sc, nrhs);
+      hipLaunchKernelGGL(sgf::k_cg_update_p, gv, dim3(sgf::WG), 0, st, p, z, n, n, stv);
+      HIP_CHECK(hipGetLastError());
+    }
+    HIP_CHECK(hipStreamSynchronize(st));
+    for (int c = 0; c < nrhs; ++c)
+      if (active[c]) all_conv = false;
+  });
+  if (s != SGF_OK) return s;
+  if (!all_conv) return fail(SGF_ENOCONV, "CG reached maxit before the tolerance");
+  return SGF_OK;
+}
+
+sgf_status sgf_get_info(sgf_handle h, sgf_info* info) {
+  if (!h || !info) return fail(SGF_EINVAL, "NULL handle or info");
+  std::memset(info, 0, sizeof(*info));
+  info->levels = (int32_t)h->plan.levels.size();
+  info->n = h->plan.n;
+  if (h->factored) info->top_size = h->plan.levels.back().elim[0].m;
+  info->factor_entries = h->factor_entries;
+  info->factor_bytes = h->factor_bytes;
+  info->compressed = h->compressed;
+  info->factor_flops = h->factor_flops;
+  info->apply_bytes = h->apply_bytes;
+  info->failed_cluster = h->failed_cluster;
+  info->failed_level = h->failed_level;
+  return SGF_OK;
+}
+
+sgf_status sgf_get_perm(sgf_handle h, int64_t* perm) {
+  if (!h || !perm) return fail(SGF_EINVAL, "NULL argument");
+  std::memcpy(perm, h->plan.perm.data(), h->plan.n * sizeof(int64_t));
+  return SGF_OK;
+}
+
+sgf_status sgf_get_level(sgf_handle h, int32_t level, int32_t* count, int32_t* cell_ids, int32_t* types,
+                         int32_t* sizes, int32_t* ranks) {
+  if (!h || !count) return fail(SGF_EINVAL, "NULL argument");
+  if (level < 1 || level > (int)h->plan.levels.size()) return fail(SGF_EINVAL, "level out of range");
+  const sgf::Level& L = h->plan.levels[level - 1];
+  const int nc = (int)L.cell.size();
+  *count = nc;
+  for (int c = 0; c < nc; ++c) {
+    if (cell_ids) cell_ids[c] = (int32_t)L.cell[c];
+    if (types) types[c] = L.top ? 0 : L.type[c];
+    if (sizes) sizes[c] = L.size[c];
+    if (ranks) {
+      bool elim = L.top || L.type[c] == 0;
+      ranks[c] = elim ? 0 : (L.rank.empty() ? L.size[c] : L.post_size(c));
+    }
+  }
+  return SGF_OK;
+}
+
+sgf_status sgf_plan_dry_run(sgf_handle h, sgf_rank_fn rank_fn, void* ctx) {
+  if (!h || !rank_fn) return fail(SGF_EINVAL, "NULL argument");
+  if (h->factored) return fail(SGF_ESTATE, "dry run on a factorized handle");
+  return guard([&] {
+    sgf::Plan& P = h->plan;
+    P.levels.resize(1);
+    P.parts.resize(1);
+    P.max_node = 0;
+    for (int s : P.levels[0].size) P.max_node = std::max<int64_t>(P.max_node, s);
+    std::vector<sgf::CopyDesc> bm, pm;
+    while (!P.levels.back().top) {
+      sgf::Level& L = P.levels.back();
+      L.rank.assign(L.comp.size(), 0);
+      for (size_t c = 0; c < L.comp.size(); ++c) {
+        int r = rank_fn(L.t, L.cell[L.comp[c].cluster], L.comp[c].s, ctx);
+        if (r < 0 || r > std::min(L.comp[c].s, L.comp[c].c)) throw SgfError(SGF_EINVAL, "rank out of range");
+        L.rank[c] = r;
+      }
+      sgf::plan_next_level(P, bm, pm);
+    }
+  });
+}
+
+sgf_status sgf_destroy(sgf_handle h) {
+  delete h;
+  return SGF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,830 @@
+// Host-side symbolic planner of the SGF factorization (integer work only).
+//
+// Builds, level by level, the nodes (B, active set) of the nested-dissection
+// partition hierarchy (Sec. 5.1, Defs. 2.1-2.4), the interior / separator
+// split, the fill pattern created by eliminating the interiors (Eq. 4.2),
+// the neighbour lists used by the compressions (Eq. 4.5) and the maps that
+// carry the coarse blocks of one level into the nodes of the next (Sec. 4.3,
+// Eq. 4.7).  Every array here is plain integers; the device kernels get them
+// as descriptor tables.
+#pragma once
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+namespace sgf {
+
+struct Options {
+  int dim = 2;
+  int grid[3] = {1, 1, 1};
+  int dpn = 1;
+  int q = 1;
+  int leaf = 8;
+  int scheme = 0;
+  int compress = 1;
+  int compress_from_level = 1;
+  int stop_rule = 0;
+  int precision = 0;
+  double rank_tol = 1e-12;
+};
+
+inline int poly_cols(int dim, int q, int dpn) {
+  int p0 = q == 0 ? 1 : (q == 1 ? 1 + dim : (dim == 2 ? 6 : 10));
+  return p0 * dpn;
+}
+
+// Per-axis classes at period d (Sec. 5.1): index i is on a cutting slab iff
+// (i + 1) % d == 0 and i <= N - 2; class = 2 * (#slabs below) + [on slab].
+struct Axis {
+  std::vector<int32_t> cls;
+  int32_t K = 1;
+  std::vector<int32_t> rep;  // first index of each class
+};
+
+inline Axis axis_classes(int N, int d) {
+  Axis a;
+  a.cls.resize(N);
+  int below = 0;
+  for (int i = 0; i < N; ++i) {
+    bool slab = ((i + 1) % d == 0) && (i <= N - 2);
+    a.cls[i] = 2 * below + (slab ? 1 : 0);
+    if (slab) ++below;
+  }
+  a.K = 2 * below + 1;
+  a.rep.assign(a.K, -1);
+  for (int i = N - 1; i >= 0; --i) a.rep[a.cls[i]] = i;
+  return a;
+}
+
+struct Partition {
+  int d = 0;
+  int dim = 2;
+  Axis ax[3];
+  int64_t ncells = 1;
+  bool is_root = false;
+  int64_t cell_of(int ix, int iy, int iz) const {
+    int64_t c = ax[0].cls[ix];
+    if (dim >= 2) c += (int64_t)ax[0].K * ax[1].cls[iy];
+    if (dim >= 3) c += (int64_t)ax[0].K * ax[1].K * ax[2].cls[iz];
+    return c;
+  }
+  void split(int64_t cid, int cls[3]) const {
+    cls[0] = (int)(cid % ax[0].K);
+    cid /= ax[0].K;
+    cls[1] = dim >= 2 ? (int)(cid % ax[1].K) : 0;
+    cid /= (dim >= 2 ? ax[1].K : 1);
+    cls[2] = dim >= 3 ? (int)cid : 0;
+  }
+  int type_of(int64_t cid) const {
+    int c[3];
+    split(cid, c);
+    int t = 0;
+    for (int a = 0; a < dim; ++a) t += c[a] & 1;
+    return t;
+  }
+};
+
+inline Partition make_partition(const Options& o, int d) {
+  Partition p;
+  p.d = d;
+  p.dim = o.dim;
+  p.ncells = 1;
+  bool root = true;
+  for (int a = 0; a < o.dim; ++a) {
+    p.ax[a] = axis_classes(o.grid[a], d);
+    p.ncells *= p.ax[a].K;
+    if (p.ax[a].K > 1) root = false;
+  }
+  p.is_root = root;
+  return p;
+}
+
+// Father of a cell of partition `lo` in the coarser partition `hi` (Sec. 4.3).
+inline int64_t father_cell(const Partition& lo, const Partition& hi, int64_t cid) {
+  int c[3];
+  lo.split(cid, c);
+  int idx[3] = {0, 0, 0};
+  for (int a = 0; a < lo.dim; ++a) idx[a] = lo.ax[a].rep[c[a]];
+  return hi.cell_of(idx[0], idx[1], idx[2]);
+}
+
+// Block copy: dst[(dr + i) + (dc + j) * dld] = src[i + j * sld] (mode 0) or
+// dst[(dr + j) + (dc + i) * dld] (mode 1, transposed), i < rows, j < cols.
+struct CopyDesc {
+  int64_t src_off;   // absolute offset in the source buffer
+  int64_t dst_off;   // absolute offset in the destination buffer, (dr, dc) included
+  int32_t src_ld, dst_ld, rows, cols, mode, pad;
+};
+
+// Interior elimination (Eq. 4.2) on a front of (m + k) x (m + k), column
+// major, whose first m columns become [L_I ; W^T] and whose trailing k x k
+// lower triangle receives -W^T W.
+struct ElimDesc {
+  int64_t front_off;
+  int64_t slot_off;     // slots of I (m entries)
+  int64_t nslot_off;    // slots of the neighbours, concatenated (k entries)
+  int64_t t_off;        // apply scratch (k entries per right-hand side)
+  int32_t m, k, cluster, pad;
+};
+
+// One Schur contribution: dst pair block (ld = s_a) += front lower part.
+struct SchurDesc {
+  int64_t src_off;      // front_off + (m + off_b) + (m + off_a) * ld  [a < b]
+  int32_t src_ld, diag;
+};
+struct PairDesc {
+  int64_t blk_off;
+  int64_t scratch_off;
+  int32_t a, b;         // separator cluster indices (a <= b)
+  int32_t s_a, s_b;
+  int32_t ca, cb;       // compression indices or -1
+  int32_t row_in_a, row_in_b;  // row of b inside a's compression front, and vice versa
+  int32_t c_ptr, c_cnt; // Schur contributions
+};
+
+// Compression of one separator B (Eqs. 3.1-3.5).
+struct CompDesc {
+  int64_t cf_off;       // compression front (s + K) x s, column major
+  int64_t n_off;        // N buffer s x c (holds the reflectors afterwards)
+  int64_t phi_off;      // Phi_B, s x pi (ld s); receives Q1^T L^T Phi_B
+  int64_t ltphi_off;    // scratch s x pi
+  int64_t tau_off;      // c entries
+  int64_t slot_off;     // slots of B
+  int32_t s, K, c, nnb, nb_ptr, cluster, blk_diag_pad;
+  int64_t blk_diag;     // offset of M_BB pair block
+};
+struct CompNbr {
+  int64_t blk_off;      // pair block holding M_BX (if X > B) or M_XB (X < B)
+  int64_t phi_off;      // Phi_X (ld s_X)
+  int32_t s_x, trans, row, pad;  // trans = 1: block stored as M_BX (s x s_X)
+};
+
+// Apply of one compressed separator: y_B <- Q^T L_B^{-1} y_B and back.
+struct CompApply {
+  int64_t cf_off;
+  int64_t v_off;
+  int64_t tau_off;
+  int64_t slot_off;
+  int32_t s, ld, r, pad;
+};
+
+// Apply: separator S collects -sum_I (W_I^T y_I)[S part] from the interiors.
+struct SepAcc {
+  int64_t slot_off;
+  int32_t s, c_ptr, c_cnt, pad;
+};
+
+struct Level {
+  int t = 1;                  // 1-based level
+  bool top = false;
+  bool compress = false;
+  // active clusters, ascending cell id
+  std::vector<int64_t> cell;
+  std::vector<int32_t> type, size;
+  std::vector<int64_t> slot_ptr;
+  std::vector<int32_t> slots;
+  std::vector<std::vector<int32_t>> adj;   // pre-elimination adjacency
+  // interiors
+  std::vector<int32_t> interiors;
+  std::vector<ElimDesc> elim;
+  std::vector<int32_t> nslots;             // neighbour slots of every interior
+  std::vector<std::vector<int32_t>> inbr;  // neighbours of each interior (ascending)
+  std::vector<std::vector<int32_t>> inbr_off;
+  int64_t front_elems = 0;
+  int64_t t_elems = 0;                     // apply scratch per rhs
+  int32_t max_front_rows = 0;
+  // separators
+  std::vector<int32_t> seps;
+  std::vector<int32_t> sep_pos;            // cluster -> position in seps or -1
+  std::vector<std::vector<int32_t>> sadj;  // post-elimination separator adjacency
+  std::vector<std::vector<int32_t>> pair_of;  // for sep position a: pair id per sadj entry with b >= a
+  std::vector<PairDesc> pairs;
+  std::vector<SchurDesc> schur;
+  int64_t blk_elems = 0;
+  int64_t scratch_elems = 0;
+  // compression
+  std::vector<int32_t> comp_of;            // cluster -> compression index or -1
+  std::vector<CompDesc> comp;
+  std::vector<CompNbr> comp_nbr;
+  int64_t cf_elems = 0, n_elems = 0, ltphi_elems = 0, tau_elems = 0;
+  int32_t max_cf_rows = 0, max_c = 0, max_s = 0;
+  // Phi per cluster
+  std::vector<int64_t> phi_off;
+  int64_t phi_elems = 0;
+  // apply
+  std::vector<SepAcc> sepacc;
+  std::vector<int64_t> sepacc_src;         // t_off + offset of S in the interior's k part
+  // results of the numeric phase
+  std::vector<int32_t> rank;               // per compression
+  std::vector<CompApply> capply;
+  int64_t n_active = 0;
+
+  int32_t post_size(int c) const {
+    int ci = comp_of.empty() ? -1 : comp_of[c];
+    if (ci >= 0 && !rank.empty() && rank[ci] < size[c]) return rank[ci];
+    return size[c];
+  }
+  int32_t find_pair(int a, int b) const {  // cluster indices, a <= b, both separators
+    int pa = sep_pos[a];
+    const auto& v = sadj[pa];
+    if (a == b) return pair_of[pa][0];
+    auto it = std::lower_bound(v.begin(), v.end(), b);
+    if (it == v.end() || *it != b) return -1;
+    // pair_of[pa][0] is the diagonal; upper neighbours follow in order
+    int idx = 1;
+    for (auto jt = v.begin(); jt != it; ++jt)
+      if (*jt > a) ++idx;
+    return pair_of[pa][idx];
+  }
+};
+
+struct Plan {
+  Options opt;
+  int64_t n = 0, n_nodes = 0;
+  int pi = 1;
+  std::vector<Partition> parts;            // partitions by level (index t-1)
+  std::vector<Level> levels;
+  std::vector<int64_t> perm;               // slot -> unknown
+  std::vector<int64_t> csr_dst;            // level-1 arena offset per CSR entry (-1 = skip)
+  double cmin[3] = {0, 0, 0}, cmax[3] = {0, 0, 0};
+  int64_t max_node = 0;
+};
+
+// ---------------------------------------------------------------------------
+
+inline bool compressible(int type, int dim, int scheme) {
+  if (type == 0 || type == dim) return false;
+  if (scheme == 0) return true;
+  return type == 1;
+}
+
+// Derive interiors, fronts, separator pairs, Schur lists and compression
+// descriptors of a level whose clusters, sizes, slots and adjacency are set.
+inline void build_level(Level& L, const Options& o, int pi) {
+  const int nc = (int)L.cell.size();
+  L.interiors.clear();
+  L.seps.clear();
+  L.sep_pos.assign(nc, -1);
+  L.n_active = 0;
+  for (int c = 0; c < nc; ++c) {
+    L.n_active += L.size[c];
+    if (L.top || L.type[c] == 0) L.interiors.push_back(c);
+    else {
+      L.sep_pos[c] = (int)L.seps.size();
+      L.seps.push_back(c);
+    }
+  }
+  // ---- interiors: fronts [I ; neighbours] -----------------------------------
+  L.elim.clear();
+  L.nslots.clear();
+  L.inbr.assign(L.interiors.size(), {});
+  L.inbr_off.assign(L.interiors.size(), {});
+  L.front_elems = 0;
+  L.t_elems = 0;
+  L.max_front_rows = 0;
+  for (size_t ii = 0; ii < L.interiors.size(); ++ii) {
+    int I = L.interiors[ii];
+    ElimDesc d{};
+    d.cluster = I;
+    d.m = L.size[I];
+    int k = 0;
+    for (int X : L.adj[I]) {
+      if (L.sep_pos[X] < 0)
+        throw std::runtime_error("two interiors are adjacent: the pattern couples nodes more than one grid step apart");
+      L.inbr[ii].push_back(X);
+      L.inbr_off[ii].push_back(k);
+      k += L.size[X];
+    }
+    d.k = k;
+    d.front_off = L.front_elems;
+    int64_t R = (int64_t)d.m + k;
+    L.front_elems += R * R;
+    L.max_front_rows = std::max<int32_t>(L.max_front_rows, (int32_t)R);
+    d.slot_off = L.slot_ptr[I];
+    d.nslot_off = (int64_t)L.nslots.size();
+    for (int X : L.inbr[ii])
+      for (int64_t s = L.slot_ptr[X]; s < L.slot_ptr[X + 1]; ++s) L.nslots.push_back(L.slots[s]);
+    d.t_off = L.t_elems;
+    L.t_elems += k;
+    L.elim.push_back(d);
+  }
+  // ---- separators: post-elimination adjacency ------------------------------
+  const int ns = (int)L.seps.size();
+  L.sadj.assign(ns, {});
+  for (int p = 0; p < ns; ++p) {
+    int a = L.seps[p];
+    for (int X : L.adj[a])
+      if (L.sep_pos[X] >= 0) L.sadj[p].push_back(X);
+  }
+  for (size_t ii = 0; ii < L.interiors.size(); ++ii) {
+    const auto& nb = L.inbr[ii];
+    for (int x : nb)
+      for (int y : nb)
+        if (x != y) L.sadj[L.sep_pos[x]].push_back(y);
+  }
+  for (auto& v : L.sadj) {
+    std::sort(v.begin(), v.end());
+    v.erase(std::unique(v.begin(), v.end()), v.end());
+  }
+  // pairs (a <= b): diagonal first, then upper neighbours ascending
+  L.pairs.clear();
+  L.pair_of.assign(ns, {});
+  L.blk_elems = 0;
+  L.scratch_elems = 0;
+  for (int p = 0; p < ns; ++p) {
+    int a = L.seps[p];
+    auto add = [&](int b) {
+      PairDesc d{};
+      d.a = a;
+      d.b = b;
+      d.s_a = L.size[a];
+      d.s_b = L.size[b];
+      d.blk_off = L.blk_elems;
+      L.blk_elems += (int64_t)d.s_a * d.s_b;
+      d.scratch_off = L.scratch_elems;
+      L.scratch_elems += 2 * (int64_t)d.s_a * d.s_b;
+      d.ca = d.cb = -1;
+      d.row_in_a = d.row_in_b = -1;
+      L.pair_of[p].push_back((int)L.pairs.size());
+      L.pairs.push_back(d);
+    };
+    add(a);
+    for (int b : L.sadj[p])
+      if (b > a) add(b);
+  }
+  // Schur contributions, grouped per pair, interiors ascending
+  std::vector<std::vector<SchurDesc>> contrib(L.pairs.size());
+  for (size_t ii = 0; ii < L.interiors.size(); ++ii) {
+    const ElimDesc& e = L.elim[ii];
+    const auto& nb = L.inbr[ii];
+    const auto& off = L.inbr_off[ii];
+    int64_t ld = (int64_t)e.m + e.k;
+    for (size_t x = 0; x < nb.size(); ++x)
+      for (size_t y = x; y < nb.size(); ++y) {
+        int pid = L.find_pair(nb[x], nb[y]);
+        SchurDesc s{};
+        s.src_ld = (int32_t)ld;
+        s.diag = x == y;
+        s.src_off = e.front_off + (e.m + off[y]) + (int64_t)(e.m + off[x]) * ld;
+        contrib[pid].push_back(s);
+      }
+  }
+  L.schur.clear();
+  for (size_t p = 0; p < L.pairs.size(); ++p) {
+    L.pairs[p].c_ptr = (int32_t)L.schur.size();
+    L.pairs[p].c_cnt = (int32_t)contrib[p].size();
+    for (auto& s : contrib[p]) L.schur.push_back(s);
+  }
+  // ---- Phi per cluster ---------------------------------------------------------
+  L.phi_off.assign(nc, 0);
+  L.phi_elems = 0;
+  for (int c = 0; c < nc; ++c) {
+    L.phi_off[c] = L.phi_elems;
+    L.phi_elems += (int64_t)L.size[c] * pi;
+  }
+  // ---- compressions --------------------------------------------------------------
+  L.comp.clear();
+  L.comp_nbr.clear();
+  L.comp_of.assign(nc, -1);
+  L.cf_elems = L.n_elems = L.ltphi_elems = L.tau_elems = 0;
+  L.max_cf_rows = L.max_c = L.max_s = 0;
+  if (L.compress) {
+    for (int p = 0; p < ns; ++p) {
+      int B = L.seps[p];
+      if (!compressible(L.type[B], o.dim, o.scheme)) continue;
+      CompDesc d{};
+      d.cluster = B;
+      d.s = L.size[B];
+      d.nb_ptr = (int32_t)L.comp_nbr.size();
+      d.nnb = (int32_t)L.sadj[p].size();
+      int K = 0;
+      for (int X : L.sadj[p]) {
+        CompNbr nbx{};
+        int pid = X > B ? L.find_pair(B, X) : L.find_pair(X, B);
+        nbx.blk_off = L.pairs[pid].blk_off;
+        nbx.trans = X > B ? 1 : 0;
+        nbx.s_x = L.size[X];
+        nbx.phi_off = L.phi_off[X];
+        nbx.row = d.s + K;
+        K += L.size[X];
+        L.comp_nbr.push_back(nbx);
+      }
+      d.K = K;
+      d.c = pi * (1 + d.nnb);
+      d.cf_off = L.cf_elems;
+      L.cf_elems += (int64_t)(d.s + K) * d.s;
+      d.n_off = L.n_elems;
+      L.n_elems += (int64_t)d.s * d.c;
+      d.ltphi_off = L.ltphi_elems;
+      L.ltphi_elems += (int64_t)d.s * pi;
+      d.tau_off = L.tau_elems;
+      L.tau_elems += d.c;
+      d.phi_off = L.phi_off[B];
+      d.slot_off = L.slot_ptr[B];
+      d.blk_diag = L.pairs[L.find_pair(B, B)].blk_off;
+      L.comp_of[B] = (int32_t)L.comp.size();
+      L.max_cf_rows = std::max<int32_t>(L.max_cf_rows, d.s + K);
+      L.max_c = std::max<int32_t>(L.max_c, d.c);
+      L.max_s = std::max<int32_t>(L.max_s, d.s);
+      L.comp.push_back(d);
+    }
+  }
+  // pair descriptors: compression indices and rows inside the fronts
+  for (auto& pd : L.pairs) {
+    pd.ca = L.comp_of[pd.a];
+    pd.cb = L.comp_of[pd.b];
+    if (pd.a != pd.b) {
+      if (pd.ca >= 0) {
+        const CompDesc& d = L.comp[pd.ca];
+        for (int j = 0; j < d.nnb; ++j)
+          if (L.sadj[L.sep_pos[pd.a]][j] == pd.b) pd.row_in_a = L.comp_nbr[d.nb_ptr + j].row;
+      }
+      if (pd.cb >= 0) {
+        const CompDesc& d = L.comp[pd.cb];
+        for (int j = 0; j < d.nnb; ++j)
+          if (L.sadj[L.sep_pos[pd.b]][j] == pd.a) pd.row_in_b = L.comp_nbr[d.nb_ptr + j].row;
+      }
+    }
+  }
+  // apply: separator accumulation lists
+  std::vector<std::vector<int64_t>> acc(ns);
+  for (size_t ii = 0; ii < L.interiors.size(); ++ii) {
+    const auto& nb = L.inbr[ii];
+    for (size_t x = 0; x < nb.size(); ++x)
+      acc[L.sep_pos[nb[x]]].push_back(L.elim[ii].t_off + L.inbr_off[ii][x]);
+  }
+  L.sepacc.clear();
+  L.sepacc_src.clear();
+  for (int p = 0; p < ns; ++p) {
+    if (acc[p].empty()) continue;
+    SepAcc s{};
+    s.slot_off = L.slot_ptr[L.seps[p]];
+    s.s = L.size[L.seps[p]];
+    s.c_ptr = (int32_t)L.sepacc_src.size();
+    s.c_cnt = (int32_t)acc[p].size();
+    for (auto v : acc[p]) L.sepacc_src.push_back(v);
+    L.sepacc.push_back(s);
+  }
+  L.rank.clear();
+  L.capply.clear();
+}
+
+// Bounds check of every descriptor of a level against its buffers; throws
+// on the first violation so that no kernel is launched on a bad table.
+inline void validate_level(const Level& L, int64_t n, int pi) {
+  auto req = [](bool ok, const char* what) {
+    if (!ok) throw std::runtime_error(std::string("plan bounds check failed: ") + what);
+  };
+  const int64_t arena = L.front_elems + L.blk_elems;
+  const int64_t nsl = (int64_t)L.slots.size(), nns = (int64_t)L.nslots.size();
+  for (int32_t v : L.slots) req(v >= 0 && v < n, "slot out of range");
+  for (int32_t v : L.nslots) req(v >= 0 && v < n, "neighbour slot out of range");
+  for (const auto& e : L.elim) {
+    int64_t R = (int64_t)e.m + e.k;
+    req(e.m >= 0 && e.k >= 0 && e.front_off >= 0 && e.front_off + R * R <= L.front_elems, "front extent");
+    req(e.slot_off >= 0 && e.slot_off + e.m <= nsl, "interior slots");
+    req(e.nslot_off >= 0 && e.nslot_off + e.k <= nns, "interior neighbour slots");
+    req(e.t_off >= 0 && e.t_off + e.k <= L.t_elems, "apply scratch");
+  }
+  for (const auto& p : L.pairs) {
+    int64_t ab = (int64_t)p.s_a * p.s_b;
+    req(p.s_a > 0 && p.s_b > 0, "empty pair block");
+    req(p.blk_off >= 0 && p.blk_off + ab <= L.blk_elems, "pair block extent");
+    req(p.scratch_off >= 0 && p.scratch_off + 2 * ab <= L.scratch_elems, "pair scratch extent");
+    req(p.c_ptr >= 0 && p.c_ptr + p.c_cnt <= (int64_t)L.schur.size(), "schur list");
+    req(p.ca < (int)L.comp.size() && p.cb < (int)L.comp.size(), "pair compression index");
+    if (p.a != p.b && p.ca >= 0)
+      req(p.row_in_a >= L.comp[p.ca].s && p.row_in_a + p.s_b <= L.comp[p.ca].s + L.comp[p.ca].K, "row in a");
+    if (p.a != p.b && p.cb >= 0)
+      req(p.row_in_b >= L.comp[p.cb].s && p.row_in_b + p.s_a <= L.comp[p.cb].s + L.comp[p.cb].K, "row in b");
+    for (int c = 0; c < p.c_cnt; ++c) {
+      const SchurDesc& s = L.schur[p.c_ptr + c];
+      int64_t last = s.diag ? s.src_off + (p.s_a - 1) + (int64_t)(p.s_a - 1) * s.src_ld
+                            : s.src_off + (p.s_b - 1) + (int64_t)(p.s_a - 1) * s.src_ld;
+      req(s.src_off >= 0 && last < L.front_elems, "schur source extent");
+    }
+  }
+  for (const auto& d : L.comp) {
+    req(d.s > 0 && d.cf_off >= 0 && d.cf_off + (int64_t)(d.s + d.K) * d.s <= L.cf_elems, "compression front");
+    req(d.n_off >= 0 && d.n_off + (int64_t)d.s * d.c <= L.n_elems, "N buffer");
+    req(d.phi_off >= 0 && d.phi_off + (int64_t)d.s * pi <= L.phi_elems, "Phi_B");
+    req(d.ltphi_off >= 0 && d.ltphi_off + (int64_t)d.s * pi <= L.ltphi_elems, "LtPhi");
+    req(d.tau_off >= 0 && d.tau_off + d.c <= L.tau_elems, "tau");
+    req(d.slot_off >= 0 && d.slot_off + d.s <= nsl, "compression slots");
+    req(d.blk_diag >= 0 && d.blk_diag + (int64_t)d.s * d.s <= L.blk_elems, "diagonal block");
+    req(d.nb_ptr >= 0 && d.nb_ptr + d.nnb <= (int64_t)L.comp_nbr.size(), "neighbour list");
+    int K = 0;
+    for (int q = 0; q < d.nnb; ++q) {
+      const CompNbr& x = L.comp_nbr[d.nb_ptr + q];
+      req(x.blk_off >= 0 && x.blk_off + (int64_t)d.s * x.s_x <= L.blk_elems, "neighbour block");
+      req(x.phi_off >= 0 && x.phi_off + (int64_t)x.s_x * pi <= L.phi_elems, "neighbour Phi");
+      req(x.row == d.s + K, "neighbour row");
+      K += x.s_x;
+    }
+    req(K == d.K, "neighbour total");
+  }
+  for (const auto& a : L.sepacc) {
+    req(a.slot_off >= 0 && a.slot_off + a.s <= nsl, "separator slots");
+    req(a.c_ptr >= 0 && a.c_ptr + a.c_cnt <= (int64_t)L.sepacc_src.size(), "accumulation list");
+    for (int c = 0; c < a.c_cnt; ++c) {
+      int64_t v = L.sepacc_src[a.c_ptr + c];
+      req(v >= 0 && v + a.s <= L.t_elems, "accumulation source");
+    }
+  }
+  req((int64_t)L.phi_off.size() == (int64_t)L.cell.size(), "phi offsets");
+  (void)arena;
+}
+
+inline void validate_copies(const std::vector<CopyDesc>& v, int64_t src_elems, int64_t dst_elems) {
+  for (const auto& c : v) {
+    if (c.rows <= 0 || c.cols <= 0) throw std::runtime_error("plan bounds check failed: empty copy");
+    int64_t s_last = c.src_off + (c.rows - 1) + (int64_t)(c.cols - 1) * c.src_ld;
+    int64_t d_last = c.mode == 0 ? c.dst_off + (c.rows - 1) + (int64_t)(c.cols - 1) * c.dst_ld
+                                 : c.dst_off + (c.cols - 1) + (int64_t)(c.rows - 1) * c.dst_ld;
+    if (c.src_off < 0 || s_last >= src_elems || c.dst_off < 0 || d_last >= dst_elems)
+      throw std::runtime_error("plan bounds check failed: copy extent");
+  }
+}
+
+// Level 1 from the CSR pattern.
+inline void plan_level1(Plan& P, const int64_t* row_ptr, const int32_t* col_idx) {
+  const Options& o = P.opt;
+  Partition part = make_partition(o, o.leaf);
+  P.parts.clear();
+  P.parts.push_back(part);
+  const int64_t nn = P.n_nodes;
+  const int dpn = o.dpn;
+  // cell of every node
+  std::vector<int64_t> cell_of_node(nn);
+  int gx = o.grid[0], gy = o.dim >= 2 ? o.grid[1] : 1;
+  for (int64_t v = 0; v < nn; ++v) {
+    int ix = (int)(v % gx), iy = (int)((v / gx) % gy), iz = (int)(v / ((int64_t)gx * gy));
+    cell_of_node[v] = part.cell_of(ix, iy, o.dim >= 3 ? iz : 0);
+  }
+  // counting sort by cell; clusters = non-empty cells ascending
+  std::vector<int64_t> cnt(part.ncells + 1, 0);
+  for (int64_t v = 0; v < nn; ++v) cnt[cell_of_node[v] + 1] += dpn;
+  std::vector<int32_t> cluster_of_cell(part.ncells, -1);
+  Level L;
+  L.t = 1;
+  L.top = part.is_root;
+  L.compress = o.compress && o.compress_from_level <= 1 && !L.top;
+  for (int64_t c = 0; c < part.ncells; ++c)
+    if (cnt[c + 1] > 0) {
+      cluster_of_cell[c] = (int32_t)L.cell.size();
+      L.cell.push_back(c);
+      L.type.push_back(part.type_of(c));
+      L.size.push_back((int32_t)cnt[c + 1]);
+    }
+  for (int64_t c = 0; c < part.ncells; ++c) cnt[c + 1] += cnt[c];
+  P.perm.assign(P.n, 0);
+  std::vector<int32_t> cl_of(P.n), loc_of(P.n);
+  std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
+  for (int64_t v = 0; v < nn; ++v)
+    for (int c = 0; c < dpn; ++c) {
+      int64_t dof = v * dpn + c;
+      int64_t cc = cell_of_node[v];
+      int64_t s = pos[cc]++;
+      P.perm[s] = dof;
+      cl_of[dof] = cluster_of_cell[cc];
+      loc_of[dof] = (int32_t)(s - cnt[cc]);
+    }
+  const int nc = (int)L.cell.size();
+  L.slot_ptr.assign(nc + 1, 0);
+  for (int c = 0; c < nc; ++c) L.slot_ptr[c + 1] = L.slot_ptr[c] + L.size[c];
+  L.slots.resize(P.n);
+  for (int64_t s = 0; s < P.n; ++s) L.slots[s] = (int32_t)s;
+  // adjacency from the pattern; check the 3^dim stencil assumption
+  L.adj.assign(nc, {});
+  for (int64_t i = 0; i < P.n; ++i) {
+    int ci = cl_of[i];
+    int64_t ni = i / dpn;
+    int ix = (int)(ni % gx), iy = (int)((ni / gx) % gy), iz = (int)(ni / ((int64_t)gx * gy));
+    for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+      int64_t j = col_idx[e];
+      if (j < 0 || j >= P.n) throw std::runtime_error("column index out of range");
+      int64_t nj = j / dpn;
+      int jx = (int)(nj % gx), jy = (int)((nj / gx) % gy), jz = (int)(nj / ((int64_t)gx * gy));
+      if (std::abs(ix - jx) > 1 || std::abs(iy - jy) > 1 || std::abs(iz - jz) > 1)
+        throw std::runtime_error("pattern couples grid nodes more than one step apart");
+      int cj = cl_of[j];
+      if (cj != ci) L.adj[ci].push_back(cj);
+    }
+  }
+  for (auto& v : L.adj) {
+    std::sort(v.begin(), v.end());
+    v.erase(std::unique(v.begin(), v.end()), v.end());
+  }
+  build_level(L, o, P.pi);
+  P.max_node = 0;
+  for (int c = 0; c < nc; ++c) P.max_node = std::max<int64_t>(P.max_node, L.size[c]);
+  // CSR fill destinations
+  const int64_t nnz = row_ptr[P.n];
+  P.csr_dst.assign(nnz, -1);
+  std::vector<int32_t> elim_of(nc, -1);
+  for (size_t ii = 0; ii < L.interiors.size(); ++ii) elim_of[L.interiors[ii]] = (int32_t)ii;
+  for (int64_t i = 0; i < P.n; ++i) {
+    int ci = cl_of[i], li = loc_of[i];
+    for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+      int64_t j = col_idx[e];
+      int cj = cl_of[j], lj = loc_of[j];
+      if (elim_of[ci] >= 0) {
+        const ElimDesc& d = L.elim[elim_of[ci]];
+        int64_t ld = (int64_t)d.m + d.k;
+        if (cj == ci) {
+          P.csr_dst[e] = d.front_off + li + (int64_t)lj * ld;
+        } else {
+          const auto& nb = L.inbr[elim_of[ci]];
+          size_t x = std::lower_bound(nb.begin(), nb.end(), cj) - nb.begin();
+          int64_t row = d.m + L.inbr_off[elim_of[ci]][x] + lj;
+          P.csr_dst[e] = d.front_off + row + (int64_t)li * ld;
+        }
+      } else if (elim_of[cj] >= 0) {
+        // separator row, interior column: written from the symmetric entry
+      } else if (ci <= cj) {
+        int pid = L.find_pair(ci, cj);
+        const PairDesc& pd = L.pairs[pid];
+        P.csr_dst[e] = L.front_elems + pd.blk_off + li + (int64_t)lj * pd.s_a;
+      }
+    }
+  }
+  for (int64_t d : P.csr_dst)
+    if (d >= L.front_elems + L.blk_elems) throw std::runtime_error("plan bounds check failed: CSR fill");
+  validate_level(L, P.n, P.pi);
+  P.levels.clear();
+  P.levels.push_back(std::move(L));
+}
+
+// Next level from the current one once its ranks are known (Secs. 4.3-4.4).
+// Returns the copy maps for the pair blocks and for Phi.
+inline void plan_next_level(Plan& P, std::vector<CopyDesc>& blk_map, std::vector<CopyDesc>& phi_map) {
+  const Options& o = P.opt;
+  Level& C = P.levels.back();
+  const Partition& lo = P.parts.back();
+  Partition hi = make_partition(o, lo.d * 2);
+  // surviving clusters: the separators, with their post-compression sizes
+  std::vector<int64_t> fcell(C.seps.size());
+  for (size_t p = 0; p < C.seps.size(); ++p) fcell[p] = father_cell(lo, hi, C.cell[C.seps[p]]);
+  std::vector<int64_t> uniq(fcell);
+  std::sort(uniq.begin(), uniq.end());
+  uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
+  Level N;
+  N.t = C.t + 1;
+  const int nc = (int)uniq.size();
+  std::vector<int32_t> father(C.seps.size());
+  for (size_t p = 0; p < C.seps.size(); ++p)
+    father[p] = (int32_t)(std::lower_bound(uniq.begin(), uniq.end(), fcell[p]) - uniq.begin());
+  N.cell = uniq;
+  N.type.resize(nc);
+  for (int c = 0; c < nc; ++c) N.type[c] = hi.type_of(uniq[c]);
+  N.size.assign(nc, 0);
+  std::vector<int32_t> loc(C.seps.size());
+  for (size_t p = 0; p < C.seps.size(); ++p) {     // seps ascending: children in order
+    int a = C.seps[p];
+    loc[p] = N.size[father[p]];
+    N.size[father[p]] += C.post_size(a);
+  }
+  int64_t n_active = 0, biggest = 0;
+  for (int c = 0; c < nc; ++c) {
+    n_active += N.size[c];
+    biggest = std::max<int64_t>(biggest, N.size[c]);
+  }
+  P.max_node = std::max<int64_t>(P.max_node, biggest);
+  bool top = hi.is_root || (o.stop_rule == 1 && n_active < P.max_node);
+  if (top && nc > 1) {
+    // merge every cluster of the new partition into one, ascending cell id
+    std::vector<int32_t> base(nc, 0);
+    for (int c = 1; c < nc; ++c) base[c] = base[c - 1] + N.size[c - 1];
+    for (size_t p = 0; p < C.seps.size(); ++p) loc[p] += base[father[p]];
+    for (auto& f : father) f = 0;
+    N.cell = {uniq[0]};
+    N.type = {0};
+    N.size = {(int32_t)n_active};
+  }
+  N.top = top;
+  const int nc2 = (int)N.cell.size();
+  N.compress = !top && o.compress && N.t >= o.compress_from_level;
+  // slots: concatenation of the children's first post-size slots
+  std::vector<std::vector<int32_t>> sl(nc2);
+  for (int c = 0; c < nc2; ++c) sl[c].resize(N.size[c]);
+  for (size_t p = 0; p < C.seps.size(); ++p) {
+    int a = C.seps[p];
+    int r = C.post_size(a);
+    for (int i = 0; i < r; ++i) sl[father[p]][loc[p] + i] = C.slots[C.slot_ptr[a] + i];
+  }
+  N.slot_ptr.assign(nc2 + 1, 0);
+  for (int c = 0; c < nc2; ++c) N.slot_ptr[c + 1] = N.slot_ptr[c] + N.size[c];
+  N.slots.reserve(N.slot_ptr[nc2]);
+  for (int c = 0; c < nc2; ++c) N.slots.insert(N.slots.end(), sl[c].begin(), sl[c].end());
+  // adjacency: fathers of adjacent separators
+  N.adj.assign(nc2, {});
+  for (size_t p = 0; p < C.seps.size(); ++p)
+    for (int b : C.sadj[p]) {
+      int fa = father[p], fb = father[C.sep_pos[b]];
+      if (fa != fb) N.adj[fa].push_back(fb);
+    }
+  for (auto& v : N.adj) {
+    std::sort(v.begin(), v.end());
+    v.erase(std::unique(v.begin(), v.end()), v.end());
+  }
+  build_level(N, o, P.pi);
+  // copy maps: level-C pair blocks (coarse part, ld s_a) -> level-N storage
+  blk_map.clear();
+  phi_map.clear();
+  std::vector<int32_t> elim_of(nc2, -1);
+  for (size_t ii = 0; ii < N.interiors.size(); ++ii) elim_of[N.interiors[ii]] = (int32_t)ii;
+  auto front_nbr_row = [&](int I, int X) {
+    int ii = elim_of[I];
+    const auto& nb = N.inbr[ii];
+    size_t x = std::lower_bound(nb.begin(), nb.end(), X) - nb.begin();
+    return N.elim[ii].m + N.inbr_off[ii][x];
+  };
+  for (const PairDesc& pd : C.pairs) {
+    int pa = C.sep_pos[pd.a], pb = C.sep_pos[pd.b];
+    int ra = C.post_size(pd.a), rb = C.post_size(pd.b);
+    if (ra == 0 || rb == 0) continue;
+    int Da = father[pa], Db = father[pb];
+    int oa = loc[pa], ob = loc[pb];
+    CopyDesc cd{};
+    cd.src_off = C.front_elems + pd.blk_off;
+    cd.src_ld = pd.s_a;
+    cd.rows = ra;
+    cd.cols = rb;
+    if (Da == Db) {
+      int64_t base, ld;
+      if (elim_of[Da] >= 0) {
+        const ElimDesc& e = N.elim[elim_of[Da]];
+        base = e.front_off;
+        ld = (int64_t)e.m + e.k;
+      } else {
+        const PairDesc& q = N.pairs[N.find_pair(Da, Da)];
+        base = N.front_elems + q.blk_off;
+        ld = q.s_a;
+      }
+      cd.dst_ld = (int32_t)ld;
+      cd.mode = 0;
+      cd.dst_off = base + oa + (int64_t)ob * ld;
+      blk_map.push_back(cd);
+      if (pd.a != pd.b) {
+        cd.mode = 1;
+        cd.dst_off = base + ob + (int64_t)oa * ld;
+        blk_map.push_back(cd);
+      }
+    } else if (elim_of[Da] >= 0) {
+      const ElimDesc& e = N.elim[elim_of[Da]];
+      int64_t ld = (int64_t)e.m + e.k;
+      cd.dst_ld = (int32_t)ld;
+      cd.mode = 1;
+      cd.dst_off = e.front_off + (front_nbr_row(Da, Db) + ob) + (int64_t)oa * ld;
+      blk_map.push_back(cd);
+    } else if (elim_of[Db] >= 0) {
+      const ElimDesc& e = N.elim[elim_of[Db]];
+      int64_t ld = (int64_t)e.m + e.k;
+      cd.dst_ld = (int32_t)ld;
+      cd.mode = 0;
+      cd.dst_off = e.front_off + (front_nbr_row(Db, Da) + oa) + (int64_t)ob * ld;
+      blk_map.push_back(cd);
+    } else {
+      if (Da < Db) {
+        const PairDesc& q = N.pairs[N.find_pair(Da, Db)];
+        cd.dst_ld = q.s_a;
+        cd.mode = 0;
+        cd.dst_off = N.front_elems + q.blk_off + oa + (int64_t)ob * q.s_a;
+      } else {
+        const PairDesc& q = N.pairs[N.find_pair(Db, Da)];
+        cd.dst_ld = q.s_a;
+        cd.mode = 1;
+        cd.dst_off = N.front_elems + q.blk_off + ob + (int64_t)oa * q.s_a;
+      }
+      blk_map.push_back(cd);
+    }
+  }
+  if (!N.top) {
+    for (size_t p = 0; p < C.seps.size(); ++p) {
+      int a = C.seps[p];
+      int r = C.post_size(a);
+      if (r == 0) continue;
+      CopyDesc cd{};
+      cd.src_off = C.phi_off[a];
+      cd.src_ld = C.size[a];
+      cd.rows = r;
+      cd.cols = P.pi;
+      cd.mode = 0;
+      int D = father[p];
+      cd.dst_ld = N.size[D];
+      cd.dst_off = N.phi_off[D] + loc[p];
+      phi_map.push_back(cd);
+    }
+  }
+  validate_level(N, P.n, P.pi);
+  validate_copies(blk_map, C.front_elems + C.blk_elems, N.front_elems + N.blk_elems);
+  validate_copies(phi_map, C.phi_elems, N.phi_elems);
+  P.parts.push_back(hi);
+  P.levels.push_back(std::move(N));
+}
+
+}  // namespace sgf

@@ -1,0 +1,193 @@
+"""Thin ctypes binding of libsgf.so (the C ABI declared in include/sgf.h).
+
+Argument marshalling only: every step of the factorization, the apply and
+CG runs in the HIP library.  PyTorch tensors provide device memory and the
+stream (``torch.cuda.current_stream().cuda_stream``).  There is no fallback:
+if the shared library is missing, importing this module raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsgf.so")
+
+SGF_OK, SGF_EINVAL, SGF_ENOTSPD, SGF_ENOMEM, SGF_EDEVICE, SGF_ENOCONV, SGF_ESTATE = range(7)
+NEST_ALL_ALL, NEST_2_ALL = 0, 1
+STOP_ROOT, STOP_PAPER = 0, 1
+FP64, FP32 = 0, 1
+
+EXPORTED = ["sgf_default_options", "sgf_analyze", "sgf_factorize_numeric", "sgf_factorize",
+            "sgf_apply", "sgf_multiply", "sgf_pcg_solve", "sgf_spmv", "sgf_get_info",
+            "sgf_get_perm", "sgf_get_level", "sgf_plan_dry_run", "sgf_destroy", "sgf_status_str",
+            "sgf_last_error"]
+
+RANK_FN = ctypes.CFUNCTYPE(ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p)
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("grid", ctypes.c_int32 * 3), ("dofs_per_node", ctypes.c_int32),
+                ("q", ctypes.c_int32), ("leaf", ctypes.c_int32), ("scheme", ctypes.c_int32),
+                ("compress", ctypes.c_int32), ("compress_from_level", ctypes.c_int32),
+                ("stop_rule", ctypes.c_int32), ("precision", ctypes.c_int32), ("rank_tol", ctypes.c_double)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("n", ctypes.c_int64), ("top_size", ctypes.c_int64),
+                ("factor_entries", ctypes.c_int64), ("factor_bytes", ctypes.c_int64),
+                ("compressed", ctypes.c_int64), ("factor_flops", ctypes.c_double),
+                ("apply_bytes", ctypes.c_double), ("failed_cluster", ctypes.c_int32),
+                ("failed_level", ctypes.c_int32)]
+
+
+class SgfError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+def load_library(path=LIB_PATH):
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_1907_03406_amd.build`")
+    lib = ctypes.CDLL(path)
+    P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    H = ctypes.c_void_p
+    sig = {
+        "sgf_default_options": (None, [ctypes.POINTER(Options)]),
+        "sgf_analyze": (I32, [I64, P, P, P, ctypes.POINTER(Options), ctypes.POINTER(H)]),
+        "sgf_factorize_numeric": (I32, [H, P, P]),
+        "sgf_factorize": (I32, [I64, P, P, P, P, ctypes.POINTER(Options), P, ctypes.POINTER(H)]),
+        "sgf_apply": (I32, [H, I32, P, I64, P, I64, P]),
+        "sgf_multiply": (I32, [H, I32, P, I64, P, I64, P]),
+        "sgf_pcg_solve": (I32, [H, I32, P, I64, P, I64, D, I32, P, P, P]),
+        "sgf_spmv": (I32, [H, P, P, P]),
+        "sgf_get_info": (I32, [H, ctypes.POINTER(Info)]),
+        "sgf_get_perm": (I32, [H, P]),
+        "sgf_get_level": (I32, [H, I32, P, P, P, P, P]),
+        "sgf_plan_dry_run": (I32, [H, RANK_FN, P]),
+        "sgf_destroy": (I32, [H]),
+        "sgf_status_str": (ctypes.c_char_p, [I32]),
+        "sgf_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_lib = load_library()
+
+
+def _check(code):
+    if code != SGF_OK:
+        raise SgfError(code, _lib.sgf_last_error().decode())
+
+
+def make_options(dim, grid, dofs_per_node=1, q=1, leaf=8, scheme=NEST_ALL_ALL, compress=True,
+                 compress_from_level=1, stop_rule=STOP_ROOT, precision=FP64, rank_tol=0.0):
+    o = Options()
+    _lib.sgf_default_options(ctypes.byref(o))
+    o.dim = dim
+    for a in range(3):
+        o.grid[a] = int(grid[a]) if a < len(grid) else 1
+    o.dofs_per_node = dofs_per_node
+    o.q, o.leaf, o.scheme = q, leaf, scheme
+    o.compress = 1 if compress else 0
+    o.compress_from_level = compress_from_level
+    o.stop_rule, o.precision, o.rank_tol = stop_rule, precision, rank_tol
+    return o
+
+
+def _ptr(a):
+    return ctypes.c_void_p(a.ctypes.data) if isinstance(a, np.ndarray) else ctypes.c_void_p(a.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return ctypes.c_void_p(stream)
+
+
+class Solver:
+    """One SGF factorization handle.
+
+    ``Solver(problem_arrays, options)`` runs the symbolic analysis (host
+    only).  ``factorize(vals)`` takes the CSR values as a device FP64 tensor.
+    """
+
+    def __init__(self, n, indptr, indices, coords, opt):
+        self.n = int(n)
+        self._indptr = np.ascontiguousarray(indptr, dtype=np.int64)
+        self._indices = np.ascontiguousarray(indices, dtype=np.int32)
+        self._coords = np.ascontiguousarray(coords, dtype=np.float64)
+        self.opt = opt
+        h = ctypes.c_void_p()
+        _check(_lib.sgf_analyze(self.n, _ptr(self._indptr), _ptr(self._indices), _ptr(self._coords),
+                                ctypes.byref(opt), ctypes.byref(h)))
+        self.h = h
+
+    @classmethod
+    def from_problem(cls, prob, **kw):
+        opt = make_options(prob.dim, prob.grid, prob.dpn, **kw)
+        return cls(prob.n, prob.indptr, prob.indices, prob.coords, opt)
+
+    def close(self):
+        if self.h:
+            _lib.sgf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def factorize(self, vals, stream=None):
+        _check(_lib.sgf_factorize_numeric(self.h, _ptr(vals), _stream(stream)))
+
+    def apply(self, r, z, stream=None):
+        nrhs = 1 if r.dim() == 1 else r.shape[1]
+        _check(_lib.sgf_apply(self.h, nrhs, _ptr(r), self.n, _ptr(z), self.n, _stream(stream)))
+
+    def multiply(self, v, y, stream=None):
+        nrhs = 1 if v.dim() == 1 else v.shape[1]
+        _check(_lib.sgf_multiply(self.h, nrhs, _ptr(v), self.n, _ptr(y), self.n, _stream(stream)))
+
+    def spmv(self, v, y, stream=None):
+        _check(_lib.sgf_spmv(self.h, _ptr(v), _ptr(y), _stream(stream)))
+
+    def pcg(self, b, x, rtol=1e-8, maxit=500, stream=None, raise_on_noconv=True):
+        nrhs = 1 if b.dim() == 1 else b.shape[1]
+        iters = np.zeros(nrhs, dtype=np.int32)
+        rel = np.zeros(nrhs, dtype=np.float64)
+        code = _lib.sgf_pcg_solve(self.h, nrhs, _ptr(b), self.n, _ptr(x), self.n, float(rtol), int(maxit),
+                                  _ptr(iters), _ptr(rel), _stream(stream))
+        if code != SGF_ENOCONV or raise_on_noconv:
+            _check(code)
+        return iters, rel
+
+    def info(self):
+        i = Info()
+        _check(_lib.sgf_get_info(self.h, ctypes.byref(i)))
+        return {f: getattr(i, f) for f, _ in Info._fields_}
+
+    def perm(self):
+        p = np.zeros(self.n, dtype=np.int64)
+        _check(_lib.sgf_get_perm(self.h, _ptr(p)))
+        return p
+
+    def plan_dry_run(self, rank_of):
+        """Host-only planning of every level with ranks from ``rank_of(level, cell, size)``."""
+        cb = RANK_FN(lambda t, cell, size, ctx: int(rank_of(t, cell, size)))
+        _check(_lib.sgf_plan_dry_run(self.h, cb, None))
+
+    def level(self, t):
+        cnt = ctypes.c_int32()
+        _check(_lib.sgf_get_level(self.h, t, ctypes.byref(cnt), None, None, None, None))
+        c = cnt.value
+        out = [np.zeros(c, dtype=np.int32) for _ in range(4)]
+        _check(_lib.sgf_get_level(self.h, t, ctypes.byref(cnt), *[_ptr(a) for a in out]))
+        return dict(zip(("cell", "type", "size", "rank"), out))
