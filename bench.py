@@ -1,0 +1,246 @@
+"""Benchmark: SGF-preconditioned CG on one MI355X.
+
+One step = one pass of the whole hot path on the resident synthetic problem:
+numeric SGF factorization (every level: interior elimination, separator
+compression, coarsening, exact top) followed by a CG solve of a fresh
+right-hand side to 1e-8 relative residual, preconditioned by the factor.
+The level-1 symbolic analysis (integer planning that depends only on the
+grid) is done once before timing, as a solver reusing its analysis would;
+its host time is reported beside the step.
+
+Prints ONE JSON line.  Usage: python bench.py [--steps K] [--warmup W]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
+
+WORKLOADS = {
+    "varcoef2d_1024": "2D -div(a grad u), 5-point FD on a 1024^2 grid (n=1,048,576), a=exp(g), g a Gaussian "
+                      "random field from 64 seeded random Fourier modes (corr. length 0.05, sigma 1), Dirichlet; "
+                      "SGF Nest-All-All, q=2, leaf 16x16; rhs U[-1,1]; CG to 1e-8",
+    "poisson2d_64": "2D Poisson, 5-point FD on 64^2 (n=4096), a=1; q=1, leaf 8x8; CG to 1e-10",
+    "varcoef3d_128": "3D -div(a grad u), 7-point FD on 128^3 (n=2,097,152), a=10^u, u~U(-2,2) constant on 8^3 "
+                     "boxes; q=1, leaf 8^3; CG to 1e-8",
+    "elasticity3d_48": "3D linear elasticity, Q1 hexahedra on 48^3 nodes (n=324,864), E=1/100 with 20 random "
+                       "inclusions, nu=0.3, x=0 clamped; q=1, leaf 6; CG to 1e-8",
+}
+
+
+def source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1907_03406_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        t = json.load(open(path))
+    except ValueError:
+        return None
+    rec = t.get(kernel)
+    if not rec or rec.get("source_hash") != source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def run_form(prob, cfg, precision, steps, warmup, profile, seed=0, log=None):
+    import torch
+    from paper_1907_03406_amd import sgf
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    s = sgf.Solver.from_problem(prob, q=cfg["q"], leaf=cfg["leaf"],
+                                precision=sgf.FP32 if precision == "fp32" else sgf.FP64)
+    t_an = time.perf_counter() - t0
+    vals = torch.from_numpy(prob.data).to(dev)
+    from sgf_inputs.problems import random_rhs
+    nrhs = cfg.get("nrhs", 1)
+    rhs = [torch.from_numpy(np.ascontiguousarray(
+        np.stack([random_rhs(seed, prob.n, j * nrhs + c) for c in range(nrhs)], axis=0))).to(dev)
+        for j in range(steps + warmup)]
+    x = torch.zeros(nrhs, prob.n, dtype=torch.float64, device=dev)
+    tol = cfg["tol"]
+    its, lat, fac = [], [], []
+    for j in range(warmup + steps):
+        if j == warmup:
+            torch.cuda.synchronize()
+            if profile:
+                s.profile(True)
+            t_start = time.perf_counter()
+        ts = time.perf_counter()
+        s.factorize(vals)
+        tf = time.perf_counter()
+        it, rel = s.pcg(rhs[j].T, x.T, rtol=tol, maxit=1000)
+        te = time.perf_counter()
+        if j >= warmup:
+            lat.append(te - ts)
+            fac.append(tf - ts)
+            its.append(int(it.max()))
+        if log:
+            print(f"[bench] {precision} step {j} factor {1e3 * (tf - ts):.1f} ms solve {1e3 * (te - tf):.1f} ms "
+                  f"it {it.tolist()}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_start
+    stats = s.profile_read() if profile else {}
+    if profile:
+        s.profile(False)
+    info = s.info()
+    # true residual of the last solve
+    A = prob.csr()
+    xb = x.cpu().numpy()
+    bb = rhs[-1].cpu().numpy()
+    true_rel = max(np.linalg.norm(bb[c] - A @ xb[c]) / np.linalg.norm(bb[c]) for c in range(nrhs))
+    s.close()
+    return dict(total=total, lat=lat, fac=fac, its=its, info=info, stats=stats, analyze_s=t_an,
+                true_rel=true_rel, nrhs=nrhs)
+
+
+def roofline(stats, precision, steps):
+    if not stats:
+        return None
+    name, k = max(stats.items(), key=lambda kv: kv[1]["ms"])
+    per = k["ms"] / max(k["launches"], 1)
+    if k["flops"] > 0:
+        peak = FP32_PEAK_TFLOPS if precision == "fp32" else FP64_PEAK_TFLOPS
+        ach = k["flops"] / (k["ms"] * 1e-3) / 1e12
+        return {"kernel": name, "bound": "alu", "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(ach / peak, 4), "traffic": traffic_for(name),
+                "avg_launch_ms": round(per, 4), "launches": k["launches"], "share_of_gpu_time": None}
+    ach = k["bytes"] / (k["ms"] * 1e-3) / 1e9
+    return {"kernel": name, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic_for(name),
+            "avg_launch_ms": round(per, 4), "launches": k["launches"]}
+
+
+def cpu_baseline(key, seed, sample_grid):
+    """The oracle (FP64 NumPy) on a bounded sample of the workload, one thread,
+    scaled to the full problem by the unknown count (the method is O(n))."""
+    from threadpoolctl import threadpool_limits
+    from oracle import sgf_oracle as O
+    from sgf_inputs.problems import config_problem, random_rhs
+    from sgf_inputs.problems import CONFIGS
+    p, cfg = config_problem(key, seed=seed, grid=sample_grid)
+    c = CONFIGS[key]
+    n_full = int(np.prod(c["grid"])) if "grid" in c else 3 * (c["nodes"] - 1) * c["nodes"] ** 2
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        F = O.factorize(p.csr(), p.coords, p.grid, p.dpn, O.Options(q=cfg["q"], leaf=cfg["leaf"]))
+        t1 = time.perf_counter()
+        x, it, rel = O.pcg(p.csr(), random_rhs(seed, p.n), lambda r: O.apply_inverse(F, r), tol=cfg["tol"])
+        t2 = time.perf_counter()
+    per_solve = (t2 - t0) * n_full / p.n
+    return {"value": round(1.0 / per_solve, 6), "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"{key} at grid {tuple(sample_grid)} (n={p.n}): factorize {t1 - t0:.1f} s + CG {t2 - t1:.1f} s "
+                      f"({it} it), FP64 NumPy, one thread; scaled by n_full/n_sample = {n_full / p.n:.0f}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="varcoef2d_1024", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--no-fp64-form", action="store_true", help="skip the plain FP64 comparison form")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--verbose", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 (the multi-GPU sharding "
+                                   "of the factor is a design note, not implemented)"}))
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    from sgf_inputs.problems import config_problem
+    t0 = time.perf_counter()
+    prob, cfg = config_problem(a.config, seed=a.seed)
+    t_gen = time.perf_counter() - t0
+    main_form = run_form(prob, cfg, a.precision, a.steps, a.warmup, profile=True, seed=a.seed, log=a.verbose)
+    other = None
+    if not a.no_fp64_form and a.precision != "fp64":
+        other = run_form(prob, cfg, "fp64", max(2, a.steps // 2), 1, profile=True, seed=a.seed, log=a.verbose)
+    lat = np.array(main_form["lat"]) * 1e3
+    steps = a.steps
+    ms = main_form["total"] / steps * 1e3
+    st = main_form["stats"]
+    gpu_ms = sum(v["ms"] for v in st.values())
+    apply_ms = sum(v["ms"] for k, v in st.items() if k.startswith("apply_"))
+    apply_bytes = sum(v["bytes"] for k, v in st.items() if k.startswith("apply_"))
+    elim = st.get("elim", {"ms": 0, "flops": 0})
+    fac_flops = main_form["info"]["factor_flops"]
+    fac_ms = float(np.mean(main_form["fac"])) * 1e3
+    rl = roofline(st, a.precision, steps)
+    if rl is not None:
+        rl["share_of_gpu_time"] = round(st[rl["kernel"]]["ms"] / gpu_ms, 3) if gpu_ms else None
+    out = {
+        "metric": "PCG solves/s (numeric SGF factorization + CG solve to 1e-8 relative residual per solve)",
+        "value": round(1e3 / ms, 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if a.precision == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{a.config}: {WORKLOADS[a.config]}",
+            "n": prob.n, "nnz": prob.nnz, "q": cfg["q"], "leaf": cfg["leaf"], "tol": cfg["tol"],
+            "factor_apply_dtype": "f32" if a.precision == "fp32" else "f64", "cg_dtype": "f64",
+            "nrhs": main_form["nrhs"], "seed": a.seed,
+        },
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3), "p99": round(float(np.percentile(lat, 99)), 3)},
+        "it_C": main_form["its"],
+        "true_rel_residual": float(main_form["true_rel"]),
+        "factor_ms": round(fac_ms, 3),
+        "factor_tflops": round(fac_flops / (fac_ms * 1e-3) / 1e12, 4),
+        "elim_kernel_tflops": round(elim["flops"] / (elim["ms"] * 1e-3) / 1e12, 4) if elim["ms"] else None,
+        "apply_gbs": round(apply_bytes / (apply_ms * 1e-3) / 1e9, 1) if apply_ms else None,
+        "pcg_only_solves_per_s": round(1e3 / (ms - fac_ms), 3) if ms > fac_ms else None,
+        "gpu_kernel_ms_per_step": round(gpu_ms / steps, 3),
+        "levels": main_form["info"]["levels"], "top_size": main_form["info"]["top_size"],
+        "factor_bytes": main_form["info"]["factor_bytes"],
+        "analyze_s": round(main_form["analyze_s"], 3), "problem_gen_s": round(t_gen, 2),
+        "kernels": {k: {"ms_per_step": round(v["ms"] / steps, 4), "launches_per_step": round(v["launches"] / steps, 1)}
+                    for k, v in sorted(st.items(), key=lambda kv: -kv[1]["ms"])},
+        "roofline": rl,
+    }
+    if other is not None:
+        oms = other["total"] / len(other["lat"]) * 1e3
+        out["fp64_form"] = {"value": round(1e3 / oms, 4), "ms_per_step": round(oms, 3), "it_C": other["its"],
+                            "factor_ms": round(float(np.mean(other["fac"])) * 1e3, 3),
+                            "speedup_of_main_form": round(oms / ms, 3)}
+    if not a.no_cpu_baseline:
+        sample = {"varcoef2d_1024": (256, 256), "poisson2d_64": (64, 64), "varcoef3d_128": (32, 32, 32),
+                  "elasticity3d_48": 12}[a.config]
+        out["cpu_baseline"] = cpu_baseline(a.config, a.seed, sample)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

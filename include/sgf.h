@@ -181,6 +181,25 @@ sgf_status sgf_get_level(sgf_handle h, int32_t level, int32_t* count, int32_t* c
 typedef int32_t (*sgf_rank_fn)(int32_t level, int64_t cell_id, int32_t size, void* ctx);
 sgf_status sgf_plan_dry_run(sgf_handle h, sgf_rank_fn rank_fn, void* ctx);
 
+/*
+ * Kernel timing.  While enabled, every kernel launch of the handle is
+ * bracketed by two hipEvents recorded on the launch stream, and charged to
+ * its kernel class together with the algorithmic work of that launch
+ * (flops for the factorization kernels, bytes that must cross HBM for the
+ * apply / CG kernels, both from the plan).  sgf_profile_enable(h, 1) clears
+ * the counters; sgf_profile_read synchronizes the pending events and copies
+ * up to `cap` records (count receives the number of classes).
+ */
+typedef struct {
+  char name[32];
+  int64_t launches;
+  double ms;      /* summed event time of the launches                  */
+  double flops;   /* summed algorithmic flops                            */
+  double bytes;   /* summed algorithmic bytes                            */
+} sgf_kernel_stat;
+sgf_status sgf_profile_enable(sgf_handle h, int32_t enable);
+sgf_status sgf_profile_read(sgf_handle h, sgf_kernel_stat* out, int32_t cap, int32_t* count);
+
 /* Releases every host and device resource of the handle (NULL is a no-op). */
 sgf_status sgf_destroy(sgf_handle h);
 

@@ -82,11 +82,71 @@ void upload(DevBuf& b, const std::vector<V>& v, hipStream_t st) {
   if (!v.empty()) HIP_CHECK(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(V), hipMemcpyHostToDevice, st));
 }
 
+// Algorithmic work of the launches of one level (from the plan).
+struct LevelWork {
+  double elim_flops = 0, schur_bytes = 0, comp_flops = 0, pair_flops = 0;
+  double fwd_bytes = 0, bwd_bytes = 0, fwd_vec = 0, bwd_vec = 0;   // factor part / per-rhs vector part
+  double acc_vec = 0, capply_bytes = 0, capply_vec = 0, top_bytes = 0, top_vec = 0;
+};
+
 struct LevelDev {
   DevBuf arena, scratch, cf, nbuf, ltphi, tau, phi, rank;
   DevBuf elim, pairs, schur, comp, compnbr, sepacc, sepsrc, capply, slots, nslots;
   DevBuf blkmap, phimap, slotptr, phioff;
   std::vector<sgf::CopyDesc> h_blkmap, h_phimap;
+  LevelWork work;
+};
+
+struct Profiler {
+  bool on = false;
+  std::vector<sgf_kernel_stat> stats;
+  struct Pending {
+    int idx;
+    hipEvent_t a, b;
+    double flops, bytes;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  int index(const char* name) {
+    for (size_t i = 0; i < stats.size(); ++i)
+      if (std::strncmp(stats[i].name, name, sizeof(stats[i].name)) == 0) return (int)i;
+    sgf_kernel_stat k{};
+    std::snprintf(k.name, sizeof(k.name), "%s", name);
+    stats.push_back(k);
+    return (int)stats.size() - 1;
+  }
+  hipEvent_t event() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) throw std::runtime_error("hipEventCreate failed");
+    return e;
+  }
+  void drain() {
+    for (auto& p : pending) {
+      float ms = 0;
+      if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+        auto& k = stats[p.idx];
+        k.launches += 1;
+        k.ms += ms;
+        k.flops += p.flops;
+        k.bytes += p.bytes;
+      }
+      pool.push_back(p.a);
+      pool.push_back(p.b);
+    }
+    pending.clear();
+  }
+  ~Profiler() {
+    for (auto& p : pending) {
+      (void)hipEventDestroy(p.a);
+      (void)hipEventDestroy(p.b);
+    }
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
 };
 
 constexpr size_t LDS_BYTES = 64 * 1024;
@@ -113,6 +173,7 @@ struct sgf_handle_s {
   int32_t failed_cluster = -1, failed_level = -1;
   double factor_flops = 0, apply_bytes = 0;
   int64_t factor_entries = 0, factor_bytes = 0, compressed = 0;
+  Profiler prof;
 };
 
 namespace {
@@ -134,6 +195,23 @@ sgf_status guard(F&& f) {
   } catch (const std::exception& e) {
     return fail(SGF_EINVAL, e.what());
   }
+}
+
+// Runs `f` (one kernel launch); when profiling, brackets it with events.
+template <typename F>
+void launch(sgf_handle h, hipStream_t st, const char* name, double flops, double bytes, F&& f) {
+  if (!h->prof.on) {
+    f();
+    return;
+  }
+  Profiler& p = h->prof;
+  int idx = p.index(name);
+  hipEvent_t a = p.event(), b = p.event();
+  HIP_CHECK(hipEventRecord(a, st));
+  f();
+  HIP_CHECK(hipEventRecord(b, st));
+  p.pending.push_back({idx, a, b, flops, bytes});
+  if (p.pending.size() > 4096) p.drain();
 }
 
 void check_options(const sgf_options* o, int64_t n) {
@@ -214,31 +292,48 @@ int check_fail(sgf_handle h, hipStream_t st) {
   return f;
 }
 
-void account_level(sgf_handle h, const sgf::Level& L) {
+void account_level(sgf_handle h, const sgf::Level& L, LevelWork& W) {
+  W = LevelWork{};
+  const double e = (double)h->esz;
   for (const auto& d : L.elim) {
-    double m = d.m, k = d.k;
-    h->factor_flops += m * m * m / 3.0 + m * m * k + m * k * k;
-    h->factor_entries += (int64_t)d.m * (d.m + 1) / 2 + (int64_t)d.m * d.k;
-    h->apply_bytes += 2.0 * ((double)d.m * (d.m + 1) / 2 + (double)d.m * d.k) * h->esz;
+    double m = d.m, k = d.k, tri = m * (m + 1) / 2;
+    W.elim_flops += m * m * m / 3.0 + m * m * k + m * k * k;
+    h->factor_entries += (int64_t)(tri + m * k);
+    if (L.top) {
+      W.top_bytes += tri * e;
+      W.top_vec += 2 * m * e + 4 * m;
+    } else {
+      W.fwd_bytes += (tri + m * k) * e;
+      W.bwd_bytes += (tri + m * k) * e;
+      W.fwd_vec += (2 * m + k) * e + 4 * m;
+      W.bwd_vec += (2 * m + k) * e + 4 * (m + k);
+    }
   }
+  for (const auto& a : L.sepacc) W.acc_vec += (double)a.s * (a.c_cnt + 2) * e + 4.0 * a.s + 8.0 * a.c_cnt;
   const int pi = h->plan.pi;
   for (size_t c = 0; c < L.comp.size(); ++c) {
     const auto& d = L.comp[c];
     double s = d.s, K = d.K, cc = d.c, r = L.rank.empty() ? 0 : L.rank[c];
-    h->factor_flops += s * s * s / 3.0 + s * s * K + s * s * pi + 2.0 * s * K * pi;
-    h->factor_flops += 4.0 * s * cc * r - 2.0 * r * r * (s + cc) + 4.0 * r * r * r / 3.0;
+    W.comp_flops += s * s * s / 3.0 + s * s * K + s * s * pi + 2.0 * s * K * pi;
+    W.comp_flops += 4.0 * s * cc * r - 2.0 * r * r * (s + cc) + 4.0 * r * r * r / 3.0;
   }
   for (const auto& a : L.capply) {
-    h->factor_entries += (int64_t)a.s * (a.s + 1) / 2 + (int64_t)a.s * a.r;
-    h->apply_bytes += 2.0 * ((double)a.s * (a.s + 1) / 2 + (double)a.s * a.r) * h->esz;
+    double s = a.s, r = a.r;
+    h->factor_entries += (int64_t)(s * (s + 1) / 2 + s * r);
+    W.capply_bytes += (s * (s + 1) / 2 + s * r) * e;
+    W.capply_vec += 2 * s * e + 4 * s;
   }
   for (const auto& p : L.pairs) {
-    if (p.a == p.b) continue;
+    W.schur_bytes += (double)p.s_a * p.s_b * (p.c_cnt + 2) * e;
+    if (p.a == p.b || L.rank.empty()) continue;
     int ra = p.ca >= 0 && L.rank[p.ca] < p.s_a ? L.rank[p.ca] : p.s_a;
     int rb = p.cb >= 0 && L.rank[p.cb] < p.s_b ? L.rank[p.cb] : p.s_b;
-    if (ra < p.s_a) h->factor_flops += 4.0 * (double)p.s_a * ra * p.s_b;
-    if (rb < p.s_b) h->factor_flops += (double)p.s_b * p.s_b * ra + 4.0 * (double)p.s_b * rb * ra;
+    if (ra < p.s_a) W.pair_flops += 4.0 * (double)p.s_a * ra * p.s_b;
+    if (rb < p.s_b) W.pair_flops += (double)p.s_b * p.s_b * ra + 4.0 * (double)p.s_b * rb * ra;
   }
+  h->factor_flops += W.elim_flops + W.comp_flops + W.pair_flops;
+  h->apply_bytes += W.fwd_bytes + W.bwd_bytes + W.fwd_vec + W.bwd_vec + W.acc_vec * 2 + 2 * W.capply_bytes +
+                    2 * W.capply_vec + W.top_bytes + W.top_vec;
 }
 
 template <typename T>
@@ -262,14 +357,18 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
     HIP_CHECK(hipMemcpyAsync(h->d_vals.p, vals, h->nnz * sizeof(double), hipMemcpyDefault, st));
   int init = -1;
   HIP_CHECK(hipMemcpyAsync(h->d_fail.p, &init, sizeof(int), hipMemcpyHostToDevice, st));
+  const double e = (double)sizeof(T);
   // ---- level 1 inputs ---------------------------------------------------------
   upload_level(h, 0, st);
   {
     sgf::Level& L = P.levels[0];
     LevelDev& D = h->lev[0];
-    zero<T>(D.arena, L.front_elems + L.blk_elems, st);
-    hipLaunchKernelGGL(sgf::k_fill_csr<T>, dim3(cdiv(h->nnz, sgf::WG)), dim3(sgf::WG), 0, st,
-                       h->d_vals.as<double>(), h->d_csrdst.as<int64_t>(), h->nnz, D.arena.as<T>());
+    const int64_t ne = L.front_elems + L.blk_elems;
+    launch(h, st, "zero", 0, ne * e, [&] { zero<T>(D.arena, ne, st); });
+    launch(h, st, "fill_csr", 0, h->nnz * (16.0 + e), [&] {
+      hipLaunchKernelGGL(sgf::k_fill_csr<T>, dim3(cdiv(h->nnz, sgf::WG)), dim3(sgf::WG), 0, st,
+                         h->d_vals.as<double>(), h->d_csrdst.as<int64_t>(), h->nnz, D.arena.as<T>());
+    });
     sgf::PhiInit pin{};
     for (int a = 0; a < 3; ++a) {
       pin.lo[a] = P.cmin[a];
@@ -281,9 +380,11 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
     pin.pi = P.pi;
     pin.p0 = P.pi / P.opt.dpn;
     if (!L.cell.empty())
-      hipLaunchKernelGGL(sgf::k_phi_init<T>, dim3((unsigned)L.cell.size()), dim3(sgf::WG), 0, st,
-                         D.slotptr.as<int64_t>(), D.phioff.as<int64_t>(), h->d_perm.as<int64_t>(),
-                         h->d_coords.as<double>(), pin, D.phi.as<T>());
+      launch(h, st, "phi_init", 0, (double)P.n * (P.pi * e + 8 + 8 * P.opt.dim), [&] {
+        hipLaunchKernelGGL(sgf::k_phi_init<T>, dim3((unsigned)L.cell.size()), dim3(sgf::WG), 0, st,
+                           D.slotptr.as<int64_t>(), D.phioff.as<int64_t>(), h->d_perm.as<int64_t>(),
+                           h->d_coords.as<double>(), pin, D.phi.as<T>());
+      });
   }
   // ---- level loop (Algorithm 4.1) --------------------------------------------
   for (int li = 0;; ++li) {
@@ -291,16 +392,21 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
     LevelDev& D = h->lev[li];
     T* arena = D.arena.as<T>();
     T* blocks = arena + L.front_elems;
-    for (const auto& e : L.elim) {
-      h->max_m_all = std::max(h->max_m_all, e.m);
-      h->max_k_all = std::max(h->max_k_all, e.k);
+    for (const auto& el : L.elim) {
+      h->max_m_all = std::max(h->max_m_all, el.m);
+      h->max_k_all = std::max(h->max_k_all, el.k);
     }
     h->max_t = std::max(h->max_t, L.t_elems);
+    double lvl_elim_flops = 0;
+    for (const auto& d : L.elim) lvl_elim_flops += (double)d.m * d.m * d.m / 3.0 + (double)d.m * d.m * d.k +
+                                                   (double)d.m * d.k * d.k;
     if (!L.elim.empty()) {
       int nb = nb_for(L.max_front_rows, sizeof(T));
       size_t lds = (size_t)nb * L.max_front_rows * sizeof(T);
-      hipLaunchKernelGGL(sgf::k_elim<T>, dim3((unsigned)L.elim.size()), dim3(sgf::WG), lds, st,
-                         D.elim.as<sgf::ElimDesc>(), arena, nb, h->d_fail.as<int>());
+      launch(h, st, L.top ? "top_potrf" : "elim", lvl_elim_flops, 0, [&] {
+        hipLaunchKernelGGL(sgf::k_elim<T>, dim3((unsigned)L.elim.size()), dim3(sgf::WG), lds, st,
+                           D.elim.as<sgf::ElimDesc>(), arena, nb, h->d_fail.as<int>());
+      });
     }
     if (L.top) {
       int f = check_fail(h, st);
@@ -310,28 +416,41 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
         h->failed_level = L.t;
         throw SgfError(SGF_ENOTSPD, "non-positive pivot at the top node");
       }
-      account_level(h, L);
+      account_level(h, L, D.work);
       break;
     }
-    if (!L.pairs.empty())
-      hipLaunchKernelGGL(sgf::k_schur<T>, dim3((unsigned)L.pairs.size()), dim3(sgf::WG), 0, st,
-                         D.pairs.as<sgf::PairDesc>(), D.schur.as<sgf::SchurDesc>(), arena, blocks);
+    if (!L.pairs.empty()) {
+      double sb = 0;
+      for (const auto& p : L.pairs) sb += (double)p.s_a * p.s_b * (p.c_cnt + 2) * e;
+      launch(h, st, "schur", 0, sb, [&] {
+        hipLaunchKernelGGL(sgf::k_schur<T>, dim3((unsigned)L.pairs.size()), dim3(sgf::WG), 0, st,
+                           D.pairs.as<sgf::PairDesc>(), D.schur.as<sgf::SchurDesc>(), arena, blocks);
+      });
+    }
     if (!L.comp.empty()) {
-      hipLaunchKernelGGL(sgf::k_comp_gather<T>, dim3((unsigned)L.comp.size()), dim3(sgf::WG), 0, st,
-                         D.comp.as<sgf::CompDesc>(), D.compnbr.as<sgf::CompNbr>(), blocks, D.cf.as<T>());
+      launch(h, st, "comp_gather", 0, 2.0 * L.cf_elems * e, [&] {
+        hipLaunchKernelGGL(sgf::k_comp_gather<T>, dim3((unsigned)L.comp.size()), dim3(sgf::WG), 0, st,
+                           D.comp.as<sgf::CompDesc>(), D.compnbr.as<sgf::CompNbr>(), blocks, D.cf.as<T>());
+      });
       int nb = nb_for(L.max_cf_rows, sizeof(T));
       size_t lds = std::max<size_t>((size_t)nb * L.max_cf_rows, (size_t)L.max_c) * sizeof(T);
       if (lds > LDS_BYTES) throw SgfError(SGF_EINVAL, "compression too wide for LDS");
       double tol = P.opt.rank_tol;
-      hipLaunchKernelGGL(sgf::k_compress<T>, dim3((unsigned)L.comp.size()), dim3(sgf::WG), lds, st,
-                         D.comp.as<sgf::CompDesc>(), D.compnbr.as<sgf::CompNbr>(), D.cf.as<T>(), D.nbuf.as<T>(),
-                         D.phi.as<T>(), D.ltphi.as<T>(), D.tau.as<T>(), D.rank.as<int>(), P.pi, nb, tol,
-                         h->d_fail.as<int>());
-      hipLaunchKernelGGL(sgf::k_phi_commit<T>, dim3((unsigned)L.comp.size()), dim3(sgf::WG), 0, st,
-                         D.comp.as<sgf::CompDesc>(), D.rank.as<int>(), D.ltphi.as<T>(), D.phi.as<T>(), P.pi);
-      hipLaunchKernelGGL(sgf::k_pair<T>, dim3((unsigned)L.pairs.size()), dim3(sgf::WG), 0, st,
-                         D.pairs.as<sgf::PairDesc>(), D.comp.as<sgf::CompDesc>(), D.rank.as<int>(), D.cf.as<T>(),
-                         D.nbuf.as<T>(), D.tau.as<T>(), blocks, D.scratch.as<T>());
+      launch(h, st, "compress", 0, 0, [&] {
+        hipLaunchKernelGGL(sgf::k_compress<T>, dim3((unsigned)L.comp.size()), dim3(sgf::WG), lds, st,
+                           D.comp.as<sgf::CompDesc>(), D.compnbr.as<sgf::CompNbr>(), D.cf.as<T>(), D.nbuf.as<T>(),
+                           D.phi.as<T>(), D.ltphi.as<T>(), D.tau.as<T>(), D.rank.as<int>(), P.pi, nb, tol,
+                           h->d_fail.as<int>());
+      });
+      launch(h, st, "phi_commit", 0, 0, [&] {
+        hipLaunchKernelGGL(sgf::k_phi_commit<T>, dim3((unsigned)L.comp.size()), dim3(sgf::WG), 0, st,
+                           D.comp.as<sgf::CompDesc>(), D.rank.as<int>(), D.ltphi.as<T>(), D.phi.as<T>(), P.pi);
+      });
+      launch(h, st, "pair", 0, 0, [&] {
+        hipLaunchKernelGGL(sgf::k_pair<T>, dim3((unsigned)L.pairs.size()), dim3(sgf::WG), 0, st,
+                           D.pairs.as<sgf::PairDesc>(), D.comp.as<sgf::CompDesc>(), D.rank.as<int>(), D.cf.as<T>(),
+                           D.nbuf.as<T>(), D.tau.as<T>(), blocks, D.scratch.as<T>());
+      });
     }
     HIP_CHECK(hipGetLastError());
     L.rank.assign(L.comp.size(), 0);
@@ -362,7 +481,7 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
       }
     }
     upload(D.capply, L.capply, st);
-    account_level(h, L);
+    account_level(h, L, D.work);
     // ---- coarsen (Secs. 4.3-4.4) ----------------------------------------------
     sgf::plan_next_level(P, D.h_blkmap, D.h_phimap);
     upload(D.blkmap, D.h_blkmap, st);
@@ -371,13 +490,21 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
     sgf::Level& N = P.levels[li + 1];
     LevelDev& E = h->lev[li + 1];
     LevelDev& Dc = h->lev[li];   // re-fetch: lev may have grown
-    zero<T>(E.arena, N.front_elems + N.blk_elems, st);
-    if (!Dc.h_blkmap.empty())
-      hipLaunchKernelGGL(sgf::k_copy_blocks<T>, dim3((unsigned)Dc.h_blkmap.size()), dim3(sgf::WG), 0, st,
-                         Dc.blkmap.as<sgf::CopyDesc>(), Dc.arena.as<T>(), E.arena.as<T>());
+    const int64_t ne = N.front_elems + N.blk_elems;
+    launch(h, st, "zero", 0, ne * e, [&] { zero<T>(E.arena, ne, st); });
+    if (!Dc.h_blkmap.empty()) {
+      double cb = 0;
+      for (const auto& c : Dc.h_blkmap) cb += 2.0 * c.rows * c.cols * e;
+      launch(h, st, "coarsen_copy", 0, cb, [&] {
+        hipLaunchKernelGGL(sgf::k_copy_blocks<T>, dim3((unsigned)Dc.h_blkmap.size()), dim3(sgf::WG), 0, st,
+                           Dc.blkmap.as<sgf::CopyDesc>(), Dc.arena.as<T>(), E.arena.as<T>());
+      });
+    }
     if (!Dc.h_phimap.empty())
-      hipLaunchKernelGGL(sgf::k_copy_blocks<T>, dim3((unsigned)Dc.h_phimap.size()), dim3(sgf::WG), 0, st,
-                         Dc.phimap.as<sgf::CopyDesc>(), Dc.phi.as<T>(), E.phi.as<T>());
+      launch(h, st, "coarsen_phi", 0, 0, [&] {
+        hipLaunchKernelGGL(sgf::k_copy_blocks<T>, dim3((unsigned)Dc.h_phimap.size()), dim3(sgf::WG), 0, st,
+                           Dc.phimap.as<sgf::CopyDesc>(), Dc.phi.as<T>(), E.phi.as<T>());
+      });
     HIP_CHECK(hipGetLastError());
   }
   // device bytes held by the factor
@@ -389,7 +516,7 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
   const auto& top = P.levels.back().elim[0];
   h->max_m_all = std::max(h->max_m_all, top.m);
   int64_t n = P.n;
-  h->apply_bytes += 2.0 * n * h->esz * 2;  // work vector read + write per sweep
+  h->apply_bytes += 2.0 * n * (8 + e + 8);  // permutation gather / scatter
   h->factored = true;
 }
 
@@ -407,84 +534,90 @@ void run_sweeps(sgf_handle h, int nrhs, bool product, hipStream_t st) {
   T* ts = h->tscr.as<T>();
   const int64_t ldt = std::max<int64_t>(h->max_t, 1);
   const int nl = (int)P.levels.size();
-  auto fwd_level = [&](int li) {
-    sgf::Level& L = P.levels[li];
-    LevelDev& D = h->lev[li];
-    int maxm = 0;
-    for (auto& e : L.elim) maxm = std::max(maxm, e.m);
-    if (!product) {
-      if (!L.elim.empty())
-        hipLaunchKernelGGL(sgf::k_elim_fwd<T>, dim3((unsigned)L.elim.size(), nrhs), dim3(sgf::WG),
-                           maxm * sizeof(T), st, D.elim.as<sgf::ElimDesc>(), D.arena.as<T>(), D.slots.as<int32_t>(),
-                           y, n, ts, ldt, 0);
-      if (!L.sepacc.empty())
-        hipLaunchKernelGGL(sgf::k_sepacc<T>, dim3((unsigned)L.sepacc.size(), nrhs), dim3(sgf::WG), 0, st,
-                           D.sepacc.as<sgf::SepAcc>(), D.sepsrc.as<int64_t>(), D.slots.as<int32_t>(), ts, ldt, y, n,
-                           T(-1));
-      if (!L.capply.empty()) {
-        int ms = 0;
-        for (auto& a : L.capply) ms = std::max(ms, a.s);
-        hipLaunchKernelGGL(sgf::k_comp_apply<T>, dim3((unsigned)L.capply.size(), nrhs), dim3(sgf::WG),
-                           2 * ms * sizeof(T), st, D.capply.as<sgf::CompApply>(), D.cf.as<T>(), D.nbuf.as<T>(),
-                           D.tau.as<T>(), D.slots.as<int32_t>(), y, n, 0);
-      }
-    } else {
-      int maxk = 0;
-      for (auto& e : L.elim) maxk = std::max(maxk, e.k);
-      if (!L.elim.empty())
-        hipLaunchKernelGGL(sgf::k_elim_bwd<T>, dim3((unsigned)L.elim.size(), nrhs), dim3(sgf::WG),
-                           (2 * maxm + maxk) * sizeof(T), st, D.elim.as<sgf::ElimDesc>(), D.arena.as<T>(),
-                           D.slots.as<int32_t>(), D.nslots.as<int32_t>(), y, n, 1);
-      if (!L.capply.empty()) {
-        int ms = 0;
-        for (auto& a : L.capply) ms = std::max(ms, a.s);
-        hipLaunchKernelGGL(sgf::k_comp_apply<T>, dim3((unsigned)L.capply.size(), nrhs), dim3(sgf::WG),
-                           2 * ms * sizeof(T), st, D.capply.as<sgf::CompApply>(), D.cf.as<T>(), D.nbuf.as<T>(),
-                           D.tau.as<T>(), D.slots.as<int32_t>(), y, n, 2);
-      }
-    }
-  };
-  auto bwd_level = [&](int li) {
-    sgf::Level& L = P.levels[li];
-    LevelDev& D = h->lev[li];
-    int maxm = 0, maxk = 0;
+  auto maxes = [](const sgf::Level& L, int& mm, int& mk, int& ms) {
+    mm = mk = ms = 0;
     for (auto& e : L.elim) {
-      maxm = std::max(maxm, e.m);
-      maxk = std::max(maxk, e.k);
+      mm = std::max(mm, e.m);
+      mk = std::max(mk, e.k);
     }
-    if (!L.capply.empty()) {
-      int ms = 0;
-      for (auto& a : L.capply) ms = std::max(ms, a.s);
+    for (auto& a : L.capply) ms = std::max(ms, a.s);
+  };
+  auto elim_fwd = [&](int li, int mode) {
+    sgf::Level& L = P.levels[li];
+    LevelDev& D = h->lev[li];
+    int mm, mk, ms;
+    maxes(L, mm, mk, ms);
+    if (L.elim.empty()) return;
+    launch(h, st, mode ? "mul_elim" : "apply_elim_fwd", 0, D.work.fwd_bytes + nrhs * D.work.fwd_vec, [&] {
+      hipLaunchKernelGGL(sgf::k_elim_fwd<T>, dim3((unsigned)L.elim.size(), nrhs), dim3(sgf::WG), mm * sizeof(T), st,
+                         D.elim.as<sgf::ElimDesc>(), D.arena.as<T>(), D.slots.as<int32_t>(), y, n, ts, ldt, mode);
+    });
+  };
+  auto elim_bwd = [&](int li, int mode) {
+    sgf::Level& L = P.levels[li];
+    LevelDev& D = h->lev[li];
+    int mm, mk, ms;
+    maxes(L, mm, mk, ms);
+    if (L.elim.empty()) return;
+    launch(h, st, mode ? "mul_elim_t" : "apply_elim_bwd", 0, D.work.bwd_bytes + nrhs * D.work.bwd_vec, [&] {
+      hipLaunchKernelGGL(sgf::k_elim_bwd<T>, dim3((unsigned)L.elim.size(), nrhs), dim3(sgf::WG),
+                         (2 * mm + mk) * sizeof(T), st, D.elim.as<sgf::ElimDesc>(), D.arena.as<T>(),
+                         D.slots.as<int32_t>(), D.nslots.as<int32_t>(), y, n, mode);
+    });
+  };
+  auto sepacc = [&](int li, T sign) {
+    sgf::Level& L = P.levels[li];
+    LevelDev& D = h->lev[li];
+    if (L.sepacc.empty()) return;
+    launch(h, st, "apply_sepacc", 0, nrhs * D.work.acc_vec, [&] {
+      hipLaunchKernelGGL(sgf::k_sepacc<T>, dim3((unsigned)L.sepacc.size(), nrhs), dim3(sgf::WG), 0, st,
+                         D.sepacc.as<sgf::SepAcc>(), D.sepsrc.as<int64_t>(), D.slots.as<int32_t>(), ts, ldt, y, n,
+                         sign);
+    });
+  };
+  auto capply = [&](int li, int mode) {
+    sgf::Level& L = P.levels[li];
+    LevelDev& D = h->lev[li];
+    int mm, mk, ms;
+    maxes(L, mm, mk, ms);
+    if (L.capply.empty()) return;
+    launch(h, st, "apply_comp", 0, D.work.capply_bytes + nrhs * D.work.capply_vec, [&] {
       hipLaunchKernelGGL(sgf::k_comp_apply<T>, dim3((unsigned)L.capply.size(), nrhs), dim3(sgf::WG),
                          2 * ms * sizeof(T), st, D.capply.as<sgf::CompApply>(), D.cf.as<T>(), D.nbuf.as<T>(),
-                         D.tau.as<T>(), D.slots.as<int32_t>(), y, n, product ? 3 : 1);
-    }
-    if (!product) {
-      if (!L.elim.empty())
-        hipLaunchKernelGGL(sgf::k_elim_bwd<T>, dim3((unsigned)L.elim.size(), nrhs), dim3(sgf::WG),
-                           (2 * maxm + maxk) * sizeof(T), st, D.elim.as<sgf::ElimDesc>(), D.arena.as<T>(),
-                           D.slots.as<int32_t>(), D.nslots.as<int32_t>(), y, n, 0);
-    } else {
-      if (!L.elim.empty())
-        hipLaunchKernelGGL(sgf::k_elim_fwd<T>, dim3((unsigned)L.elim.size(), nrhs), dim3(sgf::WG),
-                           maxm * sizeof(T), st, D.elim.as<sgf::ElimDesc>(), D.arena.as<T>(), D.slots.as<int32_t>(),
-                           y, n, ts, ldt, 1);
-      if (!L.sepacc.empty())
-        hipLaunchKernelGGL(sgf::k_sepacc<T>, dim3((unsigned)L.sepacc.size(), nrhs), dim3(sgf::WG), 0, st,
-                           D.sepacc.as<sgf::SepAcc>(), D.sepsrc.as<int64_t>(), D.slots.as<int32_t>(), ts, ldt, y, n,
-                           T(1));
-    }
+                         D.tau.as<T>(), D.slots.as<int32_t>(), y, n, mode);
+    });
   };
-  for (int li = 0; li < nl - 1; ++li) fwd_level(li);
+  for (int li = 0; li < nl - 1; ++li) {
+    if (!product) {
+      elim_fwd(li, 0);
+      sepacc(li, T(-1));
+      capply(li, 0);
+    } else {
+      elim_bwd(li, 1);
+      capply(li, 2);
+    }
+  }
   {
     sgf::Level& L = P.levels[nl - 1];
     LevelDev& D = h->lev[nl - 1];
     int m = L.elim[0].m;
     if (m > 0)
-      hipLaunchKernelGGL(sgf::k_top<T>, dim3(1, nrhs), dim3(sgf::WG), 2 * m * sizeof(T), st,
-                         D.elim.as<sgf::ElimDesc>(), D.arena.as<T>(), D.slots.as<int32_t>(), y, n, product ? 1 : 0);
+      launch(h, st, "apply_top", 0, 2 * D.work.top_bytes + nrhs * D.work.top_vec, [&] {
+        hipLaunchKernelGGL(sgf::k_top<T>, dim3(1, nrhs), dim3(sgf::WG), 2 * m * sizeof(T), st,
+                           D.elim.as<sgf::ElimDesc>(), D.arena.as<T>(), D.slots.as<int32_t>(), y, n,
+                           product ? 1 : 0);
+      });
   }
-  for (int li = nl - 2; li >= 0; --li) bwd_level(li);
+  for (int li = nl - 2; li >= 0; --li) {
+    if (!product) {
+      capply(li, 1);
+      elim_bwd(li, 0);
+    } else {
+      capply(li, 3);
+      elim_fwd(li, 1);
+      sepacc(li, T(1));
+    }
+  }
 }
 
 template <typename T>
@@ -493,11 +626,16 @@ void apply_impl(sgf_handle h, int nrhs, const double* r, int64_t ldr, double* z,
   const int64_t n = h->plan.n;
   ensure_work<T>(h, nrhs);
   dim3 g(cdiv(n, sgf::WG), nrhs);
-  hipLaunchKernelGGL((sgf::k_gather_perm<double, T>), g, dim3(sgf::WG), 0, st, h->d_perm.as<int64_t>(), n, r, ldr,
-                     h->y.as<T>(), n);
+  const double vb = (double)n * nrhs * (8.0 + sizeof(T)) + 8.0 * n;
+  launch(h, st, "apply_perm", 0, vb, [&] {
+    hipLaunchKernelGGL((sgf::k_gather_perm<double, T>), g, dim3(sgf::WG), 0, st, h->d_perm.as<int64_t>(), n, r, ldr,
+                       h->y.as<T>(), n);
+  });
   run_sweeps<T>(h, nrhs, product, st);
-  hipLaunchKernelGGL((sgf::k_scatter_perm<T, double>), g, dim3(sgf::WG), 0, st, h->d_perm.as<int64_t>(), n,
-                     h->y.as<T>(), n, z, ldz);
+  launch(h, st, "apply_perm", 0, vb, [&] {
+    hipLaunchKernelGGL((sgf::k_scatter_perm<T, double>), g, dim3(sgf::WG), 0, st, h->d_perm.as<int64_t>(), n,
+                       h->y.as<T>(), n, z, ldz);
+  });
   HIP_CHECK(hipGetLastError());
 }
 
@@ -510,9 +648,13 @@ void apply_any(sgf_handle h, int nrhs, const double* r, int64_t ldr, double* z, 
 void dot_cols(sgf_handle h, const double* a, const double* b, int nrhs, double* out, hipStream_t st) {
   const int64_t n = h->plan.n;
   const int nb = (int)std::min<int64_t>(1024, cdiv(n, sgf::WG));
-  hipLaunchKernelGGL(sgf::k_dot_partial, dim3(nb, nrhs), dim3(sgf::WG), 0, st, a, n, b, n, n,
-                     h->cg_part.as<double>());
-  hipLaunchKernelGGL(sgf::k_reduce, dim3(nrhs), dim3(sgf::WG), 0, st, h->cg_part.as<double>(), nb, out);
+  launch(h, st, "cg_dot", 0, 16.0 * n * nrhs, [&] {
+    hipLaunchKernelGGL(sgf::k_dot_partial, dim3(nb, nrhs), dim3(sgf::WG), 0, st, a, n, b, n, n,
+                       h->cg_part.as<double>());
+  });
+  launch(h, st, "cg_reduce", 0, 8.0 * nb * nrhs, [&] {
+    hipLaunchKernelGGL(sgf::k_reduce, dim3(nrhs), dim3(sgf::WG), 0, st, h->cg_part.as<double>(), nb, out);
+  });
 }
 
 }  // namespace
@@ -712,14 +854,22 @@ sgf_status sgf_pcg_solve(sgf_handle h, int32_t nrhs, const double* b, int64_t ld
       HIP_CHECK(hipMemcpyAsync(stv + 8 * c, sc + c, sizeof(double), hipMemcpyDeviceToDevice, st));
     HIP_CHECK(hipMemcpyAsync(p, z, vb, hipMemcpyDeviceToDevice, st));
     dim3 gv(cdiv(n, sgf::WG), nrhs);
+    const double spmv_bytes = nrhs * (12.0 * h->nnz + 8.0 * (n + 1) + 24.0 * n);
     for (int it = 1; it <= maxit; ++it) {
-      hipLaunchKernelGGL(sgf::k_spmv_dot, dim3(nbspmv, nrhs), dim3(sgf::WG), 0, st, h->d_rowptr.as<int64_t>(),
-                         h->d_colidx.as<int32_t>(), h->d_vals.as<double>(), n, p, n, Ap, n, h->cg_part.as<double>());
-      hipLaunchKernelGGL(sgf::k_reduce, dim3(nrhs), dim3(sgf::WG), 0, st, h->cg_part.as<double>(), nbspmv, sc);
+      launch(h, st, "cg_spmv", 0, spmv_bytes, [&] {
+        hipLaunchKernelGGL(sgf::k_spmv_dot, dim3(nbspmv, nrhs), dim3(sgf::WG), 0, st, h->d_rowptr.as<int64_t>(),
+                           h->d_colidx.as<int32_t>(), h->d_vals.as<double>(), n, p, n, Ap, n,
+                           h->cg_part.as<double>());
+      });
+      launch(h, st, "cg_reduce", 0, 8.0 * nbspmv * nrhs, [&] {
+        hipLaunchKernelGGL(sgf::k_reduce, dim3(nrhs), dim3(sgf::WG), 0, st, h->cg_part.as<double>(), nbspmv, sc);
+      });
       for (int c = 0; c < nrhs; ++c)
         HIP_CHECK(hipMemcpyAsync(stv + 8 * c + 1, sc + c, sizeof(double), hipMemcpyDeviceToDevice, st));
-      hipLaunchKernelGGL(sgf::k_cg_alpha, dim3(1), dim3(256), 0, st, stv, nrhs);
-      hipLaunchKernelGGL(sgf::k_cg_update_xr, gv, dim3(sgf::WG), 0, st, x, ldx, r, n, p, Ap, n, n, stv);
+      launch(h, st, "cg_scalar", 0, 0, [&] { hipLaunchKernelGGL(sgf::k_cg_alpha, dim3(1), dim3(256), 0, st, stv, nrhs); });
+      launch(h, st, "cg_axpy", 0, 48.0 * n * nrhs, [&] {
+        hipLaunchKernelGGL(sgf::k_cg_update_xr, gv, dim3(sgf::WG), 0, st, x, ldx, r, n, p, Ap, n, n, stv);
+      });
       dot_cols(h, r, r, nrhs, sc, st);
       HIP_CHECK(hipMemcpyAsync(rr.data(), sc, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
       HIP_CHECK(hipStreamSynchronize(st));
@@ -747,8 +897,10 @@ sgf_status sgf_pcg_solve(sgf_handle h, int32_t nrhs, const double* b, int64_t ld
       if (nactive == 0) break;
       apply_any(h, nrhs, r, n, z, n, false, st);
       dot_cols(h, r, z, nrhs, sc, st);
-      hipLaunchKernelGGL(sgf::k_cg_beta, dim3(1), dim3(256), 0, st, stv, sc, nrhs);
-      hipLaunchKernelGGL(sgf::k_cg_update_p, gv, dim3(sgf::WG), 0, st, p, z, n, n, stv);
+      launch(h, st, "cg_scalar", 0, 0, [&] { hipLaunchKernelGGL(sgf::k_cg_beta, dim3(1), dim3(256), 0, st, stv, sc, nrhs); });
+      launch(h, st, "cg_axpy", 0, 24.0 * n * nrhs, [&] {
+        hipLaunchKernelGGL(sgf::k_cg_update_p, gv, dim3(sgf::WG), 0, st, p, z, n, n, stv);
+      });
       HIP_CHECK(hipGetLastError());
     }
     HIP_CHECK(hipStreamSynchronize(st));
@@ -821,6 +973,24 @@ sgf_status sgf_plan_dry_run(sgf_handle h, sgf_rank_fn rank_fn, void* ctx) {
       }
       sgf::plan_next_level(P, bm, pm);
     }
+  });
+}
+
+sgf_status sgf_profile_enable(sgf_handle h, int32_t enable) {
+  if (!h) return fail(SGF_EINVAL, "NULL handle");
+  return guard([&] {
+    h->prof.drain();
+    h->prof.stats.clear();
+    h->prof.on = enable != 0;
+  });
+}
+
+sgf_status sgf_profile_read(sgf_handle h, sgf_kernel_stat* out, int32_t cap, int32_t* count) {
+  if (!h || !count) return fail(SGF_EINVAL, "NULL argument");
+  return guard([&] {
+    h->prof.drain();
+    *count = (int32_t)h->prof.stats.size();
+    for (int i = 0; i < std::min<int>(cap, (int)h->prof.stats.size()); ++i) out[i] = h->prof.stats[i];
   });
 }
 

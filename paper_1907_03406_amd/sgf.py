@@ -20,8 +20,8 @@ FP64, FP32 = 0, 1
 
 EXPORTED = ["sgf_default_options", "sgf_analyze", "sgf_factorize_numeric", "sgf_factorize",
             "sgf_apply", "sgf_multiply", "sgf_pcg_solve", "sgf_spmv", "sgf_get_info",
-            "sgf_get_perm", "sgf_get_level", "sgf_plan_dry_run", "sgf_destroy", "sgf_status_str",
-            "sgf_last_error"]
+            "sgf_get_perm", "sgf_get_level", "sgf_plan_dry_run", "sgf_profile_enable", "sgf_profile_read",
+            "sgf_destroy", "sgf_status_str", "sgf_last_error"]
 
 RANK_FN = ctypes.CFUNCTYPE(ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p)
 
@@ -39,6 +39,11 @@ class Info(ctypes.Structure):
                 ("compressed", ctypes.c_int64), ("factor_flops", ctypes.c_double),
                 ("apply_bytes", ctypes.c_double), ("failed_cluster", ctypes.c_int32),
                 ("failed_level", ctypes.c_int32)]
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("ms", ctypes.c_double),
+                ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 
 class SgfError(RuntimeError):
@@ -66,6 +71,8 @@ def load_library(path=LIB_PATH):
         "sgf_get_perm": (I32, [H, P]),
         "sgf_get_level": (I32, [H, I32, P, P, P, P, P]),
         "sgf_plan_dry_run": (I32, [H, RANK_FN, P]),
+        "sgf_profile_enable": (I32, [H, I32]),
+        "sgf_profile_read": (I32, [H, ctypes.POINTER(KernelStat), I32, P]),
         "sgf_destroy": (I32, [H]),
         "sgf_status_str": (ctypes.c_char_p, [I32]),
         "sgf_last_error": (ctypes.c_char_p, []),
@@ -183,6 +190,19 @@ class Solver:
         """Host-only planning of every level with ranks from ``rank_of(level, cell, size)``."""
         cb = RANK_FN(lambda t, cell, size, ctx: int(rank_of(t, cell, size)))
         _check(_lib.sgf_plan_dry_run(self.h, cb, None))
+
+    def profile(self, enable=True):
+        """Start (clear) or stop per-kernel event timing."""
+        _check(_lib.sgf_profile_enable(self.h, 1 if enable else 0))
+
+    def profile_read(self):
+        """{kernel class: dict(launches, ms, flops, bytes)} since profile()."""
+        cap = 64
+        arr = (KernelStat * cap)()
+        cnt = ctypes.c_int32()
+        _check(_lib.sgf_profile_read(self.h, arr, cap, ctypes.byref(cnt)))
+        return {arr[i].name.decode(): dict(launches=arr[i].launches, ms=arr[i].ms, flops=arr[i].flops,
+                                           bytes=arr[i].bytes) for i in range(min(cnt.value, cap))}
 
     def level(self, t):
         cnt = ctypes.c_int32()

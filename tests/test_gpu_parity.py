@@ -190,3 +190,27 @@ def test_not_spd_reports_cluster():
         s.factorize(torch.from_numpy(bad).cuda())
     assert ei.value.code == sgf.SGF_ENOTSPD
     assert s.info()["failed_level"] == 1
+
+
+@pytest.mark.parametrize("kind,grid,leaf,q", [("fourier", (128, 128), 16, 2), ("blocky", (24, 24, 24), 8, 1),
+                                              ("elast", 12, 3, 1)])
+def test_fp32_form_reaches_fp64_accuracy(kind, grid, leaf, q):
+    """Precision form: FP32 factor and apply inside FP64 CG.  CG must still
+    reach a true FP64 relative residual below 2e-8, with a bounded increase
+    of the iteration count; the distance to the FP64 solution is reported."""
+    p = _prob(kind, grid)
+    A = p.csr()
+    b = P.random_rhs(1, p.n)
+    bt = torch.from_numpy(b).cuda()
+    out = {}
+    for prec in (sgf.FP64, sgf.FP32):
+        s = _gpu(p, q=q, leaf=leaf, precision=prec)
+        x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+        it, rel = s.pcg(bt, x, rtol=1e-8)
+        out[prec] = (int(it[0]), x.cpu().numpy())
+    it64, x64 = out[sgf.FP64]
+    it32, x32 = out[sgf.FP32]
+    true32 = np.linalg.norm(b - A @ x32) / np.linalg.norm(b)
+    print(f"fp32 form: it {it32} (fp64 {it64}), true residual {true32:.2e}, |x32-x64|/|x64| {_rel(x32, x64):.2e}")
+    assert true32 < 2e-8
+    assert it32 <= 2 * it64 + 5
