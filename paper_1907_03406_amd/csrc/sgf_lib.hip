@@ -403,7 +403,7 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
     if (!L.elim.empty()) {
       int nb = nb_for(L.max_front_rows, sizeof(T));
       size_t lds = (size_t)nb * L.max_front_rows * sizeof(T);
-      launch(h, st, L.top ? "top_potrf" : "elim", lvl_elim_flops, 0, [&] {
+      launch(h, st, "elim", lvl_elim_flops, 0, [&] {
         hipLaunchKernelGGL(sgf::k_elim<T>, dim3((unsigned)L.elim.size()), dim3(sgf::WG), lds, st,
                            D.elim.as<sgf::ElimDesc>(), arena, nb, h->d_fail.as<int>());
       });
