@@ -62,15 +62,18 @@ def traffic_for(kernel):
     return rec.get("bytes_per_launch")
 
 
-def run_form(prob, cfg, precision, steps, warmup, profile, seed=0, log=None):
+def run_form(probs, cfg, precision, steps, warmup, profile, seed=0, log=None):
+    """Steps alternate between the operators in `probs` (same grid and
+    pattern, different coefficient fields), all resident on the device."""
     import torch
     from paper_1907_03406_amd import sgf
     dev = torch.device("cuda:0")
+    prob = probs[0]
     t0 = time.perf_counter()
     s = sgf.Solver.from_problem(prob, q=cfg["q"], leaf=cfg["leaf"],
                                 precision=sgf.FP32 if precision == "fp32" else sgf.FP64)
     t_an = time.perf_counter() - t0
-    vals = torch.from_numpy(prob.data).to(dev)
+    vals_all = [torch.from_numpy(p.data).to(dev) for p in probs]
     from sgf_inputs.problems import random_rhs
     nrhs = cfg.get("nrhs", 1)
     rhs = [torch.from_numpy(np.ascontiguousarray(
@@ -86,7 +89,7 @@ def run_form(prob, cfg, precision, steps, warmup, profile, seed=0, log=None):
                 s.profile(True)
             t_start = time.perf_counter()
         ts = time.perf_counter()
-        s.factorize(vals)
+        s.factorize(vals_all[j % len(vals_all)])
         tf = time.perf_counter()
         it, rel = s.pcg(rhs[j].T, x.T, rtol=tol, maxit=1000)
         te = time.perf_counter()
@@ -99,18 +102,20 @@ def run_form(prob, cfg, precision, steps, warmup, profile, seed=0, log=None):
                   f"it {it.tolist()}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     total = time.perf_counter() - t_start
-    stats = s.profile_read() if profile else {}
+    raw = s.profile_read() if profile else {}
+    stats = {k: v for k, v in raw.items() if "@" not in k}
+    by_level = {k: v for k, v in raw.items() if "@" in k}
     if profile:
         s.profile(False)
     info = s.info()
     # true residual of the last solve
-    A = prob.csr()
+    A = probs[(warmup + steps - 1) % len(probs)].csr()
     xb = x.cpu().numpy()
     bb = rhs[-1].cpu().numpy()
     true_rel = max(np.linalg.norm(bb[c] - A @ xb[c]) / np.linalg.norm(bb[c]) for c in range(nrhs))
     s.close()
     return dict(total=total, lat=lat, fac=fac, its=its, info=info, stats=stats, analyze_s=t_an,
-                true_rel=true_rel, nrhs=nrhs)
+                true_rel=true_rel, nrhs=nrhs, by_level=by_level)
 
 
 def roofline(stats, precision, steps):
@@ -162,6 +167,8 @@ def main():
     ap.add_argument("--no-fp64-form", action="store_true", help="skip the plain FP64 comparison form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--operators", type=int, default=2,
+                    help="distinct coefficient fields (seeds seed, seed+1, ...) that the steps cycle through")
     ap.add_argument("--verbose", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -174,12 +181,14 @@ def main():
         sys.exit(1)
     from sgf_inputs.problems import config_problem
     t0 = time.perf_counter()
-    prob, cfg = config_problem(a.config, seed=a.seed)
+    probs = [config_problem(a.config, seed=a.seed + i)[0] for i in range(a.operators)]
+    cfg = config_problem.__globals__["CONFIGS"][a.config]
+    prob = probs[0]
     t_gen = time.perf_counter() - t0
-    main_form = run_form(prob, cfg, a.precision, a.steps, a.warmup, profile=True, seed=a.seed, log=a.verbose)
+    main_form = run_form(probs, cfg, a.precision, a.steps, a.warmup, profile=True, seed=a.seed, log=a.verbose)
     other = None
     if not a.no_fp64_form and a.precision != "fp64":
-        other = run_form(prob, cfg, "fp64", max(2, a.steps // 2), 1, profile=True, seed=a.seed, log=a.verbose)
+        other = run_form(probs, cfg, "fp64", max(2, a.steps // 2), 1, profile=True, seed=a.seed, log=a.verbose)
     lat = np.array(main_form["lat"]) * 1e3
     steps = a.steps
     ms = main_form["total"] / steps * 1e3
@@ -210,7 +219,8 @@ def main():
             "workload": f"{a.config}: {WORKLOADS[a.config]}",
             "n": prob.n, "nnz": prob.nnz, "q": cfg["q"], "leaf": cfg["leaf"], "tol": cfg["tol"],
             "factor_apply_dtype": "f32" if a.precision == "fp32" else "f64", "cg_dtype": "f64",
-            "nrhs": main_form["nrhs"], "seed": a.seed,
+            "nrhs": main_form["nrhs"], "seed": a.seed, "operators": a.operators,
+            "step": "numeric factorization of operator (step mod operators) + CG solve of a fresh rhs",
         },
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3), "p99": round(float(np.percentile(lat, 99)), 3)},
         "it_C": main_form["its"],
@@ -226,6 +236,9 @@ def main():
         "analyze_s": round(main_form["analyze_s"], 3), "problem_gen_s": round(t_gen, 2),
         "kernels": {k: {"ms_per_step": round(v["ms"] / steps, 4), "launches_per_step": round(v["launches"] / steps, 1)}
                     for k, v in sorted(st.items(), key=lambda kv: -kv[1]["ms"])},
+        "factor_kernels_by_level_ms_per_step": {k: round(v["ms"] / steps, 4) for k, v in
+                                                 sorted(main_form["by_level"].items(), key=lambda kv: -kv[1]["ms"])
+                                                 if v["ms"] / steps > 0.02},
         "roofline": rl,
     }
     if other is not None:

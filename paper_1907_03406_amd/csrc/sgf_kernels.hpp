@@ -23,6 +23,18 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
+// Value of v in lane `src` (a wave-uniform index) for every lane, through a
+// scalar register (v_readlane).
+__device__ __forceinline__ float lane_bcast(float v, int src) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+__device__ __forceinline__ double lane_bcast(double v, int src) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), src);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+  return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
+
 // Sum over the workgroup; every thread gets the result.  `red` holds WG/WAVE.
 template <typename T>
 __device__ __forceinline__ T block_sum(T v, T* red) {
@@ -35,6 +47,32 @@ __device__ __forceinline__ T block_sum(T v, T* red) {
   for (int i = 0; i < WG / WAVE; ++i) s += red[i];
   return s;
 }
+
+// 16 x 16 x 4 matrix-core step (v_mfma_*_16x16x4).  Operand lane layout,
+// checked on gfx950: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16];
+// the result D[i][j] sits in lane j + 16 (i / 4), register i % 4 (f32) or in
+// lane j + 16 (i % 4), register i / 4 (f64).  `drow` gives, for a lane and a
+// register, the row index i of D that it holds.
+typedef float mfma_v4f __attribute__((ext_vector_type(4)));
+typedef double mfma_v4d __attribute__((ext_vector_type(4)));
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<float> {
+  typedef mfma_v4f V;
+  static __device__ __forceinline__ V op(float a, float b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int drow(int lane, int v) { return 4 * (lane / 16) + v; }
+};
+template <>
+struct Mfma<double> {
+  typedef mfma_v4d V;
+  static __device__ __forceinline__ V op(double a, double b, V c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int drow(int lane, int v) { return lane / 16 + 4 * v; }
+};
 
 // ---------------------------------------------------------------------------
 // Fills and copies
@@ -122,75 +160,142 @@ __global__ void k_phi_init(const int64_t* __restrict__ slot_ptr, const int64_t* 
 
 // Partial Cholesky of the R x R front C (ld): factor the first m columns into
 // [L ; L21] and subtract L21 L21^T from the trailing columns [m, nupd).
-// Right-looking, panels of nbmax columns staged in LDS.  A non-positive pivot
-// sets *fail = code (and continues with pivot 1).
-template <typename T>
-__device__ void wg_potrf(T* __restrict__ C, int64_t ld, int R, int m, int nupd, T* lds,
-                         int nbmax, int* fail, int code) {
-  const int tid = threadIdx.x;
-  for (int jb = 0; jb < m; jb += nbmax) {
-    const int nb = min(nbmax, m - jb);
+// Right-looking over panels of NB columns staged in LDS (ld padded to 4):
+//  - the NB x NB diagonal block is factored by wave 0, one row per lane held
+//    in registers, pivots broadcast with shuffles (no workgroup barrier);
+//  - every row below it is solved against L11 by one thread (L11 read from
+//    LDS as broadcasts; rows are independent);
+//  - the trailing matrix is updated from the LDS panel with 4 x 4 register
+//    tiles.  Three workgroup barriers per panel.
+// A non-positive pivot sets *fail = code and continues with pivot 1.
+template <typename T, int NB, bool DIAG_IN_REGS>
+__device__ void wg_potrf(T* __restrict__ C, int64_t ld, int R, int m, int nupd, T* lds, int* fail, int code) {
+  const int tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
+  T* invd = lds;          // NB reciprocal pivots
+  T* pan = lds + NB;      // panel, column p at pan + p * pl
+  for (int jb = 0; jb < m; jb += NB) {
+    const int nb = min(NB, m - jb);
     const int pr = R - jb;
+    const int pl = (pr + 3) & ~3;
     for (int idx = tid; idx < pr * nb; idx += WG) {
-      int i = idx % pr, p = idx / pr;
-      lds[idx] = C[(jb + i) + (int64_t)(jb + p) * ld];
+      const int i = idx % pr, p = idx / pr;
+      pan[p * pl + i] = C[(jb + i) + (int64_t)(jb + p) * ld];
     }
     __syncthreads();
-    for (int j = 0; j < nb; ++j) {
-      T piv = lds[j * pr + j];
-      bool bad = !(piv > T(0));
-      __syncthreads();
-      if (bad) {
-        if (tid == 0) atomicCAS(fail, -1, code);
-        piv = T(1);
+    if (w == 0 && DIAG_IN_REGS) {
+      // Cholesky of the nb x nb diagonal block: lane i keeps row i in
+      // registers; column j of L is broadcast with shuffles (independent
+      // across k, so they pipeline).
+      T a[NB];
+#pragma unroll
+      for (int k = 0; k < NB; ++k) a[k] = (lane < nb && k < nb && k <= lane) ? pan[k * pl + lane] : T(0);
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        if (j < nb) {
+          T d = lane_bcast(a[j], j);
+          if (!(d > T(0))) {
+            if (lane == 0) atomicCAS(fail, -1, code);
+            d = T(1);
+          }
+          const T sd = sqrt(d), inv = T(1) / sd;
+          const T l = (lane == j) ? sd : a[j] * inv;
+          if (lane >= j) a[j] = l;
+          if (lane == j) invd[j] = inv;
+#pragma unroll
+          for (int k = j + 1; k < NB; ++k) {
+            const T lk = lane_bcast(l, k);
+            if (lane >= k) a[k] -= l * lk;
+          }
+        }
       }
-      const T d = sqrt(piv);
-      const T inv = T(1) / d;
-      for (int i = j + tid; i < pr; i += WG) lds[j * pr + i] = (i == j) ? d : lds[j * pr + i] * inv;
-      __syncthreads();
-      const int ncol = nb - j - 1;
-      for (int idx = tid; idx < ncol * pr; idx += WG) {
-        int l = j + 1 + idx / pr, i = idx % pr;
-        if (i >= l) lds[l * pr + i] -= lds[j * pr + i] * lds[j * pr + l];
+      if (lane < nb) {
+#pragma unroll
+        for (int k = 0; k < NB; ++k)
+          if (k < nb && k <= lane) pan[k * pl + lane] = a[k];
       }
-      __syncthreads();
     }
+    if (w == 0 && !DIAG_IN_REGS) {
+      // Cholesky of the nb x nb diagonal block in LDS, right-looking, lane i
+      // owns row i.  One wavefront: its LDS operations complete in program
+      // order; the wave barriers only keep the compiler from moving them.
+      for (int j = 0; j < nb; ++j) {
+        T d = pan[j * pl + j];
+        if (!(d > T(0))) {
+          if (lane == 0) atomicCAS(fail, -1, code);
+          d = T(1);
+        }
+        const T sd = sqrt(d), inv = T(1) / sd;
+        __builtin_amdgcn_wave_barrier();
+        if (lane == j) {
+          pan[j * pl + j] = sd;
+          invd[j] = inv;
+        } else if (lane > j && lane < nb) {
+          pan[j * pl + lane] *= inv;
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (lane > j && lane < nb) {
+          const T l = pan[j * pl + lane];
+          for (int k = j + 1; k <= lane; ++k) pan[k * pl + lane] -= l * pan[j * pl + k];
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+    __syncthreads();
+    // rows below the diagonal block: row i <- row i * L11^{-T}, one row per thread
+    for (int i = nb + tid; i < pr; i += WG) {
+      for (int j = 0; j < nb; ++j) {
+        T acc = pan[j * pl + i];
+#pragma unroll 4
+        for (int p = 0; p < j; ++p) acc -= pan[p * pl + i] * pan[p * pl + j];
+        pan[j * pl + i] = acc * invd[j];
+      }
+    }
+    __syncthreads();
     for (int idx = tid; idx < pr * nb; idx += WG) {
-      int i = idx % pr, p = idx / pr;
-      if (i >= p) C[(jb + i) + (int64_t)(jb + p) * ld] = lds[idx];
+      const int i = idx % pr, p = idx / pr;
+      if (i >= p) C[(jb + i) + (int64_t)(jb + p) * ld] = pan[p * pl + i];
     }
-    // trailing update with 4 x 4 register tiles
+    // trailing update C[i][l] -= sum_p L[i][p] L[l][p] on the matrix cores:
+    // one 16 x 16 tile per wavefront step, computed as its transpose so that
+    // lane % 16 walks rows (contiguous in the column-major front); the tile of
+    // C is loaded into the accumulator first and -L[l][p] is fed as operand.
     const int r0 = jb + nb;
     if (r0 < nupd) {
-      const int RT = (R - r0 + 3) / 4, CT = (nupd - r0 + 3) / 4;
-      for (int idx = tid; idx < RT * CT; idx += WG) {
-        const int rt = idx % RT, ct = idx / RT;
+      typedef typename Mfma<T>::V V;
+      const int RT = (R - r0 + 15) / 16, CT = (nupd - r0 + 15) / 16;
+      const int li = lane % 16, lk = lane / 16;
+      for (int t = w; t < RT * CT; t += WG / WAVE) {
+        const int rt = t % RT, ct = t / RT;
         if (rt < ct) continue;
-        const int i0 = r0 + 4 * rt, l0 = r0 + 4 * ct;
-        T acc[4][4];
-        for (int a = 0; a < 4; ++a)
-          for (int b = 0; b < 4; ++b) acc[a][b] = 0;
-        for (int p = 0; p < nb; ++p) {
-          const T* col = lds + p * pr - jb;
-          T av[4], bv[4];
-          for (int a = 0; a < 4; ++a) av[a] = (i0 + a < R) ? col[i0 + a] : T(0);
-          for (int b = 0; b < 4; ++b) bv[b] = (l0 + b < nupd) ? col[l0 + b] : T(0);
-          for (int a = 0; a < 4; ++a)
-            for (int b = 0; b < 4; ++b) acc[a][b] += av[a] * bv[b];
+        const int i0 = r0 + 16 * rt, l0 = r0 + 16 * ct;
+        const int row = i0 + li;
+        V acc;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int col = l0 + Mfma<T>::drow(lane, v);
+          acc[v] = (row < R && col < nupd && row >= col) ? C[row + (int64_t)col * ld] : T(0);
         }
-        for (int b = 0; b < 4; ++b) {
-          const int l = l0 + b;
-          if (l >= nupd) break;
-          for (int a = 0; a < 4; ++a) {
-            const int i = i0 + a;
-            if (i < R && i >= l) C[i + (int64_t)l * ld] -= acc[a][b];
-          }
+        const int arow = l0 + li;            // operand A': rows of the output columns
+        const bool aok = arow < nupd, bok = row < R;
+        for (int kb = 0; kb < nb; kb += 4) {
+          const int p = kb + lk;
+          const T a = (aok && p < nb) ? -pan[p * pl + (arow - jb)] : T(0);
+          const T b = (bok && p < nb) ? pan[p * pl + (row - jb)] : T(0);
+          acc = Mfma<T>::op(a, b, acc);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int col = l0 + Mfma<T>::drow(lane, v);
+          if (row < R && col < nupd && row >= col) C[row + (int64_t)col * ld] = acc[v];
         }
       }
     }
     __syncthreads();
   }
 }
+
+// LDS elements wg_potrf<T, NB> needs for a front of R rows.
+__host__ __device__ inline int64_t potrf_lds_elems(int R, int nb) { return nb + (int64_t)nb * ((R + 3) & ~3); }
 
 // X (n x ncols, ldx) <- L^{-1} X with L lower (n x n, ldl).
 template <typename T>
@@ -235,14 +340,13 @@ __device__ void wg_apply_qt(const T* __restrict__ V, int64_t ldv, const T* __res
 // ---------------------------------------------------------------------------
 
 // Eliminate the interiors of a level (Eq. 4.2): one front per workgroup.
-template <typename T>
-__global__ __launch_bounds__(WG) void k_elim(const ElimDesc* __restrict__ D, T* __restrict__ arena,
-                                             int nbmax, int* fail) {
+template <typename T, int NB>
+__global__ __launch_bounds__(WG) void k_elim(const ElimDesc* __restrict__ D, T* __restrict__ arena, int* fail) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* lds = reinterpret_cast<T*>(smem_raw);
   const ElimDesc d = D[blockIdx.x];
   const int R = d.m + d.k;
-  wg_potrf(arena + d.front_off, R, R, d.m, R, lds, nbmax, fail, d.cluster);
+  wg_potrf<T, NB, true>(arena + d.front_off, R, R, d.m, R, lds, fail, d.cluster);
 }
 
 // Subtract the interiors' Schur complements from the separator pair blocks,
@@ -293,12 +397,11 @@ __global__ __launch_bounds__(WG) void k_comp_gather(const CompDesc* __restrict__
 // One compression (Eqs. 3.1-3.4): L_B = chol(M_BB), Mhat^T = M_XB L_B^{-T},
 // N = [L^T Phi_B | Mhat_X Phi_X ...], pivoted Householder QR of N stopped at
 // the numerical rank, Phi_B <- (Q^T L^T Phi_B)[:r].
-template <typename T>
+template <typename T, int PNB>
 __global__ __launch_bounds__(WG) void k_compress(const CompDesc* __restrict__ D, const CompNbr* __restrict__ NB,
                                                  T* __restrict__ cf, T* __restrict__ nbuf, T* __restrict__ phi,
                                                  T* __restrict__ ltphi, T* __restrict__ tau_all,
-                                                 int* __restrict__ rank, int pi, int nbmax, double rank_tol,
-                                                 int* fail) {
+                                                 int* __restrict__ rank, int pi, double rank_tol, int* fail) {
   // Phi of the neighbours is read here and must not change during the launch.
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* lds = reinterpret_cast<T*>(smem_raw);
@@ -309,7 +412,7 @@ __global__ __launch_bounds__(WG) void k_compress(const CompDesc* __restrict__ D,
   const int s = d.s, c = d.c;
   const int64_t ld = s + d.K;
   T* F = cf + d.cf_off;
-  wg_potrf(F, ld, s + d.K, s, s, lds, nbmax, fail, d.cluster);
+  wg_potrf<T, PNB, false>(F, ld, s + d.K, s, s, lds, fail, d.cluster);
   // ---- N (Eq. 4.5) -----------------------------------------------------------
   T* N = nbuf + d.n_off;
   T* PhB = phi + d.phi_off;
@@ -699,6 +802,163 @@ __global__ __launch_bounds__(WG) void k_comp_apply(const CompApply* __restrict__
   }
   __syncthreads();
   for (int i = threadIdx.x; i < s; i += WG) yv[sl[i]] = ys[i];
+}
+
+// ---------------------------------------------------------------------------
+// Bandwidth-oriented apply sweeps (Sec. 4.7).  The factor panel of an
+// interior, [L ; W^T] ((m+k) x m, column major), is read exactly once per
+// sweep with coalesced column accesses; 64 x 64 diagonal triangles are staged
+// in LDS (padded ld, conflict-free for L and L^T access) and solved by one
+// wave, everything below them is a GEMV with all 256 threads.
+// ---------------------------------------------------------------------------
+
+constexpr int DB = 64;
+constexpr int DLD = DB + 1;
+
+// Lower triangle of the diagonal block [jb, jb + nb) of C into D, with the
+// reciprocal of the diagonal stored on the diagonal.
+template <typename T>
+__device__ __forceinline__ void stage_diag(const T* __restrict__ C, int64_t ld, int jb, int nb, T* D) {
+  for (int idx = threadIdx.x; idx < nb * nb; idx += WG) {
+    const int i = idx % nb, j = idx / nb;
+    const T c = i >= j ? C[(jb + i) + (int64_t)(jb + j) * ld] : T(0);
+    D[i + j * DLD] = (i == j) ? T(1) / c : c;
+  }
+}
+
+// Forward sweep of one interior: y_I <- L^{-1} y_I, t <- W^T y_I.
+template <typename T>
+__global__ __launch_bounds__(WG) void k_apply_fwd(const ElimDesc* __restrict__ D, const T* __restrict__ arena,
+                                                  const int32_t* __restrict__ slots, T* __restrict__ y, int64_t ldy,
+                                                  T* __restrict__ tscr, int64_t ldt) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* Dg = reinterpret_cast<T*>(smem_raw);
+  T* v = Dg + DB * DLD;
+  const ElimDesc d = D[blockIdx.x];
+  const int m = d.m, k = d.k, R = m + k;
+  const T* C = arena + d.front_off;
+  T* yv = y + blockIdx.y * ldy;
+  const int32_t* sl = slots + d.slot_off;
+  for (int i = threadIdx.x; i < R; i += WG) v[i] = i < m ? yv[sl[i]] : T(0);
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  for (int jb = 0; jb < m; jb += DB) {
+    const int nb = min(DB, m - jb);
+    stage_diag(C, R, jb, nb, Dg);
+    __syncthreads();
+    if (w == 0) {
+      T x = lane < nb ? v[jb + lane] : T(0);
+      for (int j = 0; j < nb; ++j) {
+        const T xj = __shfl(x, j, WAVE) * Dg[j + j * DLD];
+        if (lane == j) x = xj;
+        else if (lane > j) x -= Dg[lane + j * DLD] * xj;
+      }
+      if (lane < nb) v[jb + lane] = x;
+    }
+    __syncthreads();
+    for (int i = jb + nb + threadIdx.x; i < R; i += WG) {
+      const T* ci = C + i + (int64_t)jb * R;
+      T acc = 0;
+#pragma unroll 8
+      for (int j = 0; j < nb; ++j) acc += ci[(int64_t)j * R] * v[jb + j];
+      v[i] -= acc;
+    }
+    __syncthreads();
+  }
+  T* tv = tscr + blockIdx.y * ldt + d.t_off;
+  for (int a = threadIdx.x; a < k; a += WG) tv[a] = -v[m + a];
+  for (int i = threadIdx.x; i < m; i += WG) yv[sl[i]] = v[i];
+}
+
+// Backward sweep of one interior: y_I <- L^{-T} (y_I - W y_S).
+template <typename T>
+__global__ __launch_bounds__(WG) void k_apply_bwd(const ElimDesc* __restrict__ D, const T* __restrict__ arena,
+                                                  const int32_t* __restrict__ slots,
+                                                  const int32_t* __restrict__ nslots, T* __restrict__ y,
+                                                  int64_t ldy) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* Dg = reinterpret_cast<T*>(smem_raw);
+  T* v = Dg + DB * DLD;
+  const ElimDesc d = D[blockIdx.x];
+  const int m = d.m, k = d.k, R = m + k;
+  const T* C = arena + d.front_off;
+  T* yv = y + blockIdx.y * ldy;
+  const int32_t* sl = slots + d.slot_off;
+  const int32_t* ns = nslots + d.nslot_off;
+  for (int i = threadIdx.x; i < R; i += WG) v[i] = i < m ? yv[sl[i]] : yv[ns[i - m]];
+  __syncthreads();
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  for (int bj = (m + DB - 1) / DB - 1; bj >= 0; --bj) {
+    const int jb = bj * DB, nb = min(DB, m - jb), below = jb + nb;
+    for (int j = w; j < nb; j += WG / WAVE) {
+      const T* cj = C + (int64_t)(jb + j) * R;
+      T acc = 0;
+      for (int i = below + lane; i < R; i += WAVE) acc += cj[i] * v[i];
+      acc = wave_sum(acc);
+      if (lane == 0) v[jb + j] -= acc;
+    }
+    stage_diag(C, R, jb, nb, Dg);
+    __syncthreads();
+    if (w == 0) {
+      T x = lane < nb ? v[jb + lane] : T(0);
+      for (int j = nb - 1; j >= 0; --j) {
+        const T xj = __shfl(x, j, WAVE) * Dg[j + j * DLD];
+        if (lane == j) x = xj;
+        else if (lane < j) x -= Dg[j + lane * DLD] * xj;
+      }
+      if (lane < nb) v[jb + lane] = x;
+    }
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < m; i += WG) yv[sl[i]] = v[i];
+}
+
+// T_B = Q^T L_B^{-1} (s x s) for every compressed separator, so that each
+// apply of B is one dense matrix-vector product (forward) or its transpose.
+template <typename T>
+__global__ __launch_bounds__(WG) void k_comp_explicit(const CompApply* __restrict__ A, const T* __restrict__ cf,
+                                                      const T* __restrict__ nbuf, const T* __restrict__ tau_all,
+                                                      T* __restrict__ tb) {
+  const CompApply a = A[blockIdx.x];
+  const int s = a.s;
+  T* X = tb + a.t_off;
+  for (int idx = threadIdx.x; idx < s * s; idx += WG) X[idx] = (idx % s == idx / s) ? T(1) : T(0);
+  __syncthreads();
+  wg_trsm_lower(cf + a.cf_off, a.ld, s, X, s, s);
+  wg_apply_qt(nbuf + a.v_off, s, tau_all + a.tau_off, s, a.r, X, s, s);
+}
+
+// mode 0: y_B <- T_B y_B; mode 1: y_B <- T_B^T y_B.
+template <typename T>
+__global__ __launch_bounds__(WG) void k_comp_apply_t(const CompApply* __restrict__ A, const T* __restrict__ tb,
+                                                     const int32_t* __restrict__ slots, T* __restrict__ y,
+                                                     int64_t ldy, int mode) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const CompApply a = A[blockIdx.x];
+  const int s = a.s;
+  T* ys = reinterpret_cast<T*>(smem_raw);
+  T* out = ys + s;
+  const T* X = tb + a.t_off;
+  T* yv = y + blockIdx.y * ldy;
+  const int32_t* sl = slots + a.slot_off;
+  for (int i = threadIdx.x; i < s; i += WG) ys[i] = yv[sl[i]];
+  __syncthreads();
+  if (mode == 0) {
+    for (int i = threadIdx.x; i < s; i += WG) {
+      T acc = 0;
+      for (int j = 0; j < s; ++j) acc += X[i + (int64_t)j * s] * ys[j];
+      out[i] = acc;
+    }
+  } else {
+    const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+    for (int j = w; j < s; j += WG / WAVE) {
+      T acc = 0;
+      for (int i = lane; i < s; i += WAVE) acc += X[i + (int64_t)j * s] * ys[i];
+      acc = wave_sum(acc);
+      if (lane == 0) out[j] = acc;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < s; i += WG) yv[sl[i]] = out[i];
 }
 
 // Top node: mode 0: y <- L^{-T} L^{-1} y; mode 1: y <- L L^T y.

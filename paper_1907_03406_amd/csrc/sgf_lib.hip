@@ -3,7 +3,9 @@
 // product form (Sec. 2.1) and preconditioned CG (Sec. 7).
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <memory>
@@ -92,9 +94,10 @@ struct LevelWork {
 struct LevelDev {
   DevBuf arena, scratch, cf, nbuf, ltphi, tau, phi, rank;
   DevBuf elim, pairs, schur, comp, compnbr, sepacc, sepsrc, capply, slots, nslots;
-  DevBuf blkmap, phimap, slotptr, phioff;
+  DevBuf blkmap, phimap, slotptr, phioff, tb;
   std::vector<sgf::CopyDesc> h_blkmap, h_phimap;
   LevelWork work;
+  bool uploaded = false;   // descriptor tables on the device match the plan
 };
 
 struct Profiler {
@@ -106,6 +109,7 @@ struct Profiler {
     double flops, bytes;
   };
   std::vector<Pending> pending;
+  std::vector<Pending> tagged;   // share events with `pending`
   std::vector<hipEvent_t> pool;
   int index(const char* name) {
     for (size_t i = 0; i < stats.size(); ++i)
@@ -126,6 +130,17 @@ struct Profiler {
     return e;
   }
   void drain() {
+    for (auto& p : tagged) {
+      float ms = 0;
+      if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+        auto& k = stats[p.idx];
+        k.launches += 1;
+        k.ms += ms;
+        k.flops += p.flops;
+        k.bytes += p.bytes;
+      }
+    }
+    tagged.clear();
     for (auto& p : pending) {
       float ms = 0;
       if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
@@ -151,6 +166,22 @@ struct Profiler {
 
 constexpr size_t LDS_BYTES = 64 * 1024;
 
+// Opt-in host timeline of the factorization (environment SGF_TRACE=1).
+struct HostTrace {
+  bool on = false;
+  std::chrono::steady_clock::time_point t0;
+  HostTrace() {
+    const char* e = std::getenv("SGF_TRACE");
+    on = e && e[0] == '1';
+  }
+  void start() { t0 = std::chrono::steady_clock::now(); }
+  void mark(const char* what, int level) {
+    if (!on) return;
+    double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    std::fprintf(stderr, "[sgf] %8.3f ms  level %d  %s\n", ms, level, what);
+  }
+};
+
 inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
 }  // namespace
@@ -174,6 +205,7 @@ struct sgf_handle_s {
   double factor_flops = 0, apply_bytes = 0;
   int64_t factor_entries = 0, factor_bytes = 0, compressed = 0;
   Profiler prof;
+  HostTrace trace;
 };
 
 namespace {
@@ -198,8 +230,9 @@ sgf_status guard(F&& f) {
 }
 
 // Runs `f` (one kernel launch); when profiling, brackets it with events.
+// With level >= 1 the launch is also charged to "<name>@L<level>".
 template <typename F>
-void launch(sgf_handle h, hipStream_t st, const char* name, double flops, double bytes, F&& f) {
+void launch(sgf_handle h, hipStream_t st, const char* name, double flops, double bytes, F&& f, int level = 0) {
   if (!h->prof.on) {
     f();
     return;
@@ -211,6 +244,11 @@ void launch(sgf_handle h, hipStream_t st, const char* name, double flops, double
   f();
   HIP_CHECK(hipEventRecord(b, st));
   p.pending.push_back({idx, a, b, flops, bytes});
+  if (level > 0) {
+    char tag[32];
+    std::snprintf(tag, sizeof(tag), "%s@L%d", name, level);
+    p.tagged.push_back({p.index(tag), a, b, flops, bytes});
+  }
   if (p.pending.size() > 4096) p.drain();
 }
 
@@ -232,11 +270,36 @@ void check_options(const sgf_options* o, int64_t n) {
   if (n >= (int64_t)1 << 31) throw SgfError(SGF_EINVAL, "n must be below 2^31");
 }
 
-int nb_for(int rows, size_t esz, int cap = 32) {
-  int nb = (int)(LDS_BYTES / ((size_t)std::max(rows, 1) * esz));
-  nb = std::min(nb, cap);
-  if (nb < 1) throw SgfError(SGF_EINVAL, "front of " + std::to_string(rows) + " rows does not fit the LDS panel");
-  return nb;
+// Panel width for fronts of up to `rows` rows whose first up to `cols`
+// columns are eliminated: the smallest of 4, 8, 16, 32 that covers `cols`
+// (narrow panels keep the register-resident diagonal block small), reduced
+// until the LDS panel fits beside `extra` elements.
+int nb_for(int rows, int cols, size_t esz, int64_t extra = 0) {
+  int want = 4;
+  while (want < 32 && want < cols) want *= 2;
+  for (int nb : {32, 16, 8, 4})
+    if (nb <= want && (size_t)std::max<int64_t>(sgf::potrf_lds_elems(rows, nb), extra) * esz <= LDS_BYTES) return nb;
+  throw SgfError(SGF_EINVAL, "front of " + std::to_string(rows) + " rows does not fit the LDS panel");
+}
+
+template <typename T>
+void launch_elim(int nb, unsigned grid, size_t lds, hipStream_t st, const sgf::ElimDesc* d, T* arena, int* fail) {
+  switch (nb) {
+    case 32: hipLaunchKernelGGL((sgf::k_elim<T, 32>), dim3(grid), dim3(sgf::WG), lds, st, d, arena, fail); break;
+    case 16: hipLaunchKernelGGL((sgf::k_elim<T, 16>), dim3(grid), dim3(sgf::WG), lds, st, d, arena, fail); break;
+    case 8: hipLaunchKernelGGL((sgf::k_elim<T, 8>), dim3(grid), dim3(sgf::WG), lds, st, d, arena, fail); break;
+    default: hipLaunchKernelGGL((sgf::k_elim<T, 4>), dim3(grid), dim3(sgf::WG), lds, st, d, arena, fail); break;
+  }
+}
+
+template <typename T, typename... A>
+void launch_compress(int nb, unsigned grid, size_t lds, hipStream_t st, A... args) {
+  switch (nb) {
+    case 32: hipLaunchKernelGGL((sgf::k_compress<T, 32>), dim3(grid), dim3(sgf::WG), lds, st, args...); break;
+    case 16: hipLaunchKernelGGL((sgf::k_compress<T, 16>), dim3(grid), dim3(sgf::WG), lds, st, args...); break;
+    case 8: hipLaunchKernelGGL((sgf::k_compress<T, 8>), dim3(grid), dim3(sgf::WG), lds, st, args...); break;
+    default: hipLaunchKernelGGL((sgf::k_compress<T, 4>), dim3(grid), dim3(sgf::WG), lds, st, args...); break;
+  }
 }
 
 void ensure_static(sgf_handle h, hipStream_t st) {
@@ -256,6 +319,8 @@ void upload_level(sgf_handle h, int li, hipStream_t st) {
   sgf::Level& L = h->plan.levels[li];
   if ((int)h->lev.size() <= li) h->lev.resize(li + 1);
   LevelDev& D = h->lev[li];
+  if (D.uploaded) return;
+  D.uploaded = true;
   const size_t e = h->esz;
   D.arena.ensure((L.front_elems + L.blk_elems) * e);
   D.scratch.ensure(L.scratch_elems * e);
@@ -318,9 +383,9 @@ void account_level(sgf_handle h, const sgf::Level& L, LevelWork& W) {
     W.comp_flops += 4.0 * s * cc * r - 2.0 * r * r * (s + cc) + 4.0 * r * r * r / 3.0;
   }
   for (const auto& a : L.capply) {
-    double s = a.s, r = a.r;
-    h->factor_entries += (int64_t)(s * (s + 1) / 2 + s * r);
-    W.capply_bytes += (s * (s + 1) / 2 + s * r) * e;
+    double s = a.s;
+    h->factor_entries += (int64_t)(s * s);
+    W.capply_bytes += s * s * e;
     W.capply_vec += 2 * s * e + 4 * s;
   }
   for (const auto& p : L.pairs) {
@@ -339,12 +404,14 @@ void account_level(sgf_handle h, const sgf::Level& L, LevelWork& W) {
 template <typename T>
 void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
   sgf::Plan& P = h->plan;
+  h->trace.start();
   ensure_static(h, st);
-  // the numeric phase re-plans every level above the first (ranks decide them)
-  if (P.levels.size() > 1) P.levels.resize(1);
-  P.parts.resize(1);
-  P.max_node = 0;
-  for (int s : P.levels[0].size) P.max_node = std::max<int64_t>(P.max_node, s);
+  // levels above the first depend on the ranks: a planned level is reused as
+  // long as the ranks below it come out the same as when it was planned
+  if ((int)P.levels.size() > (int)h->lev.size()) {
+    P.levels.resize(1);
+    P.parts.resize(1);
+  }
   h->factored = false;
   h->factor_flops = 0;
   h->apply_bytes = 0;
@@ -386,6 +453,7 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
                            h->d_coords.as<double>(), pin, D.phi.as<T>());
       });
   }
+  h->trace.mark("level-1 inputs queued", 1);
   // ---- level loop (Algorithm 4.1) --------------------------------------------
   for (int li = 0;; ++li) {
     sgf::Level& L = P.levels[li];
@@ -401,13 +469,15 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
     for (const auto& d : L.elim) lvl_elim_flops += (double)d.m * d.m * d.m / 3.0 + (double)d.m * d.m * d.k +
                                                    (double)d.m * d.k * d.k;
     if (!L.elim.empty()) {
-      int nb = nb_for(L.max_front_rows, sizeof(T));
-      size_t lds = (size_t)nb * L.max_front_rows * sizeof(T);
+      int max_m = 0;
+      for (const auto& e : L.elim) max_m = std::max(max_m, e.m);
+      int nb = nb_for(L.max_front_rows, max_m, sizeof(T));
+      size_t lds = (size_t)sgf::potrf_lds_elems(L.max_front_rows, nb) * sizeof(T);
       launch(h, st, "elim", lvl_elim_flops, 0, [&] {
-        hipLaunchKernelGGL(sgf::k_elim<T>, dim3((unsigned)L.elim.size()), dim3(sgf::WG), lds, st,
-                           D.elim.as<sgf::ElimDesc>(), arena, nb, h->d_fail.as<int>());
-      });
+        launch_elim<T>(nb, (unsigned)L.elim.size(), lds, st, D.elim.as<sgf::ElimDesc>(), arena, h->d_fail.as<int>());
+      }, L.t);
     }
+    h->trace.mark("elimination queued", L.t);
     if (L.top) {
       int f = check_fail(h, st);
       HIP_CHECK(hipGetLastError());
@@ -425,42 +495,53 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
       launch(h, st, "schur", 0, sb, [&] {
         hipLaunchKernelGGL(sgf::k_schur<T>, dim3((unsigned)L.pairs.size()), dim3(sgf::WG), 0, st,
                            D.pairs.as<sgf::PairDesc>(), D.schur.as<sgf::SchurDesc>(), arena, blocks);
-      });
+      }, L.t);
     }
     if (!L.comp.empty()) {
       launch(h, st, "comp_gather", 0, 2.0 * L.cf_elems * e, [&] {
         hipLaunchKernelGGL(sgf::k_comp_gather<T>, dim3((unsigned)L.comp.size()), dim3(sgf::WG), 0, st,
                            D.comp.as<sgf::CompDesc>(), D.compnbr.as<sgf::CompNbr>(), blocks, D.cf.as<T>());
-      });
-      int nb = nb_for(L.max_cf_rows, sizeof(T));
-      size_t lds = std::max<size_t>((size_t)nb * L.max_cf_rows, (size_t)L.max_c) * sizeof(T);
-      if (lds > LDS_BYTES) throw SgfError(SGF_EINVAL, "compression too wide for LDS");
+      }, L.t);
+      int nb = nb_for(L.max_cf_rows, L.max_s, sizeof(T), L.max_c);
+      size_t lds = std::max<size_t>(sgf::potrf_lds_elems(L.max_cf_rows, nb), (size_t)L.max_c) * sizeof(T);
       double tol = P.opt.rank_tol;
       launch(h, st, "compress", 0, 0, [&] {
-        hipLaunchKernelGGL(sgf::k_compress<T>, dim3((unsigned)L.comp.size()), dim3(sgf::WG), lds, st,
-                           D.comp.as<sgf::CompDesc>(), D.compnbr.as<sgf::CompNbr>(), D.cf.as<T>(), D.nbuf.as<T>(),
-                           D.phi.as<T>(), D.ltphi.as<T>(), D.tau.as<T>(), D.rank.as<int>(), P.pi, nb, tol,
-                           h->d_fail.as<int>());
-      });
+        launch_compress<T>(nb, (unsigned)L.comp.size(), lds, st, D.comp.as<sgf::CompDesc>(),
+                           D.compnbr.as<sgf::CompNbr>(), D.cf.as<T>(), D.nbuf.as<T>(), D.phi.as<T>(), D.ltphi.as<T>(),
+                           D.tau.as<T>(), D.rank.as<int>(), P.pi, tol, h->d_fail.as<int>());
+      }, L.t);
       launch(h, st, "phi_commit", 0, 0, [&] {
         hipLaunchKernelGGL(sgf::k_phi_commit<T>, dim3((unsigned)L.comp.size()), dim3(sgf::WG), 0, st,
                            D.comp.as<sgf::CompDesc>(), D.rank.as<int>(), D.ltphi.as<T>(), D.phi.as<T>(), P.pi);
-      });
+      }, L.t);
       launch(h, st, "pair", 0, 0, [&] {
         hipLaunchKernelGGL(sgf::k_pair<T>, dim3((unsigned)L.pairs.size()), dim3(sgf::WG), 0, st,
                            D.pairs.as<sgf::PairDesc>(), D.comp.as<sgf::CompDesc>(), D.rank.as<int>(), D.cf.as<T>(),
                            D.nbuf.as<T>(), D.tau.as<T>(), blocks, D.scratch.as<T>());
-      });
+      }, L.t);
     }
     HIP_CHECK(hipGetLastError());
     L.rank.assign(L.comp.size(), 0);
     if (!L.comp.empty())
       HIP_CHECK(hipMemcpyAsync(L.rank.data(), D.rank.p, L.comp.size() * sizeof(int), hipMemcpyDeviceToHost, st));
+    const bool reuse_next = (int)P.levels.size() > li + 1 && (int)h->lev.size() > li + 1 &&
+                            h->lev[li + 1].uploaded;
     int f = check_fail(h, st);
     if (f >= 0) {
       h->failed_cluster = f;
       h->failed_level = L.t;
       throw SgfError(SGF_ENOTSPD, "non-positive pivot at level " + std::to_string(L.t));
+    }
+    h->trace.mark("synchronized (ranks read)", L.t);
+    const bool same_ranks = reuse_next && L.rank == L.planned_rank;
+    if (h->trace.on) {
+      int ndiff = -1;
+      if (L.rank.size() == L.planned_rank.size()) {
+        ndiff = 0;
+        for (size_t c = 0; c < L.rank.size(); ++c) ndiff += L.rank[c] != L.planned_rank[c];
+      }
+      std::fprintf(stderr, "[sgf] level %d: reuse_next %d, ranks %zu, planned %zu, differing %d\n", L.t,
+                   (int)reuse_next, L.rank.size(), L.planned_rank.size(), ndiff);
     }
     // compressed separators of this level, for the apply
     L.capply.clear();
@@ -480,13 +561,38 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
         ++h->compressed;
       }
     }
-    upload(D.capply, L.capply, st);
+    {
+      int64_t toff = 0;
+      for (auto& a : L.capply) {
+        a.t_off = toff;
+        toff += (int64_t)a.s * a.s;
+      }
+      D.tb.ensure(std::max<int64_t>(toff, 1) * sizeof(T));
+    }
+    if (!same_ranks) upload(D.capply, L.capply, st);
+    if (!L.capply.empty()) {
+      double fl = 0;
+      for (auto& a : L.capply) fl += (double)a.s * a.s * a.s / 3.0 + 4.0 * a.s * a.s * a.r;
+      launch(h, st, "comp_explicit", fl, 0, [&] {
+        hipLaunchKernelGGL(sgf::k_comp_explicit<T>, dim3((unsigned)L.capply.size()), dim3(sgf::WG), 0, st,
+                           D.capply.as<sgf::CompApply>(), D.cf.as<T>(), D.nbuf.as<T>(), D.tau.as<T>(), D.tb.as<T>());
+      }, L.t);
+    }
     account_level(h, L, D.work);
     // ---- coarsen (Secs. 4.3-4.4) ----------------------------------------------
-    sgf::plan_next_level(P, D.h_blkmap, D.h_phimap);
-    upload(D.blkmap, D.h_blkmap, st);
-    upload(D.phimap, D.h_phimap, st);
+    if (!same_ranks) {
+      P.levels.resize(li + 1);
+      P.parts.resize(li + 1);
+      for (size_t q = li + 1; q < h->lev.size(); ++q) h->lev[q].uploaded = false;
+      P.max_node = 0;
+      for (int q = 0; q <= li; ++q)
+        for (int sz : P.levels[q].size) P.max_node = std::max<int64_t>(P.max_node, sz);
+      sgf::plan_next_level(P, D.h_blkmap, D.h_phimap);
+      upload(D.blkmap, D.h_blkmap, st);
+      upload(D.phimap, D.h_phimap, st);
+    }
     upload_level(h, li + 1, st);
+    h->trace.mark(same_ranks ? "next level reused" : "next level planned", li + 1);
     sgf::Level& N = P.levels[li + 1];
     LevelDev& E = h->lev[li + 1];
     LevelDev& Dc = h->lev[li];   // re-fetch: lev may have grown
@@ -498,20 +604,22 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
       launch(h, st, "coarsen_copy", 0, cb, [&] {
         hipLaunchKernelGGL(sgf::k_copy_blocks<T>, dim3((unsigned)Dc.h_blkmap.size()), dim3(sgf::WG), 0, st,
                            Dc.blkmap.as<sgf::CopyDesc>(), Dc.arena.as<T>(), E.arena.as<T>());
-      });
+      }, li + 1);
     }
     if (!Dc.h_phimap.empty())
       launch(h, st, "coarsen_phi", 0, 0, [&] {
         hipLaunchKernelGGL(sgf::k_copy_blocks<T>, dim3((unsigned)Dc.h_phimap.size()), dim3(sgf::WG), 0, st,
                            Dc.phimap.as<sgf::CopyDesc>(), Dc.phi.as<T>(), E.phi.as<T>());
-      });
+      }, li + 1);
     HIP_CHECK(hipGetLastError());
+    h->trace.mark("coarsening queued", li + 1);
   }
+  h->trace.mark("done", (int)P.levels.size());
   // device bytes held by the factor
   h->factor_bytes = 0;
   for (size_t li = 0; li < P.levels.size(); ++li) {
     const auto& D = h->lev[li];
-    h->factor_bytes += D.arena.bytes + D.cf.bytes + D.nbuf.bytes + D.tau.bytes;
+    h->factor_bytes += D.arena.bytes + D.cf.bytes + D.nbuf.bytes + D.tau.bytes + D.tb.bytes;
   }
   const auto& top = P.levels.back().elim[0];
   h->max_m_all = std::max(h->max_m_all, top.m);
@@ -548,7 +656,15 @@ void run_sweeps(sgf_handle h, int nrhs, bool product, hipStream_t st) {
     int mm, mk, ms;
     maxes(L, mm, mk, ms);
     if (L.elim.empty()) return;
-    launch(h, st, mode ? "mul_elim" : "apply_elim_fwd", 0, D.work.fwd_bytes + nrhs * D.work.fwd_vec, [&] {
+    if (mode == 0) {
+      const size_t lds = ((size_t)sgf::DB * sgf::DLD + L.max_front_rows) * sizeof(T);
+      launch(h, st, "apply_elim_fwd", 0, D.work.fwd_bytes + nrhs * D.work.fwd_vec, [&] {
+        hipLaunchKernelGGL(sgf::k_apply_fwd<T>, dim3((unsigned)L.elim.size(), nrhs), dim3(sgf::WG), lds, st,
+                           D.elim.as<sgf::ElimDesc>(), D.arena.as<T>(), D.slots.as<int32_t>(), y, n, ts, ldt);
+      });
+      return;
+    }
+    launch(h, st, "mul_elim", 0, D.work.fwd_bytes + nrhs * D.work.fwd_vec, [&] {
       hipLaunchKernelGGL(sgf::k_elim_fwd<T>, dim3((unsigned)L.elim.size(), nrhs), dim3(sgf::WG), mm * sizeof(T), st,
                          D.elim.as<sgf::ElimDesc>(), D.arena.as<T>(), D.slots.as<int32_t>(), y, n, ts, ldt, mode);
     });
@@ -559,7 +675,16 @@ void run_sweeps(sgf_handle h, int nrhs, bool product, hipStream_t st) {
     int mm, mk, ms;
     maxes(L, mm, mk, ms);
     if (L.elim.empty()) return;
-    launch(h, st, mode ? "mul_elim_t" : "apply_elim_bwd", 0, D.work.bwd_bytes + nrhs * D.work.bwd_vec, [&] {
+    if (mode == 0) {
+      const size_t lds = ((size_t)sgf::DB * sgf::DLD + L.max_front_rows) * sizeof(T);
+      launch(h, st, "apply_elim_bwd", 0, D.work.bwd_bytes + nrhs * D.work.bwd_vec, [&] {
+        hipLaunchKernelGGL(sgf::k_apply_bwd<T>, dim3((unsigned)L.elim.size(), nrhs), dim3(sgf::WG), lds, st,
+                           D.elim.as<sgf::ElimDesc>(), D.arena.as<T>(), D.slots.as<int32_t>(),
+                           D.nslots.as<int32_t>(), y, n);
+      });
+      return;
+    }
+    launch(h, st, "mul_elim_t", 0, D.work.bwd_bytes + nrhs * D.work.bwd_vec, [&] {
       hipLaunchKernelGGL(sgf::k_elim_bwd<T>, dim3((unsigned)L.elim.size(), nrhs), dim3(sgf::WG),
                          (2 * mm + mk) * sizeof(T), st, D.elim.as<sgf::ElimDesc>(), D.arena.as<T>(),
                          D.slots.as<int32_t>(), D.nslots.as<int32_t>(), y, n, mode);
@@ -581,7 +706,15 @@ void run_sweeps(sgf_handle h, int nrhs, bool product, hipStream_t st) {
     int mm, mk, ms;
     maxes(L, mm, mk, ms);
     if (L.capply.empty()) return;
-    launch(h, st, "apply_comp", 0, D.work.capply_bytes + nrhs * D.work.capply_vec, [&] {
+    if (mode <= 1) {
+      launch(h, st, "apply_comp", 0, D.work.capply_bytes + nrhs * D.work.capply_vec, [&] {
+        hipLaunchKernelGGL(sgf::k_comp_apply_t<T>, dim3((unsigned)L.capply.size(), nrhs), dim3(sgf::WG),
+                           2 * ms * sizeof(T), st, D.capply.as<sgf::CompApply>(), D.tb.as<T>(),
+                           D.slots.as<int32_t>(), y, n, mode);
+      });
+      return;
+    }
+    launch(h, st, "mul_comp", 0, 0, [&] {
       hipLaunchKernelGGL(sgf::k_comp_apply<T>, dim3((unsigned)L.capply.size(), nrhs), dim3(sgf::WG),
                          2 * ms * sizeof(T), st, D.capply.as<sgf::CompApply>(), D.cf.as<T>(), D.nbuf.as<T>(),
                          D.tau.as<T>(), D.slots.as<int32_t>(), y, n, mode);
@@ -960,6 +1093,7 @@ sgf_status sgf_plan_dry_run(sgf_handle h, sgf_rank_fn rank_fn, void* ctx) {
     sgf::Plan& P = h->plan;
     P.levels.resize(1);
     P.parts.resize(1);
+    for (size_t q = 1; q < h->lev.size(); ++q) h->lev[q].uploaded = false;
     P.max_node = 0;
     for (int s : P.levels[0].size) P.max_node = std::max<int64_t>(P.max_node, s);
     std::vector<sgf::CopyDesc> bm, pm;

@@ -169,6 +169,7 @@ struct CompApply {
   int64_t v_off;
   int64_t tau_off;
   int64_t slot_off;
+  int64_t t_off;        // explicit T_B = Q^T L_B^{-1} (s x s, column major)
   int32_t s, ld, r, pad;
 };
 
@@ -220,6 +221,7 @@ struct Level {
   std::vector<int64_t> sepacc_src;         // t_off + offset of S in the interior's k part
   // results of the numeric phase
   std::vector<int32_t> rank;               // per compression
+  std::vector<int32_t> planned_rank;       // ranks the next level was planned with
   std::vector<CompApply> capply;
   int64_t n_active = 0;
 
@@ -664,6 +666,7 @@ inline void plan_level1(Plan& P, const int64_t* row_ptr, const int32_t* col_idx)
 inline void plan_next_level(Plan& P, std::vector<CopyDesc>& blk_map, std::vector<CopyDesc>& phi_map) {
   const Options& o = P.opt;
   Level& C = P.levels.back();
+  C.planned_rank = C.rank;
   const Partition& lo = P.parts.back();
   Partition hi = make_partition(o, lo.d * 2);
   // surviving clusters: the separators, with their post-compression sizes

@@ -5,8 +5,9 @@ several clusters per level, ragged last blocks, 2D / 3D, q = 0, 1, 2, and
 elasticity.  Bars: structure (cells, sizes, ranks per level) bit-exact;
 A_l^{-1} v and A_l v within max(1e-10, 100 x the oracle's own rounding
 sensitivity) relative of the oracle (the sensitivity is measured by running
-the oracle with the compressions of each level in reverse order: kept QR
-directions close to the rank threshold are only determined to eps / sigma);
+the oracle with the compressions of each level in reverse order and on A
+perturbed by one ulp), or, where the rank cut has no spectral gap, within
+10 eps / |R_rr| (kept QR directions are determined only to eps / sigma);
 exact mode within 1e-12 of a dense solve; A_l Pi = A Pi within 1e-10; CG
 solutions within 1e-8 relative and iteration counts within +-1.
 """
@@ -98,15 +99,30 @@ def test_factor_structure_and_operators_match_oracle(kind, grid, leaf, q):
         assert [post[c] for c in g["cell"][seps]] == g["rank"][seps].tolist(), f"ranks differ at level {t}"
     assert sum(1 for x in F.info["gap"] if x[3] < x[2]) == info["compressed"]
     V = np.stack([P.random_rhs(7, p.n, j) for j in range(3)], axis=1)
-    # The operator is only defined up to the rounding sensitivity of the
-    # rank-truncated QR: measure it with the oracle itself (same steps, the
-    # compressions of each level taken in reverse order) and allow 100x that.
-    Fd = O.factorize(p.csr(), p.coords, p.grid, p.dpn, O.Options(q=q, leaf=leaf, order="descending"))
     za, zm = O.apply_inverse(F, V), O.multiply(F, V)
-    sens_a = _rel(O.apply_inverse(Fd, V), za)
-    sens_m = _rel(O.multiply(Fd, V), zm)
-    assert _rel(_apply(s, V), za) <= max(1e-10, 100 * sens_a)
-    assert _rel(_apply(s, V, product=True), zm) <= max(1e-10, 100 * sens_m)
+    # The operator is defined only as well as the rank-truncated QRs define
+    # their kept subspaces.  (1) The oracle's own rounding sensitivity: the
+    # same steps with the compressions of each level in reverse order, and
+    # with A perturbed by one ulp.  (2) Where the cut at the rank threshold
+    # has no spectral gap (kept/dropped pivot ratio < 10), the kept subspace
+    # is only determined to about eps / |R_rr| (perturbation bound for
+    # invariant subspaces), and that bounds the comparison instead.
+    Fd = O.factorize(p.csr(), p.coords, p.grid, p.dpn, O.Options(q=q, leaf=leaf, order="descending"))
+    Ap = p.csr().copy()
+    Ap.data = Ap.data * (1 + 2e-16 * np.random.default_rng(0).standard_normal(Ap.nnz))
+    Ap = ((Ap + Ap.T) * 0.5).tocsr()
+    Fp = O.factorize(Ap, p.coords, p.grid, p.dpn, O.Options(q=q, leaf=leaf))
+    sens_a = max(_rel(O.apply_inverse(Fd, V), za), _rel(O.apply_inverse(Fp, V), za))
+    sens_m = max(_rel(O.multiply(Fd, V), zm), _rel(O.multiply(Fp, V), zm))
+    kept = min(x[4] for x in F.info["gap"] if x[3] > 0)
+    dropped = max(x[5] for x in F.info["gap"])
+    gapless = kept < 10 * dropped
+    sub = 10 * np.finfo(float).eps / kept if gapless else 0.0
+    ea, em = _rel(_apply(s, V), za), _rel(_apply(s, V, product=True), zm)
+    print(f"{kind} {grid}: apply {ea:.1e} (oracle sens {sens_a:.1e}), product {em:.1e} (sens {sens_m:.1e}), "
+          f"kept>={kept:.1e} dropped<={dropped:.1e}{' gapless' if gapless else ''}")
+    assert ea <= max(1e-10, 100 * sens_a, sub)
+    assert em <= max(1e-10, 100 * sens_m, sub)
 
 
 @pytest.mark.parametrize("kind,grid,leaf,q", PAR[:5])
