@@ -394,10 +394,103 @@ __global__ __launch_bounds__(WG) void k_comp_gather(const CompDesc* __restrict__
   }
 }
 
+// Householder QR with column pivoting of the s x c matrix N (ld s), stopped
+// at the numerical rank (Eq. 3.3; convention shared with the oracle: pivot =
+// largest recomputed trailing column norm, near-ties within a relative 1e-10
+// to the lowest index; beta = -sign(alpha) ||x||, no reflection for a zero
+// tail).  One thread per column for norms and updates, wave 0 forms each
+// reflector.  Leaves the reflectors below the diagonal of the first r
+// columns, tau[0..r), and returns r.  `nrm` holds c entries of scratch.
+template <typename T>
+__device__ int wg_qrcp(T* N, int s, int c, T* nrm, T* tau, double rank_tol, int* sh_int, T* sh_val) {
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  for (int j = threadIdx.x; j < c; j += WG) {
+    const T* col = N + (int64_t)j * s;
+    T acc = 0;
+    for (int i = 0; i < s; ++i) acc += col[i] * col[i];
+    nrm[j] = sqrt(acc);
+  }
+  int r = 0;
+  const int kmax = min(s, c);
+  for (int k = 0; k < kmax; ++k) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      T nmax = 0;
+      for (int j = k; j < c; ++j) nmax = nrm[j] > nmax ? nrm[j] : nmax;
+      if (k == 0) sh_val[1] = nmax;
+      int stop = (nmax == T(0)) || (nmax <= (T)rank_tol * sh_val[1]);
+      int piv = k;
+      if (!stop) {
+        const T thr = nmax * (T)(1.0 - TIE_RTOL);
+        for (int j = k; j < c; ++j)
+          if (nrm[j] >= thr) {
+            piv = j;
+            break;
+          }
+        nrm[piv] = nrm[k];
+      }
+      sh_int[0] = piv;
+      sh_int[1] = stop;
+    }
+    __syncthreads();
+    if (sh_int[1]) break;
+    const int piv = sh_int[0];
+    if (piv != k)
+      for (int i = threadIdx.x; i < s; i += WG) {
+        const T a = N[i + (int64_t)k * s];
+        N[i + (int64_t)k * s] = N[i + (int64_t)piv * s];
+        N[i + (int64_t)piv * s] = a;
+      }
+    __syncthreads();
+    if (w == 0) {
+      T* x = N + (int64_t)k * s;
+      T part = 0;
+      for (int i = k + 1 + lane; i < s; i += WAVE) part += x[i] * x[i];
+      const T tail = wave_sum(part);
+      const T alpha = x[k];
+      T beta = alpha, tk = 0, scale = 0;
+      if (tail != T(0)) {
+        const T nv = sqrt(alpha * alpha + tail);
+        beta = alpha >= T(0) ? -nv : nv;
+        tk = (beta - alpha) / beta;
+        scale = T(1) / (alpha - beta);
+      }
+      if (tk != T(0))
+        for (int i = k + 1 + lane; i < s; i += WAVE) x[i] *= scale;
+      if (lane == 0) {
+        tau[k] = tk;
+        sh_val[0] = beta;
+      }
+    }
+    __syncthreads();
+    const T tk = tau[k];
+    const T* v = N + (int64_t)k * s;
+    for (int j = k + 1 + threadIdx.x; j < c; j += WG) {
+      T* y = N + (int64_t)j * s;
+      if (tk != T(0)) {
+        T acc = y[k];
+        for (int i = k + 1; i < s; ++i) acc += v[i] * y[i];
+        acc *= tk;
+        y[k] -= acc;
+        for (int i = k + 1; i < s; ++i) y[i] -= acc * v[i];
+      }
+      T nn = 0;
+      for (int i = k + 1; i < s; ++i) nn += y[i] * y[i];
+      nrm[j] = sqrt(nn);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) N[k + (int64_t)k * s] = sh_val[0];
+    ++r;
+  }
+  __syncthreads();
+  return r;
+}
+
 // One compression (Eqs. 3.1-3.4): L_B = chol(M_BB), Mhat^T = M_XB L_B^{-T},
 // N = [L^T Phi_B | Mhat_X Phi_X ...], pivoted Householder QR of N stopped at
-// the numerical rank, Phi_B <- (Q^T L^T Phi_B)[:r].
-template <typename T, int PNB>
+// the numerical rank, and (Q^T L^T Phi_B)[:r] into the Phi scratch.  N is
+// kept in LDS when it fits (NLDS), else in its global buffer.
+template <typename T, int PNB, bool NLDS>
 __global__ __launch_bounds__(WG) void k_compress(const CompDesc* __restrict__ D, const CompNbr* __restrict__ NB,
                                                  T* __restrict__ cf, T* __restrict__ nbuf, T* __restrict__ phi,
                                                  T* __restrict__ ltphi, T* __restrict__ tau_all,
@@ -405,20 +498,21 @@ __global__ __launch_bounds__(WG) void k_compress(const CompDesc* __restrict__ D,
   // Phi of the neighbours is read here and must not change during the launch.
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* lds = reinterpret_cast<T*>(smem_raw);
-  __shared__ T red[WG / WAVE];
-  __shared__ int s_piv, s_stop;
-  __shared__ T s_r00;
+  __shared__ int sh_int[2];
+  __shared__ T sh_val[2];
   const CompDesc d = D[blockIdx.x];
   const int s = d.s, c = d.c;
   const int64_t ld = s + d.K;
   T* F = cf + d.cf_off;
   wg_potrf<T, PNB, false>(F, ld, s + d.K, s, s, lds, fail, d.cluster);
-  // ---- N (Eq. 4.5) -----------------------------------------------------------
-  T* N = nbuf + d.n_off;
-  T* PhB = phi + d.phi_off;
+  T* Ng = nbuf + d.n_off;
+  T* nrm = lds;
+  T* N = NLDS ? lds + ((c + 3) & ~3) : Ng;
+  const T* PhB = phi + d.phi_off;
   T* LtP = ltphi + d.ltphi_off;
+  // ---- N (Eq. 4.5) -----------------------------------------------------------
   for (int idx = threadIdx.x; idx < s * pi; idx += WG) {
-    int i = idx % s, p = idx / s;
+    const int i = idx % s, p = idx / s;
     T acc = 0;
     for (int j = i; j < s; ++j) acc += F[j + (int64_t)i * ld] * PhB[j + (int64_t)p * s];
     N[i + (int64_t)p * s] = acc;
@@ -428,7 +522,7 @@ __global__ __launch_bounds__(WG) void k_compress(const CompDesc* __restrict__ D,
     const CompNbr x = NB[d.nb_ptr + q];
     const T* PhX = phi + x.phi_off;
     for (int idx = threadIdx.x; idx < s * pi; idx += WG) {
-      int i = idx % s, p = idx / s;
+      const int i = idx % s, p = idx / s;
       T acc = 0;
       for (int j = 0; j < x.s_x; ++j) acc += F[(x.row + j) + (int64_t)i * ld] * PhX[j + (int64_t)p * x.s_x];
       N[i + (int64_t)(pi * (1 + q) + p) * s] = acc;
@@ -436,81 +530,10 @@ __global__ __launch_bounds__(WG) void k_compress(const CompDesc* __restrict__ D,
   }
   __syncthreads();
   // ---- pivoted Householder QR of N (Eq. 3.3) ---------------------------------
-  T* norms = lds;  // c entries (the potrf panel is no longer needed)
   T* tau = tau_all + d.tau_off;
-  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
-  int r = 0;
-  const int kmax = min(s, c);
-  for (int k = 0; k < kmax; ++k) {
-    for (int j = k + w; j < c; j += WG / WAVE) {
-      const T* col = N + (int64_t)j * s;
-      T acc = 0;
-      for (int i = k + lane; i < s; i += WAVE) acc += col[i] * col[i];
-      acc = wave_sum(acc);
-      if (lane == 0) norms[j] = sqrt(acc);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      T nmax = 0;
-      for (int j = k; j < c; ++j) nmax = norms[j] > nmax ? norms[j] : nmax;
-      if (k == 0) s_r00 = nmax;
-      int stop = (nmax == T(0)) || (nmax <= (T)rank_tol * s_r00);
-      int piv = k;
-      if (!stop) {
-        const T thr = nmax * (T)(1.0 - TIE_RTOL);
-        for (int j = k; j < c; ++j)
-          if (norms[j] >= thr) { piv = j; break; }
-      }
-      s_piv = piv;
-      s_stop = stop;
-    }
-    __syncthreads();
-    if (s_stop) break;
-    const int piv = s_piv;
-    if (piv != k)
-      for (int i = threadIdx.x; i < s; i += WG) {
-        T a = N[i + (int64_t)k * s], b = N[i + (int64_t)piv * s];
-        N[i + (int64_t)k * s] = b;
-        N[i + (int64_t)piv * s] = a;
-      }
-    __syncthreads();
-    // reflector of column k, rows k..s-1
-    T* x = N + (int64_t)k * s;
-    T part = 0;
-    for (int i = k + 1 + threadIdx.x; i < s; i += WG) part += x[i] * x[i];
-    const T tail = block_sum(part, red);
-    const T alpha = x[k];
-    T beta, tk, scale;
-    if (tail == T(0)) {
-      beta = alpha;
-      tk = 0;
-      scale = 0;
-    } else {
-      const T nrm = sqrt(alpha * alpha + tail);
-      beta = alpha >= T(0) ? -nrm : nrm;
-      tk = (beta - alpha) / beta;
-      scale = T(1) / (alpha - beta);
-    }
-    __syncthreads();
-    if (tk != T(0))
-      for (int i = k + 1 + threadIdx.x; i < s; i += WG) x[i] *= scale;
-    __syncthreads();
-    if (tk != T(0))
-      for (int j = k + 1 + w; j < c; j += WG / WAVE) {
-        T* y = N + (int64_t)j * s;
-        T acc = 0;
-        for (int i = k + lane; i < s; i += WAVE) acc += (i == k ? T(1) : x[i]) * y[i];
-        acc = wave_sum(acc) * tk;
-        for (int i = k + lane; i < s; i += WAVE) y[i] -= acc * (i == k ? T(1) : x[i]);
-      }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      x[k] = beta;
-      tau[k] = tk;
-    }
-    __syncthreads();
-    ++r;
-  }
+  const int r = wg_qrcp(N, s, c, nrm, tau, rank_tol, sh_int, sh_val);
+  if (NLDS)
+    for (int idx = threadIdx.x; idx < s * r; idx += WG) Ng[idx] = N[idx];
   // ---- (Q^T L^T Phi_B)[:r] (Eq. 3.4) into the scratch; neighbours may still be
   // reading Phi_B, so k_phi_commit installs it after every compression ended.
   if (r < s) wg_apply_qt(N, s, tau, s, r, LtP, s, pi);
@@ -530,15 +553,17 @@ __global__ __launch_bounds__(WG) void k_phi_commit(const CompDesc* __restrict__ 
   }
 }
 
-// Coarse couplings C_ab = T_a M_ab T_b^T with T = Q_1^T L^{-1} for compressed
-// separators and T = I otherwise; the diagonal of a compressed separator
-// becomes I_r (Sec. 3.2: the scaled, rotated block; fine rows dropped).
+// Coarse couplings C_ab = T_a M_ab T_b^T (the first r rows of T = Q^T L^{-1}
+// for a compressed separator, T = I otherwise); the diagonal block of a
+// compressed separator becomes I_r (Sec. 3.2: scaled and rotated, fine rows
+// dropped).  Two small products through the pair's scratch; launched only
+// for pairs that touch a compressed separator.
 template <typename T>
-__global__ __launch_bounds__(WG) void k_pair(const PairDesc* __restrict__ P, const CompDesc* __restrict__ D,
-                                             const int* __restrict__ rank, const T* __restrict__ cf,
-                                             const T* __restrict__ nbuf, const T* __restrict__ tau_all,
-                                             T* __restrict__ blocks, T* __restrict__ scratch) {
-  const PairDesc pd = P[blockIdx.x];
+__global__ __launch_bounds__(WG) void k_pair(const PairDesc* __restrict__ P, const int32_t* __restrict__ active,
+                                             const int* __restrict__ rank, const int64_t* __restrict__ t_of_comp,
+                                             const T* __restrict__ tb, T* __restrict__ blocks,
+                                             T* __restrict__ scratch) {
+  const PairDesc pd = P[active[blockIdx.x]];
   const int sa = pd.s_a, sb = pd.s_b;
   const int ra = (pd.ca >= 0 && rank[pd.ca] < sa) ? rank[pd.ca] : sa;
   const int rb = (pd.cb >= 0 && rank[pd.cb] < sb) ? rank[pd.cb] : sb;
@@ -547,47 +572,34 @@ __global__ __launch_bounds__(WG) void k_pair(const PairDesc* __restrict__ P, con
   if (pd.a == pd.b) {
     if (ca)
       for (int idx = threadIdx.x; idx < ra * ra; idx += WG) {
-        int i = idx % ra, j = idx / ra;
+        const int i = idx % ra, j = idx / ra;
         blk[i + (int64_t)j * sa] = (i == j) ? T(1) : T(0);
       }
     return;
   }
-  if (!ca && !cb) return;
-  T* G = scratch + pd.scratch_off;             // sa x sb, ld sa
-  T* H = G + (int64_t)sa * sb;                 // sb x ra, ld sb
+  T* G = scratch + pd.scratch_off;   // ra x sb, ld ra
   if (ca) {
-    const CompDesc da = D[pd.ca];
-    const int64_t lda = da.s + da.K;
-    const T* Fa = cf + da.cf_off;
-    for (int idx = threadIdx.x; idx < sa * sb; idx += WG) {
-      int i = idx % sa, j = idx / sa;
-      G[idx] = Fa[(pd.row_in_a + j) + (int64_t)i * lda];
+    const T* Ta = tb + t_of_comp[pd.ca];
+    for (int idx = threadIdx.x; idx < ra * sb; idx += WG) {
+      const int i = idx % ra, j = idx / ra;
+      T acc = 0;
+      for (int p = 0; p < sa; ++p) acc += Ta[i + (int64_t)p * sa] * blk[p + (int64_t)j * sa];
+      G[idx] = acc;
     }
-    __syncthreads();
-    wg_apply_qt(nbuf + da.n_off, sa, tau_all + da.tau_off, sa, ra, G, sa, sb);
   } else {
-    for (int idx = threadIdx.x; idx < sa * sb; idx += WG) G[idx] = blk[idx];
+    for (int idx = threadIdx.x; idx < ra * sb; idx += WG) G[idx] = blk[(idx % ra) + (int64_t)(idx / ra) * sa];
   }
   __syncthreads();
   if (cb) {
-    const CompDesc db = D[pd.cb];
-    const int64_t ldb = db.s + db.K;
-    for (int idx = threadIdx.x; idx < sb * ra; idx += WG) {
-      int j = idx % sb, i = idx / sb;
-      H[j + (int64_t)i * sb] = G[i + (int64_t)j * sa];
-    }
-    __syncthreads();
-    wg_trsm_lower(cf + db.cf_off, ldb, sb, H, sb, ra);
-    wg_apply_qt(nbuf + db.n_off, sb, tau_all + db.tau_off, sb, rb, H, sb, ra);
+    const T* Tb = tb + t_of_comp[pd.cb];
     for (int idx = threadIdx.x; idx < ra * rb; idx += WG) {
-      int i = idx % ra, j = idx / ra;
-      blk[i + (int64_t)j * sa] = H[j + (int64_t)i * sb];
+      const int i = idx % ra, j = idx / ra;
+      T acc = 0;
+      for (int q = 0; q < sb; ++q) acc += G[i + (int64_t)q * ra] * Tb[j + (int64_t)q * sb];
+      blk[i + (int64_t)j * sa] = acc;
     }
   } else {
-    for (int idx = threadIdx.x; idx < ra * sb; idx += WG) {
-      int i = idx % ra, j = idx / ra;
-      blk[i + (int64_t)j * sa] = G[i + (int64_t)j * sa];
-    }
+    for (int idx = threadIdx.x; idx < ra * sb; idx += WG) blk[(idx % ra) + (int64_t)(idx / ra) * sa] = G[idx];
   }
 }
 

@@ -94,7 +94,7 @@ struct LevelWork {
 struct LevelDev {
   DevBuf arena, scratch, cf, nbuf, ltphi, tau, phi, rank;
   DevBuf elim, pairs, schur, comp, compnbr, sepacc, sepsrc, capply, slots, nslots;
-  DevBuf blkmap, phimap, slotptr, phioff, tb;
+  DevBuf blkmap, phimap, slotptr, phioff, tb, active, tofcomp;
   std::vector<sgf::CopyDesc> h_blkmap, h_phimap;
   LevelWork work;
   bool uploaded = false;   // descriptor tables on the device match the plan
@@ -292,14 +292,19 @@ void launch_elim(int nb, unsigned grid, size_t lds, hipStream_t st, const sgf::E
   }
 }
 
-template <typename T, typename... A>
-void launch_compress(int nb, unsigned grid, size_t lds, hipStream_t st, A... args) {
+template <typename T, bool NLDS, typename... A>
+void launch_compress_n(int nb, unsigned grid, size_t lds, hipStream_t st, A... args) {
   switch (nb) {
-    case 32: hipLaunchKernelGGL((sgf::k_compress<T, 32>), dim3(grid), dim3(sgf::WG), lds, st, args...); break;
-    case 16: hipLaunchKernelGGL((sgf::k_compress<T, 16>), dim3(grid), dim3(sgf::WG), lds, st, args...); break;
-    case 8: hipLaunchKernelGGL((sgf::k_compress<T, 8>), dim3(grid), dim3(sgf::WG), lds, st, args...); break;
-    default: hipLaunchKernelGGL((sgf::k_compress<T, 4>), dim3(grid), dim3(sgf::WG), lds, st, args...); break;
+    case 32: hipLaunchKernelGGL((sgf::k_compress<T, 32, NLDS>), dim3(grid), dim3(sgf::WG), lds, st, args...); break;
+    case 16: hipLaunchKernelGGL((sgf::k_compress<T, 16, NLDS>), dim3(grid), dim3(sgf::WG), lds, st, args...); break;
+    case 8: hipLaunchKernelGGL((sgf::k_compress<T, 8, NLDS>), dim3(grid), dim3(sgf::WG), lds, st, args...); break;
+    default: hipLaunchKernelGGL((sgf::k_compress<T, 4, NLDS>), dim3(grid), dim3(sgf::WG), lds, st, args...); break;
   }
+}
+template <typename T, typename... A>
+void launch_compress(bool nlds, int nb, unsigned grid, size_t lds, hipStream_t st, A... args) {
+  if (nlds) launch_compress_n<T, true>(nb, grid, lds, st, args...);
+  else launch_compress_n<T, false>(nb, grid, lds, st, args...);
 }
 
 void ensure_static(sgf_handle h, hipStream_t st) {
@@ -502,22 +507,22 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
         hipLaunchKernelGGL(sgf::k_comp_gather<T>, dim3((unsigned)L.comp.size()), dim3(sgf::WG), 0, st,
                            D.comp.as<sgf::CompDesc>(), D.compnbr.as<sgf::CompNbr>(), blocks, D.cf.as<T>());
       }, L.t);
-      int nb = nb_for(L.max_cf_rows, L.max_s, sizeof(T), L.max_c);
-      size_t lds = std::max<size_t>(sgf::potrf_lds_elems(L.max_cf_rows, nb), (size_t)L.max_c) * sizeof(T);
+      // N in LDS when the widest one fits beside its column norms
+      int64_t n_lds = 0;
+      for (const auto& d : L.comp) n_lds = std::max<int64_t>(n_lds, (int64_t)d.s * d.c + ((d.c + 3) & ~3));
+      const bool nlds = (size_t)n_lds * sizeof(T) <= LDS_BYTES;
+      const int64_t extra = nlds ? n_lds : L.max_c;
+      int nb = nb_for(L.max_cf_rows, L.max_s, sizeof(T), extra);
+      size_t lds = std::max<size_t>(sgf::potrf_lds_elems(L.max_cf_rows, nb), (size_t)extra) * sizeof(T);
       double tol = P.opt.rank_tol;
       launch(h, st, "compress", 0, 0, [&] {
-        launch_compress<T>(nb, (unsigned)L.comp.size(), lds, st, D.comp.as<sgf::CompDesc>(),
+        launch_compress<T>(nlds, nb, (unsigned)L.comp.size(), lds, st, D.comp.as<sgf::CompDesc>(),
                            D.compnbr.as<sgf::CompNbr>(), D.cf.as<T>(), D.nbuf.as<T>(), D.phi.as<T>(), D.ltphi.as<T>(),
                            D.tau.as<T>(), D.rank.as<int>(), P.pi, tol, h->d_fail.as<int>());
       }, L.t);
       launch(h, st, "phi_commit", 0, 0, [&] {
         hipLaunchKernelGGL(sgf::k_phi_commit<T>, dim3((unsigned)L.comp.size()), dim3(sgf::WG), 0, st,
                            D.comp.as<sgf::CompDesc>(), D.rank.as<int>(), D.ltphi.as<T>(), D.phi.as<T>(), P.pi);
-      }, L.t);
-      launch(h, st, "pair", 0, 0, [&] {
-        hipLaunchKernelGGL(sgf::k_pair<T>, dim3((unsigned)L.pairs.size()), dim3(sgf::WG), 0, st,
-                           D.pairs.as<sgf::PairDesc>(), D.comp.as<sgf::CompDesc>(), D.rank.as<int>(), D.cf.as<T>(),
-                           D.nbuf.as<T>(), D.tau.as<T>(), blocks, D.scratch.as<T>());
       }, L.t);
     }
     HIP_CHECK(hipGetLastError());
@@ -569,13 +574,36 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
       }
       D.tb.ensure(std::max<int64_t>(toff, 1) * sizeof(T));
     }
-    if (!same_ranks) upload(D.capply, L.capply, st);
+    if (!same_ranks) {
+      upload(D.capply, L.capply, st);
+      L.t_of_comp.assign(L.comp.size(), -1);
+      for (size_t c = 0, q = 0; c < L.comp.size(); ++c)
+        if (L.rank[c] < L.comp[c].s) L.t_of_comp[c] = L.capply[q++].t_off;
+      upload(D.tofcomp, L.t_of_comp, st);
+    }
     if (!L.capply.empty()) {
       double fl = 0;
       for (auto& a : L.capply) fl += (double)a.s * a.s * a.s / 3.0 + 4.0 * a.s * a.s * a.r;
       launch(h, st, "comp_explicit", fl, 0, [&] {
         hipLaunchKernelGGL(sgf::k_comp_explicit<T>, dim3((unsigned)L.capply.size()), dim3(sgf::WG), 0, st,
                            D.capply.as<sgf::CompApply>(), D.cf.as<T>(), D.nbuf.as<T>(), D.tau.as<T>(), D.tb.as<T>());
+      }, L.t);
+    }
+    // coarse couplings, only for the pairs that touch a compressed separator
+    if (!L.capply.empty()) {
+      if (!same_ranks) {
+        L.active_pairs.clear();
+        for (size_t p = 0; p < L.pairs.size(); ++p) {
+          const auto& pd = L.pairs[p];
+          const bool ca = pd.ca >= 0 && L.rank[pd.ca] < pd.s_a, cb = pd.cb >= 0 && L.rank[pd.cb] < pd.s_b;
+          if (ca || cb) L.active_pairs.push_back((int32_t)p);
+        }
+        upload(D.active, L.active_pairs, st);
+      }
+      launch(h, st, "pair", 0, 0, [&] {
+        hipLaunchKernelGGL(sgf::k_pair<T>, dim3((unsigned)L.active_pairs.size()), dim3(sgf::WG), 0, st,
+                           D.pairs.as<sgf::PairDesc>(), D.active.as<int32_t>(), D.rank.as<int>(),
+                           D.tofcomp.as<int64_t>(), D.tb.as<T>(), blocks, D.scratch.as<T>());
       }, L.t);
     }
     account_level(h, L, D.work);

@@ -222,6 +222,8 @@ struct Level {
   // results of the numeric phase
   std::vector<int32_t> rank;               // per compression
   std::vector<int32_t> planned_rank;       // ranks the next level was planned with
+  std::vector<int32_t> active_pairs;       // pairs touching a compressed separator
+  std::vector<int64_t> t_of_comp;          // offset of T_B per compression (-1: not compressed)
   std::vector<CompApply> capply;
   int64_t n_active = 0;
 
