@@ -188,21 +188,26 @@ struct Level {
   std::vector<int32_t> type, size;
   std::vector<int64_t> slot_ptr;
   std::vector<int32_t> slots;
-  std::vector<std::vector<int32_t>> adj;   // pre-elimination adjacency
+  // pre-elimination adjacency (CSR, ascending); for an interior its entries
+  // are its neighbours and nbr_off gives each one's offset in the front's k part
+  std::vector<int64_t> adj_ptr;
+  std::vector<int32_t> adj_idx;
+  std::vector<int32_t> nbr_off;
   // interiors
   std::vector<int32_t> interiors;
+  std::vector<int32_t> elim_of;            // cluster -> interior index or -1
   std::vector<ElimDesc> elim;
   std::vector<int32_t> nslots;             // neighbour slots of every interior
-  std::vector<std::vector<int32_t>> inbr;  // neighbours of each interior (ascending)
-  std::vector<std::vector<int32_t>> inbr_off;
   int64_t front_elems = 0;
   int64_t t_elems = 0;                     // apply scratch per rhs
   int32_t max_front_rows = 0;
   // separators
   std::vector<int32_t> seps;
   std::vector<int32_t> sep_pos;            // cluster -> position in seps or -1
-  std::vector<std::vector<int32_t>> sadj;  // post-elimination separator adjacency
-  std::vector<std::vector<int32_t>> pair_of;  // for sep position a: pair id per sadj entry with b >= a
+  // post-elimination separator adjacency (CSR by separator position,
+  // ascending cluster ids); sadj_pair = pair id of (a, b) when b > a
+  std::vector<int64_t> sadj_ptr;
+  std::vector<int32_t> sadj_idx, sadj_pair, pair_diag;
   std::vector<PairDesc> pairs;
   std::vector<SchurDesc> schur;
   int64_t blk_elems = 0;
@@ -232,17 +237,25 @@ struct Level {
     if (ci >= 0 && !rank.empty() && rank[ci] < size[c]) return rank[ci];
     return size[c];
   }
+  // position of separator b in the adjacency list of separator a, or -1
+  int64_t sadj_find(int a, int b) const {
+    const int pa = sep_pos[a];
+    const int32_t* lo = sadj_idx.data() + sadj_ptr[pa];
+    const int32_t* hi = sadj_idx.data() + sadj_ptr[pa + 1];
+    const int32_t* it = std::lower_bound(lo, hi, b);
+    return (it == hi || *it != b) ? -1 : (int64_t)(it - sadj_idx.data());
+  }
   int32_t find_pair(int a, int b) const {  // cluster indices, a <= b, both separators
-    int pa = sep_pos[a];
-    const auto& v = sadj[pa];
-    if (a == b) return pair_of[pa][0];
-    auto it = std::lower_bound(v.begin(), v.end(), b);
-    if (it == v.end() || *it != b) return -1;
-    // pair_of[pa][0] is the diagonal; upper neighbours follow in order
-    int idx = 1;
-    for (auto jt = v.begin(); jt != it; ++jt)
-      if (*jt > a) ++idx;
-    return pair_of[pa][idx];
+    if (a == b) return pair_diag[sep_pos[a]];
+    const int64_t e = sadj_find(a, b);
+    return e < 0 ? -1 : sadj_pair[e];
+  }
+  // row of neighbour X inside the front of interior cluster I (m + offset)
+  int32_t front_row(int I, int X) const {
+    const int32_t* lo = adj_idx.data() + adj_ptr[I];
+    const int32_t* hi = adj_idx.data() + adj_ptr[I + 1];
+    const int64_t e = std::lower_bound(lo, hi, X) - adj_idx.data();
+    return elim[elim_of[I]].m + nbr_off[e];
   }
 };
 
@@ -273,74 +286,101 @@ inline void build_level(Level& L, const Options& o, int pi) {
   L.interiors.clear();
   L.seps.clear();
   L.sep_pos.assign(nc, -1);
+  L.elim_of.assign(nc, -1);
   L.n_active = 0;
   for (int c = 0; c < nc; ++c) {
     L.n_active += L.size[c];
-    if (L.top || L.type[c] == 0) L.interiors.push_back(c);
-    else {
+    if (L.top || L.type[c] == 0) {
+      L.elim_of[c] = (int32_t)L.interiors.size();
+      L.interiors.push_back(c);
+    } else {
       L.sep_pos[c] = (int)L.seps.size();
       L.seps.push_back(c);
     }
   }
+  const int ni = (int)L.interiors.size(), ns = (int)L.seps.size();
   // ---- interiors: fronts [I ; neighbours] -----------------------------------
-  L.elim.clear();
-  L.nslots.clear();
-  L.inbr.assign(L.interiors.size(), {});
-  L.inbr_off.assign(L.interiors.size(), {});
+  L.elim.assign(ni, ElimDesc{});
+  L.nbr_off.assign(L.adj_idx.size(), 0);
   L.front_elems = 0;
   L.t_elems = 0;
   L.max_front_rows = 0;
-  for (size_t ii = 0; ii < L.interiors.size(); ++ii) {
-    int I = L.interiors[ii];
-    ElimDesc d{};
+  int64_t total_k = 0;
+  for (int ii = 0; ii < ni; ++ii) {
+    const int I = L.interiors[ii];
+    ElimDesc& d = L.elim[ii];
     d.cluster = I;
     d.m = L.size[I];
     int k = 0;
-    for (int X : L.adj[I]) {
+    for (int64_t e = L.adj_ptr[I]; e < L.adj_ptr[I + 1]; ++e) {
+      const int X = L.adj_idx[e];
       if (L.sep_pos[X] < 0)
         throw std::runtime_error("two interiors are adjacent: the pattern couples nodes more than one grid step apart");
-      L.inbr[ii].push_back(X);
-      L.inbr_off[ii].push_back(k);
+      L.nbr_off[e] = k;
       k += L.size[X];
     }
     d.k = k;
     d.front_off = L.front_elems;
-    int64_t R = (int64_t)d.m + k;
+    const int64_t R = (int64_t)d.m + k;
     L.front_elems += R * R;
     L.max_front_rows = std::max<int32_t>(L.max_front_rows, (int32_t)R);
     d.slot_off = L.slot_ptr[I];
-    d.nslot_off = (int64_t)L.nslots.size();
-    for (int X : L.inbr[ii])
-      for (int64_t s = L.slot_ptr[X]; s < L.slot_ptr[X + 1]; ++s) L.nslots.push_back(L.slots[s]);
+    d.nslot_off = total_k;
     d.t_off = L.t_elems;
     L.t_elems += k;
-    L.elim.push_back(d);
+    total_k += k;
+  }
+  L.nslots.resize(total_k);
+  for (int ii = 0; ii < ni; ++ii) {
+    const int I = L.interiors[ii];
+    int64_t q = L.elim[ii].nslot_off;
+    for (int64_t e = L.adj_ptr[I]; e < L.adj_ptr[I + 1]; ++e) {
+      const int X = L.adj_idx[e];
+      for (int64_t s = L.slot_ptr[X]; s < L.slot_ptr[X + 1]; ++s) L.nslots[q++] = L.slots[s];
+    }
   }
   // ---- separators: post-elimination adjacency ------------------------------
-  const int ns = (int)L.seps.size();
-  L.sadj.assign(ns, {});
-  for (int p = 0; p < ns; ++p) {
-    int a = L.seps[p];
-    for (int X : L.adj[a])
-      if (L.sep_pos[X] >= 0) L.sadj[p].push_back(X);
-  }
-  for (size_t ii = 0; ii < L.interiors.size(); ++ii) {
-    const auto& nb = L.inbr[ii];
-    for (int x : nb)
-      for (int y : nb)
-        if (x != y) L.sadj[L.sep_pos[x]].push_back(y);
-  }
-  for (auto& v : L.sadj) {
-    std::sort(v.begin(), v.end());
-    v.erase(std::unique(v.begin(), v.end()), v.end());
+  // sadj(a) = separators adjacent to a, plus every other neighbour of each
+  // interior adjacent to a (the fill of Eq. 4.2).
+  L.sadj_ptr.assign(ns + 1, 0);
+  L.sadj_idx.clear();
+  {
+    std::vector<int32_t> stamp(nc, -1), buf;
+    for (int p = 0; p < ns; ++p) {
+      const int a = L.seps[p];
+      buf.clear();
+      stamp[a] = p;
+      for (int64_t e = L.adj_ptr[a]; e < L.adj_ptr[a + 1]; ++e) {
+        const int X = L.adj_idx[e];
+        if (L.sep_pos[X] >= 0) {
+          if (stamp[X] != p) {
+            stamp[X] = p;
+            buf.push_back(X);
+          }
+        } else {
+          for (int64_t f = L.adj_ptr[X]; f < L.adj_ptr[X + 1]; ++f) {
+            const int Y = L.adj_idx[f];
+            if (stamp[Y] != p) {
+              stamp[Y] = p;
+              buf.push_back(Y);
+            }
+          }
+        }
+      }
+      std::sort(buf.begin(), buf.end());
+      L.sadj_idx.insert(L.sadj_idx.end(), buf.begin(), buf.end());
+      L.sadj_ptr[p + 1] = (int64_t)L.sadj_idx.size();
+    }
   }
   // pairs (a <= b): diagonal first, then upper neighbours ascending
   L.pairs.clear();
-  L.pair_of.assign(ns, {});
+  L.pairs.reserve(ns + L.sadj_idx.size() / 2);
+  L.sadj_pair.assign(L.sadj_idx.size(), -1);
+  L.pair_diag.assign(ns, -1);
   L.blk_elems = 0;
   L.scratch_elems = 0;
   for (int p = 0; p < ns; ++p) {
-    int a = L.seps[p];
+    const int a = L.seps[p];
     auto add = [&](int b) {
       PairDesc d{};
       d.a = a;
@@ -353,35 +393,49 @@ inline void build_level(Level& L, const Options& o, int pi) {
       L.scratch_elems += 2 * (int64_t)d.s_a * d.s_b;
       d.ca = d.cb = -1;
       d.row_in_a = d.row_in_b = -1;
-      L.pair_of[p].push_back((int)L.pairs.size());
       L.pairs.push_back(d);
+      return (int32_t)L.pairs.size() - 1;
     };
-    add(a);
-    for (int b : L.sadj[p])
-      if (b > a) add(b);
+    L.pair_diag[p] = add(a);
+    for (int64_t e = L.sadj_ptr[p]; e < L.sadj_ptr[p + 1]; ++e)
+      if (L.sadj_idx[e] > a) L.sadj_pair[e] = add(L.sadj_idx[e]);
   }
-  // Schur contributions, grouped per pair, interiors ascending
-  std::vector<std::vector<SchurDesc>> contrib(L.pairs.size());
-  for (size_t ii = 0; ii < L.interiors.size(); ++ii) {
-    const ElimDesc& e = L.elim[ii];
-    const auto& nb = L.inbr[ii];
-    const auto& off = L.inbr_off[ii];
-    int64_t ld = (int64_t)e.m + e.k;
-    for (size_t x = 0; x < nb.size(); ++x)
-      for (size_t y = x; y < nb.size(); ++y) {
-        int pid = L.find_pair(nb[x], nb[y]);
-        SchurDesc s{};
-        s.src_ld = (int32_t)ld;
-        s.diag = x == y;
-        s.src_off = e.front_off + (e.m + off[y]) + (int64_t)(e.m + off[x]) * ld;
-        contrib[pid].push_back(s);
-      }
-  }
-  L.schur.clear();
-  for (size_t p = 0; p < L.pairs.size(); ++p) {
-    L.pairs[p].c_ptr = (int32_t)L.schur.size();
-    L.pairs[p].c_cnt = (int32_t)contrib[p].size();
-    for (auto& s : contrib[p]) L.schur.push_back(s);
+  // Schur contributions, grouped per pair, interiors ascending (counting sort)
+  {
+    std::vector<int32_t> cnt(L.pairs.size() + 1, 0);
+    std::vector<int32_t> pid_of;
+    pid_of.reserve(L.adj_idx.size() * 4);
+    for (int ii = 0; ii < ni; ++ii) {
+      const int I = L.interiors[ii];
+      for (int64_t x = L.adj_ptr[I]; x < L.adj_ptr[I + 1]; ++x)
+        for (int64_t y = x; y < L.adj_ptr[I + 1]; ++y) {
+          const int pid = L.find_pair(L.adj_idx[x], L.adj_idx[y]);
+          pid_of.push_back(pid);
+          ++cnt[pid + 1];
+        }
+    }
+    for (size_t p = 0; p < L.pairs.size(); ++p) {
+      L.pairs[p].c_ptr = cnt[p];
+      L.pairs[p].c_cnt = cnt[p + 1];
+      cnt[p + 1] += cnt[p];
+    }
+    L.schur.assign(pid_of.size(), SchurDesc{});
+    std::vector<int32_t> cur(L.pairs.size());
+    for (size_t p = 0; p < L.pairs.size(); ++p) cur[p] = L.pairs[p].c_ptr;
+    size_t q = 0;
+    for (int ii = 0; ii < ni; ++ii) {
+      const int I = L.interiors[ii];
+      const ElimDesc& e = L.elim[ii];
+      const int64_t ld = (int64_t)e.m + e.k;
+      for (int64_t x = L.adj_ptr[I]; x < L.adj_ptr[I + 1]; ++x)
+        for (int64_t y = x; y < L.adj_ptr[I + 1]; ++y) {
+          SchurDesc sd{};
+          sd.src_ld = (int32_t)ld;
+          sd.diag = x == y;
+          sd.src_off = e.front_off + (e.m + L.nbr_off[y]) + (int64_t)(e.m + L.nbr_off[x]) * ld;
+          L.schur[cur[pid_of[q++]]++] = sd;
+        }
+    }
   }
   // ---- Phi per cluster ---------------------------------------------------------
   L.phi_off.assign(nc, 0);
@@ -397,18 +451,21 @@ inline void build_level(Level& L, const Options& o, int pi) {
   L.cf_elems = L.n_elems = L.ltphi_elems = L.tau_elems = 0;
   L.max_cf_rows = L.max_c = L.max_s = 0;
   if (L.compress) {
+    L.comp.reserve(ns);
+    L.comp_nbr.reserve(L.sadj_idx.size());
     for (int p = 0; p < ns; ++p) {
-      int B = L.seps[p];
+      const int B = L.seps[p];
       if (!compressible(L.type[B], o.dim, o.scheme)) continue;
       CompDesc d{};
       d.cluster = B;
       d.s = L.size[B];
       d.nb_ptr = (int32_t)L.comp_nbr.size();
-      d.nnb = (int32_t)L.sadj[p].size();
+      d.nnb = (int32_t)(L.sadj_ptr[p + 1] - L.sadj_ptr[p]);
       int K = 0;
-      for (int X : L.sadj[p]) {
+      for (int64_t e = L.sadj_ptr[p]; e < L.sadj_ptr[p + 1]; ++e) {
+        const int X = L.sadj_idx[e];
         CompNbr nbx{};
-        int pid = X > B ? L.find_pair(B, X) : L.find_pair(X, B);
+        const int pid = X > B ? L.sadj_pair[e] : L.find_pair(X, B);
         nbx.blk_off = L.pairs[pid].blk_off;
         nbx.trans = X > B ? 1 : 0;
         nbx.s_x = L.size[X];
@@ -429,7 +486,7 @@ inline void build_level(Level& L, const Options& o, int pi) {
       L.tau_elems += d.c;
       d.phi_off = L.phi_off[B];
       d.slot_off = L.slot_ptr[B];
-      d.blk_diag = L.pairs[L.find_pair(B, B)].blk_off;
+      d.blk_diag = L.pairs[L.pair_diag[p]].blk_off;
       L.comp_of[B] = (int32_t)L.comp.size();
       L.max_cf_rows = std::max<int32_t>(L.max_cf_rows, d.s + K);
       L.max_c = std::max<int32_t>(L.max_c, d.c);
@@ -444,34 +501,45 @@ inline void build_level(Level& L, const Options& o, int pi) {
     if (pd.a != pd.b) {
       if (pd.ca >= 0) {
         const CompDesc& d = L.comp[pd.ca];
-        for (int j = 0; j < d.nnb; ++j)
-          if (L.sadj[L.sep_pos[pd.a]][j] == pd.b) pd.row_in_a = L.comp_nbr[d.nb_ptr + j].row;
+        const int64_t e = L.sadj_find(pd.a, pd.b);
+        pd.row_in_a = L.comp_nbr[d.nb_ptr + (e - L.sadj_ptr[L.sep_pos[pd.a]])].row;
       }
       if (pd.cb >= 0) {
         const CompDesc& d = L.comp[pd.cb];
-        for (int j = 0; j < d.nnb; ++j)
-          if (L.sadj[L.sep_pos[pd.b]][j] == pd.a) pd.row_in_b = L.comp_nbr[d.nb_ptr + j].row;
+        const int64_t e = L.sadj_find(pd.b, pd.a);
+        pd.row_in_b = L.comp_nbr[d.nb_ptr + (e - L.sadj_ptr[L.sep_pos[pd.b]])].row;
       }
     }
   }
-  // apply: separator accumulation lists
-  std::vector<std::vector<int64_t>> acc(ns);
-  for (size_t ii = 0; ii < L.interiors.size(); ++ii) {
-    const auto& nb = L.inbr[ii];
-    for (size_t x = 0; x < nb.size(); ++x)
-      acc[L.sep_pos[nb[x]]].push_back(L.elim[ii].t_off + L.inbr_off[ii][x]);
-  }
-  L.sepacc.clear();
-  L.sepacc_src.clear();
-  for (int p = 0; p < ns; ++p) {
-    if (acc[p].empty()) continue;
-    SepAcc s{};
-    s.slot_off = L.slot_ptr[L.seps[p]];
-    s.s = L.size[L.seps[p]];
-    s.c_ptr = (int32_t)L.sepacc_src.size();
-    s.c_cnt = (int32_t)acc[p].size();
-    for (auto v : acc[p]) L.sepacc_src.push_back(v);
-    L.sepacc.push_back(s);
+  // apply: separator accumulation lists (counting sort, interiors ascending)
+  {
+    std::vector<int32_t> cnt(ns + 1, 0);
+    for (int ii = 0; ii < ni; ++ii) {
+      const int I = L.interiors[ii];
+      for (int64_t e = L.adj_ptr[I]; e < L.adj_ptr[I + 1]; ++e) ++cnt[L.sep_pos[L.adj_idx[e]] + 1];
+    }
+    std::vector<int32_t> start(ns + 1, 0);
+    for (int p = 0; p < ns; ++p) start[p + 1] = start[p] + cnt[p + 1];
+    std::vector<int64_t> flat(start[ns]);
+    std::vector<int32_t> cur(start.begin(), start.end() - 1);
+    for (int ii = 0; ii < ni; ++ii) {
+      const int I = L.interiors[ii];
+      for (int64_t e = L.adj_ptr[I]; e < L.adj_ptr[I + 1]; ++e)
+        flat[cur[L.sep_pos[L.adj_idx[e]]]++] = L.elim[ii].t_off + L.nbr_off[e];
+    }
+    L.sepacc.clear();
+    L.sepacc_src.clear();
+    L.sepacc_src.reserve(flat.size());
+    for (int p = 0; p < ns; ++p) {
+      if (start[p + 1] == start[p]) continue;
+      SepAcc sa{};
+      sa.slot_off = L.slot_ptr[L.seps[p]];
+      sa.s = L.size[L.seps[p]];
+      sa.c_ptr = (int32_t)L.sepacc_src.size();
+      sa.c_cnt = start[p + 1] - start[p];
+      L.sepacc_src.insert(L.sepacc_src.end(), flat.begin() + start[p], flat.begin() + start[p + 1]);
+      L.sepacc.push_back(sa);
+    }
   }
   L.rank.clear();
   L.capply.clear();
@@ -485,8 +553,11 @@ inline void validate_level(const Level& L, int64_t n, int pi) {
   };
   const int64_t arena = L.front_elems + L.blk_elems;
   const int64_t nsl = (int64_t)L.slots.size(), nns = (int64_t)L.nslots.size();
-  for (int32_t v : L.slots) req(v >= 0 && v < n, "slot out of range");
-  for (int32_t v : L.nslots) req(v >= 0 && v < n, "neighbour slot out of range");
+  // slot values above level 1 are copies of checked level-1 slots
+  if (L.t == 1) {
+    for (int32_t v : L.slots) req(v >= 0 && v < n, "slot out of range");
+    for (int32_t v : L.nslots) req(v >= 0 && v < n, "neighbour slot out of range");
+  }
   for (const auto& e : L.elim) {
     int64_t R = (int64_t)e.m + e.k;
     req(e.m >= 0 && e.k >= 0 && e.front_off >= 0 && e.front_off + R * R <= L.front_elems, "front extent");
@@ -603,7 +674,7 @@ inline void plan_level1(Plan& P, const int64_t* row_ptr, const int32_t* col_idx)
   L.slots.resize(P.n);
   for (int64_t s = 0; s < P.n; ++s) L.slots[s] = (int32_t)s;
   // adjacency from the pattern; check the 3^dim stencil assumption
-  L.adj.assign(nc, {});
+  std::vector<std::vector<int32_t>> adj(nc);
   for (int64_t i = 0; i < P.n; ++i) {
     int ci = cl_of[i];
     int64_t ni = i / dpn;
@@ -616,12 +687,17 @@ inline void plan_level1(Plan& P, const int64_t* row_ptr, const int32_t* col_idx)
       if (std::abs(ix - jx) > 1 || std::abs(iy - jy) > 1 || std::abs(iz - jz) > 1)
         throw std::runtime_error("pattern couples grid nodes more than one step apart");
       int cj = cl_of[j];
-      if (cj != ci) L.adj[ci].push_back(cj);
+      if (cj != ci) adj[ci].push_back(cj);
     }
   }
-  for (auto& v : L.adj) {
+  L.adj_ptr.assign(nc + 1, 0);
+  L.adj_idx.clear();
+  for (int c = 0; c < nc; ++c) {
+    auto& v = adj[c];
     std::sort(v.begin(), v.end());
     v.erase(std::unique(v.begin(), v.end()), v.end());
+    L.adj_idx.insert(L.adj_idx.end(), v.begin(), v.end());
+    L.adj_ptr[c + 1] = (int64_t)L.adj_idx.size();
   }
   build_level(L, o, P.pi);
   P.max_node = 0;
@@ -629,8 +705,7 @@ inline void plan_level1(Plan& P, const int64_t* row_ptr, const int32_t* col_idx)
   // CSR fill destinations
   const int64_t nnz = row_ptr[P.n];
   P.csr_dst.assign(nnz, -1);
-  std::vector<int32_t> elim_of(nc, -1);
-  for (size_t ii = 0; ii < L.interiors.size(); ++ii) elim_of[L.interiors[ii]] = (int32_t)ii;
+  const std::vector<int32_t>& elim_of = L.elim_of;
   for (int64_t i = 0; i < P.n; ++i) {
     int ci = cl_of[i], li = loc_of[i];
     for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
@@ -642,9 +717,7 @@ inline void plan_level1(Plan& P, const int64_t* row_ptr, const int32_t* col_idx)
         if (cj == ci) {
           P.csr_dst[e] = d.front_off + li + (int64_t)lj * ld;
         } else {
-          const auto& nb = L.inbr[elim_of[ci]];
-          size_t x = std::lower_bound(nb.begin(), nb.end(), cj) - nb.begin();
-          int64_t row = d.m + L.inbr_off[elim_of[ci]][x] + lj;
+          int64_t row = L.front_row(ci, cj) + lj;
           P.csr_dst[e] = d.front_off + row + (int64_t)li * ld;
         }
       } else if (elim_of[cj] >= 0) {
@@ -671,27 +744,32 @@ inline void plan_next_level(Plan& P, std::vector<CopyDesc>& blk_map, std::vector
   C.planned_rank = C.rank;
   const Partition& lo = P.parts.back();
   Partition hi = make_partition(o, lo.d * 2);
+  const int cs = (int)C.seps.size();
   // surviving clusters: the separators, with their post-compression sizes
-  std::vector<int64_t> fcell(C.seps.size());
-  for (size_t p = 0; p < C.seps.size(); ++p) fcell[p] = father_cell(lo, hi, C.cell[C.seps[p]]);
-  std::vector<int64_t> uniq(fcell);
-  std::sort(uniq.begin(), uniq.end());
-  uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
+  std::vector<int64_t> fcell(cs);
+  for (int p = 0; p < cs; ++p) fcell[p] = father_cell(lo, hi, C.cell[C.seps[p]]);
+  // father cells present, ascending (dense marking over the coarser cells)
+  std::vector<int32_t> rank_of_cell(hi.ncells, -1);
+  for (int p = 0; p < cs; ++p) rank_of_cell[fcell[p]] = 0;
+  std::vector<int64_t> uniq;
+  for (int64_t c = 0; c < hi.ncells; ++c)
+    if (rank_of_cell[c] == 0) {
+      rank_of_cell[c] = (int32_t)uniq.size();
+      uniq.push_back(c);
+    }
   Level N;
   N.t = C.t + 1;
   const int nc = (int)uniq.size();
-  std::vector<int32_t> father(C.seps.size());
-  for (size_t p = 0; p < C.seps.size(); ++p)
-    father[p] = (int32_t)(std::lower_bound(uniq.begin(), uniq.end(), fcell[p]) - uniq.begin());
+  std::vector<int32_t> father(cs);
+  for (int p = 0; p < cs; ++p) father[p] = rank_of_cell[fcell[p]];
   N.cell = uniq;
   N.type.resize(nc);
   for (int c = 0; c < nc; ++c) N.type[c] = hi.type_of(uniq[c]);
   N.size.assign(nc, 0);
-  std::vector<int32_t> loc(C.seps.size());
-  for (size_t p = 0; p < C.seps.size(); ++p) {     // seps ascending: children in order
-    int a = C.seps[p];
+  std::vector<int32_t> loc(cs);
+  for (int p = 0; p < cs; ++p) {     // seps ascending: children in order
     loc[p] = N.size[father[p]];
-    N.size[father[p]] += C.post_size(a);
+    N.size[father[p]] += C.post_size(C.seps[p]);
   }
   int64_t n_active = 0, biggest = 0;
   for (int c = 0; c < nc; ++c) {
@@ -704,7 +782,7 @@ inline void plan_next_level(Plan& P, std::vector<CopyDesc>& blk_map, std::vector
     // merge every cluster of the new partition into one, ascending cell id
     std::vector<int32_t> base(nc, 0);
     for (int c = 1; c < nc; ++c) base[c] = base[c - 1] + N.size[c - 1];
-    for (size_t p = 0; p < C.seps.size(); ++p) loc[p] += base[father[p]];
+    for (int p = 0; p < cs; ++p) loc[p] += base[father[p]];
     for (auto& f : father) f = 0;
     N.cell = {uniq[0]};
     N.type = {0};
@@ -714,46 +792,57 @@ inline void plan_next_level(Plan& P, std::vector<CopyDesc>& blk_map, std::vector
   const int nc2 = (int)N.cell.size();
   N.compress = !top && o.compress && N.t >= o.compress_from_level;
   // slots: concatenation of the children's first post-size slots
-  std::vector<std::vector<int32_t>> sl(nc2);
-  for (int c = 0; c < nc2; ++c) sl[c].resize(N.size[c]);
-  for (size_t p = 0; p < C.seps.size(); ++p) {
-    int a = C.seps[p];
-    int r = C.post_size(a);
-    for (int i = 0; i < r; ++i) sl[father[p]][loc[p] + i] = C.slots[C.slot_ptr[a] + i];
-  }
   N.slot_ptr.assign(nc2 + 1, 0);
   for (int c = 0; c < nc2; ++c) N.slot_ptr[c + 1] = N.slot_ptr[c] + N.size[c];
-  N.slots.reserve(N.slot_ptr[nc2]);
-  for (int c = 0; c < nc2; ++c) N.slots.insert(N.slots.end(), sl[c].begin(), sl[c].end());
+  N.slots.assign(N.slot_ptr[nc2], 0);
+  for (int p = 0; p < cs; ++p) {
+    const int a = C.seps[p];
+    const int r = C.post_size(a);
+    std::copy(C.slots.begin() + C.slot_ptr[a], C.slots.begin() + C.slot_ptr[a] + r,
+              N.slots.begin() + N.slot_ptr[father[p]] + loc[p]);
+  }
+  // children grouped by father (ascending)
+  std::vector<int32_t> ch_ptr(nc2 + 1, 0), ch(cs);
+  for (int p = 0; p < cs; ++p) ++ch_ptr[father[p] + 1];
+  for (int c = 0; c < nc2; ++c) ch_ptr[c + 1] += ch_ptr[c];
+  {
+    std::vector<int32_t> cur(ch_ptr.begin(), ch_ptr.end() - 1);
+    for (int p = 0; p < cs; ++p) ch[cur[father[p]]++] = p;
+  }
   // adjacency: fathers of adjacent separators
-  N.adj.assign(nc2, {});
-  for (size_t p = 0; p < C.seps.size(); ++p)
-    for (int b : C.sadj[p]) {
-      int fa = father[p], fb = father[C.sep_pos[b]];
-      if (fa != fb) N.adj[fa].push_back(fb);
+  N.adj_ptr.assign(nc2 + 1, 0);
+  N.adj_idx.clear();
+  {
+    std::vector<int32_t> stamp(nc2, -1), buf;
+    for (int fa = 0; fa < nc2; ++fa) {
+      buf.clear();
+      stamp[fa] = fa;
+      for (int q = ch_ptr[fa]; q < ch_ptr[fa + 1]; ++q) {
+        const int p = ch[q];
+        for (int64_t e = C.sadj_ptr[p]; e < C.sadj_ptr[p + 1]; ++e) {
+          const int fb = father[C.sep_pos[C.sadj_idx[e]]];
+          if (stamp[fb] != fa) {
+            stamp[fb] = fa;
+            buf.push_back(fb);
+          }
+        }
+      }
+      std::sort(buf.begin(), buf.end());
+      N.adj_idx.insert(N.adj_idx.end(), buf.begin(), buf.end());
+      N.adj_ptr[fa + 1] = (int64_t)N.adj_idx.size();
     }
-  for (auto& v : N.adj) {
-    std::sort(v.begin(), v.end());
-    v.erase(std::unique(v.begin(), v.end()), v.end());
   }
   build_level(N, o, P.pi);
   // copy maps: level-C pair blocks (coarse part, ld s_a) -> level-N storage
   blk_map.clear();
   phi_map.clear();
-  std::vector<int32_t> elim_of(nc2, -1);
-  for (size_t ii = 0; ii < N.interiors.size(); ++ii) elim_of[N.interiors[ii]] = (int32_t)ii;
-  auto front_nbr_row = [&](int I, int X) {
-    int ii = elim_of[I];
-    const auto& nb = N.inbr[ii];
-    size_t x = std::lower_bound(nb.begin(), nb.end(), X) - nb.begin();
-    return N.elim[ii].m + N.inbr_off[ii][x];
-  };
+  blk_map.reserve(2 * C.pairs.size());
   for (const PairDesc& pd : C.pairs) {
-    int pa = C.sep_pos[pd.a], pb = C.sep_pos[pd.b];
-    int ra = C.post_size(pd.a), rb = C.post_size(pd.b);
+    const int pa = C.sep_pos[pd.a], pb = C.sep_pos[pd.b];
+    const int ra = C.post_size(pd.a), rb = C.post_size(pd.b);
     if (ra == 0 || rb == 0) continue;
-    int Da = father[pa], Db = father[pb];
-    int oa = loc[pa], ob = loc[pb];
+    const int Da = father[pa], Db = father[pb];
+    const int oa = loc[pa], ob = loc[pb];
     CopyDesc cd{};
     cd.src_off = C.front_elems + pd.blk_off;
     cd.src_ld = pd.s_a;
@@ -761,12 +850,12 @@ inline void plan_next_level(Plan& P, std::vector<CopyDesc>& blk_map, std::vector
     cd.cols = rb;
     if (Da == Db) {
       int64_t base, ld;
-      if (elim_of[Da] >= 0) {
-        const ElimDesc& e = N.elim[elim_of[Da]];
+      if (N.elim_of[Da] >= 0) {
+        const ElimDesc& e = N.elim[N.elim_of[Da]];
         base = e.front_off;
         ld = (int64_t)e.m + e.k;
       } else {
-        const PairDesc& q = N.pairs[N.find_pair(Da, Da)];
+        const PairDesc& q = N.pairs[N.pair_diag[N.sep_pos[Da]]];
         base = N.front_elems + q.blk_off;
         ld = q.s_a;
       }
@@ -779,19 +868,19 @@ inline void plan_next_level(Plan& P, std::vector<CopyDesc>& blk_map, std::vector
         cd.dst_off = base + ob + (int64_t)oa * ld;
         blk_map.push_back(cd);
       }
-    } else if (elim_of[Da] >= 0) {
-      const ElimDesc& e = N.elim[elim_of[Da]];
-      int64_t ld = (int64_t)e.m + e.k;
+    } else if (N.elim_of[Da] >= 0) {
+      const ElimDesc& e = N.elim[N.elim_of[Da]];
+      const int64_t ld = (int64_t)e.m + e.k;
       cd.dst_ld = (int32_t)ld;
       cd.mode = 1;
-      cd.dst_off = e.front_off + (front_nbr_row(Da, Db) + ob) + (int64_t)oa * ld;
+      cd.dst_off = e.front_off + (N.front_row(Da, Db) + ob) + (int64_t)oa * ld;
       blk_map.push_back(cd);
-    } else if (elim_of[Db] >= 0) {
-      const ElimDesc& e = N.elim[elim_of[Db]];
-      int64_t ld = (int64_t)e.m + e.k;
+    } else if (N.elim_of[Db] >= 0) {
+      const ElimDesc& e = N.elim[N.elim_of[Db]];
+      const int64_t ld = (int64_t)e.m + e.k;
       cd.dst_ld = (int32_t)ld;
       cd.mode = 0;
-      cd.dst_off = e.front_off + (front_nbr_row(Db, Da) + oa) + (int64_t)ob * ld;
+      cd.dst_off = e.front_off + (N.front_row(Db, Da) + oa) + (int64_t)ob * ld;
       blk_map.push_back(cd);
     } else {
       if (Da < Db) {
@@ -809,9 +898,10 @@ inline void plan_next_level(Plan& P, std::vector<CopyDesc>& blk_map, std::vector
     }
   }
   if (!N.top) {
-    for (size_t p = 0; p < C.seps.size(); ++p) {
-      int a = C.seps[p];
-      int r = C.post_size(a);
+    phi_map.reserve(cs);
+    for (int p = 0; p < cs; ++p) {
+      const int a = C.seps[p];
+      const int r = C.post_size(a);
       if (r == 0) continue;
       CopyDesc cd{};
       cd.src_off = C.phi_off[a];
@@ -819,7 +909,7 @@ inline void plan_next_level(Plan& P, std::vector<CopyDesc>& blk_map, std::vector
       cd.rows = r;
       cd.cols = P.pi;
       cd.mode = 0;
-      int D = father[p];
+      const int D = father[p];
       cd.dst_ld = N.size[D];
       cd.dst_off = N.phi_off[D] + loc[p];
       phi_map.push_back(cd);
