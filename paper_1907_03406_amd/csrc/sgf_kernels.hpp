@@ -858,9 +858,12 @@ __global__ __launch_bounds__(WG) void k_apply_fwd(const ElimDesc* __restrict__ D
     stage_diag(C, R, jb, nb, Dg);
     __syncthreads();
     if (w == 0) {
+      // lane j finishes x_j at step j (scaled by its reciprocal pivot) and
+      // the value is broadcast through a scalar register
       T x = lane < nb ? v[jb + lane] : T(0);
+      const T dinv = lane < nb ? Dg[lane + lane * DLD] : T(0);
       for (int j = 0; j < nb; ++j) {
-        const T xj = __shfl(x, j, WAVE) * Dg[j + j * DLD];
+        const T xj = lane_bcast(x * dinv, j);
         if (lane == j) x = xj;
         else if (lane > j) x -= Dg[lane + j * DLD] * xj;
       }
@@ -870,7 +873,7 @@ __global__ __launch_bounds__(WG) void k_apply_fwd(const ElimDesc* __restrict__ D
     for (int i = jb + nb + threadIdx.x; i < R; i += WG) {
       const T* ci = C + i + (int64_t)jb * R;
       T acc = 0;
-#pragma unroll 8
+#pragma unroll 16
       for (int j = 0; j < nb; ++j) acc += ci[(int64_t)j * R] * v[jb + j];
       v[i] -= acc;
     }
@@ -901,19 +904,32 @@ __global__ __launch_bounds__(WG) void k_apply_bwd(const ElimDesc* __restrict__ D
   const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
   for (int bj = (m + DB - 1) / DB - 1; bj >= 0; --bj) {
     const int jb = bj * DB, nb = min(DB, m - jb), below = jb + nb;
-    for (int j = w; j < nb; j += WG / WAVE) {
+    // two columns per pass so that their loads and reductions overlap
+    for (int j = 2 * w; j < nb; j += 2 * (WG / WAVE)) {
+      const bool two = j + 1 < nb;
       const T* cj = C + (int64_t)(jb + j) * R;
-      T acc = 0;
-      for (int i = below + lane; i < R; i += WAVE) acc += cj[i] * v[i];
-      acc = wave_sum(acc);
-      if (lane == 0) v[jb + j] -= acc;
+      const T* ck = cj + R;
+      T a0 = 0, a1 = 0;
+#pragma unroll 4
+      for (int i = below + lane; i < R; i += WAVE) {
+        const T vi = v[i];
+        a0 += cj[i] * vi;
+        if (two) a1 += ck[i] * vi;
+      }
+      a0 = wave_sum(a0);
+      a1 = wave_sum(a1);
+      if (lane == 0) {
+        v[jb + j] -= a0;
+        if (two) v[jb + j + 1] -= a1;
+      }
     }
     stage_diag(C, R, jb, nb, Dg);
     __syncthreads();
     if (w == 0) {
       T x = lane < nb ? v[jb + lane] : T(0);
+      const T dinv = lane < nb ? Dg[lane + lane * DLD] : T(0);
       for (int j = nb - 1; j >= 0; --j) {
-        const T xj = __shfl(x, j, WAVE) * Dg[j + j * DLD];
+        const T xj = lane_bcast(x * dinv, j);
         if (lane == j) x = xj;
         else if (lane < j) x -= Dg[j + lane * DLD] * xj;
       }

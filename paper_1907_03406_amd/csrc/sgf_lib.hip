@@ -689,7 +689,7 @@ void run_sweeps(sgf_handle h, int nrhs, bool product, hipStream_t st) {
       launch(h, st, "apply_elim_fwd", 0, D.work.fwd_bytes + nrhs * D.work.fwd_vec, [&] {
         hipLaunchKernelGGL(sgf::k_apply_fwd<T>, dim3((unsigned)L.elim.size(), nrhs), dim3(sgf::WG), lds, st,
                            D.elim.as<sgf::ElimDesc>(), D.arena.as<T>(), D.slots.as<int32_t>(), y, n, ts, ldt);
-      });
+      }, L.t);
       return;
     }
     launch(h, st, "mul_elim", 0, D.work.fwd_bytes + nrhs * D.work.fwd_vec, [&] {
@@ -709,7 +709,7 @@ void run_sweeps(sgf_handle h, int nrhs, bool product, hipStream_t st) {
         hipLaunchKernelGGL(sgf::k_apply_bwd<T>, dim3((unsigned)L.elim.size(), nrhs), dim3(sgf::WG), lds, st,
                            D.elim.as<sgf::ElimDesc>(), D.arena.as<T>(), D.slots.as<int32_t>(),
                            D.nslots.as<int32_t>(), y, n);
-      });
+      }, L.t);
       return;
     }
     launch(h, st, "mul_elim_t", 0, D.work.bwd_bytes + nrhs * D.work.bwd_vec, [&] {
@@ -726,7 +726,7 @@ void run_sweeps(sgf_handle h, int nrhs, bool product, hipStream_t st) {
       hipLaunchKernelGGL(sgf::k_sepacc<T>, dim3((unsigned)L.sepacc.size(), nrhs), dim3(sgf::WG), 0, st,
                          D.sepacc.as<sgf::SepAcc>(), D.sepsrc.as<int64_t>(), D.slots.as<int32_t>(), ts, ldt, y, n,
                          sign);
-    });
+    }, L.t);
   };
   auto capply = [&](int li, int mode) {
     sgf::Level& L = P.levels[li];
@@ -739,7 +739,7 @@ void run_sweeps(sgf_handle h, int nrhs, bool product, hipStream_t st) {
         hipLaunchKernelGGL(sgf::k_comp_apply_t<T>, dim3((unsigned)L.capply.size(), nrhs), dim3(sgf::WG),
                            2 * ms * sizeof(T), st, D.capply.as<sgf::CompApply>(), D.tb.as<T>(),
                            D.slots.as<int32_t>(), y, n, mode);
-      });
+      }, L.t);
       return;
     }
     launch(h, st, "mul_comp", 0, 0, [&] {
@@ -767,7 +767,7 @@ void run_sweeps(sgf_handle h, int nrhs, bool product, hipStream_t st) {
         hipLaunchKernelGGL(sgf::k_top<T>, dim3(1, nrhs), dim3(sgf::WG), 2 * m * sizeof(T), st,
                            D.elim.as<sgf::ElimDesc>(), D.arena.as<T>(), D.slots.as<int32_t>(), y, n,
                            product ? 1 : 0);
-      });
+      }, L.t);
   }
   for (int li = nl - 2; li >= 0; --li) {
     if (!product) {

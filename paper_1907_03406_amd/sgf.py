@@ -197,7 +197,7 @@ class Solver:
 
     def profile_read(self):
         """{kernel class: dict(launches, ms, flops, bytes)} since profile()."""
-        cap = 64
+        cap = 1024
         arr = (KernelStat * cap)()
         cnt = ctypes.c_int32()
         _check(_lib.sgf_profile_read(self.h, arr, cap, ctypes.byref(cnt)))
