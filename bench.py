@@ -170,7 +170,18 @@ def main():
     ap.add_argument("--operators", type=int, default=2,
                     help="distinct coefficient fields (seeds seed, seed+1, ...) that the steps cycle through")
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a device-to-device copy of 1 GiB (reference for HBM byte counters)")
     a = ap.parse_args()
+    if a.copy_calibration:
+        import torch
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": src.numel() * 4, "launches": 3}))
+        return
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 (the multi-GPU sharding "
                                    "of the factor is a design note, not implemented)"}))
@@ -247,8 +258,8 @@ def main():
                             "factor_ms": round(float(np.mean(other["fac"])) * 1e3, 3),
                             "speedup_of_main_form": round(oms / ms, 3)}
     if not a.no_cpu_baseline:
-        sample = {"varcoef2d_1024": (256, 256), "poisson2d_64": (64, 64), "varcoef3d_128": (32, 32, 32),
-                  "elasticity3d_48": 12}[a.config]
+        sample = {"varcoef2d_1024": (512, 512), "poisson2d_64": (64, 64), "varcoef3d_128": (48, 48, 48),
+                  "elasticity3d_48": 16}[a.config]
         out["cpu_baseline"] = cpu_baseline(a.config, a.seed, sample)
     else:
         out["cpu_baseline"] = None
