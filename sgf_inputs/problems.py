@@ -211,23 +211,54 @@ def elasticity_q1(nodes, seed=0, n_incl=20, r_lo=0.05, r_hi=0.15, E0=1.0,
         E[inside] = E1
     lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu))
     mu = E / (2.0 * (1.0 + nu))
-    # full-grid node ids of the 8 element corners (x fastest)
-    corner = np.empty((ex.shape[0], 8), dtype=np.int64)
-    for k in range(8):
-        bx, by, bz = k & 1, (k >> 1) & 1, (k >> 2) & 1
-        corner[:, k] = (ex + bx) + N * ((ey + by) + N * (ez + bz))
+    # Node-block assembly: G[p, o] is the 3x3 coupling of full-grid node p
+    # with its neighbour at offset o (27 offsets, (dz, dy, dx) lexicographic,
+    # so neighbours come in ascending node id).  For a fixed corner pair (a, b)
+    # every element hits a different node, so each scatter-add is collision-free.
+    NN = N ** 3
+    G = np.zeros((N, N, N, 27, 3, 3))     # (z, y, x) node, offset, comps
+    bit = np.array([[k & 1, (k >> 1) & 1, (k >> 2) & 1] for k in range(8)])
+    lam3 = lam.reshape(ne, ne, ne)[..., None, None]
+    mu3 = mu.reshape(ne, ne, ne)[..., None, None]
+    for a in range(8):
+        bx, by, bz = bit[a]
+        for b in range(8):
+            d = bit[b] - bit[a]
+            o = (d[0] + 1) + 3 * (d[1] + 1) + 9 * (d[2] + 1)
+            G[bz:bz + ne, by:by + ne, bx:bx + ne, o] += (lam3 * Kl[3 * a:3 * a + 3, 3 * b:3 * b + 3]
+                                                       + mu3 * Km[3 * a:3 * a + 3, 3 * b:3 * b + 3])
+    G = G.reshape(NN, 27, 3, 3)
     # free numbering: drop ix = 0, free id = (ix - 1) + (N - 1) * (iy + N * iz)
-    full = np.arange(N ** 3)
-    ix, rest = full % N, full // N
-    free_id = np.where(ix > 0, (ix - 1) + (N - 1) * rest, -1)
-    dof = 3 * free_id[corner][:, :, None] + np.arange(3)[None, None, :]
-    dof = np.where(free_id[corner][:, :, None] >= 0, dof, -1).reshape(-1, 24)
+    full = np.arange(NN)
+    ix, iy, iz = full % N, (full // N) % N, full // (N * N)
+    free_id = np.where(ix > 0, (ix - 1) + (N - 1) * (iy + N * iz), -1)
+    off = np.array([(dx, dy, dz) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)])
+    qx = ix[:, None] + off[None, :, 0]
+    qy = iy[:, None] + off[None, :, 1]
+    qz = iz[:, None] + off[None, :, 2]
+    ok = (qx >= 1) & (qx < N) & (qy >= 0) & (qy < N) & (qz >= 0) & (qz < N) & (ix[:, None] > 0)
+    q = np.where(ok, qx + N * (qy + N * qz), 0)
+    fn = np.nonzero(ix > 0)[0]            # full ids of the free nodes, in free order
+    okf = ok[fn]
+    cnt = okf.sum(axis=1)
     n = 3 * (N - 1) * N * N
-    Ke = lam[:, None, None] * Kl[None] + mu[:, None, None] * Km[None]
-    R = np.broadcast_to(dof[:, :, None], Ke.shape)
-    C = np.broadcast_to(dof[:, None, :], Ke.shape)
-    keep = (R >= 0) & (C >= 0)
-    indptr, indices, data = _to_csr(R[keep], C[keep], Ke[keep], n)
+    indptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.repeat(3 * cnt, 3), out=indptr[1:])
+    # valid (node, offset) pairs, offsets ascending per node; j = rank of the pair in its row
+    pp, oo = np.nonzero(okf)
+    first = np.zeros(okf.shape[0] + 1, dtype=np.int64)
+    np.cumsum(cnt, out=first[1:])
+    j = np.arange(pp.shape[0]) - first[pp]
+    col0 = 3 * free_id[q[fn[pp], oo]]
+    blk = G[fn[pp], oo]                   # (M, 3, 3): [row comp, col comp]
+    start = indptr[3 * pp]
+    c = np.arange(3)
+    dest = (start[:, None, None] + c[None, :, None] * (3 * cnt[pp])[:, None, None]
+            + 3 * j[:, None, None] + c[None, None, :])
+    indices = np.empty(indptr[-1], dtype=np.int32)
+    data = np.empty(indptr[-1], dtype=np.float64)
+    indices[dest] = (col0[:, None, None] + c[None, None, :]).astype(np.int32)
+    data[dest] = blk
     gx = np.arange(1, N) * h
     gy = np.arange(N) * h
     Z, Y, X = np.meshgrid(gy, gy, gx, indexing="ij")
