@@ -65,6 +65,11 @@ typedef struct {
   int32_t compress_from_level; /* first level whose separators are compressed (1) */
   int32_t stop_rule;           /* SGF_STOP_ROOT (default) or SGF_STOP_PAPER        */
   int32_t precision;           /* SGF_FP64 (default) or SGF_FP32                   */
+  int32_t tiled_min_rows;      /* levels whose largest front has at least this many
+                                  rows are eliminated by the tiled multi-workgroup
+                                  path (0: every level); < 0 selects the built-in
+                                  threshold.  Fronts that do not fit one
+                                  workgroup's LDS panel always take it.           */
   double rank_tol;             /* pivoted-QR rank threshold relative to |R_00|;
                                   <= 0 selects 1e-12 (FP64) / 1e-6 (FP32)         */
 } sgf_options;
@@ -83,7 +88,8 @@ typedef struct {
 } sgf_info;
 
 /* Fills *opt with the defaults: scheme NEST_ALL_ALL, compress 1, compress
- * from level 1, stop ROOT, FP64, rank_tol 0 (automatic), q 1, leaf 8. */
+ * from level 1, stop ROOT, FP64, tiled_min_rows -1 (automatic), rank_tol 0
+ * (automatic), q 1, leaf 8. */
 void sgf_default_options(sgf_options* opt);
 
 /*

@@ -494,8 +494,10 @@ template <typename T, int PNB, bool NLDS>
 __global__ __launch_bounds__(WG) void k_compress(const CompDesc* __restrict__ D, const CompNbr* __restrict__ NB,
                                                  T* __restrict__ cf, T* __restrict__ nbuf, T* __restrict__ phi,
                                                  T* __restrict__ ltphi, T* __restrict__ tau_all,
-                                                 int* __restrict__ rank, int pi, double rank_tol, int* fail) {
+                                                 int* __restrict__ rank, int pi, double rank_tol, int* fail,
+                                                 int prefactored) {
   // Phi of the neighbours is read here and must not change during the launch.
+  // With `prefactored`, L_B and L_B^{-1} M_BX are already in the front.
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* lds = reinterpret_cast<T*>(smem_raw);
   __shared__ int sh_int[2];
@@ -504,7 +506,8 @@ __global__ __launch_bounds__(WG) void k_compress(const CompDesc* __restrict__ D,
   const int s = d.s, c = d.c;
   const int64_t ld = s + d.K;
   T* F = cf + d.cf_off;
-  wg_potrf<T, PNB, false>(F, ld, s + d.K, s, s, lds, fail, d.cluster);
+  if (!prefactored) wg_potrf<T, PNB, false>(F, ld, s + d.K, s, s, lds, fail, d.cluster);
+  __syncthreads();
   T* Ng = nbuf + d.n_off;
   T* nrm = lds;
   T* N = NLDS ? lds + ((c + 3) & ~3) : Ng;
@@ -989,20 +992,21 @@ __global__ __launch_bounds__(WG) void k_comp_apply_t(const CompApply* __restrict
   for (int i = threadIdx.x; i < s; i += WG) yv[sl[i]] = out[i];
 }
 
-// Top node: mode 0: y <- L^{-T} L^{-1} y; mode 1: y <- L L^T y.
-template <typename T>
-__global__ __launch_bounds__(WG) void k_top(const ElimDesc* __restrict__ D, const T* __restrict__ arena,
-                                            const int32_t* __restrict__ slots, T* __restrict__ y, int64_t ldy,
+// Top node (factor in TF, sweep vectors in TV): mode 0: y <- L^{-T} L^{-1} y;
+// mode 1: y <- L L^T y.
+template <typename TV, typename T>
+__global__ __launch_bounds__(WG) void k_top(const ElimDesc* __restrict__ D, const T* __restrict__ fac,
+                                            const int32_t* __restrict__ slots, TV* __restrict__ y, int64_t ldy,
                                             int mode) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* ys = reinterpret_cast<T*>(smem_raw);
   const ElimDesc d = D[0];
   const int m = d.m;
   T* tmp = ys + m;
-  const T* L = arena + d.front_off;
-  T* yv = y + blockIdx.y * ldy;
+  const T* L = fac + d.front_off;
+  TV* yv = y + blockIdx.y * ldy;
   const int32_t* sl = slots + d.slot_off;
-  for (int i = threadIdx.x; i < m; i += WG) ys[i] = yv[sl[i]];
+  for (int i = threadIdx.x; i < m; i += WG) ys[i] = (T)yv[sl[i]];
   __syncthreads();
   if (mode == 0) {
     wg_trsv_lower(L, m, m, ys);
@@ -1023,7 +1027,7 @@ __global__ __launch_bounds__(WG) void k_top(const ElimDesc* __restrict__ D, cons
     }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < m; i += WG) yv[sl[i]] = ys[i];
+  for (int i = threadIdx.x; i < m; i += WG) yv[sl[i]] = (TV)ys[i];
 }
 
 // Permutation between the caller's unknown order and the slot order.

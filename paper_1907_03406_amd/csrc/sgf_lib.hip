@@ -16,6 +16,7 @@
 #include "sgf.h"
 #include "sgf_kernels.hpp"
 #include "sgf_plan.hpp"
+#include "sgf_tiled.hpp"
 
 namespace {
 
@@ -98,6 +99,12 @@ struct LevelDev {
   std::vector<sgf::CopyDesc> h_blkmap, h_phimap;
   LevelWork work;
   bool uploaded = false;   // descriptor tables on the device match the plan
+  // tiled elimination (large fronts): descriptors, Zt = L_II^{-T}, apply work vector
+  bool tiled = false, comp_tiled = false;
+  DevBuf tf, zt, uw, ctf;
+  std::vector<sgf::TFront> h_tf, h_ctf;
+  int64_t z_elems = 0, u_elems = 0;
+  int tmax_m = 0, tmax_k = 0, tmax_rm = 0;
 };
 
 struct Profiler {
@@ -202,6 +209,14 @@ struct sgf_handle_s {
   int64_t max_t = 0;
   int32_t max_m_all = 0, max_k_all = 0, max_s_all = 0;
   int32_t failed_cluster = -1, failed_level = -1;
+  int32_t tiled_rows = 1024;   // levels whose largest front has this many rows go tiled
+  // top node, always factored in FP64: front copy / Cholesky factor, and for
+  // the tiled form Zt = L^{-T} and the apply work vector
+  DevBuf top64, topz, topu, d_topdesc, d_toptf;
+  std::vector<sgf::ElimDesc> h_topdesc;
+  std::vector<sgf::TFront> h_toptf;
+  bool top_tiled = false;
+  int32_t top_R = 0;
   double factor_flops = 0, apply_bytes = 0;
   int64_t factor_entries = 0, factor_bytes = 0, compressed = 0;
   Profiler prof;
@@ -319,6 +334,53 @@ void ensure_static(sgf_handle h, hipStream_t st) {
   h->dev_static = true;
 }
 
+// Whether the interiors of level L are eliminated by the tiled multi-workgroup
+// path: fronts at or above the row threshold, or too large for the LDS panel
+// of the one-workgroup-per-front kernel.
+bool level_tiled(sgf_handle h, const sgf::Level& L) {
+  if (L.top || L.elim.empty()) return false;
+  if (L.max_front_rows >= h->tiled_rows) return true;
+  int max_m = 0;
+  for (const auto& e : L.elim) max_m = std::max(max_m, e.m);
+  try {
+    (void)nb_for(L.max_front_rows, max_m, h->esz);
+  } catch (const SgfError&) {
+    return true;
+  }
+  return false;
+}
+
+// Descriptors and buffers of a tiled level: Zt (m x m per front) and the
+// apply work vector (m per front and right-hand side).
+void build_tiled(sgf_handle h, const sgf::Level& L, LevelDev& D, hipStream_t st) {
+  D.h_tf.clear();
+  D.z_elems = D.u_elems = 0;
+  D.tmax_m = D.tmax_k = D.tmax_rm = 0;
+  for (const auto& e : L.elim) {
+    sgf::TFront f{};
+    f.f_off = e.front_off;
+    f.z_off = D.z_elems;
+    f.u_off = D.u_elems;
+    f.slot_off = e.slot_off;
+    f.nslot_off = e.nslot_off;
+    f.t_off = e.t_off;
+    f.R = e.m + e.k;
+    f.m = e.m;
+    f.cluster = e.cluster;
+    f.zrows = e.m;
+    D.z_elems += (int64_t)e.m * e.m;
+    D.u_elems += e.m;
+    D.tmax_m = std::max(D.tmax_m, e.m);
+    D.tmax_k = std::max(D.tmax_k, e.k);
+    D.tmax_rm = std::max(D.tmax_rm, 2 * e.m + e.k);
+    D.h_tf.push_back(f);
+  }
+  if ((size_t)(((D.tmax_m + 3) & ~3) + sgf::WG) * h->esz > LDS_BYTES || (size_t)D.tmax_k * h->esz > LDS_BYTES)
+    throw SgfError(SGF_EINVAL, "front too large for the tiled apply kernels");
+  upload(D.tf, D.h_tf, st);
+  D.zt.ensure(std::max<int64_t>(D.z_elems, 1) * h->esz);
+}
+
 // Upload the descriptor tables of level index li and size its buffers.
 void upload_level(sgf_handle h, int li, hipStream_t st) {
   sgf::Level& L = h->plan.levels[li];
@@ -346,6 +408,39 @@ void upload_level(sgf_handle h, int li, hipStream_t st) {
   upload(D.nslots, L.nslots, st);
   upload(D.slotptr, L.slot_ptr, st);
   upload(D.phioff, L.phi_off, st);
+  D.tiled = level_tiled(h, L);
+  if (D.tiled) build_tiled(h, L, D, st);
+  // compression fronts [M_BB ; M_XB] too large for the one-workgroup panel:
+  // their Cholesky / triangular solve goes through the tiled kernels
+  D.comp_tiled = false;
+  if (!L.comp.empty()) {
+    int max_s = 0, max_rows = 0;
+    for (const auto& d : L.comp) {
+      max_s = std::max(max_s, d.s);
+      max_rows = std::max(max_rows, d.s + d.K);
+    }
+    D.comp_tiled = max_rows >= h->tiled_rows;
+    if (!D.comp_tiled) {
+      try {
+        (void)nb_for(max_rows, max_s, h->esz);
+      } catch (const SgfError&) {
+        D.comp_tiled = true;
+      }
+    }
+    if (D.comp_tiled) {
+      D.h_ctf.clear();
+      for (const auto& d : L.comp) {
+        sgf::TFront f{};
+        f.f_off = d.cf_off;
+        f.R = d.s + d.K;
+        f.m = d.s;
+        f.cluster = d.cluster;
+        f.zrows = 0;
+        D.h_ctf.push_back(f);
+      }
+      upload(D.ctf, D.h_ctf, st);
+    }
+  }
 }
 
 template <typename T>
@@ -404,6 +499,115 @@ void account_level(sgf_handle h, const sgf::Level& L, LevelWork& W) {
   h->factor_flops += W.elim_flops + W.comp_flops + W.pair_flops;
   h->apply_bytes += W.fwd_bytes + W.bwd_bytes + W.fwd_vec + W.bwd_vec + W.acc_vec * 2 + 2 * W.capply_bytes +
                     2 * W.capply_vec + W.top_bytes + W.top_vec;
+}
+
+// Tiled elimination of the fronts `tf` (factor buffer fb, Zt buffer zb): one
+// panel launch and one update launch per 64 eliminated columns, then the
+// Schur contraction.  Flops are attributed per launch from the front sizes.
+template <typename T>
+void tiled_factor(sgf_handle h, hipStream_t st, const std::vector<sgf::TFront>& tf, const sgf::TFront* dtf, T* fb,
+                  T* zb, int level, const char* kind, bool schur = true) {
+  const unsigned nf = (unsigned)tf.size();
+  if (nf == 0) return;
+  int max_m = 0, max_rm = 0;
+  double zelems = 0;
+  for (const auto& f : tf) {
+    max_m = std::max(max_m, f.m);
+    max_rm = std::max(max_rm, f.R + f.zrows);
+    zelems += (double)f.zrows * f.m;
+  }
+  const double e = sizeof(T);
+  const std::string k(kind);
+  const std::string n_init = k + "_zinit", n_panel = k + "_panel", n_upd = k + "_update", n_schur = k + "_schur";
+  if (zelems > 0)
+    launch(h, st, n_init.c_str(), 0, zelems * e, [&] {
+      hipLaunchKernelGGL(sgf::k_tinit<T>, dim3(std::min<unsigned>(cdiv(max_m * (int64_t)max_m, sgf::WG), 1024), nf),
+                         dim3(sgf::WG), 0, st, dtf, zb);
+    }, level);
+  const unsigned g1 = cdiv(max_rm, sgf::TROWS);
+  for (int p = 0; p * sgf::TB < max_m; ++p) {
+    const int c0 = p * sgf::TB;
+    double pfl = 0, ufl = 0;
+    unsigned g2 = 0;
+    for (const auto& f : tf) {
+      if (c0 >= f.m) continue;
+      const double w = std::min(sgf::TB, f.m - c0);
+      pfl += w * w * w / 3.0 + (double)(f.R - c0 - w) * w * w;
+      const int c1 = c0 + sgf::TB;
+      if (c1 < f.m) {
+        const int nj = (int)cdiv(f.m, sgf::TB) - p - 1, nrt = (int)cdiv(f.R, sgf::TB) + (f.zrows > 0 ? p + 1 : 0);
+        g2 = std::max<unsigned>(g2, (unsigned)(nj * nrt));
+        const double cols = f.m - c1, rows = f.R - c1;
+        ufl += 2.0 * sgf::TB * (rows * cols - cols * cols / 2.0);
+      }
+    }
+    launch(h, st, n_panel.c_str(), 0, 0, [&] {
+      hipLaunchKernelGGL(sgf::k_tdiag<T>, dim3(nf), dim3(sgf::WAVE), 0, st, dtf, p, fb, h->d_fail.as<int>());
+    }, level);
+    launch(h, st, n_panel.c_str(), pfl, 0, [&] {
+      hipLaunchKernelGGL(sgf::k_tpanel<T>, dim3(g1, nf), dim3(sgf::WG), 0, st, dtf, p, fb, zb);
+    }, level);
+    if (g2)
+      launch(h, st, n_upd.c_str(), ufl, 0, [&] {
+        hipLaunchKernelGGL(sgf::k_tupdate<T>, dim3(g2, nf), dim3(sgf::WG), 0, st, dtf, p, fb, zb);
+      }, level);
+  }
+  unsigned g3 = 0;
+  double sfl = 0;
+  for (const auto& f : tf) {
+    const int k = f.R - f.m, nst = (int)cdiv(k, sgf::TB);
+    g3 = std::max<unsigned>(g3, (unsigned)(nst * nst));
+    sfl += (double)k * k * f.m;
+  }
+  if (g3 && schur)
+    launch(h, st, n_schur.c_str(), sfl, 0, [&] {
+      hipLaunchKernelGGL(sgf::k_tschur<T>, dim3(g3, nf), dim3(sgf::WG), 0, st, dtf, fb);
+    }, level);
+}
+
+// The top node is always factored in FP64 (from a copy of its front), by
+// one workgroup when small, else by the tiled path, which also forms Zt.
+template <typename T>
+void factor_top(sgf_handle h, const sgf::Level& L, LevelDev& D, hipStream_t st) {
+  const sgf::ElimDesc& e0 = L.elim[0];
+  const int R = e0.m;
+  h->top_R = R;
+  h->top_tiled = false;
+  if (R == 0) return;
+  const int64_t RR = (int64_t)R * R;
+  h->top64.ensure(RR * sizeof(double));
+  launch(h, st, "top_convert", 0, RR * (8.0 + sizeof(T)), [&] {
+    hipLaunchKernelGGL((sgf::k_convert<T, double>), dim3(std::min<unsigned>(cdiv(RR, sgf::WG), 4096)), dim3(sgf::WG),
+                       0, st, D.arena.as<T>() + e0.front_off, h->top64.as<double>(), RR);
+  }, L.t);
+  h->h_topdesc.assign(1, e0);
+  h->h_topdesc[0].front_off = 0;
+  upload(h->d_topdesc, h->h_topdesc, st);
+  h->top_tiled = R > 256 || R >= h->tiled_rows;
+  if (h->top_tiled) {
+    if ((size_t)(((R + 3) & ~3) + sgf::WG) * sizeof(double) > LDS_BYTES)
+      throw SgfError(SGF_EINVAL, "top node of " + std::to_string(R) + " rows is too large for the tiled apply");
+    sgf::TFront f{};
+    f.zrows = R;
+    f.slot_off = e0.slot_off;
+    f.nslot_off = e0.nslot_off;
+    f.t_off = e0.t_off;
+    f.R = R;
+    f.m = R;
+    f.cluster = e0.cluster;
+    h->h_toptf.assign(1, f);
+    upload(h->d_toptf, h->h_toptf, st);
+    h->topz.ensure(RR * sizeof(double));
+    tiled_factor<double>(h, st, h->h_toptf, h->d_toptf.as<sgf::TFront>(), h->top64.as<double>(),
+                         h->topz.as<double>(), L.t, "top");
+  } else {
+    const int nb = nb_for(R, R, sizeof(double));
+    const size_t lds = (size_t)sgf::potrf_lds_elems(R, nb) * sizeof(double);
+    launch(h, st, "top_chol", (double)R * R * R / 3.0, 0, [&] {
+      launch_elim<double>(nb, 1, lds, st, h->d_topdesc.as<sgf::ElimDesc>(), h->top64.as<double>(),
+                          h->d_fail.as<int>());
+    }, L.t);
+  }
 }
 
 template <typename T>
@@ -473,7 +677,11 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
     double lvl_elim_flops = 0;
     for (const auto& d : L.elim) lvl_elim_flops += (double)d.m * d.m * d.m / 3.0 + (double)d.m * d.m * d.k +
                                                    (double)d.m * d.k * d.k;
-    if (!L.elim.empty()) {
+    if (L.top) {
+      factor_top<T>(h, L, D, st);
+    } else if (D.tiled) {
+      tiled_factor<T>(h, st, D.h_tf, D.tf.as<sgf::TFront>(), arena, D.zt.as<T>(), L.t, "elim");
+    } else if (!L.elim.empty()) {
       int max_m = 0;
       for (const auto& e : L.elim) max_m = std::max(max_m, e.m);
       int nb = nb_for(L.max_front_rows, max_m, sizeof(T));
@@ -512,13 +720,22 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
       for (const auto& d : L.comp) n_lds = std::max<int64_t>(n_lds, (int64_t)d.s * d.c + ((d.c + 3) & ~3));
       const bool nlds = (size_t)n_lds * sizeof(T) <= LDS_BYTES;
       const int64_t extra = nlds ? n_lds : L.max_c;
-      int nb = nb_for(L.max_cf_rows, L.max_s, sizeof(T), extra);
-      size_t lds = std::max<size_t>(sgf::potrf_lds_elems(L.max_cf_rows, nb), (size_t)extra) * sizeof(T);
+      int nb = 4;
+      size_t lds = (size_t)extra * sizeof(T);
+      if (D.comp_tiled) {
+        // L_B and L_B^{-1} M_BX of every front by the tiled kernels first
+        tiled_factor<T>(h, st, D.h_ctf, D.ctf.as<sgf::TFront>(), D.cf.as<T>(), nullptr, L.t, "comp", false);
+      } else {
+        nb = nb_for(L.max_cf_rows, L.max_s, sizeof(T), extra);
+        lds = std::max<size_t>(sgf::potrf_lds_elems(L.max_cf_rows, nb), (size_t)extra) * sizeof(T);
+      }
+      if (lds > LDS_BYTES) throw SgfError(SGF_EINVAL, "compression kernel needs more LDS than available");
       double tol = P.opt.rank_tol;
+      const int pre = D.comp_tiled ? 1 : 0;
       launch(h, st, "compress", 0, 0, [&] {
         launch_compress<T>(nlds, nb, (unsigned)L.comp.size(), lds, st, D.comp.as<sgf::CompDesc>(),
                            D.compnbr.as<sgf::CompNbr>(), D.cf.as<T>(), D.nbuf.as<T>(), D.phi.as<T>(), D.ltphi.as<T>(),
-                           D.tau.as<T>(), D.rank.as<int>(), P.pi, tol, h->d_fail.as<int>());
+                           D.tau.as<T>(), D.rank.as<int>(), P.pi, tol, h->d_fail.as<int>(), pre);
       }, L.t);
       launch(h, st, "phi_commit", 0, 0, [&] {
         hipLaunchKernelGGL(sgf::k_phi_commit<T>, dim3((unsigned)L.comp.size()), dim3(sgf::WG), 0, st,
@@ -648,7 +865,9 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
   for (size_t li = 0; li < P.levels.size(); ++li) {
     const auto& D = h->lev[li];
     h->factor_bytes += D.arena.bytes + D.cf.bytes + D.nbuf.bytes + D.tau.bytes + D.tb.bytes;
+    if (D.tiled) h->factor_bytes += D.zt.bytes;
   }
+  h->factor_bytes += h->top64.bytes + (h->top_tiled ? h->topz.bytes : 0);
   const auto& top = P.levels.back().elim[0];
   h->max_m_all = std::max(h->max_m_all, top.m);
   int64_t n = P.n;
@@ -659,6 +878,9 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
 template <typename T>
 void ensure_work(sgf_handle h, int nrhs) {
   h->y.ensure((size_t)h->plan.n * nrhs * sizeof(T));
+  for (auto& D : h->lev)
+    if (D.tiled && D.uploaded) D.uw.ensure((size_t)std::max<int64_t>(D.u_elems, 1) * nrhs * sizeof(T));
+  if (h->top_tiled) h->topu.ensure((size_t)h->top_R * nrhs * sizeof(double));
   h->tscr.ensure((size_t)std::max<int64_t>(h->max_t, 1) * nrhs * sizeof(T));
 }
 
@@ -684,6 +906,22 @@ void run_sweeps(sgf_handle h, int nrhs, bool product, hipStream_t st) {
     int mm, mk, ms;
     maxes(L, mm, mk, ms);
     if (L.elim.empty()) return;
+    if (mode == 0 && D.tiled) {
+      const unsigned nf = (unsigned)D.h_tf.size();
+      const double half = 0.5 * (D.work.fwd_bytes + nrhs * D.work.fwd_vec);
+      launch(h, st, "apply_elim_fwd", 0, half, [&] {
+        hipLaunchKernelGGL((sgf::k_tfwd_z<T, T>), dim3(cdiv(D.tmax_m, sgf::TB), nf, nrhs), dim3(sgf::WG),
+                           (size_t)D.tmax_m * sizeof(T), st, D.tf.as<sgf::TFront>(), D.zt.as<T>(),
+                           D.slots.as<int32_t>(), y, n, D.uw.as<T>(), D.u_elems);
+      }, L.t);
+      launch(h, st, "apply_elim_fwd", 0, half, [&] {
+        hipLaunchKernelGGL((sgf::k_tfwd_s<T, T>), dim3(std::max(1u, cdiv(D.tmax_k, sgf::TB)), nf, nrhs),
+                           dim3(sgf::WG), (size_t)(((D.tmax_m + 3) & ~3) + sgf::WG) * sizeof(T), st,
+                           D.tf.as<sgf::TFront>(), D.arena.as<T>(), D.uw.as<T>(), D.u_elems, D.slots.as<int32_t>(),
+                           y, n, ts, ldt);
+      }, L.t);
+      return;
+    }
     if (mode == 0) {
       const size_t lds = ((size_t)sgf::DB * sgf::DLD + L.max_front_rows) * sizeof(T);
       launch(h, st, "apply_elim_fwd", 0, D.work.fwd_bytes + nrhs * D.work.fwd_vec, [&] {
@@ -703,6 +941,21 @@ void run_sweeps(sgf_handle h, int nrhs, bool product, hipStream_t st) {
     int mm, mk, ms;
     maxes(L, mm, mk, ms);
     if (L.elim.empty()) return;
+    if (mode == 0 && D.tiled) {
+      const unsigned nf = (unsigned)D.h_tf.size();
+      const double half = 0.5 * (D.work.bwd_bytes + nrhs * D.work.bwd_vec);
+      launch(h, st, "apply_elim_bwd", 0, half, [&] {
+        hipLaunchKernelGGL((sgf::k_tbwd_s<T, T>), dim3(cdiv(D.tmax_m, sgf::TB), nf, nrhs), dim3(sgf::WG),
+                           (size_t)std::max(D.tmax_k, 1) * sizeof(T), st, D.tf.as<sgf::TFront>(), D.arena.as<T>(),
+                           D.slots.as<int32_t>(), D.nslots.as<int32_t>(), y, n, D.uw.as<T>(), D.u_elems);
+      }, L.t);
+      launch(h, st, "apply_elim_bwd", 0, half, [&] {
+        hipLaunchKernelGGL((sgf::k_tbwd_z<T, T>), dim3(cdiv(D.tmax_m, sgf::TB), nf, nrhs), dim3(sgf::WG),
+                           (size_t)(((D.tmax_m + 3) & ~3) + sgf::WG) * sizeof(T), st, D.tf.as<sgf::TFront>(),
+                           D.zt.as<T>(), D.uw.as<T>(), D.u_elems, D.slots.as<int32_t>(), y, n);
+      }, L.t);
+      return;
+    }
     if (mode == 0) {
       const size_t lds = ((size_t)sgf::DB * sgf::DLD + L.max_front_rows) * sizeof(T);
       launch(h, st, "apply_elim_bwd", 0, D.work.bwd_bytes + nrhs * D.work.bwd_vec, [&] {
@@ -761,13 +1014,28 @@ void run_sweeps(sgf_handle h, int nrhs, bool product, hipStream_t st) {
   {
     sgf::Level& L = P.levels[nl - 1];
     LevelDev& D = h->lev[nl - 1];
-    int m = L.elim[0].m;
-    if (m > 0)
-      launch(h, st, "apply_top", 0, 2 * D.work.top_bytes + nrhs * D.work.top_vec, [&] {
-        hipLaunchKernelGGL(sgf::k_top<T>, dim3(1, nrhs), dim3(sgf::WG), 2 * m * sizeof(T), st,
-                           D.elim.as<sgf::ElimDesc>(), D.arena.as<T>(), D.slots.as<int32_t>(), y, n,
+    const int m = L.elim[0].m;
+    const double tb = 2 * D.work.top_bytes * 8.0 / sizeof(T) + nrhs * D.work.top_vec;
+    if (m > 0 && h->top_tiled && !product) {
+      launch(h, st, "apply_top", 0, 0.5 * tb, [&] {
+        hipLaunchKernelGGL((sgf::k_tfwd_z<T, double>), dim3(cdiv(m, sgf::TB), 1, nrhs), dim3(sgf::WG),
+                           (size_t)m * sizeof(double), st, h->d_toptf.as<sgf::TFront>(), h->topz.as<double>(),
+                           D.slots.as<int32_t>(), y, n, h->topu.as<double>(), (int64_t)m);
+      }, L.t);
+      launch(h, st, "apply_top", 0, 0.5 * tb, [&] {
+        hipLaunchKernelGGL((sgf::k_tbwd_z<T, double>), dim3(cdiv(m, sgf::TB), 1, nrhs), dim3(sgf::WG),
+                           (size_t)(((m + 3) & ~3) + sgf::WG) * sizeof(double), st, h->d_toptf.as<sgf::TFront>(),
+                           h->topz.as<double>(), h->topu.as<double>(), (int64_t)m, D.slots.as<int32_t>(), y, n);
+      }, L.t);
+    } else if (m > 0) {
+      if ((size_t)2 * m * sizeof(double) > LDS_BYTES)
+        throw SgfError(SGF_EINVAL, "top node too large for the one-workgroup top kernel");
+      launch(h, st, "apply_top", 0, tb, [&] {
+        hipLaunchKernelGGL((sgf::k_top<T, double>), dim3(1, nrhs), dim3(sgf::WG), 2 * m * sizeof(double), st,
+                           h->d_topdesc.as<sgf::ElimDesc>(), h->top64.as<double>(), D.slots.as<int32_t>(), y, n,
                            product ? 1 : 0);
       }, L.t);
+    }
   }
   for (int li = nl - 2; li >= 0; --li) {
     if (!product) {
@@ -839,6 +1107,7 @@ void sgf_default_options(sgf_options* o) {
   o->compress_from_level = 1;
   o->stop_rule = SGF_STOP_ROOT;
   o->precision = SGF_FP64;
+  o->tiled_min_rows = -1;
   o->rank_tol = 0.0;
 }
 
@@ -878,6 +1147,7 @@ sgf_status sgf_analyze(int64_t n, const int64_t* row_ptr, const int32_t* col_idx
     o.stop_rule = opt->stop_rule;
     o.precision = opt->precision;
     o.rank_tol = opt->rank_tol > 0 ? opt->rank_tol : (opt->precision == SGF_FP64 ? 1e-12 : 1e-6);
+    h->tiled_rows = opt->tiled_min_rows < 0 ? 1024 : opt->tiled_min_rows;
     h->esz = opt->precision == SGF_FP64 ? 8 : 4;
     h->plan.n = n;
     h->plan.n_nodes = n / o.dpn;

@@ -30,7 +30,8 @@ class Options(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("grid", ctypes.c_int32 * 3), ("dofs_per_node", ctypes.c_int32),
                 ("q", ctypes.c_int32), ("leaf", ctypes.c_int32), ("scheme", ctypes.c_int32),
                 ("compress", ctypes.c_int32), ("compress_from_level", ctypes.c_int32),
-                ("stop_rule", ctypes.c_int32), ("precision", ctypes.c_int32), ("rank_tol", ctypes.c_double)]
+                ("stop_rule", ctypes.c_int32), ("precision", ctypes.c_int32), ("tiled_min_rows", ctypes.c_int32),
+                ("rank_tol", ctypes.c_double)]
 
 
 class Info(ctypes.Structure):
@@ -93,7 +94,7 @@ def _check(code):
 
 
 def make_options(dim, grid, dofs_per_node=1, q=1, leaf=8, scheme=NEST_ALL_ALL, compress=True,
-                 compress_from_level=1, stop_rule=STOP_ROOT, precision=FP64, rank_tol=0.0):
+                 compress_from_level=1, stop_rule=STOP_ROOT, precision=FP64, rank_tol=0.0, tiled_min_rows=-1):
     o = Options()
     _lib.sgf_default_options(ctypes.byref(o))
     o.dim = dim
@@ -104,6 +105,7 @@ def make_options(dim, grid, dofs_per_node=1, q=1, leaf=8, scheme=NEST_ALL_ALL, c
     o.compress = 1 if compress else 0
     o.compress_from_level = compress_from_level
     o.stop_rule, o.precision, o.rank_tol = stop_rule, precision, rank_tol
+    o.tiled_min_rows = tiled_min_rows
     return o
 
 

@@ -56,13 +56,18 @@ def _rel(a, b):
 
 
 EXACT = [("const", (16, 16), 4, 1), ("fourier", (37, 29), 4, 2), ("blocky", (9, 8, 7), 2, 1),
-         ("const", (2, 2), 8, 1)]
+         ("const", (2, 2), 8, 1), ("blocky", (17, 16, 15), 8, 1)]
+
+# tiled_min_rows: -1 = built-in choice per level; 0 = every level (and the
+# top) through the tiled multi-workgroup elimination and its apply kernels
+TILED = (-1, 0)
 
 
 @pytest.mark.parametrize("kind,grid,leaf,q", EXACT)
-def test_exact_mode_is_the_inverse(kind, grid, leaf, q):
+@pytest.mark.parametrize("tiled", TILED)
+def test_exact_mode_is_the_inverse(kind, grid, leaf, q, tiled):
     p = _prob(kind, grid)
-    s = _gpu(p, q=q, leaf=leaf, compress=False)
+    s = _gpu(p, q=q, leaf=leaf, compress=False, tiled_min_rows=tiled)
     A = p.csr()
     b = P.random_rhs(0, p.n)
     x = _apply(s, b)
@@ -87,17 +92,18 @@ def _oracle(p, q, leaf):
 def test_factor_structure_and_operators_match_oracle(kind, grid, leaf, q):
     p = _prob(kind, grid)
     F = _oracle(p, q, leaf)
-    s = _gpu(p, q=q, leaf=leaf)
-    info = s.info()
-    assert info["levels"] == F.info["nlevels"]
-    assert info["top_size"] == F.info["top_size"]
-    for t in range(1, F.info["nlevels"]):
-        g = s.level(t)
-        post = F.info["sizes"][t - 1]
-        seps = g["type"] > 0
-        assert sorted(post) == g["cell"][seps].tolist()
-        assert [post[c] for c in g["cell"][seps]] == g["rank"][seps].tolist(), f"ranks differ at level {t}"
-    assert sum(1 for x in F.info["gap"] if x[3] < x[2]) == info["compressed"]
+    solvers = {t: _gpu(p, q=q, leaf=leaf, tiled_min_rows=t) for t in TILED}
+    for s in solvers.values():
+        info = s.info()
+        assert info["levels"] == F.info["nlevels"]
+        assert info["top_size"] == F.info["top_size"]
+        for t in range(1, F.info["nlevels"]):
+            g = s.level(t)
+            post = F.info["sizes"][t - 1]
+            seps = g["type"] > 0
+            assert sorted(post) == g["cell"][seps].tolist()
+            assert [post[c] for c in g["cell"][seps]] == g["rank"][seps].tolist(), f"ranks differ at level {t}"
+        assert sum(1 for x in F.info["gap"] if x[3] < x[2]) == info["compressed"]
     V = np.stack([P.random_rhs(7, p.n, j) for j in range(3)], axis=1)
     za, zm = O.apply_inverse(F, V), O.multiply(F, V)
     # The operator is defined only as well as the rank-truncated QRs define
@@ -118,11 +124,12 @@ def test_factor_structure_and_operators_match_oracle(kind, grid, leaf, q):
     dropped = max(x[5] for x in F.info["gap"])
     gapless = kept < 10 * dropped
     sub = 10 * np.finfo(float).eps / kept if gapless else 0.0
-    ea, em = _rel(_apply(s, V), za), _rel(_apply(s, V, product=True), zm)
-    print(f"{kind} {grid}: apply {ea:.1e} (oracle sens {sens_a:.1e}), product {em:.1e} (sens {sens_m:.1e}), "
-          f"kept>={kept:.1e} dropped<={dropped:.1e}{' gapless' if gapless else ''}")
-    assert ea <= max(1e-10, 100 * sens_a, sub)
-    assert em <= max(1e-10, 100 * sens_m, sub)
+    for tiled, s in solvers.items():
+        ea, em = _rel(_apply(s, V), za), _rel(_apply(s, V, product=True), zm)
+        print(f"{kind} {grid} tiled_min_rows {tiled}: apply {ea:.1e} (oracle sens {sens_a:.1e}), product {em:.1e} "
+              f"(sens {sens_m:.1e}), kept>={kept:.1e} dropped<={dropped:.1e}{' gapless' if gapless else ''}")
+        assert ea <= max(1e-10, 100 * sens_a, sub)
+        assert em <= max(1e-10, 100 * sens_m, sub)
 
 
 @pytest.mark.parametrize("kind,grid,leaf,q", PAR[:5])
@@ -135,9 +142,10 @@ def test_preservation_on_gpu(kind, grid, leaf, q):
     assert _rel(_apply(s, Pi, product=True), AP) <= 1e-10
 
 
-def test_rigid_body_modes_on_gpu():
+@pytest.mark.parametrize("tiled", TILED)
+def test_rigid_body_modes_on_gpu(tiled):
     e = _prob("elast", 10, seed=3)
-    s = _gpu(e, q=1, leaf=3)
+    s = _gpu(e, q=1, leaf=3, tiled_min_rows=tiled)
     assert s.info()["compressed"] > 0
     R = P.rigid_body_modes(e)
     AR = e.csr() @ R
@@ -145,15 +153,18 @@ def test_rigid_body_modes_on_gpu():
     assert _rel(_apply(s, R, product=True), AR) <= 1e-10
 
 
-@pytest.mark.parametrize("kind,grid,leaf,q,tol", [("const", (64, 64), 8, 1, 1e-10), ("fourier", (96, 80), 8, 2, 1e-8),
-                                                  ("blocky", (20, 20, 20), 4, 1, 1e-8)])
-def test_pcg_matches_oracle(kind, grid, leaf, q, tol):
+@pytest.mark.parametrize("kind,grid,leaf,q,tol,tiled", [("const", (64, 64), 8, 1, 1e-10, -1),
+                                                        ("fourier", (96, 80), 8, 2, 1e-8, -1),
+                                                        ("blocky", (20, 20, 20), 4, 1, 1e-8, -1),
+                                                        ("blocky", (20, 20, 20), 4, 1, 1e-8, 0),
+                                                        ("elast", 10, 3, 1, 1e-8, 0)])
+def test_pcg_matches_oracle(kind, grid, leaf, q, tol, tiled):
     p = _prob(kind, grid)
     A = p.csr()
     F = _oracle(p, q, leaf)
     b = P.random_rhs(0, p.n)
     xo, ito, _ = O.pcg(A, b, lambda r: O.apply_inverse(F, r), tol=tol)
-    s = _gpu(p, q=q, leaf=leaf)
+    s = _gpu(p, q=q, leaf=leaf, tiled_min_rows=tiled)
     xg = torch.zeros(p.n, dtype=torch.float64, device="cuda")
     it, rel = s.pcg(torch.from_numpy(b).cuda(), xg, rtol=tol)
     x = xg.cpu().numpy()
@@ -163,9 +174,10 @@ def test_pcg_matches_oracle(kind, grid, leaf, q, tol):
     assert np.linalg.norm(b - A @ x) / np.linalg.norm(b) < 10 * tol
 
 
-def test_multi_rhs_pcg_columns_are_independent():
+@pytest.mark.parametrize("tiled", TILED)
+def test_multi_rhs_pcg_columns_are_independent(tiled):
     p = _prob("fourier", (48, 48))
-    s = _gpu(p, q=1, leaf=4)
+    s = _gpu(p, q=1, leaf=4, tiled_min_rows=tiled)
     B = np.stack([P.random_rhs(3, p.n, j) for j in range(4)], axis=1)
     B[:, 2] = 0.0
     Bt = torch.from_numpy(np.ascontiguousarray(B.T)).cuda()
@@ -194,23 +206,24 @@ def test_refactorize_with_new_values_and_spmv():
     assert _rel(y.cpu().numpy(), p2.csr() @ v) <= 1e-15
 
 
-def test_not_spd_reports_cluster():
+@pytest.mark.parametrize("tiled", TILED)
+def test_not_spd_reports_cluster(tiled):
     p = _prob("const", (16, 16))
     bad = p.data.copy()
     A = p.csr()
     # make one interior diagonal entry negative
     i = 0
     bad[A.indptr[i]:A.indptr[i + 1]][A.indices[A.indptr[i]:A.indptr[i + 1]] == i] = -4.0
-    s = sgf.Solver.from_problem(p, q=1, leaf=4)
+    s = sgf.Solver.from_problem(p, q=1, leaf=4, tiled_min_rows=tiled)
     with pytest.raises(sgf.SgfError) as ei:
         s.factorize(torch.from_numpy(bad).cuda())
     assert ei.value.code == sgf.SGF_ENOTSPD
     assert s.info()["failed_level"] == 1
 
 
-@pytest.mark.parametrize("kind,grid,leaf,q", [("fourier", (128, 128), 16, 2), ("blocky", (24, 24, 24), 8, 1),
-                                              ("elast", 12, 3, 1)])
-def test_fp32_form_reaches_fp64_accuracy(kind, grid, leaf, q):
+@pytest.mark.parametrize("kind,grid,leaf,q,tiled", [("fourier", (128, 128), 16, 2, -1), ("blocky", (24, 24, 24), 8, 1, -1),
+                                                    ("elast", 12, 3, 1, -1), ("blocky", (24, 24, 24), 8, 1, 0)])
+def test_fp32_form_reaches_fp64_accuracy(kind, grid, leaf, q, tiled):
     """Precision form: FP32 factor and apply inside FP64 CG.  CG must still
     reach a true FP64 relative residual below 2e-8, with a bounded increase
     of the iteration count; the distance to the FP64 solution is reported."""
@@ -220,7 +233,7 @@ def test_fp32_form_reaches_fp64_accuracy(kind, grid, leaf, q):
     bt = torch.from_numpy(b).cuda()
     out = {}
     for prec in (sgf.FP64, sgf.FP32):
-        s = _gpu(p, q=q, leaf=leaf, precision=prec)
+        s = _gpu(p, q=q, leaf=leaf, precision=prec, tiled_min_rows=tiled)
         x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
         it, rel = s.pcg(bt, x, rtol=1e-8)
         out[prec] = (int(it[0]), x.cpu().numpy())
