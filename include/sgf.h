@@ -130,6 +130,23 @@ sgf_status sgf_factorize(int64_t n, const int64_t* row_ptr, const int32_t* col_i
                          const sgf_options* opt, void* stream, sgf_handle* out);
 
 /*
+ * Autotuner of the batched elimination (one launch per level over clusters
+ * of uneven sizes): factorizes `vals` once per candidate -- the tiled
+ * multi-workgroup path and the one-workgroup-per-front path with panel
+ * widths 8, 16 and 32 -- and applies the result once, timing every level's
+ * elimination plus `napply` times its forward and backward apply kernels
+ * with device events; each level then keeps its fastest candidate.
+ *   vals       DEVICE double[nnz] (as for sgf_factorize_numeric)
+ *   napply     weight of the apply (expected applies per factorization)
+ *   modes_out  HOST int32[levels] or NULL: chosen candidate per level
+ *              (0 tiled, 8/16/32 panel width, -1 no interiors)
+ * Leaves the handle unfactored: call sgf_factorize_numeric next.  The choice
+ * persists for later factorizations of the handle.
+ */
+sgf_status sgf_autotune(sgf_handle h, const double* vals, int32_t napply, int32_t* modes_out,
+                        void* stream);
+
+/*
  * z = A_l^{-1} r (Sec. 4.7): forward sweep G_1^{-1}, B_1^{-1}, ..., exact top
  * solve, backward sweep with the transposes.  r and z are DEVICE FP64
  * column-major n x nrhs with leading dimensions ldr, ldz >= n; r == z is
@@ -201,7 +218,17 @@ typedef struct {
   int64_t launches;
   double ms;      /* summed event time of the launches                  */
   double flops;   /* summed algorithmic flops                            */
-  double bytes;   /* summed algorithmic bytes                            */
+  double bytes;   /*
+ * The apply sweep (permutation, all levels' kernels, top) is captured once
+ * as a HIP graph on a private stream and replayed on the caller's stream
+ * while its arguments (nrhs, r, ldr, z, ldz) and the factorization stay the
+ * same -- as they do inside sgf_pcg_solve.  enable = 0 launches every kernel
+ * directly (per-kernel profiling needs this) and keeps the captured graph
+ * for when it is enabled again; default 1.
+ */
+sgf_status sgf_set_apply_graph(sgf_handle h, int32_t enable);
+
+/* summed algorithmic bytes                            */
 } sgf_kernel_stat;
 sgf_status sgf_profile_enable(sgf_handle h, int32_t enable);
 sgf_status sgf_profile_read(sgf_handle h, sgf_kernel_stat* out, int32_t cap, int32_t* count);

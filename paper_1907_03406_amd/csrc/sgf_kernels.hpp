@@ -841,68 +841,94 @@ __device__ __forceinline__ void stage_diag(const T* __restrict__ C, int64_t ld, 
   }
 }
 
-// Forward sweep of one interior: y_I <- L^{-1} y_I, t <- W^T y_I.
-template <typename T>
+// Right-hand sides per workgroup in the apply kernels: the factor is read
+// once for up to RCM columns (grid.y = ceil(nrhs / rc)).
+constexpr int RCM = 4;
+
+// Forward sweep of one interior: y_I <- L^{-1} y_I, t <- W^T y_I, for rc
+// right-hand sides (columns blockIdx.y * rc ...) at once: the triangular
+// chains of the columns run on different wavefronts, the block products
+// share each factor load.
+template <typename T, int RC>
 __global__ __launch_bounds__(WG) void k_apply_fwd(const ElimDesc* __restrict__ D, const T* __restrict__ arena,
                                                   const int32_t* __restrict__ slots, T* __restrict__ y, int64_t ldy,
-                                                  T* __restrict__ tscr, int64_t ldt) {
+                                                  T* __restrict__ tscr, int64_t ldt, int nrhs) {
+  constexpr int rc = RC;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* Dg = reinterpret_cast<T*>(smem_raw);
   T* v = Dg + DB * DLD;
   const ElimDesc d = D[blockIdx.x];
-  const int m = d.m, k = d.k, R = m + k;
+  const int m = d.m, k = d.k, R = m + k, Rp = (R + 3) & ~3;
+  const int c0 = blockIdx.y * rc, nc = min(rc, nrhs - c0);
   const T* C = arena + d.front_off;
-  T* yv = y + blockIdx.y * ldy;
   const int32_t* sl = slots + d.slot_off;
-  for (int i = threadIdx.x; i < R; i += WG) v[i] = i < m ? yv[sl[i]] : T(0);
+  for (int idx = threadIdx.x; idx < R * nc; idx += WG) {
+    const int i = idx % R, c = idx / R;
+    v[i + c * Rp] = i < m ? y[(int64_t)(c0 + c) * ldy + sl[i]] : T(0);
+  }
   const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
   for (int jb = 0; jb < m; jb += DB) {
     const int nb = min(DB, m - jb);
     stage_diag(C, R, jb, nb, Dg);
     __syncthreads();
-    if (w == 0) {
+    if (w < nc) {
       // lane j finishes x_j at step j (scaled by its reciprocal pivot) and
       // the value is broadcast through a scalar register
-      T x = lane < nb ? v[jb + lane] : T(0);
+      T* vc = v + w * Rp;
+      T x = lane < nb ? vc[jb + lane] : T(0);
       const T dinv = lane < nb ? Dg[lane + lane * DLD] : T(0);
       for (int j = 0; j < nb; ++j) {
         const T xj = lane_bcast(x * dinv, j);
         if (lane == j) x = xj;
         else if (lane > j) x -= Dg[lane + j * DLD] * xj;
       }
-      if (lane < nb) v[jb + lane] = x;
+      if (lane < nb) vc[jb + lane] = x;
     }
     __syncthreads();
     for (int i = jb + nb + threadIdx.x; i < R; i += WG) {
       const T* ci = C + i + (int64_t)jb * R;
-      T acc = 0;
+      T acc[RC];
+#pragma unroll
+      for (int c = 0; c < RC; ++c) acc[c] = 0;
 #pragma unroll 16
-      for (int j = 0; j < nb; ++j) acc += ci[(int64_t)j * R] * v[jb + j];
-      v[i] -= acc;
+      for (int j = 0; j < nb; ++j) {
+        const T cij = ci[(int64_t)j * R];
+#pragma unroll
+        for (int c = 0; c < RC; ++c) acc[c] += cij * v[jb + j + c * Rp];
+      }
+#pragma unroll
+      for (int c = 0; c < RC; ++c)
+        if (c < nc) v[i + c * Rp] -= acc[c];
     }
     __syncthreads();
   }
-  T* tv = tscr + blockIdx.y * ldt + d.t_off;
-  for (int a = threadIdx.x; a < k; a += WG) tv[a] = -v[m + a];
-  for (int i = threadIdx.x; i < m; i += WG) yv[sl[i]] = v[i];
+  for (int idx = threadIdx.x; idx < R * nc; idx += WG) {
+    const int i = idx % R, c = idx / R;
+    if (i < m) y[(int64_t)(c0 + c) * ldy + sl[i]] = v[i + c * Rp];
+    else tscr[(int64_t)(c0 + c) * ldt + d.t_off + (i - m)] = -v[i + c * Rp];
+  }
 }
 
-// Backward sweep of one interior: y_I <- L^{-T} (y_I - W y_S).
-template <typename T>
+// Backward sweep of one interior: y_I <- L^{-T} (y_I - W y_S), rc columns.
+template <typename T, int RC>
 __global__ __launch_bounds__(WG) void k_apply_bwd(const ElimDesc* __restrict__ D, const T* __restrict__ arena,
                                                   const int32_t* __restrict__ slots,
                                                   const int32_t* __restrict__ nslots, T* __restrict__ y,
-                                                  int64_t ldy) {
+                                                  int64_t ldy, int nrhs) {
+  constexpr int rc = RC;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* Dg = reinterpret_cast<T*>(smem_raw);
   T* v = Dg + DB * DLD;
   const ElimDesc d = D[blockIdx.x];
-  const int m = d.m, k = d.k, R = m + k;
+  const int m = d.m, k = d.k, R = m + k, Rp = (R + 3) & ~3;
+  const int c0 = blockIdx.y * rc, nc = min(rc, nrhs - c0);
   const T* C = arena + d.front_off;
-  T* yv = y + blockIdx.y * ldy;
   const int32_t* sl = slots + d.slot_off;
   const int32_t* ns = nslots + d.nslot_off;
-  for (int i = threadIdx.x; i < R; i += WG) v[i] = i < m ? yv[sl[i]] : yv[ns[i - m]];
+  for (int idx = threadIdx.x; idx < R * nc; idx += WG) {
+    const int i = idx % R, c = idx / R;
+    v[i + c * Rp] = y[(int64_t)(c0 + c) * ldy + (i < m ? sl[i] : ns[i - m])];
+  }
   __syncthreads();
   const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
   for (int bj = (m + DB - 1) / DB - 1; bj >= 0; --bj) {
@@ -912,35 +938,48 @@ __global__ __launch_bounds__(WG) void k_apply_bwd(const ElimDesc* __restrict__ D
       const bool two = j + 1 < nb;
       const T* cj = C + (int64_t)(jb + j) * R;
       const T* ck = cj + R;
-      T a0 = 0, a1 = 0;
+      T a0[RC], a1[RC];
+#pragma unroll
+      for (int c = 0; c < RC; ++c) a0[c] = a1[c] = 0;
 #pragma unroll 4
       for (int i = below + lane; i < R; i += WAVE) {
-        const T vi = v[i];
-        a0 += cj[i] * vi;
-        if (two) a1 += ck[i] * vi;
+        const T c0v = cj[i], c1v = two ? ck[i] : T(0);
+#pragma unroll
+        for (int c = 0; c < RC; ++c) {
+          const T vi = v[i + c * Rp];
+          a0[c] += c0v * vi;
+          a1[c] += c1v * vi;
+        }
       }
-      a0 = wave_sum(a0);
-      a1 = wave_sum(a1);
-      if (lane == 0) {
-        v[jb + j] -= a0;
-        if (two) v[jb + j + 1] -= a1;
-      }
+#pragma unroll
+      for (int c = 0; c < RC; ++c)
+        if (c < nc) {
+          const T s0 = wave_sum(a0[c]), s1 = wave_sum(a1[c]);
+          if (lane == 0) {
+            v[jb + j + c * Rp] -= s0;
+            if (two) v[jb + j + 1 + c * Rp] -= s1;
+          }
+        }
     }
     stage_diag(C, R, jb, nb, Dg);
     __syncthreads();
-    if (w == 0) {
-      T x = lane < nb ? v[jb + lane] : T(0);
+    if (w < nc) {
+      T* vc = v + w * Rp;
+      T x = lane < nb ? vc[jb + lane] : T(0);
       const T dinv = lane < nb ? Dg[lane + lane * DLD] : T(0);
       for (int j = nb - 1; j >= 0; --j) {
         const T xj = lane_bcast(x * dinv, j);
         if (lane == j) x = xj;
         else if (lane < j) x -= Dg[j + lane * DLD] * xj;
       }
-      if (lane < nb) v[jb + lane] = x;
+      if (lane < nb) vc[jb + lane] = x;
     }
     __syncthreads();
   }
-  for (int i = threadIdx.x; i < m; i += WG) yv[sl[i]] = v[i];
+  for (int idx = threadIdx.x; idx < m * nc; idx += WG) {
+    const int i = idx % m, c = idx / m;
+    y[(int64_t)(c0 + c) * ldy + sl[i]] = v[i + c * Rp];
+  }
 }
 
 // T_B = Q^T L_B^{-1} (s x s) for every compressed separator, so that each
@@ -958,38 +997,64 @@ __global__ __launch_bounds__(WG) void k_comp_explicit(const CompApply* __restric
   wg_apply_qt(nbuf + a.v_off, s, tau_all + a.tau_off, s, a.r, X, s, s);
 }
 
-// mode 0: y_B <- T_B y_B; mode 1: y_B <- T_B^T y_B.
+// mode 0: y_B <- T_B y_B; mode 1: y_B <- T_B^T y_B; rc columns per workgroup.
 template <typename T>
 __global__ __launch_bounds__(WG) void k_comp_apply_t(const CompApply* __restrict__ A, const T* __restrict__ tb,
                                                      const int32_t* __restrict__ slots, T* __restrict__ y,
-                                                     int64_t ldy, int mode) {
+                                                     int64_t ldy, int mode, int nrhs, int rc) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const CompApply a = A[blockIdx.x];
   const int s = a.s;
+  const int c0 = blockIdx.y * rc, nc = min(rc, nrhs - c0);
   T* ys = reinterpret_cast<T*>(smem_raw);
-  T* out = ys + s;
+  T* out = ys + s * rc;
   const T* X = tb + a.t_off;
-  T* yv = y + blockIdx.y * ldy;
   const int32_t* sl = slots + a.slot_off;
-  for (int i = threadIdx.x; i < s; i += WG) ys[i] = yv[sl[i]];
+  for (int idx = threadIdx.x; idx < s * nc; idx += WG) {
+    const int i = idx % s, c = idx / s;
+    ys[i + c * s] = y[(int64_t)(c0 + c) * ldy + sl[i]];
+  }
   __syncthreads();
   if (mode == 0) {
     for (int i = threadIdx.x; i < s; i += WG) {
-      T acc = 0;
-      for (int j = 0; j < s; ++j) acc += X[i + (int64_t)j * s] * ys[j];
-      out[i] = acc;
+      T acc[RCM];
+#pragma unroll
+      for (int c = 0; c < RCM; ++c) acc[c] = 0;
+      for (int j = 0; j < s; ++j) {
+        const T xij = X[i + (int64_t)j * s];
+#pragma unroll
+        for (int c = 0; c < RCM; ++c)
+          if (c < nc) acc[c] += xij * ys[j + c * s];
+      }
+#pragma unroll
+      for (int c = 0; c < RCM; ++c)
+        if (c < nc) out[i + c * s] = acc[c];
     }
   } else {
     const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
     for (int j = w; j < s; j += WG / WAVE) {
-      T acc = 0;
-      for (int i = lane; i < s; i += WAVE) acc += X[i + (int64_t)j * s] * ys[i];
-      acc = wave_sum(acc);
-      if (lane == 0) out[j] = acc;
+      T acc[RCM];
+#pragma unroll
+      for (int c = 0; c < RCM; ++c) acc[c] = 0;
+      for (int i = lane; i < s; i += WAVE) {
+        const T xij = X[i + (int64_t)j * s];
+#pragma unroll
+        for (int c = 0; c < RCM; ++c)
+          if (c < nc) acc[c] += xij * ys[i + c * s];
+      }
+#pragma unroll
+      for (int c = 0; c < RCM; ++c)
+        if (c < nc) {
+          const T t = wave_sum(acc[c]);
+          if (lane == 0) out[j + c * s] = t;
+        }
     }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < s; i += WG) yv[sl[i]] = out[i];
+  for (int idx = threadIdx.x; idx < s * nc; idx += WG) {
+    const int i = idx % s, c = idx / s;
+    y[(int64_t)(c0 + c) * ldy + sl[i]] = out[i + c * s];
+  }
 }
 
 // Top node (factor in TF, sweep vectors in TV): mode 0: y <- L^{-T} L^{-1} y;
@@ -1048,24 +1113,66 @@ __global__ void k_scatter_perm(const int64_t* __restrict__ perm, int64_t n, cons
 // CG kernels (FP64)
 // ---------------------------------------------------------------------------
 
-// y = A x (CSR, one row per thread); partial[b] = sum over the block's rows of x_i y_i.
-__global__ __launch_bounds__(WG) void k_spmv_dot(const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                                                 const double* __restrict__ va, int64_t n,
-                                                 const double* __restrict__ x, int64_t ldx, double* __restrict__ y,
-                                                 int64_t ldy, double* __restrict__ partial) {
-  __shared__ double red[WG / WAVE];
-  const double* xv = x + blockIdx.y * ldx;
-  double* yv = y + blockIdx.y * ldy;
-  int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
-  double dot = 0;
-  if (i < n) {
-    double acc = 0;
-    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) acc += va[e] * xv[ci[e]];
-    yv[i] = acc;
-    dot = acc * xv[i];
+// y = A x for nrhs columns, G lanes per row (the row's entries strided over
+// the group, summed with shuffles), the matrix read once for up to 8
+// columns.  partial[c * gridDim.x + b] = sum over the block's rows of
+// x_ic y_ic (fixed order), or nothing when partial is NULL.
+template <int G>
+__global__ __launch_bounds__(WG) void k_spmv_multi(const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                                   const double* __restrict__ va, int64_t n,
+                                                   const double* __restrict__ x, int64_t ldx, double* __restrict__ y,
+                                                   int64_t ldy, int nrhs, double* __restrict__ partial) {
+  constexpr int RC = 8;
+  __shared__ double red[WG / WAVE][RC];
+  const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE, g = tid % G;
+  const int64_t row = (int64_t)blockIdx.x * (WG / G) + tid / G;
+  int64_t e0 = 0, e1 = 0;
+  if (row < n) {
+    e0 = rp[row];
+    e1 = rp[row + 1];
   }
-  double s = block_sum(dot, red);
-  if (threadIdx.x == 0 && partial) partial[blockIdx.y * gridDim.x + blockIdx.x] = s;
+  for (int c0 = 0; c0 < nrhs; c0 += RC) {
+    const int nc = min(RC, nrhs - c0);
+    const double* xc = x + (int64_t)c0 * ldx;
+    double acc[RC];
+#pragma unroll
+    for (int j = 0; j < RC; ++j) acc[j] = 0;
+    for (int64_t e = e0 + g; e < e1; e += G) {
+      const double a = va[e];
+      const int64_t col = ci[e];
+#pragma unroll
+      for (int j = 0; j < RC; ++j)
+        if (j < nc) acc[j] += a * xc[col + j * ldx];
+    }
+#pragma unroll
+    for (int j = 0; j < RC; ++j)
+#pragma unroll
+      for (int o = G / 2; o > 0; o >>= 1) acc[j] += __shfl_xor(acc[j], o, WAVE);
+    double d[RC];
+#pragma unroll
+    for (int j = 0; j < RC; ++j) {
+      d[j] = 0;
+      if (j < nc && row < n && g == 0) {
+        y[row + (int64_t)(c0 + j) * ldy] = acc[j];
+        d[j] = acc[j] * xc[row + j * ldx];
+      }
+    }
+    if (partial) {
+#pragma unroll
+      for (int j = 0; j < RC; ++j)
+        if (j < nc) {
+          const double sj = wave_sum(d[j]);
+          if (lane == 0) red[wv][j] = sj;
+        }
+      __syncthreads();
+      if (tid < nc) {
+        double sum = 0;
+        for (int w = 0; w < WG / WAVE; ++w) sum += red[w][tid];
+        partial[(int64_t)(c0 + tid) * gridDim.x + blockIdx.x] = sum;
+      }
+      __syncthreads();
+    }
+  }
 }
 
 // partial[b] = sum over the block of a_i * b_i.

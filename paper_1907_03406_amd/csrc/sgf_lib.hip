@@ -210,6 +210,11 @@ struct sgf_handle_s {
   int32_t max_m_all = 0, max_k_all = 0, max_s_all = 0;
   int32_t failed_cluster = -1, failed_level = -1;
   int32_t tiled_rows = 1024;   // levels whose largest front has this many rows go tiled
+  // elimination path per level: -1 built-in choice, 0 tiled, 4/8/16/32 one
+  // workgroup per front with that panel width (when its LDS panel fits);
+  // force_mode overrides all levels (used while tuning)
+  std::vector<int32_t> level_mode;
+  int32_t force_mode = -1;
   // top node, always factored in FP64: front copy / Cholesky factor, and for
   // the tiled form Zt = L^{-T} and the apply work vector
   DevBuf top64, topz, topu, d_topdesc, d_toptf;
@@ -221,6 +226,29 @@ struct sgf_handle_s {
   int64_t factor_entries = 0, factor_bytes = 0, compressed = 0;
   Profiler prof;
   HostTrace trace;
+  // apply sweep captured as a HIP graph (one cached instance, keyed by its
+  // arguments and the factorization it belongs to), replayed on the caller's
+  // stream; captured on a private stream of default priority
+  bool use_graph = true;
+  uint64_t epoch = 0;
+  hipStream_t cap_stream = nullptr;
+  struct ApplyGraph {
+    hipGraphExec_t exec = nullptr;
+    int nrhs = 0;
+    const double* r = nullptr;
+    double* z = nullptr;
+    int64_t ldr = 0, ldz = 0;
+    bool product = false;
+    uint64_t epoch = 0;
+  } ag;
+  void drop_graph() {
+    if (ag.exec) (void)hipGraphExecDestroy(ag.exec);
+    ag.exec = nullptr;
+  }
+  ~sgf_handle_s() {
+    drop_graph();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  }
 };
 
 namespace {
@@ -337,8 +365,21 @@ void ensure_static(sgf_handle h, hipStream_t st) {
 // Whether the interiors of level L are eliminated by the tiled multi-workgroup
 // path: fronts at or above the row threshold, or too large for the LDS panel
 // of the one-workgroup-per-front kernel.
+int level_mode(sgf_handle h, const sgf::Level& L) {
+  if (h->force_mode != -1) return h->force_mode;
+  const int li = L.t - 1;
+  return li < (int)h->level_mode.size() ? h->level_mode[li] : -1;
+}
+
+bool panel_fits(int rows, int nb, size_t esz) {
+  return (size_t)sgf::potrf_lds_elems(rows, nb) * esz <= LDS_BYTES;
+}
+
 bool level_tiled(sgf_handle h, const sgf::Level& L) {
   if (L.top || L.elim.empty()) return false;
+  const int mode = level_mode(h, L);
+  if (mode == 0) return true;
+  if (mode > 0) return !panel_fits(L.max_front_rows, mode, h->esz);
   if (L.max_front_rows >= h->tiled_rows) return true;
   int max_m = 0;
   for (const auto& e : L.elim) max_m = std::max(max_m, e.m);
@@ -348,6 +389,13 @@ bool level_tiled(sgf_handle h, const sgf::Level& L) {
     return true;
   }
   return false;
+}
+
+// Panel width of the one-workgroup elimination of level L.
+int level_nb(sgf_handle h, const sgf::Level& L, int max_m) {
+  const int mode = level_mode(h, L);
+  if (mode > 0 && panel_fits(L.max_front_rows, mode, h->esz)) return mode;
+  return nb_for(L.max_front_rows, max_m, h->esz);
 }
 
 // Descriptors and buffers of a tiled level: Zt (m x m per front) and the
@@ -448,6 +496,34 @@ void zero(DevBuf& b, int64_t n, hipStream_t st) {
   if (n <= 0) return;
   unsigned g = std::min<int64_t>(cdiv(n, sgf::WG), 65536);
   hipLaunchKernelGGL(sgf::k_zero<T>, dim3(g), dim3(sgf::WG), 0, st, b.as<T>(), n);
+}
+
+// Lanes per CSR row of the SpMV: about half the mean row length, 4..64.
+int spmv_group(sgf_handle h) {
+  const double avg = (double)h->nnz / std::max<int64_t>(h->plan.n, 1);
+  int g = 1;
+  while (g < 64 && 4 * g < avg) g *= 2;
+  return g;
+}
+
+unsigned spmv_blocks(sgf_handle h) { return cdiv(h->plan.n, sgf::WG / spmv_group(h)); }
+
+void spmv_launch(sgf_handle h, const double* x, int64_t ldx, double* y, int64_t ldy, int nrhs, double* partial,
+                 hipStream_t st) {
+  const int64_t n = h->plan.n;
+  const unsigned nb = spmv_blocks(h);
+  const int64_t* rp = h->d_rowptr.as<int64_t>();
+  const int32_t* ci = h->d_colidx.as<int32_t>();
+  const double* va = h->d_vals.as<double>();
+  switch (spmv_group(h)) {
+    case 1: hipLaunchKernelGGL(sgf::k_spmv_multi<1>, dim3(nb), dim3(sgf::WG), 0, st, rp, ci, va, n, x, ldx, y, ldy, nrhs, partial); break;
+    case 2: hipLaunchKernelGGL(sgf::k_spmv_multi<2>, dim3(nb), dim3(sgf::WG), 0, st, rp, ci, va, n, x, ldx, y, ldy, nrhs, partial); break;
+    case 4: hipLaunchKernelGGL(sgf::k_spmv_multi<4>, dim3(nb), dim3(sgf::WG), 0, st, rp, ci, va, n, x, ldx, y, ldy, nrhs, partial); break;
+    case 8: hipLaunchKernelGGL(sgf::k_spmv_multi<8>, dim3(nb), dim3(sgf::WG), 0, st, rp, ci, va, n, x, ldx, y, ldy, nrhs, partial); break;
+    case 16: hipLaunchKernelGGL(sgf::k_spmv_multi<16>, dim3(nb), dim3(sgf::WG), 0, st, rp, ci, va, n, x, ldx, y, ldy, nrhs, partial); break;
+    case 32: hipLaunchKernelGGL(sgf::k_spmv_multi<32>, dim3(nb), dim3(sgf::WG), 0, st, rp, ci, va, n, x, ldx, y, ldy, nrhs, partial); break;
+    default: hipLaunchKernelGGL(sgf::k_spmv_multi<64>, dim3(nb), dim3(sgf::WG), 0, st, rp, ci, va, n, x, ldx, y, ldy, nrhs, partial); break;
+  }
 }
 
 int check_fail(sgf_handle h, hipStream_t st) {
@@ -622,6 +698,8 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
     P.parts.resize(1);
   }
   h->factored = false;
+  ++h->epoch;
+  h->drop_graph();
   h->factor_flops = 0;
   h->apply_bytes = 0;
   h->factor_entries = 0;
@@ -684,7 +762,7 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
     } else if (!L.elim.empty()) {
       int max_m = 0;
       for (const auto& e : L.elim) max_m = std::max(max_m, e.m);
-      int nb = nb_for(L.max_front_rows, max_m, sizeof(T));
+      int nb = level_nb(h, L, max_m);
       size_t lds = (size_t)sgf::potrf_lds_elems(L.max_front_rows, nb) * sizeof(T);
       launch(h, st, "elim", lvl_elim_flops, 0, [&] {
         launch_elim<T>(nb, (unsigned)L.elim.size(), lds, st, D.elim.as<sgf::ElimDesc>(), arena, h->d_fail.as<int>());
@@ -884,6 +962,15 @@ void ensure_work(sgf_handle h, int nrhs) {
   h->tscr.ensure((size_t)std::max<int64_t>(h->max_t, 1) * nrhs * sizeof(T));
 }
 
+// Right-hand sides per workgroup of an apply kernel whose LDS holds `fixed`
+// bytes plus `per_rhs` bytes per column.
+int rc_for(size_t fixed, size_t per_rhs, int nrhs) {
+  if (fixed + per_rhs > LDS_BYTES) throw SgfError(SGF_EINVAL, "apply kernel needs more LDS than available");
+  int rc = std::min(sgf::RCM, nrhs);
+  while (rc > 1 && fixed + rc * per_rhs > LDS_BYTES) --rc;
+  return rc;
+}
+
 template <typename T>
 void run_sweeps(sgf_handle h, int nrhs, bool product, hipStream_t st) {
   sgf::Plan& P = h->plan;
@@ -908,25 +995,32 @@ void run_sweeps(sgf_handle h, int nrhs, bool product, hipStream_t st) {
     if (L.elim.empty()) return;
     if (mode == 0 && D.tiled) {
       const unsigned nf = (unsigned)D.h_tf.size();
-      const double half = 0.5 * (D.work.fwd_bytes + nrhs * D.work.fwd_vec);
-      launch(h, st, "apply_elim_fwd", 0, half, [&] {
-        hipLaunchKernelGGL((sgf::k_tfwd_z<T, T>), dim3(cdiv(D.tmax_m, sgf::TB), nf, nrhs), dim3(sgf::WG),
-                           (size_t)D.tmax_m * sizeof(T), st, D.tf.as<sgf::TFront>(), D.zt.as<T>(),
-                           D.slots.as<int32_t>(), y, n, D.uw.as<T>(), D.u_elems);
+      const size_t e = sizeof(T), mp = (D.tmax_m + 3) & ~3;
+      const int rc1 = rc_for(0, D.tmax_m * e, nrhs), rc2 = rc_for(0, (mp + sgf::WG) * e, nrhs);
+      launch(h, st, "apply_elim_fwd", 0, 0.5 * (cdiv(nrhs, rc1) * D.work.fwd_bytes + nrhs * D.work.fwd_vec), [&] {
+        hipLaunchKernelGGL((sgf::k_tfwd_z<T, T>), dim3(cdiv(D.tmax_m, sgf::TB), nf, cdiv(nrhs, rc1)), dim3(sgf::WG),
+                           (size_t)rc1 * D.tmax_m * e, st, D.tf.as<sgf::TFront>(), D.zt.as<T>(),
+                           D.slots.as<int32_t>(), y, n, D.uw.as<T>(), D.u_elems, nrhs, rc1);
       }, L.t);
-      launch(h, st, "apply_elim_fwd", 0, half, [&] {
-        hipLaunchKernelGGL((sgf::k_tfwd_s<T, T>), dim3(std::max(1u, cdiv(D.tmax_k, sgf::TB)), nf, nrhs),
-                           dim3(sgf::WG), (size_t)(((D.tmax_m + 3) & ~3) + sgf::WG) * sizeof(T), st,
-                           D.tf.as<sgf::TFront>(), D.arena.as<T>(), D.uw.as<T>(), D.u_elems, D.slots.as<int32_t>(),
-                           y, n, ts, ldt);
+      launch(h, st, "apply_elim_fwd", 0, 0.5 * (cdiv(nrhs, rc2) * D.work.fwd_bytes + nrhs * D.work.fwd_vec), [&] {
+        hipLaunchKernelGGL((sgf::k_tfwd_s<T, T>), dim3(std::max(1u, cdiv(D.tmax_k, sgf::TB)), nf, cdiv(nrhs, rc2)),
+                           dim3(sgf::WG), (size_t)rc2 * (mp + sgf::WG) * e, st, D.tf.as<sgf::TFront>(),
+                           D.arena.as<T>(), D.uw.as<T>(), D.u_elems, D.slots.as<int32_t>(), y, n, ts, ldt, nrhs, rc2);
       }, L.t);
       return;
     }
     if (mode == 0) {
-      const size_t lds = ((size_t)sgf::DB * sgf::DLD + L.max_front_rows) * sizeof(T);
-      launch(h, st, "apply_elim_fwd", 0, D.work.fwd_bytes + nrhs * D.work.fwd_vec, [&] {
-        hipLaunchKernelGGL(sgf::k_apply_fwd<T>, dim3((unsigned)L.elim.size(), nrhs), dim3(sgf::WG), lds, st,
-                           D.elim.as<sgf::ElimDesc>(), D.arena.as<T>(), D.slots.as<int32_t>(), y, n, ts, ldt);
+      const size_t fixed = (size_t)sgf::DB * sgf::DLD * sizeof(T);
+      const int rc = rc_for(fixed, (size_t)((L.max_front_rows + 3) & ~3) * sizeof(T), nrhs);
+      const size_t lds = fixed + (size_t)rc * ((L.max_front_rows + 3) & ~3) * sizeof(T);
+      launch(h, st, "apply_elim_fwd", 0, cdiv(nrhs, rc) * D.work.fwd_bytes + nrhs * D.work.fwd_vec, [&] {
+        const dim3 g((unsigned)L.elim.size(), cdiv(nrhs, rc));
+        const sgf::ElimDesc* dd = D.elim.as<sgf::ElimDesc>();
+        const int32_t* sl = D.slots.as<int32_t>();
+        if (rc == 1) hipLaunchKernelGGL((sgf::k_apply_fwd<T, 1>), g, dim3(sgf::WG), lds, st, dd, D.arena.as<T>(), sl, y, n, ts, ldt, nrhs);
+        else if (rc == 2) hipLaunchKernelGGL((sgf::k_apply_fwd<T, 2>), g, dim3(sgf::WG), lds, st, dd, D.arena.as<T>(), sl, y, n, ts, ldt, nrhs);
+        else if (rc == 3) hipLaunchKernelGGL((sgf::k_apply_fwd<T, 3>), g, dim3(sgf::WG), lds, st, dd, D.arena.as<T>(), sl, y, n, ts, ldt, nrhs);
+        else hipLaunchKernelGGL((sgf::k_apply_fwd<T, 4>), g, dim3(sgf::WG), lds, st, dd, D.arena.as<T>(), sl, y, n, ts, ldt, nrhs);
       }, L.t);
       return;
     }
@@ -943,25 +1037,33 @@ void run_sweeps(sgf_handle h, int nrhs, bool product, hipStream_t st) {
     if (L.elim.empty()) return;
     if (mode == 0 && D.tiled) {
       const unsigned nf = (unsigned)D.h_tf.size();
-      const double half = 0.5 * (D.work.bwd_bytes + nrhs * D.work.bwd_vec);
-      launch(h, st, "apply_elim_bwd", 0, half, [&] {
-        hipLaunchKernelGGL((sgf::k_tbwd_s<T, T>), dim3(cdiv(D.tmax_m, sgf::TB), nf, nrhs), dim3(sgf::WG),
-                           (size_t)std::max(D.tmax_k, 1) * sizeof(T), st, D.tf.as<sgf::TFront>(), D.arena.as<T>(),
-                           D.slots.as<int32_t>(), D.nslots.as<int32_t>(), y, n, D.uw.as<T>(), D.u_elems);
+      const size_t e = sizeof(T), mp = (D.tmax_m + 3) & ~3;
+      const int rc1 = rc_for(0, std::max(D.tmax_k, 1) * e, nrhs), rc2 = rc_for(0, (mp + sgf::WG) * e, nrhs);
+      launch(h, st, "apply_elim_bwd", 0, 0.5 * (cdiv(nrhs, rc1) * D.work.bwd_bytes + nrhs * D.work.bwd_vec), [&] {
+        hipLaunchKernelGGL((sgf::k_tbwd_s<T, T>), dim3(cdiv(D.tmax_m, sgf::TB), nf, cdiv(nrhs, rc1)), dim3(sgf::WG),
+                           (size_t)rc1 * std::max(D.tmax_k, 1) * e, st, D.tf.as<sgf::TFront>(), D.arena.as<T>(),
+                           D.slots.as<int32_t>(), D.nslots.as<int32_t>(), y, n, D.uw.as<T>(), D.u_elems, nrhs, rc1);
       }, L.t);
-      launch(h, st, "apply_elim_bwd", 0, half, [&] {
-        hipLaunchKernelGGL((sgf::k_tbwd_z<T, T>), dim3(cdiv(D.tmax_m, sgf::TB), nf, nrhs), dim3(sgf::WG),
-                           (size_t)(((D.tmax_m + 3) & ~3) + sgf::WG) * sizeof(T), st, D.tf.as<sgf::TFront>(),
-                           D.zt.as<T>(), D.uw.as<T>(), D.u_elems, D.slots.as<int32_t>(), y, n);
+      launch(h, st, "apply_elim_bwd", 0, 0.5 * (cdiv(nrhs, rc2) * D.work.bwd_bytes + nrhs * D.work.bwd_vec), [&] {
+        hipLaunchKernelGGL((sgf::k_tbwd_z<T, T>), dim3(cdiv(D.tmax_m, sgf::TB), nf, cdiv(nrhs, rc2)), dim3(sgf::WG),
+                           (size_t)rc2 * (mp + sgf::WG) * e, st, D.tf.as<sgf::TFront>(), D.zt.as<T>(), D.uw.as<T>(),
+                           D.u_elems, D.slots.as<int32_t>(), y, n, nrhs, rc2);
       }, L.t);
       return;
     }
     if (mode == 0) {
-      const size_t lds = ((size_t)sgf::DB * sgf::DLD + L.max_front_rows) * sizeof(T);
-      launch(h, st, "apply_elim_bwd", 0, D.work.bwd_bytes + nrhs * D.work.bwd_vec, [&] {
-        hipLaunchKernelGGL(sgf::k_apply_bwd<T>, dim3((unsigned)L.elim.size(), nrhs), dim3(sgf::WG), lds, st,
-                           D.elim.as<sgf::ElimDesc>(), D.arena.as<T>(), D.slots.as<int32_t>(),
-                           D.nslots.as<int32_t>(), y, n);
+      const size_t fixed = (size_t)sgf::DB * sgf::DLD * sizeof(T);
+      const int rc = rc_for(fixed, (size_t)((L.max_front_rows + 3) & ~3) * sizeof(T), nrhs);
+      const size_t lds = fixed + (size_t)rc * ((L.max_front_rows + 3) & ~3) * sizeof(T);
+      launch(h, st, "apply_elim_bwd", 0, cdiv(nrhs, rc) * D.work.bwd_bytes + nrhs * D.work.bwd_vec, [&] {
+        const dim3 g((unsigned)L.elim.size(), cdiv(nrhs, rc));
+        const sgf::ElimDesc* dd = D.elim.as<sgf::ElimDesc>();
+        const int32_t* sl = D.slots.as<int32_t>();
+        const int32_t* ns = D.nslots.as<int32_t>();
+        if (rc == 1) hipLaunchKernelGGL((sgf::k_apply_bwd<T, 1>), g, dim3(sgf::WG), lds, st, dd, D.arena.as<T>(), sl, ns, y, n, nrhs);
+        else if (rc == 2) hipLaunchKernelGGL((sgf::k_apply_bwd<T, 2>), g, dim3(sgf::WG), lds, st, dd, D.arena.as<T>(), sl, ns, y, n, nrhs);
+        else if (rc == 3) hipLaunchKernelGGL((sgf::k_apply_bwd<T, 3>), g, dim3(sgf::WG), lds, st, dd, D.arena.as<T>(), sl, ns, y, n, nrhs);
+        else hipLaunchKernelGGL((sgf::k_apply_bwd<T, 4>), g, dim3(sgf::WG), lds, st, dd, D.arena.as<T>(), sl, ns, y, n, nrhs);
       }, L.t);
       return;
     }
@@ -988,10 +1090,11 @@ void run_sweeps(sgf_handle h, int nrhs, bool product, hipStream_t st) {
     maxes(L, mm, mk, ms);
     if (L.capply.empty()) return;
     if (mode <= 1) {
-      launch(h, st, "apply_comp", 0, D.work.capply_bytes + nrhs * D.work.capply_vec, [&] {
-        hipLaunchKernelGGL(sgf::k_comp_apply_t<T>, dim3((unsigned)L.capply.size(), nrhs), dim3(sgf::WG),
-                           2 * ms * sizeof(T), st, D.capply.as<sgf::CompApply>(), D.tb.as<T>(),
-                           D.slots.as<int32_t>(), y, n, mode);
+      const int rc = rc_for(0, 2 * (size_t)ms * sizeof(T), nrhs);
+      launch(h, st, "apply_comp", 0, cdiv(nrhs, rc) * D.work.capply_bytes + nrhs * D.work.capply_vec, [&] {
+        hipLaunchKernelGGL(sgf::k_comp_apply_t<T>, dim3((unsigned)L.capply.size(), cdiv(nrhs, rc)), dim3(sgf::WG),
+                           2 * (size_t)rc * ms * sizeof(T), st, D.capply.as<sgf::CompApply>(), D.tb.as<T>(),
+                           D.slots.as<int32_t>(), y, n, mode, nrhs, rc);
       }, L.t);
       return;
     }
@@ -1017,15 +1120,18 @@ void run_sweeps(sgf_handle h, int nrhs, bool product, hipStream_t st) {
     const int m = L.elim[0].m;
     const double tb = 2 * D.work.top_bytes * 8.0 / sizeof(T) + nrhs * D.work.top_vec;
     if (m > 0 && h->top_tiled && !product) {
+      const size_t mp = (m + 3) & ~3;
+      const int rc1 = rc_for(0, m * sizeof(double), nrhs), rc2 = rc_for(0, (mp + sgf::WG) * sizeof(double), nrhs);
       launch(h, st, "apply_top", 0, 0.5 * tb, [&] {
-        hipLaunchKernelGGL((sgf::k_tfwd_z<T, double>), dim3(cdiv(m, sgf::TB), 1, nrhs), dim3(sgf::WG),
-                           (size_t)m * sizeof(double), st, h->d_toptf.as<sgf::TFront>(), h->topz.as<double>(),
-                           D.slots.as<int32_t>(), y, n, h->topu.as<double>(), (int64_t)m);
+        hipLaunchKernelGGL((sgf::k_tfwd_z<T, double>), dim3(cdiv(m, sgf::TB), 1, cdiv(nrhs, rc1)), dim3(sgf::WG),
+                           (size_t)rc1 * m * sizeof(double), st, h->d_toptf.as<sgf::TFront>(), h->topz.as<double>(),
+                           D.slots.as<int32_t>(), y, n, h->topu.as<double>(), (int64_t)m, nrhs, rc1);
       }, L.t);
       launch(h, st, "apply_top", 0, 0.5 * tb, [&] {
-        hipLaunchKernelGGL((sgf::k_tbwd_z<T, double>), dim3(cdiv(m, sgf::TB), 1, nrhs), dim3(sgf::WG),
-                           (size_t)(((m + 3) & ~3) + sgf::WG) * sizeof(double), st, h->d_toptf.as<sgf::TFront>(),
-                           h->topz.as<double>(), h->topu.as<double>(), (int64_t)m, D.slots.as<int32_t>(), y, n);
+        hipLaunchKernelGGL((sgf::k_tbwd_z<T, double>), dim3(cdiv(m, sgf::TB), 1, cdiv(nrhs, rc2)), dim3(sgf::WG),
+                           (size_t)rc2 * (mp + sgf::WG) * sizeof(double), st, h->d_toptf.as<sgf::TFront>(),
+                           h->topz.as<double>(), h->topu.as<double>(), (int64_t)m, D.slots.as<int32_t>(), y, n, nrhs,
+                           rc2);
       }, L.t);
     } else if (m > 0) {
       if ((size_t)2 * m * sizeof(double) > LDS_BYTES)
@@ -1056,16 +1162,55 @@ void apply_impl(sgf_handle h, int nrhs, const double* r, int64_t ldr, double* z,
   ensure_work<T>(h, nrhs);
   dim3 g(cdiv(n, sgf::WG), nrhs);
   const double vb = (double)n * nrhs * (8.0 + sizeof(T)) + 8.0 * n;
-  launch(h, st, "apply_perm", 0, vb, [&] {
-    hipLaunchKernelGGL((sgf::k_gather_perm<double, T>), g, dim3(sgf::WG), 0, st, h->d_perm.as<int64_t>(), n, r, ldr,
-                       h->y.as<T>(), n);
-  });
-  run_sweeps<T>(h, nrhs, product, st);
-  launch(h, st, "apply_perm", 0, vb, [&] {
-    hipLaunchKernelGGL((sgf::k_scatter_perm<T, double>), g, dim3(sgf::WG), 0, st, h->d_perm.as<int64_t>(), n,
-                       h->y.as<T>(), n, z, ldz);
-  });
-  HIP_CHECK(hipGetLastError());
+  auto body = [&](hipStream_t s) {
+    launch(h, s, "apply_perm", 0, vb, [&] {
+      hipLaunchKernelGGL((sgf::k_gather_perm<double, T>), g, dim3(sgf::WG), 0, s, h->d_perm.as<int64_t>(), n, r, ldr,
+                         h->y.as<T>(), n);
+    });
+    run_sweeps<T>(h, nrhs, product, s);
+    launch(h, s, "apply_perm", 0, vb, [&] {
+      hipLaunchKernelGGL((sgf::k_scatter_perm<T, double>), g, dim3(sgf::WG), 0, s, h->d_perm.as<int64_t>(), n,
+                         h->y.as<T>(), n, z, ldz);
+    });
+  };
+  if (!h->use_graph) {
+    body(st);
+    HIP_CHECK(hipGetLastError());
+    return;
+  }
+  auto& G = h->ag;
+  if (!(G.exec && G.nrhs == nrhs && G.r == r && G.ldr == ldr && G.z == z && G.ldz == ldz && G.product == product &&
+        G.epoch == h->epoch)) {
+    h->drop_graph();
+    if (!h->cap_stream) HIP_CHECK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    const bool prof = h->prof.on;
+    h->prof.on = false;   // no event records inside the graph
+    HIP_CHECK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipGraph_t graph = nullptr;
+    try {
+      body(h->cap_stream);
+    } catch (...) {
+      (void)hipStreamEndCapture(h->cap_stream, &graph);
+      if (graph) (void)hipGraphDestroy(graph);
+      h->prof.on = prof;
+      throw;
+    }
+    h->prof.on = prof;
+    HIP_CHECK(hipStreamEndCapture(h->cap_stream, &graph));
+    hipGraphExec_t exec = nullptr;
+    const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    HIP_CHECK(e);
+    G.exec = exec;
+    G.nrhs = nrhs;
+    G.r = r;
+    G.ldr = ldr;
+    G.z = z;
+    G.ldz = ldz;
+    G.product = product;
+    G.epoch = h->epoch;
+  }
+  launch(h, st, "apply_graph", 0, h->apply_bytes * nrhs, [&] { HIP_CHECK(hipGraphLaunch(G.exec, st)); });
 }
 
 void apply_any(sgf_handle h, int nrhs, const double* r, int64_t ldr, double* z, int64_t ldz, bool product,
@@ -1188,6 +1333,85 @@ sgf_status sgf_factorize_numeric(sgf_handle h, const double* vals, void* stream)
   });
 }
 
+sgf_status sgf_autotune(sgf_handle h, const double* vals, int32_t napply, int32_t* modes_out, void* stream) {
+  if (!h || !vals || napply < 0) return fail(SGF_EINVAL, "bad autotune arguments");
+  hipStream_t st = (hipStream_t)stream;
+  return guard([&] {
+    const int64_t n = h->plan.n;
+    DevBuf r, z;
+    r.ensure(n * sizeof(double));
+    z.ensure(n * sizeof(double));
+    HIP_CHECK(hipMemsetAsync(r.p, 0, n * sizeof(double), st));
+    const bool prof_was = h->prof.on;
+    h->prof.drain();
+    const auto saved = h->prof.stats;
+    struct Restore {
+      sgf_handle h;
+      bool on;
+      std::vector<sgf_kernel_stat> stats;
+      bool graph;
+      ~Restore() {
+        h->force_mode = -1;
+        h->use_graph = graph;
+        h->prof.on = on;
+        h->prof.stats = stats;
+        for (auto& D : h->lev) D.uploaded = false;
+      }
+    } restore{h, prof_was, saved, h->use_graph};
+    h->use_graph = false;   // per-level apply timings need direct launches
+    const int candidates[] = {0, 8, 16, 32};
+    std::vector<std::vector<double>> cost;   // [candidate][level]
+    std::vector<std::vector<char>> honored;  // the level really ran that candidate
+    for (int c : candidates) {
+      h->force_mode = c;
+      h->level_mode.clear();
+      for (auto& D : h->lev) D.uploaded = false;
+      h->prof.stats.clear();
+      h->prof.on = true;
+      if (h->esz == 8) factor_numeric<double>(h, vals, st);
+      else factor_numeric<float>(h, vals, st);
+      apply_any(h, 1, r.as<double>(), n, z.as<double>(), n, false, st);
+      h->prof.drain();
+      const int nl = (int)h->plan.levels.size();
+      std::vector<double> lc(nl, 0.0);
+      std::vector<char> ok(nl, 0);
+      for (int li = 0; li < nl; ++li) {
+        const auto& L = h->plan.levels[li];
+        if (L.top || L.elim.empty()) continue;
+        ok[li] = (c == 0) == h->lev[li].tiled;
+        char tag[48];
+        for (const auto& k : h->prof.stats) {
+          const std::string nm(k.name);
+          std::snprintf(tag, sizeof(tag), "@L%d", L.t);
+          const size_t at = nm.find('@');
+          if (at == std::string::npos || nm.substr(at) != tag) continue;
+          const std::string base = nm.substr(0, at);
+          if (base == "elim" || base.rfind("elim_", 0) == 0) lc[li] += k.ms;
+          else if (base == "apply_elim_fwd" || base == "apply_elim_bwd") lc[li] += napply * k.ms;
+        }
+      }
+      cost.push_back(lc);
+      honored.push_back(ok);
+    }
+    const int nl = (int)h->plan.levels.size();
+    std::vector<int32_t> modes(nl, -1);
+    for (int li = 0; li < nl; ++li) {
+      double best = 0;
+      for (size_t c = 0; c < cost.size(); ++c) {
+        if (li >= (int)cost[c].size() || !honored[c][li]) continue;
+        if (modes[li] == -1 || cost[c][li] < best) {
+          best = cost[c][li];
+          modes[li] = candidates[c];
+        }
+      }
+    }
+    h->level_mode = modes;
+    h->factored = false;
+    if (modes_out)
+      for (int li = 0; li < nl; ++li) modes_out[li] = modes[li];
+  });
+}
+
 sgf_status sgf_factorize(int64_t n, const int64_t* row_ptr, const int32_t* col_idx, const double* vals,
                          const double* coords, const sgf_options* opt, void* stream, sgf_handle* out) {
   sgf_handle h = nullptr;
@@ -1223,9 +1447,7 @@ sgf_status sgf_spmv(sgf_handle h, const double* v, double* y, void* stream) {
   if (!h->dev_static) return fail(SGF_ESTATE, "spmv before factorization");
   return guard([&] {
     const int64_t n = h->plan.n;
-    hipLaunchKernelGGL(sgf::k_spmv_dot, dim3(cdiv(n, sgf::WG), 1), dim3(sgf::WG), 0, (hipStream_t)stream,
-                       h->d_rowptr.as<int64_t>(), h->d_colidx.as<int32_t>(), h->d_vals.as<double>(), n, v, n, y, n,
-                       (double*)nullptr);
+    spmv_launch(h, v, n, y, n, 1, nullptr, (hipStream_t)stream);
     HIP_CHECK(hipGetLastError());
   });
 }
@@ -1246,7 +1468,7 @@ sgf_status sgf_pcg_solve(sgf_handle h, int32_t nrhs, const double* b, int64_t ld
     h->cg_p.ensure(vb);
     h->cg_ap.ensure(vb);
     const int nbs = (int)std::min<int64_t>(1024, cdiv(n, sgf::WG));
-    const int nbspmv = (int)cdiv(n, sgf::WG);
+    const int nbspmv = (int)spmv_blocks(h);
     h->cg_part.ensure((size_t)std::max(nbs, nbspmv) * nrhs * sizeof(double));
     h->cg_st.ensure(8 * nrhs * sizeof(double));
     h->cg_scal.ensure(2 * nrhs * sizeof(double));
@@ -1285,12 +1507,10 @@ sgf_status sgf_pcg_solve(sgf_handle h, int32_t nrhs, const double* b, int64_t ld
       HIP_CHECK(hipMemcpyAsync(stv + 8 * c, sc + c, sizeof(double), hipMemcpyDeviceToDevice, st));
     HIP_CHECK(hipMemcpyAsync(p, z, vb, hipMemcpyDeviceToDevice, st));
     dim3 gv(cdiv(n, sgf::WG), nrhs);
-    const double spmv_bytes = nrhs * (12.0 * h->nnz + 8.0 * (n + 1) + 24.0 * n);
+    const double spmv_bytes = cdiv(nrhs, 8) * (12.0 * h->nnz + 8.0 * (n + 1)) + nrhs * 24.0 * n;
     for (int it = 1; it <= maxit; ++it) {
       launch(h, st, "cg_spmv", 0, spmv_bytes, [&] {
-        hipLaunchKernelGGL(sgf::k_spmv_dot, dim3(nbspmv, nrhs), dim3(sgf::WG), 0, st, h->d_rowptr.as<int64_t>(),
-                           h->d_colidx.as<int32_t>(), h->d_vals.as<double>(), n, p, n, Ap, n,
-                           h->cg_part.as<double>());
+        spmv_launch(h, p, n, Ap, n, nrhs, h->cg_part.as<double>(), st);
       });
       launch(h, st, "cg_reduce", 0, 8.0 * nbspmv * nrhs, [&] {
         hipLaunchKernelGGL(sgf::k_reduce, dim3(nrhs), dim3(sgf::WG), 0, st, h->cg_part.as<double>(), nbspmv, sc);
@@ -1406,6 +1626,11 @@ sgf_status sgf_plan_dry_run(sgf_handle h, sgf_rank_fn rank_fn, void* ctx) {
       sgf::plan_next_level(P, bm, pm);
     }
   });
+}
+
+sgf_status sgf_set_apply_graph(sgf_handle h, int32_t enable) {
+  if (!h) return fail(SGF_EINVAL, "NULL handle");
+  return guard([&] { h->use_graph = enable != 0; });
 }
 
 sgf_status sgf_profile_enable(sgf_handle h, int32_t enable) {

@@ -290,30 +290,44 @@ __global__ __launch_bounds__(WG) void k_tschur(const TFront* __restrict__ D, T* 
 // ---------------------------------------------------------------------------
 
 // u = Z y_I with Z = Zt^T (lower): u[c] = sum_{r <= c} Zt[r][c] y_I[r].  One
-// wavefront per column, 64 columns per workgroup.
+// wavefront per column, 64 columns per workgroup, rc right-hand sides
+// (columns blockIdx.z * rc ...) sharing each factor load.
 template <typename TV, typename TF>
 __global__ __launch_bounds__(WG) void k_tfwd_z(const TFront* __restrict__ D, const TF* __restrict__ zb,
                                                const int32_t* __restrict__ slots, const TV* __restrict__ y,
-                                               int64_t ldy, TF* __restrict__ uw, int64_t ldu) {
+                                               int64_t ldy, TF* __restrict__ uw, int64_t ldu, int nrhs, int rc) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   TF* ys = reinterpret_cast<TF*>(smem_raw);
   const TFront d = D[blockIdx.y];
   const int m = d.m, cb = blockIdx.x * TB;
   if (cb >= m) return;
   const int ce = min(cb + TB, m);
-  const TV* yv = y + blockIdx.z * ldy;
+  const int q0 = blockIdx.z * rc, nc = min(rc, nrhs - q0);
   const int32_t* sl = slots + d.slot_off;
-  for (int i = threadIdx.x; i < ce; i += WG) ys[i] = (TF)yv[sl[i]];
+  for (int idx = threadIdx.x; idx < ce * nc; idx += WG) {
+    const int i = idx % ce, q = idx / ce;
+    ys[i + q * ce] = (TF)y[(int64_t)(q0 + q) * ldy + sl[i]];
+  }
   __syncthreads();
   const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
   const TF* Z = zb + d.z_off;
-  TF* u = uw + blockIdx.z * ldu + d.u_off;
   for (int c = cb + wv; c < ce; c += WG / WAVE) {
     const TF* zc = Z + (int64_t)c * m;
-    TF acc = 0;
-    for (int r = lane; r <= c; r += WAVE) acc += zc[r] * ys[r];
-    acc = wave_sum(acc);
-    if (lane == 0) u[c] = acc;
+    TF acc[RCM];
+#pragma unroll
+    for (int q = 0; q < RCM; ++q) acc[q] = 0;
+    for (int r = lane; r <= c; r += WAVE) {
+      const TF z = zc[r];
+#pragma unroll
+      for (int q = 0; q < RCM; ++q)
+        if (q < nc) acc[q] += z * ys[r + q * ce];
+    }
+#pragma unroll
+    for (int q = 0; q < RCM; ++q)
+      if (q < nc) {
+        const TF t = wave_sum(acc[q]);
+        if (lane == 0) uw[(int64_t)(q0 + q) * ldu + d.u_off + c] = t;
+      }
   }
 }
 
@@ -324,36 +338,51 @@ template <typename TV, typename TF>
 __global__ __launch_bounds__(WG) void k_tfwd_s(const TFront* __restrict__ D, const TF* __restrict__ fb,
                                                const TF* __restrict__ uw, int64_t ldu,
                                                const int32_t* __restrict__ slots, TV* __restrict__ y, int64_t ldy,
-                                               TV* __restrict__ tscr, int64_t ldt) {
+                                               TV* __restrict__ tscr, int64_t ldt, int nrhs, int rc) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   TF* us = reinterpret_cast<TF*>(smem_raw);
   const TFront d = D[blockIdx.y];
-  const int m = d.m, R = d.R, k = R - m;
+  const int m = d.m, R = d.R, k = R - m, mp = (m + 3) & ~3;
   const int rb = blockIdx.x * TB;
-  const TF* u = uw + blockIdx.z * ldu + d.u_off;
-  TV* yv = y + blockIdx.z * ldy;
+  const int q0 = blockIdx.z * rc, nc = min(rc, nrhs - q0);
   if (blockIdx.x == 0) {
     const int32_t* sl = slots + d.slot_off;
-    for (int i = threadIdx.x; i < m; i += WG) yv[sl[i]] = (TV)u[i];
+    for (int idx = threadIdx.x; idx < m * nc; idx += WG) {
+      const int i = idx % m, q = idx / m;
+      y[(int64_t)(q0 + q) * ldy + sl[i]] = (TV)uw[(int64_t)(q0 + q) * ldu + d.u_off + i];
+    }
   }
   if (rb >= k) return;
-  for (int i = threadIdx.x; i < m; i += WG) us[i] = u[i];
-  TF* part = us + ((m + 3) & ~3);
+  for (int idx = threadIdx.x; idx < m * nc; idx += WG) {
+    const int i = idx % m, q = idx / m;
+    us[i + q * mp] = uw[(int64_t)(q0 + q) * ldu + d.u_off + i];
+  }
+  TF* part = us + mp * rc;
   __syncthreads();
   const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
   const int a = rb + lane;
-  TF acc = 0;
+  TF acc[RCM];
+#pragma unroll
+  for (int q = 0; q < RCM; ++q) acc[q] = 0;
   if (a < k) {
     const TF* L = fb + d.f_off + m + a;
-#pragma unroll 8
-    for (int c = wv; c < m; c += WG / WAVE) acc += L[(int64_t)c * R] * us[c];
+#pragma unroll 4
+    for (int c = wv; c < m; c += WG / WAVE) {
+      const TF l = L[(int64_t)c * R];
+#pragma unroll
+      for (int q = 0; q < RCM; ++q)
+        if (q < nc) acc[q] += l * us[c + q * mp];
+    }
   }
-  part[wv * WAVE + lane] = acc;
+#pragma unroll
+  for (int q = 0; q < RCM; ++q)
+    if (q < nc) part[(q * (WG / WAVE) + wv) * WAVE + lane] = acc[q];
   __syncthreads();
-  if (wv == 0 && a < k) {
-    TF s = part[lane];
-    for (int q = 1; q < WG / WAVE; ++q) s += part[q * WAVE + lane];
-    tscr[blockIdx.z * ldt + d.t_off + a] = (TV)s;
+  if (wv < nc && a < k) {
+    const TF* pq = part + wv * (WG / WAVE) * WAVE;
+    TF sum = pq[lane];
+    for (int w = 1; w < WG / WAVE; ++w) sum += pq[w * WAVE + lane];
+    tscr[(int64_t)(q0 + wv) * ldt + d.t_off + a] = (TV)sum;
   }
 }
 
@@ -362,26 +391,40 @@ template <typename TV, typename TF>
 __global__ __launch_bounds__(WG) void k_tbwd_s(const TFront* __restrict__ D, const TF* __restrict__ fb,
                                                const int32_t* __restrict__ slots,
                                                const int32_t* __restrict__ nslots, const TV* __restrict__ y,
-                                               int64_t ldy, TF* __restrict__ uw, int64_t ldu) {
+                                               int64_t ldy, TF* __restrict__ uw, int64_t ldu, int nrhs, int rc) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   TF* ysS = reinterpret_cast<TF*>(smem_raw);
   const TFront d = D[blockIdx.y];
   const int m = d.m, R = d.R, k = R - m, cb = blockIdx.x * TB;
   if (cb >= m) return;
   const int ce = min(cb + TB, m);
-  const TV* yv = y + blockIdx.z * ldy;
+  const int q0 = blockIdx.z * rc, nc = min(rc, nrhs - q0);
   const int32_t* ns = nslots + d.nslot_off;
-  for (int i = threadIdx.x; i < k; i += WG) ysS[i] = (TF)yv[ns[i]];
+  for (int idx = threadIdx.x; idx < k * nc; idx += WG) {
+    const int i = idx % k, q = idx / k;
+    ysS[i + q * k] = (TF)y[(int64_t)(q0 + q) * ldy + ns[i]];
+  }
   __syncthreads();
   const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
   const int32_t* sl = slots + d.slot_off;
-  TF* v = uw + blockIdx.z * ldu + d.u_off;
   for (int c = cb + wv; c < ce; c += WG / WAVE) {
     const TF* lc = fb + d.f_off + m + (int64_t)c * R;
-    TF acc = 0;
-    for (int a = lane; a < k; a += WAVE) acc += lc[a] * ysS[a];
-    acc = wave_sum(acc);
-    if (lane == 0) v[c] = (TF)yv[sl[c]] - acc;
+    TF acc[RCM];
+#pragma unroll
+    for (int q = 0; q < RCM; ++q) acc[q] = 0;
+    for (int a = lane; a < k; a += WAVE) {
+      const TF l = lc[a];
+#pragma unroll
+      for (int q = 0; q < RCM; ++q)
+        if (q < nc) acc[q] += l * ysS[a + q * k];
+    }
+#pragma unroll
+    for (int q = 0; q < RCM; ++q)
+      if (q < nc) {
+        const TF t = wave_sum(acc[q]);
+        if (lane == 0)
+          uw[(int64_t)(q0 + q) * ldu + d.u_off + c] = (TF)y[(int64_t)(q0 + q) * ldy + sl[c]] - t;
+      }
   }
 }
 
@@ -390,32 +433,46 @@ __global__ __launch_bounds__(WG) void k_tbwd_s(const TFront* __restrict__ D, con
 template <typename TV, typename TF>
 __global__ __launch_bounds__(WG) void k_tbwd_z(const TFront* __restrict__ D, const TF* __restrict__ zb,
                                                const TF* __restrict__ uw, int64_t ldu,
-                                               const int32_t* __restrict__ slots, TV* __restrict__ y,
-                                               int64_t ldy) {
+                                               const int32_t* __restrict__ slots, TV* __restrict__ y, int64_t ldy,
+                                               int nrhs, int rc) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   TF* vs = reinterpret_cast<TF*>(smem_raw);
   const TFront d = D[blockIdx.y];
   const int m = d.m, rb = blockIdx.x * TB;
   if (rb >= m) return;
-  const TF* v = uw + blockIdx.z * ldu + d.u_off;
-  for (int i = rb + threadIdx.x; i < m; i += WG) vs[i - rb] = v[i];
-  TF* part = vs + ((m - rb + 3) & ~3);
+  const int q0 = blockIdx.z * rc, nc = min(rc, nrhs - q0);
+  const int len = m - rb, lp = (len + 3) & ~3;
+  for (int idx = threadIdx.x; idx < len * nc; idx += WG) {
+    const int i = idx % len, q = idx / len;
+    vs[i + q * lp] = uw[(int64_t)(q0 + q) * ldu + d.u_off + rb + i];
+  }
+  TF* part = vs + lp * rc;
   __syncthreads();
   const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
   const int r = rb + lane;
-  TF acc = 0;
+  TF acc[RCM];
+#pragma unroll
+  for (int q = 0; q < RCM; ++q) acc[q] = 0;
   if (r < m) {
     const TF* zr = zb + d.z_off + r;
-#pragma unroll 8
+#pragma unroll 4
     for (int c = rb + wv; c < m; c += WG / WAVE)
-      if (c >= r) acc += zr[(int64_t)c * m] * vs[c - rb];
+      if (c >= r) {
+        const TF z = zr[(int64_t)c * m];
+#pragma unroll
+        for (int q = 0; q < RCM; ++q)
+          if (q < nc) acc[q] += z * vs[c - rb + q * lp];
+      }
   }
-  part[wv * WAVE + lane] = acc;
+#pragma unroll
+  for (int q = 0; q < RCM; ++q)
+    if (q < nc) part[(q * (WG / WAVE) + wv) * WAVE + lane] = acc[q];
   __syncthreads();
-  if (wv == 0 && r < m) {
-    TF s = part[lane];
-    for (int q = 1; q < WG / WAVE; ++q) s += part[q * WAVE + lane];
-    y[blockIdx.z * ldy + slots[d.slot_off + r]] = (TV)s;
+  if (wv < nc && r < m) {
+    const TF* pq = part + wv * (WG / WAVE) * WAVE;
+    TF sum = pq[lane];
+    for (int w = 1; w < WG / WAVE; ++w) sum += pq[w * WAVE + lane];
+    y[(int64_t)(q0 + wv) * ldy + slots[d.slot_off + r]] = (TV)sum;
   }
 }
 

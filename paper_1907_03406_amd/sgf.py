@@ -18,9 +18,10 @@ NEST_ALL_ALL, NEST_2_ALL = 0, 1
 STOP_ROOT, STOP_PAPER = 0, 1
 FP64, FP32 = 0, 1
 
-EXPORTED = ["sgf_default_options", "sgf_analyze", "sgf_factorize_numeric", "sgf_factorize",
+EXPORTED = ["sgf_default_options", "sgf_analyze", "sgf_factorize_numeric", "sgf_factorize", "sgf_autotune",
             "sgf_apply", "sgf_multiply", "sgf_pcg_solve", "sgf_spmv", "sgf_get_info",
             "sgf_get_perm", "sgf_get_level", "sgf_plan_dry_run", "sgf_profile_enable", "sgf_profile_read",
+            "sgf_set_apply_graph",
             "sgf_destroy", "sgf_status_str", "sgf_last_error"]
 
 RANK_FN = ctypes.CFUNCTYPE(ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p)
@@ -64,6 +65,7 @@ def load_library(path=LIB_PATH):
         "sgf_analyze": (I32, [I64, P, P, P, ctypes.POINTER(Options), ctypes.POINTER(H)]),
         "sgf_factorize_numeric": (I32, [H, P, P]),
         "sgf_factorize": (I32, [I64, P, P, P, P, ctypes.POINTER(Options), P, ctypes.POINTER(H)]),
+        "sgf_autotune": (I32, [H, P, I32, P, P]),
         "sgf_apply": (I32, [H, I32, P, I64, P, I64, P]),
         "sgf_multiply": (I32, [H, I32, P, I64, P, I64, P]),
         "sgf_pcg_solve": (I32, [H, I32, P, I64, P, I64, D, I32, P, P, P]),
@@ -73,6 +75,7 @@ def load_library(path=LIB_PATH):
         "sgf_get_level": (I32, [H, I32, P, P, P, P, P]),
         "sgf_plan_dry_run": (I32, [H, RANK_FN, P]),
         "sgf_profile_enable": (I32, [H, I32]),
+        "sgf_set_apply_graph": (I32, [H, I32]),
         "sgf_profile_read": (I32, [H, ctypes.POINTER(KernelStat), I32, P]),
         "sgf_destroy": (I32, [H]),
         "sgf_status_str": (ctypes.c_char_p, [I32]),
@@ -157,6 +160,13 @@ class Solver:
     def factorize(self, vals, stream=None):
         _check(_lib.sgf_factorize_numeric(self.h, _ptr(vals), _stream(stream)))
 
+    def autotune(self, vals, napply=30, stream=None):
+        """Per-level elimination path / panel width by timing; returns the
+        chosen mode per level (0 tiled, 8/16/32 panel width, -1 none)."""
+        modes = np.zeros(64, dtype=np.int32)
+        _check(_lib.sgf_autotune(self.h, _ptr(vals), int(napply), _ptr(modes), _stream(stream)))
+        return modes[:self.info()["levels"]]
+
     def apply(self, r, z, stream=None):
         nrhs = 1 if r.dim() == 1 else r.shape[1]
         _check(_lib.sgf_apply(self.h, nrhs, _ptr(r), self.n, _ptr(z), self.n, _stream(stream)))
@@ -192,6 +202,10 @@ class Solver:
         """Host-only planning of every level with ranks from ``rank_of(level, cell, size)``."""
         cb = RANK_FN(lambda t, cell, size, ctx: int(rank_of(t, cell, size)))
         _check(_lib.sgf_plan_dry_run(self.h, cb, None))
+
+    def set_apply_graph(self, enable=True):
+        """Replay the apply sweep as a captured HIP graph (default) or launch directly."""
+        _check(_lib.sgf_set_apply_graph(self.h, 1 if enable else 0))
 
     def profile(self, enable=True):
         """Start (clear) or stop per-kernel event timing."""

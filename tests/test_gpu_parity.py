@@ -243,3 +243,67 @@ def test_fp32_form_reaches_fp64_accuracy(kind, grid, leaf, q, tiled):
     print(f"fp32 form: it {it32} (fp64 {it64}), true residual {true32:.2e}, |x32-x64|/|x64| {_rel(x32, x64):.2e}")
     assert true32 < 2e-8
     assert it32 <= 2 * it64 + 5
+
+
+def test_autotuned_levels_match_oracle():
+    """After the autotuner picks each level's path, the factor is the same
+    operator; the chosen modes are among the candidates."""
+    p = _prob("blocky", (20, 19, 18))
+    F = _oracle(p, 1, 4)
+    s = sgf.Solver.from_problem(p, q=1, leaf=4)
+    vals = torch.from_numpy(p.data).cuda()
+    modes = s.autotune(vals, napply=10)
+    assert len(modes) == F.info["nlevels"]
+    assert set(modes.tolist()) <= {-1, 0, 8, 16, 32}
+    assert modes[-1] == -1
+    with pytest.raises(sgf.SgfError):
+        s.apply(vals[:p.n].clone(), torch.empty(p.n, dtype=torch.float64, device="cuda"))
+    s.factorize(vals)
+    V = np.stack([P.random_rhs(4, p.n, j) for j in range(2)], axis=1)
+    assert _rel(_apply(s, V), O.apply_inverse(F, V)) <= 1e-10
+
+
+@pytest.mark.parametrize("tiled", TILED)
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batched_rhs_apply_equals_columnwise(tiled, prec):
+    """Seven right-hand sides in one apply (workgroups take up to four
+    columns, so the batch is split 4 + 3) give the same columns as seven
+    single applies."""
+    p = _prob("elast", 9, seed=5)
+    s = _gpu(p, q=1, leaf=3, tiled_min_rows=tiled, precision=sgf.FP64 if prec == "fp64" else sgf.FP32)
+    V = np.stack([P.random_rhs(11, p.n, j) for j in range(7)], axis=1)
+    Z = _apply(s, V)
+    Zc = np.stack([_apply(s, V[:, j]) for j in range(7)], axis=1)
+    print(f"batched vs columnwise ({prec}, tiled {tiled}): {np.abs(Z - Zc).max():.1e}")
+    assert _rel(Z, Zc) <= (1e-14 if prec == "fp64" else 1e-6)
+    if prec == "fp64":
+        F = _oracle(p, 1, 3)
+        assert _rel(Z, O.apply_inverse(F, V)) <= 1e-10
+
+
+@pytest.mark.parametrize("tiled", TILED)
+def test_graph_replays_match_direct_launches(tiled):
+    """One captured apply graph, replayed several times with direct-launch
+    applies, a refactorization (which retires the graph) and host
+    synchronisations in between, gives exactly the direct-launch result."""
+    p = _prob("fourier", (70, 61), seed=3)
+    s = _gpu(p, q=2, leaf=4, tiled_min_rows=tiled, precision=sgf.FP32)
+    r = torch.from_numpy(np.stack([P.random_rhs(2, p.n, j) for j in range(3)], axis=0)).cuda()
+    zg, zd = torch.empty_like(r), torch.empty_like(r)
+    for rep in range(5):
+        s.set_apply_graph(False)
+        s.apply(r.T, zd.T)
+        torch.cuda.synchronize()
+        s.set_apply_graph(True)
+        zg.fill_(float("nan"))
+        s.apply(r.T, zg.T)
+        torch.cuda.synchronize()
+        assert torch.equal(zg, zd), f"replay {rep}"
+        if rep == 2:
+            s.factorize(torch.from_numpy(p.data).cuda())
+    x = torch.zeros_like(r)
+    it, rel = s.pcg(r.T, x.T, rtol=1e-9)
+    s.set_apply_graph(False)
+    x2 = torch.zeros_like(r)
+    it2, rel2 = s.pcg(r.T, x2.T, rtol=1e-9)
+    assert it.tolist() == it2.tolist() and torch.equal(x, x2)
