@@ -85,6 +85,7 @@ typedef struct {
   double apply_bytes;          /* algorithmic bytes of one apply (factor read 2x) */
   int32_t failed_cluster;      /* cluster id of a non-positive pivot, else -1     */
   int32_t failed_level;        /* its level (1-based), else -1                    */
+  int64_t device_bytes;        /* all device memory the handle holds now          */
 } sgf_info;
 
 /* Fills *opt with the defaults: scheme NEST_ALL_ALL, compress 1, compress
@@ -213,12 +214,32 @@ sgf_status sgf_plan_dry_run(sgf_handle h, sgf_rank_fn rank_fn, void* ctx);
  * the counters; sgf_profile_read synchronizes the pending events and copies
  * up to `cap` records (count receives the number of classes).
  */
-typedef struct {
+typedef struct sgf_kernel_stat {
   char name[32];
   int64_t launches;
   double ms;      /* summed event time of the launches                  */
   double flops;   /* summed algorithmic flops                            */
-  double bytes;   /*
+  double bytes;   /* summed algorithmic bytes                            */
+} sgf_kernel_stat;
+sgf_status sgf_profile_enable(sgf_handle h, int32_t enable);
+sgf_status sgf_profile_read(sgf_handle h, sgf_kernel_stat* out, int32_t cap, int32_t* count);
+
+/*
+ * Frees every device buffer of the handle (factor, copies of A, work
+ * vectors); the symbolic analysis stays, so sgf_factorize_numeric can be
+ * called again.  Used to evict a cached factor under a memory budget.
+ */
+sgf_status sgf_release(sgf_handle h);
+
+/*
+ * Device bytes the handle needs to factorize and solve nrhs right-hand
+ * sides: for an unfactored handle an upper bound from the plan, every
+ * separator at its largest possible rank (min(|B|, columns of N), Sec. 4.5);
+ * for a factored one the bytes held plus the work vectors.  Host-only.
+ */
+sgf_status sgf_estimate_bytes(sgf_handle h, int32_t nrhs, int64_t* bytes);
+
+/*
  * The apply sweep (permutation, all levels' kernels, top) is captured once
  * as a HIP graph on a private stream and replayed on the caller's stream
  * while its arguments (nrhs, r, ldr, z, ldz) and the factorization stay the
@@ -228,16 +249,78 @@ typedef struct {
  */
 sgf_status sgf_set_apply_graph(sgf_handle h, int32_t enable);
 
-/* summed algorithmic bytes                            */
-} sgf_kernel_stat;
-sgf_status sgf_profile_enable(sgf_handle h, int32_t enable);
-sgf_status sgf_profile_read(sgf_handle h, sgf_kernel_stat* out, int32_t cap, int32_t* count);
-
 /* Releases every host and device resource of the handle (NULL is a no-op). */
 sgf_status sgf_destroy(sgf_handle h);
 
 const char* sgf_status_str(sgf_status s);
 const char* sgf_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Serving loop (continuous batching of many operators on one GPU)
+ * ------------------------------------------------------------------------
+ * Operators are registered once (analysis on the host); requests to solve
+ * nrhs right-hand sides with an operator -- factorizing it first when its
+ * factor is not on the device or when asked to -- are queued and started by
+ * `slots` worker threads, each with its own HIP stream, as soon as a slot
+ * and device memory are free.  Memory: the bytes the factors hold plus the
+ * bytes reserved for running requests stay within hbm_budget; cached factors
+ * that are not in use are evicted least-recently-used (sgf_release) to make
+ * room.  Waiting solves of one operator are coalesced into one
+ * multi-right-hand-side PCG of up to max_batch_rhs columns; columns are
+ * independent, so each result equals the result of the request alone.
+ * Threading: submit / wait may be called from any thread. */
+typedef struct sgf_server_s* sgf_server;
+
+typedef struct {
+  int64_t hbm_budget;          /* device bytes for factors + running requests   */
+  int32_t slots;               /* concurrent requests (worker streams), 1..16    */
+  int32_t max_batch_rhs;       /* columns of one coalesced PCG, 1..256          */
+} sgf_server_options;
+
+typedef struct {
+  int64_t ticket;
+  int32_t op;
+  int32_t nrhs;
+  int32_t status;              /* sgf_status of the request                       */
+  int32_t factorized;          /* 1 if its batch factorized the operator         */
+  int32_t batch_rhs;           /* columns of the PCG it ran in                    */
+  int32_t slot;                /* worker that ran it                              */
+  int32_t iters_max;           /* largest CG iteration count of its columns      */
+  double relres_max;           /* largest final relative residual                */
+  double t_submit, t_start, t_end;   /* sgf_server_clock() seconds            */
+  double t_factor;             /* seconds spent factorizing in its batch         */
+} sgf_request_info;
+
+typedef struct {
+  int64_t held_bytes;          /* device bytes held by cached factors             */
+  int64_t peak_bytes;          /* largest held + reserved seen                    */
+  int64_t evictions, factorizations, batches, queued, cached_operators;
+} sgf_server_stats;
+
+/* Defaults: 200 GiB budget, 4 slots, 16 columns per batch. */
+void sgf_server_default_options(sgf_server_options* opt);
+sgf_status sgf_server_create(const sgf_server_options* opt, sgf_server* out);
+/* Registers an operator: the arguments of sgf_analyze plus its values
+ * (HOST double[nnz], copied).  *op_id receives its id. */
+sgf_status sgf_server_add_operator(sgf_server s, int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
+                                   const double* vals, const double* coords, const sgf_options* opt,
+                                   int32_t* op_id);
+/* Queues a request: b, x DEVICE double (n x nrhs, leading dims ldb, ldx),
+ * borrowed until the request completes; refactor != 0 factorizes even if a
+ * factor is cached.  nrhs <= max_batch_rhs.  *ticket identifies it. */
+sgf_status sgf_server_submit(sgf_server s, int32_t op_id, int32_t refactor, int32_t nrhs, const double* b,
+                             int64_t ldb, double* x, int64_t ldx, double rtol, int32_t maxit, int64_t* ticket);
+/* Blocks until the request is done; fills info and, if not NULL, the HOST
+ * arrays iters[nrhs] and relres[nrhs].  A ticket can be waited for once.
+ * A request whose memory need exceeds the whole budget ends with status
+ * SGF_ENOMEM. */
+sgf_status sgf_server_wait(sgf_server s, int64_t ticket, sgf_request_info* info, int32_t* iters,
+                           double* relres);
+sgf_status sgf_server_get_stats(sgf_server s, sgf_server_stats* out);
+/* The clock of the t_* fields (monotonic seconds). */
+double sgf_server_clock(void);
+/* Finishes every queued request, stops the workers, destroys the operators. */
+sgf_status sgf_server_destroy(sgf_server s);
 
 #ifdef __cplusplus
 }

@@ -10,7 +10,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libsgf.so")
-SOURCES = [os.path.join(HERE, "csrc", "sgf_lib.hip")]
+SOURCES = [os.path.join(HERE, "csrc", "sgf_lib.hip"), os.path.join(HERE, "csrc", "sgf_server.cpp")]
 HEADERS = [os.path.join(HERE, "csrc", f) for f in ("sgf_kernels.hpp", "sgf_plan.hpp", "sgf_tiled.hpp")] + \
     [os.path.join(ROOT, "include", "sgf.h")]
 

@@ -1231,6 +1231,22 @@ void dot_cols(sgf_handle h, const double* a, const double* b, int nrhs, double* 
   });
 }
 
+// Device memory held by the handle.
+int64_t device_bytes(sgf_handle h) {
+  int64_t b = 0;
+  for (const DevBuf* x : {&h->d_perm, &h->d_rowptr, &h->d_colidx, &h->d_vals, &h->d_csrdst, &h->d_coords, &h->d_fail,
+                          &h->y, &h->tscr, &h->cg_r, &h->cg_z, &h->cg_p, &h->cg_ap, &h->cg_part, &h->cg_st,
+                          &h->cg_scal, &h->top64, &h->topz, &h->topu, &h->d_topdesc, &h->d_toptf})
+    b += x->bytes;
+  for (const auto& D : h->lev)
+    for (const DevBuf* x : {&D.arena, &D.scratch, &D.cf, &D.nbuf, &D.ltphi, &D.tau, &D.phi, &D.rank, &D.elim,
+                            &D.pairs, &D.schur, &D.comp, &D.compnbr, &D.sepacc, &D.sepsrc, &D.capply, &D.slots,
+                            &D.nslots, &D.blkmap, &D.phimap, &D.slotptr, &D.phioff, &D.tb, &D.active, &D.tofcomp,
+                            &D.tf, &D.zt, &D.uw, &D.ctf})
+      b += x->bytes;
+  return b;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1563,6 +1579,71 @@ sgf_status sgf_pcg_solve(sgf_handle h, int32_t nrhs, const double* b, int64_t ld
   return SGF_OK;
 }
 
+sgf_status sgf_release(sgf_handle h) {
+  if (!h) return fail(SGF_EINVAL, "NULL handle");
+  return guard([&] {
+    h->drop_graph();
+    h->lev.clear();
+    for (DevBuf* b : {&h->d_perm, &h->d_rowptr, &h->d_colidx, &h->d_vals, &h->d_csrdst, &h->d_coords, &h->d_fail,
+                      &h->y, &h->tscr, &h->cg_r, &h->cg_z, &h->cg_p, &h->cg_ap, &h->cg_part, &h->cg_st,
+                      &h->cg_scal, &h->top64, &h->topz, &h->topu, &h->d_topdesc, &h->d_toptf})
+      b->release();
+    h->plan.levels.resize(1);
+    h->plan.parts.resize(1);
+    h->dev_static = false;
+    h->factored = false;
+    h->top_tiled = false;
+    ++h->epoch;
+  });
+}
+
+sgf_status sgf_estimate_bytes(sgf_handle h, int32_t nrhs, int64_t* bytes) {
+  if (!h || !bytes || nrhs < 1) return fail(SGF_EINVAL, "bad estimate arguments");
+  return guard([&] {
+    const double e = (double)h->esz;
+    const int64_t n = h->plan.n;
+    double work = (double)nrhs * (n * e + 4.0 * n * 8 + 3.0 * n * 8);
+    if (h->factored) {
+      *bytes = device_bytes(h) + (int64_t)work;
+      return;
+    }
+    // plan every level with the largest rank each separator can have
+    // (min(|B|, columns of N)): an upper bound of the factor's memory
+    sgf::Plan& P = h->plan;
+    P.levels.resize(1);
+    P.parts.resize(1);
+    for (size_t q = 1; q < h->lev.size(); ++q) h->lev[q].uploaded = false;
+    P.max_node = 0;
+    for (int sz : P.levels[0].size) P.max_node = std::max<int64_t>(P.max_node, sz);
+    std::vector<sgf::CopyDesc> bm, pm;
+    double tot = (double)h->nnz * (8 + 8 + 4) + (n + 1) * 8.0 + n * 8.0 + (double)P.n_nodes * P.opt.dim * 8;
+    double tmax = 0;
+    for (;;) {
+      sgf::Level& L = P.levels.back();
+      tot += e * (double)(L.front_elems + L.blk_elems + L.scratch_elems + L.cf_elems + L.n_elems + L.ltphi_elems +
+                          L.tau_elems + L.phi_elems);
+      tmax = std::max<double>(tmax, (double)L.t_elems);
+      if (L.top) {
+        const double R = L.elim.empty() ? 0 : L.elim[0].m;
+        tot += 2.0 * R * R * 8 + (double)nrhs * R * 8;
+        break;
+      }
+      if (level_tiled(h, L))
+        for (const auto& d : L.elim) tot += e * ((double)d.m * d.m + (double)d.m * nrhs);
+      L.rank.assign(L.comp.size(), 0);
+      for (size_t c = 0; c < L.comp.size(); ++c) {
+        L.rank[c] = std::min(L.comp[c].s, L.comp[c].c);
+        tot += e * (double)L.comp[c].s * L.comp[c].s;   // T_B if it compresses
+      }
+      sgf::plan_next_level(P, bm, pm);
+    }
+    P.levels.resize(1);
+    P.parts.resize(1);
+    // descriptor tables and index maps: a few percent of the factor
+    *bytes = (int64_t)(1.05 * tot + work + tmax * nrhs * e);
+  });
+}
+
 sgf_status sgf_get_info(sgf_handle h, sgf_info* info) {
   if (!h || !info) return fail(SGF_EINVAL, "NULL handle or info");
   std::memset(info, 0, sizeof(*info));
@@ -1576,6 +1657,7 @@ sgf_status sgf_get_info(sgf_handle h, sgf_info* info) {
   info->apply_bytes = h->apply_bytes;
   info->failed_cluster = h->failed_cluster;
   info->failed_level = h->failed_level;
+  info->device_bytes = device_bytes(h);
   return SGF_OK;
 }
 

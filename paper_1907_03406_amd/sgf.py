@@ -21,7 +21,9 @@ FP64, FP32 = 0, 1
 EXPORTED = ["sgf_default_options", "sgf_analyze", "sgf_factorize_numeric", "sgf_factorize", "sgf_autotune",
             "sgf_apply", "sgf_multiply", "sgf_pcg_solve", "sgf_spmv", "sgf_get_info",
             "sgf_get_perm", "sgf_get_level", "sgf_plan_dry_run", "sgf_profile_enable", "sgf_profile_read",
-            "sgf_set_apply_graph",
+            "sgf_set_apply_graph", "sgf_release", "sgf_estimate_bytes",
+            "sgf_server_default_options", "sgf_server_create", "sgf_server_add_operator", "sgf_server_submit",
+            "sgf_server_wait", "sgf_server_get_stats", "sgf_server_clock", "sgf_server_destroy",
             "sgf_destroy", "sgf_status_str", "sgf_last_error"]
 
 RANK_FN = ctypes.CFUNCTYPE(ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p)
@@ -40,12 +42,30 @@ class Info(ctypes.Structure):
                 ("factor_entries", ctypes.c_int64), ("factor_bytes", ctypes.c_int64),
                 ("compressed", ctypes.c_int64), ("factor_flops", ctypes.c_double),
                 ("apply_bytes", ctypes.c_double), ("failed_cluster", ctypes.c_int32),
-                ("failed_level", ctypes.c_int32)]
+                ("failed_level", ctypes.c_int32), ("device_bytes", ctypes.c_int64)]
 
 
 class KernelStat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("ms", ctypes.c_double),
                 ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+
+class ServerOptions(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_int64), ("slots", ctypes.c_int32), ("max_batch_rhs", ctypes.c_int32)]
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_int64), ("op", ctypes.c_int32), ("nrhs", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("factorized", ctypes.c_int32), ("batch_rhs", ctypes.c_int32),
+                ("slot", ctypes.c_int32), ("iters_max", ctypes.c_int32), ("relres_max", ctypes.c_double),
+                ("t_submit", ctypes.c_double), ("t_start", ctypes.c_double), ("t_end", ctypes.c_double),
+                ("t_factor", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("held_bytes", ctypes.c_int64), ("peak_bytes", ctypes.c_int64), ("evictions", ctypes.c_int64),
+                ("factorizations", ctypes.c_int64), ("batches", ctypes.c_int64), ("queued", ctypes.c_int64),
+                ("cached_operators", ctypes.c_int64)]
 
 
 class SgfError(RuntimeError):
@@ -76,6 +96,16 @@ def load_library(path=LIB_PATH):
         "sgf_plan_dry_run": (I32, [H, RANK_FN, P]),
         "sgf_profile_enable": (I32, [H, I32]),
         "sgf_set_apply_graph": (I32, [H, I32]),
+        "sgf_release": (I32, [H]),
+        "sgf_estimate_bytes": (I32, [H, I32, P]),
+        "sgf_server_default_options": (None, [ctypes.POINTER(ServerOptions)]),
+        "sgf_server_create": (I32, [ctypes.POINTER(ServerOptions), ctypes.POINTER(H)]),
+        "sgf_server_add_operator": (I32, [H, I64, P, P, P, P, ctypes.POINTER(Options), P]),
+        "sgf_server_submit": (I32, [H, I32, I32, I32, P, I64, P, I64, D, I32, P]),
+        "sgf_server_wait": (I32, [H, I64, ctypes.POINTER(RequestInfo), P, P]),
+        "sgf_server_get_stats": (I32, [H, ctypes.POINTER(ServerStats)]),
+        "sgf_server_clock": (D, []),
+        "sgf_server_destroy": (I32, [H]),
         "sgf_profile_read": (I32, [H, ctypes.POINTER(KernelStat), I32, P]),
         "sgf_destroy": (I32, [H]),
         "sgf_status_str": (ctypes.c_char_p, [I32]),
@@ -203,6 +233,15 @@ class Solver:
         cb = RANK_FN(lambda t, cell, size, ctx: int(rank_of(t, cell, size)))
         _check(_lib.sgf_plan_dry_run(self.h, cb, None))
 
+    def release(self):
+        """Free all device memory of the handle (the analysis stays)."""
+        _check(_lib.sgf_release(self.h))
+
+    def estimate_bytes(self, nrhs=1):
+        b = ctypes.c_int64()
+        _check(_lib.sgf_estimate_bytes(self.h, int(nrhs), ctypes.byref(b)))
+        return b.value
+
     def set_apply_graph(self, enable=True):
         """Replay the apply sweep as a captured HIP graph (default) or launch directly."""
         _check(_lib.sgf_set_apply_graph(self.h, 1 if enable else 0))
@@ -227,3 +266,70 @@ class Solver:
         out = [np.zeros(c, dtype=np.int32) for _ in range(4)]
         _check(_lib.sgf_get_level(self.h, t, ctypes.byref(cnt), *[_ptr(a) for a in out]))
         return dict(zip(("cell", "type", "size", "rank"), out))
+
+
+class Server:
+    """Serving loop of the library (sgf_server_*): operators registered once,
+    factorize / solve requests queued and run by worker streams under an HBM
+    budget, solves of one operator coalesced into multi-column PCGs."""
+
+    def __init__(self, hbm_budget=200 << 30, slots=4, max_batch_rhs=16):
+        o = ServerOptions()
+        _lib.sgf_server_default_options(ctypes.byref(o))
+        o.hbm_budget, o.slots, o.max_batch_rhs = int(hbm_budget), int(slots), int(max_batch_rhs)
+        h = ctypes.c_void_p()
+        _check(_lib.sgf_server_create(ctypes.byref(o), ctypes.byref(h)))
+        self.h = h
+        self._keep = {}
+
+    def add_operator(self, prob, **kw):
+        """Register a problem (its CSR pattern, values and coordinates)."""
+        opt = make_options(prob.dim, prob.grid, prob.dpn, **kw)
+        ip = np.ascontiguousarray(prob.indptr, dtype=np.int64)
+        ix = np.ascontiguousarray(prob.indices, dtype=np.int32)
+        va = np.ascontiguousarray(prob.data, dtype=np.float64)
+        co = np.ascontiguousarray(prob.coords, dtype=np.float64)
+        op = ctypes.c_int32()
+        _check(_lib.sgf_server_add_operator(self.h, prob.n, _ptr(ip), _ptr(ix), _ptr(va), _ptr(co), ctypes.byref(opt),
+                                            ctypes.byref(op)))
+        return op.value
+
+    def submit(self, op, b, x, rtol=1e-8, maxit=1000, refactor=False):
+        """b, x: device float64 tensors of shape (nrhs, n) (contiguous rows =
+        columns of the n x nrhs problem); kept alive until wait()."""
+        nrhs, n = (1, b.shape[0]) if b.dim() == 1 else (b.shape[0], b.shape[1])
+        t = ctypes.c_int64()
+        _check(_lib.sgf_server_submit(self.h, int(op), 1 if refactor else 0, nrhs, _ptr(b), n, _ptr(x), n,
+                                      float(rtol), int(maxit), ctypes.byref(t)))
+        self._keep[t.value] = (b, x, nrhs)
+        return t.value
+
+    def wait(self, ticket):
+        b, x, nrhs = self._keep.pop(ticket)
+        info = RequestInfo()
+        it = np.zeros(nrhs, dtype=np.int32)
+        rel = np.zeros(nrhs, dtype=np.float64)
+        _check(_lib.sgf_server_wait(self.h, int(ticket), ctypes.byref(info), _ptr(it), _ptr(rel)))
+        d = {f: getattr(info, f) for f, _ in RequestInfo._fields_}
+        d["iters"], d["relres"] = it, rel
+        return d
+
+    def stats(self):
+        st = ServerStats()
+        _check(_lib.sgf_server_get_stats(self.h, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_}
+
+    @staticmethod
+    def clock():
+        return _lib.sgf_server_clock()
+
+    def close(self):
+        if self.h:
+            _lib.sgf_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,122 @@
+"""Serving form through the C ABI (sgf_server_*): continuous batching of
+factorize / solve requests of several operators on one GPU under an HBM
+budget.  Checks: every request converges to the requested relative
+residual; a request's result is the same alone and in a mix of concurrent,
+coalesced requests with evictions (bar: 1e-12 relative, columns of a batched
+PCG are computed independently); the FP32 factor / FP64 CG solution agrees
+with a direct solve; memory that can never fit is refused."""
+import numpy as np
+import pytest
+
+from sgf_inputs import problems as P
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+sgf = pytest.importorskip("paper_1907_03406_amd.sgf")
+
+TOL = 1e-8
+
+
+def _ops():
+    return [
+        (P.poisson_fd((96, 80), P.gaussian_field_fourier(1, 2)), dict(q=2, leaf=8)),
+        (P.poisson_fd((16, 16, 16), P.blocky_log_field(2, 3)), dict(q=1, leaf=4)),
+        (P.elasticity_q1(8, seed=3, n_incl=3), dict(q=1, leaf=3)),
+    ]
+
+
+def _rhs(n, k, seed):
+    return torch.from_numpy(np.stack([P.random_rhs(seed, n, j) for j in range(k)], axis=0)).cuda()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _solo(prob, kw, b):
+    srv = sgf.Server(slots=1)
+    op = srv.add_operator(prob, precision=sgf.FP32, **kw)
+    x = torch.zeros_like(b)
+    info = srv.wait(srv.submit(op, b, x, rtol=TOL))
+    srv.close()
+    assert info["status"] == 0
+    return x.cpu().numpy()
+
+
+def test_result_is_the_same_alone_and_in_the_mix():
+    ops = _ops()
+    probe = (0, _rhs(ops[0][0].n, 3, 77))
+    x_alone = _solo(ops[0][0], ops[0][1], probe[1])
+    # budget: the largest admission bound (an upper bound from the plan) plus
+    # a little, so that starting an operator usually evicts another
+    est = []
+    for prob, kw in ops:
+        s = sgf.Solver.from_problem(prob, precision=sgf.FP32, **kw)
+        est.append(s.estimate_bytes(16))
+        s.close()
+    budget = int(max(est) + (4 << 20))
+    srv = sgf.Server(hbm_budget=budget, slots=4, max_batch_rhs=16)
+    ids = [srv.add_operator(prob, precision=sgf.FP32, **kw) for prob, kw in ops]
+    rng = np.random.default_rng(5)
+    reqs = []
+    for k in range(30):
+        o = int(rng.integers(0, 3))
+        nr = int(rng.integers(1, 5))
+        b = _rhs(ops[o][0].n, nr, 100 + k)
+        reqs.append((o, b, torch.zeros_like(b), bool(rng.random() < 0.3)))
+        if k == 12:
+            reqs.append((probe[0], probe[1], torch.zeros_like(probe[1]), False))
+    tickets = [srv.submit(ids[o], b, x, rtol=TOL, refactor=rf) for o, b, x, rf in reqs]
+    infos = [srv.wait(t) for t in tickets]
+    st = srv.stats()
+    srv.close()
+    for (o, b, x, _), inf in zip(reqs, infos):
+        assert inf["status"] == 0, inf
+        assert inf["relres_max"] < TOL
+    x_mix = reqs[13][2].cpu().numpy()
+    diff = np.abs(x_mix - x_alone).max()
+    print(f"alone vs mix: max |dx| {diff:.1e}, batches {st['batches']}, evictions {st['evictions']}, "
+          f"factorizations {st['factorizations']}, peak {st['peak_bytes'] / 2**20:.0f} MiB of {budget / 2**20:.0f}")
+    assert _rel(x_mix, x_alone) <= 1e-12
+    assert any(inf["batch_rhs"] > inf["nrhs"] for inf in infos), "no solves were coalesced"
+    assert st["evictions"] > 0
+    assert st["peak_bytes"] <= budget
+    # the FP32-factor / FP64-CG solution against a direct sparse solve
+    import scipy.sparse.linalg as spla
+    A = ops[0][0].csr()
+    xd = spla.spsolve(A.tocsc(), probe[1].cpu().numpy()[0])
+    assert _rel(x_alone[0], xd) <= 1e-6
+
+
+def test_request_that_can_never_fit_is_refused():
+    prob, kw = _ops()[0]
+    srv = sgf.Server(hbm_budget=1 << 20, slots=2)
+    op = srv.add_operator(prob, precision=sgf.FP32, **kw)
+    b = _rhs(prob.n, 1, 3)
+    info = srv.wait(srv.submit(op, b, torch.zeros_like(b)))
+    srv.close()
+    assert info["status"] == sgf.SGF_ENOMEM
+
+
+def test_refactorize_after_eviction_gives_the_same_solution():
+    # two operators of the same shape (equal admission bounds) under a budget
+    # that holds one: each request evicts the other operator's factor
+    ops = [(P.poisson_fd((96, 80), P.gaussian_field_fourier(s, 2)), dict(q=2, leaf=8)) for s in (1, 4)]
+    s = sgf.Solver.from_problem(ops[0][0], precision=sgf.FP32, **ops[0][1])
+    est = s.estimate_bytes(2)
+    s.close()
+    srv = sgf.Server(hbm_budget=int(est + (1 << 20)), slots=1)
+    ids = [srv.add_operator(prob, precision=sgf.FP32, **kw) for prob, kw in ops]
+    b0 = _rhs(ops[0][0].n, 2, 9)
+    outs = []
+    for o in (0, 1, 0):
+        b = b0 if o == 0 else _rhs(ops[1][0].n, 2, 10)
+        x = torch.zeros_like(b)
+        inf = srv.wait(srv.submit(ids[o], b, x, rtol=TOL))
+        assert inf["status"] == 0 and inf["factorized"] == 1
+        outs.append(x.cpu().numpy())
+    st = srv.stats()
+    srv.close()
+    assert st["evictions"] >= 2
+    assert np.array_equal(outs[0], outs[2])
