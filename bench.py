@@ -35,7 +35,134 @@ WORKLOADS = {
                      "boxes; q=1, leaf 8^3; CG to 1e-8",
     "elasticity3d_48": "3D linear elasticity, Q1 hexahedra on 48^3 nodes (n=324,864), E=1/100 with 20 random "
                        "inclusions, nu=0.3, x=0 clamped; q=1, leaf 6; CG to 1e-8",
+    "serving": "request stream with Poisson arrivals at 80% of the measured capacity: operators half 2D "
+               "(128^2..1024^2, Fourier field, q=2, leaf 16) and half 3D (32^3..96^3, 10^u box field, q=1, leaf 8); "
+               "30% new operators (factorize + solve), 70% 1-16 rhs on operators seen before; 200 GiB HBM "
+               "budget; FP32 factor / FP64 CG to 1e-8",
 }
+
+SERVE_2D = (128, 256, 512, 1024)
+SERVE_3D = (32, 48, 64, 96)
+
+
+def run_serving(a):
+    """Serving workload: the library's request loop (sgf_server_*) fed by a
+    seeded open-loop arrival process.  Coefficient fields come from a pool of
+    `--pool` seeds per size (generated before the clock starts); every new
+    operator is registered afresh (own analysis and factorization)."""
+    import torch
+    from paper_1907_03406_amd import sgf
+    from sgf_inputs.problems import config_problem, random_rhs, poisson_fd, gaussian_field_fourier, blocky_log_field
+    from sgf_inputs.rng import uniform
+    t0 = time.perf_counter()
+    pool = []
+    for N in SERVE_2D:
+        for k in range(a.pool):
+            pool.append((poisson_fd((N, N), gaussian_field_fourier(100 + k, 2)), dict(q=2, leaf=16)))
+    for N in SERVE_3D:
+        for k in range(a.pool):
+            pool.append((poisson_fd((N, N, N), blocky_log_field(200 + k, 3)), dict(q=1, leaf=8)))
+    t_gen = time.perf_counter() - t0
+    nreq = a.requests
+    # seeded request stream: kind, operator pick, pool pick, nrhs (streams 3000..3004)
+    u_kind = uniform(a.seed, 3000, nreq + 64)
+    u_pick = uniform(a.seed, 3001, nreq + 64)
+    u_pool = uniform(a.seed, 3002, nreq + 64)
+    u_rhs = uniform(a.seed, 3003, nreq + 64)
+    u_gap = uniform(a.seed, 3004, nreq + 64)
+    dev = torch.device("cuda:0")
+    rhs_cache = {}
+
+    def rhs_for(n, k, j):
+        key = (n, k)
+        if key not in rhs_cache:
+            rhs_cache[key] = torch.from_numpy(np.stack([random_rhs(a.seed, n, c) for c in range(16)], axis=0)).to(dev)
+        return rhs_cache[key][:k]
+
+    def stream(srv, count, offset):
+        ops = []
+        reqs = []
+        for i in range(offset, offset + count):
+            if not ops or u_kind[i] < 0.3:
+                half = u_pool[i] < 0.5
+                sizes = len(SERVE_2D) if half else len(SERVE_3D)
+                base = 0 if half else len(SERVE_2D) * a.pool
+                pidx = base + int(u_pool[i] * 2 % 1.0 * sizes * a.pool) % (sizes * a.pool)
+                reqs.append(("new", pidx))
+                ops.append(pidx)
+            else:
+                reqs.append(("old", int(u_pick[i] * len(ops)) % len(ops)))
+            reqs[-1] += (1 + int(u_rhs[i] * 16) % 16,)
+        return reqs
+
+    def run(srv, reqs, rate):
+        ids, opsrc = [], []
+        pending = []
+        t_start = time.monotonic()
+        t_next = t_start
+        for i, (kind, ref, k) in enumerate(reqs):
+            if rate:
+                t_next += -np.log(max(1.0 - u_gap[i], 1e-12)) / rate
+                d = t_next - time.monotonic()
+                if d > 0:
+                    time.sleep(d)
+            arrival = time.monotonic()
+            if kind == "new":
+                prob, kw = pool[ref]
+                ids.append(srv.add_operator(prob, precision=sgf.FP32, **kw))
+                opsrc.append(prob)
+                op = ids[-1]
+                prob_n = prob.n
+            else:
+                op = ids[ref]
+                prob_n = opsrc[ref].n
+            b = rhs_for(prob_n, k, i)
+            x = torch.zeros_like(b)
+            pending.append((srv.submit(op, b, x, rtol=1e-8, maxit=2000), arrival, k, x))
+        out = []
+        for t, arrival, k, x in pending:
+            inf = srv.wait(t)
+            out.append((inf, arrival, k))
+        t_end = time.monotonic()
+        return out, t_start, t_end
+
+    srv = sgf.Server(hbm_budget=200 << 30, slots=a.slots, max_batch_rhs=16)
+    # capacity: a closed batch submitted at once (all requests queued together)
+    cal = stream(srv, a.calibration, nreq)
+    res, ts, te = run(srv, cal, None)
+    cap_req_s = len(cal) / (te - ts)
+    rate = 0.8 * cap_req_s
+    srv.close()
+    srv = sgf.Server(hbm_budget=200 << 30, slots=a.slots, max_batch_rhs=16)
+    reqs = stream(srv, nreq, 0)
+    res, ts, te = run(srv, reqs, rate)
+    st = srv.stats()
+    srv.close()
+    bad = [inf for inf, _, _ in res if inf["status"] != 0 or inf["relres_max"] >= 1e-8]
+    lat = np.array([(inf["t_end"] - arrival) * 1e3 for inf, arrival, _ in res])
+    solves = sum(k for _, _, k in res)
+    makespan = te - ts
+    out = {
+        "metric": "PCG solves/s (serving: factorize/solve request stream, each rhs to 1e-8 relative residual)",
+        "value": round(solves / makespan, 3),
+        "unit": "solves/s",
+        "n_gpus": 1, "steps": nreq, "warmup": a.calibration,
+        "ms_per_step": round(makespan / nreq * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"serving: {WORKLOADS['serving']}", "requests": nreq, "slots": a.slots,
+                   "pool_fields_per_size": a.pool, "seed": a.seed,
+                   "step": "one request (arrival to completion); value = right-hand sides solved / makespan"},
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 2), "p99": round(float(np.percentile(lat, 99)), 2),
+                       "mean": round(float(lat.mean()), 2)},
+        "arrival_rate_req_s": round(rate, 3), "capacity_req_s": round(cap_req_s, 3),
+        "requests_failed": len(bad),
+        "new_operators": sum(1 for r in reqs if r[0] == "new"),
+        "mean_batch_rhs": round(float(np.mean([inf["batch_rhs"] for inf, _, _ in res])), 2),
+        "server": st, "problem_gen_s": round(t_gen, 1),
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
 
 
 def source_hash():
@@ -194,6 +321,10 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="skip the per-level path autotuner")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device-to-device copy of 1 GiB (reference for HBM byte counters)")
+    ap.add_argument("--requests", type=int, default=300, help="serving: requests in the timed stream")
+    ap.add_argument("--calibration", type=int, default=40, help="serving: closed-batch requests to measure capacity")
+    ap.add_argument("--slots", type=int, default=4, help="serving: concurrent requests on the device")
+    ap.add_argument("--pool", type=int, default=2, help="serving: coefficient fields per operator size")
     a = ap.parse_args()
     if a.copy_calibration:
         import torch
@@ -212,6 +343,9 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
+    if a.config == "serving":
+        run_serving(a)
+        return
     from sgf_inputs.problems import config_problem
     t0 = time.perf_counter()
     probs = [config_problem(a.config, seed=a.seed + i)[0] for i in range(a.operators)]

@@ -301,7 +301,9 @@ typedef struct {
 void sgf_server_default_options(sgf_server_options* opt);
 sgf_status sgf_server_create(const sgf_server_options* opt, sgf_server* out);
 /* Registers an operator: the arguments of sgf_analyze plus its values
- * (HOST double[nnz], copied).  *op_id receives its id. */
+ * (HOST double[nnz]); all are copied.  Its analysis runs on a worker, ahead
+ * of its first request (a failing analysis fails that operator's requests
+ * with its status).  *op_id receives its id. */
 sgf_status sgf_server_add_operator(sgf_server s, int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
                                    const double* vals, const double* coords, const sgf_options* opt,
                                    int32_t* op_id);

@@ -45,9 +45,14 @@ double now_s() {
 }
 
 struct Op {
-  sgf_handle h = nullptr;
+  sgf_handle h = nullptr;     // created by the first worker that needs it
   int64_t n = 0, nnz = 0;
   std::vector<double> vals;   // host copy of the values, for (re)factorization
+  std::vector<int64_t> row_ptr;
+  std::vector<int32_t> col_idx;
+  std::vector<double> coords;
+  sgf_options opt{};
+  sgf_status analysis = SGF_OK;
   bool busy = false;          // a slot is working on it
   bool factored = false;      // factor resident on the device
   int64_t held = 0;           // device bytes it holds (0 when evicted)
@@ -134,6 +139,39 @@ void sgf_server_s::run(int slot) {
         Op* o = ops[(*it)->op].get();
         if (o->busy) continue;
         const auto& r = *it;
+        if (!o->h && o->analysis == SGF_OK) {
+          // symbolic analysis (host only) of a new operator, outside the lock
+          o->busy = true;
+          lk.unlock();
+          sgf_handle h = nullptr;
+          sgf_status a = sgf_analyze(o->n, o->row_ptr.data(), o->col_idx.data(), o->coords.data(), &o->opt, &h);
+          int64_t e1 = 0, e2 = 0;
+          if (a == SGF_OK && ((a = sgf_estimate_bytes(h, 1, &e1)) != SGF_OK || (a = sgf_estimate_bytes(h, 2, &e2)) != SGF_OK)) {
+            sgf_destroy(h);
+            h = nullptr;
+          }
+          lk.lock();
+          o->busy = false;
+          o->analysis = a;
+          if (a == SGF_OK) {
+            o->h = h;
+            o->est1 = e1;
+            o->per_rhs = std::max<int64_t>(e2 - e1, 0);
+            o->row_ptr = {};
+            o->col_idx = {};
+            o->coords = {};
+          }
+          cv_work.notify_all();
+          goto rescan;
+        }
+        if (o->analysis != SGF_OK) {
+          r->info.status = o->analysis;
+          r->info.t_start = r->info.t_end = now_s();
+          r->done = true;
+          queue.erase(it);
+          cv_done.notify_all();
+          goto rescan;
+        }
         const bool f = r->refactor || !o->factored;
         // the batch: this request and the following solves of the same
         // operator (up to the next refactorization), max_batch_rhs columns
@@ -304,22 +342,16 @@ sgf_status sgf_server_create(const sgf_server_options* o, sgf_server* out) {
 sgf_status sgf_server_add_operator(sgf_server s, int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
                                    const double* vals, const double* coords, const sgf_options* opt,
                                    int32_t* op_id) {
-  if (!s || !vals || !op_id) return SGF_EINVAL;
-  sgf_handle h = nullptr;
-  sgf_status st = sgf_analyze(n, row_ptr, col_idx, coords, opt, &h);
-  if (st != SGF_OK) return st;
+  if (!s || !vals || !op_id || !row_ptr || !col_idx || !coords || !opt || n < 1 || opt->dofs_per_node < 1)
+    return SGF_EINVAL;
   auto op = std::make_unique<Op>();
-  int64_t e1 = 0, e2 = 0;
-  if ((st = sgf_estimate_bytes(h, 1, &e1)) != SGF_OK || (st = sgf_estimate_bytes(h, 2, &e2)) != SGF_OK) {
-    sgf_destroy(h);
-    return st;
-  }
-  op->est1 = e1;
-  op->per_rhs = std::max<int64_t>(e2 - e1, 0);
-  op->h = h;
   op->n = n;
   op->nnz = row_ptr[n];
   op->vals.assign(vals, vals + op->nnz);
+  op->row_ptr.assign(row_ptr, row_ptr + n + 1);
+  op->col_idx.assign(col_idx, col_idx + op->nnz);
+  op->coords.assign(coords, coords + (n / opt->dofs_per_node) * opt->dim);
+  op->opt = *opt;
   std::lock_guard<std::mutex> g(s->mu);
   *op_id = (int32_t)s->ops.size();
   s->ops.push_back(std::move(op));
@@ -397,7 +429,8 @@ sgf_status sgf_server_destroy(sgf_server s) {
   }
   s->cv_work.notify_all();
   for (auto& t : s->workers) t.join();
-  for (auto& o : s->ops) sgf_destroy(o->h);
+  for (auto& o : s->ops)
+    if (o->h) sgf_destroy(o->h);
   delete s;
   return SGF_OK;
 }
