@@ -201,7 +201,7 @@ def run_form(probs, cfg, precision, steps, warmup, profile, seed=0, log=None, ti
     prob = probs[0]
     t0 = time.perf_counter()
     s = sgf.Solver.from_problem(prob, q=cfg["q"], leaf=cfg["leaf"],
-                                precision=sgf.FP32 if precision == "fp32" else sgf.FP64,
+                                precision={"fp32": sgf.FP32, "fp32_bf16n": sgf.FP32_BF16N, "fp64": sgf.FP64}[precision],
                                 tiled_min_rows=tiled_min_rows)
     t_an = time.perf_counter() - t0
     vals_all = [torch.from_numpy(p.data).to(dev) for p in probs]
@@ -269,7 +269,7 @@ def roofline(stats, precision, steps):
     if k["flops"] > 0:
         # the elimination kernels' flops are dense contractions on the matrix
         # cores (FP32 / FP64 MFMA peaks equal the vector peaks on this chip)
-        peak = FP32_PEAK_TFLOPS if precision == "fp32" else FP64_PEAK_TFLOPS
+        peak = FP64_PEAK_TFLOPS if precision == "fp64" else FP32_PEAK_TFLOPS
         ach = k["flops"] / (k["ms"] * 1e-3) / 1e12
         bound = "mfma" if name.startswith(("elim", "top", "comp_update")) else "alu"
         return {"kernel": name, "bound": bound, "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
@@ -309,7 +309,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="varcoef2d_1024", choices=sorted(WORKLOADS))
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp32_bf16n", "fp64"])
     ap.add_argument("--no-fp64-form", action="store_true", help="skip the plain FP64 comparison form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
@@ -382,12 +382,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if a.precision == "fp32" else "f64",
+        "dtype": "f64" if a.precision == "fp64" else "f32",
         "data": "synthetic",
         "config": {
             "workload": f"{a.config}: {WORKLOADS[a.config]}",
             "n": prob.n, "nnz": prob.nnz, "q": cfg["q"], "leaf": cfg["leaf"], "tol": cfg["tol"],
-            "factor_apply_dtype": "f32" if a.precision == "fp32" else "f64", "cg_dtype": "f64",
+            "factor_apply_dtype": {"fp32": "f32", "fp32_bf16n": "f32 (N from bf16 operands)", "fp64": "f64"}[a.precision],
+            "cg_dtype": "f64",
             "nrhs": main_form["nrhs"], "seed": a.seed, "operators": a.operators,
             "step": "numeric factorization of operator (step mod operators) + CG solve of nrhs fresh right-hand "
                     "sides (one batched PCG); value counts every right-hand side as a solve",

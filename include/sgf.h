@@ -51,8 +51,13 @@ typedef enum {
 enum { SGF_NEST_ALL_ALL = 0, SGF_NEST_2_ALL = 1 };
 /* When the hierarchy ends (Sec. 4.5 and Sec. 7). */
 enum { SGF_STOP_ROOT = 0, SGF_STOP_PAPER = 1 };
-/* Arithmetic of the factor and the apply; CG itself is always FP64. */
-enum { SGF_FP64 = 0, SGF_FP32 = 1 };
+/* Arithmetic of the factor and the apply; CG itself is always FP64, and so
+ * is the top node's Cholesky.  SGF_FP32_BF16N is SGF_FP32 with the
+ * compression matrix N (Eq. 4.5) formed from operands rounded to bfloat16
+ * (products accumulated in FP32); N only selects the kept subspace, whose
+ * accuracy then drops to about 2^-8, so the default rank threshold of that
+ * form is 1e-2. */
+enum { SGF_FP64 = 0, SGF_FP32 = 1, SGF_FP32_BF16N = 2 };
 
 typedef struct {
   int32_t dim;                 /* 2 or 3                                           */
@@ -71,7 +76,8 @@ typedef struct {
                                   threshold.  Fronts that do not fit one
                                   workgroup's LDS panel always take it.           */
   double rank_tol;             /* pivoted-QR rank threshold relative to |R_00|;
-                                  <= 0 selects 1e-12 (FP64) / 1e-6 (FP32)         */
+                                  <= 0 selects 1e-12 (FP64) / 1e-6 (FP32) /
+                                  1e-2 (FP32_BF16N)                              */
 } sgf_options;
 
 typedef struct {

@@ -17,6 +17,15 @@ constexpr int WG = 256;
 constexpr int WAVE = 64;
 constexpr double TIE_RTOL = 1e-10;
 
+// Nearest bfloat16 (ties to even) of an FP32 value, as FP32; FP64 values
+// pass through the FP32 rounding first.
+__device__ __forceinline__ float bf16_round(float x) {
+  unsigned u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return __uint_as_float(u & 0xffff0000u);
+}
+__device__ __forceinline__ double bf16_round(double x) { return (double)bf16_round((float)x); }
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
   for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
@@ -495,7 +504,7 @@ __global__ __launch_bounds__(WG) void k_compress(const CompDesc* __restrict__ D,
                                                  T* __restrict__ cf, T* __restrict__ nbuf, T* __restrict__ phi,
                                                  T* __restrict__ ltphi, T* __restrict__ tau_all,
                                                  int* __restrict__ rank, int pi, double rank_tol, int* fail,
-                                                 int prefactored) {
+                                                 int prefactored, int bf16n) {
   // Phi of the neighbours is read here and must not change during the launch.
   // With `prefactored`, L_B and L_B^{-1} M_BX are already in the front.
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -516,9 +525,13 @@ __global__ __launch_bounds__(WG) void k_compress(const CompDesc* __restrict__ D,
   // ---- N (Eq. 4.5) -----------------------------------------------------------
   for (int idx = threadIdx.x; idx < s * pi; idx += WG) {
     const int i = idx % s, p = idx / s;
-    T acc = 0;
-    for (int j = i; j < s; ++j) acc += F[j + (int64_t)i * ld] * PhB[j + (int64_t)p * s];
-    N[i + (int64_t)p * s] = acc;
+    T acc = 0, acc16 = 0;
+    for (int j = i; j < s; ++j) {
+      const T f = F[j + (int64_t)i * ld], ph = PhB[j + (int64_t)p * s];
+      acc += f * ph;
+      if (bf16n) acc16 += bf16_round(f) * bf16_round(ph);
+    }
+    N[i + (int64_t)p * s] = bf16n ? acc16 : acc;
     LtP[i + (int64_t)p * s] = acc;
   }
   for (int q = 0; q < d.nnb; ++q) {
@@ -527,7 +540,11 @@ __global__ __launch_bounds__(WG) void k_compress(const CompDesc* __restrict__ D,
     for (int idx = threadIdx.x; idx < s * pi; idx += WG) {
       const int i = idx % s, p = idx / s;
       T acc = 0;
-      for (int j = 0; j < x.s_x; ++j) acc += F[(x.row + j) + (int64_t)i * ld] * PhX[j + (int64_t)p * x.s_x];
+      if (bf16n)
+        for (int j = 0; j < x.s_x; ++j)
+          acc += bf16_round(F[(x.row + j) + (int64_t)i * ld]) * bf16_round(PhX[j + (int64_t)p * x.s_x]);
+      else
+        for (int j = 0; j < x.s_x; ++j) acc += F[(x.row + j) + (int64_t)i * ld] * PhX[j + (int64_t)p * x.s_x];
       N[i + (int64_t)(pi * (1 + q) + p) * s] = acc;
     }
   }

@@ -308,7 +308,8 @@ void check_options(const sgf_options* o, int64_t n) {
   if (o->q < 0 || o->q > 2) throw SgfError(SGF_EINVAL, "q must be 0, 1 or 2");
   if (o->leaf < 2) throw SgfError(SGF_EINVAL, "leaf must be > 1");
   if (o->scheme != SGF_NEST_ALL_ALL && o->scheme != SGF_NEST_2_ALL) throw SgfError(SGF_EINVAL, "unknown scheme");
-  if (o->precision != SGF_FP64 && o->precision != SGF_FP32) throw SgfError(SGF_EINVAL, "unknown precision");
+  if (o->precision != SGF_FP64 && o->precision != SGF_FP32 && o->precision != SGF_FP32_BF16N)
+    throw SgfError(SGF_EINVAL, "unknown precision");
   if (o->stop_rule != SGF_STOP_ROOT && o->stop_rule != SGF_STOP_PAPER) throw SgfError(SGF_EINVAL, "unknown stop rule");
   if (n >= (int64_t)1 << 31) throw SgfError(SGF_EINVAL, "n must be below 2^31");
 }
@@ -813,7 +814,8 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
       launch(h, st, "compress", 0, 0, [&] {
         launch_compress<T>(nlds, nb, (unsigned)L.comp.size(), lds, st, D.comp.as<sgf::CompDesc>(),
                            D.compnbr.as<sgf::CompNbr>(), D.cf.as<T>(), D.nbuf.as<T>(), D.phi.as<T>(), D.ltphi.as<T>(),
-                           D.tau.as<T>(), D.rank.as<int>(), P.pi, tol, h->d_fail.as<int>(), pre);
+                           D.tau.as<T>(), D.rank.as<int>(), P.pi, tol, h->d_fail.as<int>(), pre,
+                           P.opt.precision == SGF_FP32_BF16N ? 1 : 0);
       }, L.t);
       launch(h, st, "phi_commit", 0, 0, [&] {
         hipLaunchKernelGGL(sgf::k_phi_commit<T>, dim3((unsigned)L.comp.size()), dim3(sgf::WG), 0, st,
@@ -1307,7 +1309,8 @@ sgf_status sgf_analyze(int64_t n, const int64_t* row_ptr, const int32_t* col_idx
     o.compress_from_level = std::max(1, opt->compress_from_level);
     o.stop_rule = opt->stop_rule;
     o.precision = opt->precision;
-    o.rank_tol = opt->rank_tol > 0 ? opt->rank_tol : (opt->precision == SGF_FP64 ? 1e-12 : 1e-6);
+    o.rank_tol = opt->rank_tol > 0 ? opt->rank_tol
+                                   : (opt->precision == SGF_FP64 ? 1e-12 : opt->precision == SGF_FP32 ? 1e-6 : 1e-2);
     h->tiled_rows = opt->tiled_min_rows < 0 ? 1024 : opt->tiled_min_rows;
     h->esz = opt->precision == SGF_FP64 ? 8 : 4;
     h->plan.n = n;

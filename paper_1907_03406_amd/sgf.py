@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libsgf.so")
 SGF_OK, SGF_EINVAL, SGF_ENOTSPD, SGF_ENOMEM, SGF_EDEVICE, SGF_ENOCONV, SGF_ESTATE = range(7)
 NEST_ALL_ALL, NEST_2_ALL = 0, 1
 STOP_ROOT, STOP_PAPER = 0, 1
-FP64, FP32 = 0, 1
+FP64, FP32, FP32_BF16N = 0, 1, 2
 
 EXPORTED = ["sgf_default_options", "sgf_analyze", "sgf_factorize_numeric", "sgf_factorize", "sgf_autotune",
             "sgf_apply", "sgf_multiply", "sgf_pcg_solve", "sgf_spmv", "sgf_get_info",
