@@ -86,3 +86,18 @@ def test_planner_matches_oracle_hierarchy(kind, grid, leaf, q, dpn, stop):
         assert np.array_equal(g["type"], levels[t - 1].type[g["cell"]])
     top = s.level(nlev)
     assert top["size"].sum() == F.info["top_size"]
+
+
+def test_memory_estimate_is_host_only():
+    """sgf_estimate_bytes plans every level with the largest possible ranks
+    (host only): it grows with the right-hand sides and leaves the handle
+    able to plan again."""
+    p = P.poisson_fd((40, 36), P.gaussian_field_fourier(0, 2))
+    s = sgf.Solver.from_problem(p, q=1, leaf=4, precision=sgf.FP32)
+    e1, e4 = s.estimate_bytes(1), s.estimate_bytes(4)
+    assert 0 < e1 < e4
+    assert s.estimate_bytes(1) == e1
+    # an unfactored handle may be released (nothing to free) and still dry-run
+    s.release()
+    s.plan_dry_run(lambda t, cell, size: min(size, 3))
+    assert s.info()["levels"] >= 2 and s.info()["device_bytes"] == 0
