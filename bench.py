@@ -273,6 +273,16 @@ def roofline(stats, by_level, precision, steps):
         return None
     name, k = max(cand.items(), key=lambda kv: kv[1]["ms"])
     per = k["ms"] / max(k["launches"], 1)
+    peak_f = FP64_PEAK_TFLOPS if precision == "fp64" else FP32_PEAK_TFLOPS
+    # a kernel with both algorithmic flops and bytes is bound by whichever
+    # roof is lower at its arithmetic intensity (ridge = peak flops / HBM peak)
+    if k["flops"] > 0 and k["bytes"] > 0 and k["flops"] / k["bytes"] < peak_f * 1e12 / (HBM_PEAK_GBS * 1e9):
+        ach = k["bytes"] / (k["ms"] * 1e-3) / 1e9
+        return {"kernel": name, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic_for(name),
+                "intensity_flop_per_byte": round(k["flops"] / k["bytes"], 2),
+                "flops_tflops": round(k["flops"] / (k["ms"] * 1e-3) / 1e12, 3),
+                "avg_launch_ms": round(per, 4), "launches": k["launches"], "share_of_gpu_time": None}
     if k["flops"] > 0:
         # the elimination kernels' flops are dense contractions on the matrix
         # cores (FP32 / FP64 MFMA peaks equal the vector peaks on this chip)

@@ -72,7 +72,9 @@ typedef struct {
   int32_t precision;           /* SGF_FP64 (default) or SGF_FP32                   */
   int32_t tiled_min_rows;      /* levels whose largest front has at least this many
                                   rows are eliminated by the tiled multi-workgroup
-                                  path (0: every level); < 0 selects the built-in
+                                  path (0: every level, and every compressed
+                                  separator's apply uses the multi-workgroup
+                                  kernels too); < 0 selects the built-in
                                   threshold.  Fronts that do not fit one
                                   workgroup's LDS panel always take it.           */
   double rank_tol;             /* pivoted-QR rank threshold relative to |R_00|;

@@ -177,8 +177,12 @@ __global__ void k_phi_init(const int64_t* __restrict__ slot_ptr, const int64_t* 
 //  - the trailing matrix is updated from the LDS panel with 4 x 4 register
 //    tiles.  Three workgroup barriers per panel.
 // A non-positive pivot sets *fail = code and continues with pivot 1.
+// bw: lower bandwidth of the eliminated block C[0:m, 0:m] (m when dense).
+// The factor keeps that band, so in panel jb the rows [jb+nb+bw, m) are
+// zero: they are neither loaded, solved, written nor used in the update.
 template <typename T, int NB, bool DIAG_IN_REGS>
-__device__ void wg_potrf(T* __restrict__ C, int64_t ld, int R, int m, int nupd, T* lds, int* fail, int code) {
+__device__ void wg_potrf(T* __restrict__ C, int64_t ld, int R, int m, int nupd, T* lds, int* fail, int code,
+                         int bw) {
   const int tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
   T* invd = lds;          // NB reciprocal pivots
   T* pan = lds + NB;      // panel, column p at pan + p * pl
@@ -186,8 +190,12 @@ __device__ void wg_potrf(T* __restrict__ C, int64_t ld, int R, int m, int nupd, 
     const int nb = min(NB, m - jb);
     const int pr = R - jb;
     const int pl = (pr + 3) & ~3;
-    for (int idx = tid; idx < pr * nb; idx += WG) {
-      const int i = idx % pr, p = idx / pr;
+    // panel rows (local) [z0, z1) are zero; the live rows are [0, z0) and [z1, pr)
+    const int z0 = min(m, jb + nb + bw) - jb, z1 = m - jb;
+    const int live = z0 + (pr - z1);
+    for (int idx = tid; idx < live * nb; idx += WG) {
+      const int ii = idx % live, p = idx / live;
+      const int i = ii < z0 ? ii : ii - z0 + z1;
       pan[p * pl + i] = C[(jb + i) + (int64_t)(jb + p) * ld];
     }
     __syncthreads();
@@ -251,7 +259,8 @@ __device__ void wg_potrf(T* __restrict__ C, int64_t ld, int R, int m, int nupd, 
     }
     __syncthreads();
     // rows below the diagonal block: row i <- row i * L11^{-T}, one row per thread
-    for (int i = nb + tid; i < pr; i += WG) {
+    for (int ii = nb + tid; ii < live; ii += WG) {
+      const int i = ii < z0 ? ii : ii - z0 + z1;
       for (int j = 0; j < nb; ++j) {
         T acc = pan[j * pl + i];
 #pragma unroll 4
@@ -260,8 +269,9 @@ __device__ void wg_potrf(T* __restrict__ C, int64_t ld, int R, int m, int nupd, 
       }
     }
     __syncthreads();
-    for (int idx = tid; idx < pr * nb; idx += WG) {
-      const int i = idx % pr, p = idx / pr;
+    for (int idx = tid; idx < live * nb; idx += WG) {
+      const int ii = idx % live, p = idx / live;
+      const int i = ii < z0 ? ii : ii - z0 + z1;
       if (i >= p) C[(jb + i) + (int64_t)(jb + p) * ld] = pan[p * pl + i];
     }
     // trailing update C[i][l] -= sum_p L[i][p] L[l][p] on the matrix cores:
@@ -273,10 +283,12 @@ __device__ void wg_potrf(T* __restrict__ C, int64_t ld, int R, int m, int nupd, 
       typedef typename Mfma<T>::V V;
       const int RT = (R - r0 + 15) / 16, CT = (nupd - r0 + 15) / 16;
       const int li = lane % 16, lk = lane / 16;
+      const int zg0 = jb + z0, zg1 = jb + z1;   // zero rows / columns, global indices
       for (int t = w; t < RT * CT; t += WG / WAVE) {
         const int rt = t % RT, ct = t / RT;
         if (rt < ct) continue;
         const int i0 = r0 + 16 * rt, l0 = r0 + 16 * ct;
+        if ((i0 >= zg0 && i0 + 16 <= zg1) || (l0 >= zg0 && l0 + 16 <= zg1)) continue;
         const int row = i0 + li;
         V acc;
 #pragma unroll
@@ -285,7 +297,8 @@ __device__ void wg_potrf(T* __restrict__ C, int64_t ld, int R, int m, int nupd, 
           acc[v] = (row < R && col < nupd && row >= col) ? C[row + (int64_t)col * ld] : T(0);
         }
         const int arow = l0 + li;            // operand A': rows of the output columns
-        const bool aok = arow < nupd, bok = row < R;
+        const bool aok = arow < nupd && !(arow >= zg0 && arow < zg1);
+        const bool bok = row < R && !(row >= zg0 && row < zg1);
         for (int kb = 0; kb < nb; kb += 4) {
           const int p = kb + lk;
           const T a = (aok && p < nb) ? -pan[p * pl + (arow - jb)] : T(0);
@@ -355,7 +368,7 @@ __global__ __launch_bounds__(WG) void k_elim(const ElimDesc* __restrict__ D, T* 
   T* lds = reinterpret_cast<T*>(smem_raw);
   const ElimDesc d = D[blockIdx.x];
   const int R = d.m + d.k;
-  wg_potrf<T, NB, true>(arena + d.front_off, R, R, d.m, R, lds, fail, d.cluster);
+  wg_potrf<T, NB, true>(arena + d.front_off, R, R, d.m, R, lds, fail, d.cluster, d.bw);
 }
 
 // Subtract the interiors' Schur complements from the separator pair blocks,
@@ -515,7 +528,7 @@ __global__ __launch_bounds__(WG) void k_compress(const CompDesc* __restrict__ D,
   const int s = d.s, c = d.c;
   const int64_t ld = s + d.K;
   T* F = cf + d.cf_off;
-  if (!prefactored) wg_potrf<T, PNB, false>(F, ld, s + d.K, s, s, lds, fail, d.cluster);
+  if (!prefactored) wg_potrf<T, PNB, false>(F, ld, s + d.K, s, s, lds, fail, d.cluster, s);
   __syncthreads();
   T* Ng = nbuf + d.n_off;
   T* nrm = lds;
@@ -848,12 +861,13 @@ constexpr int DB = 64;
 constexpr int DLD = DB + 1;
 
 // Lower triangle of the diagonal block [jb, jb + nb) of C into D, with the
-// reciprocal of the diagonal stored on the diagonal.
+// reciprocal of the diagonal stored on the diagonal; entries more than bw
+// below the diagonal are known zeros and not read.
 template <typename T>
-__device__ __forceinline__ void stage_diag(const T* __restrict__ C, int64_t ld, int jb, int nb, T* D) {
+__device__ __forceinline__ void stage_diag(const T* __restrict__ C, int64_t ld, int jb, int nb, T* D, int bw) {
   for (int idx = threadIdx.x; idx < nb * nb; idx += WG) {
     const int i = idx % nb, j = idx / nb;
-    const T c = i >= j ? C[(jb + i) + (int64_t)(jb + j) * ld] : T(0);
+    const T c = (i >= j && i - j <= bw) ? C[(jb + i) + (int64_t)(jb + j) * ld] : T(0);
     D[i + j * DLD] = (i == j) ? T(1) / c : c;
   }
 }
@@ -886,7 +900,7 @@ __global__ __launch_bounds__(WG) void k_apply_fwd(const ElimDesc* __restrict__ D
   const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
   for (int jb = 0; jb < m; jb += DB) {
     const int nb = min(DB, m - jb);
-    stage_diag(C, R, jb, nb, Dg);
+    stage_diag(C, R, jb, nb, Dg, d.bw);
     __syncthreads();
     if (w < nc) {
       // lane j finishes x_j at step j (scaled by its reciprocal pivot) and
@@ -902,7 +916,10 @@ __global__ __launch_bounds__(WG) void k_apply_fwd(const ElimDesc* __restrict__ D
       if (lane < nb) vc[jb + lane] = x;
     }
     __syncthreads();
-    for (int i = jb + nb + threadIdx.x; i < R; i += WG) {
+    // rows below the block: the band rows of L_I and all rows of W^T
+    const int band = min(m, jb + nb + d.bw) - (jb + nb);
+    for (int ii = threadIdx.x; ii < band + k; ii += WG) {
+      const int i = ii < band ? jb + nb + ii : m + (ii - band);
       const T* ci = C + i + (int64_t)jb * R;
       T acc[RC];
 #pragma unroll
@@ -950,6 +967,7 @@ __global__ __launch_bounds__(WG) void k_apply_bwd(const ElimDesc* __restrict__ D
   const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
   for (int bj = (m + DB - 1) / DB - 1; bj >= 0; --bj) {
     const int jb = bj * DB, nb = min(DB, m - jb), below = jb + nb;
+    const int band = min(m, below + d.bw) - below;   // band rows of L_I below the block, then W^T
     // two columns per pass so that their loads and reductions overlap
     for (int j = 2 * w; j < nb; j += 2 * (WG / WAVE)) {
       const bool two = j + 1 < nb;
@@ -959,7 +977,8 @@ __global__ __launch_bounds__(WG) void k_apply_bwd(const ElimDesc* __restrict__ D
 #pragma unroll
       for (int c = 0; c < RC; ++c) a0[c] = a1[c] = 0;
 #pragma unroll 4
-      for (int i = below + lane; i < R; i += WAVE) {
+      for (int ii = lane; ii < band + k; ii += WAVE) {
+        const int i = ii < band ? below + ii : m + (ii - band);
         const T c0v = cj[i], c1v = two ? ck[i] : T(0);
 #pragma unroll
         for (int c = 0; c < RC; ++c) {
@@ -978,7 +997,7 @@ __global__ __launch_bounds__(WG) void k_apply_bwd(const ElimDesc* __restrict__ D
           }
         }
     }
-    stage_diag(C, R, jb, nb, Dg);
+    stage_diag(C, R, jb, nb, Dg, d.bw);
     __syncthreads();
     if (w < nc) {
       T* vc = v + w * Rp;
@@ -1001,17 +1020,23 @@ __global__ __launch_bounds__(WG) void k_apply_bwd(const ElimDesc* __restrict__ D
 
 // T_B = Q^T L_B^{-1} (s x s) for every compressed separator, so that each
 // apply of B is one dense matrix-vector product (forward) or its transpose.
+// Columns are independent: workgroup blockIdx.y forms columns
+// [CEB * blockIdx.y, CEB * (blockIdx.y + 1)) of T_B.
+constexpr int CEB = 64;
 template <typename T>
 __global__ __launch_bounds__(WG) void k_comp_explicit(const CompApply* __restrict__ A, const T* __restrict__ cf,
                                                       const T* __restrict__ nbuf, const T* __restrict__ tau_all,
                                                       T* __restrict__ tb) {
   const CompApply a = A[blockIdx.x];
-  const int s = a.s;
-  T* X = tb + a.t_off;
-  for (int idx = threadIdx.x; idx < s * s; idx += WG) X[idx] = (idx % s == idx / s) ? T(1) : T(0);
+  const int s = a.s, c0 = blockIdx.y * CEB;
+  if (c0 >= s) return;
+  const int nc = min(CEB, s - c0);
+  T* X = tb + a.t_off + (int64_t)c0 * s;
+  for (int idx = threadIdx.x; idx < s * nc; idx += WG) X[idx] = (idx % s == c0 + idx / s) ? T(1) : T(0);
   __syncthreads();
-  wg_trsm_lower(cf + a.cf_off, a.ld, s, X, s, s);
-  wg_apply_qt(nbuf + a.v_off, s, tau_all + a.tau_off, s, a.r, X, s, s);
+  // rows above c0 of L_B^{-1} I[:, c0:] are zero: solve only the trailing system
+  wg_trsm_lower(cf + a.cf_off + c0 + (int64_t)c0 * a.ld, a.ld, s - c0, X + c0, s, nc);
+  wg_apply_qt(nbuf + a.v_off, s, tau_all + a.tau_off, s, a.r, X, s, nc);
 }
 
 // mode 0: y_B <- T_B y_B; mode 1: y_B <- T_B^T y_B; rc columns per workgroup.
@@ -1072,6 +1097,84 @@ __global__ __launch_bounds__(WG) void k_comp_apply_t(const CompApply* __restrict
     const int i = idx % s, c = idx / s;
     y[(int64_t)(c0 + c) * ldy + sl[i]] = out[i + c * s];
   }
+}
+
+// Large separators: mode 0 out = T_B y_B (64 rows per workgroup, columns split
+// over the wavefronts), mode 1 out = T_B^T y_B (64 columns per workgroup, one
+// wavefront per column), rc right-hand sides; out goes to cw (ld ldc) and
+// k_comp_scatter moves it into y, so no workgroup overwrites an input another
+// one still reads.
+template <typename T>
+__global__ __launch_bounds__(WG) void k_comp_apply_big(const CompApply* __restrict__ A, const T* __restrict__ tb,
+                                                       const int32_t* __restrict__ slots, const T* __restrict__ y,
+                                                       int64_t ldy, int mode, int nrhs, int rc, T* __restrict__ cw,
+                                                       int64_t ldc) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const CompApply a = A[blockIdx.x];
+  const int s = a.s, sp = (s + 3) & ~3, b0 = blockIdx.y * 64;
+  if (b0 >= s) return;
+  const int q0 = blockIdx.z * rc, nc = min(rc, nrhs - q0);
+  T* ys = reinterpret_cast<T*>(smem_raw);
+  T* part = ys + sp * rc;
+  const T* X = tb + a.t_off;
+  const int32_t* sl = slots + a.slot_off;
+  for (int idx = threadIdx.x; idx < s * nc; idx += WG) {
+    const int i = idx % s, q = idx / s;
+    ys[i + q * sp] = y[(int64_t)(q0 + q) * ldy + sl[i]];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  if (mode == 0) {
+    const int i = b0 + lane;
+    T acc[RCM];
+#pragma unroll
+    for (int q = 0; q < RCM; ++q) acc[q] = 0;
+    if (i < s)
+      for (int j = w; j < s; j += WG / WAVE) {
+        const T x = X[i + (int64_t)j * s];
+#pragma unroll
+        for (int q = 0; q < RCM; ++q)
+          if (q < nc) acc[q] += x * ys[j + q * sp];
+      }
+#pragma unroll
+    for (int q = 0; q < RCM; ++q)
+      if (q < nc) part[(q * (WG / WAVE) + w) * WAVE + lane] = acc[q];
+    __syncthreads();
+    if (w < nc && i < s) {
+      const T* pq = part + w * (WG / WAVE) * WAVE;
+      T sum = pq[lane];
+      for (int u = 1; u < WG / WAVE; ++u) sum += pq[u * WAVE + lane];
+      cw[(int64_t)(q0 + w) * ldc + a.v_off2 + i] = sum;
+    }
+  } else {
+    for (int j = b0 + w; j < min(b0 + 64, s); j += WG / WAVE) {
+      T acc[RCM];
+#pragma unroll
+      for (int q = 0; q < RCM; ++q) acc[q] = 0;
+      for (int i = lane; i < s; i += WAVE) {
+        const T x = X[i + (int64_t)j * s];
+#pragma unroll
+        for (int q = 0; q < RCM; ++q)
+          if (q < nc) acc[q] += x * ys[i + q * sp];
+      }
+#pragma unroll
+      for (int q = 0; q < RCM; ++q)
+        if (q < nc) {
+          const T t = wave_sum(acc[q]);
+          if (lane == 0) cw[(int64_t)(q0 + q) * ldc + a.v_off2 + j] = t;
+        }
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(WG) void k_comp_scatter(const CompApply* __restrict__ A,
+                                                     const int32_t* __restrict__ slots, T* __restrict__ y,
+                                                     int64_t ldy, const T* __restrict__ cw, int64_t ldc) {
+  const CompApply a = A[blockIdx.x];
+  const int32_t* sl = slots + a.slot_off;
+  for (int i = threadIdx.x; i < a.s; i += WG)
+    y[(int64_t)blockIdx.y * ldy + sl[i]] = cw[(int64_t)blockIdx.y * ldc + a.v_off2 + i];
 }
 
 // Top node (factor in TF, sweep vectors in TV): mode 0: y <- L^{-T} L^{-1} y;

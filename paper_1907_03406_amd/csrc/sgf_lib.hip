@@ -101,6 +101,8 @@ struct LevelDev {
   bool uploaded = false;   // descriptor tables on the device match the plan
   // tiled elimination (large fronts): descriptors, Zt = L_II^{-T}, apply work vector
   bool tiled = false, comp_tiled = false;
+  int64_t c_elems = 0;   // sum of compressed separator sizes (apply vector of the large-separator path)
+  DevBuf cw;             // that vector, per right-hand side
   DevBuf tf, zt, uw, ctf;
   std::vector<sgf::TFront> h_tf, h_ctf;
   int64_t z_elems = 0, u_elems = 0;
@@ -534,19 +536,38 @@ int check_fail(sgf_handle h, hipStream_t st) {
   return f;
 }
 
+// Algorithmic work of eliminating one front (m eliminated, k separator rows)
+// whose M_II has lower bandwidth bw (bw = m: dense): band Cholesky, the k rows
+// of L_SI against the band factor, and the Schur block (lower half).  With
+// bw = m these are m^3/3 + m^2 k + k^2 m.
+double elim_flops(double m, double k, double bw) {
+  bw = std::min(bw, m);
+  return (m * bw * bw - 2.0 / 3.0 * bw * bw * bw) + k * (2.0 * m * bw - bw * bw) + k * k * m;
+}
+// Factor entries of such a front: the band of L_I and L_SI.
+double elim_entries(double m, double k, double bw) {
+  bw = std::min(bw, m);
+  return m * (bw + 1) - bw * (bw + 1) / 2 + m * k;
+}
+// HBM bytes of eliminating it: the band of M_II, M_SI and the lower M_SS read
+// once and written once.
+double elim_bytes(double m, double k, double bw, double e) {
+  return 2.0 * e * (elim_entries(m, k, bw) + k * (k + 1) / 2);
+}
+
 void account_level(sgf_handle h, const sgf::Level& L, LevelWork& W) {
   W = LevelWork{};
   const double e = (double)h->esz;
   for (const auto& d : L.elim) {
-    double m = d.m, k = d.k, tri = m * (m + 1) / 2;
-    W.elim_flops += m * m * m / 3.0 + m * m * k + m * k * k;
-    h->factor_entries += (int64_t)(tri + m * k);
+    double m = d.m, k = d.k, tri = m * (m + 1) / 2, ent = elim_entries(m, k, d.bw);
+    W.elim_flops += elim_flops(m, k, d.bw);
+    h->factor_entries += (int64_t)ent;
     if (L.top) {
       W.top_bytes += tri * e;
       W.top_vec += 2 * m * e + 4 * m;
     } else {
-      W.fwd_bytes += (tri + m * k) * e;
-      W.bwd_bytes += (tri + m * k) * e;
+      W.fwd_bytes += ent * e;
+      W.bwd_bytes += ent * e;
       W.fwd_vec += (2 * m + k) * e + 4 * m;
       W.bwd_vec += (2 * m + k) * e + 4 * (m + k);
     }
@@ -753,9 +774,11 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
       h->max_k_all = std::max(h->max_k_all, el.k);
     }
     h->max_t = std::max(h->max_t, L.t_elems);
-    double lvl_elim_flops = 0;
-    for (const auto& d : L.elim) lvl_elim_flops += (double)d.m * d.m * d.m / 3.0 + (double)d.m * d.m * d.k +
-                                                   (double)d.m * d.k * d.k;
+    double lvl_elim_flops = 0, lvl_elim_bytes = 0;
+    for (const auto& d : L.elim) {
+      lvl_elim_flops += elim_flops(d.m, d.k, d.bw);
+      lvl_elim_bytes += elim_bytes(d.m, d.k, d.bw, sizeof(T));
+    }
     if (L.top) {
       factor_top<T>(h, L, D, st);
     } else if (D.tiled) {
@@ -765,7 +788,7 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
       for (const auto& e : L.elim) max_m = std::max(max_m, e.m);
       int nb = level_nb(h, L, max_m);
       size_t lds = (size_t)sgf::potrf_lds_elems(L.max_front_rows, nb) * sizeof(T);
-      launch(h, st, "elim", lvl_elim_flops, 0, [&] {
+      launch(h, st, "elim", lvl_elim_flops, lvl_elim_bytes, [&] {
         launch_elim<T>(nb, (unsigned)L.elim.size(), lds, st, D.elim.as<sgf::ElimDesc>(), arena, h->d_fail.as<int>());
       }, L.t);
     }
@@ -864,12 +887,15 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
       }
     }
     {
-      int64_t toff = 0;
+      int64_t toff = 0, voff = 0;
       for (auto& a : L.capply) {
         a.t_off = toff;
         toff += (int64_t)a.s * a.s;
+        a.v_off2 = (int32_t)voff;
+        voff += a.s;
       }
       D.tb.ensure(std::max<int64_t>(toff, 1) * sizeof(T));
+      D.c_elems = voff;
     }
     if (!same_ranks) {
       upload(D.capply, L.capply, st);
@@ -882,7 +908,10 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
       double fl = 0;
       for (auto& a : L.capply) fl += (double)a.s * a.s * a.s / 3.0 + 4.0 * a.s * a.s * a.r;
       launch(h, st, "comp_explicit", fl, 0, [&] {
-        hipLaunchKernelGGL(sgf::k_comp_explicit<T>, dim3((unsigned)L.capply.size()), dim3(sgf::WG), 0, st,
+        int smax = 0;
+        for (auto& a : L.capply) smax = std::max(smax, a.s);
+        hipLaunchKernelGGL(sgf::k_comp_explicit<T>, dim3((unsigned)L.capply.size(), cdiv(smax, sgf::CEB)),
+                           dim3(sgf::WG), 0, st,
                            D.capply.as<sgf::CompApply>(), D.cf.as<T>(), D.nbuf.as<T>(), D.tau.as<T>(), D.tb.as<T>());
       }, L.t);
     }
@@ -958,8 +987,10 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
 template <typename T>
 void ensure_work(sgf_handle h, int nrhs) {
   h->y.ensure((size_t)h->plan.n * nrhs * sizeof(T));
-  for (auto& D : h->lev)
+  for (auto& D : h->lev) {
     if (D.tiled && D.uploaded) D.uw.ensure((size_t)std::max<int64_t>(D.u_elems, 1) * nrhs * sizeof(T));
+    if (D.uploaded) D.cw.ensure((size_t)std::max<int64_t>(D.c_elems, 1) * nrhs * sizeof(T));
+  }
   if (h->top_tiled) h->topu.ensure((size_t)h->top_R * nrhs * sizeof(double));
   h->tscr.ensure((size_t)std::max<int64_t>(h->max_t, 1) * nrhs * sizeof(T));
 }
@@ -1091,6 +1122,23 @@ void run_sweeps(sgf_handle h, int nrhs, bool product, hipStream_t st) {
     int mm, mk, ms;
     maxes(L, mm, mk, ms);
     if (L.capply.empty()) return;
+    if (mode <= 1 && (ms > 256 || h->tiled_rows == 0)) {
+      // large separators (or everything when every level is forced through the
+      // multi-workgroup kernels): several workgroups per separator, out of place
+      const unsigned nb = cdiv(ms, sgf::TB);
+      const int rc = rc_for(0, ((size_t)((ms + 3) & ~3) + sgf::WG) * sizeof(T), nrhs);
+      launch(h, st, "apply_comp", 0, cdiv(nrhs, rc) * D.work.capply_bytes + nrhs * D.work.capply_vec, [&] {
+        hipLaunchKernelGGL(sgf::k_comp_apply_big<T>, dim3((unsigned)L.capply.size(), nb, cdiv(nrhs, rc)),
+                           dim3(sgf::WG), (size_t)rc * (((ms + 3) & ~3) + sgf::WG) * sizeof(T), st,
+                           D.capply.as<sgf::CompApply>(), D.tb.as<T>(), D.slots.as<int32_t>(), y, n, mode, nrhs, rc,
+                           D.cw.as<T>(), D.c_elems);
+      }, L.t);
+      launch(h, st, "apply_comp", 0, 0, [&] {
+        hipLaunchKernelGGL(sgf::k_comp_scatter<T>, dim3((unsigned)L.capply.size(), nrhs), dim3(sgf::WG), 0, st,
+                           D.capply.as<sgf::CompApply>(), D.slots.as<int32_t>(), y, n, D.cw.as<T>(), D.c_elems);
+      }, L.t);
+      return;
+    }
     if (mode <= 1) {
       const int rc = rc_for(0, 2 * (size_t)ms * sizeof(T), nrhs);
       launch(h, st, "apply_comp", 0, cdiv(nrhs, rc) * D.work.capply_bytes + nrhs * D.work.capply_vec, [&] {

@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <stdexcept>
 #include <string>
@@ -128,7 +129,9 @@ struct ElimDesc {
   int64_t slot_off;     // slots of I (m entries)
   int64_t nslot_off;    // slots of the neighbours, concatenated (k entries)
   int64_t t_off;        // apply scratch (k entries per right-hand side)
-  int32_t m, k, cluster, pad;
+  int32_t m, k, cluster;
+  int32_t bw;           // lower bandwidth of M_II in slot order (m: dense); the
+                        // Cholesky factor keeps it, so L_I is zero below it
 };
 
 // One Schur contribution: dst pair block (ld = s_a) += front lower part.
@@ -170,7 +173,8 @@ struct CompApply {
   int64_t tau_off;
   int64_t slot_off;
   int64_t t_off;        // explicit T_B = Q^T L_B^{-1} (s x s, column major)
-  int32_t s, ld, r, pad;
+  int32_t s, ld, r;
+  int32_t v_off2;       // offset in the level's apply vector of compressed unknowns (s entries)
 };
 
 // Apply: separator S collects -sum_I (W_I^T y_I)[S part] from the interiors.
@@ -311,6 +315,7 @@ inline void build_level(Level& L, const Options& o, int pi) {
     ElimDesc& d = L.elim[ii];
     d.cluster = I;
     d.m = L.size[I];
+    d.bw = d.m;
     int k = 0;
     for (int64_t e = L.adj_ptr[I]; e < L.adj_ptr[I + 1]; ++e) {
       const int X = L.adj_idx[e];
@@ -706,6 +711,7 @@ inline void plan_level1(Plan& P, const int64_t* row_ptr, const int32_t* col_idx)
   const int64_t nnz = row_ptr[P.n];
   P.csr_dst.assign(nnz, -1);
   const std::vector<int32_t>& elim_of = L.elim_of;
+  for (auto& d : L.elim) d.bw = 0;
   for (int64_t i = 0; i < P.n; ++i) {
     int ci = cl_of[i], li = loc_of[i];
     for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
@@ -716,6 +722,7 @@ inline void plan_level1(Plan& P, const int64_t* row_ptr, const int32_t* col_idx)
         int64_t ld = (int64_t)d.m + d.k;
         if (cj == ci) {
           P.csr_dst[e] = d.front_off + li + (int64_t)lj * ld;
+          L.elim[elim_of[ci]].bw = std::max(L.elim[elim_of[ci]].bw, std::abs(li - lj));
         } else {
           int64_t row = L.front_row(ci, cj) + lj;
           P.csr_dst[e] = d.front_off + row + (int64_t)li * ld;
