@@ -189,7 +189,8 @@ def traffic_for(kernel):
     return rec.get("bytes_per_launch")
 
 
-def run_form(probs, cfg, precision, steps, warmup, profile, seed=0, log=None, tiled_min_rows=-1, autotune=True):
+def run_form(probs, cfg, precision, steps, warmup, profile, seed=0, log=None, tiled_min_rows=-1, autotune=True,
+             graph=True):
     """Steps alternate between the operators in `probs` (same grid and
     pattern, different coefficient fields), all resident on the device.
     Before the steps (untimed, like the analysis): one factorization + solve
@@ -204,6 +205,7 @@ def run_form(probs, cfg, precision, steps, warmup, profile, seed=0, log=None, ti
                                 precision={"fp32": sgf.FP32, "fp32_bf16n": sgf.FP32_BF16N, "fp64": sgf.FP64}[precision],
                                 tiled_min_rows=tiled_min_rows)
     t_an = time.perf_counter() - t0
+    s.set_apply_graph(graph)
     vals_all = [torch.from_numpy(p.data).to(dev) for p in probs]
     from sgf_inputs.problems import random_rhs
     nrhs = cfg.get("nrhs", 1)
@@ -336,6 +338,8 @@ def main():
     ap.add_argument("--tiled-min-rows", type=int, default=-1,
                     help="levels with fronts of at least this many rows use the tiled elimination (-1: built-in)")
     ap.add_argument("--no-autotune", action="store_true", help="skip the per-level path autotuner")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="launch the apply kernels directly (per-kernel apply timings) instead of the captured graph")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device-to-device copy of 1 GiB (reference for HBM byte counters)")
     ap.add_argument("--requests", type=int, default=300, help="serving: requests in the timed stream")
@@ -370,7 +374,7 @@ def main():
     prob = probs[0]
     t_gen = time.perf_counter() - t0
     main_form = run_form(probs, cfg, a.precision, a.steps, a.warmup, profile=True, seed=a.seed, log=a.verbose,
-                         tiled_min_rows=a.tiled_min_rows, autotune=not a.no_autotune)
+                         tiled_min_rows=a.tiled_min_rows, autotune=not a.no_autotune, graph=not a.no_graph)
     other = None
     if not a.no_fp64_form and a.precision != "fp64":
         other = run_form(probs, cfg, "fp64", max(2, a.steps // 2), 1, profile=True, seed=a.seed, log=a.verbose,

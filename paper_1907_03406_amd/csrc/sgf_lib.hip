@@ -378,8 +378,14 @@ bool panel_fits(int rows, int nb, size_t esz) {
   return (size_t)sgf::potrf_lds_elems(rows, nb) * esz <= LDS_BYTES;
 }
 
+// LDS bytes of the one-workgroup apply kernels for fronts of `rows` rows, one rhs.
+size_t apply_lds(int rows, size_t esz) {
+  return ((size_t)sgf::DB * sgf::DLD + ((rows + 3) & ~3)) * esz;
+}
+
 bool level_tiled(sgf_handle h, const sgf::Level& L) {
   if (L.top || L.elim.empty()) return false;
+  if (apply_lds(L.max_front_rows, h->esz) > LDS_BYTES) return true;
   const int mode = level_mode(h, L);
   if (mode == 0) return true;
   if (mode > 0) return !panel_fits(L.max_front_rows, mode, h->esz);
