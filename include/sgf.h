@@ -257,6 +257,16 @@ sgf_status sgf_estimate_bytes(sgf_handle h, int32_t nrhs, int64_t* bytes);
  */
 sgf_status sgf_set_apply_graph(sgf_handle h, int32_t enable);
 
+/*
+ * Launch shape of the per-level work lists of the one-workgroup elimination
+ * and of the compression (one launch per level over clusters of uneven
+ * size).  0 (default): one workgroup per cluster, or, for lists longer than
+ * the chip holds at once whose costs differ by more than 2x, a persistent
+ * launch whose workgroups take clusters costliest-first from a counter.
+ * max_workgroups > 0: always persistent on at most that many workgroups.
+ */
+sgf_status sgf_set_persistent(sgf_handle h, int32_t max_workgroups);
+
 /* Releases every host and device resource of the handle (NULL is a no-op). */
 sgf_status sgf_destroy(sgf_handle h);
 

@@ -361,14 +361,40 @@ __device__ void wg_apply_qt(const T* __restrict__ V, int64_t ldv, const T* __res
 // Factorization kernels
 // ---------------------------------------------------------------------------
 
-// Eliminate the interiors of a level (Eq. 4.2): one front per workgroup.
-template <typename T, int NB>
-__global__ __launch_bounds__(WG) void k_elim(const ElimDesc* __restrict__ D, T* __restrict__ arena, int* fail) {
+// Work lists of the per-level launches.  With a counter (zeroed before the
+// launch) the launch is persistent: a workgroup takes items from the counter
+// until it passes n, the items in the order of `order` (costliest first), so
+// clusters of uneven sizes balance over the resident workgroups.  Without one,
+// workgroup b takes item b only.  Every workgroup leaves when the list is done.
+template <bool PERS>
+__device__ __forceinline__ int next_item(int* ctr, int* sh, int round, int n) {
+  if constexpr (!PERS) {
+    return round == 0 ? (int)blockIdx.x : n;
+  } else {
+    if (threadIdx.x == 0) *sh = atomicAdd(ctr, 1);
+    __syncthreads();
+    const int i = *sh;
+    __syncthreads();
+    return i;
+  }
+}
+
+// Eliminate the interiors of a level (Eq. 4.2): one front at a time per
+// workgroup, persistent over the level's work list.
+template <typename T, int NB, bool PERS>
+__global__ __launch_bounds__(WG) void k_elim(const ElimDesc* __restrict__ D, T* __restrict__ arena, int* fail,
+                                             const int32_t* __restrict__ order, int n, int* ctr) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int sh;
   T* lds = reinterpret_cast<T*>(smem_raw);
-  const ElimDesc d = D[blockIdx.x];
-  const int R = d.m + d.k;
-  wg_potrf<T, NB, true>(arena + d.front_off, R, R, d.m, R, lds, fail, d.cluster, d.bw);
+  for (int round = 0; PERS || round == 0; ++round) {
+    const int it = next_item<PERS>(ctr, &sh, round, n);
+    if (it >= n) break;
+    const ElimDesc d = D[order[it]];
+    const int R = d.m + d.k;
+    wg_potrf<T, NB, true>(arena + d.front_off, R, R, d.m, R, lds, fail, d.cluster, d.bw);
+    __syncthreads();
+  }
 }
 
 // Subtract the interiors' Schur complements from the separator pair blocks,
@@ -512,19 +538,26 @@ __device__ int wg_qrcp(T* N, int s, int c, T* nrm, T* tau, double rank_tol, int*
 // N = [L^T Phi_B | Mhat_X Phi_X ...], pivoted Householder QR of N stopped at
 // the numerical rank, and (Q^T L^T Phi_B)[:r] into the Phi scratch.  N is
 // kept in LDS when it fits (NLDS), else in its global buffer.
-template <typename T, int PNB, bool NLDS>
+template <typename T, int PNB, bool NLDS, bool PERS>
 __global__ __launch_bounds__(WG) void k_compress(const CompDesc* __restrict__ D, const CompNbr* __restrict__ NB,
                                                  T* __restrict__ cf, T* __restrict__ nbuf, T* __restrict__ phi,
                                                  T* __restrict__ ltphi, T* __restrict__ tau_all,
                                                  int* __restrict__ rank, int pi, double rank_tol, int* fail,
-                                                 int prefactored, int bf16n) {
+                                                 int prefactored, int bf16n, const int32_t* __restrict__ order,
+                                                 int n, int* ctr) {
   // Phi of the neighbours is read here and must not change during the launch.
   // With `prefactored`, L_B and L_B^{-1} M_BX are already in the front.
+  // Persistent over the level's separators (costliest first).
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* lds = reinterpret_cast<T*>(smem_raw);
   __shared__ int sh_int[2];
   __shared__ T sh_val[2];
-  const CompDesc d = D[blockIdx.x];
+  __shared__ int sh_item;
+  for (int round = 0; PERS || round == 0; ++round) {
+  const int item = next_item<PERS>(ctr, &sh_item, round, n);
+  if (item >= n) break;
+  const int ci = order[item];
+  const CompDesc d = D[ci];
   const int s = d.s, c = d.c;
   const int64_t ld = s + d.K;
   T* F = cf + d.cf_off;
@@ -570,7 +603,9 @@ __global__ __launch_bounds__(WG) void k_compress(const CompDesc* __restrict__ D,
   // ---- (Q^T L^T Phi_B)[:r] (Eq. 3.4) into the scratch; neighbours may still be
   // reading Phi_B, so k_phi_commit installs it after every compression ended.
   if (r < s) wg_apply_qt(N, s, tau, s, r, LtP, s, pi);
-  if (threadIdx.x == 0) rank[blockIdx.x] = r;
+  if (threadIdx.x == 0) rank[ci] = r;
+  __syncthreads();
+  }
 }
 
 // Phi_B <- (Q^T L^T Phi_B)[:r] for the separators that were compressed.

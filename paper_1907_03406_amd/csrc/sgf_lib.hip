@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <memory>
 #include <stdexcept>
 #include <string>
@@ -101,6 +102,9 @@ struct LevelDev {
   bool uploaded = false;   // descriptor tables on the device match the plan
   // tiled elimination (large fronts): descriptors, Zt = L_II^{-T}, apply work vector
   bool tiled = false, comp_tiled = false;
+  DevBuf elim_order, comp_order;   // work lists of the persistent launches, costliest first
+  std::vector<int32_t> h_elim_order, h_comp_order;
+  bool elim_uneven = false, comp_uneven = false;
   int64_t c_elems = 0;   // sum of compressed separator sizes (apply vector of the large-separator path)
   DevBuf cw;             // that vector, per right-hand side
   DevBuf tf, zt, uw, ctf;
@@ -174,6 +178,7 @@ struct Profiler {
 };
 
 constexpr size_t LDS_BYTES = 64 * 1024;
+constexpr size_t LDS_MAX_BYTES = 160 * 1024;   // LDS of one CU on gfx950
 
 // Opt-in host timeline of the factorization (environment SGF_TRACE=1).
 struct HostTrace {
@@ -205,6 +210,7 @@ struct sgf_handle_s {
   bool dev_static = false;   // CSR structure, perm, coords, fill map on the device
   bool factored = false;
   DevBuf d_perm, d_rowptr, d_colidx, d_vals, d_csrdst, d_coords, d_fail;
+  DevBuf d_ctr, d_zero_idx;   // work counter of the persistent launches; the one-item list {0}
   std::vector<LevelDev> lev;
   DevBuf y, tscr;
   DevBuf cg_r, cg_z, cg_p, cg_ap, cg_part, cg_st, cg_scal;
@@ -232,6 +238,7 @@ struct sgf_handle_s {
   // arguments and the factorization it belongs to), replayed on the caller's
   // stream; captured on a private stream of default priority
   bool use_graph = true;
+  int32_t persist_cap = 0;   // > 0: per-level work lists persistent on at most this many workgroups
   uint64_t epoch = 0;
   hipStream_t cap_stream = nullptr;
   struct ApplyGraph {
@@ -328,29 +335,53 @@ int nb_for(int rows, int cols, size_t esz, int64_t extra = 0) {
   throw SgfError(SGF_EINVAL, "front of " + std::to_string(rows) + " rows does not fit the LDS panel");
 }
 
-template <typename T>
-void launch_elim(int nb, unsigned grid, size_t lds, hipStream_t st, const sgf::ElimDesc* d, T* arena, int* fail) {
+template <typename T, bool PERS>
+void launch_elim_p(int nb, unsigned grid, size_t lds, hipStream_t st, const sgf::ElimDesc* d, T* arena, int* fail,
+                   const int32_t* order, int n, int* ctr) {
   switch (nb) {
-    case 32: hipLaunchKernelGGL((sgf::k_elim<T, 32>), dim3(grid), dim3(sgf::WG), lds, st, d, arena, fail); break;
-    case 16: hipLaunchKernelGGL((sgf::k_elim<T, 16>), dim3(grid), dim3(sgf::WG), lds, st, d, arena, fail); break;
-    case 8: hipLaunchKernelGGL((sgf::k_elim<T, 8>), dim3(grid), dim3(sgf::WG), lds, st, d, arena, fail); break;
-    default: hipLaunchKernelGGL((sgf::k_elim<T, 4>), dim3(grid), dim3(sgf::WG), lds, st, d, arena, fail); break;
+    case 32: hipLaunchKernelGGL((sgf::k_elim<T, 32, PERS>), dim3(grid), dim3(sgf::WG), lds, st, d, arena, fail, order, n, ctr); break;
+    case 16: hipLaunchKernelGGL((sgf::k_elim<T, 16, PERS>), dim3(grid), dim3(sgf::WG), lds, st, d, arena, fail, order, n, ctr); break;
+    case 8: hipLaunchKernelGGL((sgf::k_elim<T, 8, PERS>), dim3(grid), dim3(sgf::WG), lds, st, d, arena, fail, order, n, ctr); break;
+    default: hipLaunchKernelGGL((sgf::k_elim<T, 4, PERS>), dim3(grid), dim3(sgf::WG), lds, st, d, arena, fail, order, n, ctr); break;
   }
 }
+// ctr == nullptr: one workgroup per item; otherwise persistent on the counter.
+template <typename T>
+void launch_elim(int nb, unsigned grid, size_t lds, hipStream_t st, const sgf::ElimDesc* d, T* arena, int* fail,
+                 const int32_t* order, int n, int* ctr) {
+  if (ctr) launch_elim_p<T, true>(nb, grid, lds, st, d, arena, fail, order, n, ctr);
+  else launch_elim_p<T, false>(nb, grid, lds, st, d, arena, fail, order, n, ctr);
+}
 
-template <typename T, bool NLDS, typename... A>
+// Launch shape of a level's work list of n items.  Persistent (grid = the
+// workgroups one pass of the chip holds at this LDS size, items taken from a
+// counter) when the list is longer than that and its costs are uneven;
+// otherwise one workgroup per item.  Returns the grid; *persist tells which.
+unsigned work_grid(int n, size_t lds, bool uneven, bool* persist, int cap) {
+  const size_t occ = std::max<size_t>(1, std::min<size_t>(8, LDS_MAX_BYTES / std::max<size_t>(lds, 1)));
+  const int64_t slots = cap > 0 ? cap : 256 * (int64_t)occ;
+  *persist = cap > 0 || (uneven && n > slots);
+  return (unsigned)std::max<int64_t>(1, *persist ? std::min<int64_t>(slots, n) : n);
+}
+
+template <typename T, bool NLDS, bool PERS, typename... A>
 void launch_compress_n(int nb, unsigned grid, size_t lds, hipStream_t st, A... args) {
   switch (nb) {
-    case 32: hipLaunchKernelGGL((sgf::k_compress<T, 32, NLDS>), dim3(grid), dim3(sgf::WG), lds, st, args...); break;
-    case 16: hipLaunchKernelGGL((sgf::k_compress<T, 16, NLDS>), dim3(grid), dim3(sgf::WG), lds, st, args...); break;
-    case 8: hipLaunchKernelGGL((sgf::k_compress<T, 8, NLDS>), dim3(grid), dim3(sgf::WG), lds, st, args...); break;
-    default: hipLaunchKernelGGL((sgf::k_compress<T, 4, NLDS>), dim3(grid), dim3(sgf::WG), lds, st, args...); break;
+    case 32: hipLaunchKernelGGL((sgf::k_compress<T, 32, NLDS, PERS>), dim3(grid), dim3(sgf::WG), lds, st, args...); break;
+    case 16: hipLaunchKernelGGL((sgf::k_compress<T, 16, NLDS, PERS>), dim3(grid), dim3(sgf::WG), lds, st, args...); break;
+    case 8: hipLaunchKernelGGL((sgf::k_compress<T, 8, NLDS, PERS>), dim3(grid), dim3(sgf::WG), lds, st, args...); break;
+    default: hipLaunchKernelGGL((sgf::k_compress<T, 4, NLDS, PERS>), dim3(grid), dim3(sgf::WG), lds, st, args...); break;
   }
 }
 template <typename T, typename... A>
-void launch_compress(bool nlds, int nb, unsigned grid, size_t lds, hipStream_t st, A... args) {
-  if (nlds) launch_compress_n<T, true>(nb, grid, lds, st, args...);
-  else launch_compress_n<T, false>(nb, grid, lds, st, args...);
+void launch_compress(bool nlds, bool pers, int nb, unsigned grid, size_t lds, hipStream_t st, A... args) {
+  if (nlds) {
+    if (pers) launch_compress_n<T, true, true>(nb, grid, lds, st, args...);
+    else launch_compress_n<T, true, false>(nb, grid, lds, st, args...);
+  } else {
+    if (pers) launch_compress_n<T, false, true>(nb, grid, lds, st, args...);
+    else launch_compress_n<T, false, false>(nb, grid, lds, st, args...);
+  }
 }
 
 void ensure_static(sgf_handle h, hipStream_t st) {
@@ -362,7 +393,31 @@ void ensure_static(sgf_handle h, hipStream_t st) {
   upload(h->d_coords, h->h_coords, st);
   h->d_vals.ensure(h->nnz * sizeof(double));
   h->d_fail.ensure(sizeof(int));
+  h->d_ctr.ensure(sizeof(int));
+  if (!h->d_zero_idx.p) {
+    h->d_zero_idx.ensure(sizeof(int32_t));
+    HIP_CHECK(hipMemsetAsync(h->d_zero_idx.p, 0, sizeof(int32_t), st));
+  }
   h->dev_static = true;
+}
+
+// Algorithmic work of eliminating one front (m eliminated, k separator rows)
+// whose M_II has lower bandwidth bw (bw = m: dense): band Cholesky, the k rows
+// of L_SI against the band factor, and the Schur block (lower half).  With
+// bw = m these are m^3/3 + m^2 k + k^2 m.
+double elim_flops(double m, double k, double bw) {
+  bw = std::min(bw, m);
+  return (m * bw * bw - 2.0 / 3.0 * bw * bw * bw) + k * (2.0 * m * bw - bw * bw) + k * k * m;
+}
+// Factor entries of such a front: the band of L_I and L_SI.
+double elim_entries(double m, double k, double bw) {
+  bw = std::min(bw, m);
+  return m * (bw + 1) - bw * (bw + 1) / 2 + m * k;
+}
+// HBM bytes of eliminating it: the band of M_II, M_SI and the lower M_SS read
+// once and written once.
+double elim_bytes(double m, double k, double bw, double e) {
+  return 2.0 * e * (elim_entries(m, k, bw) + k * (k + 1) / 2);
 }
 
 // Whether the interiors of level L are eliminated by the tiled multi-workgroup
@@ -467,6 +522,29 @@ void upload_level(sgf_handle h, int li, hipStream_t st) {
   upload(D.phioff, L.phi_off, st);
   D.tiled = level_tiled(h, L);
   if (D.tiled) build_tiled(h, L, D, st);
+  {
+    // work lists: costliest first when the costs differ by more than 2x
+    // (longest-processing-time order), else cluster order (memory locality)
+    auto order = [](std::vector<int32_t>& o, size_t n, const std::function<double(int32_t)>& cost, bool* uneven) {
+      o.resize(n);
+      for (size_t i = 0; i < n; ++i) o[i] = (int32_t)i;
+      double lo = 0, hi = 0;
+      for (size_t i = 0; i < n; ++i) {
+        const double c = cost((int32_t)i);
+        lo = i ? std::min(lo, c) : c;
+        hi = i ? std::max(hi, c) : c;
+      }
+      *uneven = hi > 2 * lo;
+      if (*uneven) std::stable_sort(o.begin(), o.end(), [&](int32_t a, int32_t b) { return cost(a) > cost(b); });
+    };
+    order(D.h_elim_order, L.elim.size(),
+          [&](int32_t a) { return elim_flops(L.elim[a].m, L.elim[a].k, L.elim[a].bw); }, &D.elim_uneven);
+    upload(D.elim_order, D.h_elim_order, st);
+    order(D.h_comp_order, L.comp.size(),
+          [&](int32_t c) { return (double)L.comp[c].s * L.comp[c].s * (L.comp[c].s + L.comp[c].K + L.comp[c].c); },
+          &D.comp_uneven);
+    upload(D.comp_order, D.h_comp_order, st);
+  }
   // compression fronts [M_BB ; M_XB] too large for the one-workgroup panel:
   // their Cholesky / triangular solve goes through the tiled kernels
   D.comp_tiled = false;
@@ -540,25 +618,6 @@ int check_fail(sgf_handle h, hipStream_t st) {
   HIP_CHECK(hipMemcpyAsync(&f, h->d_fail.p, sizeof(int), hipMemcpyDeviceToHost, st));
   HIP_CHECK(hipStreamSynchronize(st));
   return f;
-}
-
-// Algorithmic work of eliminating one front (m eliminated, k separator rows)
-// whose M_II has lower bandwidth bw (bw = m: dense): band Cholesky, the k rows
-// of L_SI against the band factor, and the Schur block (lower half).  With
-// bw = m these are m^3/3 + m^2 k + k^2 m.
-double elim_flops(double m, double k, double bw) {
-  bw = std::min(bw, m);
-  return (m * bw * bw - 2.0 / 3.0 * bw * bw * bw) + k * (2.0 * m * bw - bw * bw) + k * k * m;
-}
-// Factor entries of such a front: the band of L_I and L_SI.
-double elim_entries(double m, double k, double bw) {
-  bw = std::min(bw, m);
-  return m * (bw + 1) - bw * (bw + 1) / 2 + m * k;
-}
-// HBM bytes of eliminating it: the band of M_II, M_SI and the lower M_SS read
-// once and written once.
-double elim_bytes(double m, double k, double bw, double e) {
-  return 2.0 * e * (elim_entries(m, k, bw) + k * (k + 1) / 2);
 }
 
 void account_level(sgf_handle h, const sgf::Level& L, LevelWork& W) {
@@ -709,7 +768,7 @@ void factor_top(sgf_handle h, const sgf::Level& L, LevelDev& D, hipStream_t st) 
     const size_t lds = (size_t)sgf::potrf_lds_elems(R, nb) * sizeof(double);
     launch(h, st, "top_chol", (double)R * R * R / 3.0, 0, [&] {
       launch_elim<double>(nb, 1, lds, st, h->d_topdesc.as<sgf::ElimDesc>(), h->top64.as<double>(),
-                          h->d_fail.as<int>());
+                          h->d_fail.as<int>(), h->d_zero_idx.as<int32_t>(), 1, nullptr);
     }, L.t);
   }
 }
@@ -794,8 +853,13 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
       for (const auto& e : L.elim) max_m = std::max(max_m, e.m);
       int nb = level_nb(h, L, max_m);
       size_t lds = (size_t)sgf::potrf_lds_elems(L.max_front_rows, nb) * sizeof(T);
+      const int ne = (int)L.elim.size();
+      bool persist = false;
+      const unsigned grid = work_grid(ne, lds, D.elim_uneven, &persist, h->persist_cap);
+      if (persist) HIP_CHECK(hipMemsetAsync(h->d_ctr.p, 0, sizeof(int), st));
       launch(h, st, "elim", lvl_elim_flops, lvl_elim_bytes, [&] {
-        launch_elim<T>(nb, (unsigned)L.elim.size(), lds, st, D.elim.as<sgf::ElimDesc>(), arena, h->d_fail.as<int>());
+        launch_elim<T>(nb, grid, lds, st, D.elim.as<sgf::ElimDesc>(), arena, h->d_fail.as<int>(),
+                       D.elim_order.as<int32_t>(), ne, persist ? h->d_ctr.as<int>() : nullptr);
       }, L.t);
     }
     h->trace.mark("elimination queued", L.t);
@@ -840,11 +904,15 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
       if (lds > LDS_BYTES) throw SgfError(SGF_EINVAL, "compression kernel needs more LDS than available");
       double tol = P.opt.rank_tol;
       const int pre = D.comp_tiled ? 1 : 0;
+      bool cpersist = false;
+      const unsigned cgrid = work_grid((int)L.comp.size(), lds, D.comp_uneven, &cpersist, h->persist_cap);
+      if (cpersist) HIP_CHECK(hipMemsetAsync(h->d_ctr.p, 0, sizeof(int), st));
       launch(h, st, "compress", 0, 0, [&] {
-        launch_compress<T>(nlds, nb, (unsigned)L.comp.size(), lds, st, D.comp.as<sgf::CompDesc>(),
+        launch_compress<T>(nlds, cpersist, nb, cgrid, lds, st, D.comp.as<sgf::CompDesc>(),
                            D.compnbr.as<sgf::CompNbr>(), D.cf.as<T>(), D.nbuf.as<T>(), D.phi.as<T>(), D.ltphi.as<T>(),
                            D.tau.as<T>(), D.rank.as<int>(), P.pi, tol, h->d_fail.as<int>(), pre,
-                           P.opt.precision == SGF_FP32_BF16N ? 1 : 0);
+                           P.opt.precision == SGF_FP32_BF16N ? 1 : 0, D.comp_order.as<int32_t>(), (int)L.comp.size(),
+                           cpersist ? h->d_ctr.as<int>() : nullptr);
       }, L.t);
       launch(h, st, "phi_commit", 0, 0, [&] {
         hipLaunchKernelGGL(sgf::k_phi_commit<T>, dim3((unsigned)L.comp.size()), dim3(sgf::WG), 0, st,
@@ -1291,6 +1359,7 @@ void dot_cols(sgf_handle h, const double* a, const double* b, int nrhs, double* 
 int64_t device_bytes(sgf_handle h) {
   int64_t b = 0;
   for (const DevBuf* x : {&h->d_perm, &h->d_rowptr, &h->d_colidx, &h->d_vals, &h->d_csrdst, &h->d_coords, &h->d_fail,
+                          &h->d_ctr, &h->d_zero_idx,
                           &h->y, &h->tscr, &h->cg_r, &h->cg_z, &h->cg_p, &h->cg_ap, &h->cg_part, &h->cg_st,
                           &h->cg_scal, &h->top64, &h->topz, &h->topu, &h->d_topdesc, &h->d_toptf})
     b += x->bytes;
@@ -1298,7 +1367,7 @@ int64_t device_bytes(sgf_handle h) {
     for (const DevBuf* x : {&D.arena, &D.scratch, &D.cf, &D.nbuf, &D.ltphi, &D.tau, &D.phi, &D.rank, &D.elim,
                             &D.pairs, &D.schur, &D.comp, &D.compnbr, &D.sepacc, &D.sepsrc, &D.capply, &D.slots,
                             &D.nslots, &D.blkmap, &D.phimap, &D.slotptr, &D.phioff, &D.tb, &D.active, &D.tofcomp,
-                            &D.tf, &D.zt, &D.uw, &D.ctf})
+                            &D.tf, &D.zt, &D.uw, &D.ctf, &D.elim_order, &D.comp_order, &D.cw})
       b += x->bytes;
   return b;
 }
@@ -1642,6 +1711,7 @@ sgf_status sgf_release(sgf_handle h) {
     h->drop_graph();
     h->lev.clear();
     for (DevBuf* b : {&h->d_perm, &h->d_rowptr, &h->d_colidx, &h->d_vals, &h->d_csrdst, &h->d_coords, &h->d_fail,
+                      &h->d_ctr, &h->d_zero_idx,
                       &h->y, &h->tscr, &h->cg_r, &h->cg_z, &h->cg_p, &h->cg_ap, &h->cg_part, &h->cg_st,
                       &h->cg_scal, &h->top64, &h->topz, &h->topu, &h->d_topdesc, &h->d_toptf})
       b->release();
@@ -1765,6 +1835,12 @@ sgf_status sgf_plan_dry_run(sgf_handle h, sgf_rank_fn rank_fn, void* ctx) {
       sgf::plan_next_level(P, bm, pm);
     }
   });
+}
+
+sgf_status sgf_set_persistent(sgf_handle h, int32_t max_workgroups) {
+  if (!h || max_workgroups < 0) return fail(SGF_EINVAL, "bad persistent-launch argument");
+  h->persist_cap = max_workgroups;
+  return SGF_OK;
 }
 
 sgf_status sgf_set_apply_graph(sgf_handle h, int32_t enable) {

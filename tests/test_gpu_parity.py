@@ -332,3 +332,19 @@ def test_bf16_n_form_converges(kind, grid, leaf, q):
               f"compressed {s.info()['compressed']}")
         assert true < 2e-8
     assert its[sgf.FP32_BF16N] <= 2 * its[sgf.FP32] + 5
+
+
+@pytest.mark.parametrize("cap", [1, 3])
+def test_persistent_work_lists_match_oracle(cap):
+    """Persistent launches of the elimination and compression work lists (a
+    few workgroups taking clusters from a counter, costliest first) give the
+    same operator as one workgroup per cluster."""
+    p = _prob("fourier", (61, 58), seed=4)
+    F = _oracle(p, 2, 8)
+    s = sgf.Solver.from_problem(p, q=2, leaf=8)
+    s.set_persistent(cap)
+    s.factorize(torch.from_numpy(p.data).cuda())
+    V = np.stack([P.random_rhs(8, p.n, j) for j in range(2)], axis=1)
+    assert _rel(_apply(s, V), O.apply_inverse(F, V)) <= 1e-10
+    ref = _gpu(p, q=2, leaf=8)
+    assert np.array_equal(_apply(s, V), _apply(ref, V))
