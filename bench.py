@@ -425,6 +425,8 @@ def main():
         "factor_tflops": round(fac_flops / (fac_ms * 1e-3) / 1e12, 4),
         "elim_kernel_tflops": round(elim["flops"] / (elim["ms"] * 1e-3) / 1e12, 4) if elim["ms"] else None,
         "apply_gbs": round(apply_bytes / (apply_ms * 1e-3) / 1e9, 1) if apply_ms else None,
+        "pcg_iteration_gbs": (round(st["pcg_iteration_graph"]["bytes"] / (st["pcg_iteration_graph"]["ms"] * 1e-3) / 1e9, 1)
+                              if st.get("pcg_iteration_graph", {}).get("ms") else None),
         "pcg_only_solves_per_s": round(1e3 / (ms - fac_ms), 3) if ms > fac_ms else None,
         "gpu_kernel_ms_per_step": round(gpu_ms / steps, 3),
         "levels": main_form["info"]["levels"], "top_size": main_form["info"]["top_size"],

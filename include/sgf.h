@@ -140,11 +140,12 @@ sgf_status sgf_factorize(int64_t n, const int64_t* row_ptr, const int32_t* col_i
 
 /*
  * Autotuner of the batched elimination (one launch per level over clusters
- * of uneven sizes): factorizes `vals` once per candidate -- the tiled
- * multi-workgroup path and the one-workgroup-per-front path with panel
- * widths 8, 16 and 32 -- and applies the result once, timing every level's
- * elimination plus `napply` times its forward and backward apply kernels
- * with device events; each level then keeps its fastest candidate.
+ * of uneven sizes): factorizes `vals` three times per candidate (trials
+ * interleaved) -- the tiled multi-workgroup path and the one-workgroup-per-
+ * front path with panel widths 8, 16 and 32 -- and applies each result once,
+ * timing every level's elimination plus `napply` times its forward and
+ * backward interior sweeps with device events; each level then keeps the
+ * candidate with the fastest of its three times.
  *   vals       DEVICE double[nnz] (as for sgf_factorize_numeric)
  *   napply     weight of the apply (expected applies per factorization)
  *   modes_out  HOST int32[levels] or NULL: chosen candidate per level
@@ -260,12 +261,21 @@ sgf_status sgf_set_apply_graph(sgf_handle h, int32_t enable);
 /*
  * Launch shape of the per-level work lists of the one-workgroup elimination
  * and of the compression (one launch per level over clusters of uneven
- * size).  0 (default): one workgroup per cluster, or, for lists longer than
- * the chip holds at once whose costs differ by more than 2x, a persistent
- * launch whose workgroups take clusters costliest-first from a counter.
- * max_workgroups > 0: always persistent on at most that many workgroups.
+ * size).  0 (default): one workgroup per cluster, in cluster order.
+ * max_workgroups > 0: persistent launches on at most that many workgroups,
+ * which take clusters from a counter, costliest first when the costs differ
+ * by more than 2x.  Results do not depend on the launch shape.
  */
 sgf_status sgf_set_persistent(sgf_handle h, int32_t max_workgroups);
+
+/*
+ * Interior sweeps of the apply (Sec. 4.7) on levels whose M_II blocks have a
+ * lower bandwidth of at most 64: enable = 1 (default) stages the band of L_I
+ * in LDS and solves it one wavefront per right-hand side; 0 uses the blocked
+ * sweeps that also serve dense interiors.  Both give the same result up to
+ * rounding order.  Drops a captured apply graph.
+ */
+sgf_status sgf_set_band_apply(sgf_handle h, int32_t enable);
 
 /* Releases every host and device resource of the handle (NULL is a no-op). */
 sgf_status sgf_destroy(sgf_handle h);

@@ -390,7 +390,7 @@ __global__ __launch_bounds__(WG) void k_elim(const ElimDesc* __restrict__ D, T* 
   for (int round = 0; PERS || round == 0; ++round) {
     const int it = next_item<PERS>(ctr, &sh, round, n);
     if (it >= n) break;
-    const ElimDesc d = D[order[it]];
+    const ElimDesc d = D[PERS ? order[it] : it];   // the order is read only by persistent launches
     const int R = d.m + d.k;
     wg_potrf<T, NB, true>(arena + d.front_off, R, R, d.m, R, lds, fail, d.cluster, d.bw);
     __syncthreads();
@@ -556,7 +556,7 @@ __global__ __launch_bounds__(WG) void k_compress(const CompDesc* __restrict__ D,
   for (int round = 0; PERS || round == 0; ++round) {
   const int item = next_item<PERS>(ctr, &sh_item, round, n);
   if (item >= n) break;
-  const int ci = order[item];
+  const int ci = PERS ? order[item] : item;
   const CompDesc d = D[ci];
   const int s = d.s, c = d.c;
   const int64_t ld = s + d.K;
@@ -1053,6 +1053,210 @@ __global__ __launch_bounds__(WG) void k_apply_bwd(const ElimDesc* __restrict__ D
   }
 }
 
+// ---------------------------------------------------------------------------
+// Banded apply sweeps, for levels whose interiors have a narrow M_II (lower
+// bandwidth bw <= BAND_MAX, e.g. the finest interiors of a grid numbered
+// naturally).  Each workgroup stages the band of L_I once in LDS by
+// diagonals, Bd[r * ld + i] = L[i, i - r] (the reciprocal pivot at r = 0),
+// with a row stride that keeps the lanes of one step on distinct banks.  The
+// triangular solve runs on one wavefront per right-hand side, one row per
+// lane in chunks of 64: the value finished at a step reaches the other lanes
+// through a scalar register, and the lanes within the band below (above) it
+// update.  The products with the L_SI rows of the panel use all 256 threads
+// with coalesced column loads and sum in a fixed order.
+// ---------------------------------------------------------------------------
+constexpr int BAND_MAX = 64;
+
+template <typename T>
+__device__ __forceinline__ void stage_band(const T* __restrict__ C, int R, int m, int bw, T* Bd, int ld) {
+  const int nb1 = bw + 1;
+  for (int idx = threadIdx.x; idx < m * nb1; idx += WG) {
+    const int j = idx / nb1, r = idx - j * nb1, i = j + r;
+    if (i < m) {
+      const T c = C[i + (int64_t)j * R];
+      Bd[r * ld + i] = r == 0 ? T(1) / c : c;
+    }
+  }
+}
+
+// LDS elements of the banded sweeps for fronts up to (m, k, bw), RC columns.
+__host__ __device__ constexpr int band_fwd_ld(int m) { return (m + 1) & ~1; }
+__host__ __device__ constexpr int band_bwd_ld(int m) { return m | 1; }
+__host__ __device__ inline int64_t band_fwd_lds(int m, int k, int bw, int rc) {
+  (void)k;
+  return (int64_t)(bw + 1) * band_fwd_ld(m) + (int64_t)rc * band_fwd_ld(m) + (int64_t)(WG / WAVE) * rc * WAVE;
+}
+__host__ __device__ inline int64_t band_bwd_lds(int m, int k, int bw, int rc, int tj) {
+  const int64_t a = (int64_t)(bw + 1) * band_bwd_ld(m), b = (int64_t)tj * (k | 1);
+  return (a > b ? a : b) + (int64_t)rc * band_bwd_ld(m) + (int64_t)rc * k + (int64_t)(WG / WAVE) * rc * WAVE;
+}
+
+// Forward sweep: y_I <- L_I^{-1} y_I and t = L_SI y_I (into the apply scratch).
+template <typename T, int RC>
+__global__ __launch_bounds__(WG) void k_band_fwd(const ElimDesc* __restrict__ D, const T* __restrict__ arena,
+                                                 const int32_t* __restrict__ slots, T* __restrict__ y, int64_t ldy,
+                                                 T* __restrict__ tscr, int64_t ldt, int nrhs) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const ElimDesc d = D[blockIdx.x];
+  const int m = d.m, k = d.k, R = m + k, bw = min(d.bw, max(m - 1, 0));
+  const int ld = band_fwd_ld(m);
+  T* Bd = reinterpret_cast<T*>(smem_raw);
+  T* v = Bd + (bw + 1) * ld;
+  T* part = v + RC * ld;
+  const int c0 = blockIdx.y * RC, nc = min(RC, nrhs - c0);
+  const T* C = arena + d.front_off;
+  const int32_t* sl = slots + d.slot_off;
+  for (int idx = threadIdx.x; idx < m * nc; idx += WG) {
+    const int i = idx % m, c = idx / m;
+    v[c * ld + i] = y[(int64_t)(c0 + c) * ldy + sl[i]];
+  }
+  stage_band(C, R, m, bw, Bd, ld);
+  __syncthreads();
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  if (w < nc) {
+    T* vc = v + w * ld;
+    for (int i0 = 0; i0 < m; i0 += WAVE) {
+      const int i = i0 + lane, cn = min(WAVE, m - i0);
+      const bool on = i < m;
+      T x = on ? vc[i] : T(0);
+      const T dinv = on ? Bd[i] : T(0);
+      // columns of earlier chunks inside the band (their values are final)
+      for (int r = lane + 1; r <= bw; ++r)
+        if (on && i - r >= 0) x -= Bd[r * ld + i] * vc[i - r];
+#pragma unroll 4
+      for (int jj = 0; jj < cn; ++jj) {
+        const T xj = lane_bcast(x * dinv, jj);
+        const int r = lane - jj;
+        if (r == 0) x = xj;
+        else if (r > 0 && r <= bw && on) x -= Bd[r * ld + i] * xj;
+      }
+      if (on) vc[i] = x;
+    }
+  }
+  __syncthreads();
+  // t = L_SI x: 64 rows per pass, the columns dealt to the wavefronts in turn
+  for (int rb = 0; rb < k; rb += WAVE) {
+    const int r = rb + lane;
+    T acc[RC];
+#pragma unroll
+    for (int c = 0; c < RC; ++c) acc[c] = 0;
+    if (r < k) {
+      const T* cr = C + m + r;
+#pragma unroll 8
+      for (int j = w; j < m; j += WG / WAVE) {
+        const T cij = cr[(int64_t)j * R];
+#pragma unroll
+        for (int c = 0; c < RC; ++c) acc[c] += cij * v[c * ld + j];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < RC; ++c) part[(w * RC + c) * WAVE + lane] = acc[c];
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < WAVE * nc; idx += WG) {
+      const int l = idx % WAVE, c = idx / WAVE;
+      if (rb + l < k) {
+        T sum = 0;
+        for (int q = 0; q < WG / WAVE; ++q) sum += part[(q * RC + c) * WAVE + l];
+        tscr[(int64_t)(c0 + c) * ldt + d.t_off + rb + l] = sum;
+      }
+    }
+    __syncthreads();
+  }
+  for (int idx = threadIdx.x; idx < m * nc; idx += WG) {
+    const int i = idx % m, c = idx / m;
+    y[(int64_t)(c0 + c) * ldy + sl[i]] = v[c * ld + i];
+  }
+}
+
+// Backward sweep: y_I <- L_I^{-T} (y_I - L_SI^T y_S).  The L_SI^T product
+// stages tiles of tj <= 64 columns of the panel's L_SI rows transposed in
+// LDS (the space the band takes afterwards), so each lane sums down one
+// column, the rows dealt to the wavefronts in turn.
+template <typename T, int RC>
+__global__ __launch_bounds__(WG) void k_band_bwd(const ElimDesc* __restrict__ D, const T* __restrict__ arena,
+                                                 const int32_t* __restrict__ slots,
+                                                 const int32_t* __restrict__ nslots, T* __restrict__ y,
+                                                 int64_t ldy, int nrhs, int tj) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const ElimDesc d = D[blockIdx.x];
+  const int m = d.m, k = d.k, R = m + k, bw = min(d.bw, max(m - 1, 0));
+  const int ld = band_bwd_ld(m), ldk = k | 1;
+  const int64_t big = max((int64_t)(bw + 1) * ld, (int64_t)tj * ldk);
+  T* Bd = reinterpret_cast<T*>(smem_raw);   // the transposed tiles first, then the band
+  T* v = Bd + big;
+  T* ys = v + RC * ld;
+  T* part = ys + RC * k;
+  const int c0 = blockIdx.y * RC, nc = min(RC, nrhs - c0);
+  const T* C = arena + d.front_off;
+  const int32_t* sl = slots + d.slot_off;
+  const int32_t* ns = nslots + d.nslot_off;
+  for (int idx = threadIdx.x; idx < m * nc; idx += WG) {
+    const int i = idx % m, c = idx / m;
+    v[c * ld + i] = y[(int64_t)(c0 + c) * ldy + sl[i]];
+  }
+  for (int idx = threadIdx.x; idx < k * nc; idx += WG) {
+    const int r = idx % k, c = idx / k;
+    ys[c * k + r] = y[(int64_t)(c0 + c) * ldy + ns[r]];
+  }
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  for (int j0 = 0; j0 < m; j0 += tj) {
+    const int cw = min(tj, m - j0);
+    for (int idx = threadIdx.x; idx < k * cw; idx += WG) {
+      const int r = idx % k, jl = idx / k;
+      Bd[jl * ldk + r] = C[m + r + (int64_t)(j0 + jl) * R];
+    }
+    __syncthreads();
+    T acc[RC];
+#pragma unroll
+    for (int c = 0; c < RC; ++c) acc[c] = 0;
+    if (lane < cw)
+      for (int r = w; r < k; r += WG / WAVE) {
+        const T wr = Bd[lane * ldk + r];
+#pragma unroll
+        for (int c = 0; c < RC; ++c) acc[c] += wr * ys[c * k + r];
+      }
+#pragma unroll
+    for (int c = 0; c < RC; ++c) part[(w * RC + c) * WAVE + lane] = acc[c];
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < WAVE * nc; idx += WG) {
+      const int l = idx % WAVE, c = idx / WAVE;
+      if (l < cw) {
+        T sum = 0;
+        for (int q = 0; q < WG / WAVE; ++q) sum += part[(q * RC + c) * WAVE + l];
+        v[c * ld + j0 + l] -= sum;
+      }
+    }
+    __syncthreads();
+  }
+  stage_band(C, R, m, bw, Bd, ld);
+  __syncthreads();
+  if (w < nc) {
+    T* vc = v + w * ld;
+    for (int i0 = ((m - 1) / WAVE) * WAVE; i0 >= 0; i0 -= WAVE) {
+      const int i = i0 + lane, cn = min(WAVE, m - i0);
+      const bool on = i < m;
+      T x = on ? vc[i] : T(0);
+      const T dinv = on ? Bd[i] : T(0);
+      // rows of later chunks inside the band (their values are final)
+      for (int r = WAVE - lane; r <= bw; ++r)
+        if (on && i + r < m) x -= Bd[r * ld + i + r] * vc[i + r];
+#pragma unroll 4
+      for (int jj = cn - 1; jj >= 0; --jj) {
+        const T xj = lane_bcast(x * dinv, jj);
+        const int r = jj - lane;
+        if (r == 0) x = xj;
+        else if (r > 0 && r <= bw) x -= Bd[r * ld + i0 + jj] * xj;
+      }
+      if (on) vc[i] = x;
+    }
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < m * nc; idx += WG) {
+    const int i = idx % m, c = idx / m;
+    y[(int64_t)(c0 + c) * ldy + sl[i]] = v[c * ld + i];
+  }
+}
+
 // T_B = Q^T L_B^{-1} (s x s) for every compressed separator, so that each
 // apply of B is one dense matrix-vector product (forward) or its transpose.
 // Columns are independent: workgroup blockIdx.y forms columns
@@ -1343,18 +1547,20 @@ __global__ __launch_bounds__(WG) void k_dot_partial(const double* __restrict__ a
   if (threadIdx.x == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = s;
 }
 
-// out[col] = sum of npart partials (fixed order), one workgroup per column.
+// out[col * stride] = sum of npart partials (fixed order), one workgroup per column.
 __global__ __launch_bounds__(WG) void k_reduce(const double* __restrict__ partial, int npart,
-                                               double* __restrict__ out) {
+                                               double* __restrict__ out, int stride) {
   __shared__ double red[WG / WAVE];
   const double* p = partial + (int64_t)blockIdx.x * npart;
   double acc = 0;
   for (int i = threadIdx.x; i < npart; i += WG) acc += p[i];
   double s = block_sum(acc, red);
-  if (threadIdx.x == 0) out[blockIdx.x] = s;
+  if (threadIdx.x == 0) out[(int64_t)blockIdx.x * stride] = s;
 }
 
 // CG scalars per column.  st layout per column: [rz, pAp, rr, alpha, beta, active].
+// Every iteration starts from z = M r: with rz = +inf and p = 0 before the
+// first one, its beta is 0 and p = z.
 __global__ void k_cg_alpha(double* st, int nrhs) {
   int c = threadIdx.x;
   if (c < nrhs) {

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <limits>
 #include <memory>
 #include <stdexcept>
 #include <string>
@@ -111,6 +112,7 @@ struct LevelDev {
   std::vector<sgf::TFront> h_tf, h_ctf;
   int64_t z_elems = 0, u_elems = 0;
   int tmax_m = 0, tmax_k = 0, tmax_rm = 0;
+  int band_bw = -1, band_m = 0, band_k = 0;   // widest band, largest m and k of the interiors (-1: none)
 };
 
 struct Profiler {
@@ -141,6 +143,17 @@ struct Profiler {
     hipEvent_t e;
     if (hipEventCreate(&e) != hipSuccess) throw std::runtime_error("hipEventCreate failed");
     return e;
+  }
+  // Adds work to a kernel (and its "<name>@L<level>" tag) that is known only
+  // after the launch, e.g. once the ranks of a compression are read back.
+  void charge(const char* name, int level, double flops, double bytes) {
+    if (!on) return;
+    char tag[32];
+    std::snprintf(tag, sizeof(tag), "%s@L%d", name, level);
+    for (int i : {index(name), index(tag)}) {
+      stats[i].flops += flops;
+      stats[i].bytes += bytes;
+    }
   }
   void drain() {
     for (auto& p : tagged) {
@@ -213,7 +226,7 @@ struct sgf_handle_s {
   DevBuf d_ctr, d_zero_idx;   // work counter of the persistent launches; the one-item list {0}
   std::vector<LevelDev> lev;
   DevBuf y, tscr;
-  DevBuf cg_r, cg_z, cg_p, cg_ap, cg_part, cg_st, cg_scal;
+  DevBuf cg_r, cg_z, cg_p, cg_ap, cg_x, cg_part, cg_st, cg_scal;
   int64_t max_t = 0;
   int32_t max_m_all = 0, max_k_all = 0, max_s_all = 0;
   int32_t failed_cluster = -1, failed_level = -1;
@@ -238,6 +251,8 @@ struct sgf_handle_s {
   // arguments and the factorization it belongs to), replayed on the caller's
   // stream; captured on a private stream of default priority
   bool use_graph = true;
+  bool capturing = false;   // a graph is being recorded: launch directly
+  bool band_apply = true;
   int32_t persist_cap = 0;   // > 0: per-level work lists persistent on at most this many workgroups
   uint64_t epoch = 0;
   hipStream_t cap_stream = nullptr;
@@ -250,9 +265,25 @@ struct sgf_handle_s {
     bool product = false;
     uint64_t epoch = 0;
   } ag;
+  // one PCG iteration (apply, CG scalars and vector updates, SpMV, dots)
+  // captured for the buffers and solution pointer it was recorded with
+  // (the handle's own CG buffers only, so one graph serves every caller),
+  // a few kept for different right-hand-side counts
+  struct IterGraph {
+    hipGraphExec_t exec = nullptr;
+    int nrhs = 0;
+    const void* bufs[8] = {};
+    uint64_t epoch = 0;
+    uint64_t used = 0;
+  };
+  std::vector<IterGraph> ig;
+  uint64_t ig_clock = 0;
   void drop_graph() {
     if (ag.exec) (void)hipGraphExecDestroy(ag.exec);
     ag.exec = nullptr;
+    for (auto& g : ig)
+      if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    ig.clear();
   }
   ~sgf_handle_s() {
     drop_graph();
@@ -353,15 +384,14 @@ void launch_elim(int nb, unsigned grid, size_t lds, hipStream_t st, const sgf::E
   else launch_elim_p<T, false>(nb, grid, lds, st, d, arena, fail, order, n, ctr);
 }
 
-// Launch shape of a level's work list of n items.  Persistent (grid = the
-// workgroups one pass of the chip holds at this LDS size, items taken from a
-// counter) when the list is longer than that and its costs are uneven;
-// otherwise one workgroup per item.  Returns the grid; *persist tells which.
-unsigned work_grid(int n, size_t lds, bool uneven, bool* persist, int cap) {
-  const size_t occ = std::max<size_t>(1, std::min<size_t>(8, LDS_MAX_BYTES / std::max<size_t>(lds, 1)));
-  const int64_t slots = cap > 0 ? cap : 256 * (int64_t)occ;
-  *persist = cap > 0 || (uneven && n > slots);
-  return (unsigned)std::max<int64_t>(1, *persist ? std::min<int64_t>(slots, n) : n);
+// Launch shape of a level's work list of n items: one workgroup per item in
+// cluster order, or, when a cap is set, persistent (grid = min(cap, n)
+// workgroups taking items costliest first from a counter).  Returns the
+// grid; *persist tells which.  Measured on the 2D level-1 fronts the
+// one-item launch is the faster (1.17 vs 1.57 ms), so it is the default.
+unsigned work_grid(int n, bool* persist, int cap) {
+  *persist = cap > 0;
+  return (unsigned)std::max<int64_t>(1, *persist ? std::min<int64_t>(cap, n) : n);
 }
 
 template <typename T, bool NLDS, bool PERS, typename... A>
@@ -418,6 +448,27 @@ double elim_entries(double m, double k, double bw) {
 // once and written once.
 double elim_bytes(double m, double k, double bw, double e) {
   return 2.0 * e * (elim_entries(m, k, bw) + k * (k + 1) / 2);
+}
+
+// Algorithmic work of compressing one separator (s rows, K neighbour rows,
+// c = columns of N, numerical rank r, pi basis vectors): Cholesky of M_BB and
+// L_B^{-1} M_BX unless already factored, N (Eq. 4.5), the pivoted QR stopped
+// at rank r (Eq. 3.3) and Q^T applied to L^T Phi_B (Eq. 3.4).
+double comp_flops(double s, double K, double c, double r, double pi, bool prefactored) {
+  double f = prefactored ? 0.0 : s * s * s / 3.0 + s * s * K;
+  f += s * s * pi + 2.0 * s * K * pi;
+  f += 4.0 * s * c * r - 2.0 * r * r * (s + c) + 4.0 * r * r * r / 3.0;
+  if (r < s) f += 4.0 * s * r * pi;
+  return f;
+}
+// Its HBM bytes: the front (lower M_BB and M_XB) read, and written back when
+// factored here; Phi of B and its neighbours read; L^T Phi_B written (and
+// rewritten by Q^T when r < s); the reflectors (s x r) and tau written.
+double comp_bytes(double s, double K, double c, double r, double pi, bool prefactored, double e) {
+  const double front = s * (s + 1) / 2 + K * s;
+  double b = (prefactored ? 1.0 : 2.0) * front + (s + K) * pi + s * pi + s * r + c;
+  if (r < s) b += 2.0 * s * pi;
+  return b * e;
 }
 
 // Whether the interiors of level L are eliminated by the tiled multi-workgroup
@@ -522,9 +573,17 @@ void upload_level(sgf_handle h, int li, hipStream_t st) {
   upload(D.phioff, L.phi_off, st);
   D.tiled = level_tiled(h, L);
   if (D.tiled) build_tiled(h, L, D, st);
+  D.band_bw = -1;
+  D.band_m = D.band_k = 0;
+  for (const auto& e : L.elim) {
+    D.band_bw = std::max(D.band_bw, std::min(e.bw, std::max(e.m - 1, 0)));
+    D.band_m = std::max(D.band_m, e.m);
+    D.band_k = std::max(D.band_k, e.k);
+  }
   {
-    // work lists: costliest first when the costs differ by more than 2x
-    // (longest-processing-time order), else cluster order (memory locality)
+    // work lists of the persistent launches: costliest first when the costs
+    // differ by more than 2x (longest-processing-time order), else cluster
+    // order (memory locality)
     auto order = [](std::vector<int32_t>& o, size_t n, const std::function<double(int32_t)>& cost, bool* uneven) {
       o.resize(n);
       for (size_t i = 0; i < n; ++i) o[i] = (int32_t)i;
@@ -855,11 +914,12 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
       size_t lds = (size_t)sgf::potrf_lds_elems(L.max_front_rows, nb) * sizeof(T);
       const int ne = (int)L.elim.size();
       bool persist = false;
-      const unsigned grid = work_grid(ne, lds, D.elim_uneven, &persist, h->persist_cap);
+      const unsigned grid = work_grid(ne, &persist, h->persist_cap);
       if (persist) HIP_CHECK(hipMemsetAsync(h->d_ctr.p, 0, sizeof(int), st));
       launch(h, st, "elim", lvl_elim_flops, lvl_elim_bytes, [&] {
         launch_elim<T>(nb, grid, lds, st, D.elim.as<sgf::ElimDesc>(), arena, h->d_fail.as<int>(),
-                       D.elim_order.as<int32_t>(), ne, persist ? h->d_ctr.as<int>() : nullptr);
+                       D.elim_order.as<int32_t>(), ne,
+                       persist ? h->d_ctr.as<int>() : nullptr);
       }, L.t);
     }
     h->trace.mark("elimination queued", L.t);
@@ -905,7 +965,7 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
       double tol = P.opt.rank_tol;
       const int pre = D.comp_tiled ? 1 : 0;
       bool cpersist = false;
-      const unsigned cgrid = work_grid((int)L.comp.size(), lds, D.comp_uneven, &cpersist, h->persist_cap);
+      const unsigned cgrid = work_grid((int)L.comp.size(), &cpersist, h->persist_cap);
       if (cpersist) HIP_CHECK(hipMemsetAsync(h->d_ctr.p, 0, sizeof(int), st));
       launch(h, st, "compress", 0, 0, [&] {
         launch_compress<T>(nlds, cpersist, nb, cgrid, lds, st, D.comp.as<sgf::CompDesc>(),
@@ -932,6 +992,15 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
       throw SgfError(SGF_ENOTSPD, "non-positive pivot at level " + std::to_string(L.t));
     }
     h->trace.mark("synchronized (ranks read)", L.t);
+    if (h->prof.on && !L.comp.empty()) {
+      double cf = 0, cb = 0;
+      for (size_t c = 0; c < L.comp.size(); ++c) {
+        const auto& d = L.comp[c];
+        cf += comp_flops(d.s, d.K, d.c, L.rank[c], P.pi, D.comp_tiled);
+        cb += comp_bytes(d.s, d.K, d.c, L.rank[c], P.pi, D.comp_tiled, sizeof(T));
+      }
+      h->prof.charge("compress", L.t, cf, cb);
+    }
     const bool same_ranks = reuse_next && L.rank == L.planned_rank;
     if (h->trace.on) {
       int ndiff = -1;
@@ -1069,12 +1138,42 @@ void ensure_work(sgf_handle h, int nrhs) {
   h->tscr.ensure((size_t)std::max<int64_t>(h->max_t, 1) * nrhs * sizeof(T));
 }
 
+void ensure_work_any(sgf_handle h, int nrhs) {
+  if (h->esz == 8) ensure_work<double>(h, nrhs);
+  else ensure_work<float>(h, nrhs);
+}
+
 // Right-hand sides per workgroup of an apply kernel whose LDS holds `fixed`
 // bytes plus `per_rhs` bytes per column.
 int rc_for(size_t fixed, size_t per_rhs, int nrhs) {
   if (fixed + per_rhs > LDS_BYTES) throw SgfError(SGF_EINVAL, "apply kernel needs more LDS than available");
   int rc = std::min(sgf::RCM, nrhs);
   while (rc > 1 && fixed + rc * per_rhs > LDS_BYTES) --rc;
+  return rc;
+}
+
+// Whether the interior sweeps of a level run the banded kernels: enabled,
+// one-workgroup fronts, a band of at most BAND_MAX and the LDS for one rhs.
+// Columns per transposed L_SI tile of the banded backward sweep: 64, halved
+// while one right-hand side's LDS does not fit (at least 8).
+int band_tj(sgf_handle h, const LevelDev& D) {
+  int tj = sgf::WAVE;
+  while (tj > 8 && (size_t)sgf::band_bwd_lds(D.band_m, D.band_k, D.band_bw, 1, tj) * h->esz > LDS_BYTES) tj /= 2;
+  return tj;
+}
+int64_t band_lds(sgf_handle h, const LevelDev& D, bool fwd, int rc) {
+  return fwd ? sgf::band_fwd_lds(D.band_m, D.band_k, D.band_bw, rc)
+             : sgf::band_bwd_lds(D.band_m, D.band_k, D.band_bw, rc, band_tj(h, D));
+}
+bool band_level(sgf_handle h, const LevelDev& D, bool fwd) {
+  if (!h->band_apply || D.tiled || D.band_bw < 0 || D.band_bw > sgf::BAND_MAX) return false;
+  return (size_t)band_lds(h, D, fwd, 1) * h->esz <= LDS_BYTES;
+}
+// Right-hand sides per workgroup of the banded sweeps: at most one per
+// wavefront and what the LDS holds.
+int band_rc(sgf_handle h, const LevelDev& D, bool fwd, int nrhs) {
+  int rc = std::min(sgf::RCM, nrhs);
+  while (rc > 1 && (size_t)band_lds(h, D, fwd, rc) * h->esz > LDS_BYTES) --rc;
   return rc;
 }
 
@@ -1113,6 +1212,20 @@ void run_sweeps(sgf_handle h, int nrhs, bool product, hipStream_t st) {
         hipLaunchKernelGGL((sgf::k_tfwd_s<T, T>), dim3(std::max(1u, cdiv(D.tmax_k, sgf::TB)), nf, cdiv(nrhs, rc2)),
                            dim3(sgf::WG), (size_t)rc2 * (mp + sgf::WG) * e, st, D.tf.as<sgf::TFront>(),
                            D.arena.as<T>(), D.uw.as<T>(), D.u_elems, D.slots.as<int32_t>(), y, n, ts, ldt, nrhs, rc2);
+      }, L.t);
+      return;
+    }
+    if (mode == 0 && band_level(h, D, true)) {
+      const int rc = band_rc(h, D, true, nrhs);
+      const size_t lds = (size_t)sgf::band_fwd_lds(D.band_m, D.band_k, D.band_bw, rc) * sizeof(T);
+      launch(h, st, "apply_band_fwd", 0, cdiv(nrhs, rc) * D.work.fwd_bytes + nrhs * D.work.fwd_vec, [&] {
+        const dim3 g((unsigned)L.elim.size(), cdiv(nrhs, rc));
+        const sgf::ElimDesc* dd = D.elim.as<sgf::ElimDesc>();
+        const int32_t* sl = D.slots.as<int32_t>();
+        if (rc == 1) hipLaunchKernelGGL((sgf::k_band_fwd<T, 1>), g, dim3(sgf::WG), lds, st, dd, D.arena.as<T>(), sl, y, n, ts, ldt, nrhs);
+        else if (rc == 2) hipLaunchKernelGGL((sgf::k_band_fwd<T, 2>), g, dim3(sgf::WG), lds, st, dd, D.arena.as<T>(), sl, y, n, ts, ldt, nrhs);
+        else if (rc == 3) hipLaunchKernelGGL((sgf::k_band_fwd<T, 3>), g, dim3(sgf::WG), lds, st, dd, D.arena.as<T>(), sl, y, n, ts, ldt, nrhs);
+        else hipLaunchKernelGGL((sgf::k_band_fwd<T, 4>), g, dim3(sgf::WG), lds, st, dd, D.arena.as<T>(), sl, y, n, ts, ldt, nrhs);
       }, L.t);
       return;
     }
@@ -1155,6 +1268,22 @@ void run_sweeps(sgf_handle h, int nrhs, bool product, hipStream_t st) {
         hipLaunchKernelGGL((sgf::k_tbwd_z<T, T>), dim3(cdiv(D.tmax_m, sgf::TB), nf, cdiv(nrhs, rc2)), dim3(sgf::WG),
                            (size_t)rc2 * (mp + sgf::WG) * e, st, D.tf.as<sgf::TFront>(), D.zt.as<T>(), D.uw.as<T>(),
                            D.u_elems, D.slots.as<int32_t>(), y, n, nrhs, rc2);
+      }, L.t);
+      return;
+    }
+    if (mode == 0 && band_level(h, D, false)) {
+      const int rc = band_rc(h, D, false, nrhs);
+      const int tj = band_tj(h, D);
+      const size_t lds = (size_t)sgf::band_bwd_lds(D.band_m, D.band_k, D.band_bw, rc, tj) * sizeof(T);
+      launch(h, st, "apply_band_bwd", 0, cdiv(nrhs, rc) * D.work.bwd_bytes + nrhs * D.work.bwd_vec, [&] {
+        const dim3 g((unsigned)L.elim.size(), cdiv(nrhs, rc));
+        const sgf::ElimDesc* dd = D.elim.as<sgf::ElimDesc>();
+        const int32_t* sl = D.slots.as<int32_t>();
+        const int32_t* ns = D.nslots.as<int32_t>();
+        if (rc == 1) hipLaunchKernelGGL((sgf::k_band_bwd<T, 1>), g, dim3(sgf::WG), lds, st, dd, D.arena.as<T>(), sl, ns, y, n, nrhs, tj);
+        else if (rc == 2) hipLaunchKernelGGL((sgf::k_band_bwd<T, 2>), g, dim3(sgf::WG), lds, st, dd, D.arena.as<T>(), sl, ns, y, n, nrhs, tj);
+        else if (rc == 3) hipLaunchKernelGGL((sgf::k_band_bwd<T, 3>), g, dim3(sgf::WG), lds, st, dd, D.arena.as<T>(), sl, ns, y, n, nrhs, tj);
+        else hipLaunchKernelGGL((sgf::k_band_bwd<T, 4>), g, dim3(sgf::WG), lds, st, dd, D.arena.as<T>(), sl, ns, y, n, nrhs, tj);
       }, L.t);
       return;
     }
@@ -1279,6 +1408,36 @@ void run_sweeps(sgf_handle h, int nrhs, bool product, hipStream_t st) {
   }
 }
 
+// Records body(stream) on the handle's private stream as a graph and
+// instantiates it.  No event records inside (profiling paused); the body
+// must launch kernels only (no memset nodes).
+template <typename F>
+hipGraphExec_t capture_graph(sgf_handle h, F&& body) {
+  if (!h->cap_stream) HIP_CHECK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+  const bool prof = h->prof.on;
+  h->prof.on = false;
+  h->capturing = true;
+  HIP_CHECK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+  hipGraph_t graph = nullptr;
+  try {
+    body(h->cap_stream);
+  } catch (...) {
+    (void)hipStreamEndCapture(h->cap_stream, &graph);
+    if (graph) (void)hipGraphDestroy(graph);
+    h->prof.on = prof;
+    h->capturing = false;
+    throw;
+  }
+  h->prof.on = prof;
+  h->capturing = false;
+  HIP_CHECK(hipStreamEndCapture(h->cap_stream, &graph));
+  hipGraphExec_t exec = nullptr;
+  const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  HIP_CHECK(e);
+  return exec;
+}
+
 template <typename T>
 void apply_impl(sgf_handle h, int nrhs, const double* r, int64_t ldr, double* z, int64_t ldz, bool product,
                 hipStream_t st) {
@@ -1297,7 +1456,7 @@ void apply_impl(sgf_handle h, int nrhs, const double* r, int64_t ldr, double* z,
                          h->y.as<T>(), n, z, ldz);
     });
   };
-  if (!h->use_graph) {
+  if (!h->use_graph || h->capturing) {
     body(st);
     HIP_CHECK(hipGetLastError());
     return;
@@ -1305,26 +1464,9 @@ void apply_impl(sgf_handle h, int nrhs, const double* r, int64_t ldr, double* z,
   auto& G = h->ag;
   if (!(G.exec && G.nrhs == nrhs && G.r == r && G.ldr == ldr && G.z == z && G.ldz == ldz && G.product == product &&
         G.epoch == h->epoch)) {
-    h->drop_graph();
-    if (!h->cap_stream) HIP_CHECK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
-    const bool prof = h->prof.on;
-    h->prof.on = false;   // no event records inside the graph
-    HIP_CHECK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
-    hipGraph_t graph = nullptr;
-    try {
-      body(h->cap_stream);
-    } catch (...) {
-      (void)hipStreamEndCapture(h->cap_stream, &graph);
-      if (graph) (void)hipGraphDestroy(graph);
-      h->prof.on = prof;
-      throw;
-    }
-    h->prof.on = prof;
-    HIP_CHECK(hipStreamEndCapture(h->cap_stream, &graph));
-    hipGraphExec_t exec = nullptr;
-    const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    HIP_CHECK(e);
+    if (G.exec) (void)hipGraphExecDestroy(G.exec);
+    G.exec = nullptr;
+    hipGraphExec_t exec = capture_graph(h, body);
     G.exec = exec;
     G.nrhs = nrhs;
     G.r = r;
@@ -1351,7 +1493,7 @@ void dot_cols(sgf_handle h, const double* a, const double* b, int nrhs, double* 
                        h->cg_part.as<double>());
   });
   launch(h, st, "cg_reduce", 0, 8.0 * nb * nrhs, [&] {
-    hipLaunchKernelGGL(sgf::k_reduce, dim3(nrhs), dim3(sgf::WG), 0, st, h->cg_part.as<double>(), nb, out);
+    hipLaunchKernelGGL(sgf::k_reduce, dim3(nrhs), dim3(sgf::WG), 0, st, h->cg_part.as<double>(), nb, out, 1);
   });
 }
 
@@ -1360,7 +1502,7 @@ int64_t device_bytes(sgf_handle h) {
   int64_t b = 0;
   for (const DevBuf* x : {&h->d_perm, &h->d_rowptr, &h->d_colidx, &h->d_vals, &h->d_csrdst, &h->d_coords, &h->d_fail,
                           &h->d_ctr, &h->d_zero_idx,
-                          &h->y, &h->tscr, &h->cg_r, &h->cg_z, &h->cg_p, &h->cg_ap, &h->cg_part, &h->cg_st,
+                          &h->y, &h->tscr, &h->cg_r, &h->cg_z, &h->cg_p, &h->cg_ap, &h->cg_x, &h->cg_part, &h->cg_st,
                           &h->cg_scal, &h->top64, &h->topz, &h->topu, &h->d_topdesc, &h->d_toptf})
     b += x->bytes;
   for (const auto& D : h->lev)
@@ -1501,10 +1643,14 @@ sgf_status sgf_autotune(sgf_handle h, const double* vals, int32_t napply, int32_
       }
     } restore{h, prof_was, saved, h->use_graph};
     h->use_graph = false;   // per-level apply timings need direct launches
+    // every candidate runs three times, interleaved, and keeps its fastest
+    // time per level (a single trial is noisy, the first pays cold memory)
     const int candidates[] = {0, 8, 16, 32};
-    std::vector<std::vector<double>> cost;   // [candidate][level]
-    std::vector<std::vector<char>> honored;  // the level really ran that candidate
-    for (int c : candidates) {
+    const int nc = 4, reps = 3;
+    std::vector<std::vector<double>> cost(nc);   // [candidate][level]
+    std::vector<std::vector<char>> honored(nc);  // the level really ran that candidate
+    for (int trial = 0; trial < nc * reps; ++trial) {
+      const int ci = trial % nc, c = candidates[ci];
       h->force_mode = c;
       h->level_mode.clear();
       for (auto& D : h->lev) D.uploaded = false;
@@ -1529,11 +1675,17 @@ sgf_status sgf_autotune(sgf_handle h, const double* vals, int32_t napply, int32_
           if (at == std::string::npos || nm.substr(at) != tag) continue;
           const std::string base = nm.substr(0, at);
           if (base == "elim" || base.rfind("elim_", 0) == 0) lc[li] += k.ms;
-          else if (base == "apply_elim_fwd" || base == "apply_elim_bwd") lc[li] += napply * k.ms;
+          else if (base == "apply_elim_fwd" || base == "apply_elim_bwd" || base == "apply_band_fwd" ||
+                   base == "apply_band_bwd")
+            lc[li] += napply * k.ms;
         }
       }
-      cost.push_back(lc);
-      honored.push_back(ok);
+      if (cost[ci].empty()) {
+        cost[ci] = lc;
+        honored[ci] = ok;
+      } else {
+        for (int li = 0; li < nl; ++li) cost[ci][li] = std::min(cost[ci][li], lc[li]);
+      }
     }
     const int nl = (int)h->plan.levels.size();
     std::vector<int32_t> modes(nl, -1);
@@ -1609,6 +1761,7 @@ sgf_status sgf_pcg_solve(sgf_handle h, int32_t nrhs, const double* b, int64_t ld
     h->cg_z.ensure(vb);
     h->cg_p.ensure(vb);
     h->cg_ap.ensure(vb);
+    h->cg_x.ensure(vb);
     const int nbs = (int)std::min<int64_t>(1024, cdiv(n, sgf::WG));
     const int nbspmv = (int)spmv_blocks(h);
     h->cg_part.ensure((size_t)std::max(nbs, nbspmv) * nrhs * sizeof(double));
@@ -1618,13 +1771,18 @@ sgf_status sgf_pcg_solve(sgf_handle h, int32_t nrhs, const double* b, int64_t ld
     double* z = h->cg_z.as<double>();
     double* p = h->cg_p.as<double>();
     double* Ap = h->cg_ap.as<double>();
+    double* xi = h->cg_x.as<double>();   // iterate, copied to x at the end
     double* stv = h->cg_st.as<double>();
     double* sc = h->cg_scal.as<double>();
-    for (int c = 0; c < nrhs; ++c) {
-      HIP_CHECK(hipMemsetAsync(x + c * ldx, 0, n * sizeof(double), st));
+    for (int c = 0; c < nrhs; ++c)
       HIP_CHECK(hipMemcpyAsync(r + c * n, b + c * ldb, n * sizeof(double), hipMemcpyDeviceToDevice, st));
-    }
-    std::vector<double> hst(8 * nrhs, 0.0), bn(nrhs), rr(nrhs);
+    HIP_CHECK(hipMemsetAsync(xi, 0, vb, st));
+    HIP_CHECK(hipMemsetAsync(p, 0, vb, st));
+    auto copy_out = [&] {
+      HIP_CHECK(hipMemcpy2DAsync(x, ldx * sizeof(double), xi, n * sizeof(double), n * sizeof(double), nrhs,
+                                 hipMemcpyDeviceToDevice, st));
+    };
+    std::vector<double> hst(8 * nrhs, 0.0), bn(nrhs), rr(nrhs), act(nrhs);
     dot_cols(h, r, r, nrhs, sc, st);
     HIP_CHECK(hipMemcpyAsync(bn.data(), sc, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_CHECK(hipStreamSynchronize(st));
@@ -1636,34 +1794,76 @@ sgf_status sgf_pcg_solve(sgf_handle h, int32_t nrhs, const double* b, int64_t ld
       nactive += active[c];
       iters[c] = 0;
       relres[c] = 0.0;
+      hst[8 * c + 0] = std::numeric_limits<double>::infinity();   // first beta = 0
       hst[8 * c + 5] = active[c];
     }
     HIP_CHECK(hipMemcpyAsync(stv, hst.data(), 8 * nrhs * sizeof(double), hipMemcpyHostToDevice, st));
     if (nactive == 0) {
+      copy_out();
       HIP_CHECK(hipStreamSynchronize(st));
       return;
     }
-    apply_any(h, nrhs, r, n, z, n, false, st);
-    dot_cols(h, r, z, nrhs, sc, st);
-    for (int c = 0; c < nrhs; ++c)
-      HIP_CHECK(hipMemcpyAsync(stv + 8 * c, sc + c, sizeof(double), hipMemcpyDeviceToDevice, st));
-    HIP_CHECK(hipMemcpyAsync(p, z, vb, hipMemcpyDeviceToDevice, st));
     dim3 gv(cdiv(n, sgf::WG), nrhs);
     const double spmv_bytes = cdiv(nrhs, 8) * (12.0 * h->nnz + 8.0 * (n + 1)) + nrhs * 24.0 * n;
+    // one iteration: z = M r, rz, beta, p = z + beta p, Ap and p.Ap, alpha,
+    // x += alpha p, r -= alpha Ap, rr -> sc (the only value the host reads)
+    auto iteration = [&](hipStream_t s) {
+      apply_any(h, nrhs, r, n, z, n, false, s);
+      dot_cols(h, r, z, nrhs, sc, s);
+      launch(h, s, "cg_scalar", 0, 0, [&] { hipLaunchKernelGGL(sgf::k_cg_beta, dim3(1), dim3(256), 0, s, stv, sc, nrhs); });
+      launch(h, s, "cg_axpy", 0, 24.0 * n * nrhs, [&] {
+        hipLaunchKernelGGL(sgf::k_cg_update_p, gv, dim3(sgf::WG), 0, s, p, z, n, n, stv);
+      });
+      launch(h, s, "cg_spmv", 0, spmv_bytes, [&] { spmv_launch(h, p, n, Ap, n, nrhs, h->cg_part.as<double>(), s); });
+      launch(h, s, "cg_reduce", 0, 8.0 * nbspmv * nrhs, [&] {
+        hipLaunchKernelGGL(sgf::k_reduce, dim3(nrhs), dim3(sgf::WG), 0, s, h->cg_part.as<double>(), nbspmv, stv + 1, 8);
+      });
+      launch(h, s, "cg_scalar", 0, 0, [&] { hipLaunchKernelGGL(sgf::k_cg_alpha, dim3(1), dim3(256), 0, s, stv, nrhs); });
+      launch(h, s, "cg_axpy", 0, 48.0 * n * nrhs, [&] {
+        hipLaunchKernelGGL(sgf::k_cg_update_xr, gv, dim3(sgf::WG), 0, s, xi, n, r, n, p, Ap, n, n, stv);
+      });
+      dot_cols(h, r, r, nrhs, sc, s);
+    };
+    const double iter_bytes = h->apply_bytes * nrhs + spmv_bytes + 2 * 16.0 * n * nrhs + 72.0 * n * nrhs;
+    const void* bufs[8] = {r, z, p, Ap, stv, sc, h->cg_part.p, xi};
+    hipGraphExec_t exec = nullptr;
+    if (h->use_graph) {
+      ensure_work_any(h, nrhs);   // allocations before a capture, not inside it
+      // drop graphs recorded on older buffers or factors; reuse or record one
+      // for this rhs count (at most four kept, least recently used evicted)
+      auto& IG = h->ig;
+      for (size_t i = 0; i < IG.size();) {
+        if (IG[i].epoch != h->epoch || !std::equal(bufs, bufs + 8, IG[i].bufs)) {
+          (void)hipGraphExecDestroy(IG[i].exec);
+          IG.erase(IG.begin() + i);
+        } else {
+          ++i;
+        }
+      }
+      for (auto& g : IG)
+        if (g.nrhs == nrhs) exec = g.exec, g.used = ++h->ig_clock;
+      if (!exec) {
+        if (IG.size() >= 4) {
+          auto old = std::min_element(IG.begin(), IG.end(), [](const auto& a, const auto& b) { return a.used < b.used; });
+          (void)hipGraphExecDestroy(old->exec);
+          IG.erase(old);
+        }
+        sgf_handle_s::IterGraph g;
+        g.exec = capture_graph(h, iteration);
+        g.nrhs = nrhs;
+        g.epoch = h->epoch;
+        g.used = ++h->ig_clock;
+        std::copy(bufs, bufs + 8, g.bufs);
+        IG.push_back(g);
+        exec = g.exec;
+      }
+    }
     for (int it = 1; it <= maxit; ++it) {
-      launch(h, st, "cg_spmv", 0, spmv_bytes, [&] {
-        spmv_launch(h, p, n, Ap, n, nrhs, h->cg_part.as<double>(), st);
-      });
-      launch(h, st, "cg_reduce", 0, 8.0 * nbspmv * nrhs, [&] {
-        hipLaunchKernelGGL(sgf::k_reduce, dim3(nrhs), dim3(sgf::WG), 0, st, h->cg_part.as<double>(), nbspmv, sc);
-      });
-      for (int c = 0; c < nrhs; ++c)
-        HIP_CHECK(hipMemcpyAsync(stv + 8 * c + 1, sc + c, sizeof(double), hipMemcpyDeviceToDevice, st));
-      launch(h, st, "cg_scalar", 0, 0, [&] { hipLaunchKernelGGL(sgf::k_cg_alpha, dim3(1), dim3(256), 0, st, stv, nrhs); });
-      launch(h, st, "cg_axpy", 0, 48.0 * n * nrhs, [&] {
-        hipLaunchKernelGGL(sgf::k_cg_update_xr, gv, dim3(sgf::WG), 0, st, x, ldx, r, n, p, Ap, n, n, stv);
-      });
-      dot_cols(h, r, r, nrhs, sc, st);
+      if (exec) {
+        launch(h, st, "pcg_iteration_graph", 0, iter_bytes, [&] { HIP_CHECK(hipGraphLaunch(exec, st)); });
+      } else {
+        iteration(st);
+      }
       HIP_CHECK(hipMemcpyAsync(rr.data(), sc, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
       HIP_CHECK(hipStreamSynchronize(st));
       bool changed = false;
@@ -1682,20 +1882,15 @@ sgf_status sgf_pcg_solve(sgf_handle h, int32_t nrhs, const double* b, int64_t ld
       }
       if (changed) {
         for (int c = 0; c < nrhs; ++c) {
-          double a = active[c];
-          HIP_CHECK(hipMemcpyAsync(stv + 8 * c + 5, &a, sizeof(double), hipMemcpyHostToDevice, st));
-          HIP_CHECK(hipStreamSynchronize(st));
+          act[c] = active[c];
+          HIP_CHECK(hipMemcpyAsync(stv + 8 * c + 5, &act[c], sizeof(double), hipMemcpyHostToDevice, st));
         }
+        HIP_CHECK(hipStreamSynchronize(st));
       }
       if (nactive == 0) break;
-      apply_any(h, nrhs, r, n, z, n, false, st);
-      dot_cols(h, r, z, nrhs, sc, st);
-      launch(h, st, "cg_scalar", 0, 0, [&] { hipLaunchKernelGGL(sgf::k_cg_beta, dim3(1), dim3(256), 0, st, stv, sc, nrhs); });
-      launch(h, st, "cg_axpy", 0, 24.0 * n * nrhs, [&] {
-        hipLaunchKernelGGL(sgf::k_cg_update_p, gv, dim3(sgf::WG), 0, st, p, z, n, n, stv);
-      });
       HIP_CHECK(hipGetLastError());
     }
+    copy_out();
     HIP_CHECK(hipStreamSynchronize(st));
     for (int c = 0; c < nrhs; ++c)
       if (active[c]) all_conv = false;
@@ -1712,7 +1907,7 @@ sgf_status sgf_release(sgf_handle h) {
     h->lev.clear();
     for (DevBuf* b : {&h->d_perm, &h->d_rowptr, &h->d_colidx, &h->d_vals, &h->d_csrdst, &h->d_coords, &h->d_fail,
                       &h->d_ctr, &h->d_zero_idx,
-                      &h->y, &h->tscr, &h->cg_r, &h->cg_z, &h->cg_p, &h->cg_ap, &h->cg_part, &h->cg_st,
+                      &h->y, &h->tscr, &h->cg_r, &h->cg_z, &h->cg_p, &h->cg_ap, &h->cg_x, &h->cg_part, &h->cg_st,
                       &h->cg_scal, &h->top64, &h->topz, &h->topu, &h->d_topdesc, &h->d_toptf})
       b->release();
     h->plan.levels.resize(1);
@@ -1729,7 +1924,7 @@ sgf_status sgf_estimate_bytes(sgf_handle h, int32_t nrhs, int64_t* bytes) {
   return guard([&] {
     const double e = (double)h->esz;
     const int64_t n = h->plan.n;
-    double work = (double)nrhs * (n * e + 4.0 * n * 8 + 3.0 * n * 8);
+    double work = (double)nrhs * (n * e + 5.0 * n * 8 + 3.0 * n * 8);
     if (h->factored) {
       *bytes = device_bytes(h) + (int64_t)work;
       return;
@@ -1841,6 +2036,14 @@ sgf_status sgf_set_persistent(sgf_handle h, int32_t max_workgroups) {
   if (!h || max_workgroups < 0) return fail(SGF_EINVAL, "bad persistent-launch argument");
   h->persist_cap = max_workgroups;
   return SGF_OK;
+}
+
+sgf_status sgf_set_band_apply(sgf_handle h, int32_t enable) {
+  if (!h) return fail(SGF_EINVAL, "NULL handle");
+  return guard([&] {
+    h->band_apply = enable != 0;
+    h->drop_graph();
+  });
 }
 
 sgf_status sgf_set_apply_graph(sgf_handle h, int32_t enable) {
