@@ -416,7 +416,7 @@ def main():
                     "sides (one batched PCG); value counts every right-hand side as a solve",
         },
         "tuning": {"modes_per_level": main_form["modes"], "autotune_s": round(main_form["tune_s"], 2),
-                   "legend": "0 tiled multi-workgroup elimination, 8/16/32 one workgroup per front with that "
+                   "legend": "0 tiled multi-workgroup elimination, 1 banded fronts one wavefront each, 8/16/32 one workgroup per front with that "
                              "panel width, -1 no interiors (top)"},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3), "p99": round(float(np.percentile(lat, 99)), 3)},
         "it_C": main_form["its"],

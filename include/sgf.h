@@ -141,15 +141,17 @@ sgf_status sgf_factorize(int64_t n, const int64_t* row_ptr, const int32_t* col_i
 /*
  * Autotuner of the batched elimination (one launch per level over clusters
  * of uneven sizes): factorizes `vals` three times per candidate (trials
- * interleaved) -- the tiled multi-workgroup path and the one-workgroup-per-
- * front path with panel widths 8, 16 and 32 -- and applies each result once,
+ * interleaved) -- the tiled multi-workgroup path, the banded one-wavefront
+ * fronts (where the level qualifies) and the one-workgroup-per-front path
+ * with panel widths 8, 16 and 32 -- and applies each result once,
  * timing every level's elimination plus `napply` times its forward and
  * backward interior sweeps with device events; each level then keeps the
  * candidate with the fastest of its three times.
  *   vals       DEVICE double[nnz] (as for sgf_factorize_numeric)
  *   napply     weight of the apply (expected applies per factorization)
  *   modes_out  HOST int32[levels] or NULL: chosen candidate per level
- *              (0 tiled, 8/16/32 panel width, -1 no interiors)
+ *              (0 tiled, 1 banded one-wavefront fronts, 8/16/32 panel
+ *              width, -1 no interiors)
  * Leaves the handle unfactored: call sgf_factorize_numeric next.  The choice
  * persists for later factorizations of the handle.
  */
@@ -269,6 +271,16 @@ sgf_status sgf_set_apply_graph(sgf_handle h, int32_t enable);
 sgf_status sgf_set_persistent(sgf_handle h, int32_t max_workgroups);
 
 /*
+ * Elimination (Eq. 4.2) of levels whose interiors all have M_II of lower
+ * bandwidth below 32 and at most 64 separator rows: enable = 1 (default)
+ * runs one wavefront per front (band Cholesky in LDS, L_SI row by row in
+ * registers, L_SI L_SI^T on the matrix cores), one launch per group of
+ * fronts of equal ring width (8, 16, 24, 32); 0 uses the panel kernels.
+ * Same factor up to rounding order.  Takes effect at the next factorization.
+ */
+sgf_status sgf_set_band_elim(sgf_handle h, int32_t enable);
+
+/*
  * Interior sweeps of the apply (Sec. 4.7) on levels whose M_II blocks have a
  * lower bandwidth of at most 64: enable = 1 (default) stages the band of L_I
  * in LDS and solves it one wavefront per right-hand side; 0 uses the blocked
@@ -327,6 +339,9 @@ typedef struct {
 
 /* Defaults: 200 GiB budget, 4 slots, 16 columns per batch. */
 void sgf_server_default_options(sgf_server_options* opt);
+/* With the environment variable SGF_SERVER_TRACE set at creation, every
+ * finished batch prints one bookkeeping line (slot, operator, columns, bytes
+ * reserved, held before and after, totals) on stderr. */
 sgf_status sgf_server_create(const sgf_server_options* opt, sgf_server* out);
 /* Registers an operator: the arguments of sgf_analyze plus its values
  * (HOST double[nnz]); all are copied.  Its analysis runs on a worker, ahead

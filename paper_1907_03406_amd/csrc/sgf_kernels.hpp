@@ -397,6 +397,200 @@ __global__ __launch_bounds__(WG) void k_elim(const ElimDesc* __restrict__ D, T* 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Banded interior fronts (Eq. 4.2 when M_II has lower bandwidth bw < W and
+// the front has at most 64 separator rows, e.g. the finest interiors of a 2D
+// grid numbered naturally): one wavefront per front of the list, three parts.
+//  1. Band Cholesky of M_II, right-looking one column per step, on a ring of
+//     three W-row blocks in LDS; band row i is stored by diagonals,
+//     ring[i][W-1-r] = A[i][i-r].  Columns of block b+1 are staged before
+//     the steps of block b (they hold the rows those steps update), from
+//     registers loaded one block ahead.  Each finished column of L_II is
+//     written to the front at once (coalesced).
+//  2. L_SI = M_SI L_II^{-T}: lane s owns separator row s and keeps its last W
+//     values in registers; the coefficients of row j of L_II are LDS
+//     broadcasts.
+//  3. S = L_SI L_SI^T on the matrix cores, 16 x 16 tiles of the lower
+//     triangle accumulated in registers over all blocks; -S is stored once
+//     into the front's separator block, which starts at zero (the couplings
+//     among separators live in the pair blocks).
+// Entries of L_II below the band are neither read nor written.
+// ---------------------------------------------------------------------------
+constexpr int BE_KMAX = 64;
+
+__host__ __device__ inline int64_t elim_banded_lds_elems(int w) { return 3 * w * w + 3 * w + (int64_t)BE_KMAX * (w + 1); }
+
+template <typename T, int W>
+__global__ __launch_bounds__(WAVE) void k_elim_banded(const ElimDesc* __restrict__ D, T* __restrict__ arena,
+                                                      int* fail, const int32_t* __restrict__ list) {
+  static_assert(W % 4 == 0 && (W * W) % WAVE == 0, "ring width");
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* ring = reinterpret_cast<T*>(smem_raw);   // 3W rows x W
+  T* dinv = ring + 3 * W * W;                 // reciprocal pivots, by ring row
+  T* tile = dinv + 3 * W;                     // 64 x (W + 1): the block of L_SI, row-major
+  typedef typename Mfma<T>::V V;
+  const ElimDesc d = D[list[blockIdx.x]];
+  const int m = d.m, k = d.k, R = m + k, bw = min(d.bw, W - 1);
+  T* C = arena + d.front_off;
+  const int lane = threadIdx.x;
+  auto rrow = [&](int i) { return ((i / W) % 3) * W + i % W; };   // ring row of band row i
+  // this lane's pairs (s, t), 1 <= t <= s <= bw, of the trailing update
+  constexpr int NP = (W * (W - 1) / 2 + WAVE - 1) / WAVE;
+  int ps[NP], pt[NP];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
+    int p = lane + q * WAVE, ss = 1;
+    while (ss <= bw && p >= ss) p -= ss++;
+    ps[q] = ss <= bw ? ss : 0;
+    pt[q] = ss <= bw ? p + 1 : 0;
+  }
+  // staging: entries A[c + r][c] of the columns c of a block, r = 0..bw
+  constexpr int NS = W * W / WAVE;
+  auto load_cols = [&](int b, T* v) {
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+      const int idx = lane + q * WAVE, c = b * W + idx / W, r = idx % W, i = c + r;
+      v[q] = (r <= bw && c < m && i < m) ? C[i + (int64_t)c * R] : T(0);
+    }
+  };
+  auto store_cols = [&](int b, const T* v) {
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+      const int idx = lane + q * WAVE, c = b * W + idx / W, r = idx % W, i = c + r;
+      if (r <= bw && c < m && i < m) ring[rrow(i) * W + (W - 1 - r)] = v[q];
+    }
+  };
+  auto zero_block = [&](int b) {
+    for (int idx = lane; idx < W * W; idx += WAVE) ring[(((b % 3) * W) + idx / W) * W + idx % W] = T(0);
+  };
+  const int nblk = (m + W - 1) / W;
+  T pre[NS];
+  zero_block(0);
+  zero_block(1);
+  __builtin_amdgcn_wave_barrier();
+  load_cols(0, pre);
+  store_cols(0, pre);
+  if (nblk > 1) load_cols(1, pre);
+  // separator row of this lane
+  const bool srow = lane < k;
+  const T* msi = C + m + lane;
+  T* lsi = C + m + lane;
+  T x[W], mnext[W];
+#pragma unroll
+  for (int t = 0; t < W; ++t) {
+    x[t] = T(0);
+    mnext[t] = (srow && t < m) ? msi[(int64_t)t * R] : T(0);
+  }
+  constexpr int KT = BE_KMAX / 16, NT = KT * (KT + 1) / 2;
+  const int kt = (k + 15) / 16;
+  V acc[NT];
+#pragma unroll
+  for (int q = 0; q < NT; ++q)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[q][v] = T(0);
+  for (int b = 0; b < nblk; ++b) {
+    const int j0 = b * W;
+    // stage the columns of block b + 1 (rows of blocks b + 1, b + 2); fetch those of b + 2
+    __builtin_amdgcn_wave_barrier();
+    if (b + 1 < nblk) {
+      zero_block(b + 2);
+      __builtin_amdgcn_wave_barrier();
+      store_cols(b + 1, pre);
+      if (b + 2 < nblk) load_cols(b + 2, pre);
+    }
+    T mcur[W];
+#pragma unroll
+    for (int t = 0; t < W; ++t) {
+      mcur[t] = mnext[t];
+      const int jn = j0 + W + t;
+      mnext[t] = (srow && jn < m) ? msi[(int64_t)jn * R] : T(0);
+    }
+    __builtin_amdgcn_wave_barrier();
+    // ---- 1. band Cholesky, columns j0 .. j0 + W - 1 ----
+    for (int t = 0; t < W && j0 + t < m; ++t) {
+      const int j = j0 + t;
+      T a = ring[rrow(j) * W + (W - 1)];
+      const int sl = lane;   // scaling lane: row j + lane, 1 <= lane <= bw
+      const bool sc = sl >= 1 && sl <= bw && j + sl < m;
+      const T colv = sc ? ring[rrow(j + sl) * W + (W - 1 - sl)] : T(0);
+      T as[NP], at[NP], e[NP];
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+        const bool on = ps[q] > 0 && j + ps[q] < m;
+        as[q] = on ? ring[rrow(j + ps[q]) * W + (W - 1 - ps[q])] : T(0);
+        at[q] = on ? ring[rrow(j + pt[q]) * W + (W - 1 - pt[q])] : T(0);
+        e[q] = on ? ring[rrow(j + ps[q]) * W + (W - 1 - (ps[q] - pt[q]))] : T(0);
+      }
+      if (!(a > T(0))) {
+        if (lane == 0) atomicCAS(fail, -1, d.cluster);
+        a = T(1);
+      }
+      const T l = sqrt(a), inv = T(1) / l, inv2 = inv * inv;
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int q = 0; q < NP; ++q)
+        if (ps[q] > 0 && j + ps[q] < m) ring[rrow(j + ps[q]) * W + (W - 1 - (ps[q] - pt[q]))] = e[q] - as[q] * at[q] * inv2;
+      if (sc) {
+        const T lv = colv * inv;
+        ring[rrow(j + sl) * W + (W - 1 - sl)] = lv;
+        C[(j + sl) + (int64_t)j * R] = lv;
+      }
+      if (lane == 0) {
+        ring[rrow(j) * W + (W - 1)] = l;
+        dinv[rrow(j)] = inv;
+        C[j + (int64_t)j * R] = l;
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+    // ---- 2. L_SI columns j0 .. j0 + W - 1 ----
+#pragma unroll
+    for (int t = 0; t < W; ++t) {
+      const int j = j0 + t;
+      if (j < m) {
+        const T* row = ring + rrow(j) * W;
+        T acc2 = mcur[t];
+#pragma unroll
+        for (int r = W - 1; r >= 1; --r) acc2 -= row[W - 1 - r] * x[(t - r + W) % W];
+        x[t] = acc2 * dinv[rrow(j)];
+        if (srow) lsi[(int64_t)j * R] = x[t];
+      } else {
+        x[t] = T(0);
+      }
+    }
+    // ---- 3. S += L_SI(:, block) L_SI(:, block)^T ----
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int t = 0; t < W; ++t) tile[lane * (W + 1) + t] = x[t];
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int c = 0; c < W / 4; ++c) {
+      T op[KT];
+#pragma unroll
+      for (int X = 0; X < KT; ++X) op[X] = tile[(16 * X + lane % 16) * (W + 1) + 4 * c + lane / 16];
+      int q = 0;
+#pragma unroll
+      for (int I = 0; I < KT; ++I)
+#pragma unroll
+        for (int J = 0; J <= I; ++J, ++q)
+          if (I < kt) acc[q] = Mfma<T>::op(op[I], op[J], acc[q]);
+    }
+  }
+  // the separator block of the front receives -L_SI L_SI^T (lower triangle)
+  int q = 0;
+#pragma unroll
+  for (int I = 0; I < KT; ++I)
+#pragma unroll
+    for (int J = 0; J <= I; ++J, ++q) {
+      if (I >= kt) continue;
+      const int col = 16 * J + lane % 16;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * I + Mfma<T>::drow(lane, v);
+        if (row < k && col < k && row >= col) C[(m + row) + (int64_t)(m + col) * R] = -acc[q][v];
+      }
+    }
+}
+
 // Subtract the interiors' Schur complements from the separator pair blocks,
 // contributions summed in ascending interior order.
 template <typename T>

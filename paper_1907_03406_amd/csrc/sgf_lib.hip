@@ -113,6 +113,13 @@ struct LevelDev {
   int64_t z_elems = 0, u_elems = 0;
   int tmax_m = 0, tmax_k = 0, tmax_rm = 0;
   int band_bw = -1, band_m = 0, band_k = 0;   // widest band, largest m and k of the interiors (-1: none)
+  int banded_w = 0;                            // 1: the last factorization used the banded elimination
+  // fronts of the banded elimination grouped by ring width 8 / 16 / 24 / 32
+  // (band_ptr[c] .. band_ptr[c + 1] in band_list); band_ok: every front fits one
+  std::vector<int32_t> h_band_list;
+  int band_ptr[5] = {0, 0, 0, 0, 0};
+  bool band_ok = false;
+  DevBuf band_list;
 };
 
 struct Profiler {
@@ -253,6 +260,7 @@ struct sgf_handle_s {
   bool use_graph = true;
   bool capturing = false;   // a graph is being recorded: launch directly
   bool band_apply = true;
+  bool band_elim = true;
   int32_t persist_cap = 0;   // > 0: per-level work lists persistent on at most this many workgroups
   uint64_t epoch = 0;
   hipStream_t cap_stream = nullptr;
@@ -494,7 +502,7 @@ bool level_tiled(sgf_handle h, const sgf::Level& L) {
   if (apply_lds(L.max_front_rows, h->esz) > LDS_BYTES) return true;
   const int mode = level_mode(h, L);
   if (mode == 0) return true;
-  if (mode > 0) return !panel_fits(L.max_front_rows, mode, h->esz);
+  if (mode >= 8) return !panel_fits(L.max_front_rows, mode, h->esz);
   if (L.max_front_rows >= h->tiled_rows) return true;
   int max_m = 0;
   for (const auto& e : L.elim) max_m = std::max(max_m, e.m);
@@ -508,9 +516,19 @@ bool level_tiled(sgf_handle h, const sgf::Level& L) {
 
 // Panel width of the one-workgroup elimination of level L.
 int level_nb(sgf_handle h, const sgf::Level& L, int max_m) {
-  const int mode = level_mode(h, L);
-  if (mode > 0 && panel_fits(L.max_front_rows, mode, h->esz)) return mode;
+  const int mode = level_mode(h, L);   // 1 (banded) on a level that is not banded: automatic width
+  if (mode >= 8 && panel_fits(L.max_front_rows, mode, h->esz)) return mode;
   return nb_for(L.max_front_rows, max_m, h->esz);
+}
+
+// Whether a level runs the banded one-wavefront elimination (1) or not (0):
+// every interior with lower bandwidth below 32 and at most 64 separator
+// rows, the level not tiled, and the level's mode automatic (-1) or banded
+// (1).  The fronts are launched in groups of equal ring width.
+int banded_w(sgf_handle h, const sgf::Level& L, const LevelDev& D) {
+  if (!h->band_elim || L.top || L.elim.empty() || D.tiled || !D.band_ok) return 0;
+  const int mode = level_mode(h, L);
+  return mode == -1 || mode == 1 ? 1 : 0;
 }
 
 // Descriptors and buffers of a tiled level: Zt (m x m per front) and the
@@ -579,6 +597,28 @@ void upload_level(sgf_handle h, int li, hipStream_t st) {
     D.band_bw = std::max(D.band_bw, std::min(e.bw, std::max(e.m - 1, 0)));
     D.band_m = std::max(D.band_m, e.m);
     D.band_k = std::max(D.band_k, e.k);
+  }
+  {
+    // ring-width classes of the banded elimination
+    std::vector<int32_t> cls[4];
+    D.band_ok = !L.elim.empty();
+    for (size_t f = 0; f < L.elim.size(); ++f) {
+      const auto& e = L.elim[f];
+      const int b = std::min(e.bw, std::max(e.m - 1, 0));
+      const int c = b < 8 ? 0 : b < 16 ? 1 : b < 24 ? 2 : b < 32 ? 3 : -1;
+      if (c < 0 || e.k > sgf::BE_KMAX) {
+        D.band_ok = false;
+        break;
+      }
+      cls[c].push_back((int32_t)f);
+    }
+    D.h_band_list.clear();
+    D.band_ptr[0] = 0;
+    for (int c = 0; c < 4; ++c) {
+      if (D.band_ok) D.h_band_list.insert(D.h_band_list.end(), cls[c].begin(), cls[c].end());
+      D.band_ptr[c + 1] = (int)D.h_band_list.size();
+    }
+    if (D.band_ok) upload(D.band_list, D.h_band_list, st);
   }
   {
     // work lists of the persistent launches: costliest first when the costs
@@ -906,7 +946,30 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
     if (L.top) {
       factor_top<T>(h, L, D, st);
     } else if (D.tiled) {
+      D.banded_w = 0;
       tiled_factor<T>(h, st, D.h_tf, D.tf.as<sgf::TFront>(), arena, D.zt.as<T>(), L.t, "elim");
+    } else if ((D.banded_w = banded_w(h, L, D)) > 0) {
+      // one launch per ring-width class; the level's work is charged to the
+      // first launch
+      bool first = true;
+      for (int c = 0; c < 4; ++c) {
+        const unsigned cnt = (unsigned)(D.band_ptr[c + 1] - D.band_ptr[c]);
+        if (cnt == 0) continue;
+        const int w = 8 * (c + 1);
+        const size_t lds = (size_t)sgf::elim_banded_lds_elems(w) * sizeof(T);
+        const int32_t* lst = D.band_list.as<int32_t>() + D.band_ptr[c];
+        launch(h, st, "elim_banded", first ? lvl_elim_flops : 0, first ? lvl_elim_bytes : 0, [&] {
+          const sgf::ElimDesc* dd = D.elim.as<sgf::ElimDesc>();
+          int* fl = h->d_fail.as<int>();
+          switch (w) {
+            case 8: hipLaunchKernelGGL((sgf::k_elim_banded<T, 8>), dim3(cnt), dim3(sgf::WAVE), lds, st, dd, arena, fl, lst); break;
+            case 16: hipLaunchKernelGGL((sgf::k_elim_banded<T, 16>), dim3(cnt), dim3(sgf::WAVE), lds, st, dd, arena, fl, lst); break;
+            case 24: hipLaunchKernelGGL((sgf::k_elim_banded<T, 24>), dim3(cnt), dim3(sgf::WAVE), lds, st, dd, arena, fl, lst); break;
+            default: hipLaunchKernelGGL((sgf::k_elim_banded<T, 32>), dim3(cnt), dim3(sgf::WAVE), lds, st, dd, arena, fl, lst); break;
+          }
+        }, L.t);
+        first = false;
+      }
     } else if (!L.elim.empty()) {
       int max_m = 0;
       for (const auto& e : L.elim) max_m = std::max(max_m, e.m);
@@ -1509,7 +1572,7 @@ int64_t device_bytes(sgf_handle h) {
     for (const DevBuf* x : {&D.arena, &D.scratch, &D.cf, &D.nbuf, &D.ltphi, &D.tau, &D.phi, &D.rank, &D.elim,
                             &D.pairs, &D.schur, &D.comp, &D.compnbr, &D.sepacc, &D.sepsrc, &D.capply, &D.slots,
                             &D.nslots, &D.blkmap, &D.phimap, &D.slotptr, &D.phioff, &D.tb, &D.active, &D.tofcomp,
-                            &D.tf, &D.zt, &D.uw, &D.ctf, &D.elim_order, &D.comp_order, &D.cw})
+                            &D.tf, &D.zt, &D.uw, &D.ctf, &D.elim_order, &D.comp_order, &D.cw, &D.band_list})
       b += x->bytes;
   return b;
 }
@@ -1645,8 +1708,8 @@ sgf_status sgf_autotune(sgf_handle h, const double* vals, int32_t napply, int32_
     h->use_graph = false;   // per-level apply timings need direct launches
     // every candidate runs three times, interleaved, and keeps its fastest
     // time per level (a single trial is noisy, the first pays cold memory)
-    const int candidates[] = {0, 8, 16, 32};
-    const int nc = 4, reps = 3;
+    const int candidates[] = {0, 1, 8, 16, 32};
+    const int nc = 5, reps = 3;
     std::vector<std::vector<double>> cost(nc);   // [candidate][level]
     std::vector<std::vector<char>> honored(nc);  // the level really ran that candidate
     for (int trial = 0; trial < nc * reps; ++trial) {
@@ -1666,7 +1729,7 @@ sgf_status sgf_autotune(sgf_handle h, const double* vals, int32_t napply, int32_
       for (int li = 0; li < nl; ++li) {
         const auto& L = h->plan.levels[li];
         if (L.top || L.elim.empty()) continue;
-        ok[li] = (c == 0) == h->lev[li].tiled;
+        ok[li] = (c == 0) == h->lev[li].tiled && (c == 1) == (h->lev[li].banded_w > 0);
         char tag[48];
         for (const auto& k : h->prof.stats) {
           const std::string nm(k.name);
@@ -2036,6 +2099,11 @@ sgf_status sgf_set_persistent(sgf_handle h, int32_t max_workgroups) {
   if (!h || max_workgroups < 0) return fail(SGF_EINVAL, "bad persistent-launch argument");
   h->persist_cap = max_workgroups;
   return SGF_OK;
+}
+
+sgf_status sgf_set_band_elim(sgf_handle h, int32_t enable) {
+  if (!h) return fail(SGF_EINVAL, "NULL handle");
+  return guard([&] { h->band_elim = enable != 0; });
 }
 
 sgf_status sgf_set_band_apply(sgf_handle h, int32_t enable) {

@@ -23,6 +23,8 @@
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <ctime>
 #include <deque>
@@ -45,6 +47,7 @@ double now_s() {
 }
 
 struct Op {
+  int id = 0;                 // index in the server's operator list
   sgf_handle h = nullptr;     // created by the first worker that needs it
   int64_t n = 0, nnz = 0;
   std::vector<double> vals;   // host copy of the values, for (re)factorization
@@ -86,6 +89,7 @@ struct sgf_server_s {
   std::condition_variable cv_work, cv_done;
   std::vector<std::thread> workers;
   bool stop = false;
+  bool trace = std::getenv("SGF_SERVER_TRACE") != nullptr;   // bookkeeping lines on stderr
   std::vector<std::unique_ptr<Op>> ops;
   std::deque<std::shared_ptr<Req>> queue;
   std::map<int64_t, std::shared_ptr<Req>> all;
@@ -281,6 +285,10 @@ void sgf_server_s::run(int slot) {
 
     // ---- bookkeeping -------------------------------------------------------
     lk.lock();
+    if (trace)
+      std::fprintf(stderr, "[sgf-server] slot %d op %d cols %d factor %d need %lld held %lld -> %lld total %lld reserved %lld\n",
+                   slot, op->id, tot, (int)factor, (long long)need, (long long)op->held, (long long)inf.device_bytes,
+                   (long long)(held + inf.device_bytes - op->held), (long long)(reserved - need));
     reserved -= need;
     held += inf.device_bytes - op->held;
     op->held = inf.device_bytes;
@@ -354,6 +362,7 @@ sgf_status sgf_server_add_operator(sgf_server s, int64_t n, const int64_t* row_p
   op->opt = *opt;
   std::lock_guard<std::mutex> g(s->mu);
   *op_id = (int32_t)s->ops.size();
+  op->id = (int)s->ops.size();
   s->ops.push_back(std::move(op));
   return SGF_OK;
 }

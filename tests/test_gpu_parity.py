@@ -254,7 +254,7 @@ def test_autotuned_levels_match_oracle():
     vals = torch.from_numpy(p.data).cuda()
     modes = s.autotune(vals, napply=10)
     assert len(modes) == F.info["nlevels"]
-    assert set(modes.tolist()) <= {-1, 0, 8, 16, 32}
+    assert set(modes.tolist()) <= {-1, 0, 1, 8, 16, 32}
     assert modes[-1] == -1
     with pytest.raises(sgf.SgfError):
         s.apply(vals[:p.n].clone(), torch.empty(p.n, dtype=torch.float64, device="cuda"))
@@ -403,3 +403,60 @@ def test_pcg_iteration_graphs_for_several_rhs_counts():
         itd, reld = s.pcg(b.T, xd.T, rtol=1e-9)
         assert itg.tolist() == itd.tolist() and torch.equal(xg, xd), f"step {step}, {k} columns"
         assert float(relg.max()) < 1e-9
+
+
+@pytest.mark.parametrize("kind,grid,leaf,q", [("fourier", (100, 90), 16, 2), ("fourier", (61, 58), 8, 2),
+                                              ("fourier", (35, 130), 16, 1), ("blocky", (45, 45), 4, 1)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_banded_elimination_matches_panel_elimination_and_oracle(kind, grid, leaf, q, prec):
+    """Level-1 interiors eliminated one wavefront per front (band Cholesky
+    in an LDS ring, L_SI in registers, L_SI L_SI^T on the matrix cores):
+    2D leaf 16 (225-row interiors, 14 blocks of 16 columns, ragged last
+    block), leaf 8 (49 rows, ring of 8) and leaf 4; against the panel
+    kernel and the oracle; same ranks at every level."""
+    p = _prob(kind, grid)
+    F = _oracle(p, q, leaf)
+    pr = sgf.FP64 if prec == "fp64" else sgf.FP32
+    out, ranks = {}, {}
+    for banded in (True, False):
+        s = sgf.Solver.from_problem(p, q=q, leaf=leaf, precision=pr)
+        s.set_band_elim(banded)
+        s.profile(True)
+        s.factorize(torch.from_numpy(p.data).cuda())
+        torch.cuda.synchronize()
+        st = s.profile_read()
+        s.profile(False)
+        assert ("elim_banded" in st) == banded
+        V = np.stack([P.random_rhs(12, p.n, j) for j in range(2)], axis=1)
+        out[banded] = _apply(s, V)
+        ranks[banded] = [s.level(t)["rank"].tolist() for t in range(1, s.info()["levels"])]
+    assert ranks[True] == ranks[False]
+    za = O.apply_inverse(F, V)
+    d = _rel(out[True], out[False])
+    print(f"{kind} {grid} leaf {leaf} {prec}: banded vs panel {d:.1e}, vs oracle {_rel(out[True], za):.1e} "
+          f"(panel vs oracle {_rel(out[False], za):.1e})")
+    if prec == "fp64":
+        assert d <= 1e-12
+        assert _rel(out[True], za) <= 1e-10
+    else:
+        assert d <= 1e-4
+        assert _rel(out[True], za) <= 1e-3
+
+
+def test_banded_elimination_reports_non_spd_cluster():
+    """A non-positive pivot inside a banded front is reported with its cluster."""
+    p = _prob("const", (64, 64))
+    vals = p.data.copy()
+    A = p.csr()
+    s = sgf.Solver.from_problem(p, q=1, leaf=16)
+    node = 0   # a corner node: inside the first interior
+    row = slice(A.indptr[node], A.indptr[node + 1])
+    diag = np.where(A.indices[row] == node)[0][0] + A.indptr[node]
+    vals[diag] = -1.0
+    s.profile(True)
+    with pytest.raises(sgf.SgfError) as ei:
+        s.factorize(torch.from_numpy(vals).cuda())
+    st = s.profile_read()
+    assert "elim_banded@L1" in st, sorted(st)
+    assert ei.value.code == sgf.SGF_ENOTSPD
+    assert s.info()["failed_level"] == 1 and s.info()["failed_cluster"] >= 0

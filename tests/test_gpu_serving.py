@@ -5,6 +5,8 @@ residual; a request's result is the same alone and in a mix of concurrent,
 coalesced requests with evictions (bar: 1e-12 relative, columns of a batched
 PCG are computed independently); the FP32 factor / FP64 CG solution agrees
 with a direct solve; memory that can never fit is refused."""
+import os
+
 import numpy as np
 import pytest
 
@@ -56,7 +58,9 @@ def test_result_is_the_same_alone_and_in_the_mix():
         est.append(s.estimate_bytes(16))
         s.close()
     budget = int(max(est) + (4 << 20))
+    os.environ["SGF_SERVER_TRACE"] = "1"   # bookkeeping lines, shown by pytest if an assertion fails
     srv = sgf.Server(hbm_budget=budget, slots=4, max_batch_rhs=16)
+    del os.environ["SGF_SERVER_TRACE"]
     ids = [srv.add_operator(prob, precision=sgf.FP32, **kw) for prob, kw in ops]
     rng = np.random.default_rng(5)
     reqs = []
