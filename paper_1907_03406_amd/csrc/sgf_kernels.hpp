@@ -402,8 +402,9 @@ __global__ __launch_bounds__(WG) void k_elim(const ElimDesc* __restrict__ D, T* 
 // the front has at most 64 separator rows, e.g. the finest interiors of a 2D
 // grid numbered naturally): one wavefront per front of the list, three parts.
 //  1. Band Cholesky of M_II, right-looking one column per step, on a ring of
-//     three W-row blocks in LDS; band row i is stored by diagonals,
-//     ring[i][W-1-r] = A[i][i-r].  Columns of block b+1 are staged before
+//     band rows in LDS (a power of two, at least three W-row blocks); band
+//     row i is stored by diagonals, ring[i][W-1-r] = A[i][i-r].  Columns of
+//     block b+1 are staged before
 //     the steps of block b (they hold the rows those steps update), from
 //     registers loaded one block ahead.  Each finished column of L_II is
 //     written to the front at once (coalesced).
@@ -418,32 +419,67 @@ __global__ __launch_bounds__(WG) void k_elim(const ElimDesc* __restrict__ D, T* 
 // ---------------------------------------------------------------------------
 constexpr int BE_KMAX = 64;
 
-__host__ __device__ inline int64_t elim_banded_lds_elems(int w) { return 3 * w * w + 3 * w + (int64_t)BE_KMAX * (w + 1); }
+// Packed factor of a banded front for the apply sweeps, contiguous from
+// ElimDesc::pk_off: the band of L_I by diagonals with row stride
+// band_pk_ld(m), PB[r][i] = L[i][i-r] and PB[0][i] = 1 / L[i][i] (entries
+// with i < r are 0), then, from pk_off + band_pk_lsi(m, bw), L_SI column by
+// column, PL[s + j k] = L_SI[s][j].  Both parts start on 64-element bounds.
+__host__ __device__ constexpr int band_pk_ld(int m) { return (m + 1) & ~1; }
+__host__ __device__ inline int64_t band_pk_lsi(int m, int bw) {
+  return (((int64_t)(bw + 1) * band_pk_ld(m)) + 63) & ~(int64_t)63;
+}
+__host__ __device__ inline int64_t band_pk_elems(int m, int k, int bw) {
+  return band_pk_lsi(m, bw) + ((((int64_t)k * m) + 63) & ~(int64_t)63);
+}
+
+// Rows of the LDS ring of k_elim_banded<W>: a power of two holding 3W rows,
+// so the ring row of band row i is i & (rows - 1).
+__host__ __device__ constexpr int be_ring_rows(int w) { return w <= 8 ? 32 : w <= 16 ? 64 : 128; }
+__host__ __device__ inline int64_t elim_banded_lds_elems(int w) {
+  return (int64_t)be_ring_rows(w) * (w + 1) + (int64_t)BE_KMAX * (w + 1) + WAVE;
+}
+
+// Reciprocal and square root of the band pivots: the hardware
+// instructions in FP32 (1 ulp, below the rounding of the FP32 factor),
+// correctly rounded in FP64.
+__device__ __forceinline__ float be_sqrt(float a) { return __builtin_amdgcn_sqrtf(a); }
+__device__ __forceinline__ float be_rcp(float a) { return __builtin_amdgcn_rcpf(a); }
+__device__ __forceinline__ double be_sqrt(double a) { return sqrt(a); }
+__device__ __forceinline__ double be_rcp(double a) { return 1.0 / a; }
 
 template <typename T, int W>
 __global__ __launch_bounds__(WAVE) void k_elim_banded(const ElimDesc* __restrict__ D, T* __restrict__ arena,
-                                                      int* fail, const int32_t* __restrict__ list) {
+                                                      int* fail, const int32_t* __restrict__ list,
+                                                      T* __restrict__ pk) {
   static_assert(W % 4 == 0 && (W * W) % WAVE == 0, "ring width");
+  constexpr int RS = be_ring_rows(W), MASK = RS - 1;
+  static_assert(RS >= 3 * W, "ring rows");
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* ring = reinterpret_cast<T*>(smem_raw);   // 3W rows x W
-  T* dinv = ring + 3 * W * W;                 // reciprocal pivots, by ring row
-  T* tile = dinv + 3 * W;                     // 64 x (W + 1): the block of L_SI, row-major
+  T* ring = reinterpret_cast<T*>(smem_raw);   // RS rows x W
+  T* dinv = ring + RS * W;                    // reciprocal pivots, by ring row (0 beyond m)
+  T* tile = dinv + RS;                        // 64 x (W + 1): the block of L_SI, row-major
+  T* sink = tile + BE_KMAX * (W + 1);         // one slot per lane for the writes of idle lanes
   typedef typename Mfma<T>::V V;
   const ElimDesc d = D[list[blockIdx.x]];
-  const int m = d.m, k = d.k, R = m + k, bw = min(d.bw, W - 1);
+  const int m = d.m, k = d.k, R = m + k, bw = min(min(d.bw, W - 1), max(m - 1, 0));
   T* C = arena + d.front_off;
   const int lane = threadIdx.x;
-  auto rrow = [&](int i) { return ((i / W) % 3) * W + i % W; };   // ring row of band row i
-  // this lane's pairs (s, t), 1 <= t <= s <= bw, of the trailing update
+  // this lane's pairs (s, t), 1 <= t <= s <= bw, of the trailing update, and
+  // the ring columns of A[j+s][j], A[j+t][j] and A[j+s][j+t]; an idle pair
+  // (ps = 0) reads a valid entry and writes to the lane's sink slot
   constexpr int NP = (W * (W - 1) / 2 + WAVE - 1) / WAVE;
-  int ps[NP], pt[NP];
+  int ps[NP], pt[NP], cs[NP], ct[NP], ce[NP];
 #pragma unroll
   for (int q = 0; q < NP; ++q) {
     int p = lane + q * WAVE, ss = 1;
     while (ss <= bw && p >= ss) p -= ss++;
     ps[q] = ss <= bw ? ss : 0;
     pt[q] = ss <= bw ? p + 1 : 0;
+    cs[q] = W - 1 - ps[q];
+    ct[q] = W - 1 - pt[q];
+    ce[q] = W - 1 - (ps[q] - pt[q]);
   }
+  const int sink_off = (int)(sink - ring) + lane;
   // staging: entries A[c + r][c] of the columns c of a block, r = 0..bw
   constexpr int NS = W * W / WAVE;
   auto load_cols = [&](int b, T* v) {
@@ -457,11 +493,36 @@ __global__ __launch_bounds__(WAVE) void k_elim_banded(const ElimDesc* __restrict
 #pragma unroll
     for (int q = 0; q < NS; ++q) {
       const int idx = lane + q * WAVE, c = b * W + idx / W, r = idx % W, i = c + r;
-      if (r <= bw && c < m && i < m) ring[rrow(i) * W + (W - 1 - r)] = v[q];
+      if (r <= bw && c < m && i < m) ring[(i & MASK) * W + (W - 1 - r)] = v[q];
     }
   };
+  // packed copy for the apply (pk_off >= 0): band by diagonals, then L_SI
+  const bool packed = d.pk_off >= 0;
+  T* PB = pk + (packed ? d.pk_off : 0);
+  T* PL = PB + band_pk_lsi(m, bw);
+  const int pld = band_pk_ld(m);
+  // the finished columns of block b (band entries L[c + r][c]) into the front
+  // and into the packed band (reciprocal on the diagonal)
+  auto store_out = [&](int b) {
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+      const int idx = lane + q * WAVE, c = b * W + idx / W, r = idx % W, i = c + r;
+      if (r <= bw && c < m && i < m) {
+        const T v = ring[(i & MASK) * W + (W - 1 - r)];
+        C[i + (int64_t)c * R] = v;
+        if (packed) PB[r * pld + i] = r == 0 ? dinv[i & MASK] : v;
+      }
+    }
+    // band entries above the first row of the band (i < r) are zero
+    if (packed && b == 0)
+      for (int idx = lane; idx < (bw + 1) * bw; idx += WAVE) {
+        const int r = 1 + idx / bw, i = idx % bw;
+        if (i < r && i < m) PB[r * pld + i] = T(0);
+      }
+  };
   auto zero_block = [&](int b) {
-    for (int idx = lane; idx < W * W; idx += WAVE) ring[(((b % 3) * W) + idx / W) * W + idx % W] = T(0);
+    for (int idx = lane; idx < W * W; idx += WAVE) ring[((b * W + idx / W) & MASK) * W + idx % W] = T(0);
+    if (lane < W) dinv[(b * W + lane) & MASK] = T(0);
   };
   const int nblk = (m + W - 1) / W;
   T pre[NS];
@@ -488,6 +549,7 @@ __global__ __launch_bounds__(WAVE) void k_elim_banded(const ElimDesc* __restrict
   for (int q = 0; q < NT; ++q)
 #pragma unroll
     for (int v = 0; v < 4; ++v) acc[q][v] = T(0);
+  T minpiv = T(1);   // smallest pivot seen (a non-positive one is reported once, after the front)
   for (int b = 0; b < nblk; ++b) {
     const int j0 = b * W;
     // stage the columns of block b + 1 (rows of blocks b + 1, b + 2); fetch those of b + 2
@@ -506,55 +568,50 @@ __global__ __launch_bounds__(WAVE) void k_elim_banded(const ElimDesc* __restrict
       mnext[t] = (srow && jn < m) ? msi[(int64_t)jn * R] : T(0);
     }
     __builtin_amdgcn_wave_barrier();
-    // ---- 1. band Cholesky, columns j0 .. j0 + W - 1 ----
-    for (int t = 0; t < W && j0 + t < m; ++t) {
+    // ---- 1. band Cholesky, columns j0 .. j0 + W - 1 (branch-free: idle lanes
+    // read valid entries and write to their sink slot) ----
+    const int jend = min(W, m - j0);
+    const bool sc0 = lane >= 1 && lane <= bw;   // lane scales A[j + lane][j]
+    for (int t = 0; t < jend; ++t) {
       const int j = j0 + t;
-      T a = ring[rrow(j) * W + (W - 1)];
-      const int sl = lane;   // scaling lane: row j + lane, 1 <= lane <= bw
-      const bool sc = sl >= 1 && sl <= bw && j + sl < m;
-      const T colv = sc ? ring[rrow(j + sl) * W + (W - 1 - sl)] : T(0);
+      const int dg = (j & MASK) * W + (W - 1);
+      T a = ring[dg];
+      const int sa = ((j + lane) & MASK) * W + (W - 1 - min(lane, W - 1));
+      const T colv = ring[sa];
       T as[NP], at[NP], e[NP];
+      int ea[NP];
 #pragma unroll
       for (int q = 0; q < NP; ++q) {
-        const bool on = ps[q] > 0 && j + ps[q] < m;
-        as[q] = on ? ring[rrow(j + ps[q]) * W + (W - 1 - ps[q])] : T(0);
-        at[q] = on ? ring[rrow(j + pt[q]) * W + (W - 1 - pt[q])] : T(0);
-        e[q] = on ? ring[rrow(j + ps[q]) * W + (W - 1 - (ps[q] - pt[q]))] : T(0);
+        const int rs = ((j + ps[q]) & MASK) * W, rt = ((j + pt[q]) & MASK) * W;
+        as[q] = ring[rs + cs[q]];
+        at[q] = ring[rt + ct[q]];
+        e[q] = ring[rs + ce[q]];
+        ea[q] = (ps[q] > 0 && j + ps[q] < m) ? rs + ce[q] : sink_off;
       }
-      if (!(a > T(0))) {
-        if (lane == 0) atomicCAS(fail, -1, d.cluster);
-        a = T(1);
-      }
-      const T l = sqrt(a), inv = T(1) / l, inv2 = inv * inv;
+      minpiv = min(minpiv, a);
+      a = a > T(0) ? a : T(1);
+      const T l = be_sqrt(a), inv = be_rcp(l), inv2 = inv * inv;
       __builtin_amdgcn_wave_barrier();
 #pragma unroll
-      for (int q = 0; q < NP; ++q)
-        if (ps[q] > 0 && j + ps[q] < m) ring[rrow(j + ps[q]) * W + (W - 1 - (ps[q] - pt[q]))] = e[q] - as[q] * at[q] * inv2;
-      if (sc) {
-        const T lv = colv * inv;
-        ring[rrow(j + sl) * W + (W - 1 - sl)] = lv;
-        C[(j + sl) + (int64_t)j * R] = lv;
-      }
-      if (lane == 0) {
-        ring[rrow(j) * W + (W - 1)] = l;
-        dinv[rrow(j)] = inv;
-        C[j + (int64_t)j * R] = l;
-      }
+      for (int q = 0; q < NP; ++q) ring[ea[q]] = e[q] - as[q] * at[q] * inv2;
+      ring[(sc0 && j + lane < m) ? sa : sink_off] = colv * inv;
+      ring[lane == 0 ? dg : sink_off] = l;
+      dinv[j & MASK] = inv;
       __builtin_amdgcn_wave_barrier();
     }
-    // ---- 2. L_SI columns j0 .. j0 + W - 1 ----
+    store_out(b);
+    // ---- 2. L_SI columns j0 .. j0 + W - 1 (rows beyond m: zero coefficients) ----
 #pragma unroll
     for (int t = 0; t < W; ++t) {
       const int j = j0 + t;
-      if (j < m) {
-        const T* row = ring + rrow(j) * W;
-        T acc2 = mcur[t];
+      const T* row = ring + (j & MASK) * W;
+      T acc2 = mcur[t];
 #pragma unroll
-        for (int r = W - 1; r >= 1; --r) acc2 -= row[W - 1 - r] * x[(t - r + W) % W];
-        x[t] = acc2 * dinv[rrow(j)];
-        if (srow) lsi[(int64_t)j * R] = x[t];
-      } else {
-        x[t] = T(0);
+      for (int r = W - 1; r >= 1; --r) acc2 -= row[W - 1 - r] * x[(t - r + W) % W];
+      x[t] = acc2 * dinv[j & MASK];
+      if (srow && j < m) {
+        lsi[(int64_t)j * R] = x[t];
+        if (packed) PL[lane + (int64_t)j * k] = x[t];
       }
     }
     // ---- 3. S += L_SI(:, block) L_SI(:, block)^T ----
@@ -571,10 +628,10 @@ __global__ __launch_bounds__(WAVE) void k_elim_banded(const ElimDesc* __restrict
 #pragma unroll
       for (int I = 0; I < KT; ++I)
 #pragma unroll
-        for (int J = 0; J <= I; ++J, ++q)
-          if (I < kt) acc[q] = Mfma<T>::op(op[I], op[J], acc[q]);
+        for (int J = 0; J <= I; ++J, ++q) acc[q] = Mfma<T>::op(op[I], op[J], acc[q]);
     }
   }
+  if (!(minpiv > T(0)) && lane == 0) atomicCAS(fail, -1, d.cluster);
   // the separator block of the front receives -L_SI L_SI^T (lower triangle)
   int q = 0;
 #pragma unroll
@@ -1286,10 +1343,13 @@ __host__ __device__ inline int64_t band_bwd_lds(int m, int k, int bw, int rc, in
 }
 
 // Forward sweep: y_I <- L_I^{-1} y_I and t = L_SI y_I (into the apply scratch).
-template <typename T, int RC>
+// PK: the factor is read from its packed copy (contiguous, aligned) instead
+// of the front.
+template <typename T, int RC, bool PK>
 __global__ __launch_bounds__(WG) void k_band_fwd(const ElimDesc* __restrict__ D, const T* __restrict__ arena,
                                                  const int32_t* __restrict__ slots, T* __restrict__ y, int64_t ldy,
-                                                 T* __restrict__ tscr, int64_t ldt, int nrhs) {
+                                                 T* __restrict__ tscr, int64_t ldt, int nrhs,
+                                                 const T* __restrict__ pk) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const ElimDesc d = D[blockIdx.x];
   const int m = d.m, k = d.k, R = m + k, bw = min(d.bw, max(m - 1, 0));
@@ -1300,11 +1360,17 @@ __global__ __launch_bounds__(WG) void k_band_fwd(const ElimDesc* __restrict__ D,
   const int c0 = blockIdx.y * RC, nc = min(RC, nrhs - c0);
   const T* C = arena + d.front_off;
   const int32_t* sl = slots + d.slot_off;
+  const T* PB = PK ? pk + d.pk_off : nullptr;
+  const T* PL = PK ? PB + band_pk_lsi(m, bw) : nullptr;
   for (int idx = threadIdx.x; idx < m * nc; idx += WG) {
     const int i = idx % m, c = idx / m;
     v[c * ld + i] = y[(int64_t)(c0 + c) * ldy + sl[i]];
   }
-  stage_band(C, R, m, bw, Bd, ld);
+  if (PK) {
+    for (int idx = threadIdx.x; idx < (bw + 1) * ld; idx += WG) Bd[idx] = PB[idx];   // same layout
+  } else {
+    stage_band(C, R, m, bw, Bd, ld);
+  }
   __syncthreads();
   const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
   if (w < nc) {
@@ -1335,10 +1401,11 @@ __global__ __launch_bounds__(WG) void k_band_fwd(const ElimDesc* __restrict__ D,
 #pragma unroll
     for (int c = 0; c < RC; ++c) acc[c] = 0;
     if (r < k) {
-      const T* cr = C + m + r;
+      const T* cr = PK ? PL + r : C + m + r;
+      const int64_t cs = PK ? k : R;
 #pragma unroll 8
       for (int j = w; j < m; j += WG / WAVE) {
-        const T cij = cr[(int64_t)j * R];
+        const T cij = cr[(int64_t)j * cs];
 #pragma unroll
         for (int c = 0; c < RC; ++c) acc[c] += cij * v[c * ld + j];
       }
@@ -1366,11 +1433,11 @@ __global__ __launch_bounds__(WG) void k_band_fwd(const ElimDesc* __restrict__ D,
 // stages tiles of tj <= 64 columns of the panel's L_SI rows transposed in
 // LDS (the space the band takes afterwards), so each lane sums down one
 // column, the rows dealt to the wavefronts in turn.
-template <typename T, int RC>
+template <typename T, int RC, bool PK>
 __global__ __launch_bounds__(WG) void k_band_bwd(const ElimDesc* __restrict__ D, const T* __restrict__ arena,
                                                  const int32_t* __restrict__ slots,
                                                  const int32_t* __restrict__ nslots, T* __restrict__ y,
-                                                 int64_t ldy, int nrhs, int tj) {
+                                                 int64_t ldy, int nrhs, int tj, const T* __restrict__ pk) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const ElimDesc d = D[blockIdx.x];
   const int m = d.m, k = d.k, R = m + k, bw = min(d.bw, max(m - 1, 0));
@@ -1393,11 +1460,13 @@ __global__ __launch_bounds__(WG) void k_band_bwd(const ElimDesc* __restrict__ D,
     ys[c * k + r] = y[(int64_t)(c0 + c) * ldy + ns[r]];
   }
   const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  const T* PB = PK ? pk + d.pk_off : nullptr;
+  const T* PL = PK ? PB + band_pk_lsi(m, bw) : nullptr;
   for (int j0 = 0; j0 < m; j0 += tj) {
     const int cw = min(tj, m - j0);
     for (int idx = threadIdx.x; idx < k * cw; idx += WG) {
       const int r = idx % k, jl = idx / k;
-      Bd[jl * ldk + r] = C[m + r + (int64_t)(j0 + jl) * R];
+      Bd[jl * ldk + r] = PK ? PL[(int64_t)j0 * k + idx] : C[m + r + (int64_t)(j0 + jl) * R];
     }
     __syncthreads();
     T acc[RC];
@@ -1422,7 +1491,15 @@ __global__ __launch_bounds__(WG) void k_band_bwd(const ElimDesc* __restrict__ D,
     }
     __syncthreads();
   }
-  stage_band(C, R, m, bw, Bd, ld);
+  if (PK) {
+    const int pld = band_pk_ld(m);
+    for (int idx = threadIdx.x; idx < (bw + 1) * m; idx += WG) {
+      const int r = idx / m, i = idx - r * m;
+      Bd[r * ld + i] = PB[r * pld + i];
+    }
+  } else {
+    stage_band(C, R, m, bw, Bd, ld);
+  }
   __syncthreads();
   if (w < nc) {
     T* vc = v + w * ld;
@@ -1611,11 +1688,13 @@ __global__ __launch_bounds__(WG) void k_comp_scatter(const CompApply* __restrict
 }
 
 // Top node (factor in TF, sweep vectors in TV): mode 0: y <- L^{-T} L^{-1} y;
-// mode 1: y <- L L^T y.
+// mode 1: y <- L L^T y.  With `staged`, the lower triangle of the factor is
+// first copied to LDS (ld m + 1), so the sequential steps of the solves read
+// LDS instead of waiting on device memory.
 template <typename TV, typename T>
 __global__ __launch_bounds__(WG) void k_top(const ElimDesc* __restrict__ D, const T* __restrict__ fac,
                                             const int32_t* __restrict__ slots, TV* __restrict__ y, int64_t ldy,
-                                            int mode) {
+                                            int mode, int staged) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* ys = reinterpret_cast<T*>(smem_raw);
   const ElimDesc d = D[0];
@@ -1625,11 +1704,21 @@ __global__ __launch_bounds__(WG) void k_top(const ElimDesc* __restrict__ D, cons
   TV* yv = y + blockIdx.y * ldy;
   const int32_t* sl = slots + d.slot_off;
   for (int i = threadIdx.x; i < m; i += WG) ys[i] = (T)yv[sl[i]];
-  __syncthreads();
-  if (mode == 0) {
+  if (mode == 0 && staged) {
+    T* Ls = tmp + m;
+    for (int idx = threadIdx.x; idx < m * m; idx += WG) {
+      const int i = idx % m, j = idx / m;
+      if (i >= j) Ls[i + j * (m + 1)] = L[idx];
+    }
+    __syncthreads();
+    wg_trsv_lower(Ls, m + 1, m, ys);
+    wg_trsv_lower_t(Ls, m + 1, m, ys);
+  } else if (mode == 0) {
+    __syncthreads();
     wg_trsv_lower(L, m, m, ys);
     wg_trsv_lower_t(L, m, m, ys);
   } else {
+    __syncthreads();
     const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
     for (int j = w; j < m; j += WG / WAVE) {
       T acc = 0;

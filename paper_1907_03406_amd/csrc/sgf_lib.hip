@@ -120,6 +120,8 @@ struct LevelDev {
   int band_ptr[5] = {0, 0, 0, 0, 0};
   bool band_ok = false;
   DevBuf band_list;
+  DevBuf pk;                 // packed factor copies of the banded fronts (ElimDesc::pk_off)
+  int64_t pk_elems = 0;
 };
 
 struct Profiler {
@@ -293,9 +295,16 @@ struct sgf_handle_s {
       if (g.exec) (void)hipGraphExecDestroy(g.exec);
     ig.clear();
   }
+  // second stream (default priority) for independent launches of one level,
+  // forked from and joined to the caller's stream with events
+  hipStream_t side_stream = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   ~sgf_handle_s() {
     drop_graph();
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (side_stream) (void)hipStreamDestroy(side_stream);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
   }
 };
 
@@ -578,19 +587,6 @@ void upload_level(sgf_handle h, int li, hipStream_t st) {
   D.tau.ensure(L.tau_elems * e);
   D.phi.ensure(L.phi_elems * e);
   D.rank.ensure(std::max<size_t>(L.comp.size(), 1) * sizeof(int));
-  upload(D.elim, L.elim, st);
-  upload(D.pairs, L.pairs, st);
-  upload(D.schur, L.schur, st);
-  upload(D.comp, L.comp, st);
-  upload(D.compnbr, L.comp_nbr, st);
-  upload(D.sepacc, L.sepacc, st);
-  upload(D.sepsrc, L.sepacc_src, st);
-  upload(D.slots, L.slots, st);
-  upload(D.nslots, L.nslots, st);
-  upload(D.slotptr, L.slot_ptr, st);
-  upload(D.phioff, L.phi_off, st);
-  D.tiled = level_tiled(h, L);
-  if (D.tiled) build_tiled(h, L, D, st);
   D.band_bw = -1;
   D.band_m = D.band_k = 0;
   for (const auto& e : L.elim) {
@@ -619,7 +615,30 @@ void upload_level(sgf_handle h, int li, hipStream_t st) {
       D.band_ptr[c + 1] = (int)D.h_band_list.size();
     }
     if (D.band_ok) upload(D.band_list, D.h_band_list, st);
-  }
+    // packed copies for the apply sweeps, 64-element aligned
+    D.pk_elems = 0;
+    for (auto& e : L.elim) {
+      if (D.band_ok) {
+        e.pk_off = D.pk_elems;
+        D.pk_elems += sgf::band_pk_elems(e.m, e.k, std::min(e.bw, std::max(e.m - 1, 0)));
+      } else {
+        e.pk_off = -1;
+      }
+    }
+  }  upload(D.elim, L.elim, st);
+  upload(D.pairs, L.pairs, st);
+  upload(D.schur, L.schur, st);
+  upload(D.comp, L.comp, st);
+  upload(D.compnbr, L.comp_nbr, st);
+  upload(D.sepacc, L.sepacc, st);
+  upload(D.sepsrc, L.sepacc_src, st);
+  upload(D.slots, L.slots, st);
+  upload(D.nslots, L.nslots, st);
+  upload(D.slotptr, L.slot_ptr, st);
+  upload(D.phioff, L.phi_off, st);
+  D.tiled = level_tiled(h, L);
+  if (D.tiled) build_tiled(h, L, D, st);
+
   {
     // work lists of the persistent launches: costliest first when the costs
     // differ by more than 2x (longest-processing-time order), else cluster
@@ -949,27 +968,49 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
       D.banded_w = 0;
       tiled_factor<T>(h, st, D.h_tf, D.tf.as<sgf::TFront>(), arena, D.zt.as<T>(), L.t, "elim");
     } else if ((D.banded_w = banded_w(h, L, D)) > 0) {
-      // one launch per ring-width class; the level's work is charged to the
-      // first launch
-      bool first = true;
-      for (int c = 0; c < 4; ++c) {
+      // one launch per ring-width class: the class with the most fronts on
+      // the caller's stream, the others (typically a few boundary fronts with
+      // a wider band, whose latency would otherwise add up) on the side
+      // stream at the same time; timed as one launch
+      int main_c = 0;
+      for (int c = 1; c < 4; ++c)
+        if (D.band_ptr[c + 1] - D.band_ptr[c] > D.band_ptr[main_c + 1] - D.band_ptr[main_c]) main_c = c;
+      auto go = [&](int c, hipStream_t s) {
         const unsigned cnt = (unsigned)(D.band_ptr[c + 1] - D.band_ptr[c]);
-        if (cnt == 0) continue;
         const int w = 8 * (c + 1);
         const size_t lds = (size_t)sgf::elim_banded_lds_elems(w) * sizeof(T);
         const int32_t* lst = D.band_list.as<int32_t>() + D.band_ptr[c];
-        launch(h, st, "elim_banded", first ? lvl_elim_flops : 0, first ? lvl_elim_bytes : 0, [&] {
-          const sgf::ElimDesc* dd = D.elim.as<sgf::ElimDesc>();
-          int* fl = h->d_fail.as<int>();
-          switch (w) {
-            case 8: hipLaunchKernelGGL((sgf::k_elim_banded<T, 8>), dim3(cnt), dim3(sgf::WAVE), lds, st, dd, arena, fl, lst); break;
-            case 16: hipLaunchKernelGGL((sgf::k_elim_banded<T, 16>), dim3(cnt), dim3(sgf::WAVE), lds, st, dd, arena, fl, lst); break;
-            case 24: hipLaunchKernelGGL((sgf::k_elim_banded<T, 24>), dim3(cnt), dim3(sgf::WAVE), lds, st, dd, arena, fl, lst); break;
-            default: hipLaunchKernelGGL((sgf::k_elim_banded<T, 32>), dim3(cnt), dim3(sgf::WAVE), lds, st, dd, arena, fl, lst); break;
+        const sgf::ElimDesc* dd = D.elim.as<sgf::ElimDesc>();
+        int* fl = h->d_fail.as<int>();
+        T* pkp = D.pk.as<T>();
+        switch (w) {
+          case 8: hipLaunchKernelGGL((sgf::k_elim_banded<T, 8>), dim3(cnt), dim3(sgf::WAVE), lds, s, dd, arena, fl, lst, pkp); break;
+          case 16: hipLaunchKernelGGL((sgf::k_elim_banded<T, 16>), dim3(cnt), dim3(sgf::WAVE), lds, s, dd, arena, fl, lst, pkp); break;
+          case 24: hipLaunchKernelGGL((sgf::k_elim_banded<T, 24>), dim3(cnt), dim3(sgf::WAVE), lds, s, dd, arena, fl, lst, pkp); break;
+          default: hipLaunchKernelGGL((sgf::k_elim_banded<T, 32>), dim3(cnt), dim3(sgf::WAVE), lds, s, dd, arena, fl, lst, pkp); break;
+        }
+      };
+      D.pk.ensure((size_t)std::max<int64_t>(D.pk_elems, 1) * sizeof(T));
+      launch(h, st, "elim_banded", lvl_elim_flops, lvl_elim_bytes, [&] {
+        bool forked = false;
+        for (int c = 0; c < 4; ++c) {
+          if (c == main_c || D.band_ptr[c + 1] == D.band_ptr[c]) continue;
+          if (!forked) {
+            if (!h->side_stream) HIP_CHECK(hipStreamCreateWithFlags(&h->side_stream, hipStreamNonBlocking));
+            if (!h->ev_fork) HIP_CHECK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+            if (!h->ev_join) HIP_CHECK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
+            HIP_CHECK(hipEventRecord(h->ev_fork, st));
+            HIP_CHECK(hipStreamWaitEvent(h->side_stream, h->ev_fork, 0));
+            forked = true;
           }
-        }, L.t);
-        first = false;
-      }
+          go(c, h->side_stream);
+        }
+        go(main_c, st);
+        if (forked) {
+          HIP_CHECK(hipEventRecord(h->ev_join, h->side_stream));
+          HIP_CHECK(hipStreamWaitEvent(st, h->ev_join, 0));
+        }
+      }, L.t);
     } else if (!L.elim.empty()) {
       int max_m = 0;
       for (const auto& e : L.elim) max_m = std::max(max_m, e.m);
@@ -1139,6 +1180,7 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
       }, L.t);
     }
     account_level(h, L, D.work);
+    h->trace.mark("compressed-separator work queued", L.t);
     // ---- coarsen (Secs. 4.3-4.4) ----------------------------------------------
     if (!same_ranks) {
       P.levels.resize(li + 1);
@@ -1148,11 +1190,12 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
       for (int q = 0; q <= li; ++q)
         for (int sz : P.levels[q].size) P.max_node = std::max<int64_t>(P.max_node, sz);
       sgf::plan_next_level(P, D.h_blkmap, D.h_phimap);
+      h->trace.mark("next level planned (host)", li + 1);
       upload(D.blkmap, D.h_blkmap, st);
       upload(D.phimap, D.h_phimap, st);
     }
     upload_level(h, li + 1, st);
-    h->trace.mark(same_ranks ? "next level reused" : "next level planned", li + 1);
+    h->trace.mark(same_ranks ? "next level reused" : "next level uploaded", li + 1);
     sgf::Level& N = P.levels[li + 1];
     LevelDev& E = h->lev[li + 1];
     LevelDev& Dc = h->lev[li];   // re-fetch: lev may have grown
@@ -1213,6 +1256,21 @@ int rc_for(size_t fixed, size_t per_rhs, int nrhs) {
   int rc = std::min(sgf::RCM, nrhs);
   while (rc > 1 && fixed + rc * per_rhs > LDS_BYTES) --rc;
   return rc;
+}
+
+template <typename T, bool PK, typename... A>
+void band_fwd_launch(int rc, dim3 g, size_t lds, hipStream_t st, A... a) {
+  if (rc == 1) hipLaunchKernelGGL((sgf::k_band_fwd<T, 1, PK>), g, dim3(sgf::WG), lds, st, a...);
+  else if (rc == 2) hipLaunchKernelGGL((sgf::k_band_fwd<T, 2, PK>), g, dim3(sgf::WG), lds, st, a...);
+  else if (rc == 3) hipLaunchKernelGGL((sgf::k_band_fwd<T, 3, PK>), g, dim3(sgf::WG), lds, st, a...);
+  else hipLaunchKernelGGL((sgf::k_band_fwd<T, 4, PK>), g, dim3(sgf::WG), lds, st, a...);
+}
+template <typename T, bool PK, typename... A>
+void band_bwd_launch(int rc, dim3 g, size_t lds, hipStream_t st, A... a) {
+  if (rc == 1) hipLaunchKernelGGL((sgf::k_band_bwd<T, 1, PK>), g, dim3(sgf::WG), lds, st, a...);
+  else if (rc == 2) hipLaunchKernelGGL((sgf::k_band_bwd<T, 2, PK>), g, dim3(sgf::WG), lds, st, a...);
+  else if (rc == 3) hipLaunchKernelGGL((sgf::k_band_bwd<T, 3, PK>), g, dim3(sgf::WG), lds, st, a...);
+  else hipLaunchKernelGGL((sgf::k_band_bwd<T, 4, PK>), g, dim3(sgf::WG), lds, st, a...);
 }
 
 // Whether the interior sweeps of a level run the banded kernels: enabled,
@@ -1285,10 +1343,10 @@ void run_sweeps(sgf_handle h, int nrhs, bool product, hipStream_t st) {
         const dim3 g((unsigned)L.elim.size(), cdiv(nrhs, rc));
         const sgf::ElimDesc* dd = D.elim.as<sgf::ElimDesc>();
         const int32_t* sl = D.slots.as<int32_t>();
-        if (rc == 1) hipLaunchKernelGGL((sgf::k_band_fwd<T, 1>), g, dim3(sgf::WG), lds, st, dd, D.arena.as<T>(), sl, y, n, ts, ldt, nrhs);
-        else if (rc == 2) hipLaunchKernelGGL((sgf::k_band_fwd<T, 2>), g, dim3(sgf::WG), lds, st, dd, D.arena.as<T>(), sl, y, n, ts, ldt, nrhs);
-        else if (rc == 3) hipLaunchKernelGGL((sgf::k_band_fwd<T, 3>), g, dim3(sgf::WG), lds, st, dd, D.arena.as<T>(), sl, y, n, ts, ldt, nrhs);
-        else hipLaunchKernelGGL((sgf::k_band_fwd<T, 4>), g, dim3(sgf::WG), lds, st, dd, D.arena.as<T>(), sl, y, n, ts, ldt, nrhs);
+        if (D.banded_w > 0)
+          band_fwd_launch<T, true>(rc, g, lds, st, dd, D.arena.as<T>(), sl, y, n, ts, ldt, nrhs, D.pk.as<T>());
+        else
+          band_fwd_launch<T, false>(rc, g, lds, st, dd, D.arena.as<T>(), sl, y, n, ts, ldt, nrhs, (const T*)nullptr);
       }, L.t);
       return;
     }
@@ -1343,10 +1401,10 @@ void run_sweeps(sgf_handle h, int nrhs, bool product, hipStream_t st) {
         const sgf::ElimDesc* dd = D.elim.as<sgf::ElimDesc>();
         const int32_t* sl = D.slots.as<int32_t>();
         const int32_t* ns = D.nslots.as<int32_t>();
-        if (rc == 1) hipLaunchKernelGGL((sgf::k_band_bwd<T, 1>), g, dim3(sgf::WG), lds, st, dd, D.arena.as<T>(), sl, ns, y, n, nrhs, tj);
-        else if (rc == 2) hipLaunchKernelGGL((sgf::k_band_bwd<T, 2>), g, dim3(sgf::WG), lds, st, dd, D.arena.as<T>(), sl, ns, y, n, nrhs, tj);
-        else if (rc == 3) hipLaunchKernelGGL((sgf::k_band_bwd<T, 3>), g, dim3(sgf::WG), lds, st, dd, D.arena.as<T>(), sl, ns, y, n, nrhs, tj);
-        else hipLaunchKernelGGL((sgf::k_band_bwd<T, 4>), g, dim3(sgf::WG), lds, st, dd, D.arena.as<T>(), sl, ns, y, n, nrhs, tj);
+        if (D.banded_w > 0)
+          band_bwd_launch<T, true>(rc, g, lds, st, dd, D.arena.as<T>(), sl, ns, y, n, nrhs, tj, D.pk.as<T>());
+        else
+          band_bwd_launch<T, false>(rc, g, lds, st, dd, D.arena.as<T>(), sl, ns, y, n, nrhs, tj, (const T*)nullptr);
       }, L.t);
       return;
     }
@@ -1452,10 +1510,12 @@ void run_sweeps(sgf_handle h, int nrhs, bool product, hipStream_t st) {
     } else if (m > 0) {
       if ((size_t)2 * m * sizeof(double) > LDS_BYTES)
         throw SgfError(SGF_EINVAL, "top node too large for the one-workgroup top kernel");
+      const size_t staged_lds = ((size_t)2 * m + (size_t)m * (m + 1)) * sizeof(double);
+      const int staged = !product && staged_lds <= LDS_BYTES;
       launch(h, st, "apply_top", 0, tb, [&] {
-        hipLaunchKernelGGL((sgf::k_top<T, double>), dim3(1, nrhs), dim3(sgf::WG), 2 * m * sizeof(double), st,
-                           h->d_topdesc.as<sgf::ElimDesc>(), h->top64.as<double>(), D.slots.as<int32_t>(), y, n,
-                           product ? 1 : 0);
+        hipLaunchKernelGGL((sgf::k_top<T, double>), dim3(1, nrhs), dim3(sgf::WG),
+                           staged ? staged_lds : 2 * m * sizeof(double), st, h->d_topdesc.as<sgf::ElimDesc>(),
+                           h->top64.as<double>(), D.slots.as<int32_t>(), y, n, product ? 1 : 0, staged);
       }, L.t);
     }
   }
@@ -1572,7 +1632,7 @@ int64_t device_bytes(sgf_handle h) {
     for (const DevBuf* x : {&D.arena, &D.scratch, &D.cf, &D.nbuf, &D.ltphi, &D.tau, &D.phi, &D.rank, &D.elim,
                             &D.pairs, &D.schur, &D.comp, &D.compnbr, &D.sepacc, &D.sepsrc, &D.capply, &D.slots,
                             &D.nslots, &D.blkmap, &D.phimap, &D.slotptr, &D.phioff, &D.tb, &D.active, &D.tofcomp,
-                            &D.tf, &D.zt, &D.uw, &D.ctf, &D.elim_order, &D.comp_order, &D.cw, &D.band_list})
+                            &D.tf, &D.zt, &D.uw, &D.ctf, &D.elim_order, &D.comp_order, &D.cw, &D.band_list, &D.pk})
       b += x->bytes;
   return b;
 }
@@ -2015,6 +2075,17 @@ sgf_status sgf_estimate_bytes(sgf_handle h, int32_t nrhs, int64_t* bytes) {
       }
       if (level_tiled(h, L))
         for (const auto& d : L.elim) tot += e * ((double)d.m * d.m + (double)d.m * nrhs);
+      {
+        // packed copies of a level eliminated by the banded kernel
+        bool banded = !L.elim.empty();
+        double pk = 0;
+        for (const auto& d : L.elim) {
+          const int b = std::min(d.bw, std::max(d.m - 1, 0));
+          if (b >= 32 || d.k > sgf::BE_KMAX) banded = false;
+          pk += (double)sgf::band_pk_elems(d.m, d.k, b);
+        }
+        if (banded) tot += e * pk;
+      }
       L.rank.assign(L.comp.size(), 0);
       for (size_t c = 0; c < L.comp.size(); ++c) {
         L.rank[c] = std::min(L.comp[c].s, L.comp[c].c);

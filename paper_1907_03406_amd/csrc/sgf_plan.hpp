@@ -132,6 +132,7 @@ struct ElimDesc {
   int32_t m, k, cluster;
   int32_t bw;           // lower bandwidth of M_II in slot order (m: dense); the
                         // Cholesky factor keeps it, so L_I is zero below it
+  int64_t pk_off;       // packed copy of the factor for the apply sweeps (-1: none)
 };
 
 // One Schur contribution: dst pair block (ld = s_a) += front lower part.
@@ -316,6 +317,7 @@ inline void build_level(Level& L, const Options& o, int pi) {
     d.cluster = I;
     d.m = L.size[I];
     d.bw = d.m;
+    d.pk_off = -1;
     int k = 0;
     for (int64_t e = L.adj_ptr[I]; e < L.adj_ptr[I + 1]; ++e) {
       const int X = L.adj_idx[e];

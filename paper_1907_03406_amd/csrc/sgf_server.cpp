@@ -98,12 +98,15 @@ struct sgf_server_s {
   int64_t evictions = 0, factorizations = 0, batches = 0;
 
   // Bytes held plus reserved, after evicting idle factors (LRU) until `need`
-  // more fits; false if it cannot fit now.
-  bool admit(int64_t need) {
+  // more fits; false if it cannot fit now.  The operator being admitted
+  // (`self`) is never the victim: its need was computed with its factor
+  // resident.
+  bool admit(int64_t need, const Op* self) {
     while (held + reserved + need > opt.hbm_budget) {
       Op* victim = nullptr;
       for (auto& o : ops)
-        if (!o->busy && o->factored && (!victim || o->last_use < victim->last_use)) victim = o.get();
+        if (o.get() != self && !o->busy && o->factored && (!victim || o->last_use < victim->last_use))
+          victim = o.get();
       if (!victim) return false;
       sgf_release(victim->h);
       held -= victim->held;
@@ -202,7 +205,7 @@ void sgf_server_s::run(int slot) {
           cv_done.notify_all();
           goto rescan;
         }
-        if (!admit(grow)) continue;
+        if (!admit(grow, o)) continue;
         for (const auto& q : cand) queue.erase(std::find(queue.begin(), queue.end(), q));
         batch = std::move(cand);
         op = o;
