@@ -281,6 +281,16 @@ sgf_status sgf_set_persistent(sgf_handle h, int32_t max_workgroups);
 sgf_status sgf_set_band_elim(sgf_handle h, int32_t enable);
 
 /*
+ * Compression (Eqs. 3.1-3.4) of levels whose separators all have at most 64
+ * rows and at most 128 columns of N: enable = 1 (default) runs one wavefront
+ * per separator with its front, Phi blocks and N staged in LDS; 0 uses the
+ * one-workgroup kernel (also used under sgf_set_persistent).  Same ranks and,
+ * up to rounding order, the same factor.  Takes effect at the next
+ * factorization.
+ */
+sgf_status sgf_set_small_compress(sgf_handle h, int32_t enable);
+
+/*
  * Interior sweeps of the apply (Sec. 4.7) on levels whose M_II blocks have a
  * lower bandwidth of at most 64: enable = 1 (default) stages the band of L_I
  * in LDS and solves it one wavefront per right-hand side; 0 uses the blocked

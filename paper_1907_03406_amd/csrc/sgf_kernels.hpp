@@ -859,6 +859,231 @@ __global__ __launch_bounds__(WG) void k_compress(const CompDesc* __restrict__ D,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Compression of a small separator (s <= 64 rows, c <= 128 columns of N) by
+// one wavefront, the same steps and conventions as k_compress (Eqs. 3.1-3.4,
+// 4.5; pivot = largest recomputed column norm, near-ties to the lowest index,
+// stop at rank_tol relative to the first pivot norm): the front, the Phi
+// blocks and N are staged in LDS once, so the sequential parts wait on LDS
+// instead of device memory and need no workgroup barriers.  Lane i owns row
+// i of M_BB in registers for its Cholesky and row i of the neighbour part for
+// L_B^{-1}; in the pivoted QR lane j owns columns j and j + 64 (their norms),
+// the pivot is found with a wave maximum and a ballot.
+// ---------------------------------------------------------------------------
+constexpr int CS_SMAX = 64, CS_CMAX = 128;
+
+__host__ __device__ inline int64_t comp_small_lds_elems(int s, int K, int c, int pi) {
+  const int R = s + K;
+  return (int64_t)(R | 1) * s + (int64_t)(s | 1) * c + (int64_t)R * pi + (int64_t)s * pi + s + c;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    const T u = __shfl_xor(v, o, WAVE);
+    v = u > v ? u : v;
+  }
+  return v;
+}
+
+template <typename T, int NB>
+__global__ __launch_bounds__(WAVE) void k_compress_small(const CompDesc* __restrict__ D,
+                                                         const CompNbr* __restrict__ NBR, T* __restrict__ cf,
+                                                         T* __restrict__ nbuf, const T* __restrict__ phi,
+                                                         T* __restrict__ ltphi, T* __restrict__ tau_all,
+                                                         int* __restrict__ rank, int pi, double rank_tol, int* fail,
+                                                         int prefactored, int bf16n) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int ci = blockIdx.x;
+  const CompDesc d = D[ci];
+  const int s = d.s, K = d.K, c = d.c, R = s + K;
+  const int ldf = R | 1, ldn = s | 1;
+  T* Fl = reinterpret_cast<T*>(smem_raw);   // R x s, ld ldf
+  T* Nl = Fl + (int64_t)ldf * s;            // s x c, ld ldn
+  T* Ph = Nl + (int64_t)ldn * c;            // R x pi, ld R: Phi_B in rows [0, s), Phi_X at the neighbour's front rows
+  T* Lt = Ph + (int64_t)R * pi;             // s x pi, ld s
+  T* invd = Lt + (int64_t)s * pi;           // s reciprocal pivots
+  T* taul = invd + s;                       // c reflector coefficients
+  const int lane = threadIdx.x;
+  T* F = cf + d.cf_off;
+  // ---- stage the front and the Phi blocks ----
+  for (int idx = lane; idx < R * s; idx += WAVE) {
+    const int i = idx % R, j = idx / R;
+    Fl[i + j * ldf] = F[idx];
+  }
+  const T* PhB = phi + d.phi_off;
+  for (int idx = lane; idx < s * pi; idx += WAVE) Ph[idx % s + (idx / s) * R] = PhB[idx];
+  for (int q = 0; q < d.nnb; ++q) {
+    const CompNbr x = NBR[d.nb_ptr + q];
+    const T* PhX = phi + x.phi_off;
+    for (int idx = lane; idx < x.s_x * pi; idx += WAVE) Ph[x.row + idx % x.s_x + (idx / x.s_x) * R] = PhX[idx];
+  }
+  __builtin_amdgcn_wave_barrier();
+  if (!prefactored) {
+    // ---- L_B = chol(M_BB): lane i keeps row i in registers ----
+    T a[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) a[k] = (lane < s && k < s && k <= lane) ? Fl[lane + k * ldf] : T(0);
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      if (j < s) {
+        T dd = lane_bcast(a[j], j);
+        if (!(dd > T(0))) {
+          if (lane == 0) atomicCAS(fail, -1, d.cluster);
+          dd = T(1);
+        }
+        const T sd = sqrt(dd), inv = T(1) / sd;
+        const T l = (lane == j) ? sd : a[j] * inv;
+        if (lane >= j) a[j] = l;
+        if (lane == j) invd[j] = inv;
+#pragma unroll
+        for (int k = j + 1; k < NB; ++k) {
+          const T lk = lane_bcast(l, k);
+          if (lane >= k) a[k] -= l * lk;
+        }
+      }
+    }
+    if (lane < s)
+#pragma unroll
+      for (int k = 0; k < NB; ++k)
+        if (k < s && k <= lane) Fl[lane + k * ldf] = a[k];
+    __builtin_amdgcn_wave_barrier();
+    // ---- neighbour rows: row <- row L_B^{-T}, one row per lane ----
+    for (int i = s + lane; i < R; i += WAVE)
+      for (int j = 0; j < s; ++j) {
+        T acc = Fl[i + j * ldf];
+        for (int p = 0; p < j; ++p) acc -= Fl[i + p * ldf] * Fl[j + p * ldf];
+        Fl[i + j * ldf] = acc * invd[j];
+      }
+    __builtin_amdgcn_wave_barrier();
+    for (int idx = lane; idx < R * s; idx += WAVE) {
+      const int i = idx % R, j = idx / R;
+      if (i >= j) F[idx] = Fl[i + j * ldf];
+    }
+  }
+  // ---- N (Eq. 4.5) and L^T Phi_B ----
+  for (int idx = lane; idx < s * pi; idx += WAVE) {
+    const int i = idx % s, p = idx / s;
+    T acc = 0, acc16 = 0;
+    for (int j = i; j < s; ++j) {
+      const T f = Fl[j + i * ldf], ph = Ph[j + p * R];
+      acc += f * ph;
+      if (bf16n) acc16 += bf16_round(f) * bf16_round(ph);
+    }
+    Nl[i + p * ldn] = bf16n ? acc16 : acc;
+    Lt[i + p * s] = acc;
+  }
+  for (int q = 0; q < d.nnb; ++q) {
+    const CompNbr x = NBR[d.nb_ptr + q];
+    for (int idx = lane; idx < s * pi; idx += WAVE) {
+      const int i = idx % s, p = idx / s;
+      T acc = 0;
+      if (bf16n)
+        for (int j = 0; j < x.s_x; ++j)
+          acc += bf16_round(Fl[(x.row + j) + i * ldf]) * bf16_round(Ph[(x.row + j) + p * R]);
+      else
+        for (int j = 0; j < x.s_x; ++j) acc += Fl[(x.row + j) + i * ldf] * Ph[(x.row + j) + p * R];
+      Nl[i + (pi * (1 + q) + p) * ldn] = acc;
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  // ---- pivoted Householder QR of N (Eq. 3.3) ----
+  T nr[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int j = lane + h * WAVE;
+    T acc = 0;
+    if (j < c)
+      for (int i = 0; i < s; ++i) acc += Nl[i + j * ldn] * Nl[i + j * ldn];
+    nr[h] = sqrt(acc);
+  }
+  int r = 0;
+  T ref = 0;
+  const int kmax = min(s, c);
+  for (int k = 0; k < kmax; ++k) {
+    const T m0 = (lane >= k && lane < c) ? nr[0] : T(0);
+    const T m1 = (lane + WAVE >= k && lane + WAVE < c) ? nr[1] : T(0);
+    const T nmax = wave_max(m0 > m1 ? m0 : m1);
+    if (k == 0) ref = nmax;
+    if (nmax == T(0) || nmax <= (T)rank_tol * ref) break;
+    const T thr = nmax * (T)(1.0 - TIE_RTOL);
+    const unsigned long long b0 = __ballot(lane >= k && lane < c && nr[0] >= thr);
+    const unsigned long long b1 = __ballot(lane + WAVE >= k && lane + WAVE < c && nr[1] >= thr);
+    const int piv = b0 ? __ffsll((long long)b0) - 1 : WAVE + __ffsll((long long)b1) - 1;
+    const T nk = k < WAVE ? lane_bcast(nr[0], k) : lane_bcast(nr[1], k - WAVE);
+    if (piv < WAVE) {
+      if (lane == piv) nr[0] = nk;
+    } else if (lane == piv - WAVE) {
+      nr[1] = nk;
+    }
+    if (piv != k)
+      for (int i = lane; i < s; i += WAVE) {
+        const T t0 = Nl[i + k * ldn];
+        Nl[i + k * ldn] = Nl[i + piv * ldn];
+        Nl[i + piv * ldn] = t0;
+      }
+    __builtin_amdgcn_wave_barrier();
+    const T xi = lane < s ? Nl[lane + k * ldn] : T(0);
+    const T tail = wave_sum((lane > k && lane < s) ? xi * xi : T(0));
+    const T alpha = lane_bcast(xi, k);
+    T beta = alpha, tk = 0, scale = 0;
+    if (tail != T(0)) {
+      const T nv = sqrt(alpha * alpha + tail);
+      beta = alpha >= T(0) ? -nv : nv;
+      tk = (beta - alpha) / beta;
+      scale = T(1) / (alpha - beta);
+    }
+    if (tk != T(0) && lane > k && lane < s) Nl[lane + k * ldn] = xi * scale;
+    if (lane == 0) taul[k] = tk;
+    __builtin_amdgcn_wave_barrier();
+    const T* v = Nl + k * ldn;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int j = lane + h * WAVE;
+      if (j > k && j < c) {
+        T* y = Nl + j * ldn;
+        if (tk != T(0)) {
+          T acc = y[k];
+          for (int i = k + 1; i < s; ++i) acc += v[i] * y[i];
+          acc *= tk;
+          y[k] -= acc;
+          for (int i = k + 1; i < s; ++i) y[i] -= acc * v[i];
+        }
+        T nn = 0;
+        for (int i = k + 1; i < s; ++i) nn += y[i] * y[i];
+        nr[h] = sqrt(nn);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (lane == 0) Nl[k + k * ldn] = beta;
+    ++r;
+  }
+  __builtin_amdgcn_wave_barrier();
+  // ---- reflectors, tau, (Q^T L^T Phi_B) and the rank out ----
+  T* Ng = nbuf + d.n_off;
+  for (int idx = lane; idx < s * r; idx += WAVE) Ng[idx] = Nl[idx % s + (idx / s) * ldn];
+  T* tau = tau_all + d.tau_off;
+  for (int k = lane; k < r; k += WAVE) tau[k] = taul[k];
+  if (r < s)
+    for (int k = 0; k < r; ++k) {
+      const T tk = taul[k];
+      if (tk == T(0)) continue;
+      for (int p = lane; p < pi; p += WAVE) {
+        T* x = Lt + p * s;
+        T acc = x[k];
+        for (int i = k + 1; i < s; ++i) acc += Nl[i + k * ldn] * x[i];
+        acc *= tk;
+        x[k] -= acc;
+        for (int i = k + 1; i < s; ++i) x[i] -= acc * Nl[i + k * ldn];
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+  __builtin_amdgcn_wave_barrier();
+  T* LtP = ltphi + d.ltphi_off;
+  for (int idx = lane; idx < s * pi; idx += WAVE) LtP[idx] = Lt[idx];
+  if (lane == 0) rank[ci] = r;
+}
+
 // Phi_B <- (Q^T L^T Phi_B)[:r] for the separators that were compressed.
 template <typename T>
 __global__ __launch_bounds__(WG) void k_phi_commit(const CompDesc* __restrict__ D, const int* __restrict__ rank,

@@ -13,6 +13,7 @@
 #include <memory>
 #include <stdexcept>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "sgf.h"
@@ -263,6 +264,7 @@ struct sgf_handle_s {
   bool capturing = false;   // a graph is being recorded: launch directly
   bool band_apply = true;
   bool band_elim = true;
+  bool small_comp = true;
   int32_t persist_cap = 0;   // > 0: per-level work lists persistent on at most this many workgroups
   uint64_t epoch = 0;
   hipStream_t cap_stream = nullptr;
@@ -1058,20 +1060,48 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
       const int64_t extra = nlds ? n_lds : L.max_c;
       int nb = 4;
       size_t lds = (size_t)extra * sizeof(T);
+      // small separators: one wavefront each, everything in LDS
+      int snb = 0;
+      size_t slds = 0;
+      if (h->small_comp && h->persist_cap == 0) {
+        int ms = 0, mc = 0;
+        int64_t el = 0;
+        for (const auto& d : L.comp) {
+          ms = std::max(ms, d.s);
+          mc = std::max(mc, d.c);
+          el = std::max(el, sgf::comp_small_lds_elems(d.s, d.K, d.c, P.pi));
+        }
+        slds = (size_t)el * sizeof(T);
+        if (ms <= sgf::CS_SMAX && mc <= sgf::CS_CMAX && slds <= LDS_BYTES) snb = ms <= 16 ? 16 : ms <= 32 ? 32 : 64;
+      }
       if (D.comp_tiled) {
         // L_B and L_B^{-1} M_BX of every front by the tiled kernels first
         tiled_factor<T>(h, st, D.h_ctf, D.ctf.as<sgf::TFront>(), D.cf.as<T>(), nullptr, L.t, "comp", false);
-      } else {
+      } else if (!snb) {
         nb = nb_for(L.max_cf_rows, L.max_s, sizeof(T), extra);
         lds = std::max<size_t>(sgf::potrf_lds_elems(L.max_cf_rows, nb), (size_t)extra) * sizeof(T);
       }
       if (lds > LDS_BYTES) throw SgfError(SGF_EINVAL, "compression kernel needs more LDS than available");
       double tol = P.opt.rank_tol;
       const int pre = D.comp_tiled ? 1 : 0;
+      if (snb) {
+        const int bf = P.opt.precision == SGF_FP32_BF16N ? 1 : 0;
+        launch(h, st, "compress", 0, 0, [&] {
+          const dim3 g((unsigned)L.comp.size());
+          auto a = std::make_tuple(D.comp.as<sgf::CompDesc>(), D.compnbr.as<sgf::CompNbr>(), D.cf.as<T>(),
+                                   D.nbuf.as<T>(), (const T*)D.phi.as<T>(), D.ltphi.as<T>(), D.tau.as<T>(),
+                                   D.rank.as<int>(), P.pi, tol, h->d_fail.as<int>(), pre, bf);
+          std::apply([&](auto... x) {
+            if (snb == 16) hipLaunchKernelGGL((sgf::k_compress_small<T, 16>), g, dim3(sgf::WAVE), slds, st, x...);
+            else if (snb == 32) hipLaunchKernelGGL((sgf::k_compress_small<T, 32>), g, dim3(sgf::WAVE), slds, st, x...);
+            else hipLaunchKernelGGL((sgf::k_compress_small<T, 64>), g, dim3(sgf::WAVE), slds, st, x...);
+          }, a);
+        }, L.t);
+      }
       bool cpersist = false;
       const unsigned cgrid = work_grid((int)L.comp.size(), &cpersist, h->persist_cap);
       if (cpersist) HIP_CHECK(hipMemsetAsync(h->d_ctr.p, 0, sizeof(int), st));
-      launch(h, st, "compress", 0, 0, [&] {
+      if (!snb) launch(h, st, "compress", 0, 0, [&] {
         launch_compress<T>(nlds, cpersist, nb, cgrid, lds, st, D.comp.as<sgf::CompDesc>(),
                            D.compnbr.as<sgf::CompNbr>(), D.cf.as<T>(), D.nbuf.as<T>(), D.phi.as<T>(), D.ltphi.as<T>(),
                            D.tau.as<T>(), D.rank.as<int>(), P.pi, tol, h->d_fail.as<int>(), pre,
@@ -2170,6 +2200,11 @@ sgf_status sgf_set_persistent(sgf_handle h, int32_t max_workgroups) {
   if (!h || max_workgroups < 0) return fail(SGF_EINVAL, "bad persistent-launch argument");
   h->persist_cap = max_workgroups;
   return SGF_OK;
+}
+
+sgf_status sgf_set_small_compress(sgf_handle h, int32_t enable) {
+  if (!h) return fail(SGF_EINVAL, "NULL handle");
+  return guard([&] { h->small_comp = enable != 0; });
 }
 
 sgf_status sgf_set_band_elim(sgf_handle h, int32_t enable) {

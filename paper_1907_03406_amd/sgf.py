@@ -21,7 +21,7 @@ FP64, FP32, FP32_BF16N = 0, 1, 2
 EXPORTED = ["sgf_default_options", "sgf_analyze", "sgf_factorize_numeric", "sgf_factorize", "sgf_autotune",
             "sgf_apply", "sgf_multiply", "sgf_pcg_solve", "sgf_spmv", "sgf_get_info",
             "sgf_get_perm", "sgf_get_level", "sgf_plan_dry_run", "sgf_profile_enable", "sgf_profile_read",
-            "sgf_set_apply_graph", "sgf_set_persistent", "sgf_set_band_apply", "sgf_set_band_elim", "sgf_release", "sgf_estimate_bytes",
+            "sgf_set_apply_graph", "sgf_set_persistent", "sgf_set_band_apply", "sgf_set_band_elim", "sgf_set_small_compress", "sgf_release", "sgf_estimate_bytes",
             "sgf_server_default_options", "sgf_server_create", "sgf_server_add_operator", "sgf_server_submit",
             "sgf_server_wait", "sgf_server_get_stats", "sgf_server_clock", "sgf_server_destroy",
             "sgf_destroy", "sgf_status_str", "sgf_last_error"]
@@ -99,6 +99,7 @@ def load_library(path=LIB_PATH):
         "sgf_set_persistent": (I32, [H, I32]),
         "sgf_set_band_apply": (I32, [H, I32]),
         "sgf_set_band_elim": (I32, [H, I32]),
+        "sgf_set_small_compress": (I32, [H, I32]),
         "sgf_release": (I32, [H]),
         "sgf_estimate_bytes": (I32, [H, I32, P]),
         "sgf_server_default_options": (None, [ctypes.POINTER(ServerOptions)]),
@@ -243,6 +244,10 @@ class Solver:
     def set_band_elim(self, enable=True):
         """Banded one-wavefront elimination on levels with narrow M_II blocks (default on)."""
         _check(_lib.sgf_set_band_elim(self.h, int(bool(enable))))
+
+    def set_small_compress(self, enable=True):
+        """One-wavefront compression of small separators (default on)."""
+        _check(_lib.sgf_set_small_compress(self.h, int(bool(enable))))
 
     def set_band_apply(self, enable=True):
         """Banded interior sweeps on levels with narrow M_II blocks (default on)."""

@@ -460,3 +460,34 @@ def test_banded_elimination_reports_non_spd_cluster():
     assert "elim_banded@L1" in st, sorted(st)
     assert ei.value.code == sgf.SGF_ENOTSPD
     assert s.info()["failed_level"] == 1 and s.info()["failed_cluster"] >= 0
+
+
+@pytest.mark.parametrize("kind,grid,leaf,q", [("fourier", (100, 90), 16, 2), ("blocky", (17, 16, 15), 4, 1),
+                                              ("elast", 9, 3, 1), ("fourier", (61, 58), 8, 2)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_small_compression_matches_workgroup_compression_and_oracle(kind, grid, leaf, q, prec):
+    """Separators compressed one wavefront each (front, Phi and N in LDS)
+    against the one-workgroup compression and the oracle: same ranks at
+    every level, the same operator up to rounding."""
+    p = _prob(kind, grid)
+    F = _oracle(p, q, leaf)
+    pr = sgf.FP64 if prec == "fp64" else sgf.FP32
+    out, ranks = {}, {}
+    V = np.stack([P.random_rhs(13, p.n, j) for j in range(2)], axis=1)
+    for small in (True, False):
+        s = sgf.Solver.from_problem(p, q=q, leaf=leaf, precision=pr)
+        s.set_small_compress(small)
+        s.factorize(torch.from_numpy(p.data).cuda())
+        out[small] = _apply(s, V)
+        ranks[small] = [s.level(t)["rank"].tolist() for t in range(1, s.info()["levels"])]
+    assert ranks[True] == ranks[False]
+    za = O.apply_inverse(F, V)
+    d = _rel(out[True], out[False])
+    print(f"{kind} {grid} leaf {leaf} {prec}: small vs workgroup {d:.1e}, vs oracle {_rel(out[True], za):.1e} "
+          f"(workgroup vs oracle {_rel(out[False], za):.1e})")
+    if prec == "fp64":
+        assert d <= 1e-12
+        assert _rel(out[True], za) <= 1e-10
+    else:
+        assert d <= 1e-4
+        assert _rel(out[True], za) <= 1e-3
