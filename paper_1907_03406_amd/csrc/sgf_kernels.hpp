@@ -706,6 +706,7 @@ __device__ int wg_qrcp(T* N, int s, int c, T* nrm, T* tau, double rank_tol, int*
   for (int j = threadIdx.x; j < c; j += WG) {
     const T* col = N + (int64_t)j * s;
     T acc = 0;
+#pragma unroll 8
     for (int i = 0; i < s; ++i) acc += col[i] * col[i];
     nrm[j] = sqrt(acc);
   }
@@ -768,12 +769,15 @@ __device__ int wg_qrcp(T* N, int s, int c, T* nrm, T* tau, double rank_tol, int*
       T* y = N + (int64_t)j * s;
       if (tk != T(0)) {
         T acc = y[k];
+#pragma unroll 8
         for (int i = k + 1; i < s; ++i) acc += v[i] * y[i];
         acc *= tk;
         y[k] -= acc;
+#pragma unroll 8
         for (int i = k + 1; i < s; ++i) y[i] -= acc * v[i];
       }
       T nn = 0;
+#pragma unroll 8
       for (int i = k + 1; i < s; ++i) nn += y[i] * y[i];
       nrm[j] = sqrt(nn);
     }
@@ -823,6 +827,7 @@ __global__ __launch_bounds__(WG) void k_compress(const CompDesc* __restrict__ D,
   for (int idx = threadIdx.x; idx < s * pi; idx += WG) {
     const int i = idx % s, p = idx / s;
     T acc = 0, acc16 = 0;
+#pragma unroll 8
     for (int j = i; j < s; ++j) {
       const T f = F[j + (int64_t)i * ld], ph = PhB[j + (int64_t)p * s];
       acc += f * ph;
@@ -841,6 +846,7 @@ __global__ __launch_bounds__(WG) void k_compress(const CompDesc* __restrict__ D,
         for (int j = 0; j < x.s_x; ++j)
           acc += bf16_round(F[(x.row + j) + (int64_t)i * ld]) * bf16_round(PhX[j + (int64_t)p * x.s_x]);
       else
+#pragma unroll 8
         for (int j = 0; j < x.s_x; ++j) acc += F[(x.row + j) + (int64_t)i * ld] * PhX[j + (int64_t)p * x.s_x];
       N[i + (int64_t)(pi * (1 + q) + p) * s] = acc;
     }
@@ -874,7 +880,8 @@ constexpr int CS_SMAX = 64, CS_CMAX = 128;
 
 __host__ __device__ inline int64_t comp_small_lds_elems(int s, int K, int c, int pi) {
   const int R = s + K;
-  return (int64_t)(R | 1) * s + (int64_t)(s | 1) * c + (int64_t)R * pi + (int64_t)s * pi + s + c;
+  return (int64_t)(R | 1) * s + (int64_t)(s | 1) * c + (int64_t)R * pi + (int64_t)s * pi + s + c +
+         (int64_t)(s | 1) * s;
 }
 
 template <typename T>
@@ -892,7 +899,7 @@ __global__ __launch_bounds__(WAVE) void k_compress_small(const CompDesc* __restr
                                                          T* __restrict__ nbuf, const T* __restrict__ phi,
                                                          T* __restrict__ ltphi, T* __restrict__ tau_all,
                                                          int* __restrict__ rank, int pi, double rank_tol, int* fail,
-                                                         int prefactored, int bf16n) {
+                                                         int prefactored, int bf16n, T* __restrict__ tb) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int ci = blockIdx.x;
   const CompDesc d = D[ci];
@@ -904,6 +911,7 @@ __global__ __launch_bounds__(WAVE) void k_compress_small(const CompDesc* __restr
   T* Lt = Ph + (int64_t)R * pi;             // s x pi, ld s
   T* invd = Lt + (int64_t)s * pi;           // s reciprocal pivots
   T* taul = invd + s;                       // c reflector coefficients
+  T* Xl = taul + c;                         // s x s, ld s | 1: T_B = Q^T L_B^{-1}
   const int lane = threadIdx.x;
   T* F = cf + d.cf_off;
   // ---- stage the front and the Phi blocks ----
@@ -952,6 +960,7 @@ __global__ __launch_bounds__(WAVE) void k_compress_small(const CompDesc* __restr
     for (int i = s + lane; i < R; i += WAVE)
       for (int j = 0; j < s; ++j) {
         T acc = Fl[i + j * ldf];
+#pragma unroll 8
         for (int p = 0; p < j; ++p) acc -= Fl[i + p * ldf] * Fl[j + p * ldf];
         Fl[i + j * ldf] = acc * invd[j];
       }
@@ -965,6 +974,7 @@ __global__ __launch_bounds__(WAVE) void k_compress_small(const CompDesc* __restr
   for (int idx = lane; idx < s * pi; idx += WAVE) {
     const int i = idx % s, p = idx / s;
     T acc = 0, acc16 = 0;
+#pragma unroll 8
     for (int j = i; j < s; ++j) {
       const T f = Fl[j + i * ldf], ph = Ph[j + p * R];
       acc += f * ph;
@@ -982,6 +992,7 @@ __global__ __launch_bounds__(WAVE) void k_compress_small(const CompDesc* __restr
         for (int j = 0; j < x.s_x; ++j)
           acc += bf16_round(Fl[(x.row + j) + i * ldf]) * bf16_round(Ph[(x.row + j) + p * R]);
       else
+#pragma unroll 8
         for (int j = 0; j < x.s_x; ++j) acc += Fl[(x.row + j) + i * ldf] * Ph[(x.row + j) + p * R];
       Nl[i + (pi * (1 + q) + p) * ldn] = acc;
     }
@@ -994,6 +1005,7 @@ __global__ __launch_bounds__(WAVE) void k_compress_small(const CompDesc* __restr
     const int j = lane + h * WAVE;
     T acc = 0;
     if (j < c)
+#pragma unroll 8
       for (int i = 0; i < s; ++i) acc += Nl[i + j * ldn] * Nl[i + j * ldn];
     nr[h] = sqrt(acc);
   }
@@ -1044,12 +1056,15 @@ __global__ __launch_bounds__(WAVE) void k_compress_small(const CompDesc* __restr
         T* y = Nl + j * ldn;
         if (tk != T(0)) {
           T acc = y[k];
+#pragma unroll 8
           for (int i = k + 1; i < s; ++i) acc += v[i] * y[i];
           acc *= tk;
           y[k] -= acc;
+#pragma unroll 8
           for (int i = k + 1; i < s; ++i) y[i] -= acc * v[i];
         }
         T nn = 0;
+#pragma unroll 8
         for (int i = k + 1; i < s; ++i) nn += y[i] * y[i];
         nr[h] = sqrt(nn);
       }
@@ -1071,9 +1086,11 @@ __global__ __launch_bounds__(WAVE) void k_compress_small(const CompDesc* __restr
       for (int p = lane; p < pi; p += WAVE) {
         T* x = Lt + p * s;
         T acc = x[k];
+#pragma unroll 8
         for (int i = k + 1; i < s; ++i) acc += Nl[i + k * ldn] * x[i];
         acc *= tk;
         x[k] -= acc;
+#pragma unroll 8
         for (int i = k + 1; i < s; ++i) x[i] -= acc * Nl[i + k * ldn];
       }
       __builtin_amdgcn_wave_barrier();
@@ -1081,6 +1098,36 @@ __global__ __launch_bounds__(WAVE) void k_compress_small(const CompDesc* __restr
   __builtin_amdgcn_wave_barrier();
   T* LtP = ltphi + d.ltphi_off;
   for (int idx = lane; idx < s * pi; idx += WAVE) LtP[idx] = Lt[idx];
+  if (r < s) {
+    // ---- T_B = Q^T L_B^{-1} into its slot, for the apply and the coarse
+    // couplings: lane j solves column j of L_B^{-1} (rows above j are zero),
+    // then the r reflectors act on every column ----
+    const int ldx = s | 1;
+    for (int j = lane; j < s; j += WAVE) {
+      T* xc = Xl + j * ldx;
+      for (int i = 0; i < j; ++i) xc[i] = T(0);
+      for (int i = j; i < s; ++i) {
+        T acc = i == j ? T(1) : T(0);
+#pragma unroll 8
+        for (int p = j; p < i; ++p) acc -= Fl[i + p * ldf] * xc[p];
+        xc[i] = acc / Fl[i + i * ldf];
+      }
+      for (int k = 0; k < r; ++k) {
+        const T tk = taul[k];
+        if (tk == T(0)) continue;
+        T acc = xc[k];
+#pragma unroll 8
+        for (int i = k + 1; i < s; ++i) acc += Nl[i + k * ldn] * xc[i];
+        acc *= tk;
+        xc[k] -= acc;
+#pragma unroll 8
+        for (int i = k + 1; i < s; ++i) xc[i] -= acc * Nl[i + k * ldn];
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    T* X = tb + d.tb_off;
+    for (int idx = lane; idx < s * s; idx += WAVE) X[idx] = Xl[idx % s + (idx / s) * ldx];
+  }
   if (lane == 0) rank[ci] = r;
 }
 
@@ -1127,6 +1174,7 @@ __global__ __launch_bounds__(WG) void k_pair(const PairDesc* __restrict__ P, con
     for (int idx = threadIdx.x; idx < ra * sb; idx += WG) {
       const int i = idx % ra, j = idx / ra;
       T acc = 0;
+#pragma unroll 8
       for (int p = 0; p < sa; ++p) acc += Ta[i + (int64_t)p * sa] * blk[p + (int64_t)j * sa];
       G[idx] = acc;
     }
@@ -1139,6 +1187,7 @@ __global__ __launch_bounds__(WG) void k_pair(const PairDesc* __restrict__ P, con
     for (int idx = threadIdx.x; idx < ra * rb; idx += WG) {
       const int i = idx % ra, j = idx / ra;
       T acc = 0;
+#pragma unroll 8
       for (int q = 0; q < sb; ++q) acc += G[i + (int64_t)q * ra] * Tb[j + (int64_t)q * sb];
       blk[i + (int64_t)j * sa] = acc;
     }
@@ -1169,6 +1218,7 @@ __device__ void wg_trsv_lower(const T* __restrict__ L, int64_t ld, int m, T* ys)
     __syncthreads();
     for (int i = jb + nb + threadIdx.x; i < m; i += WG) {
       T acc = 0;
+#pragma unroll 8
       for (int j = 0; j < nb; ++j) acc += L[i + (int64_t)(jb + j) * ld] * ys[jb + j];
       ys[i] -= acc;
     }
@@ -1797,6 +1847,7 @@ __global__ __launch_bounds__(WG) void k_comp_apply_t(const CompApply* __restrict
       T acc[RCM];
 #pragma unroll
       for (int c = 0; c < RCM; ++c) acc[c] = 0;
+#pragma unroll 8
       for (int j = 0; j < s; ++j) {
         const T xij = X[i + (int64_t)j * s];
 #pragma unroll
@@ -1813,6 +1864,7 @@ __global__ __launch_bounds__(WG) void k_comp_apply_t(const CompApply* __restrict
       T acc[RCM];
 #pragma unroll
       for (int c = 0; c < RCM; ++c) acc[c] = 0;
+#pragma unroll 4
       for (int i = lane; i < s; i += WAVE) {
         const T xij = X[i + (int64_t)j * s];
 #pragma unroll

@@ -115,6 +115,8 @@ struct LevelDev {
   int tmax_m = 0, tmax_k = 0, tmax_rm = 0;
   int band_bw = -1, band_m = 0, band_k = 0;   // widest band, largest m and k of the interiors (-1: none)
   int banded_w = 0;                            // 1: the last factorization used the banded elimination
+  bool comp_small = false;                     // compressions by k_compress_small (T_B formed there, in its slot)
+  bool capply_small = false;                   // the uploaded apply list uses those slots
   // fronts of the banded elimination grouped by ring width 8 / 16 / 24 / 32
   // (band_ptr[c] .. band_ptr[c + 1] in band_list); band_ok: every front fits one
   std::vector<int32_t> h_band_list;
@@ -1084,13 +1086,15 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
       if (lds > LDS_BYTES) throw SgfError(SGF_EINVAL, "compression kernel needs more LDS than available");
       double tol = P.opt.rank_tol;
       const int pre = D.comp_tiled ? 1 : 0;
+      D.comp_small = snb > 0;
       if (snb) {
         const int bf = P.opt.precision == SGF_FP32_BF16N ? 1 : 0;
+        D.tb.ensure((size_t)std::max<int64_t>(L.tb_elems, 1) * sizeof(T));
         launch(h, st, "compress", 0, 0, [&] {
           const dim3 g((unsigned)L.comp.size());
           auto a = std::make_tuple(D.comp.as<sgf::CompDesc>(), D.compnbr.as<sgf::CompNbr>(), D.cf.as<T>(),
                                    D.nbuf.as<T>(), (const T*)D.phi.as<T>(), D.ltphi.as<T>(), D.tau.as<T>(),
-                                   D.rank.as<int>(), P.pi, tol, h->d_fail.as<int>(), pre, bf);
+                                   D.rank.as<int>(), P.pi, tol, h->d_fail.as<int>(), pre, bf, D.tb.as<T>());
           std::apply([&](auto... x) {
             if (snb == 16) hipLaunchKernelGGL((sgf::k_compress_small<T, 16>), g, dim3(sgf::WAVE), slds, st, x...);
             else if (snb == 32) hipLaunchKernelGGL((sgf::k_compress_small<T, 32>), g, dim3(sgf::WAVE), slds, st, x...);
@@ -1147,9 +1151,11 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
     }
     // compressed separators of this level, for the apply
     L.capply.clear();
+    std::vector<int64_t> cap_tb;   // T_B slot of each compressed separator (small compressions)
     for (size_t c = 0; c < L.comp.size(); ++c) {
       const auto& d = L.comp[c];
       if (L.rank[c] < d.s) {
+        cap_tb.push_back(d.tb_off);
         sgf::CompApply a{};
         a.cf_off = d.cf_off;
         a.v_off = d.n_off;
@@ -1164,24 +1170,28 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
       }
     }
     {
+      // T_B slots: the planned ones when the small compression formed T_B,
+      // else packed over the compressed separators for k_comp_explicit
       int64_t toff = 0, voff = 0;
-      for (auto& a : L.capply) {
-        a.t_off = toff;
+      for (size_t q = 0; q < L.capply.size(); ++q) {
+        auto& a = L.capply[q];
+        a.t_off = D.comp_small ? cap_tb[q] : toff;
         toff += (int64_t)a.s * a.s;
         a.v_off2 = (int32_t)voff;
         voff += a.s;
       }
-      D.tb.ensure(std::max<int64_t>(toff, 1) * sizeof(T));
+      D.tb.ensure(std::max<int64_t>(D.comp_small ? L.tb_elems : toff, 1) * sizeof(T));
       D.c_elems = voff;
     }
-    if (!same_ranks) {
+    if (!same_ranks || D.capply_small != D.comp_small) {
+      D.capply_small = D.comp_small;
       upload(D.capply, L.capply, st);
       L.t_of_comp.assign(L.comp.size(), -1);
       for (size_t c = 0, q = 0; c < L.comp.size(); ++c)
         if (L.rank[c] < L.comp[c].s) L.t_of_comp[c] = L.capply[q++].t_off;
       upload(D.tofcomp, L.t_of_comp, st);
     }
-    if (!L.capply.empty()) {
+    if (!L.capply.empty() && !D.comp_small) {
       double fl = 0;
       for (auto& a : L.capply) fl += (double)a.s * a.s * a.s / 3.0 + 4.0 * a.s * a.s * a.r;
       launch(h, st, "comp_explicit", fl, 0, [&] {

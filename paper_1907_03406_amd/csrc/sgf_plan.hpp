@@ -160,6 +160,7 @@ struct CompDesc {
   int64_t slot_off;     // slots of B
   int32_t s, K, c, nnb, nb_ptr, cluster, blk_diag_pad;
   int64_t blk_diag;     // offset of M_BB pair block
+  int64_t tb_off;       // s x s slot for T_B = Q^T L_B^{-1} (filled when the separator compresses)
 };
 struct CompNbr {
   int64_t blk_off;      // pair block holding M_BX (if X > B) or M_XB (X < B)
@@ -221,7 +222,7 @@ struct Level {
   std::vector<int32_t> comp_of;            // cluster -> compression index or -1
   std::vector<CompDesc> comp;
   std::vector<CompNbr> comp_nbr;
-  int64_t cf_elems = 0, n_elems = 0, ltphi_elems = 0, tau_elems = 0;
+  int64_t cf_elems = 0, n_elems = 0, ltphi_elems = 0, tau_elems = 0, tb_elems = 0;
   int32_t max_cf_rows = 0, max_c = 0, max_s = 0;
   // Phi per cluster
   std::vector<int64_t> phi_off;
@@ -455,7 +456,7 @@ inline void build_level(Level& L, const Options& o, int pi) {
   L.comp.clear();
   L.comp_nbr.clear();
   L.comp_of.assign(nc, -1);
-  L.cf_elems = L.n_elems = L.ltphi_elems = L.tau_elems = 0;
+  L.cf_elems = L.n_elems = L.ltphi_elems = L.tau_elems = L.tb_elems = 0;
   L.max_cf_rows = L.max_c = L.max_s = 0;
   if (L.compress) {
     L.comp.reserve(ns);
@@ -491,6 +492,8 @@ inline void build_level(Level& L, const Options& o, int pi) {
       L.ltphi_elems += (int64_t)d.s * pi;
       d.tau_off = L.tau_elems;
       L.tau_elems += d.c;
+      d.tb_off = L.tb_elems;
+      L.tb_elems += (int64_t)d.s * d.s;
       d.phi_off = L.phi_off[B];
       d.slot_off = L.slot_ptr[B];
       d.blk_diag = L.pairs[L.pair_diag[p]].blk_off;
@@ -596,6 +599,7 @@ inline void validate_level(const Level& L, int64_t n, int pi) {
     req(d.phi_off >= 0 && d.phi_off + (int64_t)d.s * pi <= L.phi_elems, "Phi_B");
     req(d.ltphi_off >= 0 && d.ltphi_off + (int64_t)d.s * pi <= L.ltphi_elems, "LtPhi");
     req(d.tau_off >= 0 && d.tau_off + d.c <= L.tau_elems, "tau");
+    req(d.tb_off >= 0 && d.tb_off + (int64_t)d.s * d.s <= L.tb_elems, "T_B slot");
     req(d.slot_off >= 0 && d.slot_off + d.s <= nsl, "compression slots");
     req(d.blk_diag >= 0 && d.blk_diag + (int64_t)d.s * d.s <= L.blk_elems, "diagonal block");
     req(d.nb_ptr >= 0 && d.nb_ptr + d.nnb <= (int64_t)L.comp_nbr.size(), "neighbour list");
