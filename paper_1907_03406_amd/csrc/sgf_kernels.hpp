@@ -117,6 +117,46 @@ __global__ void k_zero(T* __restrict__ p, int64_t n) {
     p[i] = T(0);
 }
 
+// Several descriptor tables uploaded as one blob: a header of pieces (offset
+// of the table in the blob, its device destination, its size in bytes, a
+// multiple of 4) followed by the tables.  Workgroup (p, c) copies chunk c of
+// piece p.
+struct BlobPiece {
+  uint64_t src_off, dst, bytes;
+};
+constexpr int BLOB_CHUNK = WG * 16;   // 4-byte words per workgroup
+__global__ __launch_bounds__(WG) void k_scatter_blob(const unsigned char* __restrict__ blob) {
+  const BlobPiece pc = reinterpret_cast<const BlobPiece*>(blob)[blockIdx.x];
+  const int64_t words = (int64_t)(pc.bytes / 4);
+  const int64_t lo = (int64_t)blockIdx.y * BLOB_CHUNK;
+  if (lo >= words) return;
+  const int64_t hi = min(words, lo + (int64_t)BLOB_CHUNK);
+  const uint32_t* __restrict__ src = reinterpret_cast<const uint32_t*>(blob + pc.src_off);
+  uint32_t* __restrict__ dst = reinterpret_cast<uint32_t*>(pc.dst);
+  for (int64_t i = lo + threadIdx.x; i < hi; i += WG) dst[i] = src[i];
+}
+
+// Clear the entries of the fronts in `list` that the banded elimination
+// reads: the lower band of M_II (rows c .. c + bw of column c, bw clamped to
+// m - 1) and M_SI (rows m .. m + k - 1 of every interior column).  Valid only
+// while the rest of each front is known to hold zeros, apart from the upper
+// band (rewritten by the CSR fill) and the lower triangle of the separator
+// block (overwritten by the banded elimination).  One workgroup per front.
+template <typename T>
+__global__ __launch_bounds__(WG) void k_zero_band(const ElimDesc* __restrict__ D, const int32_t* __restrict__ list,
+                                                  T* __restrict__ arena) {
+  const ElimDesc d = D[list[blockIdx.x]];
+  const int m = d.m, k = d.k, bw = min(d.bw, max(m - 1, 0)), per = bw + 1 + k;
+  const int64_t R = (int64_t)m + k;
+  T* C = arena + d.front_off;
+  const int64_t tot = (int64_t)m * per;
+  for (int64_t idx = threadIdx.x; idx < tot; idx += WG) {
+    const int c = (int)(idx / per), r = (int)(idx % per);
+    const int row = r <= bw ? c + r : m + (r - bw - 1);
+    if (row < R && (r > bw || c + r < m)) C[row + (int64_t)c * R] = T(0);
+  }
+}
+
 // Phi_B = Pi(B, :) for every level-1 cluster (Sec. 3.1; block diagonal per
 // component for dofs_per_node > 1, Eq. 7.4).  Coordinates normalised
 // globally to [-1, 1]: xh = (x - lo) * sc - 1 with sc = 2 / (hi - lo).
@@ -1605,6 +1645,26 @@ __device__ __forceinline__ void stage_band(const T* __restrict__ C, int R, int m
   }
 }
 
+// Workgroup gather from global memory into LDS, element idx from
+// src[f(idx).x] to dst[f(idx).y], with every load of a round issued before
+// its stores, so that a thread keeps U loads in flight instead of one.
+template <typename T, int U, typename F>
+__device__ __forceinline__ void lds_gather(T* dst, const T* __restrict__ src, int n, F f) {
+  for (int base = 0; base < n; base += U * WG) {
+    T t[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int idx = base + u * WG + (int)threadIdx.x;
+      if (idx < n) t[u] = src[f(idx).x];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int idx = base + u * WG + (int)threadIdx.x;
+      if (idx < n) dst[f(idx).y] = t[u];
+    }
+  }
+}
+
 // LDS elements of the banded sweeps for fronts up to (m, k, bw), RC columns.
 __host__ __device__ constexpr int band_fwd_ld(int m) { return (m + 1) & ~1; }
 __host__ __device__ constexpr int band_bwd_ld(int m) { return m | 1; }
@@ -1739,9 +1799,14 @@ __global__ __launch_bounds__(WG) void k_band_bwd(const ElimDesc* __restrict__ D,
   const T* PL = PK ? PB + band_pk_lsi(m, bw) : nullptr;
   for (int j0 = 0; j0 < m; j0 += tj) {
     const int cw = min(tj, m - j0);
-    for (int idx = threadIdx.x; idx < k * cw; idx += WG) {
-      const int r = idx % k, jl = idx / k;
-      Bd[jl * ldk + r] = PK ? PL[(int64_t)j0 * k + idx] : C[m + r + (int64_t)(j0 + jl) * R];
+    if (PK) {
+      const T* src = PL + (int64_t)j0 * k;
+      lds_gather<T, 8>(Bd, src, k * cw, [=](int idx) { return make_int2(idx, (idx / k) * ldk + idx % k); });
+    } else {
+      for (int idx = threadIdx.x; idx < k * cw; idx += WG) {
+        const int r = idx % k, jl = idx / k;
+        Bd[jl * ldk + r] = C[m + r + (int64_t)(j0 + jl) * R];
+      }
     }
     __syncthreads();
     T acc[RC];
@@ -1768,10 +1833,10 @@ __global__ __launch_bounds__(WG) void k_band_bwd(const ElimDesc* __restrict__ D,
   }
   if (PK) {
     const int pld = band_pk_ld(m);
-    for (int idx = threadIdx.x; idx < (bw + 1) * m; idx += WG) {
+    lds_gather<T, 8>(Bd, PB, (bw + 1) * m, [=](int idx) {
       const int r = idx / m, i = idx - r * m;
-      Bd[r * ld + i] = PB[r * pld + i];
-    }
+      return make_int2(r * pld + i, r * ld + i);
+    });
   } else {
     stage_band(C, R, m, bw, Bd, ld);
   }

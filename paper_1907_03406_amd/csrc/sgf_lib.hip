@@ -83,10 +83,110 @@ struct DevBuf {
 };
 
 template <typename V>
-void upload(DevBuf& b, const std::vector<V>& v, hipStream_t st) {
+void upload_direct(DevBuf& b, const std::vector<V>& v, hipStream_t st) {
   b.ensure(v.size() * sizeof(V));
   if (!v.empty()) HIP_CHECK(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(V), hipMemcpyHostToDevice, st));
 }
+
+// Pinned staging of the descriptor uploads.  From pageable memory the
+// runtime copies synchronously through its own bounce buffer, one table at a
+// time; a table placed in pinned memory is queued and the host goes on with
+// the next one.  The space is reused once the stream that reads it has been
+// synchronized (the factorization synchronizes once per level to read the
+// ranks), or after an explicit drain when it is full.
+struct Staging {
+  unsigned char* p = nullptr;
+  size_t cap = 0, used = 0;
+  hipStream_t st = nullptr;   // stream of the copies queued since the last reuse point
+  bool pending = false;
+  static constexpr size_t MAX_TABLE = size_t(64) << 20;   // larger tables go direct
+  Staging() = default;
+  Staging(const Staging&) = delete;
+  Staging& operator=(const Staging&) = delete;
+  void drain() {
+    if (pending) HIP_CHECK(hipStreamSynchronize(st));
+    pending = false;
+    used = 0;
+  }
+  // the caller has synchronized stream s
+  void synced(hipStream_t s) {
+    if (!pending || s == st) {
+      pending = false;
+      used = 0;
+    }
+  }
+  // space for `bytes` (256-byte aligned), after the queued copies on stream s
+  unsigned char* take(size_t bytes, hipStream_t s) {
+    if (pending && s != st) drain();
+    size_t off = (used + 255) & ~size_t(255);
+    if (off + bytes > cap) {
+      drain();
+      off = 0;
+      if (bytes > cap) {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        cap = 0;
+        const size_t want = std::max(bytes, size_t(8) << 20);
+        if (hipHostMalloc((void**)&p, want, hipHostMallocDefault) != hipSuccess) {
+          p = nullptr;
+          (void)hipGetLastError();
+          return nullptr;
+        }
+        cap = want;
+      }
+    }
+    used = off + bytes;
+    st = s;
+    pending = true;
+    return p + off;
+  }
+  ~Staging() {
+    if (pending) (void)hipDeviceSynchronize();
+    if (p) (void)hipHostFree(p);
+  }
+};
+
+// One table to an ensured device buffer, through the staging space unless
+// `direct` (or too large for it).
+inline void upload_bytes(Staging& S, bool direct, void* dst, const void* src, size_t bytes, hipStream_t st) {
+  if (!bytes) return;
+  unsigned char* q = direct || bytes > Staging::MAX_TABLE ? nullptr : S.take(bytes, st);
+  if (!q) {
+    HIP_CHECK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
+    return;
+  }
+  std::memcpy(q, src, bytes);
+  HIP_CHECK(hipMemcpyAsync(dst, q, bytes, hipMemcpyHostToDevice, st));
+}
+
+template <typename V>
+void upload_staged(Staging& S, bool direct, DevBuf& b, const std::vector<V>& v, hipStream_t st) {
+  const size_t bytes = v.size() * sizeof(V);
+  b.ensure(bytes);
+  upload_bytes(S, direct, b.p, v.data(), bytes, st);
+}
+
+// Tables queued while a batch is open (their host vectors unchanged until
+// the flush), sent as one blob: one copy and one scatter kernel in place of
+// a copy per table.  The device destination is taken when the table is
+// queued (the DevBuf object itself may move before the flush, its memory
+// does not); a buffer is queued at most once per batch.
+struct UploadBatch {
+  struct Item {
+    void* dst;
+    const void* src;
+    size_t bytes;
+  };
+  std::vector<Item> items;
+  bool flushed = false;
+  void add(DevBuf& b, const void* src, size_t bytes) {
+    b.ensure(bytes);
+    if (!bytes) return;
+    for (auto& it : items)
+      if (it.dst == b.p) throw SgfError(SGF_EINVAL, "a device table queued twice in one upload batch");
+    items.push_back({b.p, src, bytes});
+  }
+};
 
 // Algorithmic work of the launches of one level (from the plan).
 struct LevelWork {
@@ -115,6 +215,11 @@ struct LevelDev {
   int tmax_m = 0, tmax_k = 0, tmax_rm = 0;
   int band_bw = -1, band_m = 0, band_k = 0;   // widest band, largest m and k of the interiors (-1: none)
   int banded_w = 0;                            // 1: the last factorization used the banded elimination
+  // level 1 only: every front entry outside the lower band, M_SI, the upper
+  // band and the lower separator triangle is known to be zero (after a full
+  // clear, kept by the CSR fill and the banded elimination), so the next
+  // banded factorization clears just the band and M_SI
+  bool front_clean = false;
   bool comp_small = false;                     // compressions by k_compress_small (T_B formed there, in its slot)
   bool capply_small = false;                   // the uploaded apply list uses those slots
   // fronts of the banded elimination grouped by ring width 8 / 16 / 24 / 32
@@ -303,6 +408,10 @@ struct sgf_handle_s {
   // forked from and joined to the caller's stream with events
   hipStream_t side_stream = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  Staging staging;
+  UploadBatch* batch = nullptr;   // open upload batch, if any
+  DevBuf blob;                    // device copy of the last batch's blob
+  hipStream_t blob_st = nullptr;  // stream of the last scatter kernel
   ~sgf_handle_s() {
     drop_graph();
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
@@ -313,6 +422,77 @@ struct sgf_handle_s {
 };
 
 namespace {
+
+// Descriptor tables: staged through pinned memory, direct while a graph is
+// being recorded (a recorded copy would read the staging space at replay).
+template <typename V>
+void upload(sgf_handle h, DevBuf& b, const std::vector<V>& v, hipStream_t st) {
+  if (h->batch && !h->capturing) h->batch->add(b, v.data(), v.size() * sizeof(V));
+  else upload_staged(h->staging, h->capturing, b, v, st);
+}
+
+void flush_batch(sgf_handle h, UploadBatch& B, hipStream_t st) {
+  const size_t n = B.items.size();
+  auto one_by_one = [&] {
+    for (auto& it : B.items) upload_bytes(h->staging, h->capturing, it.dst, it.src, it.bytes, st);
+  };
+  size_t total = (n * sizeof(sgf::BlobPiece) + 255) & ~size_t(255);
+  size_t max_words = 0;
+  std::vector<size_t> off(n);
+  for (size_t i = 0; i < n; ++i) {
+    if (B.items[i].bytes % 4) throw SgfError(SGF_EINVAL, "descriptor table size not a multiple of 4 bytes");
+    off[i] = total;
+    total += (B.items[i].bytes + 255) & ~size_t(255);
+    max_words = std::max(max_words, B.items[i].bytes / 4);
+  }
+  unsigned char* q = nullptr;
+  if (n > 1 && !h->capturing && total <= Staging::MAX_TABLE) {
+    // the device blob is rewritten only after the previous scatter read it
+    if (h->blob_st && (h->blob_st != st || total > h->blob.bytes)) HIP_CHECK(hipStreamSynchronize(h->blob_st));
+    q = h->staging.take(total, st);
+  }
+  if (!q) {
+    one_by_one();
+  } else {
+    auto* hp = reinterpret_cast<sgf::BlobPiece*>(q);
+    for (size_t i = 0; i < n; ++i) {
+      hp[i] = sgf::BlobPiece{off[i], (uint64_t)(uintptr_t)B.items[i].dst, B.items[i].bytes};
+      std::memcpy(q + off[i], B.items[i].src, B.items[i].bytes);
+    }
+    h->blob.ensure(total);
+    HIP_CHECK(hipMemcpyAsync(h->blob.p, q, total, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(sgf::k_scatter_blob, dim3((unsigned)n, cdiv((int64_t)max_words, sgf::BLOB_CHUNK)),
+                       dim3(sgf::WG), 0, st, h->blob.as<unsigned char>());
+    HIP_CHECK(hipGetLastError());
+    h->blob_st = st;
+  }
+  B.flushed = true;
+}
+
+// Opens a batch for the uploads of its scope (unless one is open already);
+// flush() sends it.  Left without a flush (an error on the way), the levels'
+// tables are marked stale so that the next factorization uploads them again.
+struct BatchScope {
+  sgf_handle h;
+  UploadBatch b;
+  bool owner;
+  explicit BatchScope(sgf_handle hh) : h(hh), owner(hh->batch == nullptr) {
+    if (owner) h->batch = &b;
+  }
+  void flush(hipStream_t st) {
+    if (!owner) return;
+    h->batch = nullptr;
+    flush_batch(h, b, st);
+  }
+  ~BatchScope() {
+    if (!owner) return;
+    if (h->batch == &b) h->batch = nullptr;
+    if (!b.flushed) {
+      for (auto& D : h->lev) D.uploaded = false;
+      h->factored = false;
+    }
+  }
+};
 
 sgf_status fail(sgf_status c, const std::string& m) {
   g_last_error = m;
@@ -437,11 +617,11 @@ void launch_compress(bool nlds, bool pers, int nb, unsigned grid, size_t lds, hi
 
 void ensure_static(sgf_handle h, hipStream_t st) {
   if (h->dev_static) return;
-  upload(h->d_perm, h->plan.perm, st);
-  upload(h->d_rowptr, h->h_rowptr, st);
-  upload(h->d_colidx, h->h_colidx, st);
-  upload(h->d_csrdst, h->plan.csr_dst, st);
-  upload(h->d_coords, h->h_coords, st);
+  upload_direct(h->d_perm, h->plan.perm, st);
+  upload_direct(h->d_rowptr, h->h_rowptr, st);
+  upload_direct(h->d_colidx, h->h_colidx, st);
+  upload_direct(h->d_csrdst, h->plan.csr_dst, st);
+  upload_direct(h->d_coords, h->h_coords, st);
   h->d_vals.ensure(h->nnz * sizeof(double));
   h->d_fail.ensure(sizeof(int));
   h->d_ctr.ensure(sizeof(int));
@@ -571,7 +751,7 @@ void build_tiled(sgf_handle h, const sgf::Level& L, LevelDev& D, hipStream_t st)
   }
   if ((size_t)(((D.tmax_m + 3) & ~3) + sgf::WG) * h->esz > LDS_BYTES || (size_t)D.tmax_k * h->esz > LDS_BYTES)
     throw SgfError(SGF_EINVAL, "front too large for the tiled apply kernels");
-  upload(D.tf, D.h_tf, st);
+  upload(h, D.tf, D.h_tf, st);
   D.zt.ensure(std::max<int64_t>(D.z_elems, 1) * h->esz);
 }
 
@@ -582,6 +762,7 @@ void upload_level(sgf_handle h, int li, hipStream_t st) {
   LevelDev& D = h->lev[li];
   if (D.uploaded) return;
   D.uploaded = true;
+  D.front_clean = false;
   const size_t e = h->esz;
   D.arena.ensure((L.front_elems + L.blk_elems) * e);
   D.scratch.ensure(L.scratch_elems * e);
@@ -618,7 +799,7 @@ void upload_level(sgf_handle h, int li, hipStream_t st) {
       if (D.band_ok) D.h_band_list.insert(D.h_band_list.end(), cls[c].begin(), cls[c].end());
       D.band_ptr[c + 1] = (int)D.h_band_list.size();
     }
-    if (D.band_ok) upload(D.band_list, D.h_band_list, st);
+    if (D.band_ok) upload(h, D.band_list, D.h_band_list, st);
     // packed copies for the apply sweeps, 64-element aligned
     D.pk_elems = 0;
     for (auto& e : L.elim) {
@@ -629,17 +810,18 @@ void upload_level(sgf_handle h, int li, hipStream_t st) {
         e.pk_off = -1;
       }
     }
-  }  upload(D.elim, L.elim, st);
-  upload(D.pairs, L.pairs, st);
-  upload(D.schur, L.schur, st);
-  upload(D.comp, L.comp, st);
-  upload(D.compnbr, L.comp_nbr, st);
-  upload(D.sepacc, L.sepacc, st);
-  upload(D.sepsrc, L.sepacc_src, st);
-  upload(D.slots, L.slots, st);
-  upload(D.nslots, L.nslots, st);
-  upload(D.slotptr, L.slot_ptr, st);
-  upload(D.phioff, L.phi_off, st);
+  }
+  upload(h, D.elim, L.elim, st);
+  upload(h, D.pairs, L.pairs, st);
+  upload(h, D.schur, L.schur, st);
+  upload(h, D.comp, L.comp, st);
+  upload(h, D.compnbr, L.comp_nbr, st);
+  upload(h, D.sepacc, L.sepacc, st);
+  upload(h, D.sepsrc, L.sepacc_src, st);
+  upload(h, D.slots, L.slots, st);
+  upload(h, D.nslots, L.nslots, st);
+  upload(h, D.slotptr, L.slot_ptr, st);
+  upload(h, D.phioff, L.phi_off, st);
   D.tiled = level_tiled(h, L);
   if (D.tiled) build_tiled(h, L, D, st);
 
@@ -661,11 +843,11 @@ void upload_level(sgf_handle h, int li, hipStream_t st) {
     };
     order(D.h_elim_order, L.elim.size(),
           [&](int32_t a) { return elim_flops(L.elim[a].m, L.elim[a].k, L.elim[a].bw); }, &D.elim_uneven);
-    upload(D.elim_order, D.h_elim_order, st);
+    upload(h, D.elim_order, D.h_elim_order, st);
     order(D.h_comp_order, L.comp.size(),
           [&](int32_t c) { return (double)L.comp[c].s * L.comp[c].s * (L.comp[c].s + L.comp[c].K + L.comp[c].c); },
           &D.comp_uneven);
-    upload(D.comp_order, D.h_comp_order, st);
+    upload(h, D.comp_order, D.h_comp_order, st);
   }
   // compression fronts [M_BB ; M_XB] too large for the one-workgroup panel:
   // their Cholesky / triangular solve goes through the tiled kernels
@@ -695,7 +877,7 @@ void upload_level(sgf_handle h, int li, hipStream_t st) {
         f.zrows = 0;
         D.h_ctf.push_back(f);
       }
-      upload(D.ctf, D.h_ctf, st);
+      upload(h, D.ctf, D.h_ctf, st);
     }
   }
 }
@@ -739,6 +921,7 @@ int check_fail(sgf_handle h, hipStream_t st) {
   int f = -1;
   HIP_CHECK(hipMemcpyAsync(&f, h->d_fail.p, sizeof(int), hipMemcpyDeviceToHost, st));
   HIP_CHECK(hipStreamSynchronize(st));
+  h->staging.synced(st);
   return f;
 }
 
@@ -867,7 +1050,7 @@ void factor_top(sgf_handle h, const sgf::Level& L, LevelDev& D, hipStream_t st) 
   }, L.t);
   h->h_topdesc.assign(1, e0);
   h->h_topdesc[0].front_off = 0;
-  upload(h->d_topdesc, h->h_topdesc, st);
+  upload(h, h->d_topdesc, h->h_topdesc, st);
   h->top_tiled = R > 256 || R >= h->tiled_rows;
   if (h->top_tiled) {
     if ((size_t)(((R + 3) & ~3) + sgf::WG) * sizeof(double) > LDS_BYTES)
@@ -881,7 +1064,7 @@ void factor_top(sgf_handle h, const sgf::Level& L, LevelDev& D, hipStream_t st) 
     f.m = R;
     f.cluster = e0.cluster;
     h->h_toptf.assign(1, f);
-    upload(h->d_toptf, h->h_toptf, st);
+    upload(h, h->d_toptf, h->h_toptf, st);
     h->topz.ensure(RR * sizeof(double));
     tiled_factor<double>(h, st, h->h_toptf, h->d_toptf.as<sgf::TFront>(), h->top64.as<double>(),
                          h->topz.as<double>(), L.t, "top");
@@ -922,12 +1105,32 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
   HIP_CHECK(hipMemcpyAsync(h->d_fail.p, &init, sizeof(int), hipMemcpyHostToDevice, st));
   const double e = (double)sizeof(T);
   // ---- level 1 inputs ---------------------------------------------------------
-  upload_level(h, 0, st);
+  {
+    BatchScope bs(h);
+    upload_level(h, 0, st);
+    bs.flush(st);
+  }
   {
     sgf::Level& L = P.levels[0];
     LevelDev& D = h->lev[0];
     const int64_t ne = L.front_elems + L.blk_elems;
-    launch(h, st, "zero", 0, ne * e, [&] { zero<T>(D.arena, ne, st); });
+    if (D.front_clean && banded_w(h, L, D) > 0) {
+      double zb = (double)L.blk_elems * e;
+      for (const auto& d : L.elim) zb += (double)d.m * (std::min(d.bw, std::max(d.m - 1, 0)) + 1 + d.k) * e;
+      launch(h, st, "zero", 0, zb, [&] {
+        if (L.blk_elems > 0) {
+          const unsigned g = std::min<int64_t>(cdiv(L.blk_elems, sgf::WG), 65536);
+          hipLaunchKernelGGL(sgf::k_zero<T>, dim3(g), dim3(sgf::WG), 0, st, D.arena.as<T>() + L.front_elems,
+                             L.blk_elems);
+        }
+        hipLaunchKernelGGL(sgf::k_zero_band<T>, dim3((unsigned)D.h_band_list.size()), dim3(sgf::WG), 0, st,
+                           D.elim.as<sgf::ElimDesc>(), D.band_list.as<int32_t>(), D.arena.as<T>());
+      }, L.t);
+    } else {
+      launch(h, st, "zero", 0, ne * e, [&] { zero<T>(D.arena, ne, st); }, L.t);
+    }
+    // set again once the banded elimination of this factorization is queued
+    D.front_clean = false;
     launch(h, st, "fill_csr", 0, h->nnz * (16.0 + e), [&] {
       hipLaunchKernelGGL(sgf::k_fill_csr<T>, dim3(cdiv(h->nnz, sgf::WG)), dim3(sgf::WG), 0, st,
                          h->d_vals.as<double>(), h->d_csrdst.as<int64_t>(), h->nnz, D.arena.as<T>());
@@ -1015,6 +1218,7 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
           HIP_CHECK(hipStreamWaitEvent(st, h->ev_join, 0));
         }
       }, L.t);
+      if (li == 0) D.front_clean = true;
     } else if (!L.elim.empty()) {
       int max_m = 0;
       for (const auto& e : L.elim) max_m = std::max(max_m, e.m);
@@ -1183,13 +1387,27 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
       D.tb.ensure(std::max<int64_t>(D.comp_small ? L.tb_elems : toff, 1) * sizeof(T));
       D.c_elems = voff;
     }
-    if (!same_ranks || D.capply_small != D.comp_small) {
-      D.capply_small = D.comp_small;
-      upload(D.capply, L.capply, st);
-      L.t_of_comp.assign(L.comp.size(), -1);
-      for (size_t c = 0, q = 0; c < L.comp.size(); ++c)
-        if (L.rank[c] < L.comp[c].s) L.t_of_comp[c] = L.capply[q++].t_off;
-      upload(D.tofcomp, L.t_of_comp, st);
+    {
+      BatchScope bs(h);
+      if (!same_ranks || D.capply_small != D.comp_small) {
+        D.capply_small = D.comp_small;
+        upload(h, D.capply, L.capply, st);
+        L.t_of_comp.assign(L.comp.size(), -1);
+        for (size_t c = 0, q = 0; c < L.comp.size(); ++c)
+          if (L.rank[c] < L.comp[c].s) L.t_of_comp[c] = L.capply[q++].t_off;
+        upload(h, D.tofcomp, L.t_of_comp, st);
+      }
+      // pairs that touch a compressed separator (their coarse couplings)
+      if (!L.capply.empty() && !same_ranks) {
+        L.active_pairs.clear();
+        for (size_t p = 0; p < L.pairs.size(); ++p) {
+          const auto& pd = L.pairs[p];
+          const bool ca = pd.ca >= 0 && L.rank[pd.ca] < pd.s_a, cb = pd.cb >= 0 && L.rank[pd.cb] < pd.s_b;
+          if (ca || cb) L.active_pairs.push_back((int32_t)p);
+        }
+        upload(h, D.active, L.active_pairs, st);
+      }
+      bs.flush(st);
     }
     if (!L.capply.empty() && !D.comp_small) {
       double fl = 0;
@@ -1204,15 +1422,6 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
     }
     // coarse couplings, only for the pairs that touch a compressed separator
     if (!L.capply.empty()) {
-      if (!same_ranks) {
-        L.active_pairs.clear();
-        for (size_t p = 0; p < L.pairs.size(); ++p) {
-          const auto& pd = L.pairs[p];
-          const bool ca = pd.ca >= 0 && L.rank[pd.ca] < pd.s_a, cb = pd.cb >= 0 && L.rank[pd.cb] < pd.s_b;
-          if (ca || cb) L.active_pairs.push_back((int32_t)p);
-        }
-        upload(D.active, L.active_pairs, st);
-      }
       launch(h, st, "pair", 0, 0, [&] {
         hipLaunchKernelGGL(sgf::k_pair<T>, dim3((unsigned)L.active_pairs.size()), dim3(sgf::WG), 0, st,
                            D.pairs.as<sgf::PairDesc>(), D.active.as<int32_t>(), D.rank.as<int>(),
@@ -1222,19 +1431,23 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
     account_level(h, L, D.work);
     h->trace.mark("compressed-separator work queued", L.t);
     // ---- coarsen (Secs. 4.3-4.4) ----------------------------------------------
-    if (!same_ranks) {
-      P.levels.resize(li + 1);
-      P.parts.resize(li + 1);
-      for (size_t q = li + 1; q < h->lev.size(); ++q) h->lev[q].uploaded = false;
-      P.max_node = 0;
-      for (int q = 0; q <= li; ++q)
-        for (int sz : P.levels[q].size) P.max_node = std::max<int64_t>(P.max_node, sz);
-      sgf::plan_next_level(P, D.h_blkmap, D.h_phimap);
-      h->trace.mark("next level planned (host)", li + 1);
-      upload(D.blkmap, D.h_blkmap, st);
-      upload(D.phimap, D.h_phimap, st);
+    {
+      BatchScope bs(h);
+      if (!same_ranks) {
+        P.levels.resize(li + 1);
+        P.parts.resize(li + 1);
+        for (size_t q = li + 1; q < h->lev.size(); ++q) h->lev[q].uploaded = false;
+        P.max_node = 0;
+        for (int q = 0; q <= li; ++q)
+          for (int sz : P.levels[q].size) P.max_node = std::max<int64_t>(P.max_node, sz);
+        sgf::plan_next_level(P, D.h_blkmap, D.h_phimap);
+        h->trace.mark("next level planned (host)", li + 1);
+        upload(h, D.blkmap, D.h_blkmap, st);
+        upload(h, D.phimap, D.h_phimap, st);
+      }
+      upload_level(h, li + 1, st);
+      bs.flush(st);
     }
-    upload_level(h, li + 1, st);
     h->trace.mark(same_ranks ? "next level reused" : "next level uploaded", li + 1);
     sgf::Level& N = P.levels[li + 1];
     LevelDev& E = h->lev[li + 1];

@@ -447,6 +447,46 @@ def test_banded_elimination_matches_panel_elimination_and_oracle(kind, grid, lea
         assert _rel(out[True], za) <= 1e-3
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_refactorization_clears_only_the_band_and_matches_a_fresh_handle(prec):
+    """Refactorizing one handle with other coefficients: while the level-1
+    fronts are known clean outside the band, the banded path clears only
+    the lower band and M_SI of each front (and the pair blocks); the result
+    is bitwise that of a fresh handle, also after a factorization through
+    the panel path has written the fronts (the next banded one clears them
+    all again)."""
+    pa, pb = _prob("fourier", (100, 90), seed=0), _prob("fourier", (100, 90), seed=1)
+    pr = sgf.FP64 if prec == "fp64" else sgf.FP32
+    V = np.stack([P.random_rhs(5, pa.n, j) for j in range(2)], axis=1)
+    vals = {"a": torch.from_numpy(pa.data).cuda(), "b": torch.from_numpy(pb.data).cuda()}
+    ref = {}
+    for key in "ab":
+        s = sgf.Solver.from_problem(pa, q=2, leaf=16, precision=pr)
+        s.factorize(vals[key])
+        ref[key] = _apply(s, V)
+        s.close()
+    s = sgf.Solver.from_problem(pa, q=2, leaf=16, precision=pr)
+    zb = []
+    for key, banded in (("a", True), ("b", True), ("a", True), ("b", False), ("a", True), ("b", True)):
+        s.set_band_elim(banded)
+        s.profile(True)
+        s.factorize(vals[key])
+        out = _apply(s, V)
+        st = s.profile_read()
+        s.profile(False)
+        assert ("elim_banded" in st) == banded
+        zb.append(st["zero@L1"]["bytes"])
+        if banded:
+            assert np.array_equal(out, ref[key]), (key, _rel(out, ref[key]))
+        else:
+            assert _rel(out, ref[key]) <= (1e-12 if prec == "fp64" else 1e-4)
+    # full clears: the first factorization, the panel one and the banded one
+    # after it; band-only clears in between
+    print("cleared bytes per factorization:", zb)
+    assert zb[0] == zb[3] == zb[4]
+    assert zb[1] == zb[2] == zb[5] < zb[0] / 2
+
+
 def test_banded_elimination_reports_non_spd_cluster():
     """A non-positive pivot inside a banded front is reported with its cluster."""
     p = _prob("const", (64, 64))
