@@ -1434,13 +1434,17 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
     {
       BatchScope bs(h);
       if (!same_ranks) {
-        P.levels.resize(li + 1);
-        P.parts.resize(li + 1);
         for (size_t q = li + 1; q < h->lev.size(); ++q) h->lev[q].uploaded = false;
         P.max_node = 0;
         for (int q = 0; q <= li; ++q)
           for (int sz : P.levels[q].size) P.max_node = std::max<int64_t>(P.max_node, sz);
-        sgf::plan_next_level(P, D.h_blkmap, D.h_phimap);
+        // the next level's structure does not depend on the ranks: when it
+        // has been planned before, only its sizes and offsets are redone
+        if (!sgf::update_next_level(P, (size_t)li, D.h_blkmap, D.h_phimap)) {
+          P.levels.resize(li + 1);
+          P.parts.resize(li + 1);
+          sgf::plan_next_level(P, D.h_blkmap, D.h_phimap);
+        }
         h->trace.mark("next level planned (host)", li + 1);
         upload(h, D.blkmap, D.h_blkmap, st);
         upload(h, D.phimap, D.h_phimap, st);

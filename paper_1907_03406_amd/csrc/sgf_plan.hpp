@@ -237,6 +237,25 @@ struct Level {
   std::vector<int64_t> t_of_comp;          // offset of T_B per compression (-1: not compressed)
   std::vector<CompApply> capply;
   int64_t n_active = 0;
+  // structure recorded by build_level, from which build_offsets re-derives
+  // every size-dependent field when only the cluster sizes change
+  std::vector<int32_t> schur_ii;             // per Schur entry: interior index
+  std::vector<int64_t> schur_ex, schur_ey;   //   and its adjacency entries x <= y
+  std::vector<int32_t> cnbr_x, cnbr_pid;     // per compression neighbour: cluster, pair id
+  std::vector<int32_t> pair_rowa, pair_rowb; // per pair: neighbour entry giving row_in_a / row_in_b (-1: none)
+  std::vector<int32_t> sacc_p;               // per SepAcc: separator position
+  std::vector<int32_t> sacc_ii;              // per sepacc_src entry: interior index
+  std::vector<int64_t> sacc_e;               //   and adjacency entry
+  // levels above the first: where the separators of the level below go
+  // (father before a top merge) and where each pair block of the level below
+  // is copied (kind, interior index or pair id, adjacency entry of the row)
+  std::vector<int32_t> from_father;
+  int32_t from_nfathers = 0;
+  bool from_merged = false;
+  std::vector<int8_t> cp_kind;
+  std::vector<int32_t> cp_tgt;
+  std::vector<int64_t> cp_e;
+  bool can_update = false;
 
   int32_t post_size(int c) const {
     int ci = comp_of.empty() ? -1 : comp_of[c];
@@ -428,6 +447,9 @@ inline void build_level(Level& L, const Options& o, int pi) {
       cnt[p + 1] += cnt[p];
     }
     L.schur.assign(pid_of.size(), SchurDesc{});
+    L.schur_ii.assign(pid_of.size(), 0);
+    L.schur_ex.assign(pid_of.size(), 0);
+    L.schur_ey.assign(pid_of.size(), 0);
     std::vector<int32_t> cur(L.pairs.size());
     for (size_t p = 0; p < L.pairs.size(); ++p) cur[p] = L.pairs[p].c_ptr;
     size_t q = 0;
@@ -441,7 +463,11 @@ inline void build_level(Level& L, const Options& o, int pi) {
           sd.src_ld = (int32_t)ld;
           sd.diag = x == y;
           sd.src_off = e.front_off + (e.m + L.nbr_off[y]) + (int64_t)(e.m + L.nbr_off[x]) * ld;
-          L.schur[cur[pid_of[q++]]++] = sd;
+          const int32_t at = cur[pid_of[q++]]++;
+          L.schur[at] = sd;
+          L.schur_ii[at] = ii;
+          L.schur_ex[at] = x;
+          L.schur_ey[at] = y;
         }
     }
   }
@@ -455,6 +481,8 @@ inline void build_level(Level& L, const Options& o, int pi) {
   // ---- compressions --------------------------------------------------------------
   L.comp.clear();
   L.comp_nbr.clear();
+  L.cnbr_x.clear();
+  L.cnbr_pid.clear();
   L.comp_of.assign(nc, -1);
   L.cf_elems = L.n_elems = L.ltphi_elems = L.tau_elems = L.tb_elems = 0;
   L.max_cf_rows = L.max_c = L.max_s = 0;
@@ -481,6 +509,8 @@ inline void build_level(Level& L, const Options& o, int pi) {
         nbx.row = d.s + K;
         K += L.size[X];
         L.comp_nbr.push_back(nbx);
+        L.cnbr_x.push_back(X);
+        L.cnbr_pid.push_back(pid);
       }
       d.K = K;
       d.c = pi * (1 + d.nnb);
@@ -505,19 +535,24 @@ inline void build_level(Level& L, const Options& o, int pi) {
     }
   }
   // pair descriptors: compression indices and rows inside the fronts
-  for (auto& pd : L.pairs) {
+  L.pair_rowa.assign(L.pairs.size(), -1);
+  L.pair_rowb.assign(L.pairs.size(), -1);
+  for (size_t p = 0; p < L.pairs.size(); ++p) {
+    PairDesc& pd = L.pairs[p];
     pd.ca = L.comp_of[pd.a];
     pd.cb = L.comp_of[pd.b];
     if (pd.a != pd.b) {
       if (pd.ca >= 0) {
         const CompDesc& d = L.comp[pd.ca];
         const int64_t e = L.sadj_find(pd.a, pd.b);
-        pd.row_in_a = L.comp_nbr[d.nb_ptr + (e - L.sadj_ptr[L.sep_pos[pd.a]])].row;
+        L.pair_rowa[p] = (int32_t)(d.nb_ptr + (e - L.sadj_ptr[L.sep_pos[pd.a]]));
+        pd.row_in_a = L.comp_nbr[L.pair_rowa[p]].row;
       }
       if (pd.cb >= 0) {
         const CompDesc& d = L.comp[pd.cb];
         const int64_t e = L.sadj_find(pd.b, pd.a);
-        pd.row_in_b = L.comp_nbr[d.nb_ptr + (e - L.sadj_ptr[L.sep_pos[pd.b]])].row;
+        L.pair_rowb[p] = (int32_t)(d.nb_ptr + (e - L.sadj_ptr[L.sep_pos[pd.b]]));
+        pd.row_in_b = L.comp_nbr[L.pair_rowb[p]].row;
       }
     }
   }
@@ -530,16 +565,24 @@ inline void build_level(Level& L, const Options& o, int pi) {
     }
     std::vector<int32_t> start(ns + 1, 0);
     for (int p = 0; p < ns; ++p) start[p + 1] = start[p] + cnt[p + 1];
-    std::vector<int64_t> flat(start[ns]);
+    std::vector<int64_t> flat(start[ns]), flat_e(start[ns]);
+    std::vector<int32_t> flat_ii(start[ns]);
     std::vector<int32_t> cur(start.begin(), start.end() - 1);
     for (int ii = 0; ii < ni; ++ii) {
       const int I = L.interiors[ii];
-      for (int64_t e = L.adj_ptr[I]; e < L.adj_ptr[I + 1]; ++e)
-        flat[cur[L.sep_pos[L.adj_idx[e]]]++] = L.elim[ii].t_off + L.nbr_off[e];
+      for (int64_t e = L.adj_ptr[I]; e < L.adj_ptr[I + 1]; ++e) {
+        const int32_t at = cur[L.sep_pos[L.adj_idx[e]]]++;
+        flat[at] = L.elim[ii].t_off + L.nbr_off[e];
+        flat_ii[at] = ii;
+        flat_e[at] = e;
+      }
     }
     L.sepacc.clear();
     L.sepacc_src.clear();
     L.sepacc_src.reserve(flat.size());
+    L.sacc_p.clear();
+    L.sacc_ii.clear();
+    L.sacc_e.clear();
     for (int p = 0; p < ns; ++p) {
       if (start[p + 1] == start[p]) continue;
       SepAcc sa{};
@@ -548,9 +591,130 @@ inline void build_level(Level& L, const Options& o, int pi) {
       sa.c_ptr = (int32_t)L.sepacc_src.size();
       sa.c_cnt = start[p + 1] - start[p];
       L.sepacc_src.insert(L.sepacc_src.end(), flat.begin() + start[p], flat.begin() + start[p + 1]);
+      L.sacc_ii.insert(L.sacc_ii.end(), flat_ii.begin() + start[p], flat_ii.begin() + start[p + 1]);
+      L.sacc_e.insert(L.sacc_e.end(), flat_e.begin() + start[p], flat_e.begin() + start[p + 1]);
       L.sepacc.push_back(sa);
+      L.sacc_p.push_back(p);
     }
   }
+  L.rank.clear();
+  L.capply.clear();
+}
+
+// Every size-dependent field of a level whose structure build_level has
+// recorded, from its current cluster sizes: the same values build_level
+// gives for these sizes, without its adjacency searches and sorts.
+inline void build_offsets(Level& L, int pi) {
+  const int nc = (int)L.cell.size();
+  L.n_active = 0;
+  for (int c = 0; c < nc; ++c) L.n_active += L.size[c];
+  // interiors
+  L.front_elems = 0;
+  L.t_elems = 0;
+  L.max_front_rows = 0;
+  int64_t total_k = 0;
+  for (size_t ii = 0; ii < L.interiors.size(); ++ii) {
+    const int I = L.interiors[ii];
+    ElimDesc& d = L.elim[ii];
+    d.m = L.size[I];
+    d.bw = d.m;
+    d.pk_off = -1;
+    int k = 0;
+    for (int64_t e = L.adj_ptr[I]; e < L.adj_ptr[I + 1]; ++e) {
+      L.nbr_off[e] = k;
+      k += L.size[L.adj_idx[e]];
+    }
+    d.k = k;
+    d.front_off = L.front_elems;
+    const int64_t R = (int64_t)d.m + k;
+    L.front_elems += R * R;
+    L.max_front_rows = std::max<int32_t>(L.max_front_rows, (int32_t)R);
+    d.slot_off = L.slot_ptr[I];
+    d.nslot_off = total_k;
+    d.t_off = L.t_elems;
+    L.t_elems += k;
+    total_k += k;
+  }
+  L.nslots.resize(total_k);
+  for (size_t ii = 0; ii < L.interiors.size(); ++ii) {
+    const int I = L.interiors[ii];
+    int64_t q = L.elim[ii].nslot_off;
+    for (int64_t e = L.adj_ptr[I]; e < L.adj_ptr[I + 1]; ++e) {
+      const int X = L.adj_idx[e];
+      for (int64_t s = L.slot_ptr[X]; s < L.slot_ptr[X + 1]; ++s) L.nslots[q++] = L.slots[s];
+    }
+  }
+  // pair blocks, in pair order
+  L.blk_elems = 0;
+  L.scratch_elems = 0;
+  for (PairDesc& d : L.pairs) {
+    d.s_a = L.size[d.a];
+    d.s_b = L.size[d.b];
+    d.blk_off = L.blk_elems;
+    L.blk_elems += (int64_t)d.s_a * d.s_b;
+    d.scratch_off = L.scratch_elems;
+    L.scratch_elems += 2 * (int64_t)d.s_a * d.s_b;
+  }
+  // Schur sources
+  for (size_t q = 0; q < L.schur.size(); ++q) {
+    const ElimDesc& e = L.elim[L.schur_ii[q]];
+    const int64_t ld = (int64_t)e.m + e.k;
+    L.schur[q].src_ld = (int32_t)ld;
+    L.schur[q].src_off = e.front_off + (e.m + L.nbr_off[L.schur_ey[q]]) + (e.m + L.nbr_off[L.schur_ex[q]]) * ld;
+  }
+  // Phi per cluster
+  L.phi_elems = 0;
+  for (int c = 0; c < nc; ++c) {
+    L.phi_off[c] = L.phi_elems;
+    L.phi_elems += (int64_t)L.size[c] * pi;
+  }
+  // compressions
+  L.cf_elems = L.n_elems = L.ltphi_elems = L.tau_elems = L.tb_elems = 0;
+  L.max_cf_rows = L.max_c = L.max_s = 0;
+  for (CompDesc& d : L.comp) {
+    const int B = d.cluster;
+    d.s = L.size[B];
+    int K = 0;
+    for (int q = 0; q < d.nnb; ++q) {
+      const int at = d.nb_ptr + q;
+      CompNbr& nbx = L.comp_nbr[at];
+      const int X = L.cnbr_x[at];
+      nbx.blk_off = L.pairs[L.cnbr_pid[at]].blk_off;
+      nbx.s_x = L.size[X];
+      nbx.phi_off = L.phi_off[X];
+      nbx.row = d.s + K;
+      K += L.size[X];
+    }
+    d.K = K;
+    d.cf_off = L.cf_elems;
+    L.cf_elems += (int64_t)(d.s + K) * d.s;
+    d.n_off = L.n_elems;
+    L.n_elems += (int64_t)d.s * d.c;
+    d.ltphi_off = L.ltphi_elems;
+    L.ltphi_elems += (int64_t)d.s * pi;
+    d.tau_off = L.tau_elems;
+    L.tau_elems += d.c;
+    d.tb_off = L.tb_elems;
+    L.tb_elems += (int64_t)d.s * d.s;
+    d.phi_off = L.phi_off[B];
+    d.slot_off = L.slot_ptr[B];
+    d.blk_diag = L.pairs[L.pair_diag[L.sep_pos[B]]].blk_off;
+    L.max_cf_rows = std::max<int32_t>(L.max_cf_rows, d.s + K);
+    L.max_c = std::max<int32_t>(L.max_c, d.c);
+    L.max_s = std::max<int32_t>(L.max_s, d.s);
+  }
+  for (size_t p = 0; p < L.pairs.size(); ++p) {
+    if (L.pair_rowa[p] >= 0) L.pairs[p].row_in_a = L.comp_nbr[L.pair_rowa[p]].row;
+    if (L.pair_rowb[p] >= 0) L.pairs[p].row_in_b = L.comp_nbr[L.pair_rowb[p]].row;
+  }
+  // apply: separator accumulation
+  for (size_t a = 0; a < L.sepacc.size(); ++a) {
+    const int B = L.seps[L.sacc_p[a]];
+    L.sepacc[a].slot_off = L.slot_ptr[B];
+    L.sepacc[a].s = L.size[B];
+  }
+  for (size_t j = 0; j < L.sepacc_src.size(); ++j)
+    L.sepacc_src[j] = L.elim[L.sacc_ii[j]].t_off + L.nbr_off[L.sacc_e[j]];
   L.rank.clear();
   L.capply.clear();
 }
@@ -749,6 +913,94 @@ inline void plan_level1(Plan& P, const int64_t* row_ptr, const int32_t* col_idx)
   P.levels.push_back(std::move(L));
 }
 
+// Copy maps from level C to the next level N: the coarse part (ld s_a) of
+// every level-C pair block into N's storage (where N.cp_kind says), and the
+// Phi rows of every surviving separator into its father's Phi.  `father`
+// and `loc`: each separator's father in N and its first row there.
+inline void emit_copy_maps(const Level& C, const Level& N, const std::vector<int32_t>& father,
+                           const std::vector<int32_t>& loc, int pi, std::vector<CopyDesc>& blk_map,
+                           std::vector<CopyDesc>& phi_map) {
+  blk_map.clear();
+  phi_map.clear();
+  blk_map.reserve(2 * C.pairs.size());
+  for (size_t q = 0; q < C.pairs.size(); ++q) {
+    const PairDesc& pd = C.pairs[q];
+    const int pa = C.sep_pos[pd.a], pb = C.sep_pos[pd.b];
+    const int ra = C.post_size(pd.a), rb = C.post_size(pd.b);
+    if (ra == 0 || rb == 0) continue;
+    const int oa = loc[pa], ob = loc[pb];
+    CopyDesc cd{};
+    cd.src_off = C.front_elems + pd.blk_off;
+    cd.src_ld = pd.s_a;
+    cd.rows = ra;
+    cd.cols = rb;
+    const int kind = N.cp_kind[q], tg = N.cp_tgt[q];
+    if (kind == 0 || kind == 1) {
+      int64_t base, ld;
+      if (kind == 0) {
+        const ElimDesc& e = N.elim[tg];
+        base = e.front_off;
+        ld = (int64_t)e.m + e.k;
+      } else {
+        const PairDesc& p2 = N.pairs[tg];
+        base = N.front_elems + p2.blk_off;
+        ld = p2.s_a;
+      }
+      cd.dst_ld = (int32_t)ld;
+      cd.mode = 0;
+      cd.dst_off = base + oa + (int64_t)ob * ld;
+      blk_map.push_back(cd);
+      if (pd.a != pd.b) {
+        cd.mode = 1;
+        cd.dst_off = base + ob + (int64_t)oa * ld;
+        blk_map.push_back(cd);
+      }
+    } else if (kind == 2 || kind == 3) {
+      const ElimDesc& e = N.elim[tg];
+      const int64_t ld = (int64_t)e.m + e.k;
+      const int64_t row = e.m + N.nbr_off[N.cp_e[q]];
+      cd.dst_ld = (int32_t)ld;
+      if (kind == 2) {
+        cd.mode = 1;
+        cd.dst_off = e.front_off + (row + ob) + (int64_t)oa * ld;
+      } else {
+        cd.mode = 0;
+        cd.dst_off = e.front_off + (row + oa) + (int64_t)ob * ld;
+      }
+      blk_map.push_back(cd);
+    } else {
+      const PairDesc& p2 = N.pairs[tg];
+      cd.dst_ld = p2.s_a;
+      if (kind == 4) {
+        cd.mode = 0;
+        cd.dst_off = N.front_elems + p2.blk_off + oa + (int64_t)ob * p2.s_a;
+      } else {
+        cd.mode = 1;
+        cd.dst_off = N.front_elems + p2.blk_off + ob + (int64_t)oa * p2.s_a;
+      }
+      blk_map.push_back(cd);
+    }
+  }
+  if (!N.top) {
+    phi_map.reserve(C.seps.size());
+    for (size_t p = 0; p < C.seps.size(); ++p) {
+      const int a = C.seps[p];
+      const int r = C.post_size(a);
+      if (r == 0) continue;
+      CopyDesc cd{};
+      cd.src_off = C.phi_off[a];
+      cd.src_ld = C.size[a];
+      cd.rows = r;
+      cd.cols = pi;
+      cd.mode = 0;
+      const int D = father[p];
+      cd.dst_ld = N.size[D];
+      cd.dst_off = N.phi_off[D] + loc[p];
+      phi_map.push_back(cd);
+    }
+  }
+}
+
 // Next level from the current one once its ranks are known (Secs. 4.3-4.4).
 // Returns the copy maps for the pair blocks and for Phi.
 inline void plan_next_level(Plan& P, std::vector<CopyDesc>& blk_map, std::vector<CopyDesc>& phi_map) {
@@ -791,6 +1043,9 @@ inline void plan_next_level(Plan& P, std::vector<CopyDesc>& blk_map, std::vector
   }
   P.max_node = std::max<int64_t>(P.max_node, biggest);
   bool top = hi.is_root || (o.stop_rule == 1 && n_active < P.max_node);
+  N.from_father = father;
+  N.from_nfathers = nc;
+  N.from_merged = top && nc > 1;
   if (top && nc > 1) {
     // merge every cluster of the new partition into one, ascending cell id
     std::vector<int32_t> base(nc, 0);
@@ -846,93 +1101,114 @@ inline void plan_next_level(Plan& P, std::vector<CopyDesc>& blk_map, std::vector
     }
   }
   build_level(N, o, P.pi);
-  // copy maps: level-C pair blocks (coarse part, ld s_a) -> level-N storage
-  blk_map.clear();
-  phi_map.clear();
-  blk_map.reserve(2 * C.pairs.size());
-  for (const PairDesc& pd : C.pairs) {
-    const int pa = C.sep_pos[pd.a], pb = C.sep_pos[pd.b];
-    const int ra = C.post_size(pd.a), rb = C.post_size(pd.b);
-    if (ra == 0 || rb == 0) continue;
-    const int Da = father[pa], Db = father[pb];
-    const int oa = loc[pa], ob = loc[pb];
-    CopyDesc cd{};
-    cd.src_off = C.front_elems + pd.blk_off;
-    cd.src_ld = pd.s_a;
-    cd.rows = ra;
-    cd.cols = rb;
+  // where each level-C pair block goes (by the new level's structure)
+  const int ncp = (int)C.pairs.size();
+  N.cp_kind.assign(ncp, -1);
+  N.cp_tgt.assign(ncp, -1);
+  N.cp_e.assign(ncp, -1);
+  auto adj_entry = [&](int I, int X) {
+    const int32_t* lo = N.adj_idx.data() + N.adj_ptr[I];
+    const int32_t* hi2 = N.adj_idx.data() + N.adj_ptr[I + 1];
+    const int32_t* it = std::lower_bound(lo, hi2, X);
+    if (it == hi2 || *it != X) throw std::runtime_error("plan check failed: neighbour not adjacent");
+    return (int64_t)(it - N.adj_idx.data());
+  };
+  auto pair_of = [&](int a, int b) {
+    const int32_t q = N.find_pair(a, b);
+    if (q < 0) throw std::runtime_error("plan check failed: missing pair block");
+    return q;
+  };
+  for (int q = 0; q < ncp; ++q) {
+    const PairDesc& pd = C.pairs[q];
+    const int Da = father[C.sep_pos[pd.a]], Db = father[C.sep_pos[pd.b]];
     if (Da == Db) {
-      int64_t base, ld;
       if (N.elim_of[Da] >= 0) {
-        const ElimDesc& e = N.elim[N.elim_of[Da]];
-        base = e.front_off;
-        ld = (int64_t)e.m + e.k;
+        N.cp_kind[q] = 0;
+        N.cp_tgt[q] = N.elim_of[Da];
       } else {
-        const PairDesc& q = N.pairs[N.pair_diag[N.sep_pos[Da]]];
-        base = N.front_elems + q.blk_off;
-        ld = q.s_a;
-      }
-      cd.dst_ld = (int32_t)ld;
-      cd.mode = 0;
-      cd.dst_off = base + oa + (int64_t)ob * ld;
-      blk_map.push_back(cd);
-      if (pd.a != pd.b) {
-        cd.mode = 1;
-        cd.dst_off = base + ob + (int64_t)oa * ld;
-        blk_map.push_back(cd);
+        N.cp_kind[q] = 1;
+        N.cp_tgt[q] = N.pair_diag[N.sep_pos[Da]];
       }
     } else if (N.elim_of[Da] >= 0) {
-      const ElimDesc& e = N.elim[N.elim_of[Da]];
-      const int64_t ld = (int64_t)e.m + e.k;
-      cd.dst_ld = (int32_t)ld;
-      cd.mode = 1;
-      cd.dst_off = e.front_off + (N.front_row(Da, Db) + ob) + (int64_t)oa * ld;
-      blk_map.push_back(cd);
+      N.cp_kind[q] = 2;
+      N.cp_tgt[q] = N.elim_of[Da];
+      N.cp_e[q] = adj_entry(Da, Db);
     } else if (N.elim_of[Db] >= 0) {
-      const ElimDesc& e = N.elim[N.elim_of[Db]];
-      const int64_t ld = (int64_t)e.m + e.k;
-      cd.dst_ld = (int32_t)ld;
-      cd.mode = 0;
-      cd.dst_off = e.front_off + (N.front_row(Db, Da) + oa) + (int64_t)ob * ld;
-      blk_map.push_back(cd);
+      N.cp_kind[q] = 3;
+      N.cp_tgt[q] = N.elim_of[Db];
+      N.cp_e[q] = adj_entry(Db, Da);
+    } else if (Da < Db) {
+      N.cp_kind[q] = 4;
+      N.cp_tgt[q] = pair_of(Da, Db);
     } else {
-      if (Da < Db) {
-        const PairDesc& q = N.pairs[N.find_pair(Da, Db)];
-        cd.dst_ld = q.s_a;
-        cd.mode = 0;
-        cd.dst_off = N.front_elems + q.blk_off + oa + (int64_t)ob * q.s_a;
-      } else {
-        const PairDesc& q = N.pairs[N.find_pair(Db, Da)];
-        cd.dst_ld = q.s_a;
-        cd.mode = 1;
-        cd.dst_off = N.front_elems + q.blk_off + ob + (int64_t)oa * q.s_a;
-      }
-      blk_map.push_back(cd);
+      N.cp_kind[q] = 5;
+      N.cp_tgt[q] = pair_of(Db, Da);
     }
   }
-  if (!N.top) {
-    phi_map.reserve(cs);
-    for (int p = 0; p < cs; ++p) {
-      const int a = C.seps[p];
-      const int r = C.post_size(a);
-      if (r == 0) continue;
-      CopyDesc cd{};
-      cd.src_off = C.phi_off[a];
-      cd.src_ld = C.size[a];
-      cd.rows = r;
-      cd.cols = P.pi;
-      cd.mode = 0;
-      const int D = father[p];
-      cd.dst_ld = N.size[D];
-      cd.dst_off = N.phi_off[D] + loc[p];
-      phi_map.push_back(cd);
-    }
-  }
+  N.can_update = true;
+  emit_copy_maps(C, N, father, loc, P.pi, blk_map, phi_map);
   validate_level(N, P.n, P.pi);
   validate_copies(blk_map, C.front_elems + C.blk_elems, N.front_elems + N.blk_elems);
   validate_copies(phi_map, C.phi_elems, N.phi_elems);
   P.parts.push_back(hi);
   P.levels.push_back(std::move(N));
+}
+
+// The next level re-planned in place for new ranks of level li: its
+// clusters, adjacency, pairs and the order of every list depend only on the
+// partition (with the fixed top rule), so only the sizes, slots and the
+// offsets derived from them change.  Gives the same level and copy maps as
+// plan_next_level for these ranks; false when the recorded structure cannot
+// be used (no next level yet, or the rank-dependent top rule).
+inline bool update_next_level(Plan& P, size_t li, std::vector<CopyDesc>& blk_map,
+                              std::vector<CopyDesc>& phi_map) {
+  if (P.opt.stop_rule != 0 || li + 1 >= P.levels.size()) return false;
+  Level& C = P.levels[li];
+  Level& N = P.levels[li + 1];
+  const int cs = (int)C.seps.size();
+  if (!N.can_update || (int)N.from_father.size() != cs || N.cp_kind.size() != C.pairs.size()) return false;
+  C.planned_rank = C.rank;
+  const int nf = N.from_nfathers;
+  std::vector<int32_t> loc(cs), father(cs), fsize(nf, 0);
+  for (int p = 0; p < cs; ++p) {
+    loc[p] = fsize[N.from_father[p]];
+    fsize[N.from_father[p]] += C.post_size(C.seps[p]);
+  }
+  int64_t n_active = 0, biggest = 0;
+  for (int c = 0; c < nf; ++c) {
+    n_active += fsize[c];
+    biggest = std::max<int64_t>(biggest, fsize[c]);
+  }
+  P.max_node = std::max<int64_t>(P.max_node, biggest);
+  if (N.from_merged) {
+    std::vector<int32_t> base(nf, 0);
+    for (int c = 1; c < nf; ++c) base[c] = base[c - 1] + fsize[c - 1];
+    for (int p = 0; p < cs; ++p) {
+      loc[p] += base[N.from_father[p]];
+      father[p] = 0;
+    }
+    N.size.assign(1, (int32_t)n_active);
+  } else {
+    father = N.from_father;
+    N.size = fsize;
+  }
+  const int nc2 = (int)N.cell.size();
+  if ((int)N.size.size() != nc2) return false;
+  N.slot_ptr.assign(nc2 + 1, 0);
+  for (int c = 0; c < nc2; ++c) N.slot_ptr[c + 1] = N.slot_ptr[c] + N.size[c];
+  N.slots.assign(N.slot_ptr[nc2], 0);
+  for (int p = 0; p < cs; ++p) {
+    const int a = C.seps[p];
+    const int r = C.post_size(a);
+    std::copy(C.slots.begin() + C.slot_ptr[a], C.slots.begin() + C.slot_ptr[a] + r,
+              N.slots.begin() + N.slot_ptr[father[p]] + loc[p]);
+  }
+  build_offsets(N, P.pi);
+  emit_copy_maps(C, N, father, loc, P.pi, blk_map, phi_map);
+  validate_level(N, P.n, P.pi);
+  validate_copies(blk_map, C.front_elems + C.blk_elems, N.front_elems + N.blk_elems);
+  validate_copies(phi_map, C.phi_elems, N.phi_elems);
+  return true;
 }
 
 }  // namespace sgf

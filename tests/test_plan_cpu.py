@@ -4,6 +4,8 @@ oracle's partition hierarchy bit for bit (cells, types, active-set sizes and
 the level-1 permutation), given the oracle's compression ranks."""
 import os
 import re
+import shutil
+import subprocess
 
 import numpy as np
 import pytest
@@ -101,3 +103,19 @@ def test_memory_estimate_is_host_only():
     s.release()
     s.plan_dry_run(lambda t, cell, size: min(size, 3))
     assert s.info()["levels"] >= 2 and s.info()["device_bytes"] == 0
+
+
+def test_in_place_replanning_matches_planning_afresh(tmp_path):
+    """The next level re-planned in place for new ranks (only sizes, slots
+    and offsets redone) equals the level planned afresh with those ranks,
+    copy maps included, on 2D and 3D grids: a C++ check of the planner
+    header built with the host compiler."""
+    cxx = shutil.which("g++") or shutil.which("c++")
+    if not cxx:
+        pytest.skip("no host C++ compiler")
+    exe = str(tmp_path / "plan_update_check")
+    subprocess.run([cxx, "-O2", "-std=c++17", "-I", os.path.join(ROOT, "paper_1907_03406_amd", "csrc"),
+                    os.path.join(ROOT, "tests", "cpp", "plan_update_check.cpp"), "-o", exe], check=True, timeout=300)
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=300)
+    print(r.stdout)
+    assert r.returncode == 0 and r.stdout.strip().endswith("ok"), r.stdout + r.stderr
