@@ -146,14 +146,16 @@ template <typename T>
 __global__ __launch_bounds__(WG) void k_zero_band(const ElimDesc* __restrict__ D, const int32_t* __restrict__ list,
                                                   T* __restrict__ arena) {
   const ElimDesc d = D[list[blockIdx.x]];
-  const int m = d.m, k = d.k, bw = min(d.bw, max(m - 1, 0)), per = bw + 1 + k;
+  const int m = d.m, k = d.k, bw = min(d.bw, max(m - 1, 0));
   const int64_t R = (int64_t)m + k;
   T* C = arena + d.front_off;
-  const int64_t tot = (int64_t)m * per;
-  for (int64_t idx = threadIdx.x; idx < tot; idx += WG) {
-    const int c = (int)(idx / per), r = (int)(idx % per);
-    const int row = r <= bw ? c + r : m + (r - bw - 1);
-    if (row < R && (r > bw || c + r < m)) C[row + (int64_t)c * R] = T(0);
+  const int lane = threadIdx.x % WAVE;
+  // one column per wavefront at a time: its band segment, then its M_SI rows
+  for (int c = threadIdx.x / WAVE; c < m; c += WG / WAVE) {
+    T* col = C + (int64_t)c * R;
+    const int nb = min(bw, m - 1 - c) + 1;
+    for (int r = lane; r < nb; r += WAVE) col[c + r] = T(0);
+    for (int r = lane; r < k; r += WAVE) col[m + r] = T(0);
   }
 }
 
@@ -576,11 +578,13 @@ __global__ __launch_bounds__(WAVE) void k_elim_banded(const ElimDesc* __restrict
   const bool srow = lane < k;
   const T* msi = C + m + lane;
   T* lsi = C + m + lane;
-  T x[W], mnext[W];
+  // mcur: this lane's M_SI row over the current block's columns (loaded
+  // for the next block as soon as phase 2 is done with it)
+  T x[W], mcur[W];
 #pragma unroll
   for (int t = 0; t < W; ++t) {
     x[t] = T(0);
-    mnext[t] = (srow && t < m) ? msi[(int64_t)t * R] : T(0);
+    mcur[t] = (srow && t < m) ? msi[(int64_t)t * R] : T(0);
   }
   constexpr int KT = BE_KMAX / 16, NT = KT * (KT + 1) / 2;
   const int kt = (k + 15) / 16;
@@ -599,13 +603,6 @@ __global__ __launch_bounds__(WAVE) void k_elim_banded(const ElimDesc* __restrict
       __builtin_amdgcn_wave_barrier();
       store_cols(b + 1, pre);
       if (b + 2 < nblk) load_cols(b + 2, pre);
-    }
-    T mcur[W];
-#pragma unroll
-    for (int t = 0; t < W; ++t) {
-      mcur[t] = mnext[t];
-      const int jn = j0 + W + t;
-      mnext[t] = (srow && jn < m) ? msi[(int64_t)jn * R] : T(0);
     }
     __builtin_amdgcn_wave_barrier();
     // ---- 1. band Cholesky, columns j0 .. j0 + W - 1 (branch-free: idle lanes
@@ -653,6 +650,11 @@ __global__ __launch_bounds__(WAVE) void k_elim_banded(const ElimDesc* __restrict
         lsi[(int64_t)j * R] = x[t];
         if (packed) PL[lane + (int64_t)j * k] = x[t];
       }
+    }
+#pragma unroll
+    for (int t = 0; t < W; ++t) {
+      const int jn = j0 + W + t;
+      mcur[t] = (srow && jn < m) ? msi[(int64_t)jn * R] : T(0);
     }
     // ---- 3. S += L_SI(:, block) L_SI(:, block)^T ----
     __builtin_amdgcn_wave_barrier();

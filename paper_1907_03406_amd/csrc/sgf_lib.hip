@@ -828,25 +828,28 @@ void upload_level(sgf_handle h, int li, hipStream_t st) {
   {
     // work lists of the persistent launches: costliest first when the costs
     // differ by more than 2x (longest-processing-time order), else cluster
-    // order (memory locality)
-    auto order = [](std::vector<int32_t>& o, size_t n, const std::function<double(int32_t)>& cost, bool* uneven) {
+    // order (memory locality); each cost evaluated once
+    std::vector<double> cost;
+    auto order = [&cost](std::vector<int32_t>& o, bool* uneven) {
+      const size_t n = cost.size();
       o.resize(n);
       for (size_t i = 0; i < n; ++i) o[i] = (int32_t)i;
       double lo = 0, hi = 0;
       for (size_t i = 0; i < n; ++i) {
-        const double c = cost((int32_t)i);
-        lo = i ? std::min(lo, c) : c;
-        hi = i ? std::max(hi, c) : c;
+        lo = i ? std::min(lo, cost[i]) : cost[i];
+        hi = i ? std::max(hi, cost[i]) : cost[i];
       }
       *uneven = hi > 2 * lo;
-      if (*uneven) std::stable_sort(o.begin(), o.end(), [&](int32_t a, int32_t b) { return cost(a) > cost(b); });
+      if (*uneven) std::stable_sort(o.begin(), o.end(), [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
     };
-    order(D.h_elim_order, L.elim.size(),
-          [&](int32_t a) { return elim_flops(L.elim[a].m, L.elim[a].k, L.elim[a].bw); }, &D.elim_uneven);
+    cost.resize(L.elim.size());
+    for (size_t a = 0; a < L.elim.size(); ++a) cost[a] = elim_flops(L.elim[a].m, L.elim[a].k, L.elim[a].bw);
+    order(D.h_elim_order, &D.elim_uneven);
     upload(h, D.elim_order, D.h_elim_order, st);
-    order(D.h_comp_order, L.comp.size(),
-          [&](int32_t c) { return (double)L.comp[c].s * L.comp[c].s * (L.comp[c].s + L.comp[c].K + L.comp[c].c); },
-          &D.comp_uneven);
+    cost.resize(L.comp.size());
+    for (size_t c = 0; c < L.comp.size(); ++c)
+      cost[c] = (double)L.comp[c].s * L.comp[c].s * (L.comp[c].s + L.comp[c].K + L.comp[c].c);
+    order(D.h_comp_order, &D.comp_uneven);
     upload(h, D.comp_order, D.h_comp_order, st);
   }
   // compression fronts [M_BB ; M_XB] too large for the one-workgroup panel:
@@ -1154,6 +1157,15 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
   }
   h->trace.mark("level-1 inputs queued", 1);
   // ---- level loop (Algorithm 4.1) --------------------------------------------
+  // the work counters of a level are summed on the host while the GPU runs
+  // the level after it (off the path between the rank read-back and the
+  // next launches)
+  int acct = -1;
+  auto account_pending = [&] {
+    if (acct < 0) return;
+    account_level(h, P.levels[acct], h->lev[acct].work);
+    acct = -1;
+  };
   for (int li = 0;; ++li) {
     sgf::Level& L = P.levels[li];
     LevelDev& D = h->lev[li];
@@ -1236,6 +1248,7 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
     }
     h->trace.mark("elimination queued", L.t);
     if (L.top) {
+      account_pending();
       int f = check_fail(h, st);
       HIP_CHECK(hipGetLastError());
       if (f >= 0) {
@@ -1327,6 +1340,7 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
       HIP_CHECK(hipMemcpyAsync(L.rank.data(), D.rank.p, L.comp.size() * sizeof(int), hipMemcpyDeviceToHost, st));
     const bool reuse_next = (int)P.levels.size() > li + 1 && (int)h->lev.size() > li + 1 &&
                             h->lev[li + 1].uploaded;
+    account_pending();
     int f = check_fail(h, st);
     if (f >= 0) {
       h->failed_cluster = f;
@@ -1428,7 +1442,7 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
                            D.tofcomp.as<int64_t>(), D.tb.as<T>(), blocks, D.scratch.as<T>());
       }, L.t);
     }
-    account_level(h, L, D.work);
+    acct = li;   // counted while the GPU runs the next level
     h->trace.mark("compressed-separator work queued", L.t);
     // ---- coarsen (Secs. 4.3-4.4) ----------------------------------------------
     {
@@ -1450,6 +1464,7 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
         upload(h, D.phimap, D.h_phimap, st);
       }
       upload_level(h, li + 1, st);
+      h->trace.mark("next level tables built (host)", li + 1);
       bs.flush(st);
     }
     h->trace.mark(same_ranks ? "next level reused" : "next level uploaded", li + 1);
@@ -1543,8 +1558,12 @@ int64_t band_lds(sgf_handle h, const LevelDev& D, bool fwd, int rc) {
   return fwd ? sgf::band_fwd_lds(D.band_m, D.band_k, D.band_bw, rc)
              : sgf::band_bwd_lds(D.band_m, D.band_k, D.band_bw, rc, band_tj(h, D));
 }
+// Banded sweeps for levels whose fronts are banded (the widest band below
+// the largest front's size - 1, or the banded elimination's packed copy):
+// on dense upper-level fronts the blocked sweeps measured faster.
 bool band_level(sgf_handle h, const LevelDev& D, bool fwd) {
   if (!h->band_apply || D.tiled || D.band_bw < 0 || D.band_bw > sgf::BAND_MAX) return false;
+  if (D.banded_w == 0 && D.band_bw >= D.band_m - 1) return false;
   return (size_t)band_lds(h, D, fwd, 1) * h->esz <= LDS_BYTES;
 }
 // Right-hand sides per workgroup of the banded sweeps: at most one per
