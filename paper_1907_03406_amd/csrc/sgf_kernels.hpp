@@ -1710,25 +1710,66 @@ __global__ __launch_bounds__(WG) void k_band_fwd(const ElimDesc* __restrict__ D,
   }
   __syncthreads();
   const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  // rows i0 .. i0 + 63 of x = L_I^{-1} x by one wavefront (earlier rows final)
+  auto solve_chunk = [&](T* vc, int i0) {
+    const int i = i0 + lane, cn = min(WAVE, m - i0);
+    const bool on = i < m;
+    T x = on ? vc[i] : T(0);
+    const T dinv = on ? Bd[i] : T(0);
+    // columns of earlier chunks inside the band (their values are final)
+    for (int r = lane + 1; r <= bw; ++r)
+      if (on && i - r >= 0) x -= Bd[r * ld + i] * vc[i - r];
+#pragma unroll 4
+    for (int jj = 0; jj < cn; ++jj) {
+      const T xj = lane_bcast(x * dinv, jj);
+      const int r = lane - jj;
+      if (r == 0) x = xj;
+      else if (r > 0 && r <= bw && on) x -= Bd[r * ld + i] * xj;
+    }
+    if (on) vc[i] = x;
+  };
+  if (nc == 1 && k <= WAVE) {
+    // one right-hand side, at most 64 separator rows: wavefront 0 solves the
+    // chunks of 64 rows in turn while wavefronts 1-3 accumulate L_SI x over
+    // the chunk finished before.  The partial sums are those of the general
+    // path below (columns j = q mod 4 in ascending j, q = 0..3; wavefront 3
+    // keeps q = 2 and 3) combined in the same order, so the result is the
+    // same bits.
+    const T* cr = PK ? PL + lane : C + m + lane;
+    const int64_t cs = PK ? k : R;
+    const int qa = w - 1, qb = w == 3 ? 3 : -1;
+    T acca = T(0), accb = T(0);
+    const int nch = (m + WAVE - 1) / WAVE;
+    for (int ch = 0; ch <= nch; ++ch) {
+      if (w == 0) {
+        if (ch < nch) solve_chunk(v, ch * WAVE);
+      } else if (ch > 0 && lane < k) {
+        const int j0 = (ch - 1) * WAVE, j1 = min(m, j0 + WAVE);
+#pragma unroll 4
+        for (int j = j0 + qa; j < j1; j += 4) acca += cr[(int64_t)j * cs] * v[j];
+        if (qb >= 0) {
+#pragma unroll 4
+          for (int j = j0 + qb; j < j1; j += 4) accb += cr[(int64_t)j * cs] * v[j];
+        }
+      }
+      __syncthreads();
+    }
+    if (w > 0) {
+      part[(qa * RC) * WAVE + lane] = acca;
+      if (qb >= 0) part[(qb * RC) * WAVE + lane] = accb;
+    }
+    __syncthreads();
+    if (w == 0 && lane < k) {
+      T sum = 0;
+      for (int q = 0; q < WG / WAVE; ++q) sum += part[(q * RC) * WAVE + lane];
+      tscr[(int64_t)c0 * ldt + d.t_off + lane] = sum;
+    }
+    for (int idx = threadIdx.x; idx < m; idx += WG) y[(int64_t)c0 * ldy + sl[idx]] = v[idx];
+    return;
+  }
   if (w < nc) {
     T* vc = v + w * ld;
-    for (int i0 = 0; i0 < m; i0 += WAVE) {
-      const int i = i0 + lane, cn = min(WAVE, m - i0);
-      const bool on = i < m;
-      T x = on ? vc[i] : T(0);
-      const T dinv = on ? Bd[i] : T(0);
-      // columns of earlier chunks inside the band (their values are final)
-      for (int r = lane + 1; r <= bw; ++r)
-        if (on && i - r >= 0) x -= Bd[r * ld + i] * vc[i - r];
-#pragma unroll 4
-      for (int jj = 0; jj < cn; ++jj) {
-        const T xj = lane_bcast(x * dinv, jj);
-        const int r = lane - jj;
-        if (r == 0) x = xj;
-        else if (r > 0 && r <= bw && on) x -= Bd[r * ld + i] * xj;
-      }
-      if (on) vc[i] = x;
-    }
+    for (int i0 = 0; i0 < m; i0 += WAVE) solve_chunk(vc, i0);
   }
   __syncthreads();
   // t = L_SI x: 64 rows per pass, the columns dealt to the wavefronts in turn
