@@ -2226,30 +2226,23 @@ __global__ __launch_bounds__(WG) void k_reduce(const double* __restrict__ partia
   if (threadIdx.x == 0) out[(int64_t)blockIdx.x * stride] = s;
 }
 
-// CG scalars per column.  st layout per column: [rz, pAp, rr, alpha, beta, active].
+// CG scalars per column.  st layout per column: [rz, pAp, rr, alpha, -, active].
 // Every iteration starts from z = M r: with rz = +inf and p = 0 before the
-// first one, its beta is 0 and p = z.
-__global__ void k_cg_alpha(double* st, int nrhs) {
-  int c = threadIdx.x;
-  if (c < nrhs) {
-    double* s = st + 8 * c;
-    s[3] = (s[5] != 0.0 && s[1] != 0.0) ? s[0] / s[1] : 0.0;
-  }
-}
-__global__ void k_cg_beta(double* st, const double* rz_new, int nrhs) {
-  int c = threadIdx.x;
-  if (c < nrhs) {
-    double* s = st + 8 * c;
-    s[4] = (s[5] != 0.0 && s[0] != 0.0) ? rz_new[c] / s[0] : 0.0;
-    if (s[5] != 0.0) s[0] = rz_new[c];
-  }
-}
+// first one, its beta is 0 and p = z.  beta = rz_new / rz and alpha =
+// rz_new / pAp are formed by every workgroup of the vector updates from the
+// stored scalars; the x, r update's first workgroup then records rz = rz_new.
 
 // x += alpha p, r -= alpha Ap
 __global__ void k_cg_update_xr(double* __restrict__ x, int64_t ldx, double* __restrict__ r, int64_t ldr,
                                const double* __restrict__ p, const double* __restrict__ Ap, int64_t ldp, int64_t n,
-                               const double* __restrict__ st) {
-  const double alpha = st[8 * blockIdx.y + 3];
+                               double* __restrict__ st, const double* __restrict__ rz_new) {
+  double* sc = st + 8 * blockIdx.y;
+  const bool act = sc[5] != 0.0;
+  const double alpha = (act && sc[1] != 0.0) ? rz_new[blockIdx.y] / sc[1] : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc[3] = alpha;
+    if (act) sc[0] = rz_new[blockIdx.y];
+  }
   if (alpha == 0.0) return;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
@@ -2259,9 +2252,10 @@ __global__ void k_cg_update_xr(double* __restrict__ x, int64_t ldx, double* __re
 }
 // p = z + beta p
 __global__ void k_cg_update_p(double* __restrict__ p, const double* __restrict__ z, int64_t ld, int64_t n,
-                              const double* __restrict__ st) {
-  if (st[8 * blockIdx.y + 5] == 0.0) return;
-  const double beta = st[8 * blockIdx.y + 4];
+                              const double* __restrict__ st, const double* __restrict__ rz_new) {
+  const double* sc = st + 8 * blockIdx.y;
+  if (sc[5] == 0.0) return;
+  const double beta = sc[0] != 0.0 ? rz_new[blockIdx.y] / sc[0] : 0.0;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i + blockIdx.y * ld] = z[i + blockIdx.y * ld] + beta * p[i + blockIdx.y * ld];
 }

@@ -2209,17 +2209,15 @@ sgf_status sgf_pcg_solve(sgf_handle h, int32_t nrhs, const double* b, int64_t ld
     auto iteration = [&](hipStream_t s) {
       apply_any(h, nrhs, r, n, z, n, false, s);
       dot_cols(h, r, z, nrhs, sc, s);
-      launch(h, s, "cg_scalar", 0, 0, [&] { hipLaunchKernelGGL(sgf::k_cg_beta, dim3(1), dim3(256), 0, s, stv, sc, nrhs); });
       launch(h, s, "cg_axpy", 0, 24.0 * n * nrhs, [&] {
-        hipLaunchKernelGGL(sgf::k_cg_update_p, gv, dim3(sgf::WG), 0, s, p, z, n, n, stv);
+        hipLaunchKernelGGL(sgf::k_cg_update_p, gv, dim3(sgf::WG), 0, s, p, z, n, n, stv, sc);
       });
       launch(h, s, "cg_spmv", 0, spmv_bytes, [&] { spmv_launch(h, p, n, Ap, n, nrhs, h->cg_part.as<double>(), s); });
       launch(h, s, "cg_reduce", 0, 8.0 * nbspmv * nrhs, [&] {
         hipLaunchKernelGGL(sgf::k_reduce, dim3(nrhs), dim3(sgf::WG), 0, s, h->cg_part.as<double>(), nbspmv, stv + 1, 8);
       });
-      launch(h, s, "cg_scalar", 0, 0, [&] { hipLaunchKernelGGL(sgf::k_cg_alpha, dim3(1), dim3(256), 0, s, stv, nrhs); });
       launch(h, s, "cg_axpy", 0, 48.0 * n * nrhs, [&] {
-        hipLaunchKernelGGL(sgf::k_cg_update_xr, gv, dim3(sgf::WG), 0, s, xi, n, r, n, p, Ap, n, n, stv);
+        hipLaunchKernelGGL(sgf::k_cg_update_xr, gv, dim3(sgf::WG), 0, s, xi, n, r, n, p, Ap, n, n, stv, sc);
       });
       dot_cols(h, r, r, nrhs, sc, s);
     };
