@@ -1465,13 +1465,25 @@ constexpr int DLD = DB + 1;
 
 // Lower triangle of the diagonal block [jb, jb + nb) of C into D, with the
 // reciprocal of the diagonal stored on the diagonal; entries more than bw
-// below the diagonal are known zeros and not read.
-template <typename T>
+// below the diagonal are known zeros and not read.  Every load of a round
+// (U per thread) is issued before its stores.
+template <typename T, int U = 8>
 __device__ __forceinline__ void stage_diag(const T* __restrict__ C, int64_t ld, int jb, int nb, T* D, int bw) {
-  for (int idx = threadIdx.x; idx < nb * nb; idx += WG) {
-    const int i = idx % nb, j = idx / nb;
-    const T c = (i >= j && i - j <= bw) ? C[(jb + i) + (int64_t)(jb + j) * ld] : T(0);
-    D[i + j * DLD] = (i == j) ? T(1) / c : c;
+  const int n = nb * nb;
+  for (int base = 0; base < n; base += U * WG) {
+    T t[U];
+    int ii[U], jj[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int idx = base + u * WG + (int)threadIdx.x;
+      ii[u] = idx % nb;
+      jj[u] = idx < n ? idx / nb : -1;
+      const int i = ii[u], j = jj[u];
+      t[u] = (j >= 0 && i >= j && i - j <= bw) ? C[(jb + i) + (int64_t)(jb + j) * ld] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (jj[u] >= 0) D[ii[u] + jj[u] * DLD] = (ii[u] == jj[u]) ? T(1) / t[u] : t[u];
   }
 }
 
