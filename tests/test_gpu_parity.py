@@ -487,6 +487,33 @@ def test_refactorization_clears_only_the_band_and_matches_a_fresh_handle(prec):
     assert zb[1] == zb[2] == zb[5] < zb[0] / 2
 
 
+def test_refactorization_on_changing_streams_matches_fresh_handles():
+    """Descriptor tables go to the device through one pinned staging buffer
+    per handle, reused after the stream that read it is synchronized:
+    refactorizations of one handle on two side streams and the default
+    stream in turn (other coefficients each time, so the upper levels are
+    re-planned and re-uploaded) give bitwise the applies of fresh handles."""
+    pa, pb = _prob("fourier", (61, 58), seed=2), _prob("fourier", (61, 58), seed=3)
+    V = np.stack([P.random_rhs(6, pa.n, j) for j in range(3)], axis=1)
+    vals = {"a": torch.from_numpy(pa.data).cuda(), "b": torch.from_numpy(pb.data).cuda()}
+    ref = {}
+    for key in "ab":
+        s = sgf.Solver.from_problem(pa, q=2, leaf=8, precision=sgf.FP32)
+        s.factorize(vals[key])
+        ref[key] = _apply(s, V)
+        s.close()
+    s = sgf.Solver.from_problem(pa, q=2, leaf=8, precision=sgf.FP32)
+    side = [torch.cuda.Stream(), torch.cuda.Stream()]   # default priority
+    streams = [side[0].cuda_stream, side[1].cuda_stream, None]
+    for step, key in enumerate("abbaab"):
+        st = streams[step % 3]
+        torch.cuda.synchronize()
+        s.factorize(vals[key], stream=st)
+        torch.cuda.synchronize()
+        out = _apply(s, V)
+        assert np.array_equal(out, ref[key]), (step, key, _rel(out, ref[key]))
+
+
 def test_banded_elimination_reports_non_spd_cluster():
     """A non-positive pivot inside a banded front is reported with its cluster."""
     p = _prob("const", (64, 64))
