@@ -1347,6 +1347,44 @@ __global__ __launch_bounds__(WG) void k_sepacc(const SepAcc* __restrict__ A, con
   }
 }
 
+// The forward separator step of one level with one right-hand side, one
+// workgroup per accumulated separator: y_S <- y_S - sum_I t_I[S part] (as
+// k_sepacc with sign -1), then, when S was compressed (cap[b] >= 0),
+// y_S <- T_S y_S (as k_comp_apply_t, mode 0) on the values just formed.
+// Same arithmetic as the two launches it replaces.  Dynamic LDS: 2 s_max.
+template <typename T>
+__global__ __launch_bounds__(WG) void k_sepacc_comp(const SepAcc* __restrict__ A, const int64_t* __restrict__ src,
+                                                    const int32_t* __restrict__ slots, const T* __restrict__ tscr,
+                                                    T* __restrict__ y, const int32_t* __restrict__ cap,
+                                                    const CompApply* __restrict__ CA, const T* __restrict__ tb) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const SepAcc a = A[blockIdx.x];
+  const int ci = cap[blockIdx.x];
+  T* ys = reinterpret_cast<T*>(smem_raw);
+  T* out = ys + a.s;
+  const int32_t* sl = slots + a.slot_off;
+  for (int i = threadIdx.x; i < a.s; i += WG) {
+    T acc = 0;
+    for (int c = 0; c < a.c_cnt; ++c) acc += tscr[src[a.c_ptr + c] + i];
+    T& yi = y[sl[i]];
+    const T v = yi + T(-1) * acc;
+    if (ci < 0) yi = v;
+    else ys[i] = v;
+  }
+  if (ci < 0) return;
+  __syncthreads();
+  const int s = a.s;
+  const T* X = tb + CA[ci].t_off;
+  for (int i = threadIdx.x; i < s; i += WG) {
+    T acc = 0;
+#pragma unroll 8
+    for (int j = 0; j < s; ++j) acc += X[i + (int64_t)j * s] * ys[j];
+    out[i] = acc;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < s; i += WG) y[sl[i]] = out[i];
+}
+
 // Backward step of one interior: y_I <- L^{-T} (y_I - W y_S).
 // mode 1 (product form, first half): y_I <- L^T y_I + W y_S.
 template <typename T>

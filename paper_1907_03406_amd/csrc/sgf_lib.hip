@@ -198,7 +198,7 @@ struct LevelWork {
 struct LevelDev {
   DevBuf arena, scratch, cf, nbuf, ltphi, tau, phi, rank;
   DevBuf elim, pairs, schur, comp, compnbr, sepacc, sepsrc, capply, slots, nslots;
-  DevBuf blkmap, phimap, slotptr, phioff, tb, active, tofcomp;
+  DevBuf blkmap, phimap, slotptr, phioff, tb, active, tofcomp, capacc;
   std::vector<sgf::CopyDesc> h_blkmap, h_phimap;
   LevelWork work;
   bool uploaded = false;   // descriptor tables on the device match the plan
@@ -1407,9 +1407,26 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
         D.capply_small = D.comp_small;
         upload(h, D.capply, L.capply, st);
         L.t_of_comp.assign(L.comp.size(), -1);
+        std::vector<int32_t> q_of_comp(L.comp.size(), -1);
         for (size_t c = 0, q = 0; c < L.comp.size(); ++c)
-          if (L.rank[c] < L.comp[c].s) L.t_of_comp[c] = L.capply[q++].t_off;
+          if (L.rank[c] < L.comp[c].s) {
+            q_of_comp[c] = (int32_t)q;
+            L.t_of_comp[c] = L.capply[q++].t_off;
+          }
         upload(h, D.tofcomp, L.t_of_comp, st);
+        // compressed separator of every accumulation entry (for the fused
+        // forward separator step)
+        L.cap_of_acc.assign(L.sepacc.size(), -1);
+        size_t covered = 0;
+        for (size_t a = 0; a < L.sepacc.size(); ++a) {
+          const int c = L.comp_of[L.seps[L.sacc_p[a]]];
+          if (c >= 0 && q_of_comp[c] >= 0) {
+            L.cap_of_acc[a] = q_of_comp[c];
+            ++covered;
+          }
+        }
+        L.acc_covers_capply = covered == L.capply.size();
+        upload(h, D.capacc, L.cap_of_acc, st);
       }
       // pairs that touch a compressed separator (their coarse couplings)
       if (!L.capply.empty() && !same_ranks) {
@@ -1716,6 +1733,29 @@ void run_sweeps(sgf_handle h, int nrhs, bool product, hipStream_t st) {
                          sign);
     }, L.t);
   };
+  // forward separator step (accumulation, then T_S on the compressed
+  // separators) as one launch: one right-hand side, every compressed
+  // separator among the accumulated ones, T_S products on the one-workgroup
+  // kernel; false when these do not hold (then two launches)
+  auto sepacc_comp = [&](int li) {
+    sgf::Level& L = P.levels[li];
+    LevelDev& D = h->lev[li];
+    if (nrhs != 1 || L.sepacc.empty() || !L.acc_covers_capply || L.cap_of_acc.size() != L.sepacc.size())
+      return false;
+    int mm, mk, ms;
+    maxes(L, mm, mk, ms);
+    if (!L.capply.empty() && (ms > 256 || h->tiled_rows == 0)) return false;
+    int sa = 0;
+    for (const auto& a : L.sepacc) sa = std::max(sa, a.s);
+    const size_t lds = 2 * (size_t)sa * sizeof(T);
+    if (lds > LDS_BYTES) return false;
+    launch(h, st, "apply_sepacc", 0, D.work.acc_vec + D.work.capply_bytes + D.work.capply_vec, [&] {
+      hipLaunchKernelGGL(sgf::k_sepacc_comp<T>, dim3((unsigned)L.sepacc.size()), dim3(sgf::WG), lds, st,
+                         D.sepacc.as<sgf::SepAcc>(), D.sepsrc.as<int64_t>(), D.slots.as<int32_t>(), ts, y,
+                         D.capacc.as<int32_t>(), D.capply.as<sgf::CompApply>(), D.tb.as<T>());
+    }, L.t);
+    return true;
+  };
   auto capply = [&](int li, int mode) {
     sgf::Level& L = P.levels[li];
     LevelDev& D = h->lev[li];
@@ -1757,8 +1797,10 @@ void run_sweeps(sgf_handle h, int nrhs, bool product, hipStream_t st) {
   for (int li = 0; li < nl - 1; ++li) {
     if (!product) {
       elim_fwd(li, 0);
-      sepacc(li, T(-1));
-      capply(li, 0);
+      if (!sepacc_comp(li)) {
+        sepacc(li, T(-1));
+        capply(li, 0);
+      }
     } else {
       elim_bwd(li, 1);
       capply(li, 2);

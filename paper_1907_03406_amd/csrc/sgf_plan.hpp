@@ -236,6 +236,8 @@ struct Level {
   std::vector<int32_t> active_pairs;       // pairs touching a compressed separator
   std::vector<int64_t> t_of_comp;          // offset of T_B per compression (-1: not compressed)
   std::vector<CompApply> capply;
+  std::vector<int32_t> cap_of_acc;         // per SepAcc: its index in capply, or -1 (not compressed)
+  bool acc_covers_capply = false;          // every compressed separator has a SepAcc
   int64_t n_active = 0;
   // structure recorded by build_level, from which build_offsets re-derives
   // every size-dependent field when only the cluster sizes change
