@@ -941,7 +941,8 @@ __global__ __launch_bounds__(WAVE) void k_compress_small(const CompDesc* __restr
                                                          T* __restrict__ nbuf, const T* __restrict__ phi,
                                                          T* __restrict__ ltphi, T* __restrict__ tau_all,
                                                          int* __restrict__ rank, int pi, double rank_tol, int* fail,
-                                                         int prefactored, int bf16n, T* __restrict__ tb) {
+                                                         int prefactored, int bf16n, T* __restrict__ tb,
+                                                         const T* __restrict__ blocks) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int ci = blockIdx.x;
   const CompDesc d = D[ci];
@@ -957,9 +958,24 @@ __global__ __launch_bounds__(WAVE) void k_compress_small(const CompDesc* __restr
   const int lane = threadIdx.x;
   T* F = cf + d.cf_off;
   // ---- stage the front and the Phi blocks ----
-  for (int idx = lane; idx < R * s; idx += WAVE) {
-    const int i = idx % R, j = idx / R;
-    Fl[i + j * ldf] = F[idx];
+  if (blocks) {
+    // the front straight from the pair blocks (what k_comp_gather puts in cf):
+    // M_BB, then M_XB of every neighbour X (stored as M_BX when trans)
+    const T* dg = blocks + d.blk_diag;
+    for (int idx = lane; idx < s * s; idx += WAVE) Fl[idx % s + (idx / s) * ldf] = dg[idx];
+    for (int q = 0; q < d.nnb; ++q) {
+      const CompNbr x = NBR[d.nb_ptr + q];
+      const T* b = blocks + x.blk_off;
+      for (int idx = lane; idx < x.s_x * s; idx += WAVE) {
+        const int j = idx % x.s_x, i = idx / x.s_x;   // row j of X, column i of B
+        Fl[(x.row + j) + i * ldf] = x.trans ? b[i + (int64_t)j * s] : b[j + (int64_t)i * x.s_x];
+      }
+    }
+  } else {
+    for (int idx = lane; idx < R * s; idx += WAVE) {
+      const int i = idx % R, j = idx / R;
+      Fl[i + j * ldf] = F[idx];
+    }
   }
   const T* PhB = phi + d.phi_off;
   for (int idx = lane; idx < s * pi; idx += WAVE) Ph[idx % s + (idx / s) * R] = PhB[idx];
@@ -1007,9 +1023,11 @@ __global__ __launch_bounds__(WAVE) void k_compress_small(const CompDesc* __restr
         Fl[i + j * ldf] = acc * invd[j];
       }
     __builtin_amdgcn_wave_barrier();
+    // the factored front to cf (all of it when the staging skipped cf, so
+    // that cf holds what the gather and this write-back would have left)
     for (int idx = lane; idx < R * s; idx += WAVE) {
       const int i = idx % R, j = idx / R;
-      if (i >= j) F[idx] = Fl[i + j * ldf];
+      if (i >= j || blocks) F[idx] = Fl[i + j * ldf];
     }
   }
   // ---- N (Eq. 4.5) and L^T Phi_B ----

@@ -1268,10 +1268,6 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
       }, L.t);
     }
     if (!L.comp.empty()) {
-      launch(h, st, "comp_gather", 0, 2.0 * L.cf_elems * e, [&] {
-        hipLaunchKernelGGL(sgf::k_comp_gather<T>, dim3((unsigned)L.comp.size()), dim3(sgf::WG), 0, st,
-                           D.comp.as<sgf::CompDesc>(), D.compnbr.as<sgf::CompNbr>(), blocks, D.cf.as<T>());
-      }, L.t);
       // N in LDS when the widest one fits beside its column norms
       int64_t n_lds = 0;
       for (const auto& d : L.comp) n_lds = std::max<int64_t>(n_lds, (int64_t)d.s * d.c + ((d.c + 3) & ~3));
@@ -1293,6 +1289,15 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
         slds = (size_t)el * sizeof(T);
         if (ms <= sgf::CS_SMAX && mc <= sgf::CS_CMAX && slds <= LDS_BYTES) snb = ms <= 16 ? 16 : ms <= 32 ? 32 : 64;
       }
+      // compression fronts [M_BB ; M_XB] gathered from the pair blocks, here
+      // or (one-wavefront compressions of unfactored fronts) inside the
+      // compression kernel
+      const bool gather_inside = snb > 0 && !D.comp_tiled;
+      if (!gather_inside)
+        launch(h, st, "comp_gather", 0, 2.0 * L.cf_elems * e, [&] {
+          hipLaunchKernelGGL(sgf::k_comp_gather<T>, dim3((unsigned)L.comp.size()), dim3(sgf::WG), 0, st,
+                             D.comp.as<sgf::CompDesc>(), D.compnbr.as<sgf::CompNbr>(), blocks, D.cf.as<T>());
+        }, L.t);
       if (D.comp_tiled) {
         // L_B and L_B^{-1} M_BX of every front by the tiled kernels first
         tiled_factor<T>(h, st, D.h_ctf, D.ctf.as<sgf::TFront>(), D.cf.as<T>(), nullptr, L.t, "comp", false);
@@ -1311,7 +1316,8 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
           const dim3 g((unsigned)L.comp.size());
           auto a = std::make_tuple(D.comp.as<sgf::CompDesc>(), D.compnbr.as<sgf::CompNbr>(), D.cf.as<T>(),
                                    D.nbuf.as<T>(), (const T*)D.phi.as<T>(), D.ltphi.as<T>(), D.tau.as<T>(),
-                                   D.rank.as<int>(), P.pi, tol, h->d_fail.as<int>(), pre, bf, D.tb.as<T>());
+                                   D.rank.as<int>(), P.pi, tol, h->d_fail.as<int>(), pre, bf, D.tb.as<T>(),
+                                   gather_inside ? (const T*)blocks : (const T*)nullptr);
           std::apply([&](auto... x) {
             if (snb == 16) hipLaunchKernelGGL((sgf::k_compress_small<T, 16>), g, dim3(sgf::WAVE), slds, st, x...);
             else if (snb == 32) hipLaunchKernelGGL((sgf::k_compress_small<T, 32>), g, dim3(sgf::WAVE), slds, st, x...);
