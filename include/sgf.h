@@ -234,6 +234,14 @@ typedef struct sgf_kernel_stat {
 } sgf_kernel_stat;
 sgf_status sgf_profile_enable(sgf_handle h, int32_t enable);
 sgf_status sgf_profile_read(sgf_handle h, sgf_kernel_stat* out, int32_t cap, int32_t* count);
+/*
+ * Restricts the timing to the launches of one kernel class (the class name
+ * as reported by sgf_profile_read, without the "@L<level>" suffix), so that
+ * the events bracket only those launches and the rest run as without
+ * profiling; NULL or "" times every launch again (the default).  The string
+ * is copied.
+ */
+sgf_status sgf_profile_select(sgf_handle h, const char* kernel_class);
 
 /*
  * Frees every device buffer of the handle (factor, copies of A, work

@@ -234,6 +234,7 @@ struct LevelDev {
 
 struct Profiler {
   bool on = false;
+  std::string only;   // non-empty: only launches of this kernel class are timed
   std::vector<sgf_kernel_stat> stats;
   struct Pending {
     int idx;
@@ -264,7 +265,7 @@ struct Profiler {
   // Adds work to a kernel (and its "<name>@L<level>" tag) that is known only
   // after the launch, e.g. once the ranks of a compression are read back.
   void charge(const char* name, int level, double flops, double bytes) {
-    if (!on) return;
+    if (!on || (!only.empty() && only != name)) return;
     char tag[32];
     std::snprintf(tag, sizeof(tag), "%s@L%d", name, level);
     for (int i : {index(name), index(tag)}) {
@@ -517,7 +518,7 @@ sgf_status guard(F&& f) {
 // With level >= 1 the launch is also charged to "<name>@L<level>".
 template <typename F>
 void launch(sgf_handle h, hipStream_t st, const char* name, double flops, double bytes, F&& f, int level = 0) {
-  if (!h->prof.on) {
+  if (!h->prof.on || (!h->prof.only.empty() && h->prof.only != name)) {
     f();
     return;
   }
@@ -2515,6 +2516,11 @@ sgf_status sgf_set_band_apply(sgf_handle h, int32_t enable) {
 sgf_status sgf_set_apply_graph(sgf_handle h, int32_t enable) {
   if (!h) return fail(SGF_EINVAL, "NULL handle");
   return guard([&] { h->use_graph = enable != 0; });
+}
+
+sgf_status sgf_profile_select(sgf_handle h, const char* kernel_class) {
+  if (!h) return fail(SGF_EINVAL, "NULL handle");
+  return guard([&] { h->prof.only = kernel_class ? kernel_class : ""; });
 }
 
 sgf_status sgf_profile_enable(sgf_handle h, int32_t enable) {

@@ -20,7 +20,7 @@ FP64, FP32, FP32_BF16N = 0, 1, 2
 
 EXPORTED = ["sgf_default_options", "sgf_analyze", "sgf_factorize_numeric", "sgf_factorize", "sgf_autotune",
             "sgf_apply", "sgf_multiply", "sgf_pcg_solve", "sgf_spmv", "sgf_get_info",
-            "sgf_get_perm", "sgf_get_level", "sgf_plan_dry_run", "sgf_profile_enable", "sgf_profile_read",
+            "sgf_get_perm", "sgf_get_level", "sgf_plan_dry_run", "sgf_profile_enable", "sgf_profile_read", "sgf_profile_select",
             "sgf_set_apply_graph", "sgf_set_persistent", "sgf_set_band_apply", "sgf_set_band_elim", "sgf_set_small_compress", "sgf_release", "sgf_estimate_bytes",
             "sgf_server_default_options", "sgf_server_create", "sgf_server_add_operator", "sgf_server_submit",
             "sgf_server_wait", "sgf_server_get_stats", "sgf_server_clock", "sgf_server_destroy",
@@ -95,6 +95,7 @@ def load_library(path=LIB_PATH):
         "sgf_get_level": (I32, [H, I32, P, P, P, P, P]),
         "sgf_plan_dry_run": (I32, [H, RANK_FN, P]),
         "sgf_profile_enable": (I32, [H, I32]),
+        "sgf_profile_select": (I32, [H, ctypes.c_char_p]),
         "sgf_set_apply_graph": (I32, [H, I32]),
         "sgf_set_persistent": (I32, [H, I32]),
         "sgf_set_band_apply": (I32, [H, I32]),
@@ -269,6 +270,10 @@ class Solver:
     def profile(self, enable=True):
         """Start (clear) or stop per-kernel event timing."""
         _check(_lib.sgf_profile_enable(self.h, 1 if enable else 0))
+
+    def profile_select(self, kernel_class=None):
+        """Time only the launches of one kernel class (None: every launch)."""
+        _check(_lib.sgf_profile_select(self.h, kernel_class.encode() if kernel_class else None))
 
     def profile_read(self):
         """{kernel class: dict(launches, ms, flops, bytes)} since profile()."""

@@ -514,6 +514,28 @@ def test_refactorization_on_changing_streams_matches_fresh_handles():
         assert np.array_equal(out, ref[key]), (step, key, _rel(out, ref[key]))
 
 
+def test_profile_select_times_one_kernel_class():
+    """With a class selected, only its launches are timed (with their level
+    tags); the selection cleared, every launch is timed again."""
+    p = _prob("fourier", (100, 90))
+    s = sgf.Solver.from_problem(p, q=2, leaf=16, precision=sgf.FP32)
+    v = torch.from_numpy(p.data).cuda()
+    s.factorize(v)
+    s.profile_select("elim_banded")
+    s.profile(True)
+    s.factorize(v)
+    st = s.profile_read()
+    s.profile(False)
+    assert st and all(k.split("@")[0] == "elim_banded" for k in st), sorted(st)
+    assert st["elim_banded"]["launches"] >= 1 and st["elim_banded"]["ms"] > 0 and "elim_banded@L1" in st
+    s.profile_select(None)
+    s.profile(True)
+    s.factorize(v)
+    st = s.profile_read()
+    s.profile(False)
+    assert "elim_banded" in st and "compress" in st and "fill_csr" in st
+
+
 def test_banded_elimination_reports_non_spd_cluster():
     """A non-positive pivot inside a banded front is reported with its cluster."""
     p = _prob("const", (64, 64))
