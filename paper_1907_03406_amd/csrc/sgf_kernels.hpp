@@ -110,6 +110,25 @@ __global__ void k_copy_blocks(const CopyDesc* __restrict__ D, const T* __restric
   }
 }
 
+// Two copy maps in one launch: workgroups [0, n1) copy by D1 from src1 to
+// dst1, the rest by D2 from src2 to dst2 (each as k_copy_blocks).
+template <typename T>
+__global__ void k_copy_blocks2(const CopyDesc* __restrict__ D1, const T* __restrict__ src1, T* __restrict__ dst1,
+                               int n1, const CopyDesc* __restrict__ D2, const T* __restrict__ src2,
+                               T* __restrict__ dst2) {
+  const bool first = (int)blockIdx.x < n1;
+  const CopyDesc d = first ? D1[blockIdx.x] : D2[blockIdx.x - n1];
+  const T* src = first ? src1 : src2;
+  T* dst = first ? dst1 : dst2;
+  const int64_t tot = (int64_t)d.rows * d.cols;
+  for (int64_t idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+    int i = (int)(idx % d.rows), j = (int)(idx / d.rows);
+    T v = src[d.src_off + i + (int64_t)j * d.src_ld];
+    if (d.mode == 0) dst[d.dst_off + i + (int64_t)j * d.dst_ld] = v;
+    else dst[d.dst_off + j + (int64_t)i * d.dst_ld] = v;
+  }
+}
+
 template <typename T>
 __global__ void k_zero(T* __restrict__ p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;

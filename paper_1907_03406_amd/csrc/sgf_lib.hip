@@ -1497,19 +1497,19 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
     LevelDev& Dc = h->lev[li];   // re-fetch: lev may have grown
     const int64_t ne = N.front_elems + N.blk_elems;
     launch(h, st, "zero", 0, ne * e, [&] { zero<T>(E.arena, ne, st); });
-    if (!Dc.h_blkmap.empty()) {
+    // pair blocks and Phi rows of the surviving separators into the new
+    // level, one launch for both maps
+    const unsigned nbm = (unsigned)Dc.h_blkmap.size(), npm = (unsigned)Dc.h_phimap.size();
+    if (nbm + npm > 0) {
       double cb = 0;
-      for (const auto& c : Dc.h_blkmap) cb += 2.0 * c.rows * c.cols * e;
+      if (h->prof.on)
+        for (const auto& c : Dc.h_blkmap) cb += 2.0 * c.rows * c.cols * e;
       launch(h, st, "coarsen_copy", 0, cb, [&] {
-        hipLaunchKernelGGL(sgf::k_copy_blocks<T>, dim3((unsigned)Dc.h_blkmap.size()), dim3(sgf::WG), 0, st,
-                           Dc.blkmap.as<sgf::CopyDesc>(), Dc.arena.as<T>(), E.arena.as<T>());
+        hipLaunchKernelGGL(sgf::k_copy_blocks2<T>, dim3(nbm + npm), dim3(sgf::WG), 0, st,
+                           Dc.blkmap.as<sgf::CopyDesc>(), (const T*)Dc.arena.as<T>(), E.arena.as<T>(), (int)nbm,
+                           Dc.phimap.as<sgf::CopyDesc>(), (const T*)Dc.phi.as<T>(), E.phi.as<T>());
       }, li + 1);
     }
-    if (!Dc.h_phimap.empty())
-      launch(h, st, "coarsen_phi", 0, 0, [&] {
-        hipLaunchKernelGGL(sgf::k_copy_blocks<T>, dim3((unsigned)Dc.h_phimap.size()), dim3(sgf::WG), 0, st,
-                           Dc.phimap.as<sgf::CopyDesc>(), Dc.phi.as<T>(), E.phi.as<T>());
-      }, li + 1);
     HIP_CHECK(hipGetLastError());
     h->trace.mark("coarsening queued", li + 1);
   }
