@@ -103,8 +103,11 @@ struct Staging {
   Staging() = default;
   Staging(const Staging&) = delete;
   Staging& operator=(const Staging&) = delete;
-  void drain() {
-    if (pending) HIP_CHECK(hipStreamSynchronize(st));
+  // wait for the queued copies: on their stream when the caller uses that
+  // stream, else on the whole device (the caller's earlier stream may be
+  // gone by now)
+  void drain(hipStream_t current) {
+    if (pending) HIP_CHECK(current == st ? hipStreamSynchronize(st) : hipDeviceSynchronize());
     pending = false;
     used = 0;
   }
@@ -117,10 +120,10 @@ struct Staging {
   }
   // space for `bytes` (256-byte aligned), after the queued copies on stream s
   unsigned char* take(size_t bytes, hipStream_t s) {
-    if (pending && s != st) drain();
+    if (pending && s != st) drain(s);
     size_t off = (used + 255) & ~size_t(255);
     if (off + bytes > cap) {
-      drain();
+      drain(s);
       off = 0;
       if (bytes > cap) {
         if (p) (void)hipHostFree(p);
@@ -449,7 +452,8 @@ void flush_batch(sgf_handle h, UploadBatch& B, hipStream_t st) {
   unsigned char* q = nullptr;
   if (n > 1 && !h->capturing && total <= Staging::MAX_TABLE) {
     // the device blob is rewritten only after the previous scatter read it
-    if (h->blob_st && (h->blob_st != st || total > h->blob.bytes)) HIP_CHECK(hipStreamSynchronize(h->blob_st));
+    if (h->blob_st && (h->blob_st != st || total > h->blob.bytes))
+      HIP_CHECK(h->blob_st == st ? hipStreamSynchronize(st) : hipDeviceSynchronize());
     q = h->staging.take(total, st);
   }
   if (!q) {
@@ -926,6 +930,7 @@ int check_fail(sgf_handle h, hipStream_t st) {
   HIP_CHECK(hipMemcpyAsync(&f, h->d_fail.p, sizeof(int), hipMemcpyDeviceToHost, st));
   HIP_CHECK(hipStreamSynchronize(st));
   h->staging.synced(st);
+  if (h->blob_st == st) h->blob_st = nullptr;   // its last scatter has run
   return f;
 }
 
