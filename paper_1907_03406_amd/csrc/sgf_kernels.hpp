@@ -1223,6 +1223,64 @@ __global__ __launch_bounds__(WG) void k_phi_commit(const CompDesc* __restrict__ 
   }
 }
 
+// k_pair with one wavefront per pair, PPB pairs per workgroup and the
+// intermediate T_a M_ab in LDS (gmax elements per wavefront): the same
+// products in the same order, for levels of many small pairs.
+constexpr int PPB = 4;
+template <typename T>
+__global__ __launch_bounds__(PPB * WAVE) void k_pair_w(const PairDesc* __restrict__ P,
+                                                       const int32_t* __restrict__ active, int nact,
+                                                       const int* __restrict__ rank,
+                                                       const int64_t* __restrict__ t_of_comp,
+                                                       const T* __restrict__ tb, T* __restrict__ blocks, int gmax) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  const int q = blockIdx.x * PPB + w;
+  if (q >= nact) return;
+  const PairDesc pd = P[active[q]];
+  const int sa = pd.s_a, sb = pd.s_b;
+  const int ra = (pd.ca >= 0 && rank[pd.ca] < sa) ? rank[pd.ca] : sa;
+  const int rb = (pd.cb >= 0 && rank[pd.cb] < sb) ? rank[pd.cb] : sb;
+  const bool ca = ra < sa, cb = rb < sb;
+  T* blk = blocks + pd.blk_off;
+  if (pd.a == pd.b) {
+    if (ca)
+      for (int idx = lane; idx < ra * ra; idx += WAVE) {
+        const int i = idx % ra, j = idx / ra;
+        blk[i + (int64_t)j * sa] = (i == j) ? T(1) : T(0);
+      }
+    return;
+  }
+  T* G = reinterpret_cast<T*>(smem_raw) + (int64_t)w * gmax;   // ra x sb, ld ra
+  if (ca) {
+    const T* Ta = tb + t_of_comp[pd.ca];
+    for (int idx = lane; idx < ra * sb; idx += WAVE) {
+      const int i = idx % ra, j = idx / ra;
+      T acc = 0;
+#pragma unroll 8
+      for (int p = 0; p < sa; ++p) acc += Ta[i + (int64_t)p * sa] * blk[p + (int64_t)j * sa];
+      G[idx] = acc;
+    }
+  } else {
+    for (int idx = lane; idx < ra * sb; idx += WAVE) G[idx] = blk[(idx % ra) + (int64_t)(idx / ra) * sa];
+  }
+  // G is written and read by this wavefront only: its LDS accesses are
+  // performed in order, the barrier keeps the compiler from moving them
+  __builtin_amdgcn_wave_barrier();
+  if (cb) {
+    const T* Tb = tb + t_of_comp[pd.cb];
+    for (int idx = lane; idx < ra * rb; idx += WAVE) {
+      const int i = idx % ra, j = idx / ra;
+      T acc = 0;
+#pragma unroll 8
+      for (int r = 0; r < sb; ++r) acc += G[i + (int64_t)r * ra] * Tb[j + (int64_t)r * sb];
+      blk[i + (int64_t)j * sa] = acc;
+    }
+  } else {
+    for (int idx = lane; idx < ra * sb; idx += WAVE) blk[(idx % ra) + (int64_t)(idx / ra) * sa] = G[idx];
+  }
+}
+
 // Coarse couplings C_ab = T_a M_ab T_b^T (the first r rows of T = Q^T L^{-1}
 // for a compressed separator, T = I otherwise); the diagonal block of a
 // compressed separator becomes I_r (Sec. 3.2: scaled and rotated, fine rows

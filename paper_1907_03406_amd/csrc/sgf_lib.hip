@@ -1465,10 +1465,24 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
     }
     // coarse couplings, only for the pairs that touch a compressed separator
     if (!L.capply.empty()) {
+      // many small pairs: one wavefront each, T_a M_ab in LDS
+      int64_t gmax = 1;
+      for (int32_t p : L.active_pairs) {
+        const auto& pd = L.pairs[p];
+        const int ra = pd.ca >= 0 && L.rank[pd.ca] < pd.s_a ? L.rank[pd.ca] : pd.s_a;
+        gmax = std::max<int64_t>(gmax, (int64_t)ra * pd.s_b);
+      }
+      const size_t plds = (size_t)sgf::PPB * gmax * sizeof(T);
+      const unsigned nact = (unsigned)L.active_pairs.size();
       launch(h, st, "pair", 0, 0, [&] {
-        hipLaunchKernelGGL(sgf::k_pair<T>, dim3((unsigned)L.active_pairs.size()), dim3(sgf::WG), 0, st,
-                           D.pairs.as<sgf::PairDesc>(), D.active.as<int32_t>(), D.rank.as<int>(),
-                           D.tofcomp.as<int64_t>(), D.tb.as<T>(), blocks, D.scratch.as<T>());
+        if (plds <= LDS_BYTES && nact >= 4096)
+          hipLaunchKernelGGL(sgf::k_pair_w<T>, dim3(cdiv(nact, sgf::PPB)), dim3(sgf::PPB * sgf::WAVE), plds, st,
+                             D.pairs.as<sgf::PairDesc>(), D.active.as<int32_t>(), (int)nact, D.rank.as<int>(),
+                             D.tofcomp.as<int64_t>(), D.tb.as<T>(), blocks, (int)gmax);
+        else
+          hipLaunchKernelGGL(sgf::k_pair<T>, dim3(nact), dim3(sgf::WG), 0, st, D.pairs.as<sgf::PairDesc>(),
+                             D.active.as<int32_t>(), D.rank.as<int>(), D.tofcomp.as<int64_t>(), D.tb.as<T>(), blocks,
+                             D.scratch.as<T>());
       }, L.t);
     }
     acct = li;   // counted while the GPU runs the next level
