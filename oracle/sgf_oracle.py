@@ -21,6 +21,18 @@ NumPy, cluster by cluster, in the order the paper states:
 * the preconditioner apply A_l^{-1} (Sec. 4.7), the product A_l (Sec. 2.1),
 * CG with A_l^{-1} as preconditioner (Sec. 7).
 
+Schemes (Sec. 5): Nest-All-All (every interaction of every separator cell but
+the single-vertex cells is compressed), Nest-2-All (only the cells of
+codimension one: faces in 3D, edges in 2D), Nest-2-2 (those cells, with the
+couplings to the lower-dimensional cells on their boundary kept exactly by
+putting their span into Q_1), and Gen-All-All (boxes of d^dim vertices, no
+interiors, every cell compressed; Sec. 5.2).  Besides the polynomial
+compression, the "standard low-rank equivalent" of Sec. 7.4 (Eq. 7.5): the
+same factorization with Q taken from the pivoted QR of the scaled
+off-diagonal block itself, truncated to the ranks a polynomial run recorded.
+A user may also supply the near-kernel basis Pi directly (Secs. 1 and 3.1
+allow any near-kernel space) instead of monomials of the coordinates.
+
 Readings taken where the paper is silent (each listed in the design notes):
 vertices at (i + 1/2) h with cutting slabs only on internal planes; global
 coordinate normalisation for the monomials; ascending cluster ids for every
@@ -34,6 +46,11 @@ import scipy.linalg as sla
 
 NEST_ALL_ALL = 0
 NEST_2_ALL = 1
+NEST_2_2 = 2
+GEN_ALL_ALL = 3
+
+POLYNOMIAL = 0
+LOW_RANK = 1
 
 STOP_ROOT = 0
 STOP_PAPER = 1
@@ -59,14 +76,27 @@ def axis_classes(N, d):
     return (2 * below + slab).astype(np.int64), int(2 * slab.sum() + 1)
 
 
+def axis_boxes(N, d):
+    """Per-axis classes of the general partition at period d (Sec. 5.2): the
+    boxes (r d h, (r + 1) d h) hold the vertices r d .. r d + d - 1 (vertex i
+    at (i + 1/2) h), so the class of i is i // d; the last box of an axis
+    whose length is not a multiple of d is shorter.  Returns (classes,
+    #classes)."""
+    i = np.arange(N)
+    return (i // d).astype(np.int64), int((N + d - 1) // d)
+
+
 class Level:
     """Cells of one partition P_t: cell id of every grid node, number of
     cells, and each cell's type (number of odd per-axis classes: 0 = interior
-    block; 1 = face in 3D / edge in 2D; ...; dim = corner vertex)."""
+    block; 1 = face in 3D / edge in 2D; ...; dim = corner vertex).  In a
+    general partition (Sec. 5.2) every box has type 1: none is an interior,
+    all are compressed."""
 
-    def __init__(self, grid, d):
+    def __init__(self, grid, d, general=False):
         self.d = d
-        cls, K = zip(*(axis_classes(N, d) for N in grid))
+        self.general = general
+        cls, K = zip(*((axis_boxes if general else axis_classes)(N, d) for N in grid))
         self.K = K
         # cell id = cx + Kx * (cy + Ky * cz): lexicographic, x fastest
         mesh = np.meshgrid(*[c for c in cls[::-1]], indexing="ij")
@@ -79,17 +109,40 @@ class Level:
         self.cell_of_node = cid
         self.ncells = int(np.prod(K))
         self.type = np.zeros(self.ncells, dtype=np.int64)
-        self.type[cid] = odd
+        self.type[cid] = 1 if general else odd
         self.is_root = all(k == 1 for k in K)
 
+    def classes(self, cid):
+        """Per-axis classes of cell cid (x first)."""
+        out = []
+        for k in self.K:
+            out.append(cid % k)
+            cid //= k
+        return tuple(out)
 
-def partition_hierarchy(grid, leaf):
+    def on_boundary(self, B, Y):
+        """Whether cell Y lies on the boundary of cell B (Sec. 5.1): Y != B,
+        Y has B's class on every axis where B is a slab (odd class), and a
+        class within one of B's on the other axes.  For a face these are the
+        edges and corners around it; for an edge in 2D its two end corners."""
+        if B == Y:
+            return False
+        for cb, cy in zip(self.classes(B), self.classes(Y)):
+            if cb % 2 == 1 and cy != cb:
+                return False
+            if abs(cy - cb) > 1:
+                return False
+        return True
+
+
+def partition_hierarchy(grid, leaf, general=False):
     """Levels t = 1, 2, ... with d_t = leaf * 2^(t-1), up to the first level
-    whose partition is the single set V (no axis has an internal slab)."""
+    whose partition is the single set V (nested dissection: no axis has an
+    internal slab; general boxes: one box per axis)."""
     levels = []
     t = 1
     while True:
-        lev = Level(grid, leaf * 2 ** (t - 1))
+        lev = Level(grid, leaf * 2 ** (t - 1), general)
         levels.append(lev)
         if lev.is_root:
             return levels
@@ -210,6 +263,37 @@ def qrcp(N, rank_tol):
     return V, np.array(taus), V.shape[1], np.array(diag)
 
 
+def qrcp_fixed_rank(N, r):
+    """The pivoted Householder QR of qrcp (same pivot, tie and reflector
+    rules) run for exactly min(r, #rows, #cols) steps instead of stopping at
+    a threshold: the truncation of the rank-revealing QR of Eq. 7.5 to a
+    given number r of columns of Q_1.  A step whose trailing part is zero
+    takes no reflection (tau = 0).  Returns (V, tau, r, diagR) as qrcp,
+    with r the requested size of Q_1 (the first r columns of
+    Q = H_0 ... H_{k-1})."""
+    A = np.array(N, dtype=np.float64, copy=True)
+    m, c = A.shape
+    V = np.zeros((m, 0))
+    taus, diag = [], []
+    for k in range(min(r, m, c)):
+        norms = np.sqrt(np.sum(A[k:, k:] ** 2, axis=0))
+        nmax = norms.max()
+        j = k if nmax == 0.0 else int(np.nonzero(norms >= nmax * (1.0 - TIE_RTOL))[0][0]) + k
+        if j != k:
+            A[:, [k, j]] = A[:, [j, k]]
+        v, tau, beta = householder(A[k:, k].copy())
+        if tau != 0.0:
+            A[k:, k:] -= tau * np.outer(v, v @ A[k:, k:])
+        A[k, k] = beta
+        A[k + 1:, k] = 0.0
+        col = np.zeros(m)
+        col[k:] = v
+        V = np.hstack([V, col[:, None]])
+        taus.append(tau)
+        diag.append(beta)
+    return V, np.array(taus), r, np.array(diag)
+
+
 def apply_qt(V, tau, X):
     """Q^T X = H_{r-1} ... H_0 X."""
     Y = np.array(X, dtype=np.float64, copy=True)
@@ -235,9 +319,14 @@ def apply_q(V, tau, X):
 # ---------------------------------------------------------------------------
 
 class Options:
+    """compression = POLYNOMIAL (Eq. 3.2) or LOW_RANK (Eq. 7.5, with the
+    ranks recorded by a polynomial run in ``ranks``: F.info["ranks"]);
+    basis = a user near-kernel basis Pi (n x pi) replacing the monomials of
+    degree q (then q and the coordinates are not used)."""
+
     def __init__(self, q=1, leaf=8, compress=True, compress_from_level=1,
                  scheme=NEST_ALL_ALL, rank_tol=1e-12, stop_rule=STOP_ROOT,
-                 order="ascending", seed=0):
+                 order="ascending", seed=0, compression=POLYNOMIAL, ranks=None, basis=None):
         self.q = q
         self.leaf = leaf
         self.compress = compress
@@ -247,6 +336,9 @@ class Options:
         self.stop_rule = stop_rule
         self.order = order      # compression order inside a level
         self.seed = seed        # for order == "shuffled"
+        self.compression = compression
+        self.ranks = ranks
+        self.basis = basis
 
 
 class Factor:
@@ -266,12 +358,14 @@ class Factor:
 
 
 def _compressible(typ, dim, scheme):
+    if scheme == GEN_ALL_ALL:       # every box of a general partition
+        return True
     if typ == 0 or typ == dim:      # interiors; 0-cells: nothing to compress
         return False
     if scheme == NEST_ALL_ALL:
         return True
-    if scheme == NEST_2_ALL:
-        return typ == 1
+    if scheme in (NEST_2_ALL, NEST_2_2):
+        return typ == 1             # cells of codimension one
     raise ValueError("unknown scheme")
 
 
@@ -281,8 +375,10 @@ def factorize(A, coords, grid, dpn, opt):
     A = A.tocsr()
     n = A.shape[0]
     dim = len(grid)
-    Pi = poly_basis(coords, opt.q, dpn)
-    levels = partition_hierarchy(grid, opt.leaf)
+    Pi = poly_basis(coords, opt.q, dpn) if opt.basis is None else np.asarray(opt.basis, dtype=np.float64)
+    if Pi.shape[0] != n:
+        raise ValueError("the basis must have one row per unknown")
+    levels = partition_hierarchy(grid, opt.leaf, general=opt.scheme == GEN_ALL_ALL)
     F = Factor()
 
     # ---- level-1 nodes: active sets, Phi_B = Pi(B, :), blocks of A -------
@@ -363,11 +459,29 @@ def factorize(A, coords, grid, dpn, opt):
             s = len(vars_of[B])
             L = np.linalg.cholesky(blocks[(B, B)])                        # Eq. 3.1
             Mh = [sla.solve_triangular(L, blocks[(B, x)], lower=True) for x in X]
-            N = np.hstack([L.T @ Phi[B]] + [m @ Phi[x] for m, x in zip(Mh, X)])   # Eq. 4.5
-            V, tau, r, dR = qrcp(N, opt.rank_tol)                          # Eq. 3.3
-            gap_in = abs(dR[-1] / dR[0]) if r else 0.0
+            if opt.compression == LOW_RANK:
+                # Eq. 7.5: Q from the pivoted QR of the scaled off-diagonal
+                # block [M^_BX1 | M^_BX2 | ...], cut at the recorded size
+                r_rec = opt.ranks[t][B]
+                if r_rec >= s:
+                    ranks[B] = r_rec
+                    continue
+                N = np.hstack(Mh) if Mh else np.zeros((s, 0))
+                V, tau, r, dR = qrcp_fixed_rank(N, r_rec)
+                gap_in, dropped = 0.0, 0.0
+            else:
+                # Eq. 4.5; in Nest-2-2 the couplings to the cells on B's
+                # boundary enter N whole, so their span is kept in Q_1 (Sec. 5.1)
+                cols = [L.T @ Phi[B]]
+                for m, x in zip(Mh, X):
+                    full = opt.scheme == NEST_2_2 and lv.on_boundary(B, x)
+                    cols.append(m if full else m @ Phi[x])
+                N = np.hstack(cols)
+                V, tau, r, dR = qrcp(N, opt.rank_tol)                      # Eq. 3.3
+                gap_in = abs(dR[-1] / dR[0]) if r else 0.0
+                dropped = qrcp.last_dropped
             ranks[B] = r
-            F.info["gap"].append((t + 1, B, s, r, gap_in, qrcp.last_dropped))
+            F.info["gap"].append((t + 1, B, s, r, gap_in, dropped))
             if r >= s:
                 continue
             vB = vars_of[B]
