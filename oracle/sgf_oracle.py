@@ -322,11 +322,23 @@ class Options:
     """compression = POLYNOMIAL (Eq. 3.2) or LOW_RANK (Eq. 7.5, with the
     ranks recorded by a polynomial run in ``ranks``: F.info["ranks"]);
     basis = a user near-kernel basis Pi (n x pi) replacing the monomials of
-    degree q (then q and the coordinates are not used)."""
+    degree q (then q and the coordinates are not used).
+
+    low_rank_blocks (LOW_RANK only): "current" forms each separator's
+    off-diagonal block from the matrix as it stands when that separator is
+    compressed, after the compressions before it in the level (the
+    sequential recursion of Sec. 3.2 run with Q from Eq. 7.5); "level" forms
+    every separator's block from the matrix as it stands after the level's
+    eliminations, before any of its compressions.  For the polynomial
+    compression the two are the same operator (the filtered columns of a
+    compressed neighbour do not change, Sec. 3.2); for the low-rank
+    equivalent they differ, and "level" makes the compressions of a level
+    independent of their order."""
 
     def __init__(self, q=1, leaf=8, compress=True, compress_from_level=1,
                  scheme=NEST_ALL_ALL, rank_tol=1e-12, stop_rule=STOP_ROOT,
-                 order="ascending", seed=0, compression=POLYNOMIAL, ranks=None, basis=None):
+                 order="ascending", seed=0, compression=POLYNOMIAL, ranks=None, basis=None,
+                 low_rank_blocks="current"):
         self.q = q
         self.leaf = leaf
         self.compress = compress
@@ -339,6 +351,9 @@ class Options:
         self.compression = compression
         self.ranks = ranks
         self.basis = basis
+        if low_rank_blocks not in ("current", "level"):
+            raise ValueError("low_rank_blocks must be 'current' or 'level'")
+        self.low_rank_blocks = low_rank_blocks
 
 
 class Factor:
@@ -454,6 +469,9 @@ def factorize(A, coords, grid, dpn, opt):
             seps = seps[::-1]
         elif opt.order == "shuffled":
             seps = list(np.random.default_rng(opt.seed).permutation(seps))
+        # the level's blocks before any of its compressions (low-rank
+        # equivalent with blocks taken per level, see Options)
+        level_blocks = dict(blocks) if opt.compression == LOW_RANK and opt.low_rank_blocks == "level" else None
         for B in (seps if do_comp else []):
             X = sorted(nbr[B])
             s = len(vars_of[B])
@@ -466,7 +484,9 @@ def factorize(A, coords, grid, dpn, opt):
                 if r_rec >= s:
                     ranks[B] = r_rec
                     continue
-                N = np.hstack(Mh) if Mh else np.zeros((s, 0))
+                src = Mh if level_blocks is None else \
+                    [sla.solve_triangular(L, level_blocks[(B, x)], lower=True) for x in X]
+                N = np.hstack(src) if src else np.zeros((s, 0))
                 V, tau, r, dR = qrcp_fixed_rank(N, r_rec)
                 gap_in, dropped = 0.0, 0.0
             else:

@@ -339,3 +339,73 @@ def test_constant_basis_needs_no_coordinates():
     Fb = O.factorize(A, None, p.grid, 1, O.Options(leaf=4, basis=np.ones((p.n, 1))))
     v = P.random_rhs(1, p.n)
     assert np.array_equal(O.apply_inverse(Fa, v), O.apply_inverse(Fb, v))
+
+
+def test_factor_size_per_unknown_stays_flat():
+    """Prop. 5.1 (Sec. 5.4): with compression every node's active size is
+    bounded independently of n, so the top node keeps one size and the
+    stored factor entries per unknown level off as the grid grows (2D,
+    q = 1, leaf 8: 64^2, 128^2, 256^2), while without compression the top
+    grows like the grid side."""
+    per_n, tops, tops_exact = [], [], []
+    for N in (64, 128, 256):
+        p = _fourier((N, N))
+        A, F = _fact(p, q=1, leaf=8)
+        per_n.append(O.factor_entries(F) / p.n)
+        tops.append(F.info["top_size"])
+        if N <= 128:
+            _, Fe = _fact(p, q=1, leaf=8, compress=False)
+            tops_exact.append(Fe.info["top_size"])
+    assert tops[0] == tops[1] == tops[2]
+    assert per_n[2] / per_n[0] < 1.2
+    assert per_n[2] - per_n[1] < per_n[1] - per_n[0]
+    assert tops_exact[1] > 1.9 * tops_exact[0]
+
+
+def test_low_rank_with_level_blocks_is_order_independent_and_matches_dense_schur():
+    """The low-rank equivalent whose compressions take their off-diagonal
+    blocks from the level's matrix before any of its compressions: (1) the
+    compressions of a level no longer depend on their order (ascending,
+    descending, shuffled give one operator), unlike the sequential variant,
+    whose result changes with the order; (2) on level 1, each compressed
+    separator's kept subspace is that of a pivoted QR (LAPACK) of
+    chol(S_BB)^{-1} [S_BX1 | S_BX2 | ...], with S the dense Schur complement
+    of the level-1 interiors computed here from A."""
+    p = _fourier((50, 46), seed=2)
+    A = p.csr()
+    _, F = _fact(p, q=0, leaf=16)
+    kw = dict(q=0, leaf=16, compression=O.LOW_RANK, ranks=F.info["ranks"])
+    v = np.stack([P.random_rhs(6, p.n, j) for j in range(2)], axis=1)
+    outs = {o: O.apply_inverse(_fact(p, order=o, low_rank_blocks="level", **kw)[1], v)
+            for o in ("ascending", "descending", "shuffled")}
+    assert _rel(outs["descending"], outs["ascending"]) <= 1e-12
+    assert _rel(outs["shuffled"], outs["ascending"]) <= 1e-12
+    seq = {o: O.apply_inverse(_fact(p, order=o, **kw)[1], v) for o in ("ascending", "descending")}
+    assert _rel(seq["descending"], seq["ascending"]) > 1e-9
+    # (2) level 1 against a dense Schur complement
+    _, Fl = _fact(p, low_rank_blocks="level", **kw)
+    lv = O.partition_hierarchy(p.grid, 16)[0]
+    cell = lv.cell_of_node
+    interior = lv.type[cell] == 0
+    Ad = A.toarray()
+    I, S = np.nonzero(interior)[0], np.nonzero(~interior)[0]
+    Sch = Ad[np.ix_(S, S)] - Ad[np.ix_(S, I)] @ np.linalg.solve(Ad[np.ix_(I, I)], Ad[np.ix_(I, S)])
+    pos = {d: k for k, d in enumerate(S)}
+    checked = 0
+    for op in Fl.levels[0]:
+        if op[0] != "comp":
+            continue
+        _, vB, Lo, V, tau, r = op
+        B = cell[vB[0]]
+        rows = [pos[d] for d in vB]
+        nbrs = sorted({cell[S[j]] for j in range(len(S)) if cell[S[j]] != B
+                       and np.abs(Sch[np.ix_(rows, [j])]).max() > 0})
+        cols = [pos[d] for X in nbrs for d in np.nonzero(cell == X)[0]]
+        Lb = np.linalg.cholesky(Sch[np.ix_(rows, rows)])
+        N = sla.solve_triangular(Lb, Sch[np.ix_(rows, cols)], lower=True)
+        Q, R, piv = sla.qr(N, pivoting=True)
+        Pd = Q[:, :r] @ Q[:, :r].T
+        Qo = O.apply_q(V, tau, np.eye(len(vB)))[:, :r]
+        assert np.abs(Qo @ Qo.T - Pd).max() <= 1e-10
+        checked += 1
+    assert checked >= 8
