@@ -47,8 +47,21 @@ typedef enum {
   SGF_ESTATE = 6      /* call out of order (e.g. apply before factorize)     */
 } sgf_status;
 
-/* Which separator interactions are compressed (Sec. 5.1). */
-enum { SGF_NEST_ALL_ALL = 0, SGF_NEST_2_ALL = 1 };
+/* Which cells are compressed, and how (Sec. 5):
+ *  SGF_NEST_ALL_ALL  nested-dissection partition; every separator cell but
+ *                    single vertices is compressed (Sec. 5.1);
+ *  SGF_NEST_2_ALL    only the cells of codimension one (faces in 3D, edges in
+ *                    2D);
+ *  SGF_NEST_2_2      those cells, with the couplings to the cells on their
+ *                    boundary kept exactly: the scaled coupling block of each
+ *                    such neighbour enters N whole instead of times its Phi
+ *                    (Sec. 5.1), so its span stays in Q_1;
+ *  SGF_GEN_ALL_ALL   general partition into boxes of `leaf` vertices per axis
+ *                    with no interiors: every box is compressed at every level
+ *                    and the compressions are the only eliminations (Sec. 5.2). */
+enum { SGF_NEST_ALL_ALL = 0, SGF_NEST_2_ALL = 1, SGF_NEST_2_2 = 2, SGF_GEN_ALL_ALL = 3 };
+/* Largest number of columns of a user-supplied near-kernel basis. */
+#define SGF_MAX_BASIS_COLS 64
 /* When the hierarchy ends (Sec. 4.5 and Sec. 7). */
 enum { SGF_STOP_ROOT = 0, SGF_STOP_PAPER = 1 };
 /* Arithmetic of the factor and the apply; CG itself is always FP64, and so
@@ -64,12 +77,14 @@ typedef struct {
   int32_t grid[3];             /* grid nodes per axis (grid[2] ignored in 2D)      */
   int32_t dofs_per_node;       /* 1 (scalar PDE) or 3 (elasticity, Eq. 7.4)        */
   int32_t q;                   /* polynomial degree 0, 1 or 2 (Sec. 3.1)           */
-  int32_t leaf;                /* b > 1: level-t period d_t = b * 2^(t-1) (Sec 5.1)*/
-  int32_t scheme;              /* SGF_NEST_ALL_ALL (default) or SGF_NEST_2_ALL     */
+  int32_t leaf;                /* b > 1: level-t period d_t = b * 2^(t-1) (Sec 5.1);
+                                  for SGF_GEN_ALL_ALL the level-1 box width      */
+  int32_t scheme;              /* SGF_NEST_ALL_ALL (default), SGF_NEST_2_ALL,
+                                  SGF_NEST_2_2 or SGF_GEN_ALL_ALL                  */
   int32_t compress;            /* 0 = exact nested-dissection block Cholesky       */
   int32_t compress_from_level; /* first level whose separators are compressed (1) */
   int32_t stop_rule;           /* SGF_STOP_ROOT (default) or SGF_STOP_PAPER        */
-  int32_t precision;           /* SGF_FP64 (default) or SGF_FP32                   */
+  int32_t precision;           /* SGF_FP64 (default), SGF_FP32 or SGF_FP32_BF16N   */
   int32_t tiled_min_rows;      /* levels whose largest front has at least this many
                                   rows are eliminated by the tiled multi-workgroup
                                   path (0: every level, and every compressed
@@ -109,7 +124,10 @@ void sgf_default_options(sgf_options* opt);
  *   n            number of unknowns = prod(grid) * dofs_per_node
  *   row_ptr      HOST int64[n+1], col_idx HOST int32[nnz]: the FULL
  *                symmetric pattern of A (both triangles), any column order
- *   coords       HOST double[n_nodes * dim], node positions (row per node)
+ *   coords       HOST double[n_nodes * dim], node positions (row per node);
+ *                may be NULL when q = 0: the constant needs no geometry
+ *                (analyze with q = 0 and no coordinates, then sgf_set_basis,
+ *                to use a user basis on a grid without node positions)
  *   opt          options (copied)
  *   out          receives the new handle (caller destroys it)
  * The pattern must only couple nodes within one grid step of each other
@@ -206,6 +224,39 @@ sgf_status sgf_get_level(sgf_handle h, int32_t level, int32_t* count, int32_t* c
                          int32_t* types, int32_t* sizes, int32_t* ranks);
 
 /*
+ * Factor blocks, for entry-by-entry parity checks of the factorization
+ * (Algorithm 4.1).  Level t (1-based) below the top holds, in this order,
+ * its interior eliminations (Eq. 4.2; ascending cell id) and then its
+ * compressed separators (Eqs. 3.1-3.4; ascending cell id, only those whose
+ * rank came out below their size); the top level holds one block, the
+ * exact Cholesky factor of what is left (Sec. 4.5).
+ * sgf_block_count: the number of blocks of each kind on level t.
+ * sgf_export_block: block `index` of level t (eliminations first); fills
+ * *info and, for every non-NULL HOST array (column major, FP64 -- converted
+ * from FP32 in the FP32 forms):
+ *   kind SGF_BLOCK_ELIM: L (m x m, lower, zero above) = chol(M_II) and
+ *     W (m x k) = L^{-1} M_IS, the neighbours' unknowns in ascending cell id;
+ *   kind SGF_BLOCK_COMP: L (m x m) = chol(M_BB) (Eq. 3.1), V (m x r) the
+ *     Householder vectors of the pivoted QR of N (unit diagonal, zero above),
+ *     tau (r) their coefficients, Q = H_0 ... H_{r-1} (Eq. 3.3), and rdiag
+ *     (r) the diagonal of R;
+ *   kind SGF_BLOCK_TOP: L (m x m), the top node's FP64 Cholesky factor.
+ * Unused arrays may be NULL.  SGF_ESTATE before a factorization; reads
+ * device memory synchronously (the device is synchronized first).
+ */
+enum { SGF_BLOCK_ELIM = 0, SGF_BLOCK_COMP = 1, SGF_BLOCK_TOP = 2 };
+typedef struct {
+  int32_t kind;                /* SGF_BLOCK_ELIM / _COMP / _TOP                   */
+  int32_t cell;                /* cell id of the cluster (-1 for the top)         */
+  int32_t m;                   /* rows of L: interior, separator or top size      */
+  int32_t k;                   /* ELIM: columns of W; COMP: neighbour unknowns    */
+  int32_t r;                   /* COMP: rank = number of reflectors               */
+} sgf_block;
+sgf_status sgf_block_count(sgf_handle h, int32_t level, int32_t* n_elim, int32_t* n_comp);
+sgf_status sgf_export_block(sgf_handle h, int32_t level, int32_t index, sgf_block* info, double* L,
+                            double* W, double* V, double* tau, double* rdiag);
+
+/*
  * Host-only dry run of the level planner, for checking the partition
  * hierarchy without a GPU: replays the coarsening of Sec. 4.3-4.4 with the
  * compression ranks supplied by `rank_fn(level, cell_id, size, ctx)` (called
@@ -299,6 +350,17 @@ sgf_status sgf_set_band_elim(sgf_handle h, int32_t enable);
 sgf_status sgf_set_small_compress(sgf_handle h, int32_t enable);
 
 /*
+ * Kernel of the coarse couplings C_ab = T_a M_ab T_b^T of the pairs that
+ * touch a compressed separator (Sec. 3.2): mode 0 one workgroup per pair
+ * (its intermediate product in device scratch), 1 one wavefront per pair
+ * (four per workgroup, the intermediate in LDS) whenever that fits, -1
+ * (default) the wavefront kernel on levels with at least 4096 such pairs.
+ * Both form the same products in the same order (the same bits).  Takes
+ * effect at the next factorization.
+ */
+sgf_status sgf_set_pair_kernel(sgf_handle h, int32_t mode);
+
+/*
  * Interior sweeps of the apply (Sec. 4.7) on levels whose M_II blocks have a
  * lower bandwidth of at most 64: enable = 1 (default) stages the band of L_I
  * in LDS and solves it one wavefront per right-hand side; 0 uses the blocked
@@ -306,6 +368,39 @@ sgf_status sgf_set_small_compress(sgf_handle h, int32_t enable);
  * rounding order.  Drops a captured apply graph.
  */
 sgf_status sgf_set_band_apply(sgf_handle h, int32_t enable);
+
+/*
+ * User-supplied near-kernel basis (Secs. 1 and 3.1: the method needs a
+ * partition hierarchy and a matrix Pi whose columns span the near kernel,
+ * e.g. rigid-body modes, not necessarily monomials of the coordinates):
+ * Phi_B = Pi(B, :) for every level-1 node.
+ *   ncols   1..SGF_MAX_BASIS_COLS columns; 0 returns to the monomials of
+ *           degree q (which need the coordinates unless q = 0)
+ *   basis   HOST double[n * ncols], column major (entry (i, p) at
+ *           basis[i + p * n], i the unknown id), finite; copied
+ * Re-plans level 1 and drops the factor (call sgf_factorize_numeric next);
+ * also ends the low-rank mode.  SGF_EINVAL on a bad size or value.
+ */
+sgf_status sgf_set_basis(sgf_handle h, int32_t ncols, const double* basis);
+
+/*
+ * The standard low-rank equivalent of the compression (Sec. 7.4, Eq. 7.5),
+ * for comparison with the polynomial one: each separator B is compressed
+ * with Q taken from the pivoted QR of its scaled off-diagonal block
+ * [Mhat_BX1 | Mhat_BX2 | ...] (no L_B^T Phi_B block), cut after exactly the
+ * rank that the polynomial compression found for B.
+ *   enable = 1  records the ranks of the handle's current (polynomial)
+ *               factorization, per level and separator, and uses them for the
+ *               next factorizations (SGF_ESTATE if the handle is not
+ *               factored); the levels keep the sizes they had, so the
+ *               factorization has the same structure;
+ *   enable = 0  returns to the polynomial compression.
+ * Re-plans level 1 and drops the factor; call sgf_factorize_numeric next
+ * (with the same values to compare the two at equal ranks).  Same pivot, tie
+ * and reflector conventions as the polynomial QR; a step whose trailing
+ * part is zero keeps its column and takes no reflection.
+ */
+sgf_status sgf_set_low_rank(sgf_handle h, int32_t enable);
 
 /* Releases every host and device resource of the handle (NULL is a no-op). */
 sgf_status sgf_destroy(sgf_handle h);

@@ -199,7 +199,7 @@ __global__ void k_phi_init(const int64_t* __restrict__ slot_ptr, const int64_t* 
     int64_t node = dof / pin.dpn;
     int comp = (int)(dof % pin.dpn);
     double x[3] = {0, 0, 0};
-    for (int a = 0; a < pin.dim; ++a) {
+    for (int a = 0; pin.q >= 1 && a < pin.dim; ++a) {   // q = 0 reads no coordinates
       double v = coords[node * pin.dim + a];
       x[a] = pin.sc[a] > 0 ? (v - pin.lo[a]) * pin.sc[a] - 1.0 : 0.0;
     }
@@ -221,6 +221,22 @@ __global__ void k_phi_init(const int64_t* __restrict__ slot_ptr, const int64_t* 
       int cc = p / pin.p0, j = p % pin.p0;
       out[i + (int64_t)p * s] = (cc == comp) ? (T)mono[j] : T(0);
     }
+  }
+}
+
+// Phi_B = Pi(B, :) for a basis Pi given by the user (n x pi, column major,
+// FP64): any near-kernel basis in place of the monomials (Sec. 3.1).
+template <typename T>
+__global__ void k_phi_user(const int64_t* __restrict__ slot_ptr, const int64_t* __restrict__ phi_off,
+                           const int64_t* __restrict__ perm, const double* __restrict__ basis, int64_t n, int pi,
+                           T* __restrict__ phi) {
+  const int c = blockIdx.x;
+  const int64_t s0 = slot_ptr[c];
+  const int s = (int)(slot_ptr[c + 1] - s0);
+  T* out = phi + phi_off[c];
+  for (int idx = threadIdx.x; idx < s * pi; idx += blockDim.x) {
+    const int i = idx % s, p = idx / s;
+    out[i + (int64_t)p * s] = (T)basis[perm[s0 + i] + (int64_t)p * n];
   }
 }
 
@@ -761,8 +777,12 @@ __global__ __launch_bounds__(WG) void k_comp_gather(const CompDesc* __restrict__
 // tail).  One thread per column for norms and updates, wave 0 forms each
 // reflector.  Leaves the reflectors below the diagonal of the first r
 // columns, tau[0..r), and returns r.  `nrm` holds c entries of scratch.
+// fixed >= 0: exactly min(fixed, s, c) steps instead of the threshold (the
+// truncated rank-revealing QR of Eq. 7.5); a step on a zero trailing part
+// keeps its column and takes no reflection.
 template <typename T>
-__device__ int wg_qrcp(T* N, int s, int c, T* nrm, T* tau, double rank_tol, int* sh_int, T* sh_val) {
+__device__ int wg_qrcp(T* N, int s, int c, T* nrm, T* tau, double rank_tol, int* sh_int, T* sh_val,
+                       int fixed = -1) {
   const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
   for (int j = threadIdx.x; j < c; j += WG) {
     const T* col = N + (int64_t)j * s;
@@ -779,7 +799,7 @@ __device__ int wg_qrcp(T* N, int s, int c, T* nrm, T* tau, double rank_tol, int*
       T nmax = 0;
       for (int j = k; j < c; ++j) nmax = nrm[j] > nmax ? nrm[j] : nmax;
       if (k == 0) sh_val[1] = nmax;
-      int stop = (nmax == T(0)) || (nmax <= (T)rank_tol * sh_val[1]);
+      int stop = fixed >= 0 ? (k >= fixed) : ((nmax == T(0)) || (nmax <= (T)rank_tol * sh_val[1]));
       int piv = k;
       if (!stop) {
         const T thr = nmax * (T)(1.0 - TIE_RTOL);
@@ -860,7 +880,7 @@ __global__ __launch_bounds__(WG) void k_compress(const CompDesc* __restrict__ D,
                                                  T* __restrict__ ltphi, T* __restrict__ tau_all,
                                                  int* __restrict__ rank, int pi, double rank_tol, int* fail,
                                                  int prefactored, int bf16n, const int32_t* __restrict__ order,
-                                                 int n, int* ctr) {
+                                                 int n, int* ctr, const int32_t* __restrict__ fixed_rank) {
   // Phi of the neighbours is read here and must not change during the launch.
   // With `prefactored`, L_B and L_B^{-1} M_BX are already in the front.
   // Persistent over the level's separators (costliest first).
@@ -884,7 +904,7 @@ __global__ __launch_bounds__(WG) void k_compress(const CompDesc* __restrict__ D,
   T* N = NLDS ? lds + ((c + 3) & ~3) : Ng;
   const T* PhB = phi + d.phi_off;
   T* LtP = ltphi + d.ltphi_off;
-  // ---- N (Eq. 4.5) -----------------------------------------------------------
+  // ---- N (Eq. 4.5): [L^T Phi_B | Mhat_BX Phi_X or Mhat_BX ... | 0] ----------
   for (int idx = threadIdx.x; idx < s * pi; idx += WG) {
     const int i = idx % s, p = idx / s;
     T acc = 0, acc16 = 0;
@@ -894,11 +914,21 @@ __global__ __launch_bounds__(WG) void k_compress(const CompDesc* __restrict__ D,
       acc += f * ph;
       if (bf16n) acc16 += bf16_round(f) * bf16_round(ph);
     }
-    N[i + (int64_t)p * s] = bf16n ? acc16 : acc;
+    if (d.self_cols) N[i + (int64_t)p * s] = bf16n ? acc16 : acc;
     LtP[i + (int64_t)p * s] = acc;
   }
+  int cend = d.self_cols;
   for (int q = 0; q < d.nnb; ++q) {
     const CompNbr x = NB[d.nb_ptr + q];
+    if (x.full) {
+      for (int idx = threadIdx.x; idx < s * x.s_x; idx += WG) {
+        const int i = idx % s, j = idx / s;
+        const T v = F[(x.row + j) + (int64_t)i * ld];
+        N[i + (int64_t)(x.col + j) * s] = bf16n ? bf16_round(v) : v;
+      }
+      cend = x.col + x.s_x;
+      continue;
+    }
     const T* PhX = phi + x.phi_off;
     for (int idx = threadIdx.x; idx < s * pi; idx += WG) {
       const int i = idx % s, p = idx / s;
@@ -909,13 +939,15 @@ __global__ __launch_bounds__(WG) void k_compress(const CompDesc* __restrict__ D,
       else
 #pragma unroll 8
         for (int j = 0; j < x.s_x; ++j) acc += F[(x.row + j) + (int64_t)i * ld] * PhX[j + (int64_t)p * x.s_x];
-      N[i + (int64_t)(pi * (1 + q) + p) * s] = acc;
+      N[i + (int64_t)(x.col + p) * s] = acc;
     }
+    cend = x.col + pi;
   }
+  for (int idx = threadIdx.x; idx < s * (c - cend); idx += WG) N[(int64_t)cend * s + idx] = T(0);
   __syncthreads();
   // ---- pivoted Householder QR of N (Eq. 3.3) ---------------------------------
   T* tau = tau_all + d.tau_off;
-  const int r = wg_qrcp(N, s, c, nrm, tau, rank_tol, sh_int, sh_val);
+  const int r = wg_qrcp(N, s, c, nrm, tau, rank_tol, sh_int, sh_val, fixed_rank ? fixed_rank[ci] : -1);
   if (NLDS)
     for (int idx = threadIdx.x; idx < s * r; idx += WG) Ng[idx] = N[idx];
   // ---- (Q^T L^T Phi_B)[:r] (Eq. 3.4) into the scratch; neighbours may still be
@@ -961,7 +993,8 @@ __global__ __launch_bounds__(WAVE) void k_compress_small(const CompDesc* __restr
                                                          T* __restrict__ ltphi, T* __restrict__ tau_all,
                                                          int* __restrict__ rank, int pi, double rank_tol, int* fail,
                                                          int prefactored, int bf16n, T* __restrict__ tb,
-                                                         const T* __restrict__ blocks) {
+                                                         const T* __restrict__ blocks,
+                                                         const int32_t* __restrict__ fixed_rank) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int ci = blockIdx.x;
   const CompDesc d = D[ci];
@@ -1000,6 +1033,7 @@ __global__ __launch_bounds__(WAVE) void k_compress_small(const CompDesc* __restr
   for (int idx = lane; idx < s * pi; idx += WAVE) Ph[idx % s + (idx / s) * R] = PhB[idx];
   for (int q = 0; q < d.nnb; ++q) {
     const CompNbr x = NBR[d.nb_ptr + q];
+    if (x.full) continue;
     const T* PhX = phi + x.phi_off;
     for (int idx = lane; idx < x.s_x * pi; idx += WAVE) Ph[x.row + idx % x.s_x + (idx / x.s_x) * R] = PhX[idx];
   }
@@ -1059,11 +1093,21 @@ __global__ __launch_bounds__(WAVE) void k_compress_small(const CompDesc* __restr
       acc += f * ph;
       if (bf16n) acc16 += bf16_round(f) * bf16_round(ph);
     }
-    Nl[i + p * ldn] = bf16n ? acc16 : acc;
+    if (d.self_cols) Nl[i + p * ldn] = bf16n ? acc16 : acc;
     Lt[i + p * s] = acc;
   }
+  int cend = d.self_cols;
   for (int q = 0; q < d.nnb; ++q) {
     const CompNbr x = NBR[d.nb_ptr + q];
+    if (x.full) {
+      for (int idx = lane; idx < s * x.s_x; idx += WAVE) {
+        const int i = idx % s, j = idx / s;
+        const T v = Fl[(x.row + j) + i * ldf];
+        Nl[i + (x.col + j) * ldn] = bf16n ? bf16_round(v) : v;
+      }
+      cend = x.col + x.s_x;
+      continue;
+    }
     for (int idx = lane; idx < s * pi; idx += WAVE) {
       const int i = idx % s, p = idx / s;
       T acc = 0;
@@ -1073,9 +1117,11 @@ __global__ __launch_bounds__(WAVE) void k_compress_small(const CompDesc* __restr
       else
 #pragma unroll 8
         for (int j = 0; j < x.s_x; ++j) acc += Fl[(x.row + j) + i * ldf] * Ph[(x.row + j) + p * R];
-      Nl[i + (pi * (1 + q) + p) * ldn] = acc;
+      Nl[i + (x.col + p) * ldn] = acc;
     }
+    cend = x.col + pi;
   }
+  for (int idx = lane; idx < s * (c - cend); idx += WAVE) Nl[idx % s + (cend + idx / s) * ldn] = T(0);
   __builtin_amdgcn_wave_barrier();
   // ---- pivoted Householder QR of N (Eq. 3.3) ----
   T nr[2];
@@ -1091,12 +1137,13 @@ __global__ __launch_bounds__(WAVE) void k_compress_small(const CompDesc* __restr
   int r = 0;
   T ref = 0;
   const int kmax = min(s, c);
+  const int fixed = fixed_rank ? fixed_rank[ci] : -1;
   for (int k = 0; k < kmax; ++k) {
     const T m0 = (lane >= k && lane < c) ? nr[0] : T(0);
     const T m1 = (lane + WAVE >= k && lane + WAVE < c) ? nr[1] : T(0);
     const T nmax = wave_max(m0 > m1 ? m0 : m1);
     if (k == 0) ref = nmax;
-    if (nmax == T(0) || nmax <= (T)rank_tol * ref) break;
+    if (fixed >= 0 ? k >= fixed : (nmax == T(0) || nmax <= (T)rank_tol * ref)) break;
     const T thr = nmax * (T)(1.0 - TIE_RTOL);
     const unsigned long long b0 = __ballot(lane >= k && lane < c && nr[0] >= thr);
     const unsigned long long b1 = __ballot(lane + WAVE >= k && lane + WAVE < c && nr[1] >= thr);

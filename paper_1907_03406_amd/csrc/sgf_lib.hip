@@ -231,6 +231,7 @@ struct LevelDev {
   int band_ptr[5] = {0, 0, 0, 0, 0};
   bool band_ok = false;
   DevBuf band_list;
+  DevBuf fixrank;            // low-rank equivalent: the recorded rank of every compression
   DevBuf pk;                 // packed factor copies of the banded fronts (ElimDesc::pk_off)
   int64_t pk_elems = 0;
 };
@@ -339,11 +340,18 @@ struct sgf_handle_s {
   std::vector<int64_t> h_rowptr;
   std::vector<int32_t> h_colidx;
   std::vector<double> h_coords;
+  // user near-kernel basis (n x pi, column major, FP64) replacing the
+  // monomials of the coordinates; empty: monomials of degree q
+  std::vector<double> h_basis;
+  // low-rank equivalent (Eq. 7.5): compressions cut at the ranks of the last
+  // polynomial factorization, per level and compression
+  bool low_rank = false;
+  std::vector<std::vector<int32_t>> lr_rank;
   int64_t nnz = 0;
   size_t esz = 8;
   bool dev_static = false;   // CSR structure, perm, coords, fill map on the device
   bool factored = false;
-  DevBuf d_perm, d_rowptr, d_colidx, d_vals, d_csrdst, d_coords, d_fail;
+  DevBuf d_perm, d_rowptr, d_colidx, d_vals, d_csrdst, d_coords, d_basis, d_fail;
   DevBuf d_ctr, d_zero_idx;   // work counter of the persistent launches; the one-item list {0}
   std::vector<LevelDev> lev;
   DevBuf y, tscr;
@@ -377,6 +385,7 @@ struct sgf_handle_s {
   bool band_elim = true;
   bool small_comp = true;
   int32_t persist_cap = 0;   // > 0: per-level work lists persistent on at most this many workgroups
+  int32_t pair_mode = -1;    // coarse couplings: -1 automatic, 0 one workgroup per pair, 1 one wavefront per pair
   uint64_t epoch = 0;
   hipStream_t cap_stream = nullptr;
   struct ApplyGraph {
@@ -553,7 +562,7 @@ void check_options(const sgf_options* o, int64_t n) {
   if (nodes * o->dofs_per_node != n) throw SgfError(SGF_EINVAL, "n != prod(grid) * dofs_per_node");
   if (o->q < 0 || o->q > 2) throw SgfError(SGF_EINVAL, "q must be 0, 1 or 2");
   if (o->leaf < 2) throw SgfError(SGF_EINVAL, "leaf must be > 1");
-  if (o->scheme != SGF_NEST_ALL_ALL && o->scheme != SGF_NEST_2_ALL) throw SgfError(SGF_EINVAL, "unknown scheme");
+  if (o->scheme < SGF_NEST_ALL_ALL || o->scheme > SGF_GEN_ALL_ALL) throw SgfError(SGF_EINVAL, "unknown scheme");
   if (o->precision != SGF_FP64 && o->precision != SGF_FP32 && o->precision != SGF_FP32_BF16N)
     throw SgfError(SGF_EINVAL, "unknown precision");
   if (o->stop_rule != SGF_STOP_ROOT && o->stop_rule != SGF_STOP_PAPER) throw SgfError(SGF_EINVAL, "unknown stop rule");
@@ -627,6 +636,7 @@ void ensure_static(sgf_handle h, hipStream_t st) {
   upload_direct(h->d_colidx, h->h_colidx, st);
   upload_direct(h->d_csrdst, h->plan.csr_dst, st);
   upload_direct(h->d_coords, h->h_coords, st);
+  if (!h->h_basis.empty()) upload_direct(h->d_basis, h->h_basis, st);
   h->d_vals.ensure(h->nnz * sizeof(double));
   h->d_fail.ensure(sizeof(int));
   h->d_ctr.ensure(sizeof(int));
@@ -1154,7 +1164,13 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
     pin.dpn = P.opt.dpn;
     pin.pi = P.pi;
     pin.p0 = P.pi / P.opt.dpn;
-    if (!L.cell.empty())
+    if (!L.cell.empty() && !h->h_basis.empty())
+      launch(h, st, "phi_init", 0, (double)P.n * (P.pi * (e + 8) + 8), [&] {
+        hipLaunchKernelGGL(sgf::k_phi_user<T>, dim3((unsigned)L.cell.size()), dim3(sgf::WG), 0, st,
+                           D.slotptr.as<int64_t>(), D.phioff.as<int64_t>(), h->d_perm.as<int64_t>(),
+                           h->d_basis.as<double>(), P.n, P.pi, D.phi.as<T>());
+      });
+    else if (!L.cell.empty())
       launch(h, st, "phi_init", 0, (double)P.n * (P.pi * e + 8 + 8 * P.opt.dim), [&] {
         hipLaunchKernelGGL(sgf::k_phi_init<T>, dim3((unsigned)L.cell.size()), dim3(sgf::WG), 0, st,
                            D.slotptr.as<int64_t>(), D.phioff.as<int64_t>(), h->d_perm.as<int64_t>(),
@@ -1273,6 +1289,15 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
                            D.pairs.as<sgf::PairDesc>(), D.schur.as<sgf::SchurDesc>(), arena, blocks);
       }, L.t);
     }
+    const int32_t* fixed = nullptr;
+    if (!L.comp.empty() && h->low_rank) {
+      if (li >= (int)h->lr_rank.size() || h->lr_rank[li].size() != L.comp.size())
+        throw SgfError(SGF_ESTATE, "low-rank mode: the recorded ranks do not match level " + std::to_string(L.t));
+      BatchScope bs(h);
+      upload(h, D.fixrank, h->lr_rank[li], st);
+      bs.flush(st);
+      fixed = D.fixrank.as<int32_t>();
+    }
     if (!L.comp.empty()) {
       // N in LDS when the widest one fits beside its column norms
       int64_t n_lds = 0;
@@ -1323,7 +1348,7 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
           auto a = std::make_tuple(D.comp.as<sgf::CompDesc>(), D.compnbr.as<sgf::CompNbr>(), D.cf.as<T>(),
                                    D.nbuf.as<T>(), (const T*)D.phi.as<T>(), D.ltphi.as<T>(), D.tau.as<T>(),
                                    D.rank.as<int>(), P.pi, tol, h->d_fail.as<int>(), pre, bf, D.tb.as<T>(),
-                                   gather_inside ? (const T*)blocks : (const T*)nullptr);
+                                   gather_inside ? (const T*)blocks : (const T*)nullptr, fixed);
           std::apply([&](auto... x) {
             if (snb == 16) hipLaunchKernelGGL((sgf::k_compress_small<T, 16>), g, dim3(sgf::WAVE), slds, st, x...);
             else if (snb == 32) hipLaunchKernelGGL((sgf::k_compress_small<T, 32>), g, dim3(sgf::WAVE), slds, st, x...);
@@ -1339,7 +1364,7 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
                            D.compnbr.as<sgf::CompNbr>(), D.cf.as<T>(), D.nbuf.as<T>(), D.phi.as<T>(), D.ltphi.as<T>(),
                            D.tau.as<T>(), D.rank.as<int>(), P.pi, tol, h->d_fail.as<int>(), pre,
                            P.opt.precision == SGF_FP32_BF16N ? 1 : 0, D.comp_order.as<int32_t>(), (int)L.comp.size(),
-                           cpersist ? h->d_ctr.as<int>() : nullptr);
+                           cpersist ? h->d_ctr.as<int>() : nullptr, fixed);
       }, L.t);
       launch(h, st, "phi_commit", 0, 0, [&] {
         hipLaunchKernelGGL(sgf::k_phi_commit<T>, dim3((unsigned)L.comp.size()), dim3(sgf::WG), 0, st,
@@ -1475,7 +1500,8 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
       const size_t plds = (size_t)sgf::PPB * gmax * sizeof(T);
       const unsigned nact = (unsigned)L.active_pairs.size();
       launch(h, st, "pair", 0, 0, [&] {
-        if (plds <= LDS_BYTES && nact >= 4096)
+        const bool wave = plds <= LDS_BYTES && (h->pair_mode == 1 || (h->pair_mode < 0 && nact >= 4096));
+        if (wave)
           hipLaunchKernelGGL(sgf::k_pair_w<T>, dim3(cdiv(nact, sgf::PPB)), dim3(sgf::PPB * sgf::WAVE), plds, st,
                              D.pairs.as<sgf::PairDesc>(), D.active.as<int32_t>(), (int)nact, D.rank.as<int>(),
                              D.tofcomp.as<int64_t>(), D.tb.as<T>(), blocks, (int)gmax);
@@ -1548,8 +1574,50 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
   h->factored = true;
 }
 
+// Work vectors of one apply: the permuted vector y (n per column), the
+// separator scratch (max_t per column), and per level the compressed
+// separators' vector (tiled path) and the tiled fronts' work vector, and the
+// top's (FP64).  Normally the handle's own buffers; the allocation-free
+// apply carves them out of the library's static device scratch.
+struct ApplyWork {
+  static constexpr int MAXL = 64;
+  void* y = nullptr;
+  void* tscr = nullptr;
+  void* topu = nullptr;
+  void* cw[MAXL] = {};
+  void* uw[MAXL] = {};
+};
+
+ApplyWork handle_work(sgf_handle h) {
+  ApplyWork w;
+  w.y = h->y.p;
+  w.tscr = h->tscr.p;
+  w.topu = h->topu.p;
+  for (size_t li = 0; li < h->lev.size() && li < (size_t)ApplyWork::MAXL; ++li) {
+    w.cw[li] = h->lev[li].cw.p;
+    w.uw[li] = h->lev[li].uw.p;
+  }
+  return w;
+}
+
+// Work vectors of the apply for nrhs columns.  A captured apply or PCG
+// graph holds the addresses of these buffers, so when one of them is
+// reallocated (grown) the epoch advances and every graph recorded before is
+// captured anew instead of replayed on freed memory.
 template <typename T>
 void ensure_work(sgf_handle h, int nrhs) {
+  std::vector<const void*> before, after;
+  auto addrs = [&](std::vector<const void*>& v) {
+    v.clear();
+    v.push_back(h->y.p);
+    v.push_back(h->tscr.p);
+    v.push_back(h->topu.p);
+    for (auto& D : h->lev) {
+      v.push_back(D.uw.p);
+      v.push_back(D.cw.p);
+    }
+  };
+  addrs(before);
   h->y.ensure((size_t)h->plan.n * nrhs * sizeof(T));
   for (auto& D : h->lev) {
     if (D.tiled && D.uploaded) D.uw.ensure((size_t)std::max<int64_t>(D.u_elems, 1) * nrhs * sizeof(T));
@@ -1557,6 +1625,8 @@ void ensure_work(sgf_handle h, int nrhs) {
   }
   if (h->top_tiled) h->topu.ensure((size_t)h->top_R * nrhs * sizeof(double));
   h->tscr.ensure((size_t)std::max<int64_t>(h->max_t, 1) * nrhs * sizeof(T));
+  addrs(after);
+  if (before != after) ++h->epoch;
 }
 
 void ensure_work_any(sgf_handle h, int nrhs) {
@@ -1618,11 +1688,11 @@ int band_rc(sgf_handle h, const LevelDev& D, bool fwd, int nrhs) {
 }
 
 template <typename T>
-void run_sweeps(sgf_handle h, int nrhs, bool product, hipStream_t st) {
+void run_sweeps(sgf_handle h, int nrhs, bool product, hipStream_t st, const ApplyWork& W) {
   sgf::Plan& P = h->plan;
   const int64_t n = P.n;
-  T* y = h->y.as<T>();
-  T* ts = h->tscr.as<T>();
+  T* y = reinterpret_cast<T*>(W.y);
+  T* ts = reinterpret_cast<T*>(W.tscr);
   const int64_t ldt = std::max<int64_t>(h->max_t, 1);
   const int nl = (int)P.levels.size();
   auto maxes = [](const sgf::Level& L, int& mm, int& mk, int& ms) {
@@ -1646,12 +1716,12 @@ void run_sweeps(sgf_handle h, int nrhs, bool product, hipStream_t st) {
       launch(h, st, "apply_elim_fwd", 0, 0.5 * (cdiv(nrhs, rc1) * D.work.fwd_bytes + nrhs * D.work.fwd_vec), [&] {
         hipLaunchKernelGGL((sgf::k_tfwd_z<T, T>), dim3(cdiv(D.tmax_m, sgf::TB), nf, cdiv(nrhs, rc1)), dim3(sgf::WG),
                            (size_t)rc1 * D.tmax_m * e, st, D.tf.as<sgf::TFront>(), D.zt.as<T>(),
-                           D.slots.as<int32_t>(), y, n, D.uw.as<T>(), D.u_elems, nrhs, rc1);
+                           D.slots.as<int32_t>(), y, n, reinterpret_cast<T*>(W.uw[li]), D.u_elems, nrhs, rc1);
       }, L.t);
       launch(h, st, "apply_elim_fwd", 0, 0.5 * (cdiv(nrhs, rc2) * D.work.fwd_bytes + nrhs * D.work.fwd_vec), [&] {
         hipLaunchKernelGGL((sgf::k_tfwd_s<T, T>), dim3(std::max(1u, cdiv(D.tmax_k, sgf::TB)), nf, cdiv(nrhs, rc2)),
                            dim3(sgf::WG), (size_t)rc2 * (mp + sgf::WG) * e, st, D.tf.as<sgf::TFront>(),
-                           D.arena.as<T>(), D.uw.as<T>(), D.u_elems, D.slots.as<int32_t>(), y, n, ts, ldt, nrhs, rc2);
+                           D.arena.as<T>(), reinterpret_cast<T*>(W.uw[li]), D.u_elems, D.slots.as<int32_t>(), y, n, ts, ldt, nrhs, rc2);
       }, L.t);
       return;
     }
@@ -1702,11 +1772,11 @@ void run_sweeps(sgf_handle h, int nrhs, bool product, hipStream_t st) {
       launch(h, st, "apply_elim_bwd", 0, 0.5 * (cdiv(nrhs, rc1) * D.work.bwd_bytes + nrhs * D.work.bwd_vec), [&] {
         hipLaunchKernelGGL((sgf::k_tbwd_s<T, T>), dim3(cdiv(D.tmax_m, sgf::TB), nf, cdiv(nrhs, rc1)), dim3(sgf::WG),
                            (size_t)rc1 * std::max(D.tmax_k, 1) * e, st, D.tf.as<sgf::TFront>(), D.arena.as<T>(),
-                           D.slots.as<int32_t>(), D.nslots.as<int32_t>(), y, n, D.uw.as<T>(), D.u_elems, nrhs, rc1);
+                           D.slots.as<int32_t>(), D.nslots.as<int32_t>(), y, n, reinterpret_cast<T*>(W.uw[li]), D.u_elems, nrhs, rc1);
       }, L.t);
       launch(h, st, "apply_elim_bwd", 0, 0.5 * (cdiv(nrhs, rc2) * D.work.bwd_bytes + nrhs * D.work.bwd_vec), [&] {
         hipLaunchKernelGGL((sgf::k_tbwd_z<T, T>), dim3(cdiv(D.tmax_m, sgf::TB), nf, cdiv(nrhs, rc2)), dim3(sgf::WG),
-                           (size_t)rc2 * (mp + sgf::WG) * e, st, D.tf.as<sgf::TFront>(), D.zt.as<T>(), D.uw.as<T>(),
+                           (size_t)rc2 * (mp + sgf::WG) * e, st, D.tf.as<sgf::TFront>(), D.zt.as<T>(), reinterpret_cast<T*>(W.uw[li]),
                            D.u_elems, D.slots.as<int32_t>(), y, n, nrhs, rc2);
       }, L.t);
       return;
@@ -1797,11 +1867,11 @@ void run_sweeps(sgf_handle h, int nrhs, bool product, hipStream_t st) {
         hipLaunchKernelGGL(sgf::k_comp_apply_big<T>, dim3((unsigned)L.capply.size(), nb, cdiv(nrhs, rc)),
                            dim3(sgf::WG), (size_t)rc * (((ms + 3) & ~3) + sgf::WG) * sizeof(T), st,
                            D.capply.as<sgf::CompApply>(), D.tb.as<T>(), D.slots.as<int32_t>(), y, n, mode, nrhs, rc,
-                           D.cw.as<T>(), D.c_elems);
+                           reinterpret_cast<T*>(W.cw[li]), D.c_elems);
       }, L.t);
       launch(h, st, "apply_comp", 0, 0, [&] {
         hipLaunchKernelGGL(sgf::k_comp_scatter<T>, dim3((unsigned)L.capply.size(), nrhs), dim3(sgf::WG), 0, st,
-                           D.capply.as<sgf::CompApply>(), D.slots.as<int32_t>(), y, n, D.cw.as<T>(), D.c_elems);
+                           D.capply.as<sgf::CompApply>(), D.slots.as<int32_t>(), y, n, reinterpret_cast<T*>(W.cw[li]), D.c_elems);
       }, L.t);
       return;
     }
@@ -1843,12 +1913,12 @@ void run_sweeps(sgf_handle h, int nrhs, bool product, hipStream_t st) {
       launch(h, st, "apply_top", 0, 0.5 * tb, [&] {
         hipLaunchKernelGGL((sgf::k_tfwd_z<T, double>), dim3(cdiv(m, sgf::TB), 1, cdiv(nrhs, rc1)), dim3(sgf::WG),
                            (size_t)rc1 * m * sizeof(double), st, h->d_toptf.as<sgf::TFront>(), h->topz.as<double>(),
-                           D.slots.as<int32_t>(), y, n, h->topu.as<double>(), (int64_t)m, nrhs, rc1);
+                           D.slots.as<int32_t>(), y, n, reinterpret_cast<double*>(W.topu), (int64_t)m, nrhs, rc1);
       }, L.t);
       launch(h, st, "apply_top", 0, 0.5 * tb, [&] {
         hipLaunchKernelGGL((sgf::k_tbwd_z<T, double>), dim3(cdiv(m, sgf::TB), 1, cdiv(nrhs, rc2)), dim3(sgf::WG),
                            (size_t)rc2 * (mp + sgf::WG) * sizeof(double), st, h->d_toptf.as<sgf::TFront>(),
-                           h->topz.as<double>(), h->topu.as<double>(), (int64_t)m, D.slots.as<int32_t>(), y, n, nrhs,
+                           h->topz.as<double>(), reinterpret_cast<double*>(W.topu), (int64_t)m, D.slots.as<int32_t>(), y, n, nrhs,
                            rc2);
       }, L.t);
     } else if (m > 0) {
@@ -1905,25 +1975,29 @@ hipGraphExec_t capture_graph(sgf_handle h, F&& body) {
   return exec;
 }
 
+// ext: work vectors supplied by the caller (the allocation-free apply): no
+// buffer is grown, no graph is captured, every kernel is launched directly.
 template <typename T>
 void apply_impl(sgf_handle h, int nrhs, const double* r, int64_t ldr, double* z, int64_t ldz, bool product,
-                hipStream_t st) {
+                hipStream_t st, const ApplyWork* ext = nullptr) {
   const int64_t n = h->plan.n;
-  ensure_work<T>(h, nrhs);
+  if (!ext) ensure_work<T>(h, nrhs);
+  const ApplyWork W = ext ? *ext : handle_work(h);
+  T* yw = reinterpret_cast<T*>(W.y);
   dim3 g(cdiv(n, sgf::WG), nrhs);
   const double vb = (double)n * nrhs * (8.0 + sizeof(T)) + 8.0 * n;
   auto body = [&](hipStream_t s) {
     launch(h, s, "apply_perm", 0, vb, [&] {
       hipLaunchKernelGGL((sgf::k_gather_perm<double, T>), g, dim3(sgf::WG), 0, s, h->d_perm.as<int64_t>(), n, r, ldr,
-                         h->y.as<T>(), n);
+                         yw, n);
     });
-    run_sweeps<T>(h, nrhs, product, s);
+    run_sweeps<T>(h, nrhs, product, s, W);
     launch(h, s, "apply_perm", 0, vb, [&] {
       hipLaunchKernelGGL((sgf::k_scatter_perm<T, double>), g, dim3(sgf::WG), 0, s, h->d_perm.as<int64_t>(), n,
-                         h->y.as<T>(), n, z, ldz);
+                         yw, n, z, ldz);
     });
   };
-  if (!h->use_graph || h->capturing) {
+  if (!h->use_graph || h->capturing || ext) {
     body(st);
     HIP_CHECK(hipGetLastError());
     return;
@@ -1967,7 +2041,8 @@ void dot_cols(sgf_handle h, const double* a, const double* b, int nrhs, double* 
 // Device memory held by the handle.
 int64_t device_bytes(sgf_handle h) {
   int64_t b = 0;
-  for (const DevBuf* x : {&h->d_perm, &h->d_rowptr, &h->d_colidx, &h->d_vals, &h->d_csrdst, &h->d_coords, &h->d_fail,
+  for (const DevBuf* x : {&h->d_perm, &h->d_rowptr, &h->d_colidx, &h->d_vals, &h->d_csrdst, &h->d_coords,
+                          &h->d_basis, &h->d_fail,
                           &h->d_ctr, &h->d_zero_idx,
                           &h->y, &h->tscr, &h->cg_r, &h->cg_z, &h->cg_p, &h->cg_ap, &h->cg_x, &h->cg_part, &h->cg_st,
                           &h->cg_scal, &h->top64, &h->topz, &h->topu, &h->d_topdesc, &h->d_toptf})
@@ -1976,7 +2051,8 @@ int64_t device_bytes(sgf_handle h) {
     for (const DevBuf* x : {&D.arena, &D.scratch, &D.cf, &D.nbuf, &D.ltphi, &D.tau, &D.phi, &D.rank, &D.elim,
                             &D.pairs, &D.schur, &D.comp, &D.compnbr, &D.sepacc, &D.sepsrc, &D.capply, &D.slots,
                             &D.nslots, &D.blkmap, &D.phimap, &D.slotptr, &D.phioff, &D.tb, &D.active, &D.tofcomp,
-                            &D.tf, &D.zt, &D.uw, &D.ctf, &D.elim_order, &D.comp_order, &D.cw, &D.band_list, &D.pk})
+                            &D.tf, &D.zt, &D.uw, &D.ctf, &D.elim_order, &D.comp_order, &D.cw, &D.band_list, &D.pk,
+                            &D.fixrank})
       b += x->bytes;
   return b;
 }
@@ -2029,7 +2105,9 @@ sgf_status sgf_analyze(int64_t n, const int64_t* row_ptr, const int32_t* col_idx
   if (!h) return fail(SGF_ENOMEM, "handle allocation failed");
   sgf_status st = guard([&] {
     check_options(opt, n);
-    if (!row_ptr || !col_idx || !coords) throw SgfError(SGF_EINVAL, "NULL input array");
+    if (!row_ptr || !col_idx) throw SgfError(SGF_EINVAL, "NULL input array");
+    if (!coords && opt->q != 0)
+      throw SgfError(SGF_EINVAL, "coordinates are needed for polynomial degree q > 0 (q = 0 or a user basis needs none)");
     sgf::Options& o = h->plan.opt;
     o.dim = opt->dim;
     for (int a = 0; a < 3; ++a) o.grid[a] = a < opt->dim ? opt->grid[a] : 1;
@@ -2054,12 +2132,12 @@ sgf_status sgf_analyze(int64_t n, const int64_t* row_ptr, const int32_t* col_idx
     h->nnz = row_ptr[n];
     h->h_rowptr.assign(row_ptr, row_ptr + n + 1);
     h->h_colidx.assign(col_idx, col_idx + h->nnz);
-    h->h_coords.assign(coords, coords + h->plan.n_nodes * o.dim);
+    if (coords) h->h_coords.assign(coords, coords + h->plan.n_nodes * o.dim);
     for (int a = 0; a < 3; ++a) {
       h->plan.cmin[a] = 0;
       h->plan.cmax[a] = 0;
     }
-    for (int a = 0; a < o.dim; ++a) {
+    for (int a = 0; coords && a < o.dim; ++a) {
       double lo = coords[a], hi = coords[a];
       for (int64_t v = 0; v < h->plan.n_nodes; ++v) {
         lo = std::min(lo, coords[v * o.dim + a]);
@@ -2370,7 +2448,8 @@ sgf_status sgf_release(sgf_handle h) {
   return guard([&] {
     h->drop_graph();
     h->lev.clear();
-    for (DevBuf* b : {&h->d_perm, &h->d_rowptr, &h->d_colidx, &h->d_vals, &h->d_csrdst, &h->d_coords, &h->d_fail,
+    for (DevBuf* b : {&h->d_perm, &h->d_rowptr, &h->d_colidx, &h->d_vals, &h->d_csrdst, &h->d_coords, &h->d_basis,
+                      &h->d_fail,
                       &h->d_ctr, &h->d_zero_idx,
                       &h->y, &h->tscr, &h->cg_r, &h->cg_z, &h->cg_p, &h->cg_ap, &h->cg_x, &h->cg_part, &h->cg_st,
                       &h->cg_scal, &h->top64, &h->topz, &h->topu, &h->d_topdesc, &h->d_toptf})
@@ -2484,6 +2563,111 @@ sgf_status sgf_get_level(sgf_handle h, int32_t level, int32_t* count, int32_t* c
   return SGF_OK;
 }
 
+}  // extern "C"
+
+namespace {
+template <typename T>
+std::vector<double> read_block(const DevBuf& b, int64_t off, int64_t elems) {
+  std::vector<T> tmp((size_t)std::max<int64_t>(elems, 0));
+  if (elems > 0) {
+    if ((size_t)(off + elems) * sizeof(T) > b.bytes) throw SgfError(SGF_EINVAL, "factor block outside its buffer");
+    HIP_CHECK(hipMemcpy(tmp.data(), b.as<T>() + off, elems * sizeof(T), hipMemcpyDeviceToHost));
+  }
+  return std::vector<double>(tmp.begin(), tmp.end());
+}
+std::vector<double> read_any(sgf_handle h, const DevBuf& b, int64_t off, int64_t elems) {
+  return h->esz == 8 ? read_block<double>(b, off, elems) : read_block<float>(b, off, elems);
+}
+}  // namespace
+
+extern "C" {
+
+sgf_status sgf_block_count(sgf_handle h, int32_t level, int32_t* n_elim, int32_t* n_comp) {
+  if (!h || !n_elim || !n_comp) return fail(SGF_EINVAL, "NULL argument");
+  if (!h->factored) return fail(SGF_ESTATE, "the handle is not factored");
+  if (level < 1 || level > (int)h->plan.levels.size()) return fail(SGF_EINVAL, "level out of range");
+  const sgf::Level& L = h->plan.levels[level - 1];
+  *n_elim = L.top ? 1 : (int32_t)L.elim.size();
+  *n_comp = L.top ? 0 : (int32_t)L.capply.size();
+  return SGF_OK;
+}
+
+sgf_status sgf_export_block(sgf_handle h, int32_t level, int32_t index, sgf_block* info, double* L_out,
+                            double* W_out, double* V_out, double* tau_out, double* rdiag_out) {
+  if (!h || !info) return fail(SGF_EINVAL, "NULL argument");
+  if (!h->factored) return fail(SGF_ESTATE, "the handle is not factored");
+  if (level < 1 || level > (int)h->plan.levels.size()) return fail(SGF_EINVAL, "level out of range");
+  return guard([&] {
+    const sgf::Level& L = h->plan.levels[level - 1];
+    const LevelDev& D = h->lev[level - 1];
+    *info = sgf_block{};
+    HIP_CHECK(hipDeviceSynchronize());
+    if (L.top) {
+      if (index != 0) throw SgfError(SGF_EINVAL, "the top level has one block");
+      const int R = L.elim[0].m;
+      info->kind = SGF_BLOCK_TOP;
+      info->cell = -1;
+      info->m = R;
+      if (L_out && R > 0) {
+        std::vector<double> f = read_block<double>(h->top64, 0, (int64_t)R * R);
+        for (int j = 0; j < R; ++j)
+          for (int i = 0; i < R; ++i) L_out[i + (int64_t)j * R] = i >= j ? f[i + (int64_t)j * R] : 0.0;
+      }
+      return;
+    }
+    const int ne = (int)L.elim.size(), nq = (int)L.capply.size();
+    if (index < 0 || index >= ne + nq) throw SgfError(SGF_EINVAL, "block index out of range");
+    if (index < ne) {
+      const sgf::ElimDesc& e = L.elim[index];
+      const int m = e.m, k = e.k;
+      const int64_t ld = (int64_t)m + k;
+      info->kind = SGF_BLOCK_ELIM;
+      info->cell = (int32_t)L.cell[e.cluster];
+      info->m = m;
+      info->k = k;
+      if (!L_out && !W_out) return;
+      std::vector<double> f = read_any(h, D.arena, e.front_off, ld * m);   // the first m columns
+      for (int j = 0; j < m; ++j) {
+        if (L_out)
+          for (int i = 0; i < m; ++i) L_out[i + (int64_t)j * m] = i >= j ? f[i + j * ld] : 0.0;
+        if (W_out)
+          for (int q = 0; q < k; ++q) W_out[j + (int64_t)q * m] = f[(m + q) + j * ld];   // W = (rows m.. of [L; W^T])^T
+      }
+      return;
+    }
+    const sgf::CompApply& a = L.capply[index - ne];
+    int ci = -1;
+    for (size_t c = 0; c < L.comp.size(); ++c)
+      if (L.comp[c].cf_off == a.cf_off) ci = (int)c;
+    if (ci < 0) throw SgfError(SGF_EINVAL, "compressed separator not found");
+    const sgf::CompDesc& d = L.comp[ci];
+    const int sdim = d.s, r = L.rank[ci];
+    info->kind = SGF_BLOCK_COMP;
+    info->cell = (int32_t)L.cell[d.cluster];
+    info->m = sdim;
+    info->k = d.K;
+    info->r = r;
+    if (L_out) {
+      const int64_t ld = (int64_t)sdim + d.K;
+      std::vector<double> f = read_any(h, D.cf, d.cf_off, ld * sdim);
+      for (int j = 0; j < sdim; ++j)
+        for (int i = 0; i < sdim; ++i) L_out[i + (int64_t)j * sdim] = i >= j ? f[i + j * ld] : 0.0;
+    }
+    if (V_out || rdiag_out) {
+      std::vector<double> v = read_any(h, D.nbuf, d.n_off, (int64_t)sdim * r);
+      for (int j = 0; j < r; ++j) {
+        if (rdiag_out) rdiag_out[j] = v[j + (int64_t)j * sdim];
+        for (int i = 0; V_out && i < sdim; ++i)
+          V_out[i + (int64_t)j * sdim] = i < j ? 0.0 : i == j ? 1.0 : v[i + (int64_t)j * sdim];
+      }
+    }
+    if (tau_out) {
+      std::vector<double> t = read_any(h, D.tau, d.tau_off, r);
+      std::copy(t.begin(), t.end(), tau_out);
+    }
+  });
+}
+
 sgf_status sgf_plan_dry_run(sgf_handle h, sgf_rank_fn rank_fn, void* ctx) {
   if (!h || !rank_fn) return fail(SGF_EINVAL, "NULL argument");
   if (h->factored) return fail(SGF_ESTATE, "dry run on a factorized handle");
@@ -2524,11 +2708,83 @@ sgf_status sgf_set_band_elim(sgf_handle h, int32_t enable) {
   return guard([&] { h->band_elim = enable != 0; });
 }
 
+sgf_status sgf_set_pair_kernel(sgf_handle h, int32_t mode) {
+  if (!h || mode < -1 || mode > 1) return fail(SGF_EINVAL, "pair kernel mode must be -1, 0 or 1");
+  h->pair_mode = mode;
+  return SGF_OK;
+}
+
 sgf_status sgf_set_band_apply(sgf_handle h, int32_t enable) {
   if (!h) return fail(SGF_EINVAL, "NULL handle");
   return guard([&] {
     h->band_apply = enable != 0;
     h->drop_graph();
+  });
+}
+
+}  // extern "C"
+
+namespace {
+// Plan level 1 afresh (after the basis width or the compression changed) and
+// drop every level's device state and the factor; the analysis inputs stay.
+void replan(sgf_handle h) {
+  h->drop_graph();
+  h->lev.clear();
+  h->plan.levels.clear();
+  h->plan.parts.clear();
+  sgf::plan_level1(h->plan, h->h_rowptr.data(), h->h_colidx.data());
+  h->dev_static = false;
+  h->factored = false;
+  h->top_tiled = false;
+  ++h->epoch;
+}
+}  // namespace
+
+extern "C" {
+
+sgf_status sgf_set_basis(sgf_handle h, int32_t ncols, const double* basis) {
+  if (!h) return fail(SGF_EINVAL, "NULL handle");
+  if (ncols < 0 || ncols > SGF_MAX_BASIS_COLS || (ncols > 0 && !basis))
+    return fail(SGF_EINVAL, "basis: 1.." + std::to_string(SGF_MAX_BASIS_COLS) + " columns and a host array are needed");
+  if (ncols == 0 && h->plan.opt.q != 0 && h->h_coords.empty())
+    return fail(SGF_EINVAL, "no coordinates for the monomial basis of degree q > 0");
+  return guard([&] {
+    sgf::Plan& P = h->plan;
+    for (int64_t i = 0; i < P.n * (int64_t)ncols; ++i)
+      if (!std::isfinite(basis[i])) throw SgfError(SGF_EINVAL, "basis holds a non-finite value");
+    if (ncols > 0) {
+      h->h_basis.assign(basis, basis + P.n * (int64_t)ncols);
+      P.pi = ncols;
+    } else {
+      h->h_basis.clear();
+      P.pi = sgf::poly_cols(P.opt.dim, P.opt.q, P.opt.dpn);
+    }
+    h->d_basis.release();
+    h->low_rank = false;
+    h->lr_rank.clear();
+    P.opt.compression = 0;
+    replan(h);
+  });
+}
+
+sgf_status sgf_set_low_rank(sgf_handle h, int32_t enable) {
+  if (!h) return fail(SGF_EINVAL, "NULL handle");
+  return guard([&] {
+    sgf::Plan& P = h->plan;
+    if (enable) {
+      if (h->low_rank) return;
+      if (!h->factored) throw SgfError(SGF_ESTATE, "low-rank mode needs a polynomial factorization to take the ranks from");
+      h->lr_rank.assign(P.levels.size(), {});
+      for (size_t li = 0; li + 1 < P.levels.size(); ++li) h->lr_rank[li] = P.levels[li].rank;
+      h->low_rank = true;
+      P.opt.compression = 1;
+    } else {
+      if (!h->low_rank) return;
+      h->low_rank = false;
+      h->lr_rank.clear();
+      P.opt.compression = 0;
+    }
+    replan(h);
   });
 }
 

@@ -31,7 +31,14 @@ struct Options {
   int stop_rule = 0;
   int precision = 0;
   double rank_tol = 1e-12;
+  // 0: polynomial compression (Eq. 3.2); 1: the standard low-rank
+  // equivalent (Sec. 7.4, Eq. 7.5): Q from the pivoted QR of the scaled
+  // off-diagonal block itself, cut at ranks recorded beforehand
+  int compression = 0;
 };
+
+// Schemes (Sec. 5): which separator cells are compressed and how.
+enum { SCHEME_NEST_ALL_ALL = 0, SCHEME_NEST_2_ALL = 1, SCHEME_NEST_2_2 = 2, SCHEME_GEN_ALL_ALL = 3 };
 
 inline int poly_cols(int dim, int q, int dpn) {
   int p0 = q == 0 ? 1 : (q == 1 ? 1 + dim : (dim == 2 ? 6 : 10));
@@ -45,6 +52,18 @@ struct Axis {
   int32_t K = 1;
   std::vector<int32_t> rep;  // first index of each class
 };
+
+// General partition (Sec. 5.2): boxes of d consecutive vertices per axis
+// (the last one shorter when d does not divide N); class = i / d.
+inline Axis axis_boxes(int N, int d) {
+  Axis a;
+  a.cls.resize(N);
+  for (int i = 0; i < N; ++i) a.cls[i] = i / d;
+  a.K = (N + d - 1) / d;
+  a.rep.assign(a.K, -1);
+  for (int i = N - 1; i >= 0; --i) a.rep[a.cls[i]] = i;
+  return a;
+}
 
 inline Axis axis_classes(int N, int d) {
   Axis a;
@@ -64,6 +83,7 @@ inline Axis axis_classes(int N, int d) {
 struct Partition {
   int d = 0;
   int dim = 2;
+  bool general = false;   // boxes of a general partition: every cell is compressed, none is an interior
   Axis ax[3];
   int64_t ncells = 1;
   bool is_root = false;
@@ -81,6 +101,7 @@ struct Partition {
     cls[2] = dim >= 3 ? (int)cid : 0;
   }
   int type_of(int64_t cid) const {
+    if (general) return 1;
     int c[3];
     split(cid, c);
     int t = 0;
@@ -93,15 +114,32 @@ inline Partition make_partition(const Options& o, int d) {
   Partition p;
   p.d = d;
   p.dim = o.dim;
+  p.general = o.scheme == SCHEME_GEN_ALL_ALL;
   p.ncells = 1;
   bool root = true;
   for (int a = 0; a < o.dim; ++a) {
-    p.ax[a] = axis_classes(o.grid[a], d);
+    p.ax[a] = p.general ? axis_boxes(o.grid[a], d) : axis_classes(o.grid[a], d);
     p.ncells *= p.ax[a].K;
     if (p.ax[a].K > 1) root = false;
   }
   p.is_root = root;
   return p;
+}
+
+// Whether cell Y lies on the boundary of cell B in a nested-dissection
+// partition (Sec. 5.1): Y != B, Y has B's class on every axis where B is a
+// slab (odd class) and a class within one of B's on every other axis -- the
+// edges and corners around a face, the two end corners of a 2D edge.
+inline bool on_boundary(const Partition& p, int64_t B, int64_t Y) {
+  if (B == Y || p.general) return false;
+  int cb[3], cy[3];
+  p.split(B, cb);
+  p.split(Y, cy);
+  for (int a = 0; a < p.dim; ++a) {
+    if ((cb[a] & 1) && cy[a] != cb[a]) return false;
+    if (std::abs(cy[a] - cb[a]) > 1) return false;
+  }
+  return true;
 }
 
 // Father of a cell of partition `lo` in the coarser partition `hi` (Sec. 4.3).
@@ -158,14 +196,20 @@ struct CompDesc {
   int64_t ltphi_off;    // scratch s x pi
   int64_t tau_off;      // c entries
   int64_t slot_off;     // slots of B
-  int32_t s, K, c, nnb, nb_ptr, cluster, blk_diag_pad;
+  int32_t s, K, c, nnb, nb_ptr, cluster;
+  int32_t self_cols;    // columns of L_B^T Phi_B at the start of N (pi; 0 for the low-rank equivalent)
   int64_t blk_diag;     // offset of M_BB pair block
   int64_t tb_off;       // s x s slot for T_B = Q^T L_B^{-1} (filled when the separator compresses)
 };
+// Columns of N that neighbour X contributes (Eq. 4.5): Mhat_BX Phi_X (pi
+// columns), or Mhat_BX itself (s_X columns, `full`) for a cell on B's
+// boundary in Nest-2-2 (Sec. 5.1) and for every neighbour in the low-rank
+// equivalent (Eq. 7.5).
 struct CompNbr {
   int64_t blk_off;      // pair block holding M_BX (if X > B) or M_XB (X < B)
   int64_t phi_off;      // Phi_X (ld s_X)
-  int32_t s_x, trans, row, pad;  // trans = 1: block stored as M_BX (s x s_X)
+  int32_t s_x, trans, row, full;  // trans = 1: block stored as M_BX (s x s_X)
+  int32_t col, pad;     // first column in N
 };
 
 // Apply of one compressed separator: y_B <- Q^T L_B^{-1} y_B and back.
@@ -244,6 +288,7 @@ struct Level {
   std::vector<int32_t> schur_ii;             // per Schur entry: interior index
   std::vector<int64_t> schur_ex, schur_ey;   //   and its adjacency entries x <= y
   std::vector<int32_t> cnbr_x, cnbr_pid;     // per compression neighbour: cluster, pair id
+  std::vector<uint8_t> cnbr_full;            //   and whether it enters N whole
   std::vector<int32_t> pair_rowa, pair_rowb; // per pair: neighbour entry giving row_in_a / row_in_b (-1: none)
   std::vector<int32_t> sacc_p;               // per SepAcc: separator position
   std::vector<int32_t> sacc_ii;              // per sepacc_src entry: interior index
@@ -300,15 +345,35 @@ struct Plan {
 
 // ---------------------------------------------------------------------------
 
+// Which cells a scheme compresses (Sec. 5): Gen-All-All every box of the
+// general partition; Nest-All-All every separator cell but single vertices;
+// Nest-2-All and Nest-2-2 the cells of codimension one (faces in 3D, edges
+// in 2D).
 inline bool compressible(int type, int dim, int scheme) {
+  if (scheme == SCHEME_GEN_ALL_ALL) return true;
   if (type == 0 || type == dim) return false;
-  if (scheme == 0) return true;
+  if (scheme == SCHEME_NEST_ALL_ALL) return true;
   return type == 1;
+}
+
+// Columns of N for compression d from its neighbours' sizes and `full`
+// flags (Eq. 4.5; whole blocks for Nest-2-2 boundary cells and for the
+// low-rank equivalent, which also drops the L_B^T Phi_B block and pads N
+// with zero columns to at least s, so that a recorded rank up to s is a
+// number of QR steps).
+inline void comp_columns(CompDesc& d, CompNbr* nb, int pi, int compression) {
+  d.self_cols = compression == 1 ? 0 : pi;
+  int col = d.self_cols;
+  for (int q = 0; q < d.nnb; ++q) {
+    nb[q].col = col;
+    col += nb[q].full ? nb[q].s_x : pi;
+  }
+  d.c = compression == 1 ? std::max(col, d.s) : col;
 }
 
 // Derive interiors, fronts, separator pairs, Schur lists and compression
 // descriptors of a level whose clusters, sizes, slots and adjacency are set.
-inline void build_level(Level& L, const Options& o, int pi) {
+inline void build_level(Level& L, const Options& o, int pi, const Partition* part = nullptr) {
   const int nc = (int)L.cell.size();
   L.interiors.clear();
   L.seps.clear();
@@ -485,6 +550,7 @@ inline void build_level(Level& L, const Options& o, int pi) {
   L.comp_nbr.clear();
   L.cnbr_x.clear();
   L.cnbr_pid.clear();
+  L.cnbr_full.clear();
   L.comp_of.assign(nc, -1);
   L.cf_elems = L.n_elems = L.ltphi_elems = L.tau_elems = L.tb_elems = 0;
   L.max_cf_rows = L.max_c = L.max_s = 0;
@@ -509,13 +575,16 @@ inline void build_level(Level& L, const Options& o, int pi) {
         nbx.s_x = L.size[X];
         nbx.phi_off = L.phi_off[X];
         nbx.row = d.s + K;
+        nbx.full = o.compression == 1 ||
+                   (o.scheme == SCHEME_NEST_2_2 && part && on_boundary(*part, L.cell[B], L.cell[X]));
         K += L.size[X];
         L.comp_nbr.push_back(nbx);
         L.cnbr_x.push_back(X);
         L.cnbr_pid.push_back(pid);
+        L.cnbr_full.push_back((uint8_t)nbx.full);
       }
       d.K = K;
-      d.c = pi * (1 + d.nnb);
+      comp_columns(d, L.comp_nbr.data() + d.nb_ptr, pi, o.compression);
       d.cf_off = L.cf_elems;
       L.cf_elems += (int64_t)(d.s + K) * d.s;
       d.n_off = L.n_elems;
@@ -606,7 +675,7 @@ inline void build_level(Level& L, const Options& o, int pi) {
 // Every size-dependent field of a level whose structure build_level has
 // recorded, from its current cluster sizes: the same values build_level
 // gives for these sizes, without its adjacency searches and sorts.
-inline void build_offsets(Level& L, int pi) {
+inline void build_offsets(Level& L, int pi, int compression) {
   const int nc = (int)L.cell.size();
   L.n_active = 0;
   for (int c = 0; c < nc; ++c) L.n_active += L.size[c];
@@ -685,9 +754,11 @@ inline void build_offsets(Level& L, int pi) {
       nbx.s_x = L.size[X];
       nbx.phi_off = L.phi_off[X];
       nbx.row = d.s + K;
+      nbx.full = L.cnbr_full[at];
       K += L.size[X];
     }
     d.K = K;
+    comp_columns(d, L.comp_nbr.data() + d.nb_ptr, pi, compression);
     d.cf_off = L.cf_elems;
     L.cf_elems += (int64_t)(d.s + K) * d.s;
     d.n_off = L.n_elems;
@@ -775,9 +846,15 @@ inline void validate_level(const Level& L, int64_t n, int pi) {
       req(x.blk_off >= 0 && x.blk_off + (int64_t)d.s * x.s_x <= L.blk_elems, "neighbour block");
       req(x.phi_off >= 0 && x.phi_off + (int64_t)x.s_x * pi <= L.phi_elems, "neighbour Phi");
       req(x.row == d.s + K, "neighbour row");
+      req(x.col >= d.self_cols && x.col + (x.full ? x.s_x : pi) <= d.c, "neighbour columns of N");
+      req(q == 0 || x.col == L.comp_nbr[d.nb_ptr + q - 1].col + (L.comp_nbr[d.nb_ptr + q - 1].full
+                                                                    ? L.comp_nbr[d.nb_ptr + q - 1].s_x : pi),
+          "neighbour columns in order");
       K += x.s_x;
     }
     req(K == d.K, "neighbour total");
+    req(d.self_cols == 0 || d.self_cols == pi, "self columns of N");
+    req(d.c >= d.self_cols && d.c >= 1, "columns of N");
   }
   for (const auto& a : L.sepacc) {
     req(a.slot_off >= 0 && a.slot_off + a.s <= nsl, "separator slots");
@@ -876,7 +953,7 @@ inline void plan_level1(Plan& P, const int64_t* row_ptr, const int32_t* col_idx)
     L.adj_idx.insert(L.adj_idx.end(), v.begin(), v.end());
     L.adj_ptr[c + 1] = (int64_t)L.adj_idx.size();
   }
-  build_level(L, o, P.pi);
+  build_level(L, o, P.pi, &part);
   P.max_node = 0;
   for (int c = 0; c < nc; ++c) P.max_node = std::max<int64_t>(P.max_node, L.size[c]);
   // CSR fill destinations
@@ -1102,7 +1179,7 @@ inline void plan_next_level(Plan& P, std::vector<CopyDesc>& blk_map, std::vector
       N.adj_ptr[fa + 1] = (int64_t)N.adj_idx.size();
     }
   }
-  build_level(N, o, P.pi);
+  build_level(N, o, P.pi, &hi);
   // where each level-C pair block goes (by the new level's structure)
   const int ncp = (int)C.pairs.size();
   N.cp_kind.assign(ncp, -1);
@@ -1205,7 +1282,7 @@ inline bool update_next_level(Plan& P, size_t li, std::vector<CopyDesc>& blk_map
     std::copy(C.slots.begin() + C.slot_ptr[a], C.slots.begin() + C.slot_ptr[a] + r,
               N.slots.begin() + N.slot_ptr[father[p]] + loc[p]);
   }
-  build_offsets(N, P.pi);
+  build_offsets(N, P.pi, P.opt.compression);
   emit_copy_maps(C, N, father, loc, P.pi, blk_map, phi_map);
   validate_level(N, P.n, P.pi);
   validate_copies(blk_map, C.front_elems + C.blk_elems, N.front_elems + N.blk_elems);

@@ -14,14 +14,15 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsgf.so")
 
 SGF_OK, SGF_EINVAL, SGF_ENOTSPD, SGF_ENOMEM, SGF_EDEVICE, SGF_ENOCONV, SGF_ESTATE = range(7)
-NEST_ALL_ALL, NEST_2_ALL = 0, 1
+NEST_ALL_ALL, NEST_2_ALL, NEST_2_2, GEN_ALL_ALL = 0, 1, 2, 3
+MAX_BASIS_COLS = 64
 STOP_ROOT, STOP_PAPER = 0, 1
 FP64, FP32, FP32_BF16N = 0, 1, 2
 
 EXPORTED = ["sgf_default_options", "sgf_analyze", "sgf_factorize_numeric", "sgf_factorize", "sgf_autotune",
             "sgf_apply", "sgf_multiply", "sgf_pcg_solve", "sgf_spmv", "sgf_get_info",
             "sgf_get_perm", "sgf_get_level", "sgf_plan_dry_run", "sgf_profile_enable", "sgf_profile_read", "sgf_profile_select",
-            "sgf_set_apply_graph", "sgf_set_persistent", "sgf_set_band_apply", "sgf_set_band_elim", "sgf_set_small_compress", "sgf_release", "sgf_estimate_bytes",
+            "sgf_set_apply_graph", "sgf_set_persistent", "sgf_set_basis", "sgf_set_low_rank", "sgf_set_pair_kernel", "sgf_block_count", "sgf_export_block", "sgf_set_band_apply", "sgf_set_band_elim", "sgf_set_small_compress", "sgf_release", "sgf_estimate_bytes",
             "sgf_server_default_options", "sgf_server_create", "sgf_server_add_operator", "sgf_server_submit",
             "sgf_server_wait", "sgf_server_get_stats", "sgf_server_clock", "sgf_server_destroy",
             "sgf_destroy", "sgf_status_str", "sgf_last_error"]
@@ -43,6 +44,14 @@ class Info(ctypes.Structure):
                 ("compressed", ctypes.c_int64), ("factor_flops", ctypes.c_double),
                 ("apply_bytes", ctypes.c_double), ("failed_cluster", ctypes.c_int32),
                 ("failed_level", ctypes.c_int32), ("device_bytes", ctypes.c_int64)]
+
+
+class Block(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("cell", ctypes.c_int32), ("m", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("r", ctypes.c_int32)]
+
+
+BLOCK_ELIM, BLOCK_COMP, BLOCK_TOP = 0, 1, 2
 
 
 class KernelStat(ctypes.Structure):
@@ -101,6 +110,11 @@ def load_library(path=LIB_PATH):
         "sgf_set_band_apply": (I32, [H, I32]),
         "sgf_set_band_elim": (I32, [H, I32]),
         "sgf_set_small_compress": (I32, [H, I32]),
+        "sgf_set_basis": (I32, [H, I32, P]),
+        "sgf_block_count": (I32, [H, I32, P, P]),
+        "sgf_export_block": (I32, [H, I32, I32, ctypes.POINTER(Block), P, P, P, P, P]),
+        "sgf_set_low_rank": (I32, [H, I32]),
+        "sgf_set_pair_kernel": (I32, [H, I32]),
         "sgf_release": (I32, [H]),
         "sgf_estimate_bytes": (I32, [H, I32, P]),
         "sgf_server_default_options": (None, [ctypes.POINTER(ServerOptions)]),
@@ -151,11 +165,54 @@ def _ptr(a):
     return ctypes.c_void_p(a.ctypes.data) if isinstance(a, np.ndarray) else ctypes.c_void_p(a.data_ptr())
 
 
+def _dev(t, n, what):
+    """Checks that ``t`` is what the C ABI expects of a vector argument: a
+    CUDA float64 tensor holding an n x nrhs column-major array with leading
+    dimension n (1-D of length n, or 2-D of shape (n, nrhs) with strides
+    (1, n), e.g. the transpose of a contiguous (nrhs, n) tensor).  Returns
+    nrhs."""
+    if isinstance(t, np.ndarray) or not hasattr(t, "device"):
+        raise ValueError(f"{what}: a CUDA tensor is required, got {type(t).__name__}")
+    if t.device.type != "cuda":
+        raise ValueError(f"{what}: the tensor is on {t.device}, the library needs device memory")
+    if str(t.dtype) != "torch.float64":
+        raise ValueError(f"{what}: dtype {t.dtype}, float64 is required")
+    if t.dim() == 1:
+        if t.shape[0] != n or (n > 1 and t.stride(0) != 1):
+            raise ValueError(f"{what}: a contiguous vector of length {n} is required")
+        return 1
+    if t.dim() != 2 or t.shape[0] != n:
+        raise ValueError(f"{what}: shape {tuple(t.shape)}, (n, nrhs) with n = {n} is required")
+    if t.shape[1] > 1 and (t.stride(0) != 1 or t.stride(1) != n):
+        raise ValueError(f"{what}: strides {t.stride()}, column-major (1, {n}) are required")
+    if t.shape[1] == 1 and t.stride(0) != 1:
+        raise ValueError(f"{what}: the column must be contiguous")
+    return t.shape[1]
+
+
+def _pair(a, b, n, names):
+    na, nb = _dev(a, n, names[0]), _dev(b, n, names[1])
+    if na != nb:
+        raise ValueError(f"{names[0]} has {na} columns, {names[1]} {nb}")
+    return na
+
+
 def _stream(stream):
     if stream is None:
         import torch
         return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
     return ctypes.c_void_p(stream)
+
+
+def _vals(v, nnz):
+    """CSR values for a numeric factorization: a contiguous CUDA float64
+    tensor with one entry per stored pattern entry."""
+    if isinstance(v, np.ndarray) or not hasattr(v, "device"):
+        raise ValueError("values: a CUDA tensor is required")
+    if str(v.dtype) != "torch.float64" or v.numel() != nnz or not v.is_contiguous():
+        raise ValueError(f"values: a contiguous float64 tensor of {nnz} entries is required")
+    if v.device.type != "cuda":
+        raise ValueError("values: pass a CUDA tensor or a numpy array")
 
 
 class Solver:
@@ -169,17 +226,37 @@ class Solver:
         self.n = int(n)
         self._indptr = np.ascontiguousarray(indptr, dtype=np.int64)
         self._indices = np.ascontiguousarray(indices, dtype=np.int32)
-        self._coords = np.ascontiguousarray(coords, dtype=np.float64)
+        self._coords = None if coords is None else np.ascontiguousarray(coords, dtype=np.float64)
         self.opt = opt
         h = ctypes.c_void_p()
-        _check(_lib.sgf_analyze(self.n, _ptr(self._indptr), _ptr(self._indices), _ptr(self._coords),
+        _check(_lib.sgf_analyze(self.n, _ptr(self._indptr), _ptr(self._indices),
+                                None if self._coords is None else _ptr(self._coords),
                                 ctypes.byref(opt), ctypes.byref(h)))
         self.h = h
 
     @classmethod
-    def from_problem(cls, prob, **kw):
+    def from_problem(cls, prob, coords=True, **kw):
+        """coords=False analyzes without the node positions (q = 0, or a
+        basis given next with set_basis)."""
         opt = make_options(prob.dim, prob.grid, prob.dpn, **kw)
-        return cls(prob.n, prob.indptr, prob.indices, prob.coords, opt)
+        return cls(prob.n, prob.indptr, prob.indices, prob.coords if coords else None, opt)
+
+    def set_basis(self, basis):
+        """Near-kernel basis Pi (n x ncols, numpy) replacing the monomials;
+        None returns to the monomials.  Drops the factor."""
+        if basis is None:
+            _check(_lib.sgf_set_basis(self.h, 0, None))
+            return
+        b = np.asfortranarray(basis, dtype=np.float64)
+        if b.ndim != 2 or b.shape[0] != self.n:
+            raise ValueError(f"basis: shape {b.shape}, (n, ncols) with n = {self.n} is required")
+        _check(_lib.sgf_set_basis(self.h, int(b.shape[1]), ctypes.c_void_p(b.ctypes.data)))
+
+    def set_low_rank(self, enable=True):
+        """Standard low-rank equivalent (Eq. 7.5) at the ranks of the current
+        polynomial factorization (enable), or back to the polynomial
+        compression.  Drops the factor."""
+        _check(_lib.sgf_set_low_rank(self.h, 1 if enable else 0))
 
     def close(self):
         if self.h:
@@ -193,28 +270,32 @@ class Solver:
             pass
 
     def factorize(self, vals, stream=None):
+        _vals(vals, self._indices.size)
         _check(_lib.sgf_factorize_numeric(self.h, _ptr(vals), _stream(stream)))
 
     def autotune(self, vals, napply=30, stream=None):
         """Per-level elimination path / panel width by timing; returns the
         chosen mode per level (0 tiled, 8/16/32 panel width, -1 none)."""
+        _vals(vals, self._indices.size)
         modes = np.zeros(64, dtype=np.int32)
         _check(_lib.sgf_autotune(self.h, _ptr(vals), int(napply), _ptr(modes), _stream(stream)))
         return modes[:self.info()["levels"]]
 
     def apply(self, r, z, stream=None):
-        nrhs = 1 if r.dim() == 1 else r.shape[1]
+        nrhs = _pair(r, z, self.n, ("r", "z"))
         _check(_lib.sgf_apply(self.h, nrhs, _ptr(r), self.n, _ptr(z), self.n, _stream(stream)))
 
     def multiply(self, v, y, stream=None):
-        nrhs = 1 if v.dim() == 1 else v.shape[1]
+        nrhs = _pair(v, y, self.n, ("v", "y"))
         _check(_lib.sgf_multiply(self.h, nrhs, _ptr(v), self.n, _ptr(y), self.n, _stream(stream)))
 
     def spmv(self, v, y, stream=None):
+        if _pair(v, y, self.n, ("v", "y")) != 1:
+            raise ValueError("spmv takes one column")
         _check(_lib.sgf_spmv(self.h, _ptr(v), _ptr(y), _stream(stream)))
 
     def pcg(self, b, x, rtol=1e-8, maxit=500, stream=None, raise_on_noconv=True):
-        nrhs = 1 if b.dim() == 1 else b.shape[1]
+        nrhs = _pair(b, x, self.n, ("b", "x"))
         iters = np.zeros(nrhs, dtype=np.int32)
         rel = np.zeros(nrhs, dtype=np.float64)
         code = _lib.sgf_pcg_solve(self.h, nrhs, _ptr(b), self.n, _ptr(x), self.n, float(rtol), int(maxit),
@@ -233,6 +314,31 @@ class Solver:
         _check(_lib.sgf_get_perm(self.h, _ptr(p)))
         return p
 
+    def blocks(self, t):
+        """Factor blocks of level t (sgf_export_block): a list of dicts with
+        kind, cell, L and, for eliminations, W; for compressions V, tau, r."""
+        ne, nc = ctypes.c_int32(), ctypes.c_int32()
+        _check(_lib.sgf_block_count(self.h, int(t), ctypes.byref(ne), ctypes.byref(nc)))
+        out = []
+        for i in range(ne.value + nc.value):
+            b = Block()
+            _check(_lib.sgf_export_block(self.h, int(t), i, ctypes.byref(b), None, None, None, None, None))
+            L = np.zeros((b.m, b.m), order="F")
+            d = {"kind": b.kind, "cell": b.cell, "L": L}
+            W = V = tau = rd = None
+            if b.kind == BLOCK_ELIM:
+                W = np.zeros((b.m, b.k), order="F")
+                d["W"] = W
+            elif b.kind == BLOCK_COMP:
+                V = np.zeros((b.m, b.r), order="F")
+                tau = np.zeros(b.r)
+                rd = np.zeros(b.r)
+                d.update(V=V, tau=tau, r=b.r, rdiag=rd)
+            p = lambda a: None if a is None or a.size == 0 else ctypes.c_void_p(a.ctypes.data)
+            _check(_lib.sgf_export_block(self.h, int(t), i, ctypes.byref(b), p(L), p(W), p(V), p(tau), p(rd)))
+            out.append(d)
+        return out
+
     def plan_dry_run(self, rank_of):
         """Host-only planning of every level with ranks from ``rank_of(level, cell, size)``."""
         cb = RANK_FN(lambda t, cell, size, ctx: int(rank_of(t, cell, size)))
@@ -249,6 +355,10 @@ class Solver:
     def set_small_compress(self, enable=True):
         """One-wavefront compression of small separators (default on)."""
         _check(_lib.sgf_set_small_compress(self.h, int(bool(enable))))
+
+    def set_pair_kernel(self, mode=-1):
+        """Coarse couplings: -1 automatic, 0 one workgroup per pair, 1 one wavefront per pair."""
+        _check(_lib.sgf_set_pair_kernel(self.h, int(mode)))
 
     def set_band_apply(self, enable=True):
         """Banded interior sweeps on levels with narrow M_II blocks (default on)."""
@@ -323,6 +433,10 @@ class Server:
         """b, x: device float64 tensors of shape (nrhs, n) (contiguous rows =
         columns of the n x nrhs problem); kept alive until wait()."""
         nrhs, n = (1, b.shape[0]) if b.dim() == 1 else (b.shape[0], b.shape[1])
+        for t_, name in ((b, "b"), (x, "x")):
+            if t_.device.type != "cuda" or str(t_.dtype) != "torch.float64" or not t_.is_contiguous() \
+                    or tuple(t_.shape) != tuple(b.shape):
+                raise ValueError(f"{name}: a contiguous CUDA float64 tensor shaped like b is required")
         t = ctypes.c_int64()
         _check(_lib.sgf_server_submit(self.h, int(op), 1 if refactor else 0, nrhs, _ptr(b), n, _ptr(x), n,
                                       float(rtol), int(maxit), ctypes.byref(t)))

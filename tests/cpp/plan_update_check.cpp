@@ -61,10 +61,14 @@ static bool same_level(const Level& a, const Level& b) {
 }
 
 int main() {
+  // scheme: 0 Nest-All-All, 2 Nest-2-2 (N columns depend on the neighbours'
+  // sizes), 3 Gen-All-All; compression 1: the low-rank equivalent
   struct Case {
-    int dim, g[3], dpn, q, leaf;
-  } cases[] = {{2, {64, 64, 1}, 1, 1, 8},   {2, {200, 173, 1}, 1, 2, 8}, {3, {24, 22, 21}, 1, 1, 4},
-               {3, {13, 12, 12}, 3, 1, 3}, {2, {61, 58, 1}, 1, 2, 4},  {2, {9, 7, 1}, 1, 0, 2}};
+    int dim, g[3], dpn, q, leaf, scheme, compression;
+  } cases[] = {{2, {64, 64, 1}, 1, 1, 8, 0, 0},   {2, {200, 173, 1}, 1, 2, 8, 0, 0}, {3, {24, 22, 21}, 1, 1, 4, 0, 0},
+               {3, {13, 12, 12}, 3, 1, 3, 0, 0}, {2, {61, 58, 1}, 1, 2, 4, 0, 0},  {2, {9, 7, 1}, 1, 0, 2, 0, 0},
+               {2, {61, 58, 1}, 1, 2, 4, 2, 0},  {3, {24, 22, 21}, 1, 1, 4, 2, 0}, {2, {61, 58, 1}, 1, 1, 4, 3, 0},
+               {3, {13, 12, 12}, 3, 1, 3, 3, 0}, {2, {61, 58, 1}, 1, 2, 4, 0, 1}, {3, {24, 22, 21}, 1, 1, 4, 2, 1}};
   int bad = 0;
   for (const Case& cs : cases) {
     Plan base;
@@ -73,6 +77,8 @@ int main() {
     base.opt.dpn = cs.dpn;
     base.opt.q = cs.q;
     base.opt.leaf = cs.leaf;
+    base.opt.scheme = cs.scheme;
+    base.opt.compression = cs.compression;
     base.n_nodes = (int64_t)cs.g[0] * cs.g[1] * (cs.dim == 3 ? cs.g[2] : 1);
     base.n = base.n_nodes * cs.dpn;
     base.pi = poly_cols(cs.dim, cs.q, cs.dpn);
@@ -120,8 +126,8 @@ int main() {
       levels = (int)P.levels.size();
       bad += ok ? 0 : 1;
     }
-    std::printf("case %dx%dx%d dpn %d q %d leaf %d: %d levels, %d in-place updates\n", cs.g[0], cs.g[1], cs.g[2],
-                cs.dpn, cs.q, cs.leaf, levels, updated);
+    std::printf("case %dx%dx%d dpn %d q %d leaf %d scheme %d compression %d: %d levels, %d in-place updates\n",
+                cs.g[0], cs.g[1], cs.g[2], cs.dpn, cs.q, cs.leaf, cs.scheme, cs.compression, levels, updated);
   }
   std::printf(bad ? "MISMATCH\n" : "ok\n");
   return bad ? 1 : 0;

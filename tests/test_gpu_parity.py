@@ -55,6 +55,13 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
 
 
+def _maxrel(a, b):
+    """Largest entry-wise difference of each column relative to the
+    column's largest entry, maximised over the columns."""
+    a2, b2 = np.atleast_2d(a.T).T, np.atleast_2d(b.T).T
+    return float(np.max(np.abs(a2 - b2).max(axis=0) / np.maximum(np.abs(b2).max(axis=0), 1e-300)))
+
+
 EXACT = [("const", (16, 16), 4, 1), ("fourier", (37, 29), 4, 2), ("blocky", (9, 8, 7), 2, 1),
          ("const", (2, 2), 8, 1), ("blocky", (17, 16, 15), 8, 1)]
 
@@ -106,30 +113,37 @@ def test_factor_structure_and_operators_match_oracle(kind, grid, leaf, q):
         assert sum(1 for x in F.info["gap"] if x[3] < x[2]) == info["compressed"]
     V = np.stack([P.random_rhs(7, p.n, j) for j in range(3)], axis=1)
     za, zm = O.apply_inverse(F, V), O.multiply(F, V)
-    # The operator is defined only as well as the rank-truncated QRs define
-    # their kept subspaces.  (1) The oracle's own rounding sensitivity: the
-    # same steps with the compressions of each level in reverse order, and
-    # with A perturbed by one ulp.  (2) Where the cut at the rank threshold
-    # has no spectral gap (kept/dropped pivot ratio < 10), the kept subspace
-    # is only determined to about eps / |R_rr| (perturbation bound for
-    # invariant subspaces), and that bounds the comparison instead.
-    Fd = O.factorize(p.csr(), p.coords, p.grid, p.dpn, O.Options(q=q, leaf=leaf, order="descending"))
-    Ap = p.csr().copy()
-    Ap.data = Ap.data * (1 + 2e-16 * np.random.default_rng(0).standard_normal(Ap.nnz))
-    Ap = ((Ap + Ap.T) * 0.5).tocsr()
-    Fp = O.factorize(Ap, p.coords, p.grid, p.dpn, O.Options(q=q, leaf=leaf))
-    sens_a = max(_rel(O.apply_inverse(Fd, V), za), _rel(O.apply_inverse(Fp, V), za))
-    sens_m = max(_rel(O.multiply(Fd, V), zm), _rel(O.multiply(Fp, V), zm))
+    # Element by element, within 1e-10 of each column's largest entry.  The
+    # operator is defined only as well as the rank-truncated QRs define their
+    # kept subspaces.  (1) Where the cut at the rank threshold has no spectral
+    # gap (smallest kept pivot ratio < 10 x the largest dropped one), a kept
+    # direction with |R_rr| ~ rho |R_00| is determined only to about
+    # eps / rho by any implementation: parity-unpinned at 1e-10, held to that
+    # bound instead.  (2) Otherwise the bar is 1e-10, unless the oracle itself
+    # does not reproduce its operator to 1e-11 when A is perturbed by one ulp
+    # (near-tied pivots of symmetric constant-coefficient problems): then 10 x
+    # that measured sensitivity, printed.
     kept = min(x[4] for x in F.info["gap"] if x[3] > 0)
     dropped = max(x[5] for x in F.info["gap"])
     gapless = kept < 10 * dropped
-    sub = 10 * np.finfo(float).eps / kept if gapless else 0.0
+    sens = 0.0
+    for seed in range(2):
+        Ap = p.csr().copy()
+        Ap.data = Ap.data * (1 + 2e-16 * np.random.default_rng(seed).standard_normal(Ap.nnz))
+        Ap = ((Ap + Ap.T) * 0.5).tocsr()
+        Fp = O.factorize(Ap, p.coords, p.grid, p.dpn, O.Options(q=q, leaf=leaf))
+        sens = max(sens, _maxrel(O.apply_inverse(Fp, V), za), _maxrel(O.multiply(Fp, V), zm))
+    if gapless:
+        bar, why = max(1e-10, 10 * np.finfo(float).eps / kept), "GAPLESS: parity unpinned at 1e-10"
+    elif sens > 1e-11:
+        bar, why = 10 * sens, "the oracle's own one-ulp sensitivity exceeds 1e-11"
+    else:
+        bar, why = 1e-10, ""
     for tiled, s in solvers.items():
-        ea, em = _rel(_apply(s, V), za), _rel(_apply(s, V, product=True), zm)
-        print(f"{kind} {grid} tiled_min_rows {tiled}: apply {ea:.1e} (oracle sens {sens_a:.1e}), product {em:.1e} "
-              f"(sens {sens_m:.1e}), kept>={kept:.1e} dropped<={dropped:.1e}{' gapless' if gapless else ''}")
-        assert ea <= max(1e-10, 100 * sens_a, sub)
-        assert em <= max(1e-10, 100 * sens_m, sub)
+        ea, em = _maxrel(_apply(s, V), za), _maxrel(_apply(s, V, product=True), zm)
+        print(f"{kind} {grid} tiled_min_rows {tiled}: apply {ea:.1e}, product {em:.1e}, kept>={kept:.1e} "
+              f"dropped<={dropped:.1e}, oracle one-ulp sensitivity {sens:.1e}, bar {bar:.1e} {why}")
+        assert ea <= bar and em <= bar
 
 
 @pytest.mark.parametrize("kind,grid,leaf,q", PAR[:5])
@@ -584,3 +598,178 @@ def test_small_compression_matches_workgroup_compression_and_oracle(kind, grid, 
     else:
         assert d <= 1e-4
         assert _rel(out[True], za) <= 1e-3
+
+
+@pytest.mark.parametrize("order", ["pcg1-apply8-pcg1", "apply1-pcg4-apply1"])
+def test_graphs_recaptured_after_work_buffers_grow(order):
+    """The captured apply and PCG graphs hold the addresses of the apply's
+    work vectors; a call with more columns reallocates them, and a later
+    call with fewer columns must not replay a graph recorded on the freed
+    buffers.  Each call equals the same call on a fresh handle bit for bit."""
+    p = _prob("fourier", (70, 61), seed=7)
+    B = torch.from_numpy(np.stack([P.random_rhs(40, p.n, j) for j in range(8)], axis=0)).cuda()
+
+    def run(s, step):
+        kind, k = step
+        if kind == "pcg":
+            x = torch.full((k, p.n), float("nan"), dtype=torch.float64, device="cuda")
+            it, _ = s.pcg(B[:k].T, x.T, rtol=1e-9)
+            torch.cuda.synchronize()
+            return it.tolist(), x.cpu().numpy()
+        z = torch.full((k, p.n), float("nan"), dtype=torch.float64, device="cuda")
+        s.apply(B[:k].T, z.T)
+        torch.cuda.synchronize()
+        return None, z.cpu().numpy()
+
+    steps = {"pcg1-apply8-pcg1": [("pcg", 1), ("apply", 8), ("pcg", 1)],
+             "apply1-pcg4-apply1": [("apply", 1), ("pcg", 4), ("apply", 1)]}[order]
+    s = _gpu(p, q=2, leaf=4, precision=sgf.FP32)
+    for i, step in enumerate(steps):
+        got = run(s, step)
+        fresh = _gpu(p, q=2, leaf=4, precision=sgf.FP32)
+        want = run(fresh, step)
+        fresh.close()
+        assert got[0] == want[0] and np.array_equal(got[1], want[1]), f"step {i} {step}"
+
+
+def _blockrel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)) if b.size else 0.0
+
+
+@pytest.mark.parametrize("kind,grid,leaf,q,tiled", [("fourier", (100, 90), 16, 2, -1), ("fourier", (50, 41), 4, 2, -1),
+                                                    ("blocky", (14, 13, 12), 3, 1, -1), ("blocky", (14, 13, 12), 3, 1, 0),
+                                                    ("elast", 8, 3, 1, -1)])
+def test_factor_entries_match_oracle(kind, grid, leaf, q, tiled):
+    """FP64 factor entries, block by block, against the oracle's (shared QR
+    pivot, tie and sign conventions): L_I and W = L_I^{-1} M_IS of every
+    interior (Eq. 4.2), L_B, the Householder vectors and tau of every
+    compressed separator (Eqs. 3.1, 3.3), and the top factor (Sec. 4.5),
+    each within 1e-10 of its largest entry.  Reflector k is formed from a
+    trailing part of size |R_kk|, so rounding of order eps |R_00| moves it
+    by about eps |R_00| / |R_kk|: column k of V and tau_k are compared
+    within max(1e-10, 100 eps / min_{j<=k} |R_jj / R_00|) (the bar only
+    widens for columns whose pivots fall below 2e-4 |R_00|), and the
+    number of such columns is printed."""
+    p = _prob(kind, grid)
+    F = _oracle(p, q, leaf)
+    s = _gpu(p, q=q, leaf=leaf, tiled_min_rows=tiled)
+    worst = {"L_I": 0.0, "W": 0.0, "L_B": 0.0, "V": 0.0, "tau": 0.0, "top": 0.0}
+    widened = ncols = 0
+    nlev = s.info()["levels"]
+    assert nlev == F.info["nlevels"]
+    for t in range(1, nlev):
+        blocks = s.blocks(t)
+        ops = F.levels[t - 1]
+        elims = [o for o in ops if o[0] == "elim"]
+        comps = [o for o in ops if o[0] == "comp"]
+        gb_e = [b for b in blocks if b["kind"] == sgf.BLOCK_ELIM]
+        gb_c = [b for b in blocks if b["kind"] == sgf.BLOCK_COMP]
+        assert len(gb_e) == len(elims) and len(gb_c) == len(comps), f"level {t}"
+        for g, o in zip(gb_e, elims):
+            _, vI, L, Ws = o
+            W = np.hstack([w for _, w in Ws]) if Ws else np.zeros((len(vI), 0))
+            assert g["L"].shape == L.shape and g["W"].shape == W.shape
+            worst["L_I"] = max(worst["L_I"], _blockrel(g["L"], L))
+            worst["W"] = max(worst["W"], _blockrel(g["W"], W))
+        for g, o in zip(gb_c, comps):
+            _, vB, L, V, tau, r = o
+            assert g["r"] == r and g["V"].shape == V.shape
+            worst["L_B"] = max(worst["L_B"], _blockrel(g["L"], L))
+            ratio = np.minimum.accumulate(np.abs(g["rdiag"]) / abs(g["rdiag"][0]))
+            bar = np.maximum(1e-10, 100 * np.finfo(float).eps / ratio)
+            widened += int(np.sum(bar > 1e-10))
+            ncols += r
+            vmax = max(np.abs(V).max(), 1.0)
+            ev = np.abs(g["V"] - V).max(axis=0) / vmax / bar
+            et = np.abs(g["tau"] - tau) / max(np.abs(tau).max(), 1e-300) / bar
+            worst["V"] = max(worst["V"], float(ev.max()) * 1e-10)
+            worst["tau"] = max(worst["tau"], float(et.max()) * 1e-10)
+    top = s.blocks(nlev)
+    assert len(top) == 1 and top[0]["kind"] == sgf.BLOCK_TOP
+    worst["top"] = _blockrel(top[0]["L"], F.top[1])
+    print(f"{kind} {grid} leaf {leaf} q {q} tiled {tiled}: " + ", ".join(f"{k} {v:.1e}" for k, v in worst.items())
+          + f" (V, tau: error / bar x 1e-10; {widened} of {ncols} reflector columns with a widened bar)")
+    assert max(worst.values()) <= 1e-10, worst
+
+
+@pytest.mark.parametrize("kind,grid,leaf,q", [("fourier", (100, 90), 16, 2), ("fourier", (61, 58), 8, 2),
+                                              ("blocky", (17, 16, 15), 4, 1), ("elast", 9, 3, 1)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_pair_kernels_give_the_same_bits(kind, grid, leaf, q, prec):
+    """Coarse couplings by one wavefront per pair (intermediate in LDS) and
+    by one workgroup per pair (intermediate in device scratch): the same
+    products in the same order, so the same factor bit for bit."""
+    p = _prob(kind, grid)
+    pr = sgf.FP64 if prec == "fp64" else sgf.FP32
+    V = np.stack([P.random_rhs(14, p.n, j) for j in range(2)], axis=1)
+    out = {}
+    for mode in (0, 1):
+        s = sgf.Solver.from_problem(p, q=q, leaf=leaf, precision=pr)
+        s.set_pair_kernel(mode)
+        s.factorize(torch.from_numpy(p.data).cuda())
+        out[mode] = (_apply(s, V), _apply(s, V, product=True))
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+@pytest.mark.parametrize("q", [0, 2])
+def test_headline_paths_at_512_match_oracle(q):
+    """The kernels the 1024^2 workload runs, on a 512^2 grid with its leaf
+    (16): banded level-1 elimination with the 16-wide boundary blocks on
+    ring width 24, more than 4096 active pairs (so the one-wavefront
+    coupling kernel), one-wavefront compressions, banded sweeps.
+    q = 0 has a clear gap at the rank cut (kept pivot ratios >= 6e-8,
+    dropped <= 4e-15): FP64 element by element against the oracle within
+    1e-10 of each column's largest entry, CG iterations +-1, solution 1e-8;
+    the FP32 form within the FP32 bars.
+    q = 2 (the headline's degree): the level-1 edges' pivot ratios spread
+    continuously over 1e-13 .. 1e-11 around the threshold 1e-12, so no
+    implementation determines the FP64 operator beyond about eps / 1e-12:
+    parity unpinned at 1e-10; checked instead: the same ranks at every level,
+    the operator within 10 eps / (smallest kept ratio), preservation of the
+    quadratics (Prop. 6.1) within 1e-9, CG iterations +-1."""
+    p = _prob("fourier", (512, 512))
+    A = p.csr()
+    F = _oracle(p, q, 16)
+    kept = min(x[4] for x in F.info["gap"] if x[3] > 0)
+    dropped = max(x[5] for x in F.info["gap"])
+    gapless = kept < 10 * dropped
+    assert gapless == (q == 2)
+    bar = max(1e-10, 10 * np.finfo(float).eps / kept) if gapless else 1e-10
+    V = np.stack([P.random_rhs(15, p.n, j) for j in range(2)], axis=1)
+    za, zm = O.apply_inverse(F, V), O.multiply(F, V)
+    b = P.random_rhs(0, p.n)
+    xo, ito, _ = O.pcg(A, b, lambda r: O.apply_inverse(F, r), tol=1e-8)
+    for prec in (sgf.FP64, sgf.FP32):
+        s = sgf.Solver.from_problem(p, q=q, leaf=16, precision=prec)
+        s.set_apply_graph(False)
+        s.profile(True)
+        s.factorize(torch.from_numpy(p.data).cuda())
+        ea, em = _maxrel(_apply(s, V), za), _maxrel(_apply(s, V, product=True), zm)
+        st = s.profile_read()
+        s.profile(False)
+        assert "elim_banded@L1" in st and "apply_band_fwd@L1" in st and "apply_band_bwd@L1" in st
+        L1 = s.level(1)
+        assert np.sum(L1["type"] == 0) == 1024
+        xg = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+        it, rel = s.pcg(torch.from_numpy(b).cuda(), xg, rtol=1e-8)
+        ex = _maxrel(xg.cpu().numpy(), xo)
+        print(f"512^2 q {q} precision {prec}: apply {ea:.1e}, product {em:.1e}, CG it {int(it[0])} (oracle {ito}), "
+              f"x {ex:.1e}, kept >= {kept:.1e}, dropped <= {dropped:.1e}, bar {bar:.1e}")
+        if prec == sgf.FP64:
+            for t in range(1, F.info["nlevels"]):
+                g = s.level(t)
+                post = F.info["sizes"][t - 1]
+                seps = g["type"] > 0
+                assert [post[c] for c in g["cell"][seps]] == g["rank"][seps].tolist(), f"ranks at level {t}"
+            assert ea <= bar and em <= bar
+            assert abs(int(it[0]) - ito) <= 1
+            if not gapless:
+                assert ex <= 1e-8
+            else:
+                Pi = O.poly_basis(p.coords, q, 1)
+                pres = _maxrel(_apply(s, Pi, product=True), A @ Pi)
+                print(f"512^2 q {q}: preservation {pres:.1e}")
+                assert pres <= 1e-9
+        else:
+            assert ea <= 1e-3 and em <= 1e-3
+            assert np.linalg.norm(b - A @ xg.cpu().numpy()) / np.linalg.norm(b) < 2e-8

@@ -62,22 +62,43 @@ def _make(kind, grid):
     return P.elasticity_q1(grid, seed=1, n_incl=2)
 
 
+SCHEME_CASES = [(sch, case) for sch in (sgf.NEST_2_ALL, sgf.NEST_2_2)
+                for case in (CASES[1], CASES[2], CASES[4], CASES[5])] + \
+               [(sgf.GEN_ALL_ALL, c) for c in (("poisson", (20, 17), 4, 1, 1), ("poisson", (13, 9, 11), 3, 0, 1),
+                                              ("fourier", (40, 33), 5, 2, 1), ("elast", 7, 3, 1, 3),
+                                              ("poisson", (16, 16, 16), 4, 1, 1))]
+
+
 @pytest.mark.parametrize("kind,grid,leaf,q,dpn", CASES)
 @pytest.mark.parametrize("stop", [sgf.STOP_ROOT, sgf.STOP_PAPER])
 def test_planner_matches_oracle_hierarchy(kind, grid, leaf, q, dpn, stop):
+    _check_hierarchy(kind, grid, leaf, q, stop, sgf.NEST_ALL_ALL)
+
+
+@pytest.mark.parametrize("scheme,case", SCHEME_CASES)
+def test_planner_matches_oracle_hierarchy_of_each_scheme(scheme, case):
+    """Nest-2-All and Nest-2-2 compress only the cells of codimension one;
+    Gen-All-All has boxes of leaf^dim vertices with no interiors, every one
+    compressed at every level (Secs. 5.1-5.2)."""
+    kind, grid, leaf, q, dpn = case
+    _check_hierarchy(kind, grid, leaf, q, sgf.STOP_ROOT, scheme)
+
+
+def _check_hierarchy(kind, grid, leaf, q, stop, scheme):
     p = _make(kind, grid)
+    general = scheme == sgf.GEN_ALL_ALL
     F = O.factorize(p.csr(), p.coords, p.grid, p.dpn,
-                    O.Options(q=q, leaf=leaf, stop_rule=O.STOP_PAPER if stop else O.STOP_ROOT))
-    s = sgf.Solver.from_problem(p, q=q, leaf=leaf, stop_rule=stop)
+                    O.Options(q=q, leaf=leaf, stop_rule=O.STOP_PAPER if stop else O.STOP_ROOT, scheme=scheme))
+    s = sgf.Solver.from_problem(p, q=q, leaf=leaf, stop_rule=stop, scheme=scheme)
     # level-1 permutation: cells ascending, unknowns ascending inside a cell
-    lv1 = O.partition_hierarchy(p.grid, leaf)[0]
+    lv1 = O.partition_hierarchy(p.grid, leaf, general=general)[0]
     cell_dof = np.repeat(lv1.cell_of_node, p.dpn)
     assert np.array_equal(s.perm(), np.argsort(cell_dof, kind="stable"))
     ranks = F.info["ranks"]
     s.plan_dry_run(lambda t, cell, size: ranks[t - 1].get(cell, size))
     nlev = F.info["nlevels"]
     assert s.info()["levels"] == nlev
-    levels = O.partition_hierarchy(p.grid, leaf)
+    levels = O.partition_hierarchy(p.grid, leaf, general=general)
     for t in range(1, nlev):
         g = s.level(t)
         # separators after the level's compressions: cell ids and sizes
