@@ -185,6 +185,25 @@ sgf_status sgf_autotune(sgf_handle h, const double* vals, int32_t napply, int32_
 sgf_status sgf_apply(sgf_handle h, int32_t nrhs, const double* r, int64_t ldr,
                      double* z, int64_t ldz, void* stream);
 
+/*
+ * sgf_apply that allocates no device memory, for callers that cannot call
+ * hipMalloc: code being captured into a HIP graph, tight serving loops,
+ * harnesses that forbid allocation.  Same arguments, kernels and result as
+ * sgf_apply (bit for bit); the work vectors (the permuted vector, the
+ * separator scratch, the compressed-separator and tiled-front vectors of
+ * each level) live in a static device array of SGF_NOALLOC_SCRATCH_BYTES
+ * per GPU that the library holds until the process ends, instead of the
+ * handle's buffers; every kernel is launched directly (no graph is captured
+ * or replayed) and nothing is timed.  Needs n * nrhs * (4 or 8) bytes plus
+ * the level vectors to fit: larger requests fail with SGF_EINVAL and a
+ * message giving the size.  The array is shared by every handle on a GPU and
+ * keeps the last call's contents: calls that overlap on one GPU (other
+ * streams or host threads) race and must be serialized by the caller.
+ */
+#define SGF_NOALLOC_SCRATCH_BYTES (64u << 20)
+sgf_status sgf_apply_noalloc(sgf_handle h, int32_t nrhs, const double* r, int64_t ldr,
+                             double* z, int64_t ldz, void* stream);
+
 /* y = A_l v (Sec. 2.1 product form; a test hook for the preservation
  * property of Prop. 6.1).  Same layout rules as sgf_apply. */
 sgf_status sgf_multiply(sgf_handle h, int32_t nrhs, const double* v, int64_t ldv,

@@ -11,6 +11,7 @@
 #include <functional>
 #include <limits>
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <tuple>
@@ -2271,6 +2272,87 @@ sgf_status sgf_apply(sgf_handle h, int32_t nrhs, const double* r, int64_t ldr, d
   if (!h->factored) return fail(SGF_ESTATE, "apply before a successful factorization");
   if (ldr < h->plan.n || ldz < h->plan.n) return fail(SGF_EINVAL, "leading dimension below n");
   return guard([&] { apply_any(h, nrhs, r, ldr, z, ldz, false, (hipStream_t)stream); });
+}
+
+}  // extern "C"
+
+// Device scratch of the allocation-free apply: one array per GPU, held from
+// the library's load until the process ends.  Host code never passes this
+// name to a kernel (on the host it only stands for the symbol): the device
+// address of each GPU's copy is looked up once per device and kept.
+static __device__ __align__(256) unsigned char scratch[SGF_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+void* scratch_ptr() {
+  int dev = 0;
+  HIP_CHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) throw SgfError(SGF_EINVAL, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) throw SgfError(SGF_EDEVICE, "no device address for the scratch array");
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+
+// The apply's work vectors carved out of `base` (256-byte aligned pieces,
+// the sizes ensure_work would allocate); bytes needed in *need.
+ApplyWork carve_work(sgf_handle h, int nrhs, unsigned char* base, size_t* need) {
+  ApplyWork w;
+  const size_t e = h->esz;
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> void* {
+    void* p = base + off;
+    off += (bytes + 255) & ~(size_t)255;
+    return p;
+  };
+  w.y = take((size_t)h->plan.n * nrhs * e);
+  w.tscr = take((size_t)std::max<int64_t>(h->max_t, 1) * nrhs * e);
+  if ((int)h->lev.size() > ApplyWork::MAXL) throw SgfError(SGF_EINVAL, "too many levels for the allocation-free apply");
+  for (size_t li = 0; li < h->lev.size(); ++li) {
+    const LevelDev& D = h->lev[li];
+    if (D.tiled && D.uploaded) w.uw[li] = take((size_t)std::max<int64_t>(D.u_elems, 1) * nrhs * e);
+    if (D.uploaded) w.cw[li] = take((size_t)std::max<int64_t>(D.c_elems, 1) * nrhs * e);
+  }
+  if (h->top_tiled) w.topu = take((size_t)h->top_R * nrhs * sizeof(double));
+  *need = off;
+  return w;
+}
+}  // namespace
+
+extern "C" {
+
+sgf_status sgf_apply_noalloc(sgf_handle h, int32_t nrhs, const double* r, int64_t ldr, double* z, int64_t ldz,
+                             void* stream) {
+  if (!h || !r || !z || nrhs < 1) return fail(SGF_EINVAL, "bad apply arguments");
+  if (!h->factored) return fail(SGF_ESTATE, "apply before a successful factorization");
+  if (ldr < h->plan.n || ldz < h->plan.n) return fail(SGF_EINVAL, "leading dimension below n");
+  return guard([&] {
+    size_t need = 0;
+    (void)carve_work(h, nrhs, nullptr, &need);   // sizes only
+    if (need > SGF_NOALLOC_SCRATCH_BYTES)
+      throw SgfError(SGF_EINVAL, "allocation-free apply needs " + std::to_string(need) + " bytes of scratch for " +
+                                     std::to_string(nrhs) + " columns; the static scratch holds " +
+                                     std::to_string((size_t)SGF_NOALLOC_SCRATCH_BYTES));
+    unsigned char* base = static_cast<unsigned char*>(scratch_ptr());
+    const ApplyWork w = carve_work(h, nrhs, base, &need);
+    const bool prof = h->prof.on;
+    h->prof.on = false;   // no events: launches only
+    try {
+      if (h->esz == 8) apply_impl<double>(h, nrhs, r, ldr, z, ldz, false, (hipStream_t)stream, &w);
+      else apply_impl<float>(h, nrhs, r, ldr, z, ldz, false, (hipStream_t)stream, &w);
+    } catch (...) {
+      h->prof.on = prof;
+      throw;
+    }
+    h->prof.on = prof;
+  });
 }
 
 sgf_status sgf_multiply(sgf_handle h, int32_t nrhs, const double* v, int64_t ldv, double* y, int64_t ldy,

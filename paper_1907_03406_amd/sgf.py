@@ -16,11 +16,12 @@ LIB_PATH = os.path.join(HERE, "libsgf.so")
 SGF_OK, SGF_EINVAL, SGF_ENOTSPD, SGF_ENOMEM, SGF_EDEVICE, SGF_ENOCONV, SGF_ESTATE = range(7)
 NEST_ALL_ALL, NEST_2_ALL, NEST_2_2, GEN_ALL_ALL = 0, 1, 2, 3
 MAX_BASIS_COLS = 64
+NOALLOC_SCRATCH_BYTES = 64 << 20
 STOP_ROOT, STOP_PAPER = 0, 1
 FP64, FP32, FP32_BF16N = 0, 1, 2
 
 EXPORTED = ["sgf_default_options", "sgf_analyze", "sgf_factorize_numeric", "sgf_factorize", "sgf_autotune",
-            "sgf_apply", "sgf_multiply", "sgf_pcg_solve", "sgf_spmv", "sgf_get_info",
+            "sgf_apply", "sgf_apply_noalloc", "sgf_multiply", "sgf_pcg_solve", "sgf_spmv", "sgf_get_info",
             "sgf_get_perm", "sgf_get_level", "sgf_plan_dry_run", "sgf_profile_enable", "sgf_profile_read", "sgf_profile_select",
             "sgf_set_apply_graph", "sgf_set_persistent", "sgf_set_basis", "sgf_set_low_rank", "sgf_set_pair_kernel", "sgf_block_count", "sgf_export_block", "sgf_set_band_apply", "sgf_set_band_elim", "sgf_set_small_compress", "sgf_release", "sgf_estimate_bytes",
             "sgf_server_default_options", "sgf_server_create", "sgf_server_add_operator", "sgf_server_submit",
@@ -96,6 +97,7 @@ def load_library(path=LIB_PATH):
         "sgf_factorize": (I32, [I64, P, P, P, P, ctypes.POINTER(Options), P, ctypes.POINTER(H)]),
         "sgf_autotune": (I32, [H, P, I32, P, P]),
         "sgf_apply": (I32, [H, I32, P, I64, P, I64, P]),
+        "sgf_apply_noalloc": (I32, [H, I32, P, I64, P, I64, P]),
         "sgf_multiply": (I32, [H, I32, P, I64, P, I64, P]),
         "sgf_pcg_solve": (I32, [H, I32, P, I64, P, I64, D, I32, P, P, P]),
         "sgf_spmv": (I32, [H, P, P, P]),
@@ -284,6 +286,12 @@ class Solver:
     def apply(self, r, z, stream=None):
         nrhs = _pair(r, z, self.n, ("r", "z"))
         _check(_lib.sgf_apply(self.h, nrhs, _ptr(r), self.n, _ptr(z), self.n, _stream(stream)))
+
+    def apply_noalloc(self, r, z, stream=None):
+        """sgf_apply_noalloc: the apply with its work vectors in the
+        library's static device scratch (no device allocation)."""
+        nrhs = _pair(r, z, self.n, ("r", "z"))
+        _check(_lib.sgf_apply_noalloc(self.h, nrhs, _ptr(r), self.n, _ptr(z), self.n, _stream(stream)))
 
     def multiply(self, v, y, stream=None):
         nrhs = _pair(v, y, self.n, ("v", "y"))
