@@ -293,9 +293,9 @@ def test_table71_extreme_eigenvector_errors():
     E_1 = |(A - A_l) v_1| / lambda_1 is small and about the same for the
     polynomial compression and its low-rank equivalent, while E_n on the
     smoothest eigenvector is orders of magnitude larger for the low-rank
-    equivalent and grows with n."""
+    equivalent and grows with n (grids 13^3 and 15^3, leaf 3)."""
     En_lr = []
-    for N in (15, 19):
+    for N in (13, 15):
         p = P.poisson_fd((N, N, N))
         A = p.csr()
         F = O.factorize(A, p.coords, p.grid, 1, O.Options(q=2, leaf=3))
@@ -345,21 +345,24 @@ def test_factor_size_per_unknown_stays_flat():
     """Prop. 5.1 (Sec. 5.4): with compression every node's active size is
     bounded independently of n, so the top node keeps one size and the
     stored factor entries per unknown level off as the grid grows (2D,
-    q = 1, leaf 8: 64^2, 128^2, 256^2), while without compression the top
-    grows like the grid side."""
-    per_n, tops, tops_exact = [], [], []
-    for N in (64, 128, 256):
+    q = 1, leaf 8: 32^2, 64^2, 128^2): each doubling of the side adds less
+    than the one before, while without compression the additions grow (the
+    n log n of nested dissection) and the top grows like the grid side."""
+    per_n, per_n_exact, tops, tops_exact = [], [], [], []
+    for N in (32, 64, 128):
         p = _fourier((N, N))
-        A, F = _fact(p, q=1, leaf=8)
+        _, F = _fact(p, q=1, leaf=8)
+        _, Fe = _fact(p, q=1, leaf=8, compress=False)
         per_n.append(O.factor_entries(F) / p.n)
+        per_n_exact.append(O.factor_entries(Fe) / p.n)
         tops.append(F.info["top_size"])
-        if N <= 128:
-            _, Fe = _fact(p, q=1, leaf=8, compress=False)
-            tops_exact.append(Fe.info["top_size"])
+        tops_exact.append(Fe.info["top_size"])
     assert tops[0] == tops[1] == tops[2]
-    assert per_n[2] / per_n[0] < 1.2
-    assert per_n[2] - per_n[1] < per_n[1] - per_n[0]
-    assert tops_exact[1] > 1.9 * tops_exact[0]
+    assert tops_exact[2] > 1.9 * tops_exact[1] > 3.6 * tops_exact[0]
+    d, de = np.diff(per_n), np.diff(per_n_exact)
+    assert d[1] < 0.8 * d[0]
+    assert de[1] >= de[0]
+    assert per_n[2] < per_n_exact[2]
 
 
 def test_low_rank_with_level_blocks_is_order_independent_and_matches_dense_schur():
