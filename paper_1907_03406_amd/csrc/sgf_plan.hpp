@@ -17,6 +17,13 @@
 #include <string>
 #include <vector>
 
+// Functions shared by the planner (host) and the copy kernels (device).
+#if defined(__HIPCC__)
+#define SGF_HD __host__ __device__
+#else
+#define SGF_HD
+#endif
+
 namespace sgf {
 
 struct Options {
@@ -151,6 +158,23 @@ inline int64_t father_cell(const Partition& lo, const Partition& hi, int64_t cid
   return hi.cell_of(idx[0], idx[1], idx[2]);
 }
 
+// Coarsening computed on the device (Secs. 4.3-4.4): for every pair block of
+// the level below, where it goes in the new level (the kinds of
+// emit_copy_maps: 0 diagonal block of an interior front, 1 diagonal pair
+// block, 2 / 3 an interior front's neighbour rows (a's / b's father is the
+// interior), 4 / 5 an off-diagonal pair block, a's father first / second),
+// the target (front or pair index), the adjacency entry of the neighbour
+// rows, and the separator positions of a and b; for every separator of the
+// level below, its cluster and compression index.  These depend only on the
+// structure, not on the ranks.
+struct CoarsenPair {
+  int64_t e;
+  int32_t kind, tgt, pa, pb;
+};
+struct CoarsenSep {
+  int32_t cluster, ci;
+};
+
 // Block copy: dst[(dr + i) + (dc + j) * dld] = src[i + j * sld] (mode 0) or
 // dst[(dr + j) + (dc + i) * dld] (mode 1, transposed), i < rows, j < cols.
 struct CopyDesc {
@@ -187,6 +211,44 @@ struct PairDesc {
   int32_t row_in_a, row_in_b;  // row of b inside a's compression front, and vice versa
   int32_t c_ptr, c_cnt; // Schur contributions
 };
+
+// Destination in the new level's arena of a pair block of the level below
+// (CoarsenPair kinds, as in emit_copy_maps): d0 receives the block (element
+// (i, j) at d0 + i + j ld), d1 its transpose (element (i, j) at d1 + j + i ld),
+// -1 when not used.  oa / ob: first rows of a / b in their fathers; diag: the
+// block is a diagonal pair block (a == b); NE / NP / nbr_off: the new level's
+// interior fronts, pair blocks and neighbour offsets; n_front: the size of
+// the fronts part of its arena (pair blocks follow).
+struct CoarsenDst {
+  int64_t d0, d1, ld;
+};
+SGF_HD inline CoarsenDst coarsen_dest(int kind, int tgt, int64_t e, int oa, int ob, bool diag,
+                                      const ElimDesc* NE, const PairDesc* NP, const int32_t* nbr_off,
+                                      int64_t n_front) {
+  CoarsenDst r{-1, -1, 1};
+  if (kind == 0 || kind == 1) {
+    int64_t base;
+    if (kind == 0) {
+      base = NE[tgt].front_off;
+      r.ld = (int64_t)NE[tgt].m + NE[tgt].k;
+    } else {
+      base = n_front + NP[tgt].blk_off;
+      r.ld = NP[tgt].s_a;
+    }
+    r.d0 = base + oa + (int64_t)ob * r.ld;
+    if (!diag) r.d1 = base + ob + (int64_t)oa * r.ld;
+  } else if (kind == 2 || kind == 3) {
+    r.ld = (int64_t)NE[tgt].m + NE[tgt].k;
+    const int64_t row = NE[tgt].m + nbr_off[e];
+    if (kind == 2) r.d1 = NE[tgt].front_off + (row + ob) + (int64_t)oa * r.ld;
+    else r.d0 = NE[tgt].front_off + (row + oa) + (int64_t)ob * r.ld;
+  } else if (kind == 4 || kind == 5) {
+    r.ld = NP[tgt].s_a;
+    if (kind == 4) r.d0 = n_front + NP[tgt].blk_off + oa + (int64_t)ob * r.ld;
+    else r.d1 = n_front + NP[tgt].blk_off + ob + (int64_t)oa * r.ld;
+  }
+  return r;
+}
 
 // Compression of one separator B (Eqs. 3.1-3.5).
 struct CompDesc {
@@ -303,6 +365,10 @@ struct Level {
   std::vector<int32_t> cp_tgt;
   std::vector<int64_t> cp_e;
   bool can_update = false;
+  // the father (index in this level) and first row there of every separator
+  // of the level below, for the current sizes (the device coarsening
+  // computes each block's destination from these, CoarsenPair, CoarsenSep)
+  std::vector<int32_t> cp_father, cp_loc;
 
   int32_t post_size(int c) const {
     int ci = comp_of.empty() ? -1 : comp_of[c];
@@ -1080,9 +1146,29 @@ inline void emit_copy_maps(const Level& C, const Level& N, const std::vector<int
   }
 }
 
+// The structure-only coarsening tables of the pair blocks and separators of
+// level C into level N (see CoarsenPair).
+inline void coarsen_tables(const Level& C, const Level& N, std::vector<CoarsenPair>& cp, std::vector<CoarsenSep>& cs) {
+  cp.resize(C.pairs.size());
+  for (size_t q = 0; q < C.pairs.size(); ++q) {
+    CoarsenPair& x = cp[q];
+    x.kind = N.cp_kind[q];
+    x.tgt = N.cp_tgt[q];
+    x.e = N.cp_e[q];
+    x.pa = C.sep_pos[C.pairs[q].a];
+    x.pb = C.sep_pos[C.pairs[q].b];
+  }
+  cs.resize(C.seps.size());
+  for (size_t p = 0; p < C.seps.size(); ++p) {
+    cs[p].cluster = C.seps[p];
+    cs[p].ci = C.comp_of.empty() ? -1 : C.comp_of[C.seps[p]];
+  }
+}
+
 // Next level from the current one once its ranks are known (Secs. 4.3-4.4).
 // Returns the copy maps for the pair blocks and for Phi.
-inline void plan_next_level(Plan& P, std::vector<CopyDesc>& blk_map, std::vector<CopyDesc>& phi_map) {
+inline void plan_next_level(Plan& P, std::vector<CopyDesc>& blk_map, std::vector<CopyDesc>& phi_map,
+                            bool emit = true) {
   const Options& o = P.opt;
   Level& C = P.levels.back();
   C.planned_rank = C.rank;
@@ -1225,6 +1311,14 @@ inline void plan_next_level(Plan& P, std::vector<CopyDesc>& blk_map, std::vector
     }
   }
   N.can_update = true;
+  N.cp_father = father;
+  N.cp_loc = loc;
+  if (!emit) {
+    validate_level(N, P.n, P.pi);
+    P.parts.push_back(hi);
+    P.levels.push_back(std::move(N));
+    return;
+  }
   emit_copy_maps(C, N, father, loc, P.pi, blk_map, phi_map);
   validate_level(N, P.n, P.pi);
   validate_copies(blk_map, C.front_elems + C.blk_elems, N.front_elems + N.blk_elems);
@@ -1240,7 +1334,7 @@ inline void plan_next_level(Plan& P, std::vector<CopyDesc>& blk_map, std::vector
 // plan_next_level for these ranks; false when the recorded structure cannot
 // be used (no next level yet, or the rank-dependent top rule).
 inline bool update_next_level(Plan& P, size_t li, std::vector<CopyDesc>& blk_map,
-                              std::vector<CopyDesc>& phi_map) {
+                              std::vector<CopyDesc>& phi_map, bool emit = true) {
   if (P.opt.stop_rule != 0 || li + 1 >= P.levels.size()) return false;
   Level& C = P.levels[li];
   Level& N = P.levels[li + 1];
@@ -1283,6 +1377,12 @@ inline bool update_next_level(Plan& P, size_t li, std::vector<CopyDesc>& blk_map
               N.slots.begin() + N.slot_ptr[father[p]] + loc[p]);
   }
   build_offsets(N, P.pi, P.opt.compression);
+  N.cp_father = father;
+  N.cp_loc = loc;
+  if (!emit) {
+    validate_level(N, P.n, P.pi);
+    return true;
+  }
   emit_copy_maps(C, N, father, loc, P.pi, blk_map, phi_map);
   validate_level(N, P.n, P.pi);
   validate_copies(blk_map, C.front_elems + C.blk_elems, N.front_elems + N.blk_elems);

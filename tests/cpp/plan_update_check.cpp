@@ -48,6 +48,53 @@ static void set_ranks(Level& L, int variant) {
   }
 }
 
+// The destinations the device coarsening computes (coarsen_dest from the
+// structure tables, each separator's father and first row, the ranks) equal
+// the host copy lists, entry for entry, and lie inside the new level's arena
+// and Phi.
+static bool device_dest_match(const Level& C, const Level& N, const std::vector<CopyDesc>& bm,
+                              const std::vector<CopyDesc>& pm, int pi) {
+  std::vector<CoarsenPair> cp;
+  std::vector<CoarsenSep> cs;
+  coarsen_tables(C, N, cp, cs);
+  if (N.cp_father.size() != C.seps.size() || N.cp_loc.size() != C.seps.size()) return false;
+  const int64_t n_elems = N.front_elems + N.blk_elems;
+  size_t at = 0;
+  for (size_t q = 0; q < C.pairs.size(); ++q) {
+    const PairDesc& pd = C.pairs[q];
+    const int ra = C.post_size(pd.a), rb = C.post_size(pd.b);
+    if (ra == 0 || rb == 0) continue;
+    const CoarsenDst d = coarsen_dest(cp[q].kind, cp[q].tgt, cp[q].e, N.cp_loc[cp[q].pa], N.cp_loc[cp[q].pb],
+                                      pd.a == pd.b, N.elim.data(), N.pairs.data(), N.nbr_off.data(), N.front_elems);
+    for (int mode = 0; mode < 2; ++mode) {
+      const int64_t dst = mode == 0 ? d.d0 : d.d1;
+      if (dst < 0) continue;
+      if (at >= bm.size()) return false;
+      const CopyDesc& c = bm[at++];
+      if (c.mode != mode || c.dst_off != dst || c.dst_ld != d.ld || c.rows != ra || c.cols != rb ||
+          c.src_off != C.front_elems + pd.blk_off)
+        return false;
+      const int64_t last = mode == 0 ? dst + (ra - 1) + (int64_t)(rb - 1) * d.ld : dst + (rb - 1) + (int64_t)(ra - 1) * d.ld;
+      if (dst < 0 || last >= n_elems) return false;
+    }
+  }
+  if (at != bm.size()) return false;
+  if (N.top) return pm.empty();
+  size_t ap = 0;
+  for (size_t p = 0; p < C.seps.size(); ++p) {
+    const int a = cs[p].cluster;
+    const int r = C.post_size(a);
+    if (r == 0) continue;
+    if (ap >= pm.size()) return false;
+    const CopyDesc& c = pm[ap++];
+    const int D = N.cp_father[p];
+    if (c.src_off != C.phi_off[a] || c.src_ld != C.size[a] || c.rows != r || c.cols != pi ||
+        c.dst_off != N.phi_off[D] + N.cp_loc[p] || c.dst_ld != N.size[D])
+      return false;
+  }
+  return ap == pm.size();
+}
+
 static bool same_level(const Level& a, const Level& b) {
   return a.top == b.top && same(a.cell, b.cell) && same(a.size, b.size) && same(a.slot_ptr, b.slot_ptr) &&
          same(a.slots, b.slots) && same(a.nbr_off, b.nbr_off) && same(a.elim, b.elim) && same(a.nslots, b.nslots) &&
@@ -57,7 +104,8 @@ static bool same_level(const Level& a, const Level& b) {
          a.t_elems == b.t_elems && a.cf_elems == b.cf_elems && a.n_elems == b.n_elems &&
          a.ltphi_elems == b.ltphi_elems && a.tau_elems == b.tau_elems && a.tb_elems == b.tb_elems &&
          a.phi_elems == b.phi_elems && a.max_front_rows == b.max_front_rows && a.max_cf_rows == b.max_cf_rows &&
-         a.max_c == b.max_c && a.max_s == b.max_s && a.n_active == b.n_active;
+         a.max_c == b.max_c && a.max_s == b.max_s && a.n_active == b.n_active && same(a.cp_father, b.cp_father) &&
+         same(a.cp_loc, b.cp_loc);
 }
 
 int main() {
@@ -68,7 +116,8 @@ int main() {
   } cases[] = {{2, {64, 64, 1}, 1, 1, 8, 0, 0},   {2, {200, 173, 1}, 1, 2, 8, 0, 0}, {3, {24, 22, 21}, 1, 1, 4, 0, 0},
                {3, {13, 12, 12}, 3, 1, 3, 0, 0}, {2, {61, 58, 1}, 1, 2, 4, 0, 0},  {2, {9, 7, 1}, 1, 0, 2, 0, 0},
                {2, {61, 58, 1}, 1, 2, 4, 2, 0},  {3, {24, 22, 21}, 1, 1, 4, 2, 0}, {2, {61, 58, 1}, 1, 1, 4, 3, 0},
-               {3, {13, 12, 12}, 3, 1, 3, 3, 0}, {2, {61, 58, 1}, 1, 2, 4, 0, 1}, {3, {24, 22, 21}, 1, 1, 4, 2, 1}};
+               {3, {13, 12, 12}, 3, 1, 3, 3, 0}, {2, {61, 58, 1}, 1, 2, 4, 0, 1}, {3, {24, 22, 21}, 1, 1, 4, 2, 1},
+               {2, {512, 512, 1}, 1, 2, 16, 0, 0}};
   int bad = 0;
   for (const Case& cs : cases) {
     Plan base;
@@ -96,6 +145,12 @@ int main() {
         plan_next_level(fresh[v], bm, pm);
         maps[v][0].push_back(bm);
         maps[v][1].push_back(pm);
+        const size_t li = fresh[v].levels.size() - 2;
+        if (!device_dest_match(fresh[v].levels[li], fresh[v].levels[li + 1], bm, pm, base.pi)) {
+          std::printf("case %dx%dx%d: device coarsening destinations differ at level %zu\n", cs.g[0], cs.g[1],
+                      cs.g[2], li + 2);
+          ++bad;
+        }
       }
     }
     // in place: variant 0 afresh, then 1, then 0 again, level by level
@@ -120,7 +175,7 @@ int main() {
         }
         ++updated;
         ok = same_level(P.levels[li + 1], fresh[v].levels[li + 1]) && same(bm, maps[v][0][li]) &&
-             same(pm, maps[v][1][li]);
+             same(pm, maps[v][1][li]) && device_dest_match(P.levels[li], P.levels[li + 1], bm, pm, base.pi);
         if (!ok) std::printf("case %dx%dx%d: variant %d differs at level %zu\n", cs.g[0], cs.g[1], cs.g[2], v, li + 2);
       }
       levels = (int)P.levels.size();
