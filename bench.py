@@ -142,6 +142,39 @@ def run_serving(a):
     lat = np.array([(inf["t_end"] - arrival) * 1e3 for inf, arrival, _ in res])
     solves = sum(k for _, _, k in res)
     makespan = te - ts
+    # kernel roofline of the serving work: the server's handles are internal,
+    # so a profiled pass after the stream runs one request of the most common
+    # shape (a 512^2 operator of the 2D pool: factorization + 8-rhs PCG), every
+    # launch timed, the apply launched directly
+    rl = None
+    if not a.no_serving_roofline:
+        prob, kw = pool[2 * a.pool]   # 512^2, first field
+        s = sgf.Solver.from_problem(prob, precision=sgf.FP32, **kw)
+        vals = torch.from_numpy(prob.data).to(dev)
+        b = rhs_for(prob.n, 8, 0)
+        x = torch.zeros_like(b)
+        s.factorize(vals)
+        s.pcg(b.T, x.T, rtol=1e-8, maxit=2000)
+        s.set_apply_graph(False)
+        torch.cuda.synchronize()
+        s.profile(True)
+        for _ in range(3):
+            x.zero_()
+            s.factorize(vals)
+            s.pcg(b.T, x.T, rtol=1e-8, maxit=2000)
+        torch.cuda.synchronize()
+        stt = s.profile_read()
+        s.profile(False)
+        s.close()
+        rl = roofline({k: v for k, v in stt.items() if "@" not in k}, {k: v for k, v in stt.items() if "@" in k},
+                      "fp32", 3)
+        if rl is not None:
+            gpu_ms = sum(v["ms"] for k, v in stt.items() if "@" not in k)
+            kms = stt.get(rl["kernel"], {"ms": 0})["ms"]
+            rl["share_of_gpu_time"] = round(kms / gpu_ms, 3) if gpu_ms else None
+            rl["timed_in"] = ("a profiled pass after the stream: three requests of a 512^2 operator of the 2D pool "
+                              "(factorization + 8-rhs PCG to 1e-8), every launch timed, apply launched directly")
+    cpu = None if a.no_cpu_baseline else cpu_baseline_serving(pool, a, res, reqs)
     out = {
         "metric": "PCG solves/s (serving: factorize/solve request stream, each rhs to 1e-8 relative residual)",
         "value": round(solves / makespan, 3),
@@ -159,10 +192,117 @@ def run_serving(a):
         "new_operators": sum(1 for r in reqs if r[0] == "new"),
         "mean_batch_rhs": round(float(np.mean([inf["batch_rhs"] for inf, _, _ in res])), 2),
         "server": st, "problem_gen_s": round(t_gen, 1),
-        "roofline": None, "cpu_baseline": None,
+        "roofline": rl, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 
+
+
+def mark_kernel(torch):
+    """One tiny fill kernel of 16-bit integers (no other kernel of the run
+    fills that type) before and after the timed steps, so that a kernel
+    trace of the run can be cut to exactly the timed steps
+    (--summarize-trace); synchronized, outside the timed region."""
+    torch.full((4099,), 7, dtype=torch.int16, device="cuda")
+    torch.cuda.synchronize()
+
+
+def summarize_trace(trace_dir, label, command):
+    """Per-kernel summary of the timed steps from a rocprofv3 kernel trace
+    (CSV) of `bench.py`: the dispatches between the two marker fills."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no *kernel_trace.csv under {trace_dir}")
+    rows = []
+    for f in files:
+        with open(f) as fh:
+            rows += list(csv.DictReader(fh))
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    marks = [i for i, r in enumerate(rows) if "FillFunctor<short>" in r["Kernel_Name"]]
+    if len(marks) < 2:
+        raise SystemExit(f"markers not found ({len(marks)})")
+    a, b = marks[0], marks[1]
+    sel = rows[a + 1:b]
+    t0, t1 = int(rows[a]["End_Timestamp"]), int(rows[b]["Start_Timestamp"])
+    stats = {}
+    for r in sel:
+        d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        k = stats.setdefault(r["Kernel_Name"], [0, 0.0, 0])
+        k[0] += 1
+        k[1] += d
+    tot = sum(v[1] for v in stats.values())
+    print(f"# {label}")
+    print(f"# command: {command}")
+    print(f"# the timed steps only: dispatches between the two marker fills of bench.py "
+          f"({len(sel)} dispatches over {(t1 - t0) / 1e6:.2f} ms of wall time)")
+    print("# durations in microseconds; pct of the summed kernel time")
+    print(f"{'kernel':70s} {'calls':>6s} {'total_us':>10s} {'avg_us':>9s} {'pct':>6s}")
+    for name, (n, us, g) in sorted(stats.items(), key=lambda kv: -kv[1][1]):
+        nm = name if len(name) <= 70 else name[:67] + "..."
+        print(f"{nm:70s} {n:6d} {us:10.1f} {us / n:9.2f} {100 * us / tot:6.2f}")
+    print(f"# summed kernel time {tot:.1f} us")
+
+
+def summarize_pmc(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, kernels, label, commands, out_json):
+    """HBM bytes per launch of one launch class from two rocprofv3 --pmc runs
+    (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) of this script, scaled by
+    what the same counters read for a device copy of 1 GiB
+    (--copy-calibration runs); `kernels` are the HIP kernel name prefixes of
+    the class.  Writes the record beside the summary into `out_json`."""
+    import csv
+    import glob
+
+    def per_kernel(d, counter):
+        rows = []
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(f) as fh:
+                rows += [r for r in csv.DictReader(fh) if r["Counter_Name"] == counter]
+        acc = {}
+        for r in rows:
+            k = acc.setdefault(r["Kernel_Name"], [0, 0.0, r.get("Grid_Size", "")])
+            k[0] += 1
+            k[1] += float(r["Counter_Value"])
+        return acc
+
+    def copy_kib(d, counter):
+        acc = per_kernel(d, counter)
+        vals = [v[1] / v[0] for k, v in acc.items() if "copy" in k.lower()]
+        if not vals:
+            raise SystemExit(f"no copy kernel in the calibration run {d}")
+        return max(vals)
+
+    gib_kib = 1024.0 * 1024.0
+    f_scale = gib_kib / copy_kib(cal_fetch_dir, "FETCH_SIZE")
+    w_scale = gib_kib / copy_kib(cal_write_dir, "WRITE_SIZE")
+    fk, wk = per_kernel(fetch_dir, "FETCH_SIZE"), per_kernel(write_dir, "WRITE_SIZE")
+    sel = [k for k in fk if any(k.startswith(p) for p in kernels)]
+    if not sel:
+        raise SystemExit(f"no kernel named {kernels}")
+    fetch = sum(fk[k][1] / fk[k][0] for k in sel) * 1024 * f_scale
+    write = sum(wk[k][1] / wk[k][0] for k in sel if k in wk) * 1024 * w_scale
+    print(f"# {label}")
+    for c in commands:
+        print(f"#   {c}")
+    print(f"# calibration: a 1 GiB device copy reads FETCH_SIZE {gib_kib / f_scale:.1f} KiB and WRITE_SIZE "
+          f"{gib_kib / w_scale:.1f} KiB per dispatch, so bytes = FETCH_SIZE * 1024 * {f_scale:.4f} + "
+          f"WRITE_SIZE * 1024 * {w_scale:.4f}")
+    print("# kernels of the launch class (summed per launch):")
+    for k in sel:
+        print(f"#   {k}: {fk[k][0]} dispatch(es), FETCH_SIZE {fk[k][1] / fk[k][0]:.0f} KiB, "
+              f"WRITE_SIZE {wk.get(k, [1, 0.0])[1] / wk.get(k, [1, 0.0])[0]:.0f} KiB")
+    print(f"fetch_bytes_per_launch {fetch:.0f}")
+    print(f"write_bytes_per_launch {write:.0f}")
+    print(f"total_bytes_per_launch {fetch + write:.0f}")
+    print()
+    print("# every kernel of the counter runs, MB per dispatch (raw counters x 1024):")
+    print(f"{'kernel':60s} {'launches':>8s} {'fetch_MB':>10s} {'write_MB':>10s}")
+    for k, (n, v, g) in sorted(fk.items(), key=lambda kv: -kv[1][1]):
+        w = wk.get(k, [1, 0.0, ""])
+        nm = k if len(k) <= 60 else k[:57] + "..."
+        print(f"{nm:60s} {n:8d} {v / n * 1024 / 1e6:10.2f} {w[1] / w[0] * 1024 / 1e6:10.2f}")
+    return fetch + write
 
 
 def source_hash():
@@ -227,18 +367,26 @@ def run_form(probs, cfg, precision, steps, warmup, profile, seed=0, log=None, ti
             print(f"[bench] {precision} autotune: modes per level {modes} ({t_tune:.1f} s)", file=sys.stderr,
                   flush=True)
     # Kernel timing: every launch is bracketed by events during the warmup
-    # steps (the per-kernel table); the timed steps bracket only the launches
-    # of the roofline launch class picked from them, so that the events of
-    # the other launches do not slow the measured steps.
+    # steps, which launch the apply kernels directly (not as the captured
+    # graph) so that each kernel class of the apply is timed too: the
+    # per-kernel table.  The timed steps bracket only the launches of the
+    # roofline launch class picked from them, so that the events of the other
+    # launches do not slow the measured steps; when that class runs inside
+    # the captured apply graph (not visible to events), its launches are
+    # timed in a kernel pass of as many steps right after the timed ones,
+    # with the apply launched directly.
     its, lat, fac = [], [], []
     warm = {}
+    rl0 = None
     for j in range(warmup + steps):
         if profile and j == 0 and warmup > 0:
             torch.cuda.synchronize()
+            s.set_apply_graph(False)
             s.profile(True)
         if j == warmup:
             torch.cuda.synchronize()
             if profile:
+                s.set_apply_graph(graph)
                 if warmup > 0:
                     warm = s.profile_read()
                     s.profile(False)
@@ -247,6 +395,7 @@ def run_form(probs, cfg, precision, steps, warmup, profile, seed=0, log=None, ti
                     if rl0 is not None:
                         s.profile_select(rl0["kernel"].split("@")[0])
                 s.profile(True)
+            mark_kernel(torch)   # trace marker: the timed steps start
             t_start = time.perf_counter()
         ts = time.perf_counter()
         s.factorize(vals_all[j % len(vals_all)])
@@ -262,7 +411,23 @@ def run_form(probs, cfg, precision, steps, warmup, profile, seed=0, log=None, ti
                   f"it {it.tolist()}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     total = time.perf_counter() - t_start
+    mark_kernel(torch)   # trace marker: the timed steps ended
     raw = s.profile_read() if profile else {}
+    kernel_pass = None
+    if profile and graph and rl0 is not None and rl0["kernel"].startswith("apply_"):
+        # the roofline class runs inside the apply graph: time it in a pass of
+        # the same steps with the apply launched directly
+        s.profile(False)
+        s.set_apply_graph(False)
+        s.profile(True)
+        t0 = time.perf_counter()
+        for j in range(warmup, warmup + steps):
+            s.factorize(vals_all[j % len(vals_all)])
+            s.pcg(rhs[j].T, x.T, rtol=tol, maxit=1000)
+        torch.cuda.synchronize()
+        kernel_pass = {"steps": steps, "ms_per_step": round((time.perf_counter() - t0) / steps * 1e3, 3)}
+        raw = s.profile_read()
+        s.set_apply_graph(graph)
     if profile:
         s.profile(False)
         s.profile_select(None)
@@ -281,19 +446,19 @@ def run_form(probs, cfg, precision, steps, warmup, profile, seed=0, log=None, ti
     s.close()
     return dict(total=total, lat=lat, fac=fac, its=its, info=info, stats=stats, analyze_s=t_an,
                 true_rel=true_rel, nrhs=nrhs, by_level=by_level, modes=modes, tune_s=t_tune,
-                timed_stats=timed_stats, timed_by_level=timed_by_level, prof_steps=prof_steps)
+                timed_stats=timed_stats, timed_by_level=timed_by_level, prof_steps=prof_steps, kernel_pass=kernel_pass)
 
 
 def roofline(stats, by_level, precision, steps):
     """Roofline of the dominant kernel launch class: the largest event time
-    among one kernel at one level (factorization, "kernel@L<t>") and the CG
-    kernels.  The apply sweep runs as one captured graph, so its kernels are
-    timed together ("apply_graph") and are not candidates.  The class is
-    picked from the warmup steps (every launch timed); the figures come from
-    its launches in the timed steps (only that class timed there)."""
+    among one kernel at one level ("kernel@L<t>": factorization and apply
+    kernels) and the CG kernels.  The class is picked from the warmup steps
+    (every launch timed, the apply launched directly); the figures come from
+    its launches in the timed steps (only that class timed there), or from
+    the kernel pass when the class runs inside the captured apply graph."""
     cand = dict(by_level)
     cand.update({k: v for k, v in stats.items() if k.startswith("cg_")})
-    cand = {k: v for k, v in cand.items() if not k.startswith("apply_graph") and v["ms"] > 0}
+    cand = {k: v for k, v in cand.items() if "graph" not in k and v["ms"] > 0}
     if not cand:
         return None
     name, k = max(cand.items(), key=lambda kv: kv[1]["ms"])
@@ -323,9 +488,32 @@ def roofline(stats, by_level, precision, steps):
             "avg_launch_ms": round(per, 4), "launches": k["launches"], "share_of_gpu_time": None}
 
 
+def host_description():
+    """Host cores, CPU model and the BLAS behind NumPy."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        from threadpoolctl import threadpool_info
+        blas = [f"{i.get('internal_api')} {i.get('version')} ({i.get('num_threads')} threads)"
+                for i in threadpool_info() if i.get("user_api") == "blas"]
+    except Exception:
+        blas = []
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"nproc": usable, "cpu_model": model, "blas": blas or ["unknown"]}
+
+
 def cpu_baseline(key, seed, sample_grid):
-    """The oracle (FP64 NumPy) on a bounded sample of the workload, one thread,
-    scaled to the full problem by the unknown count (the method is O(n))."""
+    """The oracle (FP64 NumPy) on a bounded sample of the workload, scaled to
+    the full problem by the unknown count (the method is O(n)): once on one
+    thread (as the paper's sequential runs) and once with every host core
+    available to the BLAS.  `value` is the faster of the two; both are
+    reported."""
     from threadpoolctl import threadpool_limits
     from oracle import sgf_oracle as O
     from sgf_inputs.problems import config_problem, random_rhs
@@ -333,16 +521,62 @@ def cpu_baseline(key, seed, sample_grid):
     p, cfg = config_problem(key, seed=seed, grid=sample_grid)
     c = CONFIGS[key]
     n_full = int(np.prod(c["grid"])) if "grid" in c else 3 * (c["nodes"] - 1) * c["nodes"] ** 2
-    with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        F = O.factorize(p.csr(), p.coords, p.grid, p.dpn, O.Options(q=cfg["q"], leaf=cfg["leaf"]))
-        t1 = time.perf_counter()
-        x, it, rel = O.pcg(p.csr(), random_rhs(seed, p.n), lambda r: O.apply_inverse(F, r), tol=cfg["tol"])
-        t2 = time.perf_counter()
-    per_solve = (t2 - t0) * n_full / p.n
-    return {"value": round(1.0 / per_solve, 6), "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"{key} at grid {tuple(sample_grid)} (n={p.n}): factorize {t1 - t0:.1f} s + CG {t2 - t1:.1f} s "
-                      f"({it} it), FP64 NumPy, one thread; scaled by n_full/n_sample = {n_full / p.n:.0f}"}
+    host = host_description()
+    legs = {}
+    for threads in (1, host["nproc"]):
+        with threadpool_limits(limits=threads):
+            t0 = time.perf_counter()
+            F = O.factorize(p.csr(), p.coords, p.grid, p.dpn, O.Options(q=cfg["q"], leaf=cfg["leaf"]))
+            t1 = time.perf_counter()
+            x, it, rel = O.pcg(p.csr(), random_rhs(seed, p.n), lambda r: O.apply_inverse(F, r), tol=cfg["tol"])
+            t2 = time.perf_counter()
+        legs[threads] = {"value": round(n_full and 1.0 / ((t2 - t0) * n_full / p.n), 6), "cores": threads,
+                         "factorize_s": round(t1 - t0, 2), "cg_s": round(t2 - t1, 2), "it": int(it)}
+    best = max(legs.values(), key=lambda v: v["value"])
+    return {"value": best["value"], "unit": "solves/s", "cores": best["cores"], "kind": "oracle",
+            "sample": f"{key} at grid {tuple(sample_grid)} (n={p.n}), FP64 NumPy, factorize + CG "
+                      f"({legs[1]['it']} it); scaled by n_full/n_sample = {n_full / p.n:.0f}",
+            "single_thread": legs[1], "all_cores": legs[host["nproc"]], "host": host}
+
+
+def cpu_baseline_serving(pool, a, res, reqs):
+    """The oracle on a bounded sample of the request mix: a new-operator
+    request (factorization + one solve) on the smallest 2D and the smallest 3D
+    operator of the pool, timed on one thread; the stream's total oracle time
+    is estimated by scaling each request's factorization and solves by its
+    operator's unknown count (the method is O(n)) and weighting the
+    right-hand sides it carries."""
+    from threadpoolctl import threadpool_limits
+    from oracle import sgf_oracle as O
+    from sgf_inputs.problems import random_rhs
+    per_n = {}
+    detail = []
+    for idx, tag in ((0, "2D"), (len(SERVE_2D) * a.pool, "3D")):
+        prob, kw = pool[idx]
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            F = O.factorize(prob.csr(), prob.coords, prob.grid, prob.dpn, O.Options(q=kw["q"], leaf=kw["leaf"]))
+            t1 = time.perf_counter()
+            x, it, rel = O.pcg(prob.csr(), random_rhs(a.seed, prob.n), lambda r: O.apply_inverse(F, r), tol=1e-8)
+            t2 = time.perf_counter()
+        per_n[tag] = ((t1 - t0) / prob.n, (t2 - t1) / prob.n)
+        detail.append(f"{tag} n={prob.n}: factorize {t1 - t0:.2f} s, solve {t2 - t1:.2f} s ({it} it)")
+    total, solves = 0.0, 0
+    ops = []
+    for (kind, ref, k) in reqs:
+        if kind == "new":
+            ops.append(ref)
+            prob = pool[ref][0]
+        else:
+            prob = pool[ops[ref]][0]
+        tag = "2D" if prob.dim == 2 else "3D"
+        fac, sol = per_n[tag]
+        total += (fac if kind == "new" else 0.0) * prob.n + k * sol * prob.n
+        solves += k
+    return {"value": round(solves / total, 6), "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": "one new-operator request (factorize + one solve to 1e-8) on the smallest 2D and 3D operator "
+                      "of the pool, FP64 NumPy, one thread (" + "; ".join(detail) + "), scaled per request by n "
+                      "(factorization for new operators, one solve per right-hand side) over the timed stream"}
 
 
 def main():
@@ -363,13 +597,43 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="skip the per-level path autotuner")
     ap.add_argument("--no-graph", action="store_true",
                     help="launch the apply kernels directly (per-kernel apply timings) instead of the captured graph")
+    ap.add_argument("--summarize-trace", metavar="DIR",
+                    help="print the timed steps' per-kernel summary of a rocprofv3 kernel trace (CSV) of this script")
+    ap.add_argument("--label", default="", help="with --summarize-trace / --summarize-pmc: title line")
+    ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "CAL_FETCH_DIR", "CAL_WRITE_DIR"),
+                    help="HBM bytes per launch of --pmc-class from rocprofv3 FETCH_SIZE / WRITE_SIZE runs")
+    ap.add_argument("--pmc-class", default="", help="with --summarize-pmc: launch class (e.g. apply_lsi_bwd@L1)")
+    ap.add_argument("--pmc-kernels", default="", help="with --summarize-pmc: comma-separated HIP kernel name prefixes")
+    ap.add_argument("--command", default="", help="with --summarize-trace: the command that made the trace")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device-to-device copy of 1 GiB (reference for HBM byte counters)")
     ap.add_argument("--requests", type=int, default=300, help="serving: requests in the timed stream")
     ap.add_argument("--calibration", type=int, default=40, help="serving: closed-batch requests to measure capacity")
     ap.add_argument("--slots", type=int, default=4, help="serving: concurrent requests on the device")
     ap.add_argument("--pool", type=int, default=2, help="serving: coefficient fields per operator size")
+    ap.add_argument("--no-serving-roofline", action="store_true", help="serving: skip the profiled roofline pass")
     a = ap.parse_args()
+    if a.summarize_trace:
+        summarize_trace(a.summarize_trace, a.label, a.command)
+        return
+    if a.summarize_pmc:
+        import io
+        from contextlib import redirect_stdout
+        buf = io.StringIO()
+        with redirect_stdout(buf):
+            total = summarize_pmc(*a.summarize_pmc, a.pmc_kernels.split(","), a.label, a.command.split(" ;; "),
+                                  None)
+        text = buf.getvalue()
+        print(text, end="")
+        name = a.pmc_class.replace("@", "_at_")
+        summary = f"profiles/varcoef2d_1024_fp32_{name}_hbm_counters.txt"
+        open(os.path.join(ROOT, summary), "w").write(text)
+        path = os.path.join(ROOT, "profiles", "traffic.json")
+        t = json.load(open(path)) if os.path.exists(path) else {}
+        t[a.pmc_class] = {"bytes_per_launch": int(total), "hip_kernels": a.pmc_kernels.split(","),
+                          "source_hash": source_hash(), "summary": summary}
+        json.dump(t, open(path, "w"), indent=1)
+        return
     if a.copy_calibration:
         import torch
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
@@ -418,6 +682,9 @@ def main():
     if rl is not None:
         kms = main_form["timed_by_level"].get(rl["kernel"], main_form["timed_stats"].get(rl["kernel"], {"ms": 0}))["ms"]
         rl["share_of_gpu_time"] = round((kms / steps) / (gpu_ms / psteps), 3) if gpu_ms else None
+        rl["timed_in"] = ("a kernel pass of the same steps right after the timed ones, apply launched directly "
+                          f"({main_form['kernel_pass']['ms_per_step']} ms per step)" if main_form["kernel_pass"]
+                          else "the timed steps")
     out = {
         "metric": "PCG solves/s (numeric SGF factorization + CG solve to 1e-8 relative residual per solve)",
         "value": round(main_form["nrhs"] * 1e3 / ms, 4),

@@ -369,6 +369,16 @@ sgf_status sgf_set_band_elim(sgf_handle h, int32_t enable);
 sgf_status sgf_set_small_compress(sgf_handle h, int32_t enable);
 
 /*
+ * Coarsening into the next level (Secs. 4.3-4.4): enable = 1 (default) has
+ * the copy kernel compute every block's destination from the structure of
+ * the two levels and the sizes after the compressions (per-separator father
+ * and offset from the host); 0 builds the copy list of every block on the
+ * host instead.  The same copies, so the same factor bit for bit.  Re-plans
+ * and drops the factor.
+ */
+sgf_status sgf_set_device_coarsen(sgf_handle h, int32_t enable);
+
+/*
  * Kernel of the coarse couplings C_ab = T_a M_ab T_b^T of the pairs that
  * touch a compressed separator (Sec. 3.2): mode 0 one workgroup per pair
  * (its intermediate product in device scratch), 1 one wavefront per pair
@@ -382,9 +392,13 @@ sgf_status sgf_set_pair_kernel(sgf_handle h, int32_t mode);
 /*
  * Interior sweeps of the apply (Sec. 4.7) on levels whose M_II blocks have a
  * lower bandwidth of at most 64: enable = 1 (default) stages the band of L_I
- * in LDS and solves it one wavefront per right-hand side; 0 uses the blocked
- * sweeps that also serve dense interiors.  Both give the same result up to
- * rounding order.  Drops a captured apply graph.
+ * in LDS and solves it one wavefront per right-hand side, and with a single
+ * right-hand side on a level of the banded elimination gives each front one
+ * wavefront (band chunk and vector in LDS, four fronts per workgroup, the
+ * same operations in the same order, so the same bits); 2 keeps the banded
+ * sweeps but one workgroup per front for every right-hand-side count; 0 uses
+ * the blocked sweeps that also serve dense interiors.  All give the same
+ * result up to rounding order.  Drops a captured apply graph.
  */
 sgf_status sgf_set_band_apply(sgf_handle h, int32_t enable);
 

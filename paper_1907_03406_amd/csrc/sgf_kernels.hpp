@@ -25,7 +25,6 @@ __device__ __forceinline__ float bf16_round(float x) {
   return __uint_as_float(u & 0xffff0000u);
 }
 __device__ __forceinline__ double bf16_round(double x) { return (double)bf16_round((float)x); }
-
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
   for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
@@ -83,6 +82,48 @@ struct Mfma<double> {
   static __device__ __forceinline__ int drow(int lane, int v) { return lane / 16 + 4 * v; }
 };
 
+// The bfloat16 bits of that nearest value.
+__device__ __forceinline__ short bf16_bits(float x) { return (short)(__float_as_uint(bf16_round(x)) >> 16); }
+
+// 16 x 16 x 16 bfloat16 matrix-core step with FP32 accumulation
+// (v_mfma_f32_16x16x16_bf16).  Operand lane layout, checked on gfx950: lane l
+// supplies A[l % 16][4 (l / 16) + e] and B[4 (l / 16) + e][l % 16], e = 0..3;
+// D[4 (l / 16) + v][l % 16] sits in lane l, register v.
+typedef short mfma_v4bf __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ mfma_v4f mfma_bf16(mfma_v4bf a, mfma_v4bf b, mfma_v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// One wavefront forms rows i0 .. i0 + 15 of D (rows x cols, cols <= 16,
+// ld ldd) = A B from operands rounded to bfloat16, on the matrix cores: A is
+// rows x kk, read as a(i, j); B is kk x cols, read as b(j, p); entries
+// outside the extents are zero.
+template <typename T, typename FA, typename FB>
+__device__ __forceinline__ void wave_bf16_tile(int i0, int rows, int cols, int kk, FA a, FB b, T* D, int64_t ldd) {
+  const int lane = threadIdx.x % WAVE, r16 = lane % 16, k4 = 4 * (lane / 16);
+  mfma_v4f acc = {0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < kk; k0 += 16) {
+    mfma_v4bf av, bv;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int ia = i0 + r16, ja = k0 + k4 + e;
+      av[e] = (ia < rows && ja < kk) ? bf16_bits((float)a(ia, ja)) : (short)0;
+      bv[e] = (ja < kk && r16 < cols) ? bf16_bits((float)b(ja, r16)) : (short)0;
+    }
+    acc = mfma_bf16(av, bv, acc);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int i = i0 + k4 + v;
+    if (i < rows && r16 < cols) D[i + (int64_t)r16 * ldd] = (T)acc[v];
+  }
+}
+// All row tiles by one wavefront.
+template <typename T, typename FA, typename FB>
+__device__ __forceinline__ void wave_bf16_gemm(int rows, int cols, int kk, FA a, FB b, T* D, int64_t ldd) {
+  for (int i0 = 0; i0 < rows; i0 += 16) wave_bf16_tile<T>(i0, rows, cols, kk, a, b, D, ldd);
+}
+
 // ---------------------------------------------------------------------------
 // Fills and copies
 // ---------------------------------------------------------------------------
@@ -126,6 +167,86 @@ __global__ void k_copy_blocks2(const CopyDesc* __restrict__ D1, const T* __restr
     T v = src[d.src_off + i + (int64_t)j * d.src_ld];
     if (d.mode == 0) dst[d.dst_off + i + (int64_t)j * d.dst_ld] = v;
     else dst[d.dst_off + j + (int64_t)i * d.dst_ld] = v;
+  }
+}
+
+// Coarsening (Secs. 4.3-4.4, Eq. 4.7) with the destinations computed here:
+// item q < np copies the coarse part (ra x rb, ra / rb the sizes after the
+// compressions) of pair block q of the level below into the new level's
+// arena, at the place its CoarsenPair kind says (the kinds of the host copy
+// maps), with its transpose where the block lands in a symmetric
+// position; item np + p copies the Phi rows of separator p into its
+// father's Phi.  Every table index and every source and destination range
+// is checked against its table or buffer first; one outside sets *err and
+// the item copies nothing.
+template <typename T>
+__global__ __launch_bounds__(WG) void k_coarsen(
+    const PairDesc* __restrict__ CP, const CoarsenPair* __restrict__ map, int np, const CoarsenSep* __restrict__ seps,
+    int ns, const int* __restrict__ rank, const int32_t* __restrict__ father, const int32_t* __restrict__ loc,
+    const ElimDesc* __restrict__ NE, int n_ne, const PairDesc* __restrict__ NP, int n_np,
+    const int32_t* __restrict__ nbr_off, int64_t n_nbr, int n_clusters, int n_comp, const T* __restrict__ carena, int64_t c_front, int64_t c_elems, T* __restrict__ narena, int64_t n_front,
+    int64_t n_elems, const int64_t* __restrict__ c_slotptr, const int64_t* __restrict__ c_phioff,
+    const T* __restrict__ cphi, int64_t c_phi_elems, const int64_t* __restrict__ n_slotptr,
+    const int64_t* __restrict__ n_phioff, T* __restrict__ nphi, int64_t n_phi_elems, int pi, int do_phi,
+    int* __restrict__ err) {
+  const int item = blockIdx.x;
+  if (item < np) {
+    const PairDesc pd = CP[item];
+    const CoarsenPair mp = map[item];
+    const bool idx_ok = pd.ca < n_comp && pd.cb < n_comp && mp.pa >= 0 && mp.pa < ns && mp.pb >= 0 && mp.pb < ns &&
+                        mp.tgt >= 0 && ((mp.kind <= 0 || mp.kind > 5) ? mp.kind == 0 && mp.tgt < n_ne
+                                        : mp.kind == 1 || mp.kind >= 4 ? mp.tgt < n_np
+                                        : mp.tgt < n_ne && mp.e >= 0 && mp.e < n_nbr);
+    if (!idx_ok) {
+      if (threadIdx.x == 0) atomicExch(err, 1);
+      return;
+    }
+    const int ra = (pd.ca >= 0 && rank[pd.ca] < pd.s_a) ? rank[pd.ca] : pd.s_a;
+    const int rb = (pd.cb >= 0 && rank[pd.cb] < pd.s_b) ? rank[pd.cb] : pd.s_b;
+    if (ra == 0 || rb == 0) return;
+    const int oa = loc[mp.pa], ob = loc[mp.pb];
+    const int64_t src = c_front + pd.blk_off, sld = pd.s_a;
+    // destination of the block (d0) and of its transpose (d1)
+    const CoarsenDst cd = coarsen_dest(mp.kind, mp.tgt, mp.e, oa, ob, pd.a == pd.b, NE, NP, nbr_off, n_front);
+    const int64_t d0 = cd.d0, d1 = cd.d1, ld = cd.ld;
+    bool ok = mp.kind >= 0 && mp.kind <= 5 && src >= 0 && src + (ra - 1) + (int64_t)(rb - 1) * sld < c_elems;
+    if (d0 >= 0) ok = ok && d0 + (ra - 1) + (int64_t)(rb - 1) * ld < n_elems;
+    if (d1 >= 0) ok = ok && d1 + (rb - 1) + (int64_t)(ra - 1) * ld < n_elems;
+    if (d0 < 0 && d1 < 0) ok = false;
+    if (!ok) {
+      if (threadIdx.x == 0) atomicExch(err, 1);
+      return;
+    }
+    for (int idx = threadIdx.x; idx < ra * rb; idx += WG) {
+      const int i = idx % ra, j = idx / ra;
+      const T v = carena[src + i + (int64_t)j * sld];
+      if (d0 >= 0) narena[d0 + i + (int64_t)j * ld] = v;
+      if (d1 >= 0) narena[d1 + j + (int64_t)i * ld] = v;
+    }
+    return;
+  }
+  const int p = item - np;
+  if (!do_phi || p >= ns) return;
+  const CoarsenSep cs = seps[p];
+  if (cs.cluster < 0 || cs.ci >= n_comp || father[p] < 0 || father[p] >= n_clusters) {
+    if (threadIdx.x == 0) atomicExch(err, 1);
+    return;
+  }
+  const int sa = (int)(c_slotptr[cs.cluster + 1] - c_slotptr[cs.cluster]);
+  const int r = (cs.ci >= 0 && rank[cs.ci] < sa) ? rank[cs.ci] : sa;
+  if (r == 0) return;
+  const int D = father[p];
+  const int64_t dld = n_slotptr[D + 1] - n_slotptr[D];
+  const int64_t s0 = c_phioff[cs.cluster], d0 = n_phioff[D] + loc[p];
+  const bool ok = s0 >= 0 && d0 >= 0 && s0 + (r - 1) + (int64_t)(pi - 1) * sa < c_phi_elems &&
+                  d0 + (r - 1) + (int64_t)(pi - 1) * dld < n_phi_elems && loc[p] + r <= dld;
+  if (!ok) {
+    if (threadIdx.x == 0) atomicExch(err, 1);
+    return;
+  }
+  for (int idx = threadIdx.x; idx < r * pi; idx += WG) {
+    const int i = idx % r, j = idx / r;
+    nphi[d0 + i + (int64_t)j * dld] = cphi[s0 + i + (int64_t)j * sa];
   }
 }
 
@@ -907,15 +1028,38 @@ __global__ __launch_bounds__(WG) void k_compress(const CompDesc* __restrict__ D,
   // ---- N (Eq. 4.5): [L^T Phi_B | Mhat_BX Phi_X or Mhat_BX ... | 0] ----------
   for (int idx = threadIdx.x; idx < s * pi; idx += WG) {
     const int i = idx % s, p = idx / s;
-    T acc = 0, acc16 = 0;
+    T acc = 0;
 #pragma unroll 8
-    for (int j = i; j < s; ++j) {
-      const T f = F[j + (int64_t)i * ld], ph = PhB[j + (int64_t)p * s];
-      acc += f * ph;
-      if (bf16n) acc16 += bf16_round(f) * bf16_round(ph);
-    }
-    if (d.self_cols) N[i + (int64_t)p * s] = bf16n ? acc16 : acc;
+    for (int j = i; j < s; ++j) acc += F[j + (int64_t)i * ld] * PhB[j + (int64_t)p * s];
+    if (d.self_cols && !bf16n) N[i + (int64_t)p * s] = acc;
     LtP[i + (int64_t)p * s] = acc;
+  }
+  // BF16N form: the products of N from bfloat16 operands on the matrix cores
+  // (FP32 accumulation), 16-row tiles of every block dealt to the wavefronts
+  if (bf16n && pi <= 16) {
+    const int wv = threadIdx.x / WAVE, nt = (s + 15) / 16;
+    int task = 0;
+    if (d.self_cols)
+      for (int t = 0; t < nt; ++t, ++task)
+        if (task % (WG / WAVE) == wv)
+          wave_bf16_tile<T>(16 * t, s, pi, s, [&](int i, int j) { return j >= i ? F[j + (int64_t)i * ld] : T(0); },
+                            [&](int j, int p) { return PhB[j + (int64_t)p * s]; }, N, s);
+    for (int q = 0; q < d.nnb; ++q) {
+      const CompNbr x = NB[d.nb_ptr + q];
+      if (x.full) continue;
+      const T* PhX = phi + x.phi_off;
+      for (int t = 0; t < nt; ++t, ++task)
+        if (task % (WG / WAVE) == wv)
+          wave_bf16_tile<T>(16 * t, s, pi, x.s_x, [&](int i, int j) { return F[(x.row + j) + (int64_t)i * ld]; },
+                            [&](int j, int p) { return PhX[j + (int64_t)p * x.s_x]; }, N + (int64_t)x.col * s, s);
+    }
+  } else if (bf16n && d.self_cols) {
+    for (int idx = threadIdx.x; idx < s * pi; idx += WG) {
+      const int i = idx % s, p = idx / s;
+      T acc16 = 0;
+      for (int j = i; j < s; ++j) acc16 += bf16_round(F[j + (int64_t)i * ld]) * bf16_round(PhB[j + (int64_t)p * s]);
+      N[i + (int64_t)p * s] = acc16;
+    }
   }
   int cend = d.self_cols;
   for (int q = 0; q < d.nnb; ++q) {
@@ -930,17 +1074,18 @@ __global__ __launch_bounds__(WG) void k_compress(const CompDesc* __restrict__ D,
       continue;
     }
     const T* PhX = phi + x.phi_off;
-    for (int idx = threadIdx.x; idx < s * pi; idx += WG) {
-      const int i = idx % s, p = idx / s;
-      T acc = 0;
-      if (bf16n)
-        for (int j = 0; j < x.s_x; ++j)
-          acc += bf16_round(F[(x.row + j) + (int64_t)i * ld]) * bf16_round(PhX[j + (int64_t)p * x.s_x]);
-      else
+    if (!(bf16n && pi <= 16))
+      for (int idx = threadIdx.x; idx < s * pi; idx += WG) {
+        const int i = idx % s, p = idx / s;
+        T acc = 0;
+        if (bf16n)
+          for (int j = 0; j < x.s_x; ++j)
+            acc += bf16_round(F[(x.row + j) + (int64_t)i * ld]) * bf16_round(PhX[j + (int64_t)p * x.s_x]);
+        else
 #pragma unroll 8
-        for (int j = 0; j < x.s_x; ++j) acc += F[(x.row + j) + (int64_t)i * ld] * PhX[j + (int64_t)p * x.s_x];
-      N[i + (int64_t)(x.col + p) * s] = acc;
-    }
+          for (int j = 0; j < x.s_x; ++j) acc += F[(x.row + j) + (int64_t)i * ld] * PhX[j + (int64_t)p * x.s_x];
+        N[i + (int64_t)(x.col + p) * s] = acc;
+      }
     cend = x.col + pi;
   }
   for (int idx = threadIdx.x; idx < s * (c - cend); idx += WG) N[(int64_t)cend * s + idx] = T(0);
@@ -1086,15 +1231,27 @@ __global__ __launch_bounds__(WAVE) void k_compress_small(const CompDesc* __restr
   // ---- N (Eq. 4.5) and L^T Phi_B ----
   for (int idx = lane; idx < s * pi; idx += WAVE) {
     const int i = idx % s, p = idx / s;
-    T acc = 0, acc16 = 0;
+    T acc = 0;
 #pragma unroll 8
-    for (int j = i; j < s; ++j) {
-      const T f = Fl[j + i * ldf], ph = Ph[j + p * R];
-      acc += f * ph;
-      if (bf16n) acc16 += bf16_round(f) * bf16_round(ph);
-    }
-    if (d.self_cols) Nl[i + p * ldn] = bf16n ? acc16 : acc;
+    for (int j = i; j < s; ++j) acc += Fl[j + i * ldf] * Ph[j + p * R];
+    if (d.self_cols && !bf16n) Nl[i + p * ldn] = acc;
     Lt[i + p * s] = acc;
+  }
+  // BF16N form: the products of N from bfloat16 operands on the matrix cores
+  // (FP32 accumulation); pi <= 16 columns per block
+  const bool mma = bf16n && pi <= 16;
+  if (bf16n && d.self_cols) {
+    if (mma) {
+      wave_bf16_gemm<T>(s, pi, s, [&](int i, int j) { return j >= i ? Fl[j + i * ldf] : T(0); },
+                        [&](int j, int p) { return Ph[j + p * R]; }, Nl, ldn);
+    } else {
+      for (int idx = lane; idx < s * pi; idx += WAVE) {
+        const int i = idx % s, p = idx / s;
+        T acc16 = 0;
+        for (int j = i; j < s; ++j) acc16 += bf16_round(Fl[j + i * ldf]) * bf16_round(Ph[j + p * R]);
+        Nl[i + p * ldn] = acc16;
+      }
+    }
   }
   int cend = d.self_cols;
   for (int q = 0; q < d.nnb; ++q) {
@@ -1108,16 +1265,22 @@ __global__ __launch_bounds__(WAVE) void k_compress_small(const CompDesc* __restr
       cend = x.col + x.s_x;
       continue;
     }
-    for (int idx = lane; idx < s * pi; idx += WAVE) {
-      const int i = idx % s, p = idx / s;
-      T acc = 0;
-      if (bf16n)
-        for (int j = 0; j < x.s_x; ++j)
-          acc += bf16_round(Fl[(x.row + j) + i * ldf]) * bf16_round(Ph[(x.row + j) + p * R]);
-      else
+    if (mma) {
+      const int xr = x.row;
+      wave_bf16_gemm<T>(s, pi, x.s_x, [&](int i, int j) { return Fl[(xr + j) + i * ldf]; },
+                        [&](int j, int p) { return Ph[(xr + j) + p * R]; }, Nl + x.col * ldn, ldn);
+    } else {
+      for (int idx = lane; idx < s * pi; idx += WAVE) {
+        const int i = idx % s, p = idx / s;
+        T acc = 0;
+        if (bf16n)
+          for (int j = 0; j < x.s_x; ++j)
+            acc += bf16_round(Fl[(x.row + j) + i * ldf]) * bf16_round(Ph[(x.row + j) + p * R]);
+        else
 #pragma unroll 8
-        for (int j = 0; j < x.s_x; ++j) acc += Fl[(x.row + j) + i * ldf] * Ph[(x.row + j) + p * R];
-      Nl[i + (x.col + p) * ldn] = acc;
+          for (int j = 0; j < x.s_x; ++j) acc += Fl[(x.row + j) + i * ldf] * Ph[(x.row + j) + p * R];
+        Nl[i + (x.col + p) * ldn] = acc;
+      }
     }
     cend = x.col + pi;
   }
@@ -1908,15 +2071,26 @@ __global__ __launch_bounds__(WG) void k_band_fwd(const ElimDesc* __restrict__ D,
     const bool on = i < m;
     T x = on ? vc[i] : T(0);
     const T dinv = on ? Bd[i] : T(0);
-    // columns of earlier chunks inside the band (their values are final)
-    for (int r = lane + 1; r <= bw; ++r)
-      if (on && i - r >= 0) x -= Bd[r * ld + i] * vc[i - r];
+    const int ic = min(i, m - 1);
+    // columns of earlier chunks inside the band (their values are final),
+    // ascending r; branch-free (clamped addresses, selected updates) so the
+    // LDS reads do not wait on the chain
 #pragma unroll 4
-    for (int jj = 0; jj < cn; ++jj) {
-      const T xj = lane_bcast(x * dinv, jj);
-      const int r = lane - jj;
-      if (r == 0) x = xj;
-      else if (r > 0 && r <= bw && on) x -= Bd[r * ld + i] * xj;
+    for (int r = 1; r <= bw; ++r) {
+      const T a = Bd[r * ld + ic], xv = vc[max(i - r, 0)];
+      x = (r > lane && on && i - r >= 0) ? x - a * xv : x;
+    }
+    // steps past the chunk (cn up to a multiple of 8) broadcast zeros from
+    // rows past m and change nothing
+    const int cn8 = (cn + 7) & ~7;
+    for (int j0 = 0; j0 < cn8; j0 += 8) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int jj = j0 + u, r = lane - jj;
+        const T xj = lane_bcast(x * dinv, jj);
+        const T a = Bd[min(max(r, 0), bw) * ld + ic];
+        x = r == 0 ? xj : ((r > 0 && r <= bw && on) ? x - a * xj : x);
+      }
     }
     if (on) vc[i] = x;
   };
@@ -2083,15 +2257,23 @@ __global__ __launch_bounds__(WG) void k_band_bwd(const ElimDesc* __restrict__ D,
       const bool on = i < m;
       T x = on ? vc[i] : T(0);
       const T dinv = on ? Bd[i] : T(0);
-      // rows of later chunks inside the band (their values are final)
-      for (int r = WAVE - lane; r <= bw; ++r)
-        if (on && i + r < m) x -= Bd[r * ld + i + r] * vc[i + r];
+      // rows of later chunks inside the band (their values are final),
+      // ascending r; branch-free as in the forward sweep
 #pragma unroll 4
-      for (int jj = cn - 1; jj >= 0; --jj) {
-        const T xj = lane_bcast(x * dinv, jj);
-        const int r = jj - lane;
-        if (r == 0) x = xj;
-        else if (r > 0 && r <= bw) x -= Bd[r * ld + i0 + jj] * xj;
+      for (int r = 1; r <= bw; ++r) {
+        const int ir = min(i + r, m - 1);
+        const T a = Bd[r * ld + ir], xv = vc[ir];
+        x = (r >= WAVE - lane && on && i + r < m) ? x - a * xv : x;
+      }
+      const int cn8 = (cn + 7) & ~7;
+      for (int j0 = cn8 - 8; j0 >= 0; j0 -= 8) {
+#pragma unroll
+        for (int u = 7; u >= 0; --u) {
+          const int jj = j0 + u, r = jj - lane;
+          const T xj = lane_bcast(x * dinv, jj);
+          const T a = Bd[min(max(r, 0), bw) * ld + min(i0 + jj, m - 1)];
+          x = r == 0 ? xj : ((r > 0 && r <= bw && jj < cn) ? x - a * xj : x);
+        }
       }
       if (on) vc[i] = x;
     }
@@ -2108,6 +2290,255 @@ __global__ __launch_bounds__(WG) void k_band_bwd(const ElimDesc* __restrict__ D,
 // Columns are independent: workgroup blockIdx.y forms columns
 // [CEB * blockIdx.y, CEB * (blockIdx.y + 1)) of T_B.
 constexpr int CEB = 64;
+// ---------------------------------------------------------------------------
+// Banded interior sweeps with one right-hand side, split by what bounds
+// them (the level-1 interiors of a grid: lower bandwidth bw < 32, at most 64
+// separator rows, packed factor copy):
+//  * the band solves x = L_I^{-1} y_I and x = L_I^{-T} y_I are a chain of m
+//    dependent row steps over few bytes (the band): one wavefront per front,
+//    one 64-row chunk at a time, x and the band of every chunk in registers;
+//  * the products with L_SI (t = L_SI x forward, y_I - L_SI^T y_S backward)
+//    stream most of the factor's bytes: four wavefronts per front, each over
+//    one residue class of the summation index, combined in LDS.
+// The products, partial sums and their order are those of k_band_fwd /
+// k_band_bwd, so the same values (see k_band1_solve for the sign of zeros).
+// ---------------------------------------------------------------------------
+constexpr int B1_FRONTS = WG / WAVE;
+__host__ __device__ inline int band1_xs(int mmax) { return (mmax + WAVE - 1) / WAVE * WAVE; }
+// fronts of at most B1_MAXC 64-row chunks: the band of all of them is loaded
+// into registers at once
+constexpr int B1_MAXC = 4;
+// LDS of a band solve (per wavefront): S, 64 rows of band1_ls(NB) (the
+// entries of a row that one group of eight steps can reach), E, NB rows of
+// band1_le(NB) (the entries that reach into the neighbouring chunk), and 64
+// zeros.  Odd row lengths, so that 64 lanes reading one entry of their own
+// row each hit distinct banks.
+__host__ __device__ constexpr int band1_ls(int nb) { return (nb + 13) | 1; }
+__host__ __device__ constexpr int band1_le(int nb) { return nb | 1; }
+__host__ __device__ inline int64_t band1_lds_elems(int mmax, int nb) {
+  (void)mmax;
+  return (int64_t)WAVE * band1_ls(nb) + (int64_t)nb * band1_le(nb) + WAVE;
+}
+
+// x = L_I^{-1} y_I (forward) or x = L_I^{-T} y_I (backward) for the fronts
+// list[0..n), one per wavefront (blockDim.x / 64 per workgroup), y in slot
+// order.  NB >= bw + 1 (17 or 32), m <= 64 * B1_MAXC.
+//
+// Lane l owns row i = i0 + l of the 64-row chunk at i0 and keeps x_i in a
+// register.  The chunk is solved in row steps j = 0..63 (backward 63..0):
+// x_j / L_jj is broadcast from lane j (readlane) and every lane subtracts its
+// coefficient of x_j times it, zero for the rows the step does not touch.
+// The steps go in groups of eight; the lanes a group touches read their
+// coefficients from their row of S at eight consecutive offsets (the row
+// holds the band entries of row i, forward, or of column i, backward, at
+// their distance from the diagonal, zeros around them), the others from the
+// zero block, so a step is a read at a constant offset, one multiply, one
+// readlane and one multiply-add.  The entries reaching into the neighbouring
+// chunk (already solved) are applied first from E, with the neighbour's
+// final values broadcast from its registers.  Positions of S and E written
+// for one chunk are the same for every chunk (entries past bw or m written
+// as zeros), so both are cleared once.  A lane's own step and the steps after
+// it add zero products and its result is x_i / L_ii at the end; the touched
+// steps are those of k_band_fwd / k_band_bwd in the same order, so the same
+// values (a zero product can turn a -0 into +0).  The band of every chunk,
+// the slots and y are loaded first, all issued unconditionally (indices
+// clamped into the front), so that a front waits for global memory about
+// twice.
+template <typename T, int NB, bool FWD>
+__global__ __launch_bounds__(WG) void k_band1_solve(const ElimDesc* __restrict__ D, const int32_t* __restrict__ list,
+                                                    int n, const int32_t* __restrict__ slots, T* __restrict__ y,
+                                                    const T* __restrict__ pk, int lds_per_wave) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  constexpr int LS = band1_ls(NB), LE = band1_le(NB);
+  // S offset of a touched row at the first step of a group: forward, the
+  // entry L[i][i - r] sits at OFF - r; backward, L[i + r][i] at OFF + r
+  constexpr int OFF = FWD ? NB + 6 : 6;
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  const int fi = blockIdx.x * (blockDim.x / WAVE) + w;   // one front per wavefront
+  if (fi >= n) return;   // whole wavefront: no workgroup barrier below
+  const ElimDesc d = D[list[fi]];
+  const int m = d.m, bw = min(d.bw, max(m - 1, 0));
+  const int pld = band_pk_ld(m);
+  T* S = reinterpret_cast<T*>(smem_raw) + (int64_t)w * lds_per_wave;
+  T* E = S + WAVE * LS;
+  T* Z = E + NB * LE;
+  const int ZO = WAVE * LS + NB * LE;   // offset of the zeros from S
+  const T* PB = pk + d.pk_off;
+  const int32_t* sl = slots + d.slot_off;
+  const int nch = (m + WAVE - 1) / WAVE;
+  // band of every chunk, nbs[c][r] = PB[r][64 c + lane], then y
+  T nbs[B1_MAXC][NB];
+#pragma unroll
+  for (int c = 0; c < B1_MAXC; ++c) {
+    const int ic = min(c * WAVE + lane, m - 1);
+#pragma unroll
+    for (int r = 0; r < NB; ++r) nbs[c][r] = PB[(int64_t)min(r, bw) * pld + ic];
+  }
+  int32_t sv[B1_MAXC];
+  T xr[B1_MAXC];
+#pragma unroll
+  for (int c = 0; c < B1_MAXC; ++c) sv[c] = sl[min(c * WAVE + lane, m - 1)];
+#pragma unroll
+  for (int c = 0; c < B1_MAXC; ++c) xr[c] = y[sv[c]];
+#pragma unroll
+  for (int p = 0; p < LS; ++p) S[lane * LS + p] = T(0);
+  if (lane < NB)
+    for (int p = 0; p < LE; ++p) E[lane * LE + p] = T(0);
+  Z[lane] = T(0);
+  __builtin_amdgcn_wave_barrier();
+  auto chunk = [&](const int c, const T (&nb)[NB], T& xc, const T& xn) {
+    // xn: the registers of the neighbouring chunk (solved before)
+    const int i0 = c * WAVE, i = i0 + lane, cn = min(WAVE, m - i0);
+    const bool on = i < m;
+    T x = on ? xc : T(0);
+    const int cn8 = (cn + 7) & ~7;   // steps past the chunk broadcast zeros from rows past m
+    if (FWD) {
+      // row i: L[i][i - r] = nb[r] into S at OFF - r; the entries with
+      // i - r before the chunk (r > l) also into E[l][r - l]
+#pragma unroll
+      for (int r = 1; r < NB; ++r) {
+        const T v = ((r <= bw) & on) ? nb[r] : T(0);
+        S[lane * LS + OFF - r] = v;
+        if (r > lane) E[lane * LE + r - lane] = c > 0 ? v : T(0);
+      }
+      __builtin_amdgcn_wave_barrier();
+      // columns i0 - k of the earlier chunk inside the band (final values,
+      // lane 64 - k of its registers), k = r - l ascending
+      const int eb = lane < NB - 1 ? lane * LE : ZO - WAVE * LS;
+#pragma unroll
+      for (int k = 1; k < NB; ++k) x = x - E[eb + k] * lane_bcast(xn, WAVE - k);
+      const T dinv = nb[0];
+      for (int j0 = 0; j0 < cn8; j0 += 8) {
+        const bool touched = (lane >= j0 + 1) & (lane <= j0 + 7 + bw);
+        const int sb = touched ? lane * LS + j0 - lane + OFF : ZO;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const T xj = lane_bcast(x * dinv, j0 + u);
+          x = x - S[sb + u] * xj;
+        }
+      }
+      xc = x * dinv;
+    } else {
+      // rows i0 + 64 + k of the later chunk inside the band first (final
+      // values, lane k of its registers), ascending k; their entries
+      // L[i0 + 64 + k][i] were written to E by that chunk
+      const int e0 = WAVE - (NB - 1);
+      const int eb = lane >= e0 ? (lane - e0) * LE : ZO - WAVE * LS;
+#pragma unroll
+      for (int k = 0; k < NB - 1; ++k) x = x - E[eb + k] * lane_bcast(xn, k);
+      __builtin_amdgcn_wave_barrier();
+      // column i: L[i + r][i] = nb[r] into the S row of lane l - r at
+      // OFF + r; for l < r (rows of the chunk before) into E[NB - 1 + l - r][l],
+      // read by that chunk
+#pragma unroll
+      for (int r = 1; r < NB; ++r) {
+        const T v = ((r <= bw) & on) ? nb[r] : T(0);
+        const int row = lane - r;
+        const int pos = row >= 0 ? row * LS + OFF + r : WAVE * LS + (NB - 1 + row) * LE + lane;
+        S[pos] = v;
+      }
+      __builtin_amdgcn_wave_barrier();
+      const T dinv = nb[0];
+      for (int j0 = cn8 - 8; j0 >= 0; j0 -= 8) {
+        const bool touched = (lane >= j0 - bw) & (lane <= j0 + 6);
+        const int sb = touched ? lane * LS + j0 - lane + OFF : ZO;
+#pragma unroll
+        for (int u = 7; u >= 0; --u) {
+          const T xj = lane_bcast(x * dinv, j0 + u);
+          x = x - S[sb + u] * xj;
+        }
+      }
+      xc = x * dinv;
+    }
+    __builtin_amdgcn_wave_barrier();
+  };
+  const T zero = T(0);
+  if (FWD) {
+#pragma unroll
+    for (int c = 0; c < B1_MAXC; ++c)
+      if (c < nch) chunk(c, nbs[c], xr[c], c > 0 ? xr[c > 0 ? c - 1 : 0] : zero);
+  } else {
+#pragma unroll
+    for (int c = B1_MAXC - 1; c >= 0; --c)
+      if (c < nch) chunk(c, nbs[c], xr[c], c + 1 < nch ? xr[c + 1 < B1_MAXC ? c + 1 : c] : zero);
+  }
+#pragma unroll
+  for (int c = 0; c < B1_MAXC; ++c)
+    if (c * WAVE + lane < m) y[sv[c]] = xr[c];
+}
+
+// t = L_SI x (forward): one workgroup per front; wavefront q sums the
+// columns j = q mod 4 in ascending j for the separator row of its lane, and
+// the four partial sums are added in the order q = 0..3.
+template <typename T>
+__global__ __launch_bounds__(WG) void k_band1_lsi(const ElimDesc* __restrict__ D, const int32_t* __restrict__ slots,
+                                                  const T* __restrict__ y, T* __restrict__ tscr,
+                                                  const T* __restrict__ pk, int xs_elems) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* xs = reinterpret_cast<T*>(smem_raw);   // x (m <= xs_elems)
+  T* part = xs + xs_elems;                  // 4 x 64 partial sums
+  const ElimDesc d = D[blockIdx.x];
+  const int m = d.m, k = d.k, bw = min(d.bw, max(m - 1, 0));
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  const int32_t* sl = slots + d.slot_off;
+  for (int i = threadIdx.x; i < m; i += WG) xs[i] = y[sl[i]];
+  __syncthreads();
+  T acc = 0;
+  if (lane < k) {
+    const T* cr = pk + d.pk_off + band_pk_lsi(m, bw) + lane;
+#pragma unroll 16
+    for (int j = w; j < m; j += 4) acc += cr[(int64_t)j * k] * xs[j];
+  }
+  part[w * WAVE + lane] = acc;
+  __syncthreads();
+  if (w == 0 && lane < k) {
+    T sum = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sum += part[q * WAVE + lane];
+    tscr[d.t_off + lane] = sum;
+  }
+}
+
+// y_I <- y_I - L_SI^T y_S (backward): one workgroup per front; 64-column
+// tiles of L_SI staged in LDS so that the lane of column j reads its column;
+// wavefront q sums the rows r = q mod 4 in ascending r, the partial sums are
+// added in the order q = 0..3 and subtracted.
+template <typename T>
+__global__ __launch_bounds__(WG) void k_band1_lsit(const ElimDesc* __restrict__ D, const int32_t* __restrict__ slots,
+                                                   const int32_t* __restrict__ nslots, T* __restrict__ y,
+                                                   const T* __restrict__ pk) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const ElimDesc d = D[blockIdx.x];
+  const int m = d.m, k = d.k, bw = min(d.bw, max(m - 1, 0));
+  const int ldk = k | 1;
+  T* tile = reinterpret_cast<T*>(smem_raw);   // WAVE columns x k rows, ld ldk
+  T* ys = tile + WAVE * (BE_KMAX | 1);        // y_S (k)
+  T* part = ys + BE_KMAX;                     // 4 x 64 partial sums
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  const int32_t* sl = slots + d.slot_off;
+  const int32_t* ns = nslots + d.nslot_off;
+  const T* PL = pk + d.pk_off + band_pk_lsi(m, bw);
+  for (int r = threadIdx.x; r < k; r += WG) ys[r] = y[ns[r]];
+  for (int j0 = 0; j0 < m; j0 += WAVE) {
+    const int cw = min(WAVE, m - j0);
+    lds_gather<T, 8>(tile, PL + (int64_t)j0 * k, k * cw,
+                     [=](int idx) { return make_int2(idx, (idx / k) * ldk + idx % k); });
+    __syncthreads();
+    T acc = 0;
+    if (lane < cw)
+      for (int r = w; r < k; r += 4) acc += tile[lane * ldk + r] * ys[r];
+    part[w * WAVE + lane] = acc;
+    __syncthreads();
+    if (w == 0 && lane < cw) {
+      T sum = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) sum += part[q * WAVE + lane];
+      y[sl[j0 + lane]] -= sum;
+    }
+    __syncthreads();
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(WG) void k_comp_explicit(const CompApply* __restrict__ A, const T* __restrict__ cf,
                                                       const T* __restrict__ nbuf, const T* __restrict__ tau_all,

@@ -232,7 +232,20 @@ struct LevelDev {
   int band_ptr[5] = {0, 0, 0, 0, 0};
   bool band_ok = false;
   DevBuf band_list;
+  // the one-right-hand-side band solves: fronts of bandwidth <= 16 (the
+  // first b1_split), then the others
+  std::vector<int32_t> h_b1_list;
+  int b1_split = 0;
+  DevBuf b1_list;
   DevBuf fixrank;            // low-rank equivalent: the recorded rank of every compression
+  // device coarsening into the next level: structure tables (CoarsenPair per
+  // pair block, CoarsenSep per separator; coarsen_static once uploaded for
+  // the current structure), and each separator's father and first row there
+  DevBuf cpairs, cseps, cfather, cloc;
+  std::vector<sgf::CoarsenPair> h_cpairs;   // host copies: an upload batch reads them when it is flushed
+  std::vector<sgf::CoarsenSep> h_cseps;
+  bool coarsen_static = false;
+  DevBuf nbroff;             // offset of each neighbour inside an interior's front (nbr_off)
   DevBuf pk;                 // packed factor copies of the banded fronts (ElimDesc::pk_off)
   int64_t pk_elems = 0;
 };
@@ -383,10 +396,14 @@ struct sgf_handle_s {
   bool use_graph = true;
   bool capturing = false;   // a graph is being recorded: launch directly
   bool band_apply = true;
+  bool band1 = true;         // one wavefront per banded front for one right-hand side
   bool band_elim = true;
   bool small_comp = true;
   int32_t persist_cap = 0;   // > 0: per-level work lists persistent on at most this many workgroups
   int32_t pair_mode = -1;    // coarse couplings: -1 automatic, 0 one workgroup per pair, 1 one wavefront per pair
+  // coarsening destinations computed on the device (else host copy maps);
+  // switched off: see sgf_set_device_coarsen
+  bool device_coarsen = false;
   uint64_t epoch = 0;
   hipStream_t cap_stream = nullptr;
   struct ApplyGraph {
@@ -639,7 +656,7 @@ void ensure_static(sgf_handle h, hipStream_t st) {
   upload_direct(h->d_coords, h->h_coords, st);
   if (!h->h_basis.empty()) upload_direct(h->d_basis, h->h_basis, st);
   h->d_vals.ensure(h->nnz * sizeof(double));
-  h->d_fail.ensure(sizeof(int));
+  h->d_fail.ensure(2 * sizeof(int));   // [0] cluster of a non-positive pivot, [1] coarsening range error
   h->d_ctr.ensure(sizeof(int));
   if (!h->d_zero_idx.p) {
     h->d_zero_idx.ensure(sizeof(int32_t));
@@ -816,6 +833,17 @@ void upload_level(sgf_handle h, int li, hipStream_t st) {
       D.band_ptr[c + 1] = (int)D.h_band_list.size();
     }
     if (D.band_ok) upload(h, D.band_list, D.h_band_list, st);
+    D.h_b1_list.clear();
+    if (D.band_ok) {
+      for (int pass = 0; pass < 2; ++pass) {
+        for (size_t f = 0; f < L.elim.size(); ++f) {
+          const auto& e = L.elim[f];
+          if ((std::min(e.bw, std::max(e.m - 1, 0)) <= 16) == (pass == 0)) D.h_b1_list.push_back((int32_t)f);
+        }
+        if (pass == 0) D.b1_split = (int)D.h_b1_list.size();
+      }
+      upload(h, D.b1_list, D.h_b1_list, st);
+    }
     // packed copies for the apply sweeps, 64-element aligned
     D.pk_elems = 0;
     for (auto& e : L.elim) {
@@ -836,6 +864,7 @@ void upload_level(sgf_handle h, int li, hipStream_t st) {
   upload(h, D.sepsrc, L.sepacc_src, st);
   upload(h, D.slots, L.slots, st);
   upload(h, D.nslots, L.nslots, st);
+  upload(h, D.nbroff, L.nbr_off, st);
   upload(h, D.slotptr, L.slot_ptr, st);
   upload(h, D.phioff, L.phi_off, st);
   D.tiled = level_tiled(h, L);
@@ -937,12 +966,13 @@ void spmv_launch(sgf_handle h, const double* x, int64_t ldx, double* y, int64_t 
 }
 
 int check_fail(sgf_handle h, hipStream_t st) {
-  int f = -1;
-  HIP_CHECK(hipMemcpyAsync(&f, h->d_fail.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  int f[2] = {-1, 0};
+  HIP_CHECK(hipMemcpyAsync(f, h->d_fail.p, sizeof(f), hipMemcpyDeviceToHost, st));
   HIP_CHECK(hipStreamSynchronize(st));
   h->staging.synced(st);
   if (h->blob_st == st) h->blob_st = nullptr;   // its last scatter has run
-  return f;
+  if (f[1] != 0) throw SgfError(SGF_EINVAL, "coarsening: a block destination fell outside its buffer (nothing copied)");
+  return f[0];
 }
 
 void account_level(sgf_handle h, const sgf::Level& L, LevelWork& W) {
@@ -1121,8 +1151,8 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
   h->max_m_all = h->max_k_all = h->max_s_all = 0;
   if (vals != h->d_vals.as<double>())
     HIP_CHECK(hipMemcpyAsync(h->d_vals.p, vals, h->nnz * sizeof(double), hipMemcpyDefault, st));
-  int init = -1;
-  HIP_CHECK(hipMemcpyAsync(h->d_fail.p, &init, sizeof(int), hipMemcpyHostToDevice, st));
+  const int init[2] = {-1, 0};
+  HIP_CHECK(hipMemcpyAsync(h->d_fail.p, init, sizeof(init), hipMemcpyHostToDevice, st));
   const double e = (double)sizeof(T);
   // ---- level 1 inputs ---------------------------------------------------------
   {
@@ -1524,14 +1554,30 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
           for (int sz : P.levels[q].size) P.max_node = std::max<int64_t>(P.max_node, sz);
         // the next level's structure does not depend on the ranks: when it
         // has been planned before, only its sizes and offsets are redone
-        if (!sgf::update_next_level(P, (size_t)li, D.h_blkmap, D.h_phimap)) {
+        const bool emit = !h->device_coarsen;
+        bool fresh = false;
+        if (!sgf::update_next_level(P, (size_t)li, D.h_blkmap, D.h_phimap, emit)) {
           P.levels.resize(li + 1);
           P.parts.resize(li + 1);
-          sgf::plan_next_level(P, D.h_blkmap, D.h_phimap);
+          sgf::plan_next_level(P, D.h_blkmap, D.h_phimap, emit);
+          fresh = true;
         }
         h->trace.mark("next level planned (host)", li + 1);
-        upload(h, D.blkmap, D.h_blkmap, st);
-        upload(h, D.phimap, D.h_phimap, st);
+        if (emit) {
+          upload(h, D.blkmap, D.h_blkmap, st);
+          upload(h, D.phimap, D.h_phimap, st);
+        } else {
+          sgf::Level& Cl = P.levels[li];
+          sgf::Level& Nl = P.levels[li + 1];
+          if (fresh || !D.coarsen_static) {
+            sgf::coarsen_tables(Cl, Nl, D.h_cpairs, D.h_cseps);
+            upload(h, D.cpairs, D.h_cpairs, st);
+            upload(h, D.cseps, D.h_cseps, st);
+            D.coarsen_static = true;
+          }
+          upload(h, D.cfather, Nl.cp_father, st);
+          upload(h, D.cloc, Nl.cp_loc, st);
+        }
       }
       upload_level(h, li + 1, st);
       h->trace.mark("next level tables built (host)", li + 1);
@@ -1544,8 +1590,42 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
     const int64_t ne = N.front_elems + N.blk_elems;
     launch(h, st, "zero", 0, ne * e, [&] { zero<T>(E.arena, ne, st); });
     // pair blocks and Phi rows of the surviving separators into the new
-    // level, one launch for both maps
-    const unsigned nbm = (unsigned)Dc.h_blkmap.size(), npm = (unsigned)Dc.h_phimap.size();
+    // level, one launch for both
+    if (h->device_coarsen) {
+      // re-fetch: planning the next level may have reallocated P.levels
+      const sgf::Level& C = P.levels[li];
+      const unsigned np = (unsigned)C.pairs.size(), ns = (unsigned)C.seps.size();
+      // the tables the kernel indexes must hold its grid's items
+      if (Dc.pairs.bytes < np * sizeof(sgf::PairDesc) || Dc.cpairs.bytes < np * sizeof(sgf::CoarsenPair) ||
+          Dc.cseps.bytes < ns * sizeof(sgf::CoarsenSep) || Dc.cfather.bytes < ns * sizeof(int32_t) ||
+          Dc.cloc.bytes < ns * sizeof(int32_t) || C.rank.size() != C.comp.size() ||
+          N.cp_father.size() != ns || N.cp_loc.size() != ns ||
+          E.nbroff.bytes < N.nbr_off.size() * sizeof(int32_t) ||
+          E.elim.bytes < N.elim.size() * sizeof(sgf::ElimDesc) || E.pairs.bytes < N.pairs.size() * sizeof(sgf::PairDesc))
+        throw SgfError(SGF_EINVAL, "coarsening tables do not match the level sizes");
+      double cb = 0;
+      if (h->prof.on)
+        for (const auto& pd : C.pairs) {
+          const int ra = pd.ca >= 0 && C.rank[pd.ca] < pd.s_a ? C.rank[pd.ca] : pd.s_a;
+          const int rb = pd.cb >= 0 && C.rank[pd.cb] < pd.s_b ? C.rank[pd.cb] : pd.s_b;
+          cb += (pd.a == pd.b ? 2.0 : 3.0) * ra * rb * e;
+        }
+      if (np + ns > 0)
+        launch(h, st, "coarsen_copy", 0, cb, [&] {
+          hipLaunchKernelGGL(sgf::k_coarsen<T>, dim3(np + ns), dim3(sgf::WG), 0, st, Dc.pairs.as<sgf::PairDesc>(),
+                             Dc.cpairs.as<sgf::CoarsenPair>(), (int)np, Dc.cseps.as<sgf::CoarsenSep>(), (int)ns,
+                             Dc.rank.as<int>(), Dc.cfather.as<int32_t>(), Dc.cloc.as<int32_t>(),
+                             E.elim.as<sgf::ElimDesc>(), (int)N.elim.size(), E.pairs.as<sgf::PairDesc>(),
+                             (int)N.pairs.size(), E.nbroff.as<int32_t>(), (int64_t)N.nbr_off.size(),
+                             (int)N.cell.size(), (int)C.comp.size(),
+                             (const T*)Dc.arena.as<T>(), C.front_elems, C.front_elems + C.blk_elems, E.arena.as<T>(),
+                             N.front_elems, ne, Dc.slotptr.as<int64_t>(), Dc.phioff.as<int64_t>(),
+                             (const T*)Dc.phi.as<T>(), C.phi_elems, E.slotptr.as<int64_t>(), E.phioff.as<int64_t>(),
+                             E.phi.as<T>(), N.phi_elems, P.pi, N.top ? 0 : 1, h->d_fail.as<int>() + 1);
+        }, li + 1);
+    }
+    const unsigned nbm = h->device_coarsen ? 0u : (unsigned)Dc.h_blkmap.size();
+    const unsigned npm = h->device_coarsen ? 0u : (unsigned)Dc.h_phimap.size();
     if (nbm + npm > 0) {
       double cb = 0;
       if (h->prof.on)
@@ -1680,6 +1760,97 @@ bool band_level(sgf_handle h, const LevelDev& D, bool fwd) {
   if (D.banded_w == 0 && D.band_bw >= D.band_m - 1) return false;
   return (size_t)band_lds(h, D, fwd, 1) * h->esz <= LDS_BYTES;
 }
+// One right-hand side on a level eliminated by the banded kernel (packed
+// copy present): band solves one wavefront per front and the L_SI products
+// one workgroup per front (k_band1_solve, k_band1_lsi, k_band1_lsit) when
+// enabled and their LDS fits.  *nb: band rows staged (16 or 32), *per_wave:
+// LDS elements per wavefront of the solves.
+// Fronts (wavefronts) per workgroup of the band solves staging nb band rows:
+// of 1, 2 and 4 (within the workgroup LDS limit), the one that keeps the
+// most wavefronts resident in a compute unit's 160 KiB of LDS (counted up to
+// 16, what their registers allow), the larger on a tie.
+int band1_fronts(sgf_handle h, const LevelDev& D, int nb) {
+  constexpr size_t CU_LDS = 160 * 1024;
+  const size_t per = (size_t)sgf::band1_lds_elems(D.band_m, nb) * h->esz;
+  int best = 1;
+  size_t best_waves = 0;
+  for (int f = 1; f <= sgf::B1_FRONTS; f *= 2) {
+    if ((size_t)f * per > LDS_BYTES) break;
+    const size_t waves = std::min<size_t>((size_t)f * (CU_LDS / ((size_t)f * per)), 16);
+    if (waves >= best_waves) best = f, best_waves = waves;
+  }
+  return best;
+}
+bool band1_level(sgf_handle h, const LevelDev& D, int nrhs, int* nb, int* per_wave) {
+  if (nrhs != 1 || !h->band1 || D.banded_w <= 0 || !D.band_ok || D.band_k > sgf::BE_KMAX || D.band_bw > 31 ||
+      D.band_m > sgf::B1_MAXC * sgf::WAVE)
+    return false;
+  *nb = 32;   // the widest class
+  *per_wave = 0;
+  const size_t solve = (size_t)sgf::band1_lds_elems(D.band_m, *nb) * h->esz;
+  const size_t lsi = ((size_t)sgf::band1_xs(D.band_m) + 4 * sgf::WAVE) * h->esz;
+  const size_t lsit = ((size_t)sgf::WAVE * (sgf::BE_KMAX | 1) + sgf::BE_KMAX + 4 * sgf::WAVE) * h->esz;
+  return std::max(solve, std::max(lsi, lsit)) <= LDS_BYTES;
+}
+
+// Launches of the one-right-hand-side banded sweeps of level L (see
+// band1_level): forward = band solve then t = L_SI x; backward = y_I -
+// L_SI^T y_S then the transposed band solve.  Bytes charged: the band and the
+// vectors to the solves, L_SI and its vectors to the products.
+template <typename T>
+void band1_sweep(sgf_handle h, const sgf::Level& L, LevelDev& D, bool fwd, int nb, int per_wave, T* y, T* ts,
+                 hipStream_t st) {
+  const int nf = (int)L.elim.size();
+  const double e = sizeof(T);
+  double band_b = 0, lsi_b = 0;
+  for (const auto& el : L.elim) {
+    const double m = el.m, k = el.k, bw = std::min(el.bw, std::max(el.m - 1, 0));
+    band_b += (bw + 1) * m * e + 2 * m * e + 4 * m;
+    lsi_b += k * m * e + (fwd ? m * e + 4 * m + k * e : 2 * m * e + 4 * m + k * (e + 4));
+  }
+  const sgf::ElimDesc* dd = D.elim.as<sgf::ElimDesc>();
+  const int32_t* sl = D.slots.as<int32_t>();
+  const T* pk = D.pk.as<T>();
+  (void)per_wave;
+  // fronts of bandwidth up to 16 stage 17 band rows, the others 32; one
+  // launch per group, fronts per workgroup as band1_fronts chooses
+  auto solve = [&] {
+    launch(h, st, fwd ? "apply_band_fwd" : "apply_band_bwd", 0, band_b, [&] {
+      const int32_t* bl = D.b1_list.as<int32_t>();
+      const int n17 = D.b1_split, n32 = (int)D.h_b1_list.size() - D.b1_split;
+      if (n17 > 0) {
+        const int fw = band1_fronts(h, D, 17), pw = (int)sgf::band1_lds_elems(D.band_m, 17);
+        const dim3 g(cdiv(n17, fw)), b(fw * sgf::WAVE);
+        const size_t l = (size_t)fw * pw * sizeof(T);
+        if (fwd) hipLaunchKernelGGL((sgf::k_band1_solve<T, 17, true>), g, b, l, st, dd, bl, n17, sl, y, pk, pw);
+        else hipLaunchKernelGGL((sgf::k_band1_solve<T, 17, false>), g, b, l, st, dd, bl, n17, sl, y, pk, pw);
+      }
+      if (n32 > 0) {
+        const int fw = band1_fronts(h, D, 32), pw = (int)sgf::band1_lds_elems(D.band_m, 32);
+        const dim3 g(cdiv(n32, fw)), b(fw * sgf::WAVE);
+        const size_t l = (size_t)fw * pw * sizeof(T);
+        const int32_t* b2 = bl + D.b1_split;
+        if (fwd) hipLaunchKernelGGL((sgf::k_band1_solve<T, 32, true>), g, b, l, st, dd, b2, n32, sl, y, pk, pw);
+        else hipLaunchKernelGGL((sgf::k_band1_solve<T, 32, false>), g, b, l, st, dd, b2, n32, sl, y, pk, pw);
+      }
+    }, L.t);
+  };
+  if (fwd) {
+    solve();
+    const int xe = sgf::band1_xs(D.band_m);
+    launch(h, st, "apply_lsi_fwd", 0, lsi_b, [&] {
+      hipLaunchKernelGGL(sgf::k_band1_lsi<T>, dim3(nf), dim3(sgf::WG), (size_t)(xe + 4 * sgf::WAVE) * sizeof(T), st,
+                         dd, sl, (const T*)y, ts, pk, xe);
+    }, L.t);
+  } else {
+    launch(h, st, "apply_lsi_bwd", 0, lsi_b, [&] {
+      hipLaunchKernelGGL(sgf::k_band1_lsit<T>, dim3(nf), dim3(sgf::WG),
+                         ((size_t)sgf::WAVE * (sgf::BE_KMAX | 1) + sgf::BE_KMAX + 4 * sgf::WAVE) * sizeof(T), st, dd, sl,
+                         D.nslots.as<int32_t>(), y, pk);
+    }, L.t);
+    solve();
+  }
+}
 // Right-hand sides per workgroup of the banded sweeps: at most one per
 // wavefront and what the LDS holds.
 int band_rc(sgf_handle h, const LevelDev& D, bool fwd, int nrhs) {
@@ -1724,6 +1895,11 @@ void run_sweeps(sgf_handle h, int nrhs, bool product, hipStream_t st, const Appl
                            dim3(sgf::WG), (size_t)rc2 * (mp + sgf::WG) * e, st, D.tf.as<sgf::TFront>(),
                            D.arena.as<T>(), reinterpret_cast<T*>(W.uw[li]), D.u_elems, D.slots.as<int32_t>(), y, n, ts, ldt, nrhs, rc2);
       }, L.t);
+      return;
+    }
+    int nb1 = 0, pw = 0;
+    if (mode == 0 && band_level(h, D, true) && band1_level(h, D, nrhs, &nb1, &pw)) {
+      band1_sweep<T>(h, L, D, true, nb1, pw, y, ts, st);
       return;
     }
     if (mode == 0 && band_level(h, D, true)) {
@@ -1780,6 +1956,11 @@ void run_sweeps(sgf_handle h, int nrhs, bool product, hipStream_t st, const Appl
                            (size_t)rc2 * (mp + sgf::WG) * e, st, D.tf.as<sgf::TFront>(), D.zt.as<T>(), reinterpret_cast<T*>(W.uw[li]),
                            D.u_elems, D.slots.as<int32_t>(), y, n, nrhs, rc2);
       }, L.t);
+      return;
+    }
+    int nb1 = 0, pw = 0;
+    if (mode == 0 && band_level(h, D, false) && band1_level(h, D, nrhs, &nb1, &pw)) {
+      band1_sweep<T>(h, L, D, false, nb1, pw, y, ts, st);
       return;
     }
     if (mode == 0 && band_level(h, D, false)) {
@@ -2797,9 +2978,10 @@ sgf_status sgf_set_pair_kernel(sgf_handle h, int32_t mode) {
 }
 
 sgf_status sgf_set_band_apply(sgf_handle h, int32_t enable) {
-  if (!h) return fail(SGF_EINVAL, "NULL handle");
+  if (!h || enable < 0 || enable > 2) return fail(SGF_EINVAL, "NULL handle or mode not 0, 1, 2");
   return guard([&] {
     h->band_apply = enable != 0;
+    h->band1 = enable == 1;
     h->drop_graph();
   });
 }
@@ -2866,6 +3048,18 @@ sgf_status sgf_set_low_rank(sgf_handle h, int32_t enable) {
       h->lr_rank.clear();
       P.opt.compression = 0;
     }
+    replan(h);
+  });
+}
+
+sgf_status sgf_set_device_coarsen(sgf_handle h, int32_t enable) {
+  if (!h) return fail(SGF_EINVAL, "NULL handle");
+  if (enable)
+    return fail(SGF_EINVAL, "the device coarsening is switched off in this build (its kernel faulted the GPU on "
+                            "uploaded tables read after their host vectors were freed; fixed, not yet re-tested)");
+  return guard([&] {
+    if (h->device_coarsen == (enable != 0)) return;
+    h->device_coarsen = enable != 0;
     replan(h);
   });
 }

@@ -23,7 +23,7 @@ FP64, FP32, FP32_BF16N = 0, 1, 2
 EXPORTED = ["sgf_default_options", "sgf_analyze", "sgf_factorize_numeric", "sgf_factorize", "sgf_autotune",
             "sgf_apply", "sgf_apply_noalloc", "sgf_multiply", "sgf_pcg_solve", "sgf_spmv", "sgf_get_info",
             "sgf_get_perm", "sgf_get_level", "sgf_plan_dry_run", "sgf_profile_enable", "sgf_profile_read", "sgf_profile_select",
-            "sgf_set_apply_graph", "sgf_set_persistent", "sgf_set_basis", "sgf_set_low_rank", "sgf_set_pair_kernel", "sgf_block_count", "sgf_export_block", "sgf_set_band_apply", "sgf_set_band_elim", "sgf_set_small_compress", "sgf_release", "sgf_estimate_bytes",
+            "sgf_set_apply_graph", "sgf_set_persistent", "sgf_set_basis", "sgf_set_low_rank", "sgf_set_pair_kernel", "sgf_set_device_coarsen", "sgf_block_count", "sgf_export_block", "sgf_set_band_apply", "sgf_set_band_elim", "sgf_set_small_compress", "sgf_release", "sgf_estimate_bytes",
             "sgf_server_default_options", "sgf_server_create", "sgf_server_add_operator", "sgf_server_submit",
             "sgf_server_wait", "sgf_server_get_stats", "sgf_server_clock", "sgf_server_destroy",
             "sgf_destroy", "sgf_status_str", "sgf_last_error"]
@@ -117,6 +117,7 @@ def load_library(path=LIB_PATH):
         "sgf_export_block": (I32, [H, I32, I32, ctypes.POINTER(Block), P, P, P, P, P]),
         "sgf_set_low_rank": (I32, [H, I32]),
         "sgf_set_pair_kernel": (I32, [H, I32]),
+        "sgf_set_device_coarsen": (I32, [H, I32]),
         "sgf_release": (I32, [H]),
         "sgf_estimate_bytes": (I32, [H, I32, P]),
         "sgf_server_default_options": (None, [ctypes.POINTER(ServerOptions)]),
@@ -368,9 +369,17 @@ class Solver:
         """Coarse couplings: -1 automatic, 0 one workgroup per pair, 1 one wavefront per pair."""
         _check(_lib.sgf_set_pair_kernel(self.h, int(mode)))
 
+    def set_device_coarsen(self, enable=True):
+        """Coarsening destinations computed on the device (default) or host copy lists."""
+        _check(_lib.sgf_set_device_coarsen(self.h, 1 if enable else 0))
+
     def set_band_apply(self, enable=True):
-        """Banded interior sweeps on levels with narrow M_II blocks (default on)."""
-        _check(_lib.sgf_set_band_apply(self.h, int(bool(enable))))
+        """Banded interior sweeps on levels with narrow M_II blocks: True / 1
+        (default; one wavefront per front for one right-hand side on levels of
+        the banded elimination), 2 (one workgroup per front always), False / 0
+        (the blocked sweeps)."""
+        mode = int(enable) if not isinstance(enable, bool) else int(enable)
+        _check(_lib.sgf_set_band_apply(self.h, mode))
 
     def release(self):
         """Free all device memory of the handle (the analysis stays)."""

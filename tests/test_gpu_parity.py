@@ -396,6 +396,12 @@ def test_band_sweeps_match_blocked_sweeps_and_oracle(kind, grid, leaf, q):
         print(f"{kind} {grid} leaf {leaf}, {nc} columns: banded vs blocked {_rel(zb, zd):.1e}")
         assert _rel(zb, zd) <= 1e-13
         assert _rel(zb, O.apply_inverse(F, V)) <= 1e-10
+        if nc == 1:
+            # one wavefront per front (default for one column on levels of the
+            # banded elimination) against one workgroup per front: the same bits
+            s.set_band_apply(2)
+            zw = _apply(s, V)
+            assert np.array_equal(zb, zw)
         if nc == 7:
             s.set_band_apply(True)
             zc = np.stack([_apply(s, V[:, j]) for j in range(nc)], axis=1)
@@ -773,3 +779,63 @@ def test_headline_paths_at_512_match_oracle(q):
         else:
             assert ea <= 1e-3 and em <= 1e-3
             assert np.linalg.norm(b - A @ xg.cpu().numpy()) / np.linalg.norm(b) < 2e-8
+
+
+@pytest.mark.skip(reason="the device coarsening is switched off: its kernel faulted the GPU (tables uploaded from "
+                         "host vectors freed before the upload batch was flushed); fixed, not re-tested on the GPU")
+@pytest.mark.parametrize("kind,grid,leaf,q", [("fourier", (100, 90), 16, 2), ("blocky", (17, 16, 15), 4, 1),
+                                              ("elast", 9, 3, 1)])
+@pytest.mark.parametrize("stop", [sgf.STOP_ROOT, sgf.STOP_PAPER])
+def test_device_coarsening_equals_host_copy_lists(kind, grid, leaf, q, stop):
+    """Coarsening destinations computed on the device from the two levels'
+    structure and the sizes after compression, against the copy list of
+    every block built on the host: the same factor bit for bit, also over
+    refactorizations with other values (levels re-planned in place)."""
+    p = _prob(kind, grid)
+    p2 = _prob(kind, grid, seed=1)
+    V = np.stack([P.random_rhs(16, p.n, j) for j in range(2)], axis=1)
+    out = {}
+    for dev in (True, False):
+        s = sgf.Solver.from_problem(p, q=q, leaf=leaf, stop_rule=stop, precision=sgf.FP32)
+        s.set_device_coarsen(dev)
+        res = []
+        for vals in (p.data, p2.data, p.data):
+            s.factorize(torch.from_numpy(vals).cuda())
+            res.append(_apply(s, V))
+        out[dev] = res
+        s.close()
+    for a, b in zip(out[True], out[False]):
+        assert np.array_equal(a, b)
+
+
+def test_full_size_headline_fp64_against_oracle():
+    """The 1024^2 workload of the benchmark (q = 2, leaf 16) in the FP64 form
+    against the oracle at full size: the same rank at every separator of
+    every level, CG iterations +-1 at 1e-8, the solution within 1e-8, and
+    the quadratics preserved (Prop. 6.1) through the device product.  (The
+    rank cut of this shape has no spectral gap, so the operator itself is
+    compared only through these; see the 512^2 tests.)"""
+    import time
+    from sgf_inputs.problems import config_problem
+    p, cfg = config_problem("varcoef2d_1024", seed=0)
+    A = p.csr()
+    t0 = time.perf_counter()
+    F = _oracle(p, cfg["q"], cfg["leaf"])
+    b = P.random_rhs(0, p.n)
+    xo, ito, _ = O.pcg(A, b, lambda r: O.apply_inverse(F, r), tol=1e-8)
+    t1 = time.perf_counter()
+    s = _gpu(p, q=cfg["q"], leaf=cfg["leaf"])
+    assert s.info()["levels"] == F.info["nlevels"]
+    for t in range(1, F.info["nlevels"]):
+        g = s.level(t)
+        post = F.info["sizes"][t - 1]
+        seps = g["type"] > 0
+        assert [post[c] for c in g["cell"][seps]] == g["rank"][seps].tolist(), f"ranks at level {t}"
+    xg = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+    it, rel = s.pcg(torch.from_numpy(b).cuda(), xg, rtol=1e-8)
+    ex = _maxrel(xg.cpu().numpy(), xo)
+    Pi = O.poly_basis(p.coords, cfg["q"], 1)[:, [0, 3, 5]]   # 1, x^2, xy
+    pres = _maxrel(_apply(s, Pi, product=True), A @ Pi)
+    print(f"1024^2 FP64: CG it {int(it[0])} (oracle {ito}), x {ex:.1e}, preservation {pres:.1e}, "
+          f"oracle {t1 - t0:.0f} s")
+    assert abs(int(it[0]) - ito) <= 1 and ex <= 1e-8 and pres <= 1e-9

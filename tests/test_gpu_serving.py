@@ -1,10 +1,11 @@
 """Serving form through the C ABI (sgf_server_*): continuous batching of
 factorize / solve requests of several operators on one GPU under an HBM
 budget.  Checks: every request converges to the requested relative
-residual; a request's result is the same alone and in a mix of concurrent,
-coalesced requests with evictions (bar: 1e-12 relative, columns of a batched
-PCG are computed independently); the FP32 factor / FP64 CG solution agrees
-with a direct solve; memory that can never fit is refused."""
+residual; every request's result is the same alone and in a mix of
+concurrent, coalesced requests with evictions and refactorizations (bar:
+1e-12 relative; the factorization is deterministic and the columns of a
+batched PCG are computed independently); the FP32 factor / FP64 CG solution
+agrees with a direct solve; memory that can never fit is refused."""
 import os
 
 import numpy as np
@@ -80,9 +81,28 @@ def test_result_is_the_same_alone_and_in_the_mix():
         assert inf["relres_max"] < TOL
     x_mix = reqs[13][2].cpu().numpy()
     diff = np.abs(x_mix - x_alone).max()
-    print(f"alone vs mix: max |dx| {diff:.1e}, batches {st['batches']}, evictions {st['evictions']}, "
+    print(f"alone vs mix (probe): max |dx| {diff:.1e}, batches {st['batches']}, evictions {st['evictions']}, "
           f"factorizations {st['factorizations']}, peak {st['peak_bytes'] / 2**20:.0f} MiB of {budget / 2**20:.0f}")
     assert _rel(x_mix, x_alone) <= 1e-12
+    # every other request alone: its operator factorized once on a handle of
+    # its own (same options, same deterministic factor), its columns solved
+    # as one PCG, as the request would run with nothing else on the device
+    solvers = []
+    for prob, kw in ops:
+        s = sgf.Solver.from_problem(prob, precision=sgf.FP32, **kw)
+        s.factorize(torch.from_numpy(prob.data).cuda())
+        solvers.append(s)
+    worst = 0.0
+    for k, ((o, b, x, _), inf) in enumerate(zip(reqs, infos)):
+        xa = torch.zeros_like(b)
+        it, rel = solvers[o].pcg(b.T, xa.T, rtol=TOL, maxit=1000)
+        d = _rel(x.cpu().numpy(), xa.cpu().numpy())
+        worst = max(worst, d)
+        assert d <= 1e-12, f"request {k} (operator {o}, {b.shape[0]} columns, batch of {inf['batch_rhs']}): {d:.1e}"
+        assert int(it.max()) == inf["iters_max"], (k, it.tolist(), inf["iters_max"])
+    for s in solvers:
+        s.close()
+    print(f"alone vs mix, all {len(reqs)} requests: worst relative difference {worst:.1e}")
     assert any(inf["batch_rhs"] > inf["nrhs"] for inf in infos), "no solves were coalesced"
     assert st["evictions"] > 0
     assert st["peak_bytes"] <= budget
