@@ -43,6 +43,33 @@ __device__ __forceinline__ double lane_bcast(double v, int src) {
   return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
 }
 
+// Global memory through a buffer resource covering [base, base + bytes): an
+// access at a byte offset past the end is dropped by the hardware (a load
+// returns 0), so a lane with nothing to load or store passes BUF_OOB instead
+// of branching around the access.  Straight-line accesses let the compiler
+// count outstanding memory operations exactly, so that waiting for a load
+// does not also wait for every store issued before it.
+constexpr int BUF_OOB = 0x7fffffff;
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_res(const void* base, int64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ int buf_off(bool valid, int64_t elem, int esz) {
+  return valid ? (int)(elem * esz) : BUF_OOB;
+}
+__device__ __forceinline__ float buf_ld(__amdgpu_buffer_rsrc_t r, int off, float) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ double buf_ld(__amdgpu_buffer_rsrc_t r, int off, double) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, int off, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, off, 0, 0);
+}
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, int off, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+}
+
 // Sum over the workgroup; every thread gets the result.  `red` holds WG/WAVE.
 template <typename T>
 __device__ __forceinline__ T block_sum(T v, T* red) {
@@ -661,6 +688,10 @@ __global__ __launch_bounds__(WAVE) void k_elim_banded(const ElimDesc* __restrict
   const ElimDesc d = D[list[blockIdx.x]];
   const int m = d.m, k = d.k, R = m + k, bw = min(min(d.bw, W - 1), max(m - 1, 0));
   T* C = arena + d.front_off;
+  constexpr int E = sizeof(T);
+  // every global access of the front and of its packed copy goes through
+  // buffer resources (idle lanes pass BUF_OOB; no packed copy: empty range)
+  const auto rc = buf_res(C, (int64_t)R * R * E);
   const int lane = threadIdx.x;
   // this lane's pairs (s, t), 1 <= t <= s <= bw, of the trailing update, and
   // the ring columns of A[j+s][j], A[j+t][j] and A[j+s][j+t]; an idle pair
@@ -684,7 +715,7 @@ __global__ __launch_bounds__(WAVE) void k_elim_banded(const ElimDesc* __restrict
 #pragma unroll
     for (int q = 0; q < NS; ++q) {
       const int idx = lane + q * WAVE, c = b * W + idx / W, r = idx % W, i = c + r;
-      v[q] = (r <= bw && c < m && i < m) ? C[i + (int64_t)c * R] : T(0);
+      v[q] = buf_ld(rc, buf_off(r <= bw && c < m && i < m, i + (int64_t)c * R, E), T());
     }
   };
   auto store_cols = [&](int b, const T* v) {
@@ -697,7 +728,8 @@ __global__ __launch_bounds__(WAVE) void k_elim_banded(const ElimDesc* __restrict
   // packed copy for the apply (pk_off >= 0): band by diagonals, then L_SI
   const bool packed = d.pk_off >= 0;
   T* PB = pk + (packed ? d.pk_off : 0);
-  T* PL = PB + band_pk_lsi(m, bw);
+  const auto rp = buf_res(PB, packed ? band_pk_elems(m, k, bw) * E : 0);
+  const int64_t lsi0 = band_pk_lsi(m, bw);   // L_SI in the packed copy
   const int pld = band_pk_ld(m);
   // the finished columns of block b (band entries L[c + r][c]) into the front
   // and into the packed band (reciprocal on the diagonal)
@@ -705,17 +737,16 @@ __global__ __launch_bounds__(WAVE) void k_elim_banded(const ElimDesc* __restrict
 #pragma unroll
     for (int q = 0; q < NS; ++q) {
       const int idx = lane + q * WAVE, c = b * W + idx / W, r = idx % W, i = c + r;
-      if (r <= bw && c < m && i < m) {
-        const T v = ring[(i & MASK) * W + (W - 1 - r)];
-        C[i + (int64_t)c * R] = v;
-        if (packed) PB[r * pld + i] = r == 0 ? dinv[i & MASK] : v;
-      }
+      const bool ok = r <= bw && c < m && i < m;
+      const T v = ring[(i & MASK) * W + (W - 1 - r)];
+      buf_st(rc, buf_off(ok, i + (int64_t)c * R, E), v);
+      buf_st(rp, buf_off(ok, (int64_t)r * pld + i, E), r == 0 ? dinv[i & MASK] : v);
     }
     // band entries above the first row of the band (i < r) are zero
-    if (packed && b == 0)
+    if (b == 0)
       for (int idx = lane; idx < (bw + 1) * bw; idx += WAVE) {
         const int r = 1 + idx / bw, i = idx % bw;
-        if (i < r && i < m) PB[r * pld + i] = T(0);
+        buf_st(rp, buf_off(i < r && i < m, (int64_t)r * pld + i, E), T(0));
       }
   };
   auto zero_block = [&](int b) {
@@ -730,17 +761,15 @@ __global__ __launch_bounds__(WAVE) void k_elim_banded(const ElimDesc* __restrict
   load_cols(0, pre);
   store_cols(0, pre);
   if (nblk > 1) load_cols(1, pre);
-  // separator row of this lane
+  // separator row of this lane: M_SI / L_SI entry (lane, j) at m + lane + j R
   const bool srow = lane < k;
-  const T* msi = C + m + lane;
-  T* lsi = C + m + lane;
   // mcur: this lane's M_SI row over the current block's columns (loaded
   // for the next block as soon as phase 2 is done with it)
   T x[W], mcur[W];
 #pragma unroll
   for (int t = 0; t < W; ++t) {
     x[t] = T(0);
-    mcur[t] = (srow && t < m) ? msi[(int64_t)t * R] : T(0);
+    mcur[t] = buf_ld(rc, buf_off(srow && t < m, m + lane + (int64_t)t * R, E), T());
   }
   constexpr int KT = BE_KMAX / 16, NT = KT * (KT + 1) / 2;
   const int kt = (k + 15) / 16;
@@ -802,15 +831,13 @@ __global__ __launch_bounds__(WAVE) void k_elim_banded(const ElimDesc* __restrict
 #pragma unroll
       for (int r = W - 1; r >= 1; --r) acc2 -= row[W - 1 - r] * x[(t - r + W) % W];
       x[t] = acc2 * dinv[j & MASK];
-      if (srow && j < m) {
-        lsi[(int64_t)j * R] = x[t];
-        if (packed) PL[lane + (int64_t)j * k] = x[t];
-      }
+      buf_st(rc, buf_off(srow && j < m, m + lane + (int64_t)j * R, E), x[t]);
+      buf_st(rp, buf_off(srow && j < m, lsi0 + lane + (int64_t)j * k, E), x[t]);
     }
 #pragma unroll
     for (int t = 0; t < W; ++t) {
       const int jn = j0 + W + t;
-      mcur[t] = (srow && jn < m) ? msi[(int64_t)jn * R] : T(0);
+      mcur[t] = buf_ld(rc, buf_off(srow && jn < m, m + lane + (int64_t)jn * R, E), T());
     }
     // ---- 3. S += L_SI(:, block) L_SI(:, block)^T ----
     __builtin_amdgcn_wave_barrier();
@@ -841,7 +868,7 @@ __global__ __launch_bounds__(WAVE) void k_elim_banded(const ElimDesc* __restrict
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = 16 * I + Mfma<T>::drow(lane, v);
-        if (row < k && col < k && row >= col) C[(m + row) + (int64_t)(m + col) * R] = -acc[q][v];
+        buf_st(rc, buf_off(row < k && col < k && row >= col, (m + row) + (int64_t)(m + col) * R, E), -acc[q][v]);
       }
     }
 }
