@@ -673,9 +673,8 @@ __device__ __forceinline__ double be_sqrt(double a) { return sqrt(a); }
 __device__ __forceinline__ double be_rcp(double a) { return 1.0 / a; }
 
 template <typename T, int W>
-__global__ __launch_bounds__(WAVE) void k_elim_banded(const ElimDesc* __restrict__ D, T* __restrict__ arena,
-                                                      int* fail, const int32_t* __restrict__ list,
-                                                      T* __restrict__ pk) {
+__device__ __forceinline__ void elim_banded_front(const ElimDesc d, T* __restrict__ arena, int* fail,
+                                                  T* __restrict__ pk) {
   static_assert(W % 4 == 0 && (W * W) % WAVE == 0, "ring width");
   constexpr int RS = be_ring_rows(W), MASK = RS - 1;
   static_assert(RS >= 3 * W, "ring rows");
@@ -685,7 +684,6 @@ __global__ __launch_bounds__(WAVE) void k_elim_banded(const ElimDesc* __restrict
   T* tile = dinv + RS;                        // 64 x (W + 1): the block of L_SI, row-major
   T* sink = tile + BE_KMAX * (W + 1);         // one slot per lane for the writes of idle lanes
   typedef typename Mfma<T>::V V;
-  const ElimDesc d = D[list[blockIdx.x]];
   const int m = d.m, k = d.k, R = m + k, bw = min(min(d.bw, W - 1), max(m - 1, 0));
   T* C = arena + d.front_off;
   constexpr int E = sizeof(T);
@@ -871,6 +869,26 @@ __global__ __launch_bounds__(WAVE) void k_elim_banded(const ElimDesc* __restrict
         buf_st(rc, buf_off(row < k && col < k && row >= col, (m + row) + (int64_t)(m + col) * R, E), -acc[q][v]);
       }
     }
+}
+
+template <typename T, int W>
+__global__ __launch_bounds__(WAVE) void k_elim_banded(const ElimDesc* __restrict__ D, T* __restrict__ arena,
+                                                      int* fail, const int32_t* __restrict__ list,
+                                                      T* __restrict__ pk) {
+  elim_banded_front<T, W>(D[list[blockIdx.x]], arena, fail, pk);
+}
+
+// Two ring widths in one launch: the nA fronts of listA (width WA: the few
+// wide fronts, e.g. the boundary blocks of a grid) first, so that they are
+// dispatched before the many fronts of listB (width WB) take the compute
+// units and end about when those do instead of trailing them; registers and
+// LDS are those of the wider class.
+template <typename T, int WA, int WB>
+__global__ __launch_bounds__(WAVE) void k_elim_banded2(const ElimDesc* __restrict__ D, T* __restrict__ arena,
+                                                       int* fail, const int32_t* __restrict__ listA, int nA,
+                                                       const int32_t* __restrict__ listB, T* __restrict__ pk) {
+  if ((int)blockIdx.x < nA) elim_banded_front<T, WA>(D[listA[blockIdx.x]], arena, fail, pk);
+  else elim_banded_front<T, WB>(D[listB[blockIdx.x - nA]], arena, fail, pk);
 }
 
 // Subtract the interiors' Schur complements from the separator pair blocks,

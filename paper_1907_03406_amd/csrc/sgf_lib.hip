@@ -1263,6 +1263,38 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
         }
       };
       D.pk.ensure((size_t)std::max<int64_t>(D.pk_elems, 1) * sizeof(T));
+      // two classes (the common case: the fronts of a grid and its few wider
+      // boundary blocks): one launch, the other class's fronts dispatched
+      // first (k_elim_banded2)
+      int other_c = -1, nclass = 0;
+      for (int c = 0; c < 4; ++c)
+        if (D.band_ptr[c + 1] > D.band_ptr[c]) {
+          ++nclass;
+          if (c != main_c) other_c = c;
+        }
+      const int wa = other_c >= 0 ? 8 * (other_c + 1) : 0, wb = 8 * (main_c + 1);
+      const bool merged = nclass == 2 && ((wa == 24 && wb == 16) || (wa == 32 && wb == 16) || (wa == 16 && wb == 8));
+      if (merged) {
+        launch(h, st, "elim_banded", lvl_elim_flops, lvl_elim_bytes, [&] {
+          const unsigned na = (unsigned)(D.band_ptr[other_c + 1] - D.band_ptr[other_c]);
+          const unsigned nb = (unsigned)(D.band_ptr[main_c + 1] - D.band_ptr[main_c]);
+          const size_t lds = (size_t)std::max(sgf::elim_banded_lds_elems(wa), sgf::elim_banded_lds_elems(wb)) * sizeof(T);
+          const int32_t* la = D.band_list.as<int32_t>() + D.band_ptr[other_c];
+          const int32_t* lb = D.band_list.as<int32_t>() + D.band_ptr[main_c];
+          const sgf::ElimDesc* dd = D.elim.as<sgf::ElimDesc>();
+          int* fl = h->d_fail.as<int>();
+          T* pkp = D.pk.as<T>();
+          if (wa == 24)
+            hipLaunchKernelGGL((sgf::k_elim_banded2<T, 24, 16>), dim3(na + nb), dim3(sgf::WAVE), lds, st, dd, arena, fl,
+                               la, (int)na, lb, pkp);
+          else if (wa == 32)
+            hipLaunchKernelGGL((sgf::k_elim_banded2<T, 32, 16>), dim3(na + nb), dim3(sgf::WAVE), lds, st, dd, arena, fl,
+                               la, (int)na, lb, pkp);
+          else
+            hipLaunchKernelGGL((sgf::k_elim_banded2<T, 16, 8>), dim3(na + nb), dim3(sgf::WAVE), lds, st, dd, arena, fl,
+                               la, (int)na, lb, pkp);
+        }, L.t);
+      } else
       launch(h, st, "elim_banded", lvl_elim_flops, lvl_elim_bytes, [&] {
         bool forked = false;
         for (int c = 0; c < 4; ++c) {
