@@ -510,10 +510,11 @@ def host_description():
 
 def cpu_baseline(key, seed, sample_grid):
     """The oracle (FP64 NumPy) on a bounded sample of the workload, scaled to
-    the full problem by the unknown count (the method is O(n)): once on one
-    thread (as the paper's sequential runs) and once with every host core
-    available to the BLAS.  `value` is the faster of the two; both are
-    reported."""
+    the full problem by the unknown count (the method is O(n)): one
+    factorization and a CG solve of each of the configuration's right-hand
+    sides (every one counts as a solve, as on the GPU), once on one thread
+    (as the paper's sequential runs) and once with every host core available
+    to the BLAS.  `value` is the faster of the two; both are reported."""
     from threadpoolctl import threadpool_limits
     from oracle import sgf_oracle as O
     from sgf_inputs.problems import config_problem, random_rhs
@@ -521,6 +522,7 @@ def cpu_baseline(key, seed, sample_grid):
     p, cfg = config_problem(key, seed=seed, grid=sample_grid)
     c = CONFIGS[key]
     n_full = int(np.prod(c["grid"])) if "grid" in c else 3 * (c["nodes"] - 1) * c["nodes"] ** 2
+    nrhs = int(c.get("nrhs", 1))
     host = host_description()
     legs = {}
     for threads in (1, host["nproc"]):
@@ -528,14 +530,20 @@ def cpu_baseline(key, seed, sample_grid):
             t0 = time.perf_counter()
             F = O.factorize(p.csr(), p.coords, p.grid, p.dpn, O.Options(q=cfg["q"], leaf=cfg["leaf"]))
             t1 = time.perf_counter()
-            x, it, rel = O.pcg(p.csr(), random_rhs(seed, p.n), lambda r: O.apply_inverse(F, r), tol=cfg["tol"])
+            its = []
+            for j in range(nrhs):
+                x, it, rel = O.pcg(p.csr(), random_rhs(seed + j, p.n), lambda r: O.apply_inverse(F, r),
+                                   tol=cfg["tol"])
+                its.append(int(it))
             t2 = time.perf_counter()
-        legs[threads] = {"value": round(n_full and 1.0 / ((t2 - t0) * n_full / p.n), 6), "cores": threads,
-                         "factorize_s": round(t1 - t0, 2), "cg_s": round(t2 - t1, 2), "it": int(it)}
+        legs[threads] = {"value": round(n_full and nrhs / ((t2 - t0) * n_full / p.n), 6), "cores": threads,
+                         "factorize_s": round(t1 - t0, 2), "cg_s": round(t2 - t1, 2), "it": max(its)}
     best = max(legs.values(), key=lambda v: v["value"])
     return {"value": best["value"], "unit": "solves/s", "cores": best["cores"], "kind": "oracle",
-            "sample": f"{key} at grid {tuple(sample_grid)} (n={p.n}), FP64 NumPy, factorize + CG "
-                      f"({legs[1]['it']} it); scaled by n_full/n_sample = {n_full / p.n:.0f}",
+            "sample": f"{key} at " + (f"{sample_grid} nodes per side" if isinstance(sample_grid, int)
+                                      else f"grid {tuple(sample_grid)}")
+                      + f" (n={p.n}), FP64 NumPy, factorize + CG of {nrhs} right-hand side(s) "
+                      f"(at most {legs[1]['it']} it); scaled by n_full/n_sample = {n_full / p.n:.0f}",
             "single_thread": legs[1], "all_cores": legs[host["nproc"]], "host": host}
 
 

@@ -393,14 +393,26 @@ sgf_status sgf_set_pair_kernel(sgf_handle h, int32_t mode);
  * Interior sweeps of the apply (Sec. 4.7) on levels whose M_II blocks have a
  * lower bandwidth of at most 64: enable = 1 (default) stages the band of L_I
  * in LDS and solves it one wavefront per right-hand side, and with a single
- * right-hand side on a level of the banded elimination gives each front one
- * wavefront (band chunk and vector in LDS, four fronts per workgroup, the
- * same operations in the same order, so the same bits); 2 keeps the banded
- * sweeps but one workgroup per front for every right-hand-side count; 0 uses
- * the blocked sweeps that also serve dense interiors.  All give the same
- * result up to rounding order.  Drops a captured apply graph.
+ * right-hand side on a level of the banded elimination gives each front's
+ * band solve one wavefront (x and the band in registers, the coefficients in
+ * an LDS tile) and its L_SI products a workgroup; these are the operations of
+ * mode 2 in the same order, so the same values (a zero product can only turn
+ * a -0 into +0).  2 keeps the banded sweeps but one workgroup per front for
+ * every right-hand-side count; 0 uses the blocked sweeps that also serve
+ * dense interiors.  All give the same result up to rounding order.  Drops a
+ * captured apply graph.
  */
 sgf_status sgf_set_band_apply(sgf_handle h, int32_t enable);
+
+/*
+ * Interior sweeps of the apply (Sec. 4.7) with one right-hand side on levels
+ * whose interiors all have at most 64 rows (the upper levels of a 2D grid):
+ * enable = 1 (default) gives each front one workgroup that issues every load
+ * of the front before waiting and solves with a single wavefront; 0 uses the
+ * blocked sweeps.  Same result up to rounding order.  Drops a captured apply
+ * graph.  SGF_EINVAL for a NULL handle or another value.
+ */
+sgf_status sgf_set_small_apply(sgf_handle h, int32_t enable);
 
 /*
  * User-supplied near-kernel basis (Secs. 1 and 3.1: the method needs a

@@ -2022,6 +2022,160 @@ __global__ __launch_bounds__(WG) void k_apply_bwd(const ElimDesc* __restrict__ D
 }
 
 // ---------------------------------------------------------------------------
+// One right-hand side on a level whose interiors have at most 64 unknowns
+// (the upper levels of a 2D grid): one workgroup per front.  Every load of
+// the front is issued before any wait (the triangle of L_I masked to its
+// band, L_SI, the slots, then y; buffer loads, out-of-range ones read 0), so
+// a front waits for memory about twice; wavefront 0 then solves with the
+// triangle in an LDS tile (row l of the tile holds the coefficients of row l's
+// update, zero elsewhere: a row step is one read at a constant offset, a
+// multiply, a readlane and a multiply-add, as in k_band1_solve), and the
+// L_SI products run on all threads from LDS.
+//   forward:  x = L_I^{-1} y_I, t = L_SI x (into the apply scratch);
+//   backward: x = L_I^{-T} (y_I - L_SI^T y_S).
+// The products are summed in the order of the sweeps that several columns
+// take on the level (order 1: the banded sweeps, four partial sums over the
+// residue classes of the summation index mod 4, added in class order; 0: the
+// blocked sweeps, forward one running sum, backward lane-strided partial
+// sums reduced by wave_sum), and the solve takes their steps, so a column
+// gets the same values whatever the column count (a zero product can only
+// turn a -0 into +0).
+// LDS: the 64 x 65 tile, 1 / L_ll, x, y_S (kmax) and L_SI (k | 1 per column).
+// ---------------------------------------------------------------------------
+__host__ __device__ inline int64_t apply1_lds_elems(int kmax) {
+  return (int64_t)WAVE * (WAVE + 1) + 2 * WAVE + kmax + (int64_t)(kmax | 1) * WAVE;
+}
+
+template <typename T, bool FWD>
+__global__ __launch_bounds__(WG) void k_apply1(const ElimDesc* __restrict__ D, const T* __restrict__ arena,
+                                               const int32_t* __restrict__ slots,
+                                               const int32_t* __restrict__ nslots, T* __restrict__ y,
+                                               T* __restrict__ tscr, int kmax, int order) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  constexpr int E = sizeof(T), TL = WAVE + 1, U = 8;
+  T* Tt = reinterpret_cast<T*>(smem_raw);   // 64 x TL
+  T* dv = Tt + WAVE * TL;                    // 1 / L_ll (0 past m)
+  T* xs = dv + WAVE;                         // x
+  T* ys = xs + WAVE;                         // y_S (backward)
+  T* Wl = ys + kmax;                         // L_SI(r, j) at Wl[r + j * KP]
+  const ElimDesc d = D[blockIdx.x];
+  const int m = d.m, k = d.k, R = m + k, bw = min(d.bw, max(m - 1, 0)), KP = k | 1;
+  const int tid = threadIdx.x, lane = tid % WAVE;
+  const auto rc = buf_res(arena + d.front_off, (int64_t)R * R * E);
+  // triangle tile: position (l, j) of the tile, lanes consecutive in the
+  // front's row index so that the loads are coalesced
+  T tv[WAVE * WAVE / WG];
+#pragma unroll
+  for (int u = 0; u < WAVE * WAVE / WG; ++u) {
+    const int p = tid + u * WG, a = p % WAVE, b = p / WAVE;
+    // forward: (l, j) = (a, b), L[l][j] for j < l; backward: (l, j) = (b, a), L[j][l] for j > l
+    const int l = FWD ? a : b, j = FWD ? b : a;
+    const int ri = FWD ? l : j, ci = FWD ? j : l;   // L[ri][ci], ri > ci
+    tv[u] = buf_ld(rc, buf_off(ri > ci && ri < m && ri - ci <= bw, ri + (int64_t)ci * R, E), T());
+  }
+  const T piv = buf_ld(rc, buf_off(tid < m, tid + (int64_t)tid * R, E), T());
+  // L_SI, issued in rounds of U per thread before their stores
+  const int nw = k * m;
+  for (int base = 0; base < nw; base += U * WG) {
+    T wv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int idx = base + u * WG + tid, r = idx % max(k, 1), j = idx / max(k, 1);
+      wv[u] = buf_ld(rc, buf_off(idx < nw, m + r + (int64_t)j * R, E), T());
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int idx = base + u * WG + tid, r = idx % max(k, 1), j = idx / max(k, 1);
+      if (idx < nw) Wl[r + j * KP] = wv[u];
+    }
+  }
+  // slots and y (indices clamped into the front; fronts without interior or
+  // separator rows read none)
+  const int32_t* sl = slots + d.slot_off;
+  const int32_t si = m > 0 ? sl[min(tid, m - 1)] : 0;
+  int32_t sn = 0;
+  if (!FWD && k > 0) sn = nslots[d.nslot_off + min(tid, k - 1)];
+  const T yi = m > 0 ? y[si] : T(0);
+  T yn = T(0);
+  if (!FWD && k > 0) yn = y[sn];
+#pragma unroll
+  for (int u = 0; u < WAVE * WAVE / WG; ++u) {
+    const int p = tid + u * WG, a = p % WAVE, b = p / WAVE;
+    const int l = FWD ? a : b, j = FWD ? b : a;
+    Tt[l * TL + j] = tv[u];
+  }
+  if (tid < WAVE) {
+    dv[tid] = tid < m ? T(1) / piv : T(0);
+    xs[tid] = tid < m ? yi : T(0);
+  }
+  if (!FWD && tid < k) ys[tid] = yn;
+  __syncthreads();
+  if (!FWD) {
+    // y_I - L_SI^T y_S, column j summed over the separator rows
+    if (order == 1) {
+      if (tid < m) {
+        T p[4] = {0, 0, 0, 0};
+        for (int r = 0; r < k; ++r) p[r & 3] += Wl[r + tid * KP] * ys[r];
+        T sum = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sum += p[q];
+        xs[tid] = xs[tid] - sum;
+      }
+    } else {
+      const int w = tid / WAVE;
+      for (int j = w; j < m; j += WG / WAVE) {
+        T a = 0;
+        for (int r = lane; r < k; r += WAVE) a += Wl[r + j * KP] * ys[r];
+        const T sum = wave_sum(a);
+        if (lane == 0) xs[j] = xs[j] - sum;
+      }
+    }
+    __syncthreads();
+  }
+  if (tid < WAVE) {
+    T x = xs[lane];
+    const T dinv = dv[lane];
+    const int m8 = (m + 7) & ~7;
+    if (FWD) {
+      for (int j0 = 0; j0 < m8; j0 += 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const T xj = lane_bcast(x * dinv, j0 + u);
+          x = x - Tt[lane * TL + j0 + u] * xj;
+        }
+      }
+    } else {
+      for (int j0 = m8 - 8; j0 >= 0; j0 -= 8) {
+#pragma unroll
+        for (int u = 7; u >= 0; --u) {
+          const T xj = lane_bcast(x * dinv, j0 + u);
+          x = x - Tt[lane * TL + j0 + u] * xj;
+        }
+      }
+    }
+    x = x * dinv;
+    xs[lane] = x;
+    if (lane < m) y[si] = x;
+  }
+  if (FWD) {
+    __syncthreads();
+    // t = L_SI x: thread r sums row r over the interior columns
+    for (int r = tid; r < k; r += WG) {
+      T sum = 0;
+      if (order == 1) {
+        T p[4] = {0, 0, 0, 0};
+        for (int j = 0; j < m; ++j) p[j & 3] += Wl[r + j * KP] * xs[j];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sum += p[q];
+      } else {
+        for (int j = 0; j < m; ++j) sum += Wl[r + j * KP] * xs[j];
+      }
+      tscr[d.t_off + r] = sum;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Banded apply sweeps, for levels whose interiors have a narrow M_II (lower
 // bandwidth bw <= BAND_MAX, e.g. the finest interiors of a grid numbered
 // naturally).  Each workgroup stages the band of L_I once in LDS by

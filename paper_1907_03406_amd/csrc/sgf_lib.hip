@@ -397,6 +397,7 @@ struct sgf_handle_s {
   bool capturing = false;   // a graph is being recorded: launch directly
   bool band_apply = true;
   bool band1 = true;         // one wavefront per banded front for one right-hand side
+  bool apply1 = true;        // one right-hand side on levels of fronts with at most 64 rows: k_apply1
   bool band_elim = true;
   bool small_comp = true;
   int32_t persist_cap = 0;   // > 0: per-level work lists persistent on at most this many workgroups
@@ -1883,6 +1884,21 @@ void band1_sweep(sgf_handle h, const sgf::Level& L, LevelDev& D, bool fwd, int n
     solve();
   }
 }
+// One right-hand side on a level whose interiors all have at most 64 rows
+// (k_apply1), when its LDS (the triangle tile and L_SI) fits and the level
+// was not eliminated by the banded kernel (whose packed copy, read by the
+// banded sweeps, holds the pivots' hardware reciprocals); *kmax: the level's
+// largest k.
+bool apply1_level(sgf_handle h, const sgf::Level& L, const LevelDev& D, int nrhs, int* kmax) {
+  if (nrhs != 1 || !h->apply1 || L.elim.empty() || D.banded_w > 0) return false;
+  int mm = 0, kk = 0;
+  for (const auto& e : L.elim) {
+    mm = std::max(mm, e.m);
+    kk = std::max(kk, e.k);
+  }
+  *kmax = std::max(kk, 1);
+  return mm <= sgf::WAVE && (size_t)sgf::apply1_lds_elems(*kmax) * h->esz <= LDS_BYTES;
+}
 // Right-hand sides per workgroup of the banded sweeps: at most one per
 // wavefront and what the LDS holds.
 int band_rc(sgf_handle h, const LevelDev& D, bool fwd, int nrhs) {
@@ -1932,6 +1948,16 @@ void run_sweeps(sgf_handle h, int nrhs, bool product, hipStream_t st, const Appl
     int nb1 = 0, pw = 0;
     if (mode == 0 && band_level(h, D, true) && band1_level(h, D, nrhs, &nb1, &pw)) {
       band1_sweep<T>(h, L, D, true, nb1, pw, y, ts, st);
+      return;
+    }
+    int k1 = 0;
+    if (mode == 0 && apply1_level(h, L, D, nrhs, &k1)) {
+      const int order = band_level(h, D, true) ? 1 : 0;   // the summation order of the multi-column sweeps
+      launch(h, st, "apply_small_fwd", 0, D.work.fwd_bytes + D.work.fwd_vec, [&] {
+        hipLaunchKernelGGL((sgf::k_apply1<T, true>), dim3((unsigned)L.elim.size()), dim3(sgf::WG),
+                           (size_t)sgf::apply1_lds_elems(k1) * sizeof(T), st, D.elim.as<sgf::ElimDesc>(),
+                           (const T*)D.arena.as<T>(), D.slots.as<int32_t>(), D.nslots.as<int32_t>(), y, ts, k1, order);
+      }, L.t);
       return;
     }
     if (mode == 0 && band_level(h, D, true)) {
@@ -1993,6 +2019,16 @@ void run_sweeps(sgf_handle h, int nrhs, bool product, hipStream_t st, const Appl
     int nb1 = 0, pw = 0;
     if (mode == 0 && band_level(h, D, false) && band1_level(h, D, nrhs, &nb1, &pw)) {
       band1_sweep<T>(h, L, D, false, nb1, pw, y, ts, st);
+      return;
+    }
+    int k1 = 0;
+    if (mode == 0 && apply1_level(h, L, D, nrhs, &k1)) {
+      const int order = band_level(h, D, false) ? 1 : 0;   // the summation order of the multi-column sweeps
+      launch(h, st, "apply_small_bwd", 0, D.work.bwd_bytes + D.work.bwd_vec, [&] {
+        hipLaunchKernelGGL((sgf::k_apply1<T, false>), dim3((unsigned)L.elim.size()), dim3(sgf::WG),
+                           (size_t)sgf::apply1_lds_elems(k1) * sizeof(T), st, D.elim.as<sgf::ElimDesc>(),
+                           (const T*)D.arena.as<T>(), D.slots.as<int32_t>(), D.nslots.as<int32_t>(), y, (T*)nullptr, k1, order);
+      }, L.t);
       return;
     }
     if (mode == 0 && band_level(h, D, false)) {
@@ -3014,6 +3050,14 @@ sgf_status sgf_set_band_apply(sgf_handle h, int32_t enable) {
   return guard([&] {
     h->band_apply = enable != 0;
     h->band1 = enable == 1;
+    h->drop_graph();
+  });
+}
+
+sgf_status sgf_set_small_apply(sgf_handle h, int32_t enable) {
+  if (!h || enable < 0 || enable > 1) return fail(SGF_EINVAL, "NULL handle or enable not 0 or 1");
+  return guard([&] {
+    h->apply1 = enable != 0;
     h->drop_graph();
   });
 }

@@ -23,7 +23,7 @@ FP64, FP32, FP32_BF16N = 0, 1, 2
 EXPORTED = ["sgf_default_options", "sgf_analyze", "sgf_factorize_numeric", "sgf_factorize", "sgf_autotune",
             "sgf_apply", "sgf_apply_noalloc", "sgf_multiply", "sgf_pcg_solve", "sgf_spmv", "sgf_get_info",
             "sgf_get_perm", "sgf_get_level", "sgf_plan_dry_run", "sgf_profile_enable", "sgf_profile_read", "sgf_profile_select",
-            "sgf_set_apply_graph", "sgf_set_persistent", "sgf_set_basis", "sgf_set_low_rank", "sgf_set_pair_kernel", "sgf_set_device_coarsen", "sgf_block_count", "sgf_export_block", "sgf_set_band_apply", "sgf_set_band_elim", "sgf_set_small_compress", "sgf_release", "sgf_estimate_bytes",
+            "sgf_set_apply_graph", "sgf_set_persistent", "sgf_set_basis", "sgf_set_low_rank", "sgf_set_pair_kernel", "sgf_set_device_coarsen", "sgf_block_count", "sgf_export_block", "sgf_set_band_apply", "sgf_set_small_apply", "sgf_set_band_elim", "sgf_set_small_compress", "sgf_release", "sgf_estimate_bytes",
             "sgf_server_default_options", "sgf_server_create", "sgf_server_add_operator", "sgf_server_submit",
             "sgf_server_wait", "sgf_server_get_stats", "sgf_server_clock", "sgf_server_destroy",
             "sgf_destroy", "sgf_status_str", "sgf_last_error"]
@@ -110,6 +110,7 @@ def load_library(path=LIB_PATH):
         "sgf_set_apply_graph": (I32, [H, I32]),
         "sgf_set_persistent": (I32, [H, I32]),
         "sgf_set_band_apply": (I32, [H, I32]),
+        "sgf_set_small_apply": (I32, [H, I32]),
         "sgf_set_band_elim": (I32, [H, I32]),
         "sgf_set_small_compress": (I32, [H, I32]),
         "sgf_set_basis": (I32, [H, I32, P]),
@@ -380,6 +381,12 @@ class Solver:
         (the blocked sweeps)."""
         mode = int(enable) if not isinstance(enable, bool) else int(enable)
         _check(_lib.sgf_set_band_apply(self.h, mode))
+
+    def set_small_apply(self, enable=True):
+        """One right-hand side on levels of fronts with at most 64 rows: one
+        workgroup per front, all loads issued first (default), or the blocked
+        sweeps."""
+        _check(_lib.sgf_set_small_apply(self.h, 1 if enable else 0))
 
     def release(self):
         """Free all device memory of the handle (the analysis stays)."""

@@ -408,6 +408,43 @@ def test_band_sweeps_match_blocked_sweeps_and_oracle(kind, grid, leaf, q):
             assert np.array_equal(zb, zc)
 
 
+@pytest.mark.parametrize("kind,grid,leaf,q", [("const", (70, 66), 4, 1), ("blocky", (96, 80), 8, 1),
+                                              ("fourier", (61, 58), 8, 2), ("fourier", (200, 190), 16, 2)])
+def test_small_front_sweeps_match_blocked_sweeps_and_oracle(kind, grid, leaf, q):
+    """One right-hand side on levels whose interiors have at most 64 rows
+    (FP32 factor and sweeps, the form whose L_SI fits the kernel's LDS):
+    one workgroup per front with every load issued before waiting and the
+    solve on one wavefront (k_apply1, both directions) against the sweeps
+    several columns take (the same steps and summation orders, so the same
+    values) and the FP64 oracle."""
+    p = _prob(kind, grid)
+    F = _oracle(p, q, leaf)
+    s = _gpu(p, q=q, leaf=leaf, precision=sgf.FP32)
+    s.set_apply_graph(False)
+    v = P.random_rhs(13, p.n)
+    s.set_small_apply(True)
+    s.profile(True)
+    za = _apply(s, v)
+    used = s.profile_read()
+    s.profile(False)
+    assert used.get("apply_small_fwd", {}).get("launches", 0) >= 1
+    assert used.get("apply_small_bwd", {}).get("launches", 0) >= 1
+    s.set_small_apply(False)
+    s.profile(True)
+    zb = _apply(s, v)
+    assert "apply_small_fwd" not in s.profile_read()
+    s.profile(False)
+    ref = O.apply_inverse(F, v)
+    print(f"{kind} {grid} leaf {leaf}: small vs blocked {_maxrel(za, zb):.1e}, vs oracle {_rel(za, ref):.1e} "
+          f"(blocked vs oracle {_rel(zb, ref):.1e})")
+    assert np.array_equal(za, zb)
+    assert _rel(za, ref) <= 1e-4
+    # the graph replays the same kernels
+    s.set_small_apply(True)
+    s.set_apply_graph(True)
+    assert np.array_equal(_apply(s, v), za)
+
+
 def test_pcg_iteration_graphs_for_several_rhs_counts():
     """The captured PCG iteration is kept per right-hand-side count and is
     independent of the caller's solution buffer: solves with 1, 2, 1 and 3
