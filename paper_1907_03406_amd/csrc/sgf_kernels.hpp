@@ -1697,12 +1697,52 @@ __global__ __launch_bounds__(WG) void k_sepacc(const SepAcc* __restrict__ A, con
   }
 }
 
+// k_sepacc_comp for a separator of at most SB <= 64 rows: wavefront 0 loads
+// row i of T_S (registers, zero past s, so its products past s add zeros),
+// the contributions and y before its first wait; the arithmetic is that of
+// the general path (dynamic LDS: at least 64 entries of ys).
+template <typename T, int SB>
+__device__ __forceinline__ void sepacc_comp_small(const SepAcc& a, int ci, const int64_t* __restrict__ src,
+                                                  const int32_t* __restrict__ sl, const T* __restrict__ tscr,
+                                                  T* __restrict__ y, const CompApply* __restrict__ CA,
+                                                  const T* __restrict__ tb, T* ys) {
+  constexpr int E = sizeof(T);
+  const int s = a.s, i = threadIdx.x, ic = min(i, s - 1);
+  const bool on = i < s, w0 = threadIdx.x < WAVE;
+  int32_t si = 0;
+  T xr[SB], v = T(0);
+  if (w0) {
+    si = sl[ic];
+    if (ci >= 0) {
+      const auto rx = buf_res(tb + CA[ci].t_off, (int64_t)s * s * E);
+#pragma unroll
+      for (int j = 0; j < SB; ++j) xr[j] = buf_ld(rx, buf_off(on && j < s, i + (int64_t)j * s, E), T());
+    }
+    T acc = 0;
+    for (int c = 0; c < a.c_cnt; ++c) acc += tscr[src[a.c_ptr + c] + ic];
+    v = y[si] + T(-1) * acc;
+  }
+  if (ci < 0) {   // the same for the whole workgroup
+    if (w0 && on) y[si] = v;
+    return;
+  }
+  if (w0) ys[i] = on ? v : T(0);
+  __syncthreads();
+  if (w0 && on) {
+    T o = 0;
+#pragma unroll
+    for (int j = 0; j < SB; ++j) o += xr[j] * ys[j];
+    y[si] = o;
+  }
+}
+
 // The forward separator step of one level with one right-hand side, one
 // workgroup per accumulated separator: y_S <- y_S - sum_I t_I[S part] (as
 // k_sepacc with sign -1), then, when S was compressed (cap[b] >= 0),
 // y_S <- T_S y_S (as k_comp_apply_t, mode 0) on the values just formed.
-// Same arithmetic as the two launches it replaces.  Dynamic LDS: 2 s_max.
-template <typename T>
+// Same arithmetic as the two launches it replaces.  Dynamic LDS: 2 s_max
+// (at least 2 x 64 with SB > 0).
+template <typename T, int SB>
 __global__ __launch_bounds__(WG) void k_sepacc_comp(const SepAcc* __restrict__ A, const int64_t* __restrict__ src,
                                                     const int32_t* __restrict__ slots, const T* __restrict__ tscr,
                                                     T* __restrict__ y, const int32_t* __restrict__ cap,
@@ -1713,6 +1753,12 @@ __global__ __launch_bounds__(WG) void k_sepacc_comp(const SepAcc* __restrict__ A
   T* ys = reinterpret_cast<T*>(smem_raw);
   T* out = ys + a.s;
   const int32_t* sl = slots + a.slot_off;
+  // SB > 0: the level's separators have at most SB rows (one register row
+  // per thread); 0: the general path only
+  if (SB > 0 && a.s <= SB) {
+    sepacc_comp_small<T, (SB > 0 ? SB : 16)>(a, ci, src, sl, tscr, y, CA, tb, ys);
+    return;
+  }
   for (int i = threadIdx.x; i < a.s; i += WG) {
     T acc = 0;
     for (int c = 0; c < a.c_cnt; ++c) acc += tscr[src[a.c_ptr + c] + i];
@@ -2754,8 +2800,69 @@ __global__ __launch_bounds__(WG) void k_comp_explicit(const CompApply* __restric
   wg_apply_qt(nbuf + a.v_off, s, tau_all + a.tau_off, s, a.r, X, s, nc);
 }
 
+// k_comp_apply_t for a separator of at most SB <= 64 rows: the entries of
+// T_B each thread multiplies are loaded into registers before the first wait
+// (mode 0: row i, by the threads of rows; mode 1: one entry of each of the
+// wavefront's columns per lane), zero past s so that their products add
+// zeros; the arithmetic is that of the general path.
+template <typename T, int SB>
+__device__ __forceinline__ void comp_apply_small(const T* __restrict__ X, const int32_t* __restrict__ sl,
+                                                 T* __restrict__ y, int64_t ldy, int mode, int s, int c0, int nc,
+                                                 T* ys, T* out) {
+  constexpr int E = sizeof(T), NW = WG / WAVE, NQ = (SB + NW - 1) / NW;
+  const auto rx = buf_res(X, (int64_t)s * s * E);
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  T xr[SB];
+  if (mode == 0) {
+    const int i = threadIdx.x;
+    if (i < SB)
+#pragma unroll
+      for (int j = 0; j < SB; ++j) xr[j] = buf_ld(rx, buf_off(i < s && j < s, i + (int64_t)j * s, E), T());
+  } else if (lane < SB) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int j = w + q * NW;
+      xr[q] = buf_ld(rx, buf_off(lane < s && j < s, lane + (int64_t)j * s, E), T());
+    }
+  }
+  for (int idx = threadIdx.x; idx < s * nc; idx += WG) {
+    const int i = idx % s, c = idx / s;
+    ys[i + c * s] = y[(int64_t)(c0 + c) * ldy + sl[i]];
+  }
+  __syncthreads();
+  if (mode == 0) {
+    const int i = threadIdx.x;
+    if (i < s)
+      for (int c = 0; c < nc; ++c) {
+        T acc = 0;
+#pragma unroll
+        for (int j = 0; j < SB; ++j) acc += xr[j] * (j < s ? ys[j + c * s] : T(0));
+        out[i + c * s] = acc;
+      }
+  } else {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int j = w + q * NW;
+      if (j < s)
+        for (int c = 0; c < nc; ++c) {
+          T acc = 0;
+          if (lane < s) acc += xr[q] * ys[lane + c * s];
+          const T t = wave_sum(acc);
+          if (lane == 0) out[j + c * s] = t;
+        }
+    }
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < s * nc; idx += WG) {
+    const int i = idx % s, c = idx / s;
+    y[(int64_t)(c0 + c) * ldy + sl[i]] = out[i + c * s];
+  }
+}
+
 // mode 0: y_B <- T_B y_B; mode 1: y_B <- T_B^T y_B; rc columns per workgroup.
-template <typename T>
+// SB > 0: the level's separators have at most SB rows (comp_apply_small);
+// 0: the general path only.
+template <typename T, int SB>
 __global__ __launch_bounds__(WG) void k_comp_apply_t(const CompApply* __restrict__ A, const T* __restrict__ tb,
                                                      const int32_t* __restrict__ slots, T* __restrict__ y,
                                                      int64_t ldy, int mode, int nrhs, int rc) {
@@ -2767,6 +2874,10 @@ __global__ __launch_bounds__(WG) void k_comp_apply_t(const CompApply* __restrict
   T* out = ys + s * rc;
   const T* X = tb + a.t_off;
   const int32_t* sl = slots + a.slot_off;
+  if (SB > 0 && s <= SB) {
+    comp_apply_small<T, (SB > 0 ? SB : 16)>(X, sl, y, ldy, mode, s, c0, nc, ys, out);
+    return;
+  }
   for (int idx = threadIdx.x; idx < s * nc; idx += WG) {
     const int i = idx % s, c = idx / s;
     ys[i + c * s] = y[(int64_t)(c0 + c) * ldy + sl[i]];

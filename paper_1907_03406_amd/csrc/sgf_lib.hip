@@ -1884,6 +1884,11 @@ void band1_sweep(sgf_handle h, const sgf::Level& L, LevelDev& D, bool fwd, int n
     solve();
   }
 }
+// Register rows of the small-separator paths of k_sepacc_comp and
+// k_comp_apply_t for a level whose separators have at most s rows (0: the
+// general path).
+int small_rows(int s) { return s <= 16 ? 16 : s <= 32 ? 32 : s <= 64 ? 64 : 0; }
+
 // One right-hand side on a level whose interiors all have at most 64 rows
 // (k_apply1), when its LDS (the triangle tile and L_SI) fits and the level
 // was not eliminated by the banded kernel (whose packed copy, read by the
@@ -2093,12 +2098,20 @@ void run_sweeps(sgf_handle h, int nrhs, bool product, hipStream_t st, const Appl
     if (!L.capply.empty() && (ms > 256 || h->tiled_rows == 0)) return false;
     int sa = 0;
     for (const auto& a : L.sepacc) sa = std::max(sa, a.s);
-    const size_t lds = 2 * (size_t)sa * sizeof(T);
+    const size_t lds = 2 * (size_t)std::max(sa, sgf::WAVE) * sizeof(T);   // the small-separator path stages 64 entries
     if (lds > LDS_BYTES) return false;
+    // register rows of the small-separator path sized for the level's largest separator
+    const int sb = small_rows(sa);
     launch(h, st, "apply_sepacc", 0, D.work.acc_vec + D.work.capply_bytes + D.work.capply_vec, [&] {
-      hipLaunchKernelGGL(sgf::k_sepacc_comp<T>, dim3((unsigned)L.sepacc.size()), dim3(sgf::WG), lds, st,
-                         D.sepacc.as<sgf::SepAcc>(), D.sepsrc.as<int64_t>(), D.slots.as<int32_t>(), ts, y,
-                         D.capacc.as<int32_t>(), D.capply.as<sgf::CompApply>(), D.tb.as<T>());
+      auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3((unsigned)L.sepacc.size()), dim3(sgf::WG), lds, st,
+                           D.sepacc.as<sgf::SepAcc>(), D.sepsrc.as<int64_t>(), D.slots.as<int32_t>(), ts, y,
+                           D.capacc.as<int32_t>(), D.capply.as<sgf::CompApply>(), D.tb.as<T>());
+      };
+      if (sb == 16) go(sgf::k_sepacc_comp<T, 16>);
+      else if (sb == 32) go(sgf::k_sepacc_comp<T, 32>);
+      else if (sb == 64) go(sgf::k_sepacc_comp<T, 64>);
+      else go(sgf::k_sepacc_comp<T, 0>);
     }, L.t);
     return true;
   };
@@ -2127,10 +2140,17 @@ void run_sweeps(sgf_handle h, int nrhs, bool product, hipStream_t st, const Appl
     }
     if (mode <= 1) {
       const int rc = rc_for(0, 2 * (size_t)ms * sizeof(T), nrhs);
+      const int sb = small_rows(ms);
       launch(h, st, "apply_comp", 0, cdiv(nrhs, rc) * D.work.capply_bytes + nrhs * D.work.capply_vec, [&] {
-        hipLaunchKernelGGL(sgf::k_comp_apply_t<T>, dim3((unsigned)L.capply.size(), cdiv(nrhs, rc)), dim3(sgf::WG),
-                           2 * (size_t)rc * ms * sizeof(T), st, D.capply.as<sgf::CompApply>(), D.tb.as<T>(),
-                           D.slots.as<int32_t>(), y, n, mode, nrhs, rc);
+        auto go = [&](auto kern) {
+          hipLaunchKernelGGL(kern, dim3((unsigned)L.capply.size(), cdiv(nrhs, rc)), dim3(sgf::WG),
+                             2 * (size_t)rc * ms * sizeof(T), st, D.capply.as<sgf::CompApply>(), D.tb.as<T>(),
+                             D.slots.as<int32_t>(), y, n, mode, nrhs, rc);
+        };
+        if (sb == 16) go(sgf::k_comp_apply_t<T, 16>);
+        else if (sb == 32) go(sgf::k_comp_apply_t<T, 32>);
+        else if (sb == 64) go(sgf::k_comp_apply_t<T, 64>);
+        else go(sgf::k_comp_apply_t<T, 0>);
       }, L.t);
       return;
     }
