@@ -611,7 +611,7 @@ def main():
     ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "CAL_FETCH_DIR", "CAL_WRITE_DIR"),
                     help="HBM bytes per launch of --pmc-class from rocprofv3 FETCH_SIZE / WRITE_SIZE runs")
     ap.add_argument("--pmc-class", default="", help="with --summarize-pmc: launch class (e.g. apply_lsi_bwd@L1)")
-    ap.add_argument("--pmc-kernels", default="", help="with --summarize-pmc: comma-separated HIP kernel name prefixes")
+    ap.add_argument("--pmc-kernels", default="", help="with --summarize-pmc: HIP kernel name prefixes separated by ';' (template arguments hold commas)")
     ap.add_argument("--command", default="", help="with --summarize-trace: the command that made the trace")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device-to-device copy of 1 GiB (reference for HBM byte counters)")
@@ -629,7 +629,7 @@ def main():
         from contextlib import redirect_stdout
         buf = io.StringIO()
         with redirect_stdout(buf):
-            total = summarize_pmc(*a.summarize_pmc, a.pmc_kernels.split(","), a.label, a.command.split(" ;; "),
+            total = summarize_pmc(*a.summarize_pmc, a.pmc_kernels.split(";"), a.label, a.command.split(" ;; "),
                                   None)
         text = buf.getvalue()
         print(text, end="")
@@ -638,7 +638,7 @@ def main():
         open(os.path.join(ROOT, summary), "w").write(text)
         path = os.path.join(ROOT, "profiles", "traffic.json")
         t = json.load(open(path)) if os.path.exists(path) else {}
-        t[a.pmc_class] = {"bytes_per_launch": int(total), "hip_kernels": a.pmc_kernels.split(","),
+        t[a.pmc_class] = {"bytes_per_launch": int(total), "hip_kernels": a.pmc_kernels.split(";"),
                           "source_hash": source_hash(), "summary": summary}
         json.dump(t, open(path, "w"), indent=1)
         return
