@@ -1257,14 +1257,24 @@ __global__ __launch_bounds__(WAVE) void k_compress_small(const CompDesc* __restr
       for (int k = 0; k < NB; ++k)
         if (k < s && k <= lane) Fl[lane + k * ldf] = a[k];
     __builtin_amdgcn_wave_barrier();
-    // ---- neighbour rows: row <- row L_B^{-T}, one row per lane ----
-    for (int i = s + lane; i < R; i += WAVE)
-      for (int j = 0; j < s; ++j) {
-        T acc = Fl[i + j * ldf];
-#pragma unroll 8
-        for (int p = 0; p < j; ++p) acc -= Fl[i + p * ldf] * Fl[j + p * ldf];
-        Fl[i + j * ldf] = acc * invd[j];
+    // ---- neighbour rows: row <- row L_B^{-T}, one row per lane, the row's
+    // solved entries in registers (the coefficients of L_B are LDS
+    // broadcasts) ----
+    for (int i = s + lane; i < R; i += WAVE) {
+      T x[NB];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        if (j < s) {
+          T acc = Fl[i + j * ldf];
+#pragma unroll
+          for (int p = 0; p < j; ++p) acc -= x[p] * Fl[j + p * ldf];
+          x[j] = acc * invd[j];
+        }
       }
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+        if (j < s) Fl[i + j * ldf] = x[j];
+    }
     __builtin_amdgcn_wave_barrier();
     // the factored front to cf (all of it when the staging skipped cf, so
     // that cf holds what the gather and this write-back would have left)
@@ -1388,6 +1398,9 @@ __global__ __launch_bounds__(WAVE) void k_compress_small(const CompDesc* __restr
       const int j = lane + h * WAVE;
       if (j > k && j < c) {
         T* y = Nl + j * ldn;
+        // the updated column's trailing norm is summed in the update pass
+        // (the same values in the same order as a pass of its own)
+        T nn = 0;
         if (tk != T(0)) {
           T acc = y[k];
 #pragma unroll 8
@@ -1395,11 +1408,15 @@ __global__ __launch_bounds__(WAVE) void k_compress_small(const CompDesc* __restr
           acc *= tk;
           y[k] -= acc;
 #pragma unroll 8
-          for (int i = k + 1; i < s; ++i) y[i] -= acc * v[i];
-        }
-        T nn = 0;
+          for (int i = k + 1; i < s; ++i) {
+            const T yi = y[i] - acc * v[i];
+            y[i] = yi;
+            nn += yi * yi;
+          }
+        } else {
 #pragma unroll 8
-        for (int i = k + 1; i < s; ++i) nn += y[i] * y[i];
+          for (int i = k + 1; i < s; ++i) nn += y[i] * y[i];
+        }
         nr[h] = sqrt(nn);
       }
     }
@@ -1436,27 +1453,42 @@ __global__ __launch_bounds__(WAVE) void k_compress_small(const CompDesc* __restr
     // ---- T_B = Q^T L_B^{-1} into its slot, for the apply and the coarse
     // couplings: lane j solves column j of L_B^{-1} (rows above j are zero),
     // then the r reflectors act on every column ----
+    // (the column in registers: rows above j are zero, and the products
+    // with them that the unrolled solve adds are zeros; the coefficients of
+    // L_B and of the reflectors are LDS broadcasts)
     const int ldx = s | 1;
     for (int j = lane; j < s; j += WAVE) {
+      T x[NB];
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        if (i < s) {
+          T acc = i == j ? T(1) : T(0);
+#pragma unroll
+          for (int p = 0; p < i; ++p) acc -= Fl[i + p * ldf] * x[p];
+          x[i] = i < j ? T(0) : acc / Fl[i + i * ldf];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < NB; ++k) {
+        if (k < r) {
+          const T tk = taul[k];
+          if (tk != T(0)) {
+            T acc = x[k];
+#pragma unroll
+            for (int i = k + 1; i < NB; ++i)
+              if (i < s) acc += Nl[i + k * ldn] * x[i];
+            acc *= tk;
+            x[k] -= acc;
+#pragma unroll
+            for (int i = k + 1; i < NB; ++i)
+              if (i < s) x[i] -= acc * Nl[i + k * ldn];
+          }
+        }
+      }
       T* xc = Xl + j * ldx;
-      for (int i = 0; i < j; ++i) xc[i] = T(0);
-      for (int i = j; i < s; ++i) {
-        T acc = i == j ? T(1) : T(0);
-#pragma unroll 8
-        for (int p = j; p < i; ++p) acc -= Fl[i + p * ldf] * xc[p];
-        xc[i] = acc / Fl[i + i * ldf];
-      }
-      for (int k = 0; k < r; ++k) {
-        const T tk = taul[k];
-        if (tk == T(0)) continue;
-        T acc = xc[k];
-#pragma unroll 8
-        for (int i = k + 1; i < s; ++i) acc += Nl[i + k * ldn] * xc[i];
-        acc *= tk;
-        xc[k] -= acc;
-#pragma unroll 8
-        for (int i = k + 1; i < s; ++i) xc[i] -= acc * Nl[i + k * ldn];
-      }
+#pragma unroll
+      for (int i = 0; i < NB; ++i)
+        if (i < s) xc[i] = x[i];
     }
     __builtin_amdgcn_wave_barrier();
     T* X = tb + d.tb_off;
