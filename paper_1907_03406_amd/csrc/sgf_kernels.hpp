@@ -1176,6 +1176,28 @@ __device__ __forceinline__ T wave_max(T v) {
   return v;
 }
 
+// Copy of n contiguous device elements into LDS by one wavefront with U loads
+// in flight per lane (buffer loads over exactly the n elements, so the lanes
+// past the end load nothing): element e goes to dst[dl(e)].
+template <typename T, int U = 8, typename DL>
+__device__ __forceinline__ void wave_stage(T* dst, const T* src, int n, DL dl) {
+  const __amdgpu_buffer_rsrc_t r = buf_res(src, (int64_t)n * (int64_t)sizeof(T));
+  const int lane = threadIdx.x % WAVE;
+  for (int b = 0; b < n; b += U * WAVE) {
+    T v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = b + u * WAVE + lane;
+      v[u] = buf_ld(r, buf_off(e < n, e, (int)sizeof(T)), T());
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = b + u * WAVE + lane;
+      if (e < n) dst[dl(e)] = v[u];
+    }
+  }
+}
+
 template <typename T, int NB>
 __global__ __launch_bounds__(WAVE) void k_compress_small(const CompDesc* __restrict__ D,
                                                          const CompNbr* __restrict__ NBR, T* __restrict__ cf,
@@ -1200,32 +1222,28 @@ __global__ __launch_bounds__(WAVE) void k_compress_small(const CompDesc* __restr
   const int lane = threadIdx.x;
   T* F = cf + d.cf_off;
   // ---- stage the front and the Phi blocks ----
+  // (every block is read in its own storage order, batches of loads in flight)
   if (blocks) {
     // the front straight from the pair blocks (what k_comp_gather puts in cf):
     // M_BB, then M_XB of every neighbour X (stored as M_BX when trans)
-    const T* dg = blocks + d.blk_diag;
-    for (int idx = lane; idx < s * s; idx += WAVE) Fl[idx % s + (idx / s) * ldf] = dg[idx];
+    wave_stage(Fl, blocks + d.blk_diag, s * s, [&](int e) { return e % s + (e / s) * ldf; });
     for (int q = 0; q < d.nnb; ++q) {
       const CompNbr x = NBR[d.nb_ptr + q];
-      const T* b = blocks + x.blk_off;
-      for (int idx = lane; idx < x.s_x * s; idx += WAVE) {
-        const int j = idx % x.s_x, i = idx / x.s_x;   // row j of X, column i of B
-        Fl[(x.row + j) + i * ldf] = x.trans ? b[i + (int64_t)j * s] : b[j + (int64_t)i * x.s_x];
-      }
+      const int sx = x.s_x, xr = x.row;
+      if (x.trans)   // M_BX: element e is row e % s of B, column e / s of X
+        wave_stage(Fl, blocks + x.blk_off, sx * s, [&](int e) { return xr + e / s + (e % s) * ldf; });
+      else           // M_XB: element e is row e % s_X of X, column e / s_X of B
+        wave_stage(Fl, blocks + x.blk_off, sx * s, [&](int e) { return xr + e % sx + (e / sx) * ldf; });
     }
   } else {
-    for (int idx = lane; idx < R * s; idx += WAVE) {
-      const int i = idx % R, j = idx / R;
-      Fl[i + j * ldf] = F[idx];
-    }
+    wave_stage(Fl, F, R * s, [&](int e) { return e % R + (e / R) * ldf; });
   }
-  const T* PhB = phi + d.phi_off;
-  for (int idx = lane; idx < s * pi; idx += WAVE) Ph[idx % s + (idx / s) * R] = PhB[idx];
+  wave_stage(Ph, phi + d.phi_off, s * pi, [&](int e) { return e % s + (e / s) * R; });
   for (int q = 0; q < d.nnb; ++q) {
     const CompNbr x = NBR[d.nb_ptr + q];
     if (x.full) continue;
-    const T* PhX = phi + x.phi_off;
-    for (int idx = lane; idx < x.s_x * pi; idx += WAVE) Ph[x.row + idx % x.s_x + (idx / x.s_x) * R] = PhX[idx];
+    const int sx = x.s_x, xr = x.row;
+    wave_stage(Ph, phi + x.phi_off, sx * pi, [&](int e) { return xr + e % sx + (e / sx) * R; });
   }
   __builtin_amdgcn_wave_barrier();
   if (!prefactored) {
@@ -1425,48 +1443,36 @@ __global__ __launch_bounds__(WAVE) void k_compress_small(const CompDesc* __restr
     ++r;
   }
   __builtin_amdgcn_wave_barrier();
-  // ---- reflectors, tau, (Q^T L^T Phi_B) and the rank out ----
+  // ---- reflectors, tau and the rank out; then Q^T acts, one column per
+  // lane, on the columns of L_B^{-1} (T_B = Q^T L_B^{-1}, for the apply and
+  // the coarse couplings) and on those of L^T Phi_B ((Q^T L^T Phi_B)[:r],
+  // Eq. 3.4); the column in registers, the coefficients of L_B and of the
+  // reflectors LDS broadcasts ----
   T* Ng = nbuf + d.n_off;
   for (int idx = lane; idx < s * r; idx += WAVE) Ng[idx] = Nl[idx % s + (idx / s) * ldn];
   T* tau = tau_all + d.tau_off;
   for (int k = lane; k < r; k += WAVE) tau[k] = taul[k];
-  if (r < s)
-    for (int k = 0; k < r; ++k) {
-      const T tk = taul[k];
-      if (tk == T(0)) continue;
-      for (int p = lane; p < pi; p += WAVE) {
-        T* x = Lt + p * s;
-        T acc = x[k];
-#pragma unroll 8
-        for (int i = k + 1; i < s; ++i) acc += Nl[i + k * ldn] * x[i];
-        acc *= tk;
-        x[k] -= acc;
-#pragma unroll 8
-        for (int i = k + 1; i < s; ++i) x[i] -= acc * Nl[i + k * ldn];
-      }
-      __builtin_amdgcn_wave_barrier();
-    }
-  __builtin_amdgcn_wave_barrier();
-  T* LtP = ltphi + d.ltphi_off;
-  for (int idx = lane; idx < s * pi; idx += WAVE) LtP[idx] = Lt[idx];
   if (r < s) {
-    // ---- T_B = Q^T L_B^{-1} into its slot, for the apply and the coarse
-    // couplings: lane j solves column j of L_B^{-1} (rows above j are zero),
-    // then the r reflectors act on every column ----
-    // (the column in registers: rows above j are zero, and the products
-    // with them that the unrolled solve adds are zeros; the coefficients of
-    // L_B and of the reflectors are LDS broadcasts)
     const int ldx = s | 1;
-    for (int j = lane; j < s; j += WAVE) {
+    for (int j = lane; j < s + pi; j += WAVE) {
       T x[NB];
+      if (j < s) {
+        // column j of L_B^{-1}: rows above j are zero, and the products with
+        // them that the unrolled solve adds are zeros
 #pragma unroll
-      for (int i = 0; i < NB; ++i) {
-        if (i < s) {
-          T acc = i == j ? T(1) : T(0);
+        for (int i = 0; i < NB; ++i) {
+          if (i < s) {
+            T acc = i == j ? T(1) : T(0);
 #pragma unroll
-          for (int p = 0; p < i; ++p) acc -= Fl[i + p * ldf] * x[p];
-          x[i] = i < j ? T(0) : acc / Fl[i + i * ldf];
+            for (int p = 0; p < i; ++p) acc -= Fl[i + p * ldf] * x[p];
+            x[i] = i < j ? T(0) : acc / Fl[i + i * ldf];
+          }
         }
+      } else {
+        const T* lc = Lt + (j - s) * s;
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+          if (i < s) x[i] = lc[i];
       }
 #pragma unroll
       for (int k = 0; k < NB; ++k) {
@@ -1485,7 +1491,7 @@ __global__ __launch_bounds__(WAVE) void k_compress_small(const CompDesc* __restr
           }
         }
       }
-      T* xc = Xl + j * ldx;
+      T* xc = j < s ? Xl + j * ldx : Lt + (j - s) * s;
 #pragma unroll
       for (int i = 0; i < NB; ++i)
         if (i < s) xc[i] = x[i];
@@ -1494,6 +1500,8 @@ __global__ __launch_bounds__(WAVE) void k_compress_small(const CompDesc* __restr
     T* X = tb + d.tb_off;
     for (int idx = lane; idx < s * s; idx += WAVE) X[idx] = Xl[idx % s + (idx / s) * ldx];
   }
+  T* LtP = ltphi + d.ltphi_off;
+  for (int idx = lane; idx < s * pi; idx += WAVE) LtP[idx] = Lt[idx];
   if (lane == 0) rank[ci] = r;
 }
 
