@@ -326,6 +326,73 @@ __global__ __launch_bounds__(WG) void k_zero_band(const ElimDesc* __restrict__ D
   }
 }
 
+// Level-1 inputs of one banded front per workgroup: the band and the M_SI
+// rows (all that the banded elimination reads, as k_zero_band clears them)
+// set to zero with every lane busy, then, after the barrier, the front's own
+// matrix entries (FP64, rounded to T) from its list, whose writes meet the
+// fresh lines in L2 instead of scattering partial lines to HBM.
+template <typename T>
+__global__ __launch_bounds__(WG) void k_fill_band(const ElimDesc* __restrict__ D, const int32_t* __restrict__ list,
+                                                  const int64_t* __restrict__ ptr, const int32_t* __restrict__ off,
+                                                  const int64_t* __restrict__ src, const double* __restrict__ vals,
+                                                  T* __restrict__ arena) {
+  const ElimDesc d = D[list[blockIdx.x]];
+  const int m = d.m, k = d.k, bw = min(d.bw, max(m - 1, 0));
+  const int64_t R = (int64_t)m + k;
+  T* C = arena + d.front_off;
+  // the first PF entries of each thread are fetched before the clearing, so
+  // that their loads overlap its stores (clamped indices: no branches)
+  constexpr int PF = 8;
+  const int64_t q0 = ptr[blockIdx.x], q1 = ptr[blockIdx.x + 1];
+  int po[PF];
+  T pv[PF];
+  if (q1 > q0) {
+    int64_t ps[PF];
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+      const int64_t q = min(q0 + threadIdx.x + (int64_t)u * WG, q1 - 1);
+      po[u] = off[q];
+      ps[u] = src[q];
+    }
+#pragma unroll
+    for (int u = 0; u < PF; ++u) pv[u] = (T)vals[ps[u]];
+  }
+  const int w2 = bw + 1 + k;   // per column: rows c .. c + bw of the band, then the k rows of M_SI
+  const int n = m * w2;
+  for (int e = threadIdx.x; e < n; e += WG) {
+    const int c = e / w2, r = e - c * w2;
+    const int row = r <= bw ? c + r : m + (r - bw - 1);
+    if (r > bw || row < m) C[row + (int64_t)c * R] = T(0);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < PF; ++u)
+    if (q0 + threadIdx.x + (int64_t)u * WG < q1) C[po[u]] = pv[u];
+  for (int64_t q = q0 + threadIdx.x + (int64_t)PF * WG; q < q1; q += WG) C[off[q]] = (T)vals[src[q]];
+}
+
+// The level-1 entries outside the banded fronts (pair blocks).
+// (four entries per thread, every load issued before the stores)
+template <typename T>
+__global__ void k_fill_rest(const double* __restrict__ vals, const int64_t* __restrict__ dst,
+                            const int64_t* __restrict__ src, int64_t n, T* __restrict__ arena) {
+  constexpr int U = 4;
+  const int64_t e0 = (int64_t)blockIdx.x * blockDim.x * U + threadIdx.x;
+  int64_t dd[U], ss[U];
+  T vv[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int64_t e = min(e0 + (int64_t)u * blockDim.x, n - 1);
+    dd[u] = dst[e];
+    ss[u] = src[e];
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) vv[u] = (T)vals[ss[u]];
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+    if (e0 + (int64_t)u * blockDim.x < n) arena[dd[u]] = vv[u];
+}
+
 // Phi_B = Pi(B, :) for every level-1 cluster (Sec. 3.1; block diagonal per
 // component for dofs_per_node > 1, Eq. 7.4).  Coordinates normalised
 // globally to [-1, 1]: xh = (x - lo) * sc - 1 with sc = 2 / (hi - lo).

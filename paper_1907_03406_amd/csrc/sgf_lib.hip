@@ -3,8 +3,11 @@
 // product form (Sec. 2.1) and preconditioned CG (Sec. 7).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <condition_variable>
+#include <exception>
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
@@ -14,6 +17,7 @@
 #include <mutex>
 #include <stdexcept>
 #include <string>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -232,6 +236,15 @@ struct LevelDev {
   int band_ptr[5] = {0, 0, 0, 0, 0};
   bool band_ok = false;
   DevBuf band_list;
+  // level-1 inputs of the banded fronts (k_fill_band): the matrix entries
+  // that land in the front at band_list position p are fill_ptr[p] ..
+  // fill_ptr[p + 1], each with its offset in the front and its CSR index
+  // (CSR order); the other entries (pair blocks) for k_fill_rest
+  bool fill_ok = false;
+  std::vector<int64_t> h_fill_ptr, h_fill_src, h_rest_dst, h_rest_src;
+  std::vector<int32_t> h_fill_off;
+  DevBuf fill_ptr, fill_off, fill_src, rest_dst, rest_src;
+  int64_t fill_rest_n = 0;
   // the one-right-hand-side band solves: fronts of bandwidth <= 16 (the
   // first b1_split), then the others
   std::vector<int32_t> h_b1_list;
@@ -349,6 +362,79 @@ inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b);
 
 }  // namespace
 
+// One host thread beside the caller's, for host planning that can run while
+// the caller's thread queues device work: started on first use, one job at a
+// time; wait() returns once the job has ended and rethrows what it threw.
+struct HostWorker {
+  std::thread th;
+  std::mutex m;
+  std::condition_variable cv;
+  std::function<void()> job;
+  bool has_job = false, done = true, quit = false;
+  std::exception_ptr err;
+  void start(std::function<void()> f) {
+    if (!th.joinable()) th = std::thread([this] { loop(); });
+    std::lock_guard<std::mutex> g(m);
+    job = std::move(f);
+    has_job = true;
+    done = false;
+    err = nullptr;
+    cv.notify_all();
+  }
+  void wait() {
+    std::unique_lock<std::mutex> g(m);
+    cv.wait(g, [this] { return done; });
+    if (err) {
+      std::exception_ptr e = err;
+      err = nullptr;
+      std::rethrow_exception(e);
+    }
+  }
+  void loop() {
+    std::unique_lock<std::mutex> g(m);
+    for (;;) {
+      cv.wait(g, [this] { return has_job || quit; });
+      if (quit) return;
+      std::function<void()> f = std::move(job);
+      has_job = false;
+      g.unlock();
+      std::exception_ptr e;
+      try {
+        f();
+      } catch (...) {
+        e = std::current_exception();
+      }
+      g.lock();
+      err = e;
+      done = true;
+      cv.notify_all();
+    }
+  }
+  ~HostWorker() {
+    {
+      std::lock_guard<std::mutex> g(m);
+      quit = true;
+      cv.notify_all();
+    }
+    if (th.joinable()) th.join();
+  }
+};
+
+// Waits for the worker's job on the way out of a scope that started it,
+// unless the scope waited itself (active cleared); the job's error is
+// dropped there, since another error is already on its way out.
+struct WorkerJoin {
+  HostWorker* w;
+  bool active;
+  ~WorkerJoin() {
+    if (!active) return;
+    try {
+      w->wait();
+    } catch (...) {
+    }
+  }
+};
+
 struct sgf_handle_s {
   sgf::Plan plan;
   std::vector<int64_t> h_rowptr;
@@ -444,6 +530,9 @@ struct sgf_handle_s {
   UploadBatch* batch = nullptr;   // open upload batch, if any
   DevBuf blob;                    // device copy of the last batch's blob
   hipStream_t blob_st = nullptr;  // stream of the last scatter kernel
+  // re-plans the next level while the level loop queues the compressed-
+  // separator work (joined before anything reads the next level)
+  HostWorker worker;
   ~sgf_handle_s() {
     drop_graph();
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
@@ -790,6 +879,77 @@ void build_tiled(sgf_handle h, const sgf::Level& L, LevelDev& D, hipStream_t st)
 }
 
 // Upload the descriptor tables of level index li and size its buffers.
+// Level-1 matrix entries split by destination: those in a banded front go
+// to that front's list (k_fill_band writes them after clearing the front's
+// band), the rest (pair blocks) to one list for k_fill_rest.  Only when every
+// front is banded and fits the 32-bit in-front offsets.
+void build_fill_lists(sgf_handle h, const sgf::Level& L, LevelDev& D, hipStream_t st) {
+  D.fill_ok = false;
+  if (!D.band_ok || D.h_band_list.empty()) return;
+  const std::vector<int64_t>& dst = h->plan.csr_dst;
+  const int nb = (int)D.h_band_list.size();
+  std::vector<std::pair<int64_t, int>> fo(nb);   // (front offset, band position)
+  for (int p = 0; p < nb; ++p) {
+    const auto& e = L.elim[D.h_band_list[p]];
+    const int64_t R = (int64_t)e.m + e.k;
+    if (R * R >= ((int64_t)1 << 31)) return;
+    fo[p] = {e.front_off, p};
+  }
+  std::sort(fo.begin(), fo.end());
+  // band position of an arena offset inside a banded front, else -1
+  auto front_of = [&](int64_t d) {
+    auto it = std::upper_bound(fo.begin(), fo.end(), std::make_pair(d, std::numeric_limits<int>::max()));
+    if (it == fo.begin()) return -1;
+    --it;
+    const auto& e = L.elim[D.h_band_list[it->second]];
+    const int64_t R = (int64_t)e.m + e.k;
+    return d < it->first + R * R ? it->second : -1;
+  };
+  const int64_t nnz = (int64_t)dst.size();
+  std::vector<int32_t> pos(nnz, -1);
+  D.h_fill_ptr.assign(nb + 1, 0);
+  D.h_rest_dst.clear();
+  D.h_rest_src.clear();
+  for (int64_t e = 0; e < nnz; ++e) {
+    if (dst[e] < 0) continue;
+    pos[e] = front_of(dst[e]);
+    if (pos[e] >= 0) {
+      ++D.h_fill_ptr[pos[e] + 1];
+    } else {
+      D.h_rest_dst.push_back(dst[e]);
+      D.h_rest_src.push_back(e);
+    }
+  }
+  for (int p = 0; p < nb; ++p) D.h_fill_ptr[p + 1] += D.h_fill_ptr[p];
+  D.h_fill_off.assign(D.h_fill_ptr[nb], 0);
+  D.h_fill_src.assign(D.h_fill_ptr[nb], 0);
+  std::vector<int64_t> cur(D.h_fill_ptr.begin(), D.h_fill_ptr.end() - 1);
+  for (int64_t e = 0; e < nnz; ++e) {
+    if (pos[e] < 0) continue;
+    const int64_t q = cur[pos[e]]++;
+    D.h_fill_off[q] = (int32_t)(dst[e] - L.elim[D.h_band_list[pos[e]]].front_off);
+    D.h_fill_src[q] = e;
+  }
+  // keep the device lists non-empty (valid pointers for empty launches)
+  if (D.h_rest_dst.empty()) {
+    D.h_rest_dst.push_back(0);
+    D.h_rest_src.push_back(0);
+    D.fill_rest_n = 0;
+  } else {
+    D.fill_rest_n = (int64_t)D.h_rest_dst.size();
+  }
+  if (D.h_fill_off.empty()) {
+    D.h_fill_off.push_back(0);
+    D.h_fill_src.push_back(0);
+  }
+  upload(h, D.fill_ptr, D.h_fill_ptr, st);
+  upload(h, D.fill_off, D.h_fill_off, st);
+  upload(h, D.fill_src, D.h_fill_src, st);
+  upload(h, D.rest_dst, D.h_rest_dst, st);
+  upload(h, D.rest_src, D.h_rest_src, st);
+  D.fill_ok = true;
+}
+
 void upload_level(sgf_handle h, int li, hipStream_t st) {
   sgf::Level& L = h->plan.levels[li];
   if ((int)h->lev.size() <= li) h->lev.resize(li + 1);
@@ -834,6 +994,7 @@ void upload_level(sgf_handle h, int li, hipStream_t st) {
       D.band_ptr[c + 1] = (int)D.h_band_list.size();
     }
     if (D.band_ok) upload(h, D.band_list, D.h_band_list, st);
+    if (li == 0) build_fill_lists(h, L, D, st);
     D.h_b1_list.clear();
     if (D.band_ok) {
       for (int pass = 0; pass < 2; ++pass) {
@@ -1165,7 +1326,8 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
     sgf::Level& L = P.levels[0];
     LevelDev& D = h->lev[0];
     const int64_t ne = L.front_elems + L.blk_elems;
-    if (D.front_clean && banded_w(h, L, D) > 0) {
+    const bool band_inputs = D.front_clean && banded_w(h, L, D) > 0;
+    if (band_inputs) {
       double zb = (double)L.blk_elems * e;
       for (const auto& d : L.elim) zb += (double)d.m * (std::min(d.bw, std::max(d.m - 1, 0)) + 1 + d.k) * e;
       launch(h, st, "zero", 0, zb, [&] {
@@ -1174,18 +1336,33 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
           hipLaunchKernelGGL(sgf::k_zero<T>, dim3(g), dim3(sgf::WG), 0, st, D.arena.as<T>() + L.front_elems,
                              L.blk_elems);
         }
-        hipLaunchKernelGGL(sgf::k_zero_band<T>, dim3((unsigned)D.h_band_list.size()), dim3(sgf::WG), 0, st,
-                           D.elim.as<sgf::ElimDesc>(), D.band_list.as<int32_t>(), D.arena.as<T>());
+        if (D.fill_ok)   // the band cleared and the front's entries written in one pass
+          hipLaunchKernelGGL(sgf::k_fill_band<T>, dim3((unsigned)D.h_band_list.size()), dim3(sgf::WG), 0, st,
+                             D.elim.as<sgf::ElimDesc>(), D.band_list.as<int32_t>(), D.fill_ptr.as<int64_t>(),
+                             D.fill_off.as<int32_t>(), D.fill_src.as<int64_t>(), h->d_vals.as<double>(),
+                             D.arena.as<T>());
+        else
+          hipLaunchKernelGGL(sgf::k_zero_band<T>, dim3((unsigned)D.h_band_list.size()), dim3(sgf::WG), 0, st,
+                             D.elim.as<sgf::ElimDesc>(), D.band_list.as<int32_t>(), D.arena.as<T>());
       }, L.t);
     } else {
       launch(h, st, "zero", 0, ne * e, [&] { zero<T>(D.arena, ne, st); }, L.t);
     }
     // set again once the banded elimination of this factorization is queued
     D.front_clean = false;
-    launch(h, st, "fill_csr", 0, h->nnz * (16.0 + e), [&] {
-      hipLaunchKernelGGL(sgf::k_fill_csr<T>, dim3(cdiv(h->nnz, sgf::WG)), dim3(sgf::WG), 0, st,
-                         h->d_vals.as<double>(), h->d_csrdst.as<int64_t>(), h->nnz, D.arena.as<T>());
-    });
+    if (band_inputs && D.fill_ok) {
+      if (D.fill_rest_n > 0)
+        launch(h, st, "fill_csr", 0, D.fill_rest_n * (24.0 + e), [&] {
+          hipLaunchKernelGGL(sgf::k_fill_rest<T>, dim3(cdiv(D.fill_rest_n, 4 * sgf::WG)), dim3(sgf::WG), 0, st,
+                             h->d_vals.as<double>(), D.rest_dst.as<int64_t>(), D.rest_src.as<int64_t>(),
+                             D.fill_rest_n, D.arena.as<T>());
+        });
+    } else {
+      launch(h, st, "fill_csr", 0, h->nnz * (16.0 + e), [&] {
+        hipLaunchKernelGGL(sgf::k_fill_csr<T>, dim3(cdiv(h->nnz, sgf::WG)), dim3(sgf::WG), 0, st,
+                           h->d_vals.as<double>(), h->d_csrdst.as<int64_t>(), h->nnz, D.arena.as<T>());
+      });
+    }
     sgf::PhiInit pin{};
     for (int a = 0; a < 3; ++a) {
       pin.lo[a] = P.cmin[a];
@@ -1468,128 +1645,149 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
       std::fprintf(stderr, "[sgf] level %d: reuse_next %d, ranks %zu, planned %zu, differing %d\n", L.t,
                    (int)reuse_next, L.rank.size(), L.planned_rank.size(), ndiff);
     }
-    // compressed separators of this level, for the apply
-    L.capply.clear();
-    std::vector<int64_t> cap_tb;   // T_B slot of each compressed separator (small compressions)
-    for (size_t c = 0; c < L.comp.size(); ++c) {
-      const auto& d = L.comp[c];
-      if (L.rank[c] < d.s) {
-        cap_tb.push_back(d.tb_off);
-        sgf::CompApply a{};
-        a.cf_off = d.cf_off;
-        a.v_off = d.n_off;
-        a.tau_off = d.tau_off;
-        a.slot_off = d.slot_off;
-        a.s = d.s;
-        a.ld = d.s + d.K;
-        a.r = L.rank[c];
-        L.capply.push_back(a);
-        h->max_s_all = std::max(h->max_s_all, d.s);
-        ++h->compressed;
-      }
+    const bool emit = !h->device_coarsen;
+    if (!same_ranks) {
+      for (size_t q = li + 1; q < h->lev.size(); ++q) h->lev[q].uploaded = false;
+      P.max_node = 0;
+      for (int q = 0; q <= li; ++q)
+        for (int sz : P.levels[q].size) P.max_node = std::max<int64_t>(P.max_node, sz);
     }
-    {
-      // T_B slots: the planned ones when the small compression formed T_B,
-      // else packed over the compressed separators for k_comp_explicit
-      int64_t toff = 0, voff = 0;
-      for (size_t q = 0; q < L.capply.size(); ++q) {
-        auto& a = L.capply[q];
-        a.t_off = D.comp_small ? cap_tb[q] : toff;
-        toff += (int64_t)a.s * a.s;
-        a.v_off2 = (int32_t)voff;
-        voff += a.s;
-      }
-      D.tb.ensure(std::max<int64_t>(D.comp_small ? L.tb_elems : toff, 1) * sizeof(T));
-      D.c_elems = voff;
-    }
-    {
-      BatchScope bs(h);
-      if (!same_ranks || D.capply_small != D.comp_small) {
-        D.capply_small = D.comp_small;
-        upload(h, D.capply, L.capply, st);
-        L.t_of_comp.assign(L.comp.size(), -1);
-        std::vector<int32_t> q_of_comp(L.comp.size(), -1);
-        for (size_t c = 0, q = 0; c < L.comp.size(); ++c)
-          if (L.rank[c] < L.comp[c].s) {
-            q_of_comp[c] = (int32_t)q;
-            L.t_of_comp[c] = L.capply[q++].t_off;
-          }
-        upload(h, D.tofcomp, L.t_of_comp, st);
-        // compressed separator of every accumulation entry (for the fused
-        // forward separator step)
-        L.cap_of_acc.assign(L.sepacc.size(), -1);
-        size_t covered = 0;
-        for (size_t a = 0; a < L.sepacc.size(); ++a) {
-          const int c = L.comp_of[L.seps[L.sacc_p[a]]];
-          if (c >= 0 && q_of_comp[c] >= 0) {
-            L.cap_of_acc[a] = q_of_comp[c];
-            ++covered;
-          }
+    auto comp_work = [&] {
+      // compressed separators of this level, for the apply
+      L.capply.clear();
+      std::vector<int64_t> cap_tb;   // T_B slot of each compressed separator (small compressions)
+      for (size_t c = 0; c < L.comp.size(); ++c) {
+        const auto& d = L.comp[c];
+        if (L.rank[c] < d.s) {
+          cap_tb.push_back(d.tb_off);
+          sgf::CompApply a{};
+          a.cf_off = d.cf_off;
+          a.v_off = d.n_off;
+          a.tau_off = d.tau_off;
+          a.slot_off = d.slot_off;
+          a.s = d.s;
+          a.ld = d.s + d.K;
+          a.r = L.rank[c];
+          L.capply.push_back(a);
+          h->max_s_all = std::max(h->max_s_all, d.s);
+          ++h->compressed;
         }
-        L.acc_covers_capply = covered == L.capply.size();
-        upload(h, D.capacc, L.cap_of_acc, st);
       }
-      // pairs that touch a compressed separator (their coarse couplings)
-      if (!L.capply.empty() && !same_ranks) {
-        L.active_pairs.clear();
-        for (size_t p = 0; p < L.pairs.size(); ++p) {
+      {
+        // T_B slots: the planned ones when the small compression formed T_B,
+        // else packed over the compressed separators for k_comp_explicit
+        int64_t toff = 0, voff = 0;
+        for (size_t q = 0; q < L.capply.size(); ++q) {
+          auto& a = L.capply[q];
+          a.t_off = D.comp_small ? cap_tb[q] : toff;
+          toff += (int64_t)a.s * a.s;
+          a.v_off2 = (int32_t)voff;
+          voff += a.s;
+        }
+        D.tb.ensure(std::max<int64_t>(D.comp_small ? L.tb_elems : toff, 1) * sizeof(T));
+        D.c_elems = voff;
+      }
+      {
+        BatchScope bs(h);
+        if (!same_ranks || D.capply_small != D.comp_small) {
+          D.capply_small = D.comp_small;
+          upload(h, D.capply, L.capply, st);
+          L.t_of_comp.assign(L.comp.size(), -1);
+          std::vector<int32_t> q_of_comp(L.comp.size(), -1);
+          for (size_t c = 0, q = 0; c < L.comp.size(); ++c)
+            if (L.rank[c] < L.comp[c].s) {
+              q_of_comp[c] = (int32_t)q;
+              L.t_of_comp[c] = L.capply[q++].t_off;
+            }
+          upload(h, D.tofcomp, L.t_of_comp, st);
+          // compressed separator of every accumulation entry (for the fused
+          // forward separator step)
+          L.cap_of_acc.assign(L.sepacc.size(), -1);
+          size_t covered = 0;
+          for (size_t a = 0; a < L.sepacc.size(); ++a) {
+            const int c = L.comp_of[L.seps[L.sacc_p[a]]];
+            if (c >= 0 && q_of_comp[c] >= 0) {
+              L.cap_of_acc[a] = q_of_comp[c];
+              ++covered;
+            }
+          }
+          L.acc_covers_capply = covered == L.capply.size();
+          upload(h, D.capacc, L.cap_of_acc, st);
+        }
+        // pairs that touch a compressed separator (their coarse couplings)
+        if (!L.capply.empty() && !same_ranks) {
+          L.active_pairs.clear();
+          for (size_t p = 0; p < L.pairs.size(); ++p) {
+            const auto& pd = L.pairs[p];
+            const bool ca = pd.ca >= 0 && L.rank[pd.ca] < pd.s_a, cb = pd.cb >= 0 && L.rank[pd.cb] < pd.s_b;
+            if (ca || cb) L.active_pairs.push_back((int32_t)p);
+          }
+          upload(h, D.active, L.active_pairs, st);
+        }
+        bs.flush(st);
+      }
+      if (!L.capply.empty() && !D.comp_small) {
+        double fl = 0;
+        for (auto& a : L.capply) fl += (double)a.s * a.s * a.s / 3.0 + 4.0 * a.s * a.s * a.r;
+        launch(h, st, "comp_explicit", fl, 0, [&] {
+          int smax = 0;
+          for (auto& a : L.capply) smax = std::max(smax, a.s);
+          hipLaunchKernelGGL(sgf::k_comp_explicit<T>, dim3((unsigned)L.capply.size(), cdiv(smax, sgf::CEB)),
+                             dim3(sgf::WG), 0, st,
+                             D.capply.as<sgf::CompApply>(), D.cf.as<T>(), D.nbuf.as<T>(), D.tau.as<T>(), D.tb.as<T>());
+        }, L.t);
+      }
+      // coarse couplings, only for the pairs that touch a compressed separator
+      if (!L.capply.empty()) {
+        // many small pairs: one wavefront each, T_a M_ab in LDS
+        int64_t gmax = 1;
+        for (int32_t p : L.active_pairs) {
           const auto& pd = L.pairs[p];
-          const bool ca = pd.ca >= 0 && L.rank[pd.ca] < pd.s_a, cb = pd.cb >= 0 && L.rank[pd.cb] < pd.s_b;
-          if (ca || cb) L.active_pairs.push_back((int32_t)p);
+          const int ra = pd.ca >= 0 && L.rank[pd.ca] < pd.s_a ? L.rank[pd.ca] : pd.s_a;
+          gmax = std::max<int64_t>(gmax, (int64_t)ra * pd.s_b);
         }
-        upload(h, D.active, L.active_pairs, st);
+        const size_t plds = (size_t)sgf::PPB * gmax * sizeof(T);
+        const unsigned nact = (unsigned)L.active_pairs.size();
+        launch(h, st, "pair", 0, 0, [&] {
+          const bool wave = plds <= LDS_BYTES && (h->pair_mode == 1 || (h->pair_mode < 0 && nact >= 4096));
+          if (wave)
+            hipLaunchKernelGGL(sgf::k_pair_w<T>, dim3(cdiv(nact, sgf::PPB)), dim3(sgf::PPB * sgf::WAVE), plds, st,
+                               D.pairs.as<sgf::PairDesc>(), D.active.as<int32_t>(), (int)nact, D.rank.as<int>(),
+                               D.tofcomp.as<int64_t>(), D.tb.as<T>(), blocks, (int)gmax);
+          else
+            hipLaunchKernelGGL(sgf::k_pair<T>, dim3(nact), dim3(sgf::WG), 0, st, D.pairs.as<sgf::PairDesc>(),
+                               D.active.as<int32_t>(), D.rank.as<int>(), D.tofcomp.as<int64_t>(), D.tb.as<T>(), blocks,
+                               D.scratch.as<T>());
+        }, L.t);
       }
-      bs.flush(st);
+      acct = li;   // counted while the GPU runs the next level
+    };
+    // The next level's in-place re-plan for these ranks (its structure does
+    // not depend on them: only sizes and offsets are redone) reads only this
+    // level's ranks and the plan; the compressed-separator work above reads
+    // and writes other fields of this level and queues device work.  So the
+    // worker thread queues that work while this thread, whose caches hold
+    // the plan, re-plans; the worker is joined before anything else (or on
+    // the way out of an error).
+    bool planned = false;
+    if (!same_ranks && sgf::can_update_next_level(P, (size_t)li)) {
+      h->worker.start(comp_work);
+      WorkerJoin wjoin{&h->worker, true};
+      planned = sgf::update_next_level(P, (size_t)li, D.h_blkmap, D.h_phimap, emit);
+      wjoin.active = false;
+      h->worker.wait();
+    } else {
+      comp_work();
+      if (!same_ranks) planned = sgf::update_next_level(P, (size_t)li, D.h_blkmap, D.h_phimap, emit);
     }
-    if (!L.capply.empty() && !D.comp_small) {
-      double fl = 0;
-      for (auto& a : L.capply) fl += (double)a.s * a.s * a.s / 3.0 + 4.0 * a.s * a.s * a.r;
-      launch(h, st, "comp_explicit", fl, 0, [&] {
-        int smax = 0;
-        for (auto& a : L.capply) smax = std::max(smax, a.s);
-        hipLaunchKernelGGL(sgf::k_comp_explicit<T>, dim3((unsigned)L.capply.size(), cdiv(smax, sgf::CEB)),
-                           dim3(sgf::WG), 0, st,
-                           D.capply.as<sgf::CompApply>(), D.cf.as<T>(), D.nbuf.as<T>(), D.tau.as<T>(), D.tb.as<T>());
-      }, L.t);
-    }
-    // coarse couplings, only for the pairs that touch a compressed separator
-    if (!L.capply.empty()) {
-      // many small pairs: one wavefront each, T_a M_ab in LDS
-      int64_t gmax = 1;
-      for (int32_t p : L.active_pairs) {
-        const auto& pd = L.pairs[p];
-        const int ra = pd.ca >= 0 && L.rank[pd.ca] < pd.s_a ? L.rank[pd.ca] : pd.s_a;
-        gmax = std::max<int64_t>(gmax, (int64_t)ra * pd.s_b);
-      }
-      const size_t plds = (size_t)sgf::PPB * gmax * sizeof(T);
-      const unsigned nact = (unsigned)L.active_pairs.size();
-      launch(h, st, "pair", 0, 0, [&] {
-        const bool wave = plds <= LDS_BYTES && (h->pair_mode == 1 || (h->pair_mode < 0 && nact >= 4096));
-        if (wave)
-          hipLaunchKernelGGL(sgf::k_pair_w<T>, dim3(cdiv(nact, sgf::PPB)), dim3(sgf::PPB * sgf::WAVE), plds, st,
-                             D.pairs.as<sgf::PairDesc>(), D.active.as<int32_t>(), (int)nact, D.rank.as<int>(),
-                             D.tofcomp.as<int64_t>(), D.tb.as<T>(), blocks, (int)gmax);
-        else
-          hipLaunchKernelGGL(sgf::k_pair<T>, dim3(nact), dim3(sgf::WG), 0, st, D.pairs.as<sgf::PairDesc>(),
-                             D.active.as<int32_t>(), D.rank.as<int>(), D.tofcomp.as<int64_t>(), D.tb.as<T>(), blocks,
-                             D.scratch.as<T>());
-      }, L.t);
-    }
-    acct = li;   // counted while the GPU runs the next level
     h->trace.mark("compressed-separator work queued", L.t);
     // ---- coarsen (Secs. 4.3-4.4) ----------------------------------------------
     {
       BatchScope bs(h);
       if (!same_ranks) {
-        for (size_t q = li + 1; q < h->lev.size(); ++q) h->lev[q].uploaded = false;
-        P.max_node = 0;
-        for (int q = 0; q <= li; ++q)
-          for (int sz : P.levels[q].size) P.max_node = std::max<int64_t>(P.max_node, sz);
-        // the next level's structure does not depend on the ranks: when it
-        // has been planned before, only its sizes and offsets are redone
-        const bool emit = !h->device_coarsen;
+        // the in-place re-plan, else a fresh one
         bool fresh = false;
-        if (!sgf::update_next_level(P, (size_t)li, D.h_blkmap, D.h_phimap, emit)) {
+        if (!planned) {
           P.levels.resize(li + 1);
           P.parts.resize(li + 1);
           sgf::plan_next_level(P, D.h_blkmap, D.h_phimap, emit);

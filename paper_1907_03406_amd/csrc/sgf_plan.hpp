@@ -1327,6 +1327,16 @@ inline void plan_next_level(Plan& P, std::vector<CopyDesc>& blk_map, std::vector
   P.levels.push_back(std::move(N));
 }
 
+// Whether update_next_level can take the recorded next level of level li:
+// the rank-dependent top rule is off and that level was planned before for
+// this level's clusters and pairs.
+inline bool can_update_next_level(const Plan& P, size_t li) {
+  if (P.opt.stop_rule != 0 || li + 1 >= P.levels.size()) return false;
+  const Level& C = P.levels[li];
+  const Level& N = P.levels[li + 1];
+  return N.can_update && N.from_father.size() == C.seps.size() && N.cp_kind.size() == C.pairs.size();
+}
+
 // The next level re-planned in place for new ranks of level li: its
 // clusters, adjacency, pairs and the order of every list depend only on the
 // partition (with the fixed top rule), so only the sizes, slots and the
