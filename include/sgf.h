@@ -360,8 +360,11 @@ sgf_status sgf_set_band_elim(sgf_handle h, int32_t enable);
 
 /*
  * Compression (Eqs. 3.1-3.4) of levels whose separators all have at most 64
- * rows and at most 128 columns of N: enable = 1 (default) runs one wavefront
- * per separator with its front, Phi blocks and N staged in LDS; 0 uses the
+ * rows and at most 128 columns of N: enable = 1 (default) runs each separator
+ * with its front, Phi blocks and N staged in LDS, on four wavefronts when the
+ * level has fewer than 1024 separators of at most 32 rows (wavefront 0 alone
+ * in the Cholesky and the pivoted QR) and on one otherwise; 2 the same on one
+ * wavefront at every level (the same values as 1, bit for bit); 0 uses the
  * one-workgroup kernel (also used under sgf_set_persistent).  Same ranks and,
  * up to rounding order, the same factor.  Takes effect at the next
  * factorization.

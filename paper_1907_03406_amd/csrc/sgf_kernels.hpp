@@ -1243,30 +1243,31 @@ __device__ __forceinline__ T wave_max(T v) {
   return v;
 }
 
-// Copy of n contiguous device elements into LDS by one wavefront with U loads
-// in flight per lane (buffer loads over exactly the n elements, so the lanes
-// past the end load nothing): element e goes to dst[dl(e)].
-template <typename T, int U = 8, typename DL>
+// Copy of n contiguous device elements into LDS by the first NT threads (one
+// wavefront by default) with U loads in flight per thread (buffer loads over
+// exactly the n elements, so the threads past the end load nothing): element
+// e goes to dst[dl(e)].
+template <typename T, int U = 8, int NT = WAVE, typename DL>
 __device__ __forceinline__ void wave_stage(T* dst, const T* src, int n, DL dl) {
   const __amdgpu_buffer_rsrc_t r = buf_res(src, (int64_t)n * (int64_t)sizeof(T));
-  const int lane = threadIdx.x % WAVE;
-  for (int b = 0; b < n; b += U * WAVE) {
+  const int t = threadIdx.x % NT;
+  for (int b = 0; b < n; b += U * NT) {
     T v[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int e = b + u * WAVE + lane;
+      const int e = b + u * NT + t;
       v[u] = buf_ld(r, buf_off(e < n, e, (int)sizeof(T)), T());
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int e = b + u * WAVE + lane;
+      const int e = b + u * NT + t;
       if (e < n) dst[dl(e)] = v[u];
     }
   }
 }
 
-template <typename T, int NB>
-__global__ __launch_bounds__(WAVE) void k_compress_small(const CompDesc* __restrict__ D,
+template <typename T, int NB, int NW>
+__global__ __launch_bounds__(NW * WAVE) void k_compress_small(const CompDesc* __restrict__ D,
                                                          const CompNbr* __restrict__ NBR, T* __restrict__ cf,
                                                          T* __restrict__ nbuf, const T* __restrict__ phi,
                                                          T* __restrict__ ltphi, T* __restrict__ tau_all,
@@ -1286,35 +1287,46 @@ __global__ __launch_bounds__(WAVE) void k_compress_small(const CompDesc* __restr
   T* invd = Lt + (int64_t)s * pi;           // s reciprocal pivots
   T* taul = invd + s;                       // c reflector coefficients
   T* Xl = taul + c;                         // s x s, ld s | 1: T_B = Q^T L_B^{-1}
-  const int lane = threadIdx.x;
+  // NW wavefronts: all of them in the parallel phases (staging, neighbour
+  // rows, write-back, N, the reflector pass), wavefront 0 alone in the
+  // sequential ones (Cholesky, QRCP); each element is computed by the same
+  // code whatever NW is, so the values do not depend on it
+  constexpr int NT = NW * WAVE;
+  const int tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
+  __shared__ int sh_r;
+  auto sync = [] {
+    if constexpr (NW > 1) __syncthreads();
+    else __builtin_amdgcn_wave_barrier();
+  };
   T* F = cf + d.cf_off;
   // ---- stage the front and the Phi blocks ----
   // (every block is read in its own storage order, batches of loads in flight)
   if (blocks) {
     // the front straight from the pair blocks (what k_comp_gather puts in cf):
     // M_BB, then M_XB of every neighbour X (stored as M_BX when trans)
-    wave_stage(Fl, blocks + d.blk_diag, s * s, [&](int e) { return e % s + (e / s) * ldf; });
+    wave_stage<T, 8, NT>(Fl, blocks + d.blk_diag, s * s, [&](int e) { return e % s + (e / s) * ldf; });
     for (int q = 0; q < d.nnb; ++q) {
       const CompNbr x = NBR[d.nb_ptr + q];
       const int sx = x.s_x, xr = x.row;
       if (x.trans)   // M_BX: element e is row e % s of B, column e / s of X
-        wave_stage(Fl, blocks + x.blk_off, sx * s, [&](int e) { return xr + e / s + (e % s) * ldf; });
+        wave_stage<T, 8, NT>(Fl, blocks + x.blk_off, sx * s, [&](int e) { return xr + e / s + (e % s) * ldf; });
       else           // M_XB: element e is row e % s_X of X, column e / s_X of B
-        wave_stage(Fl, blocks + x.blk_off, sx * s, [&](int e) { return xr + e % sx + (e / sx) * ldf; });
+        wave_stage<T, 8, NT>(Fl, blocks + x.blk_off, sx * s, [&](int e) { return xr + e % sx + (e / sx) * ldf; });
     }
   } else {
-    wave_stage(Fl, F, R * s, [&](int e) { return e % R + (e / R) * ldf; });
+    wave_stage<T, 8, NT>(Fl, F, R * s, [&](int e) { return e % R + (e / R) * ldf; });
   }
-  wave_stage(Ph, phi + d.phi_off, s * pi, [&](int e) { return e % s + (e / s) * R; });
+  wave_stage<T, 8, NT>(Ph, phi + d.phi_off, s * pi, [&](int e) { return e % s + (e / s) * R; });
   for (int q = 0; q < d.nnb; ++q) {
     const CompNbr x = NBR[d.nb_ptr + q];
     if (x.full) continue;
     const int sx = x.s_x, xr = x.row;
-    wave_stage(Ph, phi + x.phi_off, sx * pi, [&](int e) { return xr + e % sx + (e / sx) * R; });
+    wave_stage<T, 8, NT>(Ph, phi + x.phi_off, sx * pi, [&](int e) { return xr + e % sx + (e / sx) * R; });
   }
-  __builtin_amdgcn_wave_barrier();
+  sync();
   if (!prefactored) {
     // ---- L_B = chol(M_BB): lane i keeps row i in registers ----
+    if (w == 0) {
     T a[NB];
 #pragma unroll
     for (int k = 0; k < NB; ++k) a[k] = (lane < s && k < s && k <= lane) ? Fl[lane + k * ldf] : T(0);
@@ -1341,11 +1353,12 @@ __global__ __launch_bounds__(WAVE) void k_compress_small(const CompDesc* __restr
 #pragma unroll
       for (int k = 0; k < NB; ++k)
         if (k < s && k <= lane) Fl[lane + k * ldf] = a[k];
-    __builtin_amdgcn_wave_barrier();
+    }
+    sync();
     // ---- neighbour rows: row <- row L_B^{-T}, one row per lane, the row's
     // solved entries in registers (the coefficients of L_B are LDS
     // broadcasts) ----
-    for (int i = s + lane; i < R; i += WAVE) {
+    for (int i = s + tid; i < R; i += NT) {
       T x[NB];
 #pragma unroll
       for (int j = 0; j < NB; ++j) {
@@ -1360,16 +1373,16 @@ __global__ __launch_bounds__(WAVE) void k_compress_small(const CompDesc* __restr
       for (int j = 0; j < NB; ++j)
         if (j < s) Fl[i + j * ldf] = x[j];
     }
-    __builtin_amdgcn_wave_barrier();
+    sync();
     // the factored front to cf (all of it when the staging skipped cf, so
     // that cf holds what the gather and this write-back would have left)
-    for (int idx = lane; idx < R * s; idx += WAVE) {
+    for (int idx = tid; idx < R * s; idx += NT) {
       const int i = idx % R, j = idx / R;
       if (i >= j || blocks) F[idx] = Fl[i + j * ldf];
     }
   }
   // ---- N (Eq. 4.5) and L^T Phi_B ----
-  for (int idx = lane; idx < s * pi; idx += WAVE) {
+  for (int idx = tid; idx < s * pi; idx += NT) {
     const int i = idx % s, p = idx / s;
     T acc = 0;
 #pragma unroll 8
@@ -1382,10 +1395,11 @@ __global__ __launch_bounds__(WAVE) void k_compress_small(const CompDesc* __restr
   const bool mma = bf16n && pi <= 16;
   if (bf16n && d.self_cols) {
     if (mma) {
-      wave_bf16_gemm<T>(s, pi, s, [&](int i, int j) { return j >= i ? Fl[j + i * ldf] : T(0); },
-                        [&](int j, int p) { return Ph[j + p * R]; }, Nl, ldn);
+      if (w == 0)
+        wave_bf16_gemm<T>(s, pi, s, [&](int i, int j) { return j >= i ? Fl[j + i * ldf] : T(0); },
+                          [&](int j, int p) { return Ph[j + p * R]; }, Nl, ldn);
     } else {
-      for (int idx = lane; idx < s * pi; idx += WAVE) {
+      for (int idx = tid; idx < s * pi; idx += NT) {
         const int i = idx % s, p = idx / s;
         T acc16 = 0;
         for (int j = i; j < s; ++j) acc16 += bf16_round(Fl[j + i * ldf]) * bf16_round(Ph[j + p * R]);
@@ -1397,7 +1411,7 @@ __global__ __launch_bounds__(WAVE) void k_compress_small(const CompDesc* __restr
   for (int q = 0; q < d.nnb; ++q) {
     const CompNbr x = NBR[d.nb_ptr + q];
     if (x.full) {
-      for (int idx = lane; idx < s * x.s_x; idx += WAVE) {
+      for (int idx = tid; idx < s * x.s_x; idx += NT) {
         const int i = idx % s, j = idx / s;
         const T v = Fl[(x.row + j) + i * ldf];
         Nl[i + (x.col + j) * ldn] = bf16n ? bf16_round(v) : v;
@@ -1407,10 +1421,11 @@ __global__ __launch_bounds__(WAVE) void k_compress_small(const CompDesc* __restr
     }
     if (mma) {
       const int xr = x.row;
-      wave_bf16_gemm<T>(s, pi, x.s_x, [&](int i, int j) { return Fl[(xr + j) + i * ldf]; },
-                        [&](int j, int p) { return Ph[(xr + j) + p * R]; }, Nl + x.col * ldn, ldn);
+      if (w == 0)
+        wave_bf16_gemm<T>(s, pi, x.s_x, [&](int i, int j) { return Fl[(xr + j) + i * ldf]; },
+                          [&](int j, int p) { return Ph[(xr + j) + p * R]; }, Nl + x.col * ldn, ldn);
     } else {
-      for (int idx = lane; idx < s * pi; idx += WAVE) {
+      for (int idx = tid; idx < s * pi; idx += NT) {
         const int i = idx % s, p = idx / s;
         T acc = 0;
         if (bf16n)
@@ -1424,9 +1439,11 @@ __global__ __launch_bounds__(WAVE) void k_compress_small(const CompDesc* __restr
     }
     cend = x.col + pi;
   }
-  for (int idx = lane; idx < s * (c - cend); idx += WAVE) Nl[idx % s + (cend + idx / s) * ldn] = T(0);
-  __builtin_amdgcn_wave_barrier();
-  // ---- pivoted Householder QR of N (Eq. 3.3) ----
+  for (int idx = tid; idx < s * (c - cend); idx += NT) Nl[idx % s + (cend + idx / s) * ldn] = T(0);
+  sync();
+  // ---- pivoted Householder QR of N (Eq. 3.3), wavefront 0 ----
+  int r = 0;
+  if (w == 0) {
   T nr[2];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
@@ -1437,7 +1454,6 @@ __global__ __launch_bounds__(WAVE) void k_compress_small(const CompDesc* __restr
       for (int i = 0; i < s; ++i) acc += Nl[i + j * ldn] * Nl[i + j * ldn];
     nr[h] = sqrt(acc);
   }
-  int r = 0;
   T ref = 0;
   const int kmax = min(s, c);
   const int fixed = fixed_rank ? fixed_rank[ci] : -1;
@@ -1510,18 +1526,22 @@ __global__ __launch_bounds__(WAVE) void k_compress_small(const CompDesc* __restr
     ++r;
   }
   __builtin_amdgcn_wave_barrier();
+  if (lane == 0) sh_r = r;
+  }
+  sync();
+  if constexpr (NW > 1) r = sh_r;
   // ---- reflectors, tau and the rank out; then Q^T acts, one column per
   // lane, on the columns of L_B^{-1} (T_B = Q^T L_B^{-1}, for the apply and
   // the coarse couplings) and on those of L^T Phi_B ((Q^T L^T Phi_B)[:r],
   // Eq. 3.4); the column in registers, the coefficients of L_B and of the
   // reflectors LDS broadcasts ----
   T* Ng = nbuf + d.n_off;
-  for (int idx = lane; idx < s * r; idx += WAVE) Ng[idx] = Nl[idx % s + (idx / s) * ldn];
+  for (int idx = tid; idx < s * r; idx += NT) Ng[idx] = Nl[idx % s + (idx / s) * ldn];
   T* tau = tau_all + d.tau_off;
-  for (int k = lane; k < r; k += WAVE) tau[k] = taul[k];
+  for (int k = tid; k < r; k += NT) tau[k] = taul[k];
   if (r < s) {
     const int ldx = s | 1;
-    for (int j = lane; j < s + pi; j += WAVE) {
+    for (int j = tid; j < s + pi; j += NT) {
       T x[NB];
       if (j < s) {
         // column j of L_B^{-1}: rows above j are zero, and the products with
@@ -1563,13 +1583,13 @@ __global__ __launch_bounds__(WAVE) void k_compress_small(const CompDesc* __restr
       for (int i = 0; i < NB; ++i)
         if (i < s) xc[i] = x[i];
     }
-    __builtin_amdgcn_wave_barrier();
+    sync();
     T* X = tb + d.tb_off;
-    for (int idx = lane; idx < s * s; idx += WAVE) X[idx] = Xl[idx % s + (idx / s) * ldx];
+    for (int idx = tid; idx < s * s; idx += NT) X[idx] = Xl[idx % s + (idx / s) * ldx];
   }
   T* LtP = ltphi + d.ltphi_off;
-  for (int idx = lane; idx < s * pi; idx += WAVE) LtP[idx] = Lt[idx];
-  if (lane == 0) rank[ci] = r;
+  for (int idx = tid; idx < s * pi; idx += NT) LtP[idx] = Lt[idx];
+  if (tid == 0) rank[ci] = r;
 }
 
 // Phi_B <- (Q^T L^T Phi_B)[:r] for the separators that were compressed.

@@ -486,6 +486,7 @@ struct sgf_handle_s {
   bool apply1 = true;        // one right-hand side on levels of fronts with at most 64 rows: k_apply1
   bool band_elim = true;
   bool small_comp = true;
+  bool small_comp_one = false;   // one wavefront per small compression on every level
   int32_t persist_cap = 0;   // > 0: per-level work lists persistent on at most this many workgroups
   int32_t pair_mode = -1;    // coarse couplings: -1 automatic, 0 one workgroup per pair, 1 one wavefront per pair
   // coarsening destinations computed on the device (else host copy maps);
@@ -1590,10 +1591,17 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
                                    D.nbuf.as<T>(), (const T*)D.phi.as<T>(), D.ltphi.as<T>(), D.tau.as<T>(),
                                    D.rank.as<int>(), P.pi, tol, h->d_fail.as<int>(), pre, bf, D.tb.as<T>(),
                                    gather_inside ? (const T*)blocks : (const T*)nullptr, fixed);
+          // few separators: four wavefronts each (the parallel phases spread
+          // over them); many: one each, so that more separators share the chip
+          // (measured on the 1024^2 grid: 480 separators and fewer gain, 1984 lose)
+          const bool wide = !h->small_comp_one && L.comp.size() < 1024 && snb <= 32;
+          const dim3 b1(sgf::WAVE), b4(4 * sgf::WAVE);
           std::apply([&](auto... x) {
-            if (snb == 16) hipLaunchKernelGGL((sgf::k_compress_small<T, 16>), g, dim3(sgf::WAVE), slds, st, x...);
-            else if (snb == 32) hipLaunchKernelGGL((sgf::k_compress_small<T, 32>), g, dim3(sgf::WAVE), slds, st, x...);
-            else hipLaunchKernelGGL((sgf::k_compress_small<T, 64>), g, dim3(sgf::WAVE), slds, st, x...);
+            if (snb == 16 && wide) hipLaunchKernelGGL((sgf::k_compress_small<T, 16, 4>), g, b4, slds, st, x...);
+            else if (snb == 16) hipLaunchKernelGGL((sgf::k_compress_small<T, 16, 1>), g, b1, slds, st, x...);
+            else if (snb == 32 && wide) hipLaunchKernelGGL((sgf::k_compress_small<T, 32, 4>), g, b4, slds, st, x...);
+            else if (snb == 32) hipLaunchKernelGGL((sgf::k_compress_small<T, 32, 1>), g, b1, slds, st, x...);
+            else hipLaunchKernelGGL((sgf::k_compress_small<T, 64, 1>), g, b1, slds, st, x...);
           }, a);
         }, L.t);
       }
@@ -3249,7 +3257,10 @@ sgf_status sgf_set_persistent(sgf_handle h, int32_t max_workgroups) {
 
 sgf_status sgf_set_small_compress(sgf_handle h, int32_t enable) {
   if (!h) return fail(SGF_EINVAL, "NULL handle");
-  return guard([&] { h->small_comp = enable != 0; });
+  return guard([&] {
+    h->small_comp = enable != 0;
+    h->small_comp_one = enable == 2;
+  });
 }
 
 sgf_status sgf_set_band_elim(sgf_handle h, int32_t enable) {

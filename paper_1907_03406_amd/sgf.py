@@ -363,8 +363,11 @@ class Solver:
         _check(_lib.sgf_set_band_elim(self.h, int(bool(enable))))
 
     def set_small_compress(self, enable=True):
-        """One-wavefront compression of small separators (default on)."""
-        _check(_lib.sgf_set_small_compress(self.h, int(bool(enable))))
+        """Compression of small separators in LDS (default on: four
+        wavefronts per separator on levels of few separators, one otherwise);
+        "one": one wavefront per separator on every level (same bits)."""
+        mode = 2 if enable == "one" else int(bool(enable))
+        _check(_lib.sgf_set_small_compress(self.h, mode))
 
     def set_pair_kernel(self, mode=-1):
         """Coarse couplings: -1 automatic, 0 one workgroup per pair, 1 one wavefront per pair."""

@@ -643,6 +643,34 @@ def test_small_compression_matches_workgroup_compression_and_oracle(kind, grid, 
         assert _rel(out[True], za) <= 1e-3
 
 
+@pytest.mark.parametrize("kind,grid,leaf,q", [("fourier", (100, 90), 16, 2), ("blocky", (17, 16, 15), 4, 1),
+                                              ("fourier", (61, 58), 8, 2)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_small_compression_on_four_wavefronts_equals_one(kind, grid, leaf, q, prec):
+    """Levels with few small separators compress each on four wavefronts
+    (staging, neighbour rows, N and the reflector pass spread over them,
+    the Cholesky and the pivoted QR on the first); every value comes from
+    the same code as on one wavefront, so the ranks and the preconditioner
+    are the same bit for bit."""
+    p = _prob(kind, grid)
+    pr = sgf.FP64 if prec == "fp64" else sgf.FP32
+    V = np.stack([P.random_rhs(17, p.n, j) for j in range(2)], axis=1)
+    out, ranks = {}, {}
+    for mode in (True, "one"):
+        s = sgf.Solver.from_problem(p, q=q, leaf=leaf, precision=pr)
+        s.set_small_compress(mode)
+        s.profile(True)
+        s.factorize(torch.from_numpy(p.data).cuda())
+        st = s.profile_read()
+        s.profile(False)
+        assert st.get("compress", {}).get("launches", 0) >= 1
+        out[mode] = _apply(s, V)
+        ranks[mode] = [s.level(t)["rank"].tolist() for t in range(1, s.info()["levels"])]
+        s.close()
+    assert ranks[True] == ranks["one"]
+    assert np.array_equal(out[True], out["one"])
+
+
 @pytest.mark.parametrize("order", ["pcg1-apply8-pcg1", "apply1-pcg4-apply1"])
 def test_graphs_recaptured_after_work_buffers_grow(order):
     """The captured apply and PCG graphs hold the addresses of the apply's
