@@ -3224,12 +3224,29 @@ __global__ __launch_bounds__(WG) void k_spmv_multi(const int64_t* __restrict__ r
     double acc[RC];
 #pragma unroll
     for (int j = 0; j < RC; ++j) acc[j] = 0;
-    for (int64_t e = e0 + g; e < e1; e += G) {
-      const double a = va[e];
-      const int64_t col = ci[e];
+    // UE entries of the lane at a time, their loads issued first (clamped
+    // indices; the entries past the row's end add nothing), accumulated in
+    // the lane's entry order
+    constexpr int UE = 4;
+    for (int64_t eb = e0 + g; eb < e1; eb += (int64_t)G * UE) {
+      double a[UE];
+      int64_t col[UE];
 #pragma unroll
-      for (int j = 0; j < RC; ++j)
-        if (j < nc) acc[j] += a * xc[col + j * ldx];
+      for (int u = 0; u < UE; ++u) {
+        const int64_t e = min(eb + (int64_t)u * G, e1 - 1);
+        a[u] = va[e];
+        col[u] = ci[e];
+      }
+#pragma unroll
+      for (int u = 0; u < UE; ++u) {
+        const bool ok = eb + (int64_t)u * G < e1;
+#pragma unroll
+        for (int j = 0; j < RC; ++j)
+          if (j < nc) {
+            const double xv = xc[col[u] + j * ldx];
+            if (ok) acc[j] += a[u] * xv;
+          }
+      }
     }
 #pragma unroll
     for (int j = 0; j < RC; ++j)
