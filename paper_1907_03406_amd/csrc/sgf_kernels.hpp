@@ -485,10 +485,29 @@ __device__ void wg_potrf(T* __restrict__ C, int64_t ld, int R, int m, int nupd, 
     // panel rows (local) [z0, z1) are zero; the live rows are [0, z0) and [z1, pr)
     const int z0 = min(m, jb + nb + bw) - jb, z1 = m - jb;
     const int live = z0 + (pr - z1);
-    for (int idx = tid; idx < live * nb; idx += WG) {
-      const int ii = idx % live, p = idx / live;
-      const int i = ii < z0 ? ii : ii - z0 + z1;
-      pan[p * pl + i] = C[(jb + i) + (int64_t)(jb + p) * ld];
+    {
+      // U loads in flight per thread (clamped indices), then their stores
+      constexpr int U = 8;
+      const int n = live * nb;
+      for (int b = 0; b < n; b += U * WG) {
+        T v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int q = min(b + u * WG + tid, n - 1);
+          const int ii = q % live, p = q / live;
+          const int i = ii < z0 ? ii : ii - z0 + z1;
+          v[u] = C[(jb + i) + (int64_t)(jb + p) * ld];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int idx = b + u * WG + tid;
+          if (idx < n) {
+            const int ii = idx % live, p = idx / live;
+            const int i = ii < z0 ? ii : ii - z0 + z1;
+            pan[p * pl + i] = v[u];
+          }
+        }
+      }
     }
     __syncthreads();
     if (w == 0 && DIAG_IN_REGS) {
