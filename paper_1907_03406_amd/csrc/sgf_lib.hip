@@ -1328,6 +1328,7 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
     LevelDev& D = h->lev[0];
     const int64_t ne = L.front_elems + L.blk_elems;
     const bool band_inputs = D.front_clean && banded_w(h, L, D) > 0;
+    const bool fused = band_inputs && D.fill_ok;
     if (band_inputs) {
       double zb = (double)L.blk_elems * e;
       for (const auto& d : L.elim) zb += (double)d.m * (std::min(d.bw, std::max(d.m - 1, 0)) + 1 + d.k) * e;
@@ -1337,12 +1338,7 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
           hipLaunchKernelGGL(sgf::k_zero<T>, dim3(g), dim3(sgf::WG), 0, st, D.arena.as<T>() + L.front_elems,
                              L.blk_elems);
         }
-        if (D.fill_ok)   // the band cleared and the front's entries written in one pass
-          hipLaunchKernelGGL(sgf::k_fill_band<T>, dim3((unsigned)D.h_band_list.size()), dim3(sgf::WG), 0, st,
-                             D.elim.as<sgf::ElimDesc>(), D.band_list.as<int32_t>(), D.fill_ptr.as<int64_t>(),
-                             D.fill_off.as<int32_t>(), D.fill_src.as<int64_t>(), h->d_vals.as<double>(),
-                             D.arena.as<T>());
-        else
+        if (!fused)
           hipLaunchKernelGGL(sgf::k_zero_band<T>, dim3((unsigned)D.h_band_list.size()), dim3(sgf::WG), 0, st,
                              D.elim.as<sgf::ElimDesc>(), D.band_list.as<int32_t>(), D.arena.as<T>());
       }, L.t);
@@ -1351,13 +1347,22 @@ void factor_numeric(sgf_handle h, const double* vals, hipStream_t st) {
     }
     // set again once the banded elimination of this factorization is queued
     D.front_clean = false;
-    if (band_inputs && D.fill_ok) {
+    if (fused) {
+      // the pair-block entries first, while the blocks just cleared are still
+      // cached; then, per banded front, the band and M_SI cleared and the
+      // front's own entries written in one pass
       if (D.fill_rest_n > 0)
         launch(h, st, "fill_csr", 0, D.fill_rest_n * (24.0 + e), [&] {
           hipLaunchKernelGGL(sgf::k_fill_rest<T>, dim3(cdiv(D.fill_rest_n, 4 * sgf::WG)), dim3(sgf::WG), 0, st,
                              h->d_vals.as<double>(), D.rest_dst.as<int64_t>(), D.rest_src.as<int64_t>(),
                              D.fill_rest_n, D.arena.as<T>());
         });
+      launch(h, st, "fill_band", 0, (double)(D.h_fill_ptr.back()) * (20.0 + e), [&] {
+        hipLaunchKernelGGL(sgf::k_fill_band<T>, dim3((unsigned)D.h_band_list.size()), dim3(sgf::WG), 0, st,
+                           D.elim.as<sgf::ElimDesc>(), D.band_list.as<int32_t>(), D.fill_ptr.as<int64_t>(),
+                           D.fill_off.as<int32_t>(), D.fill_src.as<int64_t>(), h->d_vals.as<double>(),
+                           D.arena.as<T>());
+      }, L.t);
     } else {
       launch(h, st, "fill_csr", 0, h->nnz * (16.0 + e), [&] {
         hipLaunchKernelGGL(sgf::k_fill_csr<T>, dim3(cdiv(h->nnz, sgf::WG)), dim3(sgf::WG), 0, st,
